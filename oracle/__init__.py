@@ -1,0 +1,27 @@
+"""Independent CPU FP64 checker for the staggered FFT non-local damage solver.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke entry point and the
+benchmark's CPU-baseline leg may import or run anything in this package.  The
+GPU library never calls it and shares no code, table or constant with it.
+
+It is a plain, slow, vectorised numpy/scipy implementation of what the paper
+computes, written to be checked against the paper by eye:
+
+  spectral   discrete frequencies and the rotated-scheme derivative symbols
+             (Sec. 3.2.1)
+  mandel     Mandel vector <-> tensor helpers
+  material   J2 return mapping on the effective stress with frozen damage,
+             consistent tangent, linear damage laws (Sec. 2.1.2, Sec. 2.2.3,
+             appendix A.2)
+  galerkin   FFT-Galerkin projection with mixed macroscopic control, the
+             Newton + CG mechanical solver (Sec. 3.2.2)
+  helmholtz  generalised Helmholtz operator in Fourier space and its
+             preconditioned CG (Sec. 3.2.3, Algorithm 2)
+  staggered  one load increment of the iterated staggered scheme
+             (Sec. 3.2, Algorithm 1)
+
+Transforms use numpy.fft on the full complex spectrum (fftn / ifftn) as a
+library primitive; Krylov solvers run in the plain real-space (mechanics) or
+full-spectrum Hermitian (Helmholtz) inner product.
+"""
+from . import spectral, mandel, material, galerkin, helmholtz, staggered  # noqa: F401
