@@ -115,7 +115,7 @@ def fftg_solve(phase, table, D, epsp_n, kappa_n, target, eps0, h=1.0,
     c = eps0.shape[0]
     N = int(np.prod(S))
     J = D.shape[0] if nfields is None else nfields
-    q, _ = spectral.symbols(S, h, scheme)
+    q = spectral.projection_symbol(S, h, scheme)
     Sbar = np.where(mask.astype(bool), np.asarray(Smac, dtype=np.float64), 0.0)
     Sbar_f = Sbar.reshape((c,) + (1,) * len(S))
     eps = set_strain_means(eps0, mask, Emac)

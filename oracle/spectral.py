@@ -68,3 +68,12 @@ def symbols(shape, h=1.0, scheme=ROTATED):
         q.append(np.broadcast_to(v, shape).copy())
     qt = [np.where(np.broadcast_to(nyq[j], shape), 0.0, q[j]) for j in range(ndim)]
     return q, qt
+
+
+def projection_symbol(shape, h=1.0, scheme=ROTATED):
+    """Symbol used by the Galerkin projection.  ROTATED: q itself (the
+    projector depends on q (x) q only, which is even on the Nyquist planes).
+    SPECTRAL: q_tilde, since theta_j/h is not odd on its own Nyquist plane
+    and the projected field would not stay real."""
+    q, qt = symbols(shape, h, scheme)
+    return q if scheme == ROTATED else qt
