@@ -1,0 +1,208 @@
+/*
+ * fftg.h -- C ABI of the MI355X (gfx950) staggered FFT solver for non-local
+ * ductile damage on periodic voxel RVEs.
+ *
+ * Method: Magri, Lucarini, Lemoine, Adam, Segurado, "An FFT framework for
+ * simulating non-local ductile failure in heterogeneous materials" (CMAME).
+ *   - fftg_solve      : FFT-Galerkin mechanics with mixed macroscopic control,
+ *                       Newton + conjugate gradients (Sec. 3.2.2, eq. weakeq,
+ *                       eq. eqdiscrete2, eq. lin_stress).
+ *   - helmholtz_solve : generalised Helmholtz equation with a per-voxel length,
+ *                       preconditioned CG in Fourier space (Sec. 3.2.3,
+ *                       eq. LhelmFourier, eq. preconditioner, Algorithm 2).
+ *   - staggered_step  : one load increment of the iterated staggered scheme
+ *                       (Sec. 3.2, Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *   Grid       N1 x N2 x N3 voxels (N3 = 1 in 2D plane strain), voxel size h.
+ *              Every N_i must be 1 or of the form 2^a 3^b with N_i <= 1024, and
+ *              N1 must be even.  N = N1 N2 N3.
+ *   Fields     FP64, contiguous, component-major [comp][z][y][x] (x fastest).
+ *   Tensors    Mandel order (11, 22, 33, sqrt2*23, sqrt2*13, sqrt2*12) in 3D,
+ *              (11, 22, sqrt2*12) in 2D; c = 6 (3D) or 3 (2D) components.
+ *              Macro targets (fftg_macro) and homogenised outputs use the
+ *              same Mandel values.
+ *   Pointers   Arguments marked "dev" are device pointers owned by the caller
+ *              (the library never frees them); "host" pointers are read or
+ *              written before the call returns.
+ *   Streams    All work is enqueued on the stream given to fftg_create; every
+ *              call returns after its host-visible outputs are valid.  One
+ *              handle per stream and per host thread.
+ *   Errors     No exception crosses the ABI.  FFTG_NOT_CONVERGED is a warning:
+ *              outputs hold the last iterate and stats are valid.  Negative
+ *              codes leave outputs unspecified; fftg_last_error() explains.
+ */
+#ifndef FFTG_H
+#define FFTG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fftg_handle fftg_handle;
+
+typedef enum {
+  FFTG_OK = 0,
+  FFTG_NOT_CONVERGED = 1,
+  FFTG_E_INVALID = -1,     /* bad argument: null pointer, ndim, mask entry, phase id, ... */
+  FFTG_E_UNSUPPORTED = -2, /* grid size with a prime factor other than 2 and 3, odd N1, ... */
+  FFTG_E_HIP = -3,         /* a HIP runtime call failed */
+  FFTG_E_BREAKDOWN = -4,   /* Krylov breakdown: p.Ap <= 0 (operator not positive) */
+  FFTG_E_NONFINITE = -5    /* NaN or Inf met in a Krylov scalar */
+} fftg_status;
+
+typedef enum { FFTG_FP64 = 0, FFTG_FP32_REFINED = 1 } fftg_precision;
+
+/* Derivative symbol (Sec. 3.2.1).  ROTATED: Willot's rotated finite-difference
+ * scheme, q_j = (2/h) sin(theta_j/2) prod_{m!=j} cos(theta_m/2);
+ * SPECTRAL: q_j = theta_j / h. */
+typedef enum { FFTG_ROTATED = 0, FFTG_SPECTRAL = 1 } fftg_scheme;
+
+/* Phase models.
+ * ELASTIC          isotropic elasticity, never damages.
+ * J2_DAMAGE        Lemaitre-type: J2 plasticity with linear hardening
+ *                  sy + H eps_p on the effective stress, sigma = (1-D) sigma_eff,
+ *                  D = clip((abar - dC)/(dR - dC), 0, dmax) from non-local field
+ *                  `dfield`; local source eps_p (Sec. 2.1.2, Sec. 2.2.3).
+ * ELASTIC_CRACKING isotropic elasticity with sigma = (1-D) C:eps,
+ *                  D = clip((max(hist, abar) - dC)/(dR - dC), 0, dmax); local
+ *                  source = Mazars equivalent strain sqrt(sum <e_i>_+^2).  Not in
+ *                  the paper: a second damage mechanism with its own field. */
+typedef enum { FFTG_ELASTIC = 0, FFTG_J2_DAMAGE = 1, FFTG_ELASTIC_CRACKING = 2 } fftg_model;
+
+#define FFTG_MAX_FIELDS 4
+#define FFTG_MAX_PHASES 16
+
+typedef struct {
+  int ndim;         /* 2 (plane strain) or 3 */
+  int n[3];         /* N1 (x), N2 (y), N3 (z); n[2] = 1 when ndim = 2 */
+  double h;         /* voxel size (lengths ell are in the same unit) */
+  int scheme;       /* fftg_scheme */
+  int prec;         /* fftg_precision */
+} fftg_grid;
+
+typedef struct {
+  int model;                    /* fftg_model */
+  double E, nu;                 /* Young's modulus, Poisson ratio */
+  double sy, H;                 /* yield stress and linear plastic hardening modulus */
+  int dfield;                   /* non-local field driving this phase's damage, -1 none */
+  double dC, dR, dmax;          /* damage law thresholds and cap */
+  double ell[FFTG_MAX_FIELDS];  /* characteristic length of field j inside this phase */
+} fftg_phase;
+
+/* Mixed macroscopic control (Sec. 3.1): mask[k] = 1 -> component k is
+ * stress-controlled with <sigma>_k = S[k]; mask[k] = 0 -> strain-controlled
+ * with <eps>_k = E[k].  Only the first c entries are read. */
+typedef struct {
+  unsigned char mask[6];
+  double E[6];
+  double S[6];
+} fftg_macro;
+
+/* ConjGrad(A, M, b, TOL) of Algorithm 2: stop when ||r|| <= tol ||b||. */
+typedef struct {
+  double tol;
+  int maxit;
+} fftg_krylov_opts;
+
+typedef struct {
+  int newton_iters;   /* Newton corrections (CG solves) */
+  int cg_iters;       /* Galerkin CG iterations, summed */
+  int pcg_iters;      /* Helmholtz PCG iterations, summed over fields */
+  int stagger_iters;  /* staggered passes */
+  double relres;      /* last Newton residual ratio (fftg_solve) or PCG ratio */
+  double err;         /* last staggered error ERR (Algorithm 1 (iii)) */
+  double t_ms[4];     /* wall time: constitutive, Galerkin CG, Helmholtz PCG, other */
+} fftg_stats;
+
+/* Create a solver for one grid.  `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  The handle owns its workspace (spectra, Krylov vectors,
+ * tangent, FFT tables, reduction scratch), sized from the grid, until
+ * fftg_destroy.  Errors: INVALID (null, ndim), UNSUPPORTED (sizes), HIP. */
+fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** out);
+fftg_status fftg_destroy(fftg_handle* h);
+/* Text of the last error on this handle (or of the last failed create when h
+ * is NULL).  Valid until the next call on the handle. */
+const char* fftg_last_error(const fftg_handle* h);
+
+/* Mechanics at frozen damage (Algorithm 1 step (i); Sec. 3.2.2).
+ *   phase     dev u8 [N], phase id of every voxel (< nphase)
+ *   tab       host [nphase] phase table
+ *   D         dev [nfields][N] frozen damage per field (a voxel takes the field
+ *             its phase names); may be NULL when nfields = 0
+ *   state_n   dev [7][N]: eps_p (6 Mandel comps) and kappa = eq. plastic strain
+ *             at t_n
+ *   target    host macro targets at t_{n+1}
+ *   eps       dev [c][N]: in = initial guess (its strain-controlled means are
+ *             moved to E), out = converged strain
+ *   sigma     dev [c][N] out
+ *   state_np1 dev [7][N] out: eps_p, kappa at the solution (may alias nothing
+ *             else)
+ *   alpha     dev [nfields][N] out: local sources (may be NULL if nfields = 0)
+ * Newton stops when ||G*(sigma - S)||_2 <= newton_tol max(||sigma||_2,
+ * s_ref sqrt(N)) after at least one correction (s_ref = largest yield stress
+ * in the table, 1 if none), or after newton_maxit corrections. */
+fftg_status fftg_solve(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
+                       int nphase, int nfields, const double* D, const double* state_n,
+                       const fftg_macro* target, double* eps, double* sigma, double* state_np1,
+                       double* alpha, const fftg_krylov_opts* cg, double newton_tol,
+                       int newton_maxit, fftg_stats* stats);
+
+/* Algorithm 2: solve abar - div(ell2 grad abar) = alpha for one field.
+ *   alpha     dev [N] source
+ *   ell2      dev [N] squared length per voxel
+ *   ell2_ref  preconditioner length^2; <= 0 -> volume mean of ell2
+ *   abar      dev [N] in = initial guess, out = solution */
+fftg_status helmholtz_solve(fftg_handle* h, const double* alpha, const double* ell2,
+                            double ell2_ref, double* abar, const fftg_krylov_opts* opts,
+                            fftg_stats* stats);
+
+/* Algorithm 1, one load increment n -> n+1.
+ *   state  dev packed [c + 6 + 1 + 2*nfields][N]:
+ *          eps (c), eps_p (6), kappa (1), hist (nfields), abar (nfields);
+ *          in = state at t_n, out = state at t_{n+1} (written on every return
+ *          code >= 0; with FFTG_NOT_CONVERGED it holds the last iterate)
+ *   sigma_out  dev [c][N] stress at t_{n+1}
+ *   homog_out  host [12]: <sigma> (first c of 6 slots), <eps> (slots 6..6+c)
+ * max_stagger_iters = 1 is the "simple staggered" single pass.  The loop
+ * stops when ERR <= stagger_tol. */
+fftg_status staggered_step(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
+                           int nphase, int nfields, double* state, const fftg_macro* target,
+                           const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
+                           double newton_tol, int newton_maxit, double stagger_tol,
+                           int max_stagger_iters, double* sigma_out, double* homog_out,
+                           fftg_stats* stats);
+
+/* ---- single-operator entry points (same kernels as the solvers) ---- */
+
+/* Forward real-to-half-spectrum transform of `ncomp` fields (Sec. 3.2.1):
+ * in dev [ncomp][N] real, out dev [ncomp][N3][N2][N1/2+1] complex
+ * (interleaved re, im).  Unnormalised: X[k] = sum_x u[x] exp(-i theta.x). */
+fftg_status fftg_forward(fftg_handle* h, int ncomp, const double* in, double* out);
+/* Inverse of fftg_forward, normalised by 1/N (Hermitian input assumed; the
+ * imaginary parts of self-conjugate coefficients are ignored). */
+fftg_status fftg_inverse(fftg_handle* h, int ncomp, const double* in, double* out);
+/* out = G*(tau) for a real Mandel field (dev [c][N] both), with the mixed
+ * control mask of `target` at the zero frequency (Sec. 3.2.2). */
+fftg_status fftg_project(fftg_handle* h, const fftg_macro* target, const double* tau,
+                         double* out);
+/* Constitutive update on the grid (the per-voxel step of fftg_solve):
+ * sigma dev [c][N], state_np1 dev [7][N], alpha dev [nfields][N] out; also
+ * keeps the consistent tangent inside the handle for fftg_apply_tangent_op. */
+fftg_status fftg_constitutive(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
+                              int nphase, int nfields, const double* D, const double* state_n,
+                              const double* eps, double* sigma, double* state_np1,
+                              double* alpha);
+/* out = G*(K : p) with the tangent of the last fftg_constitutive call;
+ * p, out dev [c][N] real; `target` supplies the zero-frequency mask. */
+fftg_status fftg_apply_galerkin(fftg_handle* h, const fftg_macro* target, const double* p,
+                                double* out);
+/* out = L(u) = u - div(ell2 grad u) for real u, out, ell2 dev [N] (the
+ * operator of Algorithm 2 taken back to real space). */
+fftg_status fftg_apply_helmholtz(fftg_handle* h, const double* ell2, const double* u,
+                                 double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFTG_H */

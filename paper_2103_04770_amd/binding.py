@@ -1,0 +1,286 @@
+"""ctypes binding of libfftg.so (argument marshalling only).
+
+Every entry point of include/fftg.h has a method of the same name on
+`Solver`.  Device arrays are torch CUDA tensors (float64, contiguous,
+component-major [comp][z][y][x]); phase images are uint8 CUDA tensors.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+FP64, FP32_REFINED = 0, 1
+ROTATED, SPECTRAL = 0, 1
+_MODELS = {"elastic": 0, "j2_damage": 1, "elastic_cracking": 2}
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_INVALID", -2: "E_UNSUPPORTED", -3: "E_HIP",
+          -4: "E_BREAKDOWN", -5: "E_NONFINITE"}
+
+
+class FFTGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Grid(ct.Structure):
+    _fields_ = [("ndim", ct.c_int), ("n", ct.c_int * 3), ("h", ct.c_double),
+                ("scheme", ct.c_int), ("prec", ct.c_int)]
+
+
+class Phase(ct.Structure):
+    _fields_ = [("model", ct.c_int), ("E", ct.c_double), ("nu", ct.c_double),
+                ("sy", ct.c_double), ("H", ct.c_double), ("dfield", ct.c_int),
+                ("dC", ct.c_double), ("dR", ct.c_double), ("dmax", ct.c_double),
+                ("ell", ct.c_double * 4)]
+
+
+class Macro(ct.Structure):
+    _fields_ = [("mask", ct.c_ubyte * 6), ("E", ct.c_double * 6), ("S", ct.c_double * 6)]
+
+
+class KrylovOpts(ct.Structure):
+    _fields_ = [("tol", ct.c_double), ("maxit", ct.c_int)]
+
+
+class Stats(ct.Structure):
+    _fields_ = [("newton_iters", ct.c_int), ("cg_iters", ct.c_int), ("pcg_iters", ct.c_int),
+                ("stagger_iters", ct.c_int), ("relres", ct.c_double), ("err", ct.c_double),
+                ("t_ms", ct.c_double * 4)]
+
+    def as_dict(self):
+        return dict(newton_iters=self.newton_iters, cg_iters=self.cg_iters,
+                    pcg_iters=self.pcg_iters, stagger_iters=self.stagger_iters,
+                    relres=self.relres, err=self.err, t_ms=list(self.t_ms))
+
+
+def lib_path():
+    return os.path.join(_PKG, "libfftg.so")
+
+
+def load_library():
+    """Load libfftg.so from the package directory; raises if it is not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    p = lib_path()
+    if not os.path.exists(p):
+        raise ImportError("libfftg.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2103_04770_amd.build)")
+    lib = ct.CDLL(p)
+    P = ct.c_void_p
+    I, D = ct.c_int, ct.c_double
+    sig = {
+        "fftg_create": [ct.POINTER(Grid), P, ct.POINTER(P)],
+        "fftg_destroy": [P],
+        "fftg_forward": [P, I, P, P],
+        "fftg_inverse": [P, I, P, P],
+        "fftg_project": [P, ct.POINTER(Macro), P, P],
+        "fftg_constitutive": [P, P, ct.POINTER(Phase), I, I, P, P, P, P, P, P],
+        "fftg_apply_galerkin": [P, ct.POINTER(Macro), P, P],
+        "fftg_apply_helmholtz": [P, P, P, P],
+        "helmholtz_solve": [P, P, P, D, P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
+        "fftg_solve": [P, P, ct.POINTER(Phase), I, I, P, P, ct.POINTER(Macro), P, P, P, P,
+                       ct.POINTER(KrylovOpts), D, I, ct.POINTER(Stats)],
+        "staggered_step": [P, P, ct.POINTER(Phase), I, I, P, ct.POINTER(Macro),
+                           ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D, I, D, I, P,
+                           ct.POINTER(ct.c_double), ct.POINTER(Stats)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ct.c_int
+    lib.fftg_last_error.argtypes = [P]
+    lib.fftg_last_error.restype = ct.c_char_p
+    _LIB = lib
+    return lib
+
+
+def phase_table(table):
+    """Phase dicts (see microstructure) -> ctypes array of fftg_phase."""
+    arr = (Phase * len(table))()
+    for i, ph in enumerate(table):
+        a = arr[i]
+        a.model = _MODELS[ph["model"]]
+        a.E, a.nu, a.sy, a.H = ph["E"], ph["nu"], ph["sy"], ph["H"]
+        a.dfield = int(ph["dfield"])
+        a.dC, a.dR, a.dmax = ph["dC"], ph["dR"], ph["dmax"]
+        ell = list(ph["ell"]) + [0.0] * (4 - len(ph["ell"]))
+        for j in range(4):
+            a.ell[j] = float(ell[j])
+    return arr
+
+
+def _macro(target):
+    mask, E, S = target
+    m = Macro()
+    for k in range(len(mask)):
+        m.mask[k] = int(mask[k])
+        m.E[k] = float(E[k])
+        m.S[k] = float(S[k])
+    return m
+
+
+def _ptr(t, dtype, numel=None, name="array"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+    return ct.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One grid, one stream.  shape is (N1, N2) in 2D or (N1, N2, N3) in 3D
+    (x first, as in the C ABI); device fields use numpy axis order
+    [comp][z][y][x]."""
+
+    def __init__(self, shape, h=1.0, scheme=ROTATED, prec=FP64, stream=None):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.ndim = len(shape)
+        n = list(shape) + [1] * (3 - len(shape))
+        g = Grid(self.ndim, (ct.c_int * 3)(*n), float(h), int(scheme), int(prec))
+        self.n = n
+        self.N = int(np.prod(n))
+        self.c = 6 if self.ndim == 3 else 3
+        self.n1h = n[0] // 2 + 1
+        self.Ns = self.n1h * n[1] * n[2]
+        self.prec = prec
+        st = torch.cuda.current_stream() if stream is None else stream
+        self.stream = st
+        hnd = ct.c_void_p()
+        rc = self.lib.fftg_create(ct.byref(g), ct.c_void_p(st.cuda_stream), ct.byref(hnd))
+        if rc != 0:
+            raise FFTGError(rc, self.lib.fftg_last_error(None).decode())
+        self.h = hnd
+
+    # numpy-order spatial shape
+    @property
+    def spatial(self):
+        return tuple(reversed(self.n[: self.ndim]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fftg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise FFTGError(rc, self.lib.fftg_last_error(self.h).decode())
+        return rc == 0
+
+    # ---------------------------------------------------------------- ops
+    def fftg_forward(self, x, out):
+        ncomp = x.numel() // self.N
+        self._check(self.lib.fftg_forward(self.h, ncomp, _ptr(x, self.torch.float64, ncomp * self.N, "in"),
+                                          _ptr(out, self.torch.float64, 2 * ncomp * self.Ns, "out")))
+
+    def fftg_inverse(self, x, out):
+        ncomp = out.numel() // self.N
+        self._check(self.lib.fftg_inverse(self.h, ncomp, _ptr(x, self.torch.float64, 2 * ncomp * self.Ns, "in"),
+                                          _ptr(out, self.torch.float64, ncomp * self.N, "out")))
+
+    def fftg_project(self, target, tau, out):
+        m = _macro(target)
+        f64 = self.torch.float64
+        self._check(self.lib.fftg_project(self.h, ct.byref(m), _ptr(tau, f64, self.c * self.N, "tau"),
+                                          _ptr(out, f64, self.c * self.N, "out")))
+
+    def fftg_constitutive(self, phase, table, nfields, D, state_n, eps, sigma, state_np1, alpha):
+        tab = phase_table(table)
+        f64 = self.torch.float64
+        self._check(self.lib.fftg_constitutive(
+            self.h, _ptr(phase, self.torch.uint8, self.N, "phase"), tab, len(table), nfields,
+            _ptr(D, f64, nfields * self.N, "D") if nfields else None,
+            _ptr(state_n, f64, 7 * self.N, "state_n"), _ptr(eps, f64, self.c * self.N, "eps"),
+            _ptr(sigma, f64, self.c * self.N, "sigma"), _ptr(state_np1, f64, 7 * self.N, "state_np1"),
+            _ptr(alpha, f64, nfields * self.N, "alpha") if nfields else None))
+
+    def fftg_apply_galerkin(self, target, p, out):
+        m = _macro(target)
+        f64 = self.torch.float64
+        self._check(self.lib.fftg_apply_galerkin(self.h, ct.byref(m), _ptr(p, f64, self.c * self.N, "p"),
+                                                 _ptr(out, f64, self.c * self.N, "out")))
+
+    def fftg_apply_helmholtz(self, ell2, u, out):
+        f64 = self.torch.float64
+        self._check(self.lib.fftg_apply_helmholtz(self.h, _ptr(ell2, f64, self.N, "ell2"),
+                                                  _ptr(u, f64, self.N, "u"), _ptr(out, f64, self.N, "out")))
+
+    def helmholtz_solve(self, alpha, ell2, abar, tol=1e-8, maxit=1000, ell2_ref=-1.0):
+        f64 = self.torch.float64
+        st = Stats()
+        opts = KrylovOpts(tol, maxit)
+        ok = self._check(self.lib.helmholtz_solve(self.h, _ptr(alpha, f64, self.N, "alpha"),
+                                                  _ptr(ell2, f64, self.N, "ell2"), float(ell2_ref),
+                                                  _ptr(abar, f64, self.N, "abar"), ct.byref(opts),
+                                                  ct.byref(st)))
+        d = st.as_dict()
+        d["converged"] = ok
+        return d
+
+    def fftg_solve(self, phase, table, nfields, D, state_n, target, eps, sigma, state_np1, alpha,
+                   cg_tol=1e-8, cg_maxit=5000, newton_tol=1e-8, newton_maxit=50):
+        f64 = self.torch.float64
+        tab = phase_table(table)
+        m = _macro(target)
+        st = Stats()
+        opts = KrylovOpts(cg_tol, cg_maxit)
+        ok = self._check(self.lib.fftg_solve(
+            self.h, _ptr(phase, self.torch.uint8, self.N, "phase"), tab, len(table), nfields,
+            _ptr(D, f64, nfields * self.N, "D") if nfields else None,
+            _ptr(state_n, f64, 7 * self.N, "state_n"), ct.byref(m),
+            _ptr(eps, f64, self.c * self.N, "eps"), _ptr(sigma, f64, self.c * self.N, "sigma"),
+            _ptr(state_np1, f64, 7 * self.N, "state_np1"),
+            _ptr(alpha, f64, nfields * self.N, "alpha") if nfields else None,
+            ct.byref(opts), float(newton_tol), int(newton_maxit), ct.byref(st)))
+        d = st.as_dict()
+        d["converged"] = ok
+        return d
+
+    def staggered_step(self, phase, table, nfields, state, target, sigma_out, cg_tol=1e-8,
+                       cg_maxit=5000, pcg_tol=1e-8, pcg_maxit=2000, newton_tol=1e-8,
+                       newton_maxit=50, stagger_tol=1e-6, max_stagger=20):
+        f64 = self.torch.float64
+        tab = phase_table(table)
+        m = _macro(target)
+        st = Stats()
+        hom = (ct.c_double * 12)()
+        ok = self._check(self.lib.staggered_step(
+            self.h, _ptr(phase, self.torch.uint8, self.N, "phase"), tab, len(table), nfields,
+            _ptr(state, f64, (self.c + 7 + 2 * nfields) * self.N, "state"), ct.byref(m),
+            ct.byref(KrylovOpts(cg_tol, cg_maxit)), ct.byref(KrylovOpts(pcg_tol, pcg_maxit)),
+            float(newton_tol), int(newton_maxit), float(stagger_tol), int(max_stagger),
+            _ptr(sigma_out, f64, self.c * self.N, "sigma_out"), hom, ct.byref(st)))
+        d = st.as_dict()
+        d["converged"] = ok
+        c = self.c
+        d["sigma_mean"] = np.array(hom[:c])
+        d["eps_mean"] = np.array(hom[6:6 + c])
+        return d
+
+    # ---------------------------------------------------------------- helpers
+    def state_layout(self, nfields):
+        """Slices of the packed staggered state [c + 7 + 2J][N]."""
+        c, J = self.c, nfields
+        return dict(eps=slice(0, c), epsp=slice(c, c + 6), kappa=c + 6,
+                    hist=slice(c + 7, c + 7 + J), abar=slice(c + 7 + J, c + 7 + 2 * J))

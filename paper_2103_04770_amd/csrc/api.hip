@@ -1,0 +1,1100 @@
+// Host side of the solver: handle, transform plans and tables, the Krylov,
+// Newton and staggered drivers, and the C ABI declared in include/fftg.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "fftg.h"
+#include "kernels.hpp"
+
+using fftg::cpx;
+using fftg::Geo;
+using fftg::KrylovCtl;
+using fftg::MatTable;
+using fftg::Plan;
+using fftg::Sym;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// FFTG_VERBOSE=1 prints one line per Newton correction and per Krylov solve.
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("FFTG_VERBOSE");
+    return e && e[0] == '1';
+  }();
+  return v;
+}
+
+struct HipError {
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw HipError{std::string(#expr) + ": " + hipGetErrorString(e_)};               \
+  } while (0)
+
+struct Fail {
+  fftg_status code;
+  std::string msg;
+};
+
+}  // namespace
+
+struct fftg_handle {
+  Geo g{};
+  int c = 0;
+  double h = 1.0;
+  int scheme = 0, prec = 0;
+  hipStream_t st = nullptr;
+  Plan plan[3]{};
+  cpx<double>* tw64[3]{};
+  cpx<float>* tw32[3]{};
+  double* sym64 = nullptr;
+  float* sym32 = nullptr;
+  Sym<double> S64{};
+  Sym<float> S32{};
+  // Galerkin workspace (work precision), c-component half spectra
+  void *kx = nullptr, *kr = nullptr, *kp = nullptr, *kw = nullptr;
+  cpx<double>* spec64 = nullptr;  // FP64 c-component spectrum (stress, residual)
+  void* tan = nullptr;            // compact tangent [8][N], work precision
+  bool tan_valid = false;
+  double* partials = nullptr;
+  size_t npartials = 0;
+  double* dsums = nullptr;
+  KrylovCtl* ctl = nullptr;
+  KrylovCtl* hctl = nullptr;  // pinned
+  double* hsums = nullptr;    // pinned
+  // Helmholtz workspace (work precision), scalar half spectra + ndim gradient comps
+  void *hx = nullptr, *hr = nullptr, *hp = nullptr, *hAp = nullptr, *hb = nullptr,
+       *hw = nullptr;
+  void* rtmp = nullptr;   // real scratch [max(c, 2)][N] in work precision
+  void* ell2w = nullptr;  // work-precision ell2 [N]
+  // staggered workspace (FP64)
+  int stJ = -1;
+  double *eps_k = nullptr, *eps_prev = nullptr, *ab_k = nullptr, *ab_prev = nullptr,
+         *Dj = nullptr, *alph = nullptr, *st1 = nullptr, *sig_k = nullptr;
+  void* ell2j = nullptr;  // [J][N] work precision
+  hipEvent_t ev[8]{};
+  std::string err;
+
+  bool fp32() const { return prec == FFTG_FP32_REFINED; }
+  size_t wsz() const { return fp32() ? sizeof(float) : sizeof(double); }
+};
+
+namespace {
+
+// ------------------------------------------------------------ tables
+bool smooth23(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+Plan make_plan(int n) {
+  Plan p{};
+  p.n = n;
+  int a = 0, b = 0, m = n;
+  while (m % 2 == 0) m /= 2, ++a;
+  while (m % 3 == 0) m /= 3, ++b;
+  int n8 = a / 3, rem = a % 3, n4 = 0, n2 = 0;
+  if (rem == 1 && n8 >= 1) {
+    --n8;
+    n4 = 2;
+  } else if (rem == 2) {
+    n4 = 1;
+  } else if (rem == 1) {
+    n2 = 1;
+  }
+  int s = 0;
+  for (int i = 0; i < n8; ++i) p.radix[s++] = 8;
+  for (int i = 0; i < n4; ++i) p.radix[s++] = 4;
+  for (int i = 0; i < n2; ++i) p.radix[s++] = 2;
+  for (int i = 0; i < b; ++i) p.radix[s++] = 3;
+  p.nst = s;
+  return p;
+}
+
+// exp(-2 pi i k / n), evaluated in extended precision and rounded.
+std::vector<double> twiddles(int n) {
+  std::vector<double> t(2 * (size_t)n);
+  const long double tp = 6.283185307179586476925286766559005768L;
+  for (int k = 0; k < n; ++k) {
+    long double a = tp * (long double)k / (long double)n;
+    t[2 * k] = (double)cosl(a);
+    t[2 * k + 1] = (double)(-sinl(a));
+  }
+  return t;
+}
+
+// Per-axis derivative tables: signed frequency k' (x axis: 0..n/2), theta = 2 pi k'/n.
+void axis_tables(int n, bool xaxis, double h, int scheme, std::vector<double>& pq,
+                 std::vector<double>& gq, std::vector<double>& cs) {
+  const int len = xaxis ? n / 2 + 1 : n;
+  pq.assign(len, 0.0);
+  gq.assign(len, 0.0);
+  cs.assign(len, 1.0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < len; ++k) {
+    const int ks = xaxis ? k : (k <= (n - 1) / 2 ? k : k - n);
+    const bool nyq = (n % 2 == 0) && (2 * (ks < 0 ? -ks : ks) == n);
+    const long double th = 2.0L * pi * (long double)ks / (long double)n;
+    if (scheme == FFTG_ROTATED) {
+      pq[k] = (double)(2.0L / (long double)h * sinl(th / 2.0L));
+      gq[k] = nyq ? 0.0 : pq[k];
+      cs[k] = nyq ? 0.0 : (double)cosl(th / 2.0L);
+    } else {
+      pq[k] = nyq ? 0.0 : (double)(th / (long double)h);
+      gq[k] = pq[k];
+      cs[k] = 1.0;
+    }
+  }
+}
+
+template <typename T>
+const cpx<T>* TW(fftg_handle* H, int a);
+template <>
+const cpx<double>* TW<double>(fftg_handle* H, int a) { return H->tw64[a]; }
+template <>
+const cpx<float>* TW<float>(fftg_handle* H, int a) { return H->tw32[a]; }
+template <typename T>
+const Sym<T>& SY(fftg_handle* H);
+template <>
+const Sym<double>& SY<double>(fftg_handle* H) { return H->S64; }
+template <>
+const Sym<float>& SY<float>(fftg_handle* H) { return H->S32; }
+template <typename T>
+cpx<T>* C(void* p) { return reinterpret_cast<cpx<T>*>(p); }
+
+void* dalloc(size_t bytes) {
+  void* p = nullptr;
+  HIPCHK(hipMalloc(&p, bytes < 256 ? 256 : bytes));
+  return p;
+}
+void dfree(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void sync(fftg_handle* H) { HIPCHK(hipStreamSynchronize(H->st)); }
+void check_launch() { HIPCHK(hipGetLastError()); }
+
+// read back the control block
+KrylovCtl read_ctl(fftg_handle* H) {
+  HIPCHK(hipMemcpyAsync(H->hctl, H->ctl, sizeof(KrylovCtl), hipMemcpyDeviceToHost, H->st));
+  sync(H);
+  return *H->hctl;
+}
+void write_ctl(fftg_handle* H, const KrylovCtl& k) {
+  *H->hctl = k;
+  HIPCHK(hipMemcpyAsync(H->ctl, H->hctl, sizeof(KrylovCtl), hipMemcpyHostToDevice, H->st));
+}
+// finalise nred sums of partials [nred][nb] and read them back
+void read_sums(fftg_handle* H, int nb, int nred, double* out) {
+  fftg::launch_fin_sums(H->partials, nb, nred, H->dsums, H->st);
+  HIPCHK(hipMemcpyAsync(H->hsums, H->dsums, sizeof(double) * nred, hipMemcpyDeviceToHost, H->st));
+  sync(H);
+  for (int i = 0; i < nred; ++i) out[i] = H->hsums[i];
+}
+
+// ------------------------------------------------------------ 3D transforms
+template <typename T>
+void fwd3(fftg_handle* H, int ncomp, const T* in, cpx<T>* out, const KrylovCtl* ctl = nullptr) {
+  const Geo& g = H->g;
+  fftg::launch_x_r2c<T>(H->plan[0], TW<T>(H, 0), in, out, (long long)ncomp * g.n2 * g.n3, g.n1,
+                        g.n1h, H->st);
+  if (g.n2 > 1)
+    fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), out, (long long)ncomp * g.n3 * g.n1h, g.n1h,
+                            (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st);
+  if (g.n3 > 1)
+    fftg::launch_strided<T>(H->plan[2], TW<T>(H, 2), out, (long long)ncomp * g.n2 * g.n1h,
+                            (long long)g.n2 * g.n1h, g.Ns, (long long)g.n2 * g.n1h, true, ctl,
+                            H->st);
+}
+
+// in is destroyed; out (=|+=) scale * inverse
+template <typename T, typename TO>
+void inv3(fftg_handle* H, int ncomp, cpx<T>* in, TO* out, T scale, bool acc) {
+  const Geo& g = H->g;
+  if (g.n3 > 1)
+    fftg::launch_strided<T>(H->plan[2], TW<T>(H, 2), in, (long long)ncomp * g.n2 * g.n1h,
+                            (long long)g.n2 * g.n1h, g.Ns, (long long)g.n2 * g.n1h, false,
+                            nullptr, H->st);
+  if (g.n2 > 1)
+    fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), in, (long long)ncomp * g.n3 * g.n1h, g.n1h,
+                            (long long)g.n2 * g.n1h, g.n1h, false, nullptr, H->st);
+  fftg::launch_x_c2r<T, TO>(H->plan[0], TW<T>(H, 0), in, out, (long long)ncomp * g.n2 * g.n3,
+                            g.n1, g.n1h, scale, acc, H->st);
+}
+
+// inner (non-outer) passes of an operator application on an ncomp spectrum
+template <typename T>
+void inner_inv(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl) {
+  const Geo& g = H->g;
+  if (g.ndim == 3 && g.n2 > 1)
+    fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), w, (long long)ncomp * g.n3 * g.n1h, g.n1h,
+                            (long long)g.n2 * g.n1h, g.n1h, false, ctl, H->st);
+}
+template <typename T>
+void inner_fwd(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl) {
+  const Geo& g = H->g;
+  if (g.ndim == 3 && g.n2 > 1)
+    fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), w, (long long)ncomp * g.n3 * g.n1h, g.n1h,
+                            (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st);
+}
+int outer_axis(fftg_handle* H) { return H->g.ndim == 3 ? 2 : 1; }
+
+MatTable make_table(const fftg_phase* tab, int nphase, int J) {
+  MatTable t{};
+  t.nphase = nphase;
+  for (int p = 0; p < nphase; ++p) {
+    const fftg_phase& q = tab[p];
+    fftg::Mat& m = t.m[p];
+    m.model = q.model;
+    m.dfield = q.dfield;
+    m.mu = q.E / (2.0 * (1.0 + q.nu));
+    m.K = q.E / (3.0 * (1.0 - 2.0 * q.nu));
+    m.sy = q.sy;
+    m.H = q.H;
+    m.dC = q.dC;
+    m.dR = q.dR;
+    m.dmax = q.dmax;
+    for (int j = 0; j < FFTG_MAX_FIELDS; ++j) m.ell2[j] = q.ell[j] * q.ell[j];
+  }
+  (void)J;
+  return t;
+}
+
+void validate_table(const fftg_phase* tab, int nphase, int nfields) {
+  if (!tab || nphase < 1 || nphase > FFTG_MAX_PHASES)
+    throw Fail{FFTG_E_INVALID, "phase table: null or nphase outside [1, 16]"};
+  if (nfields < 0 || nfields > FFTG_MAX_FIELDS)
+    throw Fail{FFTG_E_INVALID, "nfields outside [0, 4]"};
+  for (int p = 0; p < nphase; ++p) {
+    const fftg_phase& q = tab[p];
+    if (q.model < 0 || q.model > 2) throw Fail{FFTG_E_INVALID, "unknown phase model"};
+    if (!(q.E > 0) || !(q.nu > -1.0 && q.nu < 0.5))
+      throw Fail{FFTG_E_INVALID, "phase elastic constants out of range"};
+    if (q.dfield >= nfields) throw Fail{FFTG_E_INVALID, "phase dfield >= nfields"};
+    if (q.model != FFTG_ELASTIC && q.dfield >= 0 && !(q.dR > q.dC))
+      throw Fail{FFTG_E_INVALID, "damage law needs dR > dC"};
+  }
+}
+
+void validate_macro(const fftg_macro* t, int c) {
+  if (!t) throw Fail{FFTG_E_INVALID, "null macro target"};
+  for (int k = 0; k < c; ++k)
+    if (t->mask[k] > 1) throw Fail{FFTG_E_INVALID, "macro mask entries must be 0 or 1"};
+}
+
+// ------------------------------------------------------------ Galerkin CG
+// Solves G*(K : dx) = b in the half spectrum, b in H->kr, dx -> H->kx.
+template <typename T>
+void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double tol, int maxit,
+                 int& iters, int& status) {
+  const Geo& g = H->g;
+  const int c = H->c;
+  const bool zo = g.ndim == 3;
+  const int oa = outer_axis(H);
+  KrylovCtl k{};
+  k.rz = bb;
+  k.rr = bb;
+  k.bb = bb;
+  k.tol2 = tol * tol * bb;
+  k.maxit = maxit;
+  k.done = (bb == 0.0 || maxit <= 0) ? 1 : 0;
+  write_ctl(H, k);
+  HIPCHK(hipMemsetAsync(H->kx, 0, sizeof(cpx<T>) * c * g.Ns, H->st));
+  HIPCHK(hipMemsetAsync(H->kp, 0, sizeof(cpx<T>) * c * g.Ns, H->st));
+  const T scl = T(1.0 / (double)g.N);
+  int chunk = 2;
+  while (!k.done) {
+    for (int it = 0; it < chunk; ++it) {
+      fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr), C<T>(H->kp),
+                                  C<T>(H->kx), C<T>(H->kw), H->ctl, H->st);
+      inner_inv<T>(H, c, C<T>(H->kw), H->ctl);
+      fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
+                                     reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st);
+      inner_fwd<T>(H, c, C<T>(H->kw), H->ctl);
+      const int nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
+                                                 C<T>(H->kw), H->partials, H->ctl, H->st);
+      fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
+      const int nr = fftg::launch_gal_resid<T>(g, c, SY<T>(H), mask, C<T>(H->kr), C<T>(H->kw),
+                                               H->partials, H->ctl, H->st);
+      fftg::launch_fin_beta(H->partials, nr, 1, H->ctl, H->st);
+    }
+    check_launch();
+    k = read_ctl(H);
+    if (chunk < 16) chunk *= 2;
+  }
+  fftg::launch_xfinal<T>(C<T>(H->kx), C<T>(H->kp), (long long)c * g.Ns, H->ctl, H->st);
+  check_launch();
+  iters = k.iters;
+  status = k.done;
+}
+
+// ------------------------------------------------------------ Helmholtz PCG
+// Solves L x = b for a scalar field; alpha, abar FP64 [N]; ell2 work precision [N].
+template <typename T>
+void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double ell2_ref,
+                   double* abar, double tol, int maxit, int& iters, double& relres,
+                   int& status) {
+  const Geo& g = H->g;
+  const bool zo = g.ndim == 3;
+  const int oa = outer_axis(H);
+  const int nd = g.ndim;
+  const T scl = T(1.0 / (double)g.N);
+  // b = F(alpha)
+  const T* ain;
+  if (H->fp32()) {
+    fftg::launch_convert<double, float>(g.N, alpha, reinterpret_cast<float*>(H->rtmp), H->st);
+    ain = reinterpret_cast<const T*>(H->rtmp);
+  } else {
+    ain = reinterpret_cast<const T*>(alpha);
+  }
+  fwd3<T>(H, 1, ain, C<T>(H->hb));
+  fftg::launch_hermitize<T>(g, 1, C<T>(H->hb), H->st);
+  double bb;
+  read_sums(H, fftg::launch_wnorm2<T>(g, 1, C<T>(H->hb), H->partials, H->st), 1, &bb);
+  if (bb == 0.0) {
+    HIPCHK(hipMemsetAsync(abar, 0, sizeof(double) * g.N, H->st));
+    iters = 0;
+    relres = 0.0;
+    status = 1;
+    return;
+  }
+  if (!(ell2_ref > 0.0)) {
+    double s;
+    read_sums(H, fftg::launch_sum_ell2<T>(g.N, ell2, H->partials, H->st), 1, &s);
+    ell2_ref = s / (double)g.N;
+  }
+  KrylovCtl k{};
+  k.bb = bb;
+  k.tol2 = tol * tol * bb;
+  k.maxit = maxit;
+  k.ell2ref = ell2_ref;
+  write_ctl(H, k);
+  // x0 = F(abar)
+  const T* xin;
+  if (H->fp32()) {
+    fftg::launch_convert<double, float>(g.N, abar, reinterpret_cast<float*>(H->rtmp), H->st);
+    xin = reinterpret_cast<const T*>(H->rtmp);
+  } else {
+    xin = reinterpret_cast<const T*>(abar);
+  }
+  fwd3<T>(H, 1, xin, C<T>(H->hx));
+  // r = b - L x0
+  fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), false, C<T>(H->hr),
+                            C<T>(H->hx), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
+  inner_inv<T>(H, nd, C<T>(H->hw), nullptr);
+  fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, nullptr,
+                                  H->st);
+  inner_fwd<T>(H, nd, C<T>(H->hw), nullptr);
+  fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hx), C<T>(H->hw),
+                            C<T>(H->hAp), nullptr, H->ctl, H->st);
+  const int nr0 = fftg::launch_h_resid<T>(g, SY<T>(H), true, C<T>(H->hr), C<T>(H->hb),
+                                          C<T>(H->hAp), H->partials, H->ctl, H->st);
+  double s2[2];
+  read_sums(H, nr0, 2, s2);
+  k.rz = s2[0];
+  k.rr = s2[1];
+  k.done = (s2[1] <= k.tol2 || maxit <= 0) ? 1 : 0;
+  write_ctl(H, k);
+  HIPCHK(hipMemsetAsync(H->hp, 0, sizeof(cpx<T>) * g.Ns, H->st));
+  int chunk = 2;
+  while (!k.done) {
+    for (int it = 0; it < chunk; ++it) {
+      fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true, C<T>(H->hr),
+                                C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
+      inner_inv<T>(H, nd, C<T>(H->hw), H->ctl);
+      fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, H->ctl,
+                                      H->st);
+      inner_fwd<T>(H, nd, C<T>(H->hw), H->ctl);
+      const int nb = fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H),
+                                               C<T>(H->hp), C<T>(H->hw), C<T>(H->hAp),
+                                               H->partials, H->ctl, H->st);
+      fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
+      const int nr = fftg::launch_h_resid<T>(g, SY<T>(H), false, C<T>(H->hr), C<T>(H->hb),
+                                             C<T>(H->hAp), H->partials, H->ctl, H->st);
+      fftg::launch_fin_beta(H->partials, nr, 2, H->ctl, H->st);
+    }
+    check_launch();
+    k = read_ctl(H);
+    if (chunk < 16) chunk *= 2;
+  }
+  fftg::launch_xfinal<T>(C<T>(H->hx), C<T>(H->hp), g.Ns, H->ctl, H->st);
+  inv3<T, double>(H, 1, C<T>(H->hx), abar, scl, false);
+  check_launch();
+  if (verbose())
+    std::fprintf(stderr, "[fftg] pcg iters %d status %d rr/bb %.3e ell2ref %.4g\n", k.iters,
+                 k.done, k.rr / bb, ell2_ref);
+  iters = k.iters;
+  relres = std::sqrt(k.rr / bb);
+  status = k.done;
+}
+
+// ------------------------------------------------------------ mechanics
+struct MechOut {
+  int newton = 0, cg = 0;
+  double relres = 0.0;
+  bool converged = false;
+  double t_const = 0.0, t_cg = 0.0;
+};
+
+void comp_means(fftg_handle* H, int ncomp, const double* f, double* out) {
+  read_sums(H, fftg::launch_comp_sums(H->g.N, ncomp, f, H->partials, H->st), ncomp, out);
+  for (int k = 0; k < ncomp; ++k) out[k] /= (double)H->g.N;
+}
+
+double wall_ms(std::chrono::steady_clock::time_point a) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+}
+
+template <typename T>
+MechOut mechanics(fftg_handle* H, const unsigned char* phase, const MatTable& tab, int J,
+                  const double* D, const double* state_n, const fftg_macro* tgt, double* eps,
+                  double* sigma, double* st_np1, double* alpha, const fftg_krylov_opts* cg,
+                  double ntol, int nmaxit) {
+  const Geo& g = H->g;
+  const int c = H->c;
+  MechOut o;
+  // move the strain-controlled means to their targets
+  double mean[6], delta[6] = {0, 0, 0, 0, 0, 0};
+  comp_means(H, c, eps, mean);
+  bool any = false;
+  for (int k = 0; k < c; ++k)
+    if (!tgt->mask[k]) {
+      delta[k] = tgt->E[k] - mean[k];
+      any = any || delta[k] != 0.0;
+    }
+  if (any) fftg::launch_add_const(g.N, c, eps, delta, H->st);
+  double sref = 0.0;
+  for (int p = 0; p < tab.nphase; ++p) sref = std::max(sref, tab.m[p].sy);
+  if (!(sref > 0.0)) sref = 1.0;
+  double Sbar[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < c; ++k) Sbar[k] = tgt->mask[k] ? tgt->S[k] : 0.0;
+  const double sqN = std::sqrt((double)g.N);
+  int r = 0;
+  while (true) {
+    auto t0 = std::chrono::steady_clock::now();
+    fftg::launch_constitutive<T>(tab, g, c, J, phase, eps, state_n, D, sigma, st_np1, alpha,
+                                 reinterpret_cast<T*>(H->tan), H->st);
+    H->tan_valid = true;
+    check_launch();
+    sync(H);
+    o.t_const += wall_ms(t0);
+    t0 = std::chrono::steady_clock::now();
+    fwd3<double>(H, c, sigma, H->spec64);
+    fftg::launch_hermitize<double>(g, c, H->spec64, H->st);
+    const int nr = fftg::launch_gal_rhs<T>(g, c, H->S64, tgt->mask, Sbar, H->spec64, C<T>(H->kr),
+                                           H->partials, H->st);
+    double s2[2];
+    read_sums(H, nr, 2, s2);
+    const double nb = std::sqrt(s2[0] / (double)g.N), ns = std::sqrt(s2[1] / (double)g.N);
+    o.relres = nb / std::max(ns, sref * sqN);
+    if (!std::isfinite(o.relres)) throw Fail{FFTG_E_NONFINITE, "non-finite Newton residual"};
+    if (r >= 1 && o.relres <= ntol) {
+      o.converged = true;
+      o.t_cg += wall_ms(t0);
+      break;
+    }
+    if (r >= nmaxit) {
+      o.t_cg += wall_ms(t0);
+      break;
+    }
+    int it = 0, status = 0;
+    galerkin_cg<T>(H, tgt->mask, s2[0], cg->tol, cg->maxit, it, status);
+    if (verbose()) {
+      const KrylovCtl kk = *H->hctl;
+      std::fprintf(stderr, "[fftg] newton %d relres %.3e |b| %.3e cg %d status %d rr/bb %.3e\n", r,
+                   o.relres, nb, it, status, kk.rr / kk.bb);
+    }
+    if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Galerkin CG breakdown (p.Ap <= 0)"};
+    if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Galerkin CG"};
+    o.cg += it;
+    inv3<T, double>(H, c, C<T>(H->kx), eps, T(1.0 / (double)g.N), true);
+    check_launch();
+    sync(H);
+    o.t_cg += wall_ms(t0);
+    ++r;
+  }
+  o.newton = r;
+  return o;
+}
+
+// ------------------------------------------------------------ workspace
+void alloc_helm(fftg_handle* H) {
+  if (H->hx) return;
+  const Geo& g = H->g;
+  const size_t cs = 2 * H->wsz() * (size_t)g.Ns;
+  H->hx = dalloc(cs);
+  H->hr = dalloc(cs);
+  H->hp = dalloc(cs);
+  H->hAp = dalloc(cs);
+  H->hb = dalloc(cs);
+  H->hw = dalloc(cs * g.ndim);
+  H->ell2w = dalloc(H->wsz() * (size_t)g.N);
+}
+
+void alloc_stagger(fftg_handle* H, int J) {
+  if (H->stJ >= J) return;
+  dfree((void*&)H->eps_k);
+  dfree((void*&)H->eps_prev);
+  dfree((void*&)H->ab_k);
+  dfree((void*&)H->ab_prev);
+  dfree((void*&)H->Dj);
+  dfree((void*&)H->alph);
+  dfree((void*&)H->st1);
+  dfree((void*&)H->sig_k);
+  dfree(H->ell2j);
+  const size_t N = H->g.N;
+  const size_t Jm = J > 0 ? J : 1;
+  H->eps_k = (double*)dalloc(sizeof(double) * H->c * N);
+  H->eps_prev = (double*)dalloc(sizeof(double) * H->c * N);
+  H->sig_k = (double*)dalloc(sizeof(double) * H->c * N);
+  H->ab_k = (double*)dalloc(sizeof(double) * Jm * N);
+  H->ab_prev = (double*)dalloc(sizeof(double) * Jm * N);
+  H->Dj = (double*)dalloc(sizeof(double) * Jm * N);
+  H->alph = (double*)dalloc(sizeof(double) * Jm * N);
+  H->st1 = (double*)dalloc(sizeof(double) * 7 * N);
+  H->ell2j = dalloc(H->wsz() * Jm * N);
+  H->stJ = J;
+}
+
+void destroy(fftg_handle* H) {
+  for (int a = 0; a < 3; ++a) {
+    dfree((void*&)H->tw64[a]);
+    dfree((void*&)H->tw32[a]);
+  }
+  dfree((void*&)H->sym64);
+  dfree((void*&)H->sym32);
+  dfree(H->kx);
+  dfree(H->kr);
+  dfree(H->kp);
+  dfree(H->kw);
+  dfree((void*&)H->spec64);
+  dfree(H->tan);
+  dfree((void*&)H->partials);
+  dfree((void*&)H->dsums);
+  dfree((void*&)H->ctl);
+  if (H->hctl) (void)hipHostFree(H->hctl);
+  if (H->hsums) (void)hipHostFree(H->hsums);
+  dfree(H->hx);
+  dfree(H->hr);
+  dfree(H->hp);
+  dfree(H->hAp);
+  dfree(H->hb);
+  dfree(H->hw);
+  dfree(H->rtmp);
+  dfree(H->ell2w);
+  dfree((void*&)H->eps_k);
+  dfree((void*&)H->eps_prev);
+  dfree((void*&)H->ab_k);
+  dfree((void*&)H->ab_prev);
+  dfree((void*&)H->Dj);
+  dfree((void*&)H->alph);
+  dfree((void*&)H->st1);
+  dfree((void*&)H->sig_k);
+  dfree(H->ell2j);
+  for (auto& e : H->ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+fftg_status run_guarded(fftg_handle* H, const std::function<fftg_status()>& f) {
+  try {
+    return f();
+  } catch (const Fail& e) {
+    if (H) H->err = e.msg;
+    return e.code;
+  } catch (const HipError& e) {
+    if (H) H->err = e.msg;
+    return FFTG_E_HIP;
+  } catch (const std::exception& e) {
+    if (H) H->err = e.what();
+    return FFTG_E_HIP;
+  }
+}
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** out) {
+  g_create_error.clear();
+  if (!grid || !out) {
+    g_create_error = "fftg_create: null argument";
+    return FFTG_E_INVALID;
+  }
+  *out = nullptr;
+  if (grid->ndim != 2 && grid->ndim != 3) {
+    g_create_error = "fftg_create: ndim must be 2 or 3";
+    return FFTG_E_INVALID;
+  }
+  const int n1 = grid->n[0], n2 = grid->n[1], n3 = grid->ndim == 3 ? grid->n[2] : 1;
+  if (grid->ndim == 2 && grid->n[2] != 1 && grid->n[2] != 0) {
+    g_create_error = "fftg_create: n[2] must be 1 in 2D";
+    return FFTG_E_INVALID;
+  }
+  if (n1 < 2 || n2 < 1 || n3 < 1 || !(grid->h > 0.0)) {
+    g_create_error = "fftg_create: bad grid size or voxel size";
+    return FFTG_E_INVALID;
+  }
+  if (grid->scheme != FFTG_ROTATED && grid->scheme != FFTG_SPECTRAL) {
+    g_create_error = "fftg_create: unknown derivative scheme";
+    return FFTG_E_INVALID;
+  }
+  if (grid->prec != FFTG_FP64 && grid->prec != FFTG_FP32_REFINED) {
+    g_create_error = "fftg_create: unknown precision";
+    return FFTG_E_INVALID;
+  }
+  const int nmax = grid->ndim == 3 ? 256 : 512;
+  if (!smooth23(n1) || !smooth23(n2) || !smooth23(n3) || n1 % 2 != 0 || n1 > nmax || n2 > nmax ||
+      n3 > nmax) {
+    g_create_error =
+        "fftg_create: unsupported size (need N = 2^a 3^b, N1 even, N <= 256 in 3D, 512 in 2D)";
+    return FFTG_E_UNSUPPORTED;
+  }
+  fftg_handle* H = new fftg_handle();
+  fftg_status rc = run_guarded(H, [&]() -> fftg_status {
+    H->g.ndim = grid->ndim;
+    H->g.n1 = n1;
+    H->g.n2 = n2;
+    H->g.n3 = n3;
+    H->g.n1h = n1 / 2 + 1;
+    H->g.N = (long long)n1 * n2 * n3;
+    H->g.Ns = (long long)H->g.n1h * n2 * n3;
+    H->c = grid->ndim == 3 ? 6 : 3;
+    H->h = grid->h;
+    H->scheme = grid->scheme;
+    H->prec = grid->prec;
+    H->st = reinterpret_cast<hipStream_t>(hip_stream);
+    const int ns[3] = {n1, n2, n3};
+    std::vector<double> pq[3], gq[3], cs[3];
+    for (int a = 0; a < 3; ++a) {
+      H->plan[a] = make_plan(ns[a]);
+      std::vector<double> t = twiddles(ns[a]);
+      H->tw64[a] = (cpx<double>*)dalloc(sizeof(double) * t.size());
+      HIPCHK(hipMemcpy(H->tw64[a], t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+      std::vector<float> tf(t.begin(), t.end());
+      H->tw32[a] = (cpx<float>*)dalloc(sizeof(float) * tf.size());
+      HIPCHK(hipMemcpy(H->tw32[a], tf.data(), sizeof(float) * tf.size(), hipMemcpyHostToDevice));
+      axis_tables(ns[a], a == 0, grid->h, grid->scheme, pq[a], gq[a], cs[a]);
+    }
+    std::vector<double> all;
+    int off = 0;
+    for (int a = 0; a < 3; ++a) {
+      H->S64.pq[a] = off;
+      all.insert(all.end(), pq[a].begin(), pq[a].end());
+      off += (int)pq[a].size();
+    }
+    for (int a = 0; a < 3; ++a) {
+      H->S64.gq[a] = off;
+      all.insert(all.end(), gq[a].begin(), gq[a].end());
+      off += (int)gq[a].size();
+    }
+    for (int a = 0; a < 3; ++a) {
+      H->S64.cs[a] = off;
+      all.insert(all.end(), cs[a].begin(), cs[a].end());
+      off += (int)cs[a].size();
+    }
+    H->sym64 = (double*)dalloc(sizeof(double) * all.size());
+    HIPCHK(hipMemcpy(H->sym64, all.data(), sizeof(double) * all.size(), hipMemcpyHostToDevice));
+    std::vector<float> allf(all.begin(), all.end());
+    H->sym32 = (float*)dalloc(sizeof(float) * allf.size());
+    HIPCHK(hipMemcpy(H->sym32, allf.data(), sizeof(float) * allf.size(), hipMemcpyHostToDevice));
+    H->S64.base = H->sym64;
+    H->S32.base = H->sym32;
+    for (int a = 0; a < 3; ++a) {
+      H->S32.pq[a] = H->S64.pq[a];
+      H->S32.gq[a] = H->S64.gq[a];
+      H->S32.cs[a] = H->S64.cs[a];
+    }
+    const Geo& g = H->g;
+    const size_t cs_bytes = 2 * H->wsz() * (size_t)H->c * g.Ns;
+    H->kx = dalloc(cs_bytes);
+    H->kr = dalloc(cs_bytes);
+    H->kp = dalloc(cs_bytes);
+    H->kw = dalloc(cs_bytes);
+    H->spec64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * 6 * g.Ns);
+    H->tan = dalloc(H->wsz() * 8 * (size_t)g.N);
+    H->rtmp = dalloc(H->wsz() * (size_t)std::max(H->c, 2) * g.N);
+    // partials: largest block count of any reduction
+    long long maxb = fftg::RED_BLOCKS * 16;
+    for (int a = 1; a < 3; ++a) {
+      const long long nl = (long long)H->c * g.Ns / std::max(1, ns[a]);
+      maxb = std::max(maxb, 2 * (nl + 1));
+    }
+    H->npartials = (size_t)maxb;
+    H->partials = (double*)dalloc(sizeof(double) * H->npartials);
+    H->dsums = (double*)dalloc(sizeof(double) * 64);
+    H->ctl = (KrylovCtl*)dalloc(sizeof(KrylovCtl));
+    HIPCHK(hipHostMalloc((void**)&H->hctl, sizeof(KrylovCtl), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * 64, hipHostMallocDefault));
+    for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
+    return FFTG_OK;
+  });
+  if (rc != FFTG_OK) {
+    g_create_error = H->err;
+    destroy(H);
+    delete H;
+    return rc;
+  }
+  *out = H;
+  return FFTG_OK;
+}
+
+fftg_status fftg_destroy(fftg_handle* H) {
+  if (!H) return FFTG_E_INVALID;
+  (void)hipStreamSynchronize(H->st);
+  destroy(H);
+  delete H;
+  return FFTG_OK;
+}
+
+const char* fftg_last_error(const fftg_handle* H) {
+  return H ? H->err.c_str() : g_create_error.c_str();
+}
+
+fftg_status fftg_forward(fftg_handle* H, int ncomp, const double* in, double* out) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!in || !out || ncomp < 1 || ncomp > 8) throw Fail{FFTG_E_INVALID, "fftg_forward: bad args"};
+    // transform through the work buffer so `in` is not modified
+    fwd3<double>(H, ncomp, in, reinterpret_cast<cpx<double>*>(out));
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_inverse(fftg_handle* H, int ncomp, const double* in, double* out) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!in || !out || ncomp < 1 || ncomp > 6) throw Fail{FFTG_E_INVALID, "fftg_inverse: bad args"};
+    const Geo& g = H->g;
+    HIPCHK(hipMemcpyAsync(H->spec64, in, sizeof(cpx<double>) * ncomp * g.Ns,
+                          hipMemcpyDeviceToDevice, H->st));
+    inv3<double, double>(H, ncomp, H->spec64, out, 1.0 / (double)g.N, false);
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_project(fftg_handle* H, const fftg_macro* tgt, const double* tau, double* out) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!tau || !out) throw Fail{FFTG_E_INVALID, "fftg_project: null pointer"};
+    validate_macro(tgt, H->c);
+    const Geo& g = H->g;
+    fwd3<double>(H, H->c, tau, H->spec64);
+    fftg::launch_project<double>(g, H->c, H->S64, tgt->mask, H->spec64, H->st);
+    inv3<double, double>(H, H->c, H->spec64, out, 1.0 / (double)g.N, false);
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_constitutive(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
+                              int nphase, int nfields, const double* D, const double* state_n,
+                              const double* eps, double* sigma, double* state_np1,
+                              double* alpha) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, nfields);
+    if (!phase || !state_n || !eps || !sigma || !state_np1 || (nfields > 0 && (!D || !alpha)))
+      throw Fail{FFTG_E_INVALID, "fftg_constitutive: null pointer"};
+    MatTable t = make_table(tab, nphase, nfields);
+    if (H->fp32())
+      fftg::launch_constitutive<float>(t, H->g, H->c, nfields, phase, eps, state_n, D, sigma,
+                                       state_np1, alpha, reinterpret_cast<float*>(H->tan), H->st);
+    else
+      fftg::launch_constitutive<double>(t, H->g, H->c, nfields, phase, eps, state_n, D, sigma,
+                                        state_np1, alpha, reinterpret_cast<double*>(H->tan), H->st);
+    H->tan_valid = true;
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_apply_galerkin(fftg_handle* H, const fftg_macro* tgt, const double* p,
+                                double* out) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!p || !out) throw Fail{FFTG_E_INVALID, "fftg_apply_galerkin: null pointer"};
+    validate_macro(tgt, H->c);
+    if (!H->tan_valid) throw Fail{FFTG_E_INVALID, "fftg_apply_galerkin: no tangent yet"};
+    if (H->fp32()) throw Fail{FFTG_E_UNSUPPORTED, "fftg_apply_galerkin: FP64 handles only"};
+    const Geo& g = H->g;
+    const int c = H->c;
+    // out = G*(K : p) through the same passes as the CG operator
+    fwd3<double>(H, c, p, C<double>(H->kw));
+    const int oa = outer_axis(H);
+    if (g.ndim == 3)
+      fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
+                                   (long long)c * g.n2 * g.n1h, (long long)g.n2 * g.n1h, g.Ns,
+                                   (long long)g.n2 * g.n1h, false, nullptr, H->st);
+    else
+      fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
+                                   (long long)c * g.n1h, g.n1h, g.Ns, g.n1h, false, nullptr,
+                                   H->st);
+    inner_inv<double>(H, c, C<double>(H->kw), nullptr);
+    fftg::launch_x_fused_gal<double, double>(H->plan[0], TW<double>(H, 0), g, c, C<double>(H->kw),
+                                             reinterpret_cast<const double*>(H->tan),
+                                             1.0 / (double)g.N, nullptr, H->st);
+    inner_fwd<double>(H, c, C<double>(H->kw), nullptr);
+    if (g.ndim == 3)
+      fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
+                                   (long long)c * g.n2 * g.n1h, (long long)g.n2 * g.n1h, g.Ns,
+                                   (long long)g.n2 * g.n1h, true, nullptr, H->st);
+    else
+      fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
+                                   (long long)c * g.n1h, g.n1h, g.Ns, g.n1h, true, nullptr,
+                                   H->st);
+    fftg::launch_project<double>(g, c, H->S64, tgt->mask, C<double>(H->kw), H->st);
+    inv3<double, double>(H, c, C<double>(H->kw), out, 1.0 / (double)g.N, false);
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_apply_helmholtz(fftg_handle* H, const double* ell2, const double* u,
+                                 double* out) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!ell2 || !u || !out) throw Fail{FFTG_E_INVALID, "fftg_apply_helmholtz: null pointer"};
+    if (H->fp32()) throw Fail{FFTG_E_UNSUPPORTED, "fftg_apply_helmholtz: FP64 handles only"};
+    alloc_helm(H);
+    const Geo& g = H->g;
+    const bool zo = g.ndim == 3;
+    const int oa = outer_axis(H);
+    KrylovCtl k{};
+    write_ctl(H, k);
+    fwd3<double>(H, 1, u, C<double>(H->hx));
+    fftg::launch_h_dir_inv<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64, false,
+                                   C<double>(H->hr), C<double>(H->hx), C<double>(H->hx),
+                                   C<double>(H->hw), H->ctl, H->st);
+    inner_inv<double>(H, g.ndim, C<double>(H->hw), nullptr);
+    fftg::launch_x_fused_helm<double, double>(H->plan[0], TW<double>(H, 0), g, C<double>(H->hw),
+                                              ell2, 1.0 / (double)g.N, nullptr, H->st);
+    inner_fwd<double>(H, g.ndim, C<double>(H->hw), nullptr);
+    fftg::launch_h_div_fwd<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64,
+                                   C<double>(H->hx), C<double>(H->hw), C<double>(H->hAp), nullptr,
+                                   H->ctl, H->st);
+    inv3<double, double>(H, 1, C<double>(H->hAp), out, 1.0 / (double)g.N, false);
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status helmholtz_solve(fftg_handle* H, const double* alpha, const double* ell2,
+                            double ell2_ref, double* abar, const fftg_krylov_opts* opts,
+                            fftg_stats* stats) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!alpha || !ell2 || !abar || !opts)
+      throw Fail{FFTG_E_INVALID, "helmholtz_solve: null pointer"};
+    alloc_helm(H);
+    auto t0 = std::chrono::steady_clock::now();
+    int it = 0, status = 0;
+    double rel = 0.0;
+    if (H->fp32()) {
+      fftg::launch_convert<double, float>(H->g.N, ell2, reinterpret_cast<float*>(H->ell2w), H->st);
+      helmholtz_pcg<float>(H, alpha, reinterpret_cast<const float*>(H->ell2w), ell2_ref, abar,
+                           opts->tol, opts->maxit, it, rel, status);
+    } else {
+      helmholtz_pcg<double>(H, alpha, ell2, ell2_ref, abar, opts->tol, opts->maxit, it, rel,
+                            status);
+    }
+    sync(H);
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->pcg_iters = it;
+      stats->relres = rel;
+      stats->t_ms[2] = wall_ms(t0);
+    }
+    if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
+    if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+    return status == 1 ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+}
+
+fftg_status fftg_solve(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
+                       int nphase, int nfields, const double* D, const double* state_n,
+                       const fftg_macro* target, double* eps, double* sigma, double* state_np1,
+                       double* alpha, const fftg_krylov_opts* cg, double newton_tol,
+                       int newton_maxit, fftg_stats* stats) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, nfields);
+    validate_macro(target, H->c);
+    if (!phase || !state_n || !eps || !sigma || !state_np1 || !cg ||
+        (nfields > 0 && (!D || !alpha)))
+      throw Fail{FFTG_E_INVALID, "fftg_solve: null pointer"};
+    MatTable t = make_table(tab, nphase, nfields);
+    MechOut o = H->fp32() ? mechanics<float>(H, phase, t, nfields, D, state_n, target, eps, sigma,
+                                             state_np1, alpha, cg, newton_tol, newton_maxit)
+                          : mechanics<double>(H, phase, t, nfields, D, state_n, target, eps,
+                                              sigma, state_np1, alpha, cg, newton_tol,
+                                              newton_maxit);
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->newton_iters = o.newton;
+      stats->cg_iters = o.cg;
+      stats->relres = o.relres;
+      stats->t_ms[0] = o.t_const;
+      stats->t_ms[1] = o.t_cg;
+    }
+    return o.converged ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+}
+
+fftg_status staggered_step(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
+                           int nphase, int nfields, double* state, const fftg_macro* target,
+                           const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
+                           double newton_tol, int newton_maxit, double stagger_tol,
+                           int max_stagger_iters, double* sigma_out, double* homog_out,
+                           fftg_stats* stats) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, nfields);
+    validate_macro(target, H->c);
+    if (!phase || !state || !cg || !pcg || !sigma_out || !homog_out)
+      throw Fail{FFTG_E_INVALID, "staggered_step: null pointer"};
+    if (max_stagger_iters < 1) throw Fail{FFTG_E_INVALID, "max_stagger_iters must be >= 1"};
+    auto t_all = std::chrono::steady_clock::now();
+    const Geo& g = H->g;
+    const int c = H->c, J = nfields;
+    const long long N = g.N;
+    alloc_stagger(H, J);
+    alloc_helm(H);
+    MatTable t = make_table(tab, nphase, J);
+    double* s_eps = state;
+    double* s_epsp = state + (long long)c * N;  // eps_p (6) followed by kappa (1)
+    double* s_hist = state + (long long)(c + 7) * N;
+    double* s_abar = state + (long long)(c + 7 + J) * N;
+    HIPCHK(hipMemcpyAsync(H->eps_k, s_eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
+    if (J > 0)
+      HIPCHK(hipMemcpyAsync(H->ab_k, s_abar, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
+                            H->st));
+    for (int j = 0; j < J; ++j) {
+      if (H->fp32())
+        fftg::launch_ell2<float>(t, N, j, phase, reinterpret_cast<float*>(H->ell2j) + j * N, H->st);
+      else
+        fftg::launch_ell2<double>(t, N, j, phase, reinterpret_cast<double*>(H->ell2j) + j * N,
+                                  H->st);
+    }
+    fftg_stats acc{};
+    bool converged = false;
+    int k = 0;
+    double err = 0.0;
+    for (k = 0; k < max_stagger_iters; ++k) {
+      if (J > 0) fftg::launch_damage(t, N, J, phase, H->ab_k, s_hist, H->Dj, H->st);
+      HIPCHK(hipMemcpyAsync(H->eps_prev, H->eps_k, sizeof(double) * c * N,
+                            hipMemcpyDeviceToDevice, H->st));
+      MechOut o = H->fp32()
+                      ? mechanics<float>(H, phase, t, J, H->Dj, s_epsp, target, H->eps_k,
+                                         H->sig_k, H->st1, H->alph, cg, newton_tol, newton_maxit)
+                      : mechanics<double>(H, phase, t, J, H->Dj, s_epsp, target, H->eps_k,
+                                          H->sig_k, H->st1, H->alph, cg, newton_tol,
+                                          newton_maxit);
+      acc.newton_iters += o.newton;
+      acc.cg_iters += o.cg;
+      acc.relres = o.relres;
+      acc.t_ms[0] += o.t_const;
+      acc.t_ms[1] += o.t_cg;
+      auto th = std::chrono::steady_clock::now();
+      if (J > 0)
+        HIPCHK(hipMemcpyAsync(H->ab_prev, H->ab_k, sizeof(double) * J * N,
+                              hipMemcpyDeviceToDevice, H->st));
+      for (int j = 0; j < J; ++j) {
+        int it = 0, status = 0;
+        double rel = 0.0;
+        if (H->fp32())
+          helmholtz_pcg<float>(H, H->alph + j * N, reinterpret_cast<const float*>(H->ell2j) + j * N,
+                               -1.0, H->ab_k + j * N, pcg->tol, pcg->maxit, it, rel, status);
+        else
+          helmholtz_pcg<double>(H, H->alph + j * N,
+                                reinterpret_cast<const double*>(H->ell2j) + j * N, -1.0,
+                                H->ab_k + j * N, pcg->tol, pcg->maxit, it, rel, status);
+        if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
+        if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+        acc.pcg_iters += it;
+      }
+      sync(H);
+      acc.t_ms[2] += wall_ms(th);
+      // staggered error (Algorithm 1 (iii))
+      const int nbe = fftg::launch_stagger_err(N, c, J, H->eps_k, H->eps_prev, H->ab_k,
+                                               H->ab_prev, H->partials, H->st);
+      // block partials: [0] max of |d eps|^2, then per field sum d^2, sum abar^2
+      std::vector<double> part((size_t)nbe * (1 + 2 * J));
+      HIPCHK(hipMemcpyAsync(part.data(), H->partials, sizeof(double) * part.size(),
+                            hipMemcpyDeviceToHost, H->st));
+      sync(H);
+      double mx = 0.0;
+      for (int b = 0; b < nbe; ++b) mx = std::max(mx, part[b]);
+      double mean[6];
+      comp_means(H, c, H->eps_k, mean);
+      double mn = 0.0;
+      for (int i = 0; i < c; ++i) mn += mean[i] * mean[i];
+      mn = std::sqrt(mn);
+      err = std::sqrt(mx) / (mn > 0.0 ? mn : 1.0);
+      for (int j = 0; j < J; ++j) {
+        double d2 = 0.0, a2 = 0.0;
+        for (int b = 0; b < nbe; ++b) {
+          d2 += part[(size_t)(1 + 2 * j) * nbe + b];
+          a2 += part[(size_t)(2 + 2 * j) * nbe + b];
+        }
+        if (d2 > 0.0) err = std::max(err, std::sqrt(d2) / std::max(std::sqrt(a2), 1e-12 * std::sqrt((double)N)));
+      }
+      acc.stagger_iters = k + 1;
+      acc.err = err;
+      if (err <= stagger_tol) {
+        converged = true;
+        break;
+      }
+    }
+    // commit the increment
+    HIPCHK(hipMemcpyAsync(s_eps, H->eps_k, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
+    HIPCHK(hipMemcpyAsync(s_epsp, H->st1, sizeof(double) * 7 * N, hipMemcpyDeviceToDevice, H->st));
+    if (J > 0) {
+      fftg::launch_vmax((long long)J * N, s_hist, H->ab_k, H->st);
+      HIPCHK(hipMemcpyAsync(s_abar, H->ab_k, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
+                            H->st));
+    }
+    HIPCHK(hipMemcpyAsync(sigma_out, H->sig_k, sizeof(double) * c * N, hipMemcpyDeviceToDevice,
+                          H->st));
+    double ms[6], me[6];
+    comp_means(H, c, H->sig_k, ms);
+    comp_means(H, c, H->eps_k, me);
+    for (int i = 0; i < 12; ++i) homog_out[i] = 0.0;
+    for (int i = 0; i < c; ++i) {
+      homog_out[i] = ms[i];
+      homog_out[6 + i] = me[i];
+    }
+    check_launch();
+    sync(H);
+    const double tot = wall_ms(t_all);
+    acc.t_ms[3] = std::max(0.0, tot - acc.t_ms[0] - acc.t_ms[1] - acc.t_ms[2]);
+    if (stats) *stats = acc;
+    return converged ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+}
+
+}  // extern "C"

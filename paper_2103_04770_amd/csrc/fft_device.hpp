@@ -1,0 +1,205 @@
+// Device building blocks for the LDS-staged mixed-radix (2, 3, 4, 8) Stockham
+// FFT used by every transform pass.  One workgroup of FFT_THREADS threads
+// transforms a batch of lines that sits in LDS; each stage reads its inputs
+// into registers, synchronises, and writes the autosorted outputs back, so a
+// single LDS buffer suffices.
+//
+// Stockham autosort (decimation in time), natural order in and out: for a
+// stage of radix R after stages whose radices multiply to Ns, butterfly j of
+// a line reads elements j + r n/R, multiplies element r by W_n^(k r n/(Ns R))
+// with k = j mod Ns, applies the length-R DFT and writes output r to
+// (j div Ns) Ns R + k + r Ns.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fftg {
+
+constexpr int FFT_THREADS = 256;
+constexpr int LDS_ELEMS = 2048;  // complex elements of one batch held in LDS
+constexpr int MAX_STAGES = 12;
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T a, T b) { return cpx<T>{a, b}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.x, -a.y}; }
+// a * i
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_i(cpx<T> a) { return {-a.y, a.x}; }
+// a * (-i)
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) { return {a.y, -a.x}; }
+
+// a * W4, W4 = exp(-i pi/2) = -i (forward) or +i (inverse)
+template <bool FWD, typename T>
+__device__ __forceinline__ cpx<T> rot4(cpx<T> a) { return FWD ? mul_mi(a) : mul_i(a); }
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft2(cpx<T>* v) {
+  cpx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft3(cpx<T>* v) {
+  const T s3 = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+  cpx<T> t = v[1] + v[2];
+  cpx<T> m = v[0] - scale(t, T(0.5));
+  cpx<T> d = scale(v[1] - v[2], s3);
+  cpx<T> s = FWD ? mul_mi(d) : mul_i(d);
+  v[0] = v[0] + t;
+  v[1] = m + s;
+  v[2] = m - s;
+}
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft4(cpx<T>& v0, cpx<T>& v1, cpx<T>& v2, cpx<T>& v3) {
+  cpx<T> t0 = v0 + v2, t1 = v0 - v2, t2 = v1 + v3, t3 = rot4<FWD>(v1 - v3);
+  v0 = t0 + t2;
+  v1 = t1 + t3;
+  v2 = t0 - t2;
+  v3 = t1 - t3;
+}
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft4(cpx<T>* v) { dft4<FWD>(v[0], v[1], v[2], v[3]); }
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft8(cpx<T>* v) {
+  const T c = T(0.70710678118654752440084436210485);  // sqrt(1/2)
+  cpx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cpx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<FWD>(e0, e1, e2, e3);
+  dft4<FWD>(o0, o1, o2, o3);
+  // o_k *= W8^k
+  cpx<T> w1, w3;
+  if (FWD) {
+    w1 = mk(c * (o1.x + o1.y), c * (o1.y - o1.x));
+    w3 = mk(c * (o3.y - o3.x), -c * (o3.x + o3.y));
+  } else {
+    w1 = mk(c * (o1.x - o1.y), c * (o1.x + o1.y));
+    w3 = mk(-c * (o3.x + o3.y), c * (o3.x - o3.y));
+  }
+  cpx<T> w2 = rot4<FWD>(o2);
+  v[0] = e0 + o0;
+  v[4] = e0 - o0;
+  v[1] = e1 + w1;
+  v[5] = e1 - w1;
+  v[2] = e2 + w2;
+  v[6] = e2 - w2;
+  v[3] = e3 + w3;
+  v[7] = e3 - w3;
+}
+
+// One 1D transform plan: length and radix sequence.
+struct Plan {
+  int n;
+  int nst;
+  int radix[MAX_STAGES];
+};
+
+// LDS addressing: LINEFAST -> element t of line l at t*ld + l (lines adjacent);
+// otherwise at l*ld + t (each line contiguous).
+template <bool LINEFAST>
+__device__ __forceinline__ int laddr(int line, int t, int ld) {
+  return LINEFAST ? t * ld + line : line * ld + t;
+}
+
+template <typename T, int R, bool FWD, bool LINEFAST>
+__device__ __forceinline__ void stage(cpx<T>* buf, int n, int nlines, int ld, int Ns,
+                                      const cpx<T>* __restrict__ tw) {
+  constexpr int MAXB = (LDS_ELEMS / R + FFT_THREADS - 1) / FFT_THREADS;
+  const int m = n / R;
+  const int total = nlines * m;
+  const int tid = threadIdx.x;
+  cpx<T> v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = tid + q * FFT_THREADS;
+    if (b < total) {
+      const int line = LINEFAST ? b % nlines : b / m;
+      const int j = LINEFAST ? b / nlines : b % m;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[laddr<LINEFAST>(line, j + r * m, ld)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = tid + q * FFT_THREADS;
+    if (b < total) {
+      const int line = LINEFAST ? b % nlines : b / m;
+      const int j = LINEFAST ? b / nlines : b % m;
+      const int k = j % Ns;
+      if (Ns > 1) {
+        const int step = n / (Ns * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[k * r * step];
+          if (!FWD) w.y = -w.y;
+          v[q][r] = v[q][r] * w;
+        }
+      }
+      if (R == 2) dft2<FWD>(v[q]);
+      if (R == 3) dft3<FWD>(v[q]);
+      if (R == 4) dft4<FWD>(v[q]);
+      if (R == 8) dft8<FWD>(v[q]);
+      const int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[laddr<LINEFAST>(line, o + r * Ns, ld)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Transform `nlines` lines of length plan.n held in LDS (nlines * n must not
+// exceed LDS_ELEMS).  FWD: exp(-i ...), unnormalised; otherwise exp(+i ...).
+// The caller synchronises before the call; the call ends synchronised.
+template <typename T, bool FWD, bool LINEFAST>
+__device__ void lds_fft(cpx<T>* buf, const Plan& plan, int nlines, int ld,
+                        const cpx<T>* __restrict__ tw) {
+  int Ns = 1;
+  for (int s = 0; s < plan.nst; ++s) {
+    const int R = plan.radix[s];
+    if (R == 8)
+      stage<T, 8, FWD, LINEFAST>(buf, plan.n, nlines, ld, Ns, tw);
+    else if (R == 4)
+      stage<T, 4, FWD, LINEFAST>(buf, plan.n, nlines, ld, Ns, tw);
+    else if (R == 3)
+      stage<T, 3, FWD, LINEFAST>(buf, plan.n, nlines, ld, Ns, tw);
+    else
+      stage<T, 2, FWD, LINEFAST>(buf, plan.n, nlines, ld, Ns, tw);
+    Ns *= R;
+  }
+}
+
+// Deterministic workgroup sum (fixed tree over FFT_THREADS lanes); the result
+// is valid in thread 0.  `red` must hold FFT_THREADS doubles of LDS.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  red[tid] = v;
+  __syncthreads();
+  for (int s = FFT_THREADS / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+}  // namespace fftg

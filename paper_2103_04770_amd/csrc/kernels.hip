@@ -1,0 +1,1326 @@
+// HIP kernels for gfx950: transform passes, fused Galerkin / Helmholtz
+// operator passes with their Krylov prologues and epilogues, pointwise
+// projection and residual kernels, deterministic reductions, and the
+// per-voxel constitutive update.
+#include "kernels.hpp"
+
+#include <cmath>
+#include <stdexcept>
+
+namespace fftg {
+
+#define FFTG_KERNEL __global__ __launch_bounds__(FFT_THREADS)
+
+// Hermitian weight of a half-spectrum coefficient: its mirror image is not
+// stored except on the planes kx = 0 and kx = n1/2.
+__device__ __forceinline__ double hweight(int kx, int n1h) {
+  return (kx == 0 || kx == n1h - 1) ? 1.0 : 2.0;
+}
+
+__device__ __forceinline__ void decode(const Geo& g, long long gi, int& kx, int& ky, int& kz) {
+  kx = (int)(gi % g.n1h);
+  long long r = gi / g.n1h;
+  ky = (int)(r % g.n2);
+  kz = (int)((r / g.n2) % g.n3);
+}
+
+template <typename T>
+__device__ __forceinline__ void qvec(const Sym<T>& s, bool grad, int kx, int ky, int kz, T q[3]) {
+  const T* b = s.base;
+  const T cx = b[s.cs[0] + kx], cy = b[s.cs[1] + ky], cz = b[s.cs[2] + kz];
+  const int* o = grad ? s.gq : s.pq;
+  q[0] = b[o[0] + kx] * cy * cz;
+  q[1] = cx * b[o[1] + ky] * cz;
+  q[2] = cx * cy * b[o[2] + kz];
+}
+
+// Orthogonal projection of a symmetric Mandel tensor onto {sym(u (x) q)}
+// (Sec. 3.2.2): t = tau q, P tau = (t(x)q + q(x)t)/|q|^2 - (q(x)q)(q.t)/|q|^4;
+// zero where |q| = 0.
+template <typename T, int C>
+__device__ __forceinline__ void project_point(const T q[3], cpx<T>* v) {
+  const T q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  if (!(q2 > T(0))) {
+#pragma unroll
+    for (int i = 0; i < C; ++i) v[i] = mk(T(0), T(0));
+    return;
+  }
+  const T ir2 = T(0.70710678118654752440084436210485);
+  const T inv = T(1) / q2;
+  if (C == 6) {
+    // full tensor from Mandel
+    cpx<T> t11 = v[0], t22 = v[1], t33 = v[2];
+    cpx<T> t23 = scale(v[3], ir2), t13 = scale(v[4], ir2), t12 = scale(v[5], ir2);
+    cpx<T> a0 = scale(t11, q[0]) + scale(t12, q[1]) + scale(t13, q[2]);
+    cpx<T> a1 = scale(t12, q[0]) + scale(t22, q[1]) + scale(t23, q[2]);
+    cpx<T> a2 = scale(t13, q[0]) + scale(t23, q[1]) + scale(t33, q[2]);
+    cpx<T> s = scale(a0, q[0]) + scale(a1, q[1]) + scale(a2, q[2]);
+    cpx<T> si = scale(s, inv * inv);
+    cpx<T> p11 = scale(scale(a0, q[0]), T(2) * inv) - scale(si, q[0] * q[0]);
+    cpx<T> p22 = scale(scale(a1, q[1]), T(2) * inv) - scale(si, q[1] * q[1]);
+    cpx<T> p33 = scale(scale(a2, q[2]), T(2) * inv) - scale(si, q[2] * q[2]);
+    cpx<T> p23 = scale(scale(a1, q[2]) + scale(a2, q[1]), inv) - scale(si, q[1] * q[2]);
+    cpx<T> p13 = scale(scale(a0, q[2]) + scale(a2, q[0]), inv) - scale(si, q[0] * q[2]);
+    cpx<T> p12 = scale(scale(a0, q[1]) + scale(a1, q[0]), inv) - scale(si, q[0] * q[1]);
+    const T r2 = T(1.4142135623730950488016887242097);
+    v[0] = p11;
+    v[1] = p22;
+    v[2] = p33;
+    v[3] = scale(p23, r2);
+    v[4] = scale(p13, r2);
+    v[5] = scale(p12, r2);
+  } else {
+    cpx<T> t11 = v[0], t22 = v[1], t12 = scale(v[2], ir2);
+    cpx<T> a0 = scale(t11, q[0]) + scale(t12, q[1]);
+    cpx<T> a1 = scale(t12, q[0]) + scale(t22, q[1]);
+    cpx<T> s = scale(a0, q[0]) + scale(a1, q[1]);
+    cpx<T> si = scale(s, inv * inv);
+    cpx<T> p11 = scale(scale(a0, q[0]), T(2) * inv) - scale(si, q[0] * q[0]);
+    cpx<T> p22 = scale(scale(a1, q[1]), T(2) * inv) - scale(si, q[1] * q[1]);
+    cpx<T> p12 = scale(scale(a0, q[1]) + scale(a1, q[0]), inv) - scale(si, q[0] * q[1]);
+    const T r2 = T(1.4142135623730950488016887242097);
+    v[0] = p11;
+    v[1] = p22;
+    v[2] = scale(p12, r2);
+  }
+}
+
+// ============================================================ x passes
+// Two real lines a, b are transformed together as z = a + i b.  After the
+// forward transform A[k] = (Z[k] + conj Z[n-k])/2, B[k] = -i (Z[k] - conj Z[n-k])/2;
+// the inverse rebuilds Z[k] = A[k] + i B[k] and Z[n-k] = conj A[k] + i conj B[k].
+
+template <typename T>
+__device__ __forceinline__ void pack_inverse(cpx<T>* buf, int p, int k, int n1, cpx<T> A,
+                                             cpx<T> B) {
+  if (k == 0 || 2 * k == n1) {
+    A.y = T(0);
+    B.y = T(0);
+  }
+  buf[p * n1 + k] = mk(A.x - B.y, A.y + B.x);
+  if (k > 0 && 2 * k < n1) buf[p * n1 + (n1 - k)] = mk(A.x + B.y, B.x - A.y);
+}
+
+template <typename T>
+__device__ __forceinline__ void unpack_forward(const cpx<T>* buf, int p, int k, int n1,
+                                               cpx<T>& A, cpx<T>& B) {
+  const cpx<T> Z = buf[p * n1 + k];
+  const cpx<T> Zm = buf[p * n1 + ((n1 - k) % n1)];
+  A = mk(T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y));
+  B = mk(T(0.5) * (Z.y + Zm.y), T(0.5) * (Zm.x - Z.x));
+}
+
+template <typename T>
+FFTG_KERNEL void k_x_r2c(Plan plan, const cpx<T>* __restrict__ tw, const T* __restrict__ in,
+                         cpx<T>* __restrict__ out, long long S, int n1, int n1h, int P) {
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  const long long s0 = (long long)blockIdx.x * (2 * P);
+  for (int e = threadIdx.x; e < P * n1; e += FFT_THREADS) {
+    const int p = e / n1, x = e % n1;
+    const long long sa = s0 + p, sb = s0 + p + P;
+    const T a = sa < S ? in[sa * n1 + x] : T(0);
+    const T b = sb < S ? in[sb * n1 + x] : T(0);
+    buf[p * n1 + x] = mk(a, b);
+  }
+  __syncthreads();
+  lds_fft<T, true, false>(buf, plan, P, n1, tw);
+  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+    const int p = e / n1h, k = e % n1h;
+    const long long sa = s0 + p, sb = s0 + p + P;
+    cpx<T> A, B;
+    unpack_forward(buf, p, k, n1, A, B);
+    if (sa < S) out[sa * n1h + k] = A;
+    if (sb < S) out[sb * n1h + k] = B;
+  }
+}
+
+template <typename T, typename TO>
+FFTG_KERNEL void k_x_c2r(Plan plan, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ in,
+                         TO* __restrict__ out, long long S, int n1, int n1h, int P, T scl,
+                         int acc) {
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  const long long s0 = (long long)blockIdx.x * (2 * P);
+  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+    const int p = e / n1h, k = e % n1h;
+    const long long sa = s0 + p, sb = s0 + p + P;
+    const cpx<T> A = sa < S ? in[sa * n1h + k] : mk(T(0), T(0));
+    const cpx<T> B = sb < S ? in[sb * n1h + k] : mk(T(0), T(0));
+    pack_inverse(buf, p, k, n1, A, B);
+  }
+  __syncthreads();
+  lds_fft<T, false, false>(buf, plan, P, n1, tw);
+  for (int e = threadIdx.x; e < P * n1; e += FFT_THREADS) {
+    const int p = e / n1, x = e % n1;
+    const long long sa = s0 + p, sb = s0 + p + P;
+    const cpx<T> z = buf[p * n1 + x];
+    if (sa < S) {
+      TO v = (TO)(z.x * scl);
+      out[sa * n1 + x] = acc ? (TO)(out[sa * n1 + x] + v) : v;
+    }
+    if (sb < S) {
+      TO v = (TO)(z.y * scl);
+      out[sb * n1 + x] = acc ? (TO)(out[sb * n1 + x] + v) : v;
+    }
+  }
+}
+
+// Fused x pass of the Galerkin operator: half spectrum -> real (C2R), then
+// sigma = scale * K : eps per voxel with the compact tangent
+// K:e = a tr(e) I + b dev(e) - (m.e) m, then real -> half spectrum (R2C).
+// A workgroup owns NL whole x-lines with all c components.
+template <typename T, typename TT>
+FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int c, int NL,
+                               cpx<T>* __restrict__ w, const TT* __restrict__ tan, T scl,
+                               const KrylovCtl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  const long long nlines = (long long)g.n2 * g.n3;
+  const long long line0 = (long long)blockIdx.x * NL;
+  const int n1 = g.n1, n1h = g.n1h;
+  const int R = c * NL, P = R / 2;
+  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+    const int p = e / n1h, k = e % n1h;
+    const int sa = p, sb = p + P;
+    const long long la = line0 + sa % NL, lb = line0 + sb % NL;
+    const cpx<T> A = la < nlines ? w[(sa / NL) * g.Ns + la * n1h + k] : mk(T(0), T(0));
+    const cpx<T> B = lb < nlines ? w[(sb / NL) * g.Ns + lb * n1h + k] : mk(T(0), T(0));
+    pack_inverse(buf, p, k, n1, A, B);
+  }
+  __syncthreads();
+  lds_fft<T, false, false>(buf, plan, P, n1, tw);
+  T* fb = reinterpret_cast<T*>(buf);
+  for (int e = threadIdx.x; e < NL * n1; e += FFT_THREADS) {
+    const int l = e / n1, x = e % n1;
+    const long long line = line0 + l;
+    if (line >= nlines) continue;
+    const long long v = line * n1 + x;
+    int slot[6];
+    T ev[6];
+    for (int q = 0; q < c; ++q) {
+      const int s = q * NL + l;
+      slot[q] = s < P ? 2 * (s * n1 + x) : 2 * ((s - P) * n1 + x) + 1;
+      ev[q] = fb[slot[q]];
+    }
+    const T a = (T)tan[v], b = (T)tan[g.N + v];
+    T m[6];
+    for (int i = 0; i < 6; ++i) m[i] = (T)tan[(2 + i) * g.N + v];
+    T out[6];
+    if (c == 6) {
+      const T tr = ev[0] + ev[1] + ev[2];
+      const T md = m[0] * ev[0] + m[1] * ev[1] + m[2] * ev[2] + m[3] * ev[3] + m[4] * ev[4] +
+                   m[5] * ev[5];
+      const T dv = tr / T(3);
+      for (int i = 0; i < 3; ++i) out[i] = a * tr + b * (ev[i] - dv) - md * m[i];
+      for (int i = 3; i < 6; ++i) out[i] = b * ev[i] - md * m[i];
+    } else {
+      const T tr = ev[0] + ev[1];
+      const T md = m[0] * ev[0] + m[1] * ev[1] + m[5] * ev[2];
+      const T dv = tr / T(3);
+      out[0] = a * tr + b * (ev[0] - dv) - md * m[0];
+      out[1] = a * tr + b * (ev[1] - dv) - md * m[1];
+      out[2] = b * ev[2] - md * m[5];
+    }
+    for (int q = 0; q < c; ++q) fb[slot[q]] = out[q] * scl;
+  }
+  __syncthreads();
+  lds_fft<T, true, false>(buf, plan, P, n1, tw);
+  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+    const int p = e / n1h, k = e % n1h;
+    const int sa = p, sb = p + P;
+    const long long la = line0 + sa % NL, lb = line0 + sb % NL;
+    cpx<T> A, B;
+    unpack_forward(buf, p, k, n1, A, B);
+    if (la < nlines) w[(sa / NL) * g.Ns + la * n1h + k] = A;
+    if (lb < nlines) w[(sb / NL) * g.Ns + lb * n1h + k] = B;
+  }
+}
+
+// Fused x pass of the Helmholtz operator: C2R of the ndim gradient
+// components, multiply by scale * ell^2(x), R2C.
+template <typename T, typename TL>
+FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int NL,
+                                cpx<T>* __restrict__ w, const TL* __restrict__ ell2, T scl,
+                                const KrylovCtl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  const int c = g.ndim;
+  const long long nlines = (long long)g.n2 * g.n3;
+  const long long line0 = (long long)blockIdx.x * NL;
+  const int n1 = g.n1, n1h = g.n1h;
+  const int R = c * NL, P = R / 2;
+  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+    const int p = e / n1h, k = e % n1h;
+    const int sa = p, sb = p + P;
+    const long long la = line0 + sa % NL, lb = line0 + sb % NL;
+    const cpx<T> A = la < nlines ? w[(sa / NL) * g.Ns + la * n1h + k] : mk(T(0), T(0));
+    const cpx<T> B = lb < nlines ? w[(sb / NL) * g.Ns + lb * n1h + k] : mk(T(0), T(0));
+    pack_inverse(buf, p, k, n1, A, B);
+  }
+  __syncthreads();
+  lds_fft<T, false, false>(buf, plan, P, n1, tw);
+  T* fb = reinterpret_cast<T*>(buf);
+  for (int e = threadIdx.x; e < NL * n1; e += FFT_THREADS) {
+    const int l = e / n1, x = e % n1;
+    const long long line = line0 + l;
+    if (line >= nlines) continue;
+    const T f = (T)ell2[line * n1 + x] * scl;
+    for (int q = 0; q < c; ++q) {
+      const int s = q * NL + l;
+      const int slot = s < P ? 2 * (s * n1 + x) : 2 * ((s - P) * n1 + x) + 1;
+      fb[slot] = fb[slot] * f;
+    }
+  }
+  __syncthreads();
+  lds_fft<T, true, false>(buf, plan, P, n1, tw);
+  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+    const int p = e / n1h, k = e % n1h;
+    const int sa = p, sb = p + P;
+    const long long la = line0 + sa % NL, lb = line0 + sb % NL;
+    cpx<T> A, B;
+    unpack_forward(buf, p, k, n1, A, B);
+    if (la < nlines) w[(sa / NL) * g.Ns + la * n1h + k] = A;
+    if (lb < nlines) w[(sb / NL) * g.Ns + lb * n1h + k] = B;
+  }
+}
+
+// ============================================================ strided passes
+// Lines are numbered L = o * inner + i; line L starts at o * ostride + i and
+// its elements are es apart.  A workgroup takes TL consecutive lines, so the
+// loads of one row of the tile are contiguous within a slab.
+__device__ __forceinline__ long long line_base(long long L, long long inner, long long ostride) {
+  return (L / inner) * ostride + (L % inner);
+}
+
+template <typename T, bool FWD>
+FFTG_KERNEL void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __restrict__ data,
+                           long long nlines, long long inner, long long ostride, long long es,
+                           int TL, const KrylovCtl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  const int n = plan.n;
+  const long long L0 = (long long)blockIdx.x * TL;
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    buf[t * TL + l] = L < nlines ? data[line_base(L, inner, ostride) + t * es] : mk(T(0), T(0));
+  }
+  __syncthreads();
+  lds_fft<T, FWD, true>(buf, plan, TL, TL, tw);
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    if (L < nlines) data[line_base(L, inner, ostride) + t * es] = buf[t * TL + l];
+  }
+}
+
+// Outer-axis inverse pass of the Galerkin CG (per component):
+//   p <- r + beta p ; x <- x + alpha p_old ; w <- inverse transform of p.
+template <typename T>
+FFTG_KERNEL void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
+                               const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
+                               cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
+                               long long inner, long long ostride, long long es, int TL,
+                               const KrylovCtl* __restrict__ ctl) {
+  if (ctl->done) return;
+  const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  const int n = plan.n;
+  const long long L0 = (long long)blockIdx.x * TL;
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    cpx<T> pn = mk(T(0), T(0));
+    if (L < nlines) {
+      const long long gi = line_base(L, inner, ostride) + t * es;
+      const cpx<T> po = pp[gi];
+      x[gi] = x[gi] + scale(po, alpha);
+      pn = r[gi] + scale(po, beta);
+      pp[gi] = pn;
+    }
+    buf[t * TL + l] = pn;
+  }
+  __syncthreads();
+  lds_fft<T, false, true>(buf, plan, TL, TL, tw);
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    if (L < nlines) w[line_base(L, inner, ostride) + t * es] = buf[t * TL + l];
+  }
+}
+
+// Outer-axis forward pass of the Galerkin CG: w <- forward transform of w,
+// and the partial sums of the Hermitian-weighted p.w (= p.Ap, since p lies in
+// the range of the orthogonal projector).
+template <typename T>
+FFTG_KERNEL void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
+                               const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
+                               long long nlines, long long inner, long long ostride,
+                               long long es, int TL, int n1h, double* __restrict__ partials,
+                               const KrylovCtl* __restrict__ ctl) {
+  if (ctl->done) return;
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  __shared__ double red[FFT_THREADS];
+  const int n = plan.n;
+  const long long L0 = (long long)blockIdx.x * TL;
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    buf[t * TL + l] = L < nlines ? w[line_base(L, inner, ostride) + t * es] : mk(T(0), T(0));
+  }
+  __syncthreads();
+  lds_fft<T, true, true>(buf, plan, TL, TL, tw);
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    if (L < nlines) {
+      const long long gi = line_base(L, inner, ostride) + t * es;
+      const cpx<T> v = buf[t * TL + l];
+      w[gi] = v;
+      const cpx<T> pv = pp[gi];
+      acc += hweight((int)(gi % n1h), n1h) * ((double)pv.x * (double)v.x + (double)pv.y * (double)v.y);
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Outer-axis inverse pass of the Helmholtz PCG (single scalar spectrum):
+//   update: p <- M r + beta p ; x <- x + alpha p_old
+//   w_j <- inverse transform of (i q~_j p), j < ndim.
+template <typename T>
+FFTG_KERNEL void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
+                             int update, const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
+                             cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
+                             long long inner, long long ostride, long long es, int TL,
+                             const KrylovCtl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  const int n = plan.n;
+  const int c = g.ndim;
+  const int ld = c * TL;
+  const long long L0 = (long long)blockIdx.x * TL;
+  const T alpha = ctl ? (T)ctl->alpha : T(0), beta = ctl ? (T)ctl->beta : T(0);
+  const T l2 = ctl ? (T)ctl->ell2ref : T(0);
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    cpx<T> pn = mk(T(0), T(0));
+    T q[3] = {T(0), T(0), T(0)};
+    if (L < nlines) {
+      const long long gi = line_base(L, inner, ostride) + t * es;
+      int kx, ky, kz;
+      decode(g, gi, kx, ky, kz);
+      qvec(sym, true, kx, ky, kz, q);
+      if (update) {
+        const T minv = T(1) / (T(1) + l2 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]));
+        const cpx<T> po = pp[gi];
+        x[gi] = x[gi] + scale(po, alpha);
+        pn = scale(r[gi], minv) + scale(po, beta);
+        pp[gi] = pn;
+      } else {
+        pn = pp[gi];
+      }
+    }
+    const cpx<T> ip = mul_i(pn);
+    for (int j = 0; j < c; ++j) buf[t * ld + j * TL + l] = scale(ip, q[j]);
+  }
+  __syncthreads();
+  lds_fft<T, false, true>(buf, plan, ld, ld, tw);
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    if (L < nlines) {
+      const long long gi = line_base(L, inner, ostride) + t * es;
+      for (int j = 0; j < c; ++j) w[j * g.Ns + gi] = buf[t * ld + j * TL + l];
+    }
+  }
+}
+
+// Outer-axis forward pass of the Helmholtz operator:
+//   Ap = p - i sum_j q~_j FFT(w_j) ; partial sums of weighted p.Ap.
+template <typename T>
+FFTG_KERNEL void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
+                             const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
+                             cpx<T>* __restrict__ Ap, long long nlines, long long inner,
+                             long long ostride, long long es, int TL,
+                             double* __restrict__ partials, const KrylovCtl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  __shared__ cpx<T> buf[LDS_ELEMS];
+  __shared__ double red[FFT_THREADS];
+  const int n = plan.n;
+  const int c = g.ndim;
+  const int ld = c * TL;
+  const long long L0 = (long long)blockIdx.x * TL;
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    if (L < nlines) {
+      const long long gi = line_base(L, inner, ostride) + t * es;
+      for (int j = 0; j < c; ++j) buf[t * ld + j * TL + l] = w[j * g.Ns + gi];
+    } else {
+      for (int j = 0; j < c; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
+    }
+  }
+  __syncthreads();
+  lds_fft<T, true, true>(buf, plan, ld, ld, tw);
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
+    const int l = e % TL, t = e / TL;
+    const long long L = L0 + l;
+    if (L < nlines) {
+      const long long gi = line_base(L, inner, ostride) + t * es;
+      int kx, ky, kz;
+      decode(g, gi, kx, ky, kz);
+      T q[3];
+      qvec(sym, true, kx, ky, kz, q);
+      const cpx<T> pv = pp[gi];
+      cpx<T> div = mk(T(0), T(0));
+      for (int j = 0; j < c; ++j) div = div + scale(buf[t * ld + j * TL + l], q[j]);
+      const cpx<T> a = pv + mul_mi(div);
+      Ap[gi] = a;
+      acc += hweight(kx, g.n1h) * ((double)pv.x * (double)a.x + (double)pv.y * (double)a.y);
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (partials && threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ============================================================ pointwise
+// r <- r - alpha G*(w) ; partial sums of weighted |r|^2
+template <typename T, int C>
+FFTG_KERNEL void k_gal_resid(Geo g, Sym<T> sym, unsigned char mk0, unsigned char mk1,
+                             unsigned char mk2, unsigned char mk3, unsigned char mk4,
+                             unsigned char mk5, cpx<T>* __restrict__ r,
+                             const cpx<T>* __restrict__ w, double* __restrict__ partials,
+                             const KrylovCtl* __restrict__ ctl) {
+  if (ctl->done) return;
+  __shared__ double red[FFT_THREADS];
+  const T alpha = (T)ctl->alpha;
+  const unsigned char mask[6] = {mk0, mk1, mk2, mk3, mk4, mk5};
+  double acc = 0.0;
+  for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
+       gi += (long long)gridDim.x * FFT_THREADS) {
+    int kx, ky, kz;
+    decode(g, gi, kx, ky, kz);
+    cpx<T> v[C];
+    for (int i = 0; i < C; ++i) v[i] = w[i * g.Ns + gi];
+    if (gi == 0) {
+      for (int i = 0; i < C; ++i)
+        if (!mask[i]) v[i] = mk(T(0), T(0));
+    } else {
+      T q[3];
+      qvec(sym, false, kx, ky, kz, q);
+      project_point<T, C>(q, v);
+    }
+    const double wt = hweight(kx, g.n1h);
+    for (int i = 0; i < C; ++i) {
+      const cpx<T> rn = r[i * g.Ns + gi] - scale(v[i], alpha);
+      r[i * g.Ns + gi] = rn;
+      acc += wt * ((double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y);
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Newton right-hand side b = -G*(sigma - Sbar) from the FP64 stress spectrum;
+// partials: [0] weighted |b|^2, [1] weighted |sigma_hat|^2.
+template <typename T, int C>
+FFTG_KERNEL void k_gal_rhs(Geo g, Sym<double> sym, unsigned char mk0, unsigned char mk1,
+                           unsigned char mk2, unsigned char mk3, unsigned char mk4,
+                           unsigned char mk5, double s0, double s1, double s2, double s3,
+                           double s4, double s5, const cpx<double>* __restrict__ sh,
+                           cpx<T>* __restrict__ r, double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  const unsigned char mask[6] = {mk0, mk1, mk2, mk3, mk4, mk5};
+  const double Sb[6] = {s0, s1, s2, s3, s4, s5};
+  double accb = 0.0, accs = 0.0;
+  for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
+       gi += (long long)gridDim.x * FFT_THREADS) {
+    int kx, ky, kz;
+    decode(g, gi, kx, ky, kz);
+    const double wt = hweight(kx, g.n1h);
+    cpx<double> v[C];
+    for (int i = 0; i < C; ++i) {
+      v[i] = sh[i * g.Ns + gi];
+      accs += wt * (v[i].x * v[i].x + v[i].y * v[i].y);
+    }
+    if (gi == 0) {
+      for (int i = 0; i < C; ++i)
+        v[i] = mask[i] ? mk(v[i].x - (double)g.N * Sb[i], v[i].y) : mk(0.0, 0.0);
+    } else {
+      double q[3];
+      qvec(sym, false, kx, ky, kz, q);
+      project_point<double, C>(q, v);
+    }
+    for (int i = 0; i < C; ++i) {
+      const cpx<double> b = mk(-v[i].x, -v[i].y);
+      r[i * g.Ns + gi] = mk((T)b.x, (T)b.y);
+      accb += wt * (b.x * b.x + b.y * b.y);
+    }
+  }
+  double s = block_sum(accb, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  s = block_sum(accs, red);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s;
+}
+
+// In-place projection of a c-component spectrum (zero frequency: mask).
+template <typename T, int C>
+FFTG_KERNEL void k_project(Geo g, Sym<T> sym, unsigned char mk0, unsigned char mk1,
+                           unsigned char mk2, unsigned char mk3, unsigned char mk4,
+                           unsigned char mk5, cpx<T>* __restrict__ d) {
+  const unsigned char mask[6] = {mk0, mk1, mk2, mk3, mk4, mk5};
+  for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
+       gi += (long long)gridDim.x * FFT_THREADS) {
+    int kx, ky, kz;
+    decode(g, gi, kx, ky, kz);
+    cpx<T> v[C];
+    for (int i = 0; i < C; ++i) v[i] = d[i * g.Ns + gi];
+    if (gi == 0) {
+      for (int i = 0; i < C; ++i)
+        if (!mask[i]) v[i] = mk(T(0), T(0));
+    } else {
+      T q[3];
+      qvec(sym, false, kx, ky, kz, q);
+      project_point<T, C>(q, v);
+    }
+    for (int i = 0; i < C; ++i) d[i * g.Ns + gi] = v[i];
+  }
+}
+
+// Helmholtz residual update (init: r = b - Ap; else r -= alpha Ap), with
+// partials [0] weighted r.Mr and [1] weighted r.r.
+template <typename T>
+FFTG_KERNEL void k_h_resid(Geo g, Sym<T> sym, int init, cpx<T>* __restrict__ r,
+                           const cpx<T>* __restrict__ b, const cpx<T>* __restrict__ Ap,
+                           double* __restrict__ partials, const KrylovCtl* __restrict__ ctl) {
+  if (!init && ctl->done) return;
+  __shared__ double red[FFT_THREADS];
+  const T alpha = init ? T(0) : (T)ctl->alpha;
+  const T l2 = (T)ctl->ell2ref;
+  double arz = 0.0, arr = 0.0;
+  for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
+       gi += (long long)gridDim.x * FFT_THREADS) {
+    int kx, ky, kz;
+    decode(g, gi, kx, ky, kz);
+    T q[3];
+    qvec(sym, true, kx, ky, kz, q);
+    const T minv = T(1) / (T(1) + l2 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]));
+    const cpx<T> rn = init ? b[gi] - Ap[gi] : r[gi] - scale(Ap[gi], alpha);
+    r[gi] = rn;
+    const double wt = hweight(kx, g.n1h);
+    const double rr = (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
+    arr += wt * rr;
+    arz += wt * rr * (double)minv;
+  }
+  double s = block_sum(arz, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  s = block_sum(arr, red);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s;
+}
+
+// Exact Hermitian symmetry on the planes kx = 0 and kx = n1/2, where both
+// members of a conjugate pair (ky, kz) <-> (-ky, -kz) are stored: replace the
+// pair by (a + conj b)/2 and its conjugate.  Rounding in the y/z transforms of
+// real data leaves an anti-Hermitian part there that no real field carries and
+// that the half-spectrum operator maps to zero.  One thread per pair: the
+// member with the smaller flat (kz, ky) index writes both.
+template <typename T>
+FFTG_KERNEL void k_hermitize(Geo g, int ncomp, cpx<T>* __restrict__ d) {
+  const long long plane = (long long)g.n2 * g.n3;
+  const long long total = plane * 2 * ncomp;
+  for (long long e = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; e < total;
+       e += (long long)gridDim.x * FFT_THREADS) {
+    const long long yz = e % plane;
+    const int side = (int)((e / plane) % 2);
+    const long long comp = e / (2 * plane);
+    const int kx = side ? g.n1h - 1 : 0;
+    const int ky = (int)(yz % g.n2), kz = (int)(yz / g.n2);
+    const int my = (g.n2 - ky) % g.n2, mz = (g.n3 - kz) % g.n3;
+    const long long myz = (long long)mz * g.n2 + my;
+    if (myz < yz) continue;
+    const long long ia = comp * g.Ns + yz * g.n1h + kx;
+    const long long ib = comp * g.Ns + myz * g.n1h + kx;
+    const cpx<T> a = d[ia], b = d[ib];
+    const cpx<T> avg = mk(T(0.5) * (a.x + b.x), T(0.5) * (a.y - b.y));
+    d[ia] = avg;
+    d[ib] = mk(avg.x, -avg.y);
+  }
+}
+
+// Deferred last update x <- x + alpha p.
+template <typename T>
+FFTG_KERNEL void k_xfinal(cpx<T>* __restrict__ x, const cpx<T>* __restrict__ p, long long n,
+                          const KrylovCtl* __restrict__ ctl) {
+  const T alpha = (T)ctl->alpha;
+  if (alpha == T(0)) return;
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * FFT_THREADS)
+    x[i] = x[i] + scale(p[i], alpha);
+}
+
+template <typename T>
+FFTG_KERNEL void k_wnorm2(Geo g, int ncomp, const cpx<T>* __restrict__ a,
+                          double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  double acc = 0.0;
+  const long long n = g.Ns * ncomp;
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * FFT_THREADS) {
+    const cpx<T> v = a[i];
+    acc += hweight((int)(i % g.n1h), g.n1h) * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ============================================================ scalars
+__device__ double ordered_sum(const double* __restrict__ p, int nb, double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += FFT_THREADS) acc += p[i];
+  return block_sum(acc, red);
+}
+
+FFTG_KERNEL void k_fin_alpha(const double* __restrict__ partials, int nb, KrylovCtl* ctl) {
+  if (ctl->done) return;
+  __shared__ double red[FFT_THREADS];
+  const double pAp = ordered_sum(partials, nb, red);
+  if (threadIdx.x == 0) {
+    ctl->pAp = pAp;
+    if (!isfinite(pAp) || !isfinite(ctl->rz)) {
+      ctl->alpha = 0.0;
+      ctl->done = 4;
+    } else if (!(pAp > 0.0)) {
+      ctl->alpha = 0.0;
+      ctl->done = 3;
+    } else {
+      ctl->alpha = ctl->rz / pAp;
+    }
+  }
+}
+
+// nred = 1 (CG: partials = r.r) or 2 (PCG: partials = [r.Mr | r.r]).
+FFTG_KERNEL void k_fin_beta(const double* __restrict__ partials, int nb, int nred,
+                            KrylovCtl* ctl) {
+  if (ctl->done) return;
+  __shared__ double red[FFT_THREADS];
+  const double rz = ordered_sum(partials, nb, red);
+  const double rr = nred == 2 ? ordered_sum(partials + nb, nb, red) : rz;
+  if (threadIdx.x == 0) {
+    ctl->iters += 1;
+    ctl->beta = rz / ctl->rz;
+    ctl->rz = rz;
+    ctl->rr = rr;
+    if (!isfinite(rr) || !isfinite(rz))
+      ctl->done = 4;
+    else if (rr <= ctl->tol2)
+      ctl->done = 1;
+    else if (ctl->iters >= ctl->maxit)
+      ctl->done = 2;
+  }
+}
+
+FFTG_KERNEL void k_fin_sums(const double* __restrict__ partials, int nb, int nred,
+                            double* __restrict__ out) {
+  __shared__ double red[FFT_THREADS];
+  for (int k = 0; k < nred; ++k) {
+    const double s = ordered_sum(partials + (long long)k * nb, nb, red);
+    if (threadIdx.x == 0) out[k] = s;
+  }
+}
+
+// ============================================================ constitutive
+// Principal values of a symmetric 3x3 tensor (Mandel input) by the closed-form
+// trigonometric solution of the characteristic cubic (Smith 1961).
+__device__ void principal3(const double e[6], double lam[3]) {
+  const double r2 = 0.70710678118654752440084436210485;
+  const double a11 = e[0], a22 = e[1], a33 = e[2];
+  const double a23 = e[3] * r2, a13 = e[4] * r2, a12 = e[5] * r2;
+  const double p1 = a12 * a12 + a13 * a13 + a23 * a23;
+  const double qm = (a11 + a22 + a33) / 3.0;
+  const double d1 = a11 - qm, d2 = a22 - qm, d3 = a33 - qm;
+  const double p2 = d1 * d1 + d2 * d2 + d3 * d3 + 2.0 * p1;
+  if (p2 <= 0.0) {
+    lam[0] = lam[1] = lam[2] = qm;
+    return;
+  }
+  const double p = sqrt(p2 / 6.0);
+  const double ip = 1.0 / p;
+  const double b11 = d1 * ip, b22 = d2 * ip, b33 = d3 * ip;
+  const double b12 = a12 * ip, b13 = a13 * ip, b23 = a23 * ip;
+  const double detb = b11 * (b22 * b33 - b23 * b23) - b12 * (b12 * b33 - b23 * b13) +
+                      b13 * (b12 * b23 - b22 * b13);
+  double rr = 0.5 * detb;
+  rr = rr < -1.0 ? -1.0 : (rr > 1.0 ? 1.0 : rr);
+  const double phi = acos(rr) / 3.0;
+  lam[0] = qm + 2.0 * p * cos(phi);
+  lam[2] = qm + 2.0 * p * cos(phi + 2.0943951023931954923084289221863);
+  lam[1] = 3.0 * qm - lam[0] - lam[2];
+}
+
+// Per voxel: backward-Euler J2 radial return on the effective stress with
+// linear hardening, frozen damage, sigma = (1-D) sigma_eff, compact consistent
+// tangent (1-D){K, 2 mu theta, 2 mu theta_bar, n} stored as
+// [a, b, m0..m5] with K:e = a tr(e) I + b dev(e) - (m.e) m, m = sqrt(c) n;
+// local sources per field.  Elastic phases: sigma = (1-D) C:e.
+template <typename TT>
+FFTG_KERNEL void k_constitutive(MatTable tab, Geo g, int c, int J,
+                                const unsigned char* __restrict__ phase,
+                                const double* __restrict__ eps, const double* __restrict__ st_n,
+                                const double* __restrict__ D, double* __restrict__ sigma,
+                                double* __restrict__ st_np1, double* __restrict__ alpha,
+                                TT* __restrict__ tan) {
+  const long long N = g.N;
+  const double sq32 = 1.2247448713915890490986420373529;  // sqrt(3/2)
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    double e[6];
+    if (c == 6) {
+      for (int i = 0; i < 6; ++i) e[i] = eps[i * N + v];
+    } else {
+      e[0] = eps[v];
+      e[1] = eps[N + v];
+      e[2] = 0.0;
+      e[3] = 0.0;
+      e[4] = 0.0;
+      e[5] = eps[2 * N + v];
+    }
+    double ep[6];
+    for (int i = 0; i < 6; ++i) ep[i] = st_n[i * N + v];
+    double kap = st_n[6 * N + v];
+    const double K = m.K, mu = m.mu;
+    double s[6], tb = 2.0 * mu, tc = 0.0, nv[6] = {0, 0, 0, 0, 0, 0};
+    if (m.model == 1) {
+      double ee[6];
+      for (int i = 0; i < 6; ++i) ee[i] = e[i] - ep[i];
+      const double tr = ee[0] + ee[1] + ee[2];
+      double dev[6];
+      for (int i = 0; i < 6; ++i) dev[i] = 2.0 * mu * ee[i];
+      for (int i = 0; i < 3; ++i) dev[i] -= 2.0 * mu * tr / 3.0;
+      double ns2 = 0.0;
+      for (int i = 0; i < 6; ++i) ns2 += dev[i] * dev[i];
+      const double ns = sqrt(ns2);
+      const double f = sq32 * ns - (m.sy + m.H * kap);
+      if (f > 0.0) {
+        const double dk = f / (3.0 * mu + m.H);
+        for (int i = 0; i < 6; ++i) nv[i] = dev[i] / ns;
+        const double gam = sq32 * dk;
+        for (int i = 0; i < 6; ++i) {
+          ep[i] += gam * nv[i];
+          dev[i] -= 2.0 * mu * gam * nv[i];
+        }
+        kap += dk;
+        const double theta = 1.0 - 2.0 * mu * gam / ns;
+        const double thetab = 1.0 / (1.0 + m.H / (3.0 * mu)) - (1.0 - theta);
+        tb = 2.0 * mu * theta;
+        tc = 2.0 * mu * thetab;
+      }
+      for (int i = 0; i < 6; ++i) s[i] = dev[i];
+      for (int i = 0; i < 3; ++i) s[i] += K * tr;
+    } else {
+      const double tr = e[0] + e[1] + e[2];
+      for (int i = 0; i < 6; ++i) s[i] = 2.0 * mu * e[i];
+      for (int i = 0; i < 3; ++i) s[i] += (K - 2.0 * mu / 3.0) * tr;
+    }
+    double dmg = 0.0;
+    if (m.model != 0 && m.dfield >= 0 && m.dfield < J) dmg = D[(long long)m.dfield * N + v];
+    const double w1 = 1.0 - dmg;
+    if (c == 6) {
+      for (int i = 0; i < 6; ++i) sigma[i * N + v] = w1 * s[i];
+    } else {
+      sigma[v] = w1 * s[0];
+      sigma[N + v] = w1 * s[1];
+      sigma[2 * N + v] = w1 * s[5];
+    }
+    for (int i = 0; i < 6; ++i) st_np1[i * N + v] = ep[i];
+    st_np1[6 * N + v] = kap;
+    tan[v] = (TT)(w1 * K);
+    tan[N + v] = (TT)(w1 * tb);
+    const double sc = sqrt(w1 * tc);
+    for (int i = 0; i < 6; ++i) tan[(2 + i) * N + v] = (TT)(sc * nv[i]);
+    for (int j = 0; j < J; ++j) {
+      double a = 0.0;
+      if (j == m.dfield) {
+        if (m.model == 1) {
+          a = kap;
+        } else if (m.model == 2) {
+          double lam[3];
+          principal3(e, lam);
+          double s2 = 0.0;
+          for (int i = 0; i < 3; ++i)
+            if (lam[i] > 0.0) s2 += lam[i] * lam[i];
+          a = sqrt(s2);
+        }
+      }
+      alpha[(long long)j * N + v] = a;
+    }
+  }
+}
+
+// D_j(x) from the non-local fields (damage laws of the phase models).
+FFTG_KERNEL void k_damage(MatTable tab, long long N, int J, const unsigned char* __restrict__ phase,
+                          const double* __restrict__ abar, const double* __restrict__ hist,
+                          double* __restrict__ D) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    for (int j = 0; j < J; ++j) {
+      double d = 0.0;
+      if (m.model != 0 && m.dfield == j) {
+        double a = abar[(long long)j * N + v];
+        if (m.model == 2) {
+          const double hv = hist[(long long)j * N + v];
+          a = hv > a ? hv : a;
+        }
+        d = (a - m.dC) / (m.dR - m.dC);
+        d = d < 0.0 ? 0.0 : (d > m.dmax ? m.dmax : d);
+      }
+      D[(long long)j * N + v] = d;
+    }
+  }
+}
+
+template <typename TL>
+FFTG_KERNEL void k_ell2(MatTable tab, long long N, int j, const unsigned char* __restrict__ phase,
+                        TL* __restrict__ ell2) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    ell2[v] = (TL)tab.m[ph < tab.nphase ? ph : 0].ell2[j];
+  }
+}
+
+// Per-component sums of a real field [ncomp][N] -> partials [ncomp][gridDim].
+FFTG_KERNEL void k_comp_sums(long long N, int ncomp, const double* __restrict__ f,
+                             double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  for (int k = 0; k < ncomp; ++k) {
+    double acc = 0.0;
+    for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+         v += (long long)gridDim.x * FFT_THREADS)
+      acc += f[k * N + v];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[(long long)k * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+struct Vec6 {
+  double v[6];
+};
+
+FFTG_KERNEL void k_add_const(long long N, int ncomp, double* __restrict__ f, Vec6 d) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS)
+    for (int k = 0; k < ncomp; ++k)
+      if (d.v[k] != 0.0) f[k * N + v] += d.v[k];
+}
+
+// Staggered error terms: partials [0] max_x ||eps_new - eps_old||^2,
+// [1 + 2j] sum (abar_new - abar_old)^2, [2 + 2j] sum abar_new^2.
+FFTG_KERNEL void k_stagger_err(long long N, int c, int J, const double* __restrict__ en,
+                               const double* __restrict__ eo, const double* __restrict__ an,
+                               const double* __restrict__ ao, double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  double mx = 0.0;
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    double s = 0.0;
+    for (int k = 0; k < c; ++k) {
+      const double d = en[k * N + v] - eo[k * N + v];
+      s += d * d;
+    }
+    mx = s > mx ? s : mx;
+  }
+  // max reduction
+  __syncthreads();
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = FFT_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s && red[threadIdx.x + s] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+  for (int j = 0; j < J; ++j) {
+    double a1 = 0.0, a2 = 0.0;
+    for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+         v += (long long)gridDim.x * FFT_THREADS) {
+      const double x = an[j * N + v], d = x - ao[j * N + v];
+      a1 += d * d;
+      a2 += x * x;
+    }
+    double s = block_sum(a1, red);
+    if (threadIdx.x == 0) partials[(long long)(1 + 2 * j) * gridDim.x + blockIdx.x] = s;
+    s = block_sum(a2, red);
+    if (threadIdx.x == 0) partials[(long long)(2 + 2 * j) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+FFTG_KERNEL void k_vmax(long long n, double* __restrict__ a, const double* __restrict__ b) {
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * FFT_THREADS)
+    a[i] = b[i] > a[i] ? b[i] : a[i];
+}
+
+template <typename TA, typename TB>
+FFTG_KERNEL void k_convert(long long n, const TA* __restrict__ a, TB* __restrict__ b) {
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * FFT_THREADS)
+    b[i] = (TB)a[i];
+}
+
+template <typename T>
+FFTG_KERNEL void k_sum_ell2(long long N, const T* __restrict__ e, double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  double acc = 0.0;
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS)
+    acc += (double)e[v];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ============================================================ launchers
+static inline int grid_for(long long n) {
+  long long b = (n + FFT_THREADS - 1) / FFT_THREADS;
+  if (b > RED_BLOCKS) b = RED_BLOCKS;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T>
+void launch_x_r2c(const Plan& p, const cpx<T>* tw, const T* in, cpx<T>* out, long long S,
+                  int n1, int n1h, hipStream_t st) {
+  const int P = LDS_ELEMS / n1;
+  const long long nb = (S + 2 * P - 1) / (2 * P);
+  hipLaunchKernelGGL(k_x_r2c<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, in, out,
+                     S, n1, n1h, P);
+}
+
+template <typename T, typename TO>
+void launch_x_c2r(const Plan& p, const cpx<T>* tw, const cpx<T>* in, TO* out, long long S,
+                  int n1, int n1h, T scl, bool acc, hipStream_t st) {
+  const int P = LDS_ELEMS / n1;
+  const long long nb = (S + 2 * P - 1) / (2 * P);
+  hipLaunchKernelGGL((k_x_c2r<T, TO>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, in,
+                     out, S, n1, n1h, P, scl, acc ? 1 : 0);
+}
+
+static inline int tile_lines(int n, int ncomp) {
+  const int tl = LDS_ELEMS / (n * ncomp);
+  if (tl < 1) throw std::runtime_error("strided pass: line does not fit in LDS");
+  return tl;
+}
+
+template <typename T>
+void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nlines,
+                    long long inner, long long ostride, long long es, bool fwd,
+                    const KrylovCtl* ctl, hipStream_t st) {
+  const int TL = tile_lines(p.n, 1);
+  const long long nb = (nlines + TL - 1) / TL;
+  if (fwd)
+    hipLaunchKernelGGL((k_strided<T, true>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
+                       data, nlines, inner, ostride, es, TL, ctl);
+  else
+    hipLaunchKernelGGL((k_strided<T, false>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
+                       data, nlines, inner, ostride, es, TL, ctl);
+}
+
+// outer axis line geometry for a c-component spectrum
+static inline void outer_lines(const Geo& g, int ncomp, bool zouter, long long& nlines,
+                               long long& inner, long long& ostride, long long& es) {
+  if (zouter) {
+    inner = (long long)g.n2 * g.n1h;
+    nlines = inner * ncomp;
+    ostride = g.Ns;
+    es = inner;
+  } else {  // 2D: y is the outer axis, n3 == 1
+    inner = g.n1h;
+    nlines = inner * ncomp;
+    ostride = g.Ns;
+    es = g.n1h;
+  }
+}
+
+template <typename T>
+int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
+                       cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, const KrylovCtl* ctl,
+                       hipStream_t st) {
+  long long nl, inner, os, es;
+  outer_lines(g, c, zouter, nl, inner, os, es);
+  const int TL = tile_lines(p.n, 1);
+  const long long nb = (nl + TL - 1) / TL;
+  hipLaunchKernelGGL(k_gal_dir_inv<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, r, pp,
+                     x, w, nl, inner, os, es, TL, ctl);
+  return (int)nb;
+}
+
+template <typename T>
+int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
+                       const cpx<T>* pp, cpx<T>* w, double* partials, const KrylovCtl* ctl,
+                       hipStream_t st) {
+  long long nl, inner, os, es;
+  outer_lines(g, c, zouter, nl, inner, os, es);
+  const int TL = tile_lines(p.n, 1);
+  const long long nb = (nl + TL - 1) / TL;
+  hipLaunchKernelGGL(k_gal_dot_fwd<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, pp, w,
+                     nl, inner, os, es, TL, g.n1h, partials, ctl);
+  return (int)nb;
+}
+
+static inline void require(bool ok, const char* what) {
+  if (!ok) throw std::runtime_error(what);
+}
+
+template <typename T, typename TT>
+void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
+                        const TT* tan, T scl, const KrylovCtl* ctl, hipStream_t st) {
+  int NL = (2 * LDS_ELEMS) / (c * g.n1);
+  NL -= NL % 2;
+  if (NL < 2) NL = 2;
+  require((c * NL / 2) * g.n1 <= LDS_ELEMS, "x pass: line batch does not fit in LDS");
+  const long long nlines = (long long)g.n2 * g.n3;
+  const long long nb = (nlines + NL - 1) / NL;
+  hipLaunchKernelGGL((k_x_fused_gal<T, TT>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
+                     g, c, NL, w, tan, scl, ctl);
+}
+
+template <typename T, typename TL>
+void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
+                         const TL* ell2, T scl, const KrylovCtl* ctl, hipStream_t st) {
+  int NL = (2 * LDS_ELEMS) / (g.ndim * g.n1);
+  NL -= NL % 2;
+  if (NL < 2) NL = 2;
+  require((g.ndim * NL / 2) * g.n1 <= LDS_ELEMS, "x pass: line batch does not fit in LDS");
+  const long long nlines = (long long)g.n2 * g.n3;
+  const long long nb = (nlines + NL - 1) / NL;
+  hipLaunchKernelGGL((k_x_fused_helm<T, TL>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
+                     g, NL, w, ell2, scl, ctl);
+}
+
+template <typename T>
+int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char* m,
+                     cpx<T>* r, const cpx<T>* w, double* partials, const KrylovCtl* ctl,
+                     hipStream_t st) {
+  const int nb = grid_for(g.Ns);
+  if (c == 6)
+    hipLaunchKernelGGL((k_gal_resid<T, 6>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
+                       m[2], m[3], m[4], m[5], r, w, partials, ctl);
+  else
+    hipLaunchKernelGGL((k_gal_resid<T, 3>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
+                       m[2], m[3], m[4], m[5], r, w, partials, ctl);
+  return nb;
+}
+
+template <typename T>
+int launch_gal_rhs(const Geo& g, int c, const Sym<double>& sym, const unsigned char* m,
+                   const double* S, const cpx<double>* sh, cpx<T>* r, double* partials,
+                   hipStream_t st) {
+  const int nb = grid_for(g.Ns);
+  if (c == 6)
+    hipLaunchKernelGGL((k_gal_rhs<T, 6>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
+                       m[2], m[3], m[4], m[5], S[0], S[1], S[2], S[3], S[4], S[5], sh, r,
+                       partials);
+  else
+    hipLaunchKernelGGL((k_gal_rhs<T, 3>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
+                       m[2], m[3], m[4], m[5], S[0], S[1], S[2], S[3], S[4], S[5], sh, r,
+                       partials);
+  return nb;
+}
+
+template <typename T>
+void launch_project(const Geo& g, int c, const Sym<T>& sym, const unsigned char* m,
+                    cpx<T>* data, hipStream_t st) {
+  const int nb = grid_for(g.Ns);
+  if (c == 6)
+    hipLaunchKernelGGL((k_project<T, 6>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
+                       m[2], m[3], m[4], m[5], data);
+  else
+    hipLaunchKernelGGL((k_project<T, 3>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
+                       m[2], m[3], m[4], m[5], data);
+}
+
+template <typename T>
+int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
+                     const Sym<T>& sym, bool update, const cpx<T>* r, cpx<T>* pp, cpx<T>* x,
+                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st) {
+  long long nl, inner, os, es;
+  outer_lines(g, 1, zouter, nl, inner, os, es);
+  const int TL = tile_lines(p.n, g.ndim);
+  const long long nb = (nl + TL - 1) / TL;
+  hipLaunchKernelGGL(k_h_dir_inv<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, g, sym,
+                     update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
+  return (int)nb;
+}
+
+template <typename T>
+int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
+                     const Sym<T>& sym, const cpx<T>* pp, cpx<T>* w, cpx<T>* Ap,
+                     double* partials, const KrylovCtl* ctl, hipStream_t st) {
+  long long nl, inner, os, es;
+  outer_lines(g, 1, zouter, nl, inner, os, es);
+  const int TL = tile_lines(p.n, g.ndim);
+  const long long nb = (nl + TL - 1) / TL;
+  hipLaunchKernelGGL(k_h_div_fwd<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, g, sym,
+                     pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
+  return (int)nb;
+}
+
+template <typename T>
+int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const cpx<T>* b,
+                   const cpx<T>* Ap, double* partials, const KrylovCtl* ctl, hipStream_t st) {
+  const int nb = grid_for(g.Ns);
+  hipLaunchKernelGGL(k_h_resid<T>, dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, init ? 1 : 0, r, b,
+                     Ap, partials, ctl);
+  return nb;
+}
+
+void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FFT_THREADS), 0, st, partials, nb, ctl);
+}
+void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(FFT_THREADS), 0, st, partials, nb, nred, ctl);
+}
+void launch_fin_sums(const double* partials, int nb, int nred, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_sums, dim3(1), dim3(FFT_THREADS), 0, st, partials, nb, nred, out);
+}
+
+template <typename T>
+void launch_xfinal(cpx<T>* x, const cpx<T>* p, long long n, const KrylovCtl* ctl,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_xfinal<T>, dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, x, p, n, ctl);
+}
+
+template <typename T>
+void launch_hermitize(const Geo& g, int ncomp, cpx<T>* d, hipStream_t st) {
+  hipLaunchKernelGGL(k_hermitize<T>, dim3(grid_for(2LL * g.n2 * g.n3 * ncomp)), dim3(FFT_THREADS), 0,
+                     st, g, ncomp, d);
+}
+
+template <typename T>
+int launch_wnorm2(const Geo& g, int ncomp, const cpx<T>* a, double* partials, hipStream_t st) {
+  const int nb = grid_for(g.Ns * ncomp);
+  hipLaunchKernelGGL(k_wnorm2<T>, dim3(nb), dim3(FFT_THREADS), 0, st, g, ncomp, a, partials);
+  return nb;
+}
+
+template <typename TT>
+void launch_constitutive(const MatTable& tab, const Geo& g, int c, int J,
+                         const unsigned char* phase, const double* eps, const double* st_n,
+                         const double* D, double* sigma, double* st_np1, double* alpha, TT* tan,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_constitutive<TT>, dim3(grid_for(g.N)), dim3(FFT_THREADS), 0, st, tab, g, c,
+                     J, phase, eps, st_n, D, sigma, st_np1, alpha, tan);
+}
+
+void launch_damage(const MatTable& tab, long long N, int J, const unsigned char* phase,
+                   const double* abar, const double* hist, double* D, hipStream_t st) {
+  hipLaunchKernelGGL(k_damage, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, J, phase, abar,
+                     hist, D);
+}
+
+template <typename TL>
+void launch_ell2(const MatTable& tab, long long N, int j, const unsigned char* phase, TL* ell2,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_ell2<TL>, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, j, phase,
+                     ell2);
+}
+
+int launch_comp_sums(long long N, int ncomp, const double* f, double* partials,
+                     hipStream_t st) {
+  const int nb = grid_for(N);
+  hipLaunchKernelGGL(k_comp_sums, dim3(nb), dim3(FFT_THREADS), 0, st, N, ncomp, f, partials);
+  return nb;
+}
+
+void launch_add_const(long long N, int ncomp, double* f, const double* delta6, hipStream_t st) {
+  Vec6 d;
+  for (int i = 0; i < 6; ++i) d.v[i] = i < ncomp ? delta6[i] : 0.0;
+  hipLaunchKernelGGL(k_add_const, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, N, ncomp, f, d);
+}
+
+int launch_stagger_err(long long N, int c, int J, const double* en, const double* eo,
+                       const double* an, const double* ao, double* partials, hipStream_t st) {
+  const int nb = grid_for(N);
+  hipLaunchKernelGGL(k_stagger_err, dim3(nb), dim3(FFT_THREADS), 0, st, N, c, J, en, eo, an, ao,
+                     partials);
+  return nb;
+}
+
+void launch_vmax(long long n, double* a, const double* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_vmax, dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, a, b);
+}
+
+template <typename TA, typename TB>
+void launch_convert(long long n, const TA* a, TB* b, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<TA, TB>), dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, a, b);
+}
+
+template <typename T>
+int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st) {
+  const int nb = grid_for(N);
+  hipLaunchKernelGGL(k_sum_ell2<T>, dim3(nb), dim3(FFT_THREADS), 0, st, N, e, partials);
+  return nb;
+}
+
+// ------------------------------------------------------------ instantiations
+#define INST_T(T)                                                                               \
+  template void launch_x_r2c<T>(const Plan&, const cpx<T>*, const T*, cpx<T>*, long long, int,  \
+                                int, hipStream_t);                                               \
+  template void launch_strided<T>(const Plan&, const cpx<T>*, cpx<T>*, long long, long long,     \
+                                  long long, long long, bool, const KrylovCtl*, hipStream_t);    \
+  template int launch_gal_dir_inv<T>(const Plan&, const cpx<T>*, const Geo&, int, bool, cpx<T>*, \
+                                     cpx<T>*, cpx<T>*, cpx<T>*, const KrylovCtl*, hipStream_t);  \
+  template int launch_gal_dot_fwd<T>(const Plan&, const cpx<T>*, const Geo&, int, bool,          \
+                                     const cpx<T>*, cpx<T>*, double*, const KrylovCtl*,          \
+                                     hipStream_t);                                               \
+  template int launch_gal_resid<T>(const Geo&, int, const Sym<T>&, const unsigned char*,        \
+                                    cpx<T>*, const cpx<T>*, double*, const KrylovCtl*,           \
+                                    hipStream_t);                                                \
+  template int launch_gal_rhs<T>(const Geo&, int, const Sym<double>&, const unsigned char*,     \
+                                  const double*, const cpx<double>*, cpx<T>*, double*,           \
+                                  hipStream_t);                                                  \
+  template void launch_project<T>(const Geo&, int, const Sym<T>&, const unsigned char*, cpx<T>*, \
+                                  hipStream_t);                                                  \
+  template int launch_h_dir_inv<T>(const Plan&, const cpx<T>*, const Geo&, bool, const Sym<T>&,  \
+                                   bool, const cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*,               \
+                                   const KrylovCtl*, hipStream_t);                               \
+  template int launch_h_div_fwd<T>(const Plan&, const cpx<T>*, const Geo&, bool, const Sym<T>&,  \
+                                   const cpx<T>*, cpx<T>*, cpx<T>*, double*, const KrylovCtl*,   \
+                                   hipStream_t);                                                 \
+  template int launch_h_resid<T>(const Geo&, const Sym<T>&, bool, cpx<T>*, const cpx<T>*,       \
+                                  const cpx<T>*, double*, const KrylovCtl*, hipStream_t);        \
+  template void launch_xfinal<T>(cpx<T>*, const cpx<T>*, long long, const KrylovCtl*,            \
+                                 hipStream_t);                                                   \
+  template void launch_hermitize<T>(const Geo&, int, cpx<T>*, hipStream_t);                     \
+  template int launch_wnorm2<T>(const Geo&, int, const cpx<T>*, double*, hipStream_t);          \
+  template void launch_x_fused_gal<T, T>(const Plan&, const cpx<T>*, const Geo&, int, cpx<T>*,   \
+                                         const T*, T, const KrylovCtl*, hipStream_t);            \
+  template void launch_x_fused_helm<T, T>(const Plan&, const cpx<T>*, const Geo&, cpx<T>*,       \
+                                          const T*, T, const KrylovCtl*, hipStream_t);           \
+  template void launch_constitutive<T>(const MatTable&, const Geo&, int, int,                    \
+                                       const unsigned char*, const double*, const double*,       \
+                                       const double*, double*, double*, double*, T*,             \
+                                       hipStream_t);                                             \
+  template void launch_ell2<T>(const MatTable&, long long, int, const unsigned char*, T*,        \
+                               hipStream_t);                                                     \
+  template int launch_sum_ell2<T>(long long, const T*, double*, hipStream_t);
+
+INST_T(double)
+INST_T(float)
+
+template void launch_x_c2r<double, double>(const Plan&, const cpx<double>*, const cpx<double>*,
+                                           double*, long long, int, int, double, bool,
+                                           hipStream_t);
+template void launch_x_c2r<float, double>(const Plan&, const cpx<float>*, const cpx<float>*,
+                                          double*, long long, int, int, float, bool, hipStream_t);
+template void launch_x_c2r<float, float>(const Plan&, const cpx<float>*, const cpx<float>*,
+                                         float*, long long, int, int, float, bool, hipStream_t);
+template void launch_convert<double, float>(long long, const double*, float*, hipStream_t);
+template void launch_convert<float, double>(long long, const float*, double*, hipStream_t);
+
+}  // namespace fftg

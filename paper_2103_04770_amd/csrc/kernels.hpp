@@ -1,0 +1,150 @@
+// Shared declarations between the kernels and the host solver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "fft_device.hpp"
+
+namespace fftg {
+
+// Grid geometry.  Real fields: [comp][n3][n2][n1]; half spectra:
+// [comp][n3][n2][n1h], n1h = n1/2 + 1.
+struct Geo {
+  int ndim, n1, n2, n3, n1h;
+  long long N;   // n1 n2 n3
+  long long Ns;  // n1h n2 n3
+};
+
+// Per-axis derivative tables (Sec. 3.2.1), packed in one device array:
+//   pq[a][k] : projection numerator   ROTATED (2/h) sin(theta/2); SPECTRAL theta/h
+//              (zero on the Nyquist frequency for SPECTRAL)
+//   gq[a][k] : gradient numerator, as pq but zero on the Nyquist frequency
+//   cs[a][k] : ROTATED cos(theta/2) (exactly zero on Nyquist); SPECTRAL 1
+// theta = 2 pi k'/n with k' the signed frequency (x axis: 0..n1/2).
+template <typename T>
+struct Sym {
+  const T* base;
+  int pq[3], gq[3], cs[3];  // offsets into base
+};
+
+// Krylov control block kept in device memory.  The finalize kernels update
+// it; every iteration kernel reads it and returns at once when done != 0, so
+// that the host can launch iterations in chunks and read it back rarely.
+struct KrylovCtl {
+  double rz;      // r.z (PCG) or r.r (CG) of the current residual
+  double rr;      // r.r of the current residual (stopping test)
+  double pAp;
+  double alpha;   // step of the current iteration (applied to x lazily)
+  double beta;
+  double bb;      // ||b||^2
+  double tol2;    // tol^2 ||b||^2
+  double ell2ref; // preconditioner length^2 (Helmholtz)
+  int iters, maxit;
+  int done;       // 0 running, 1 converged, 2 max iterations, 3 breakdown, 4 non-finite
+  int pad;
+};
+
+struct Mat {
+  int model;  // 0 elastic, 1 J2 damage, 2 elastic cracking
+  int dfield;
+  double K, mu, sy, H, dC, dR, dmax;
+  double ell2[4];
+};
+struct MatTable {
+  int nphase;
+  int pad;
+  Mat m[16];
+};
+
+constexpr int RED_BLOCKS = 1024;  // largest grid of the pointwise reduction kernels
+// Every reduction launcher returns its block count; the finalisers take it.
+
+// ---------------------------------------------------------------- launchers
+template <typename T>
+void launch_x_r2c(const Plan& p, const cpx<T>* tw, const T* in, cpx<T>* out, long long S,
+                  int n1, int n1h, hipStream_t st);
+template <typename T, typename TO>
+void launch_x_c2r(const Plan& p, const cpx<T>* tw, const cpx<T>* in, TO* out, long long S,
+                  int n1, int n1h, T scale, bool acc, hipStream_t st);
+template <typename T>
+void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nlines,
+                    long long inner, long long ostride, long long es, bool fwd,
+                    const KrylovCtl* ctl, hipStream_t st);
+
+// Galerkin CG passes
+template <typename T>
+int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
+                       cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, const KrylovCtl* ctl,
+                       hipStream_t st);
+template <typename T>
+int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
+                       const cpx<T>* pp, cpx<T>* w, double* partials, const KrylovCtl* ctl,
+                       hipStream_t st);
+template <typename T, typename TT>
+void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
+                        const TT* tan, T scale, const KrylovCtl* ctl, hipStream_t st);
+template <typename T>
+int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char* mask6,
+                      cpx<T>* r, const cpx<T>* w, double* partials, const KrylovCtl* ctl,
+                      hipStream_t st);
+template <typename T>
+int launch_gal_rhs(const Geo& g, int c, const Sym<double>& sym, const unsigned char* mask6,
+                    const double* Sbar6, const cpx<double>* sig_hat, cpx<T>* r,
+                    double* partials, hipStream_t st);
+template <typename T>
+void launch_project(const Geo& g, int c, const Sym<T>& sym, const unsigned char* mask6,
+                    cpx<T>* data, hipStream_t st);
+
+// Helmholtz PCG passes
+template <typename T>
+int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
+                     const Sym<T>& sym, bool update, const cpx<T>* r, cpx<T>* pp, cpx<T>* x,
+                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st);
+template <typename T>
+int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
+                     const Sym<T>& sym, const cpx<T>* pp, cpx<T>* w, cpx<T>* Ap,
+                     double* partials, const KrylovCtl* ctl, hipStream_t st);
+template <typename T, typename TL>
+void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
+                         const TL* ell2, T scale, const KrylovCtl* ctl, hipStream_t st);
+template <typename T>
+int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const cpx<T>* b,
+                    const cpx<T>* Ap, double* partials, const KrylovCtl* ctl, hipStream_t st);
+
+// Krylov scalars
+void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st);
+void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st);
+void launch_fin_sums(const double* partials, int nb, int nred, double* out, hipStream_t st);
+template <typename T>
+void launch_xfinal(cpx<T>* x, const cpx<T>* p, long long n, const KrylovCtl* ctl,
+                   hipStream_t st);
+template <typename T>
+void launch_hermitize(const Geo& g, int ncomp, cpx<T>* d, hipStream_t st);
+template <typename T>
+int launch_wnorm2(const Geo& g, int ncomp, const cpx<T>* a, double* partials, hipStream_t st);
+
+// grid-space kernels (FP64)
+template <typename TT>
+void launch_constitutive(const MatTable& tab, const Geo& g, int c, int J,
+                         const unsigned char* phase, const double* eps, const double* state_n,
+                         const double* D, double* sigma, double* state_np1, double* alpha,
+                         TT* tan, hipStream_t st);
+void launch_damage(const MatTable& tab, long long N, int J, const unsigned char* phase,
+                   const double* abar, const double* hist, double* D, hipStream_t st);
+template <typename TL>
+void launch_ell2(const MatTable& tab, long long N, int j, const unsigned char* phase, TL* ell2,
+                 hipStream_t st);
+int launch_comp_sums(long long N, int ncomp, const double* f, double* partials,
+                      hipStream_t st);
+void launch_add_const(long long N, int ncomp, double* f, const double* delta6,
+                      hipStream_t st);
+int launch_stagger_err(long long N, int c, int J, const double* eps_new, const double* eps_old,
+                        const double* ab_new, const double* ab_old, double* partials,
+                        hipStream_t st);
+void launch_vmax(long long n, double* a, const double* b, hipStream_t st);
+template <typename TA, typename TB>
+void launch_convert(long long n, const TA* a, TB* b, hipStream_t st);
+template <typename T>
+int launch_sum_ell2(long long N, const T* ell2, double* partials, hipStream_t st);
+
+}  // namespace fftg

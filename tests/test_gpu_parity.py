@@ -1,0 +1,268 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle,
+element by element on the same seeded inputs.
+
+Tolerances: single operator applications 1e-13 relative to the largest
+magnitude (FP64 transforms of these sizes round at ~1e-15 per element);
+converged solves 1e-10 relative with Krylov tolerances of 1e-12 and Newton
+1e-11 on both sides (two correct solvers differ by about tol times the
+condition number).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import galerkin, helmholtz, material, spectral, staggered  # noqa: E402
+from paper_2103_04770_amd import microstructure as ms  # noqa: E402
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def solver(shape_np, **kw):
+    """shape_np in numpy order (z, y, x) or (y, x)."""
+    from paper_2103_04770_amd import Solver
+    _need_gpu()
+    return Solver(tuple(reversed(shape_np)), **kw)
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+FFT_SHAPES = [(18, 12), (32, 32), (6, 64), (24, 12, 16), (8, 8, 8), (18, 24, 64), (4, 6, 96),
+              (3, 9, 12), (1, 4, 8)]
+
+
+@pytest.mark.parametrize("shape", FFT_SHAPES)
+@pytest.mark.parametrize("ncomp", [1, 3, 6])
+def test_forward_inverse_match_dft(shape, ncomp):
+    say("forward/inverse", shape, ncomp)
+    s = solver(shape)
+    x = np.random.default_rng(0).standard_normal((ncomp,) + shape)
+    n1h = shape[-1] // 2 + 1
+    out = torch.empty((ncomp,) + shape[:-1] + (n1h, 2), dtype=torch.float64, device="cuda")
+    s.fftg_forward(dev(x), out)
+    got = host(out)
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = np.fft.fftn(x, axes=tuple(range(1, len(shape) + 1)))[..., :n1h]
+    assert relerr(got, ref) <= 1e-13
+    back = torch.empty((ncomp,) + shape, dtype=torch.float64, device="cuda")
+    s.fftg_inverse(out, back)
+    assert relerr(host(back), x) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", [(12, 18), (16, 16), (6, 8, 12), (12, 8, 16), (9, 6, 24)])
+@pytest.mark.parametrize("scheme", [spectral.ROTATED, spectral.SPECTRAL])
+def test_projection(shape, scheme):
+    say("projection", shape, scheme)
+    from paper_2103_04770_amd import ROTATED, SPECTRAL
+    s = solver(shape, scheme=ROTATED if scheme == spectral.ROTATED else SPECTRAL, h=0.5)
+    c = 6 if len(shape) == 3 else 3
+    tau = np.random.default_rng(1).standard_normal((c,) + shape)
+    mask = np.array([0, 1, 1, 0, 1, 0][:c], np.uint8)
+    out = torch.empty((c,) + shape, dtype=torch.float64, device="cuda")
+    s.fftg_project((mask, np.zeros(c), np.zeros(c)), dev(tau), out)
+    ref = galerkin.project(tau, spectral.projection_symbol(shape, 0.5, scheme), mask)
+    assert relerr(host(out), ref) <= 1e-13
+
+
+def _mixed_inputs(shape, seed, nfields=2):
+    rng = np.random.default_rng(seed)
+    phase = rng.integers(0, 3, size=shape).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0, 0.04], dfield=0),
+             ms.particle_elastic(ell=[0.04, 0.04]),
+             ms.particle_cracking(ell=[0.06, 1.5], dfield=1)]
+    c = 6 if len(shape) == 3 else 3
+    eps = rng.standard_normal((c,) + shape) * 4e-3
+    epsp = rng.standard_normal((6,) + shape) * 1e-3
+    epsp[:3] -= epsp[:3].mean(axis=0)
+    kap = np.abs(rng.standard_normal(shape)) * 5e-3
+    D = rng.uniform(0, 0.6, size=(nfields,) + shape)
+    return phase, table, eps, epsp, kap, D
+
+
+@pytest.mark.parametrize("shape", [(8, 12), (6, 8, 12), (12, 12, 12)])
+def test_constitutive(shape):
+    say("constitutive", shape)
+    s = solver(shape)
+    phase, table, eps, epsp, kap, D = _mixed_inputs(shape, 2)
+    c = eps.shape[0]
+    J = 2
+    ref = material.constitutive(eps, epsp, kap, D, phase, table, J)
+    sig = torch.empty((c,) + shape, dtype=torch.float64, device="cuda")
+    st1 = torch.empty((7,) + shape, dtype=torch.float64, device="cuda")
+    al = torch.empty((J,) + shape, dtype=torch.float64, device="cuda")
+    state_n = np.concatenate([epsp, kap[None]], axis=0)
+    s.fftg_constitutive(dev(phase, torch.uint8), table, J, dev(D), dev(state_n), dev(eps), sig, st1, al)
+    assert relerr(host(sig), ref["sigma"]) <= 1e-13
+    st1h = host(st1)
+    assert relerr(st1h[:6], ref["epsp"]) <= 1e-13
+    assert relerr(st1h[6], ref["kappa"]) <= 1e-13
+    assert relerr(host(al), ref["alpha"]) <= 1e-12
+    assert (ref["kappa"] > kap).sum() > 10          # plastic voxels present
+    # the consistent tangent, through G*(K : p)
+    p = np.random.default_rng(3).standard_normal((c,) + shape)
+    mask = np.array([0, 1, 1, 0, 1, 1][:c], np.uint8)
+    out = torch.empty((c,) + shape, dtype=torch.float64, device="cuda")
+    s.fftg_apply_galerkin((mask, np.zeros(c), np.zeros(c)), dev(p), out)
+    q = spectral.projection_symbol(shape)
+    refo = galerkin.project(material.apply_tangent(ref["C"], p), q, mask)
+    assert relerr(host(out), refo) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(12, 18), (8, 12, 16), (16, 16, 16)])
+def test_apply_helmholtz(shape):
+    say("apply_helmholtz", shape)
+    s = solver(shape)
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal(shape)
+    ell2 = rng.uniform(0.0, 4.0, size=shape)
+    out = torch.empty(shape, dtype=torch.float64, device="cuda")
+    s.fftg_apply_helmholtz(dev(ell2), dev(u), out)
+    _, qt = spectral.symbols(shape)
+    qt = [np.broadcast_to(v, shape) for v in qt]
+    ref = np.real(np.fft.ifftn(helmholtz.operator(np.fft.fftn(u), ell2, qt)))
+    assert relerr(host(out), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", [(32, 32), (12, 18), (16, 16, 16), (24, 12, 18)])
+def test_helmholtz_solve(shape):
+    say("helmholtz_solve", shape)
+    s = solver(shape)
+    rng = np.random.default_rng(5)
+    phase = rng.uniform(size=shape) < 0.3
+    ell2 = np.where(phase, 0.04 ** 2, 2.0 ** 2)
+    alpha = np.where(phase, 0.0, np.abs(rng.standard_normal(shape)) * 1e-2)
+    x0 = np.zeros(shape)
+    ref = helmholtz.helmholtz_solve(alpha, ell2, tol=1e-12, maxit=5000)
+    ab = dev(x0)
+    st = s.helmholtz_solve(dev(alpha), dev(ell2), ab, tol=1e-12, maxit=5000)
+    assert st["converged"]
+    assert abs(st["pcg_iters"] - ref["iters"]) <= max(2, ref["iters"] // 10)
+    assert relerr(host(ab), ref["abar"]) <= 1e-10
+    # warm start from the solution converges at once
+    st2 = s.helmholtz_solve(dev(alpha), dev(ell2), ab, tol=1e-9, maxit=5000)
+    assert st2["pcg_iters"] <= 1
+
+
+def test_helmholtz_constant_length_one_iteration():
+    shape = (16, 16, 16)
+    say("helmholtz constant ell", shape)
+    s = solver(shape)
+    alpha = np.random.default_rng(6).standard_normal(shape)
+    ab = dev(np.zeros(shape))
+    st = s.helmholtz_solve(dev(alpha), dev(np.full(shape, 6.25)), ab, tol=1e-12)
+    _, qt = spectral.symbols(shape)
+    q2 = sum(np.broadcast_to(v, shape) ** 2 for v in qt)
+    ref = np.real(np.fft.ifftn(np.fft.fftn(alpha) / (1 + 6.25 * q2)))
+    assert st["pcg_iters"] == 1
+    assert relerr(host(ab), ref) <= 1e-13
+
+
+def _mech_case(shape, seed):
+    rng = np.random.default_rng(seed)
+    phase = (rng.uniform(size=shape) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_elastic(ell=[1.0])]
+    return phase, table
+
+
+@pytest.mark.parametrize("shape,e11", [((32, 32), 5e-3), ((16, 16, 16), 6e-3), ((12, 18, 24), 4e-3)])
+def test_fftg_solve(shape, e11):
+    say("fftg_solve", shape)
+    s = solver(shape)
+    phase, table = _mech_case(shape, 7)
+    c = 6 if len(shape) == 3 else 3
+    J = 1
+    D = np.random.default_rng(8).uniform(0, 0.3, size=(J,) + shape) * (phase == 0)
+    tgt = ms.uniaxial_mixed(len(shape), e11)
+    ref = galerkin.fftg_solve(phase, table, D, np.zeros((6,) + shape), np.zeros(shape), tgt,
+                              np.zeros((c,) + shape), cg_tol=1e-12, newton_tol=1e-11)
+    eps = dev(np.zeros((c,) + shape))
+    sig = torch.empty((c,) + shape, dtype=torch.float64, device="cuda")
+    st1 = torch.empty((7,) + shape, dtype=torch.float64, device="cuda")
+    al = torch.empty((J,) + shape, dtype=torch.float64, device="cuda")
+    st = s.fftg_solve(dev(phase, torch.uint8), table, J, dev(D), dev(np.zeros((7,) + shape)), tgt,
+                      eps, sig, st1, al, cg_tol=1e-12, newton_tol=1e-11)
+    say("  gpu", st, "oracle newton", ref["newton_iters"], "cg", ref["cg_iters"])
+    assert st["converged"] and ref["converged"]
+    assert relerr(host(eps), ref["eps"]) <= 1e-10
+    assert relerr(host(sig), ref["sigma"]) <= 1e-10
+    assert relerr(host(al), ref["alpha"]) <= 1e-9
+    sm = host(sig).reshape(c, -1).mean(1)
+    rm = ref["sigma"].reshape(c, -1).mean(1)
+    assert np.abs(sm - rm).max() <= 1e-10 * np.abs(rm).max()
+
+
+def _run_staggered(w, max_stagger, tols, ninc=1):
+    shape = w["shape"]
+    s = solver(shape)
+    J = w["nfields"]
+    c = 6 if len(shape) == 3 else 3
+    st_o = staggered.initial_state(shape, len(shape), J)
+    state = dev(np.zeros((c + 7 + 2 * J,) + shape))
+    sig = torch.empty((c,) + shape, dtype=torch.float64, device="cuda")
+    ph = dev(w["phase"], torch.uint8)
+    out = []
+    for inc in range(ninc):
+        tgt = w["load"][inc]
+        st_o, sig_o, hom_o, stats_o = staggered.staggered_step(
+            w["phase"], w["table"], J, st_o, tgt, max_stagger=max_stagger, **tols)
+        d = s.staggered_step(ph, w["table"], J, state, tgt, sig, max_stagger=max_stagger, **tols)
+        say("  inc", inc, "gpu", {k: d[k] for k in ("newton_iters", "cg_iters", "pcg_iters",
+                                                    "stagger_iters", "err")},
+            "oracle", stats_o)
+        out.append((d, host(state), host(sig), st_o, sig_o, hom_o, stats_o))
+    return out, c, J
+
+
+def test_staggered_disc2d_config():
+    """The 32x32 plane-strain disc, one increment to E11 = 5e-3, one staggered pass."""
+    w = ms.workload("disc2d_32")
+    say("staggered disc2d_32")
+    tols = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11, stagger_tol=1e-10)
+    res, c, J = _run_staggered(w, 1, tols)
+    d, state, sig, st_o, sig_o, hom_o, stats_o = res[0]
+    assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-10 * abs(hom_o["sigma"][0])
+    assert relerr(sig, sig_o) <= 1e-10
+    assert relerr(state[:c], st_o["eps"]) <= 1e-10
+    assert relerr(state[c + 7 + J:], st_o["abar"]) <= 1e-9
+    assert relerr(state[c + 6], st_o["kappa"]) <= 1e-9
+
+
+def test_staggered_two_fields_3d():
+    """3D spheres with matrix damage and particle cracking fields; two
+    increments with damage onset forced by low thresholds."""
+    w = ms.workload("spheres_two_fields_16")
+    w["table"][0]["dC"], w["table"][0]["dR"] = 0.0005, 0.02
+    w["table"][1]["dC"], w["table"][1]["dR"] = 5e-4, 5e-3
+    say("staggered spheres_two_fields_16")
+    tols = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11, stagger_tol=1e-9)
+    w["load"] = [ms.uniaxial_mixed(3, 3e-3), ms.uniaxial_mixed(3, 6e-3)]
+    res, c, J = _run_staggered(w, 30, tols, ninc=2)
+    for d, state, sig, st_o, sig_o, hom_o, stats_o in res:
+        assert d["stagger_iters"] == stats_o["stagger_iters"]
+        assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-9 * abs(hom_o["sigma"][0])
+        assert relerr(state[:c], st_o["eps"]) <= 1e-9
+        assert relerr(state[c + 7 + J:], st_o["abar"]) <= 1e-8
+    assert res[-1][3]["abar"][1].max() > 5e-4  # the cracking field is active
