@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Throughput of the staggered FFT solver on one MI355X.
+
+A step is one load increment of the iterated staggered scheme (constitutive
+update, Newton + Galerkin CG, Helmholtz PCG for every non-local field,
+staggered error) on the 128^3 RVE with 25% spheres (radii U(4, 8) voxels),
+a J2-damage matrix and cracking particles (two non-local fields), under
+uniaxial mixed control with increments of 1e-3.  Inputs live in HBM before the
+timed region starts.
+
+Prints ONE JSON line.  value = voxels x (Galerkin CG + Helmholtz PCG
+iterations) / wall time of the timed steps, for the FP64 form; the
+FP32-refined form is reported beside it on the same load path.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "voxel-Krylov-iters/s and HBM GB/s at 128^3, FP64 vs FP32-refined, at 1e-6"
+UNIT = "voxel-Krylov-iters/s"
+PEAK_HBM_GBS = 8000.0
+TOLS = dict(cg_tol=1e-8, pcg_tol=1e-8, newton_tol=1e-8, stagger_tol=1e-6, max_stagger=20)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+KERNEL_CLASSES = ["galerkin_x_fused", "galerkin_y_inv", "galerkin_y_fwd", "galerkin_outer_dir_inv",
+                  "galerkin_outer_dot_fwd", "galerkin_resid", "helmholtz_x_fused",
+                  "helmholtz_outer_dir_inv", "helmholtz_outer_div_fwd", "helmholtz_resid"]
+
+
+def kernel_bytes(name, n, c, nd, J, fp32):
+    """Algorithmic HBM bytes of one launch of a kernel class (each pass reads
+    its inputs once and writes its outputs once)."""
+    N = n ** 3
+    Ns = (n // 2 + 1) * n * n
+    zc = 8 if fp32 else 16       # complex element
+    zr = 4 if fp32 else 8        # real element
+    table = {
+        "galerkin_x_fused": 2 * c * Ns * zc + 8 * N * zr,
+        "galerkin_y_inv": 2 * c * Ns * zc,
+        "galerkin_y_fwd": 2 * c * Ns * zc,
+        "galerkin_outer_dir_inv": 6 * c * Ns * zc,
+        "galerkin_outer_dot_fwd": 3 * c * Ns * zc,
+        "galerkin_resid": 3 * c * Ns * zc,
+        "helmholtz_x_fused": 2 * nd * Ns * zc + N * zr,
+        "helmholtz_y_inv": 2 * nd * Ns * zc,
+        "helmholtz_y_fwd": 2 * nd * Ns * zc,
+        "helmholtz_outer_dir_inv": (5 + nd) * Ns * zc,
+        "helmholtz_outer_div_fwd": (nd + 2) * Ns * zc,
+        "helmholtz_resid": 3 * Ns * zc,
+        "constitutive": N * (1 + 8 * (2 * c + 14 + 2 * J) + 8 * zr),
+    }
+    return table.get(name)
+
+
+def run_form(ws, prec, warmup, steps, profile_kernel=None):
+    import torch
+    from paper_2103_04770_amd import Solver, FP64, FP32_REFINED
+    shape, J, c = ws["shape"], ws["nfields"], 6
+    s = Solver(tuple(reversed(shape)), prec=FP64 if prec == "fp64" else FP32_REFINED)
+    state = torch.zeros((c + 7 + 2 * J,) + shape, dtype=torch.float64, device="cuda")
+    sig = torch.empty((c,) + shape, dtype=torch.float64, device="cuda")
+    ph = torch.from_numpy(ws["phase"]).cuda()
+    load = ws["load"]
+    homog = []
+    for k in range(warmup):
+        d = s.staggered_step(ph, ws["table"], J, state, load[k], sig, **TOLS)
+        homog.append(d["sigma_mean"])
+        log("[%s] warmup inc %d: cg %d pcg %d newton %d stag %d err %.2e  %.0f ms" % (
+            prec, k, d["cg_iters"], d["pcg_iters"], d["newton_iters"], d["stagger_iters"],
+            d["err"], sum(d["t_ms"])))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = dict(cg=0, pcg=0, newton=0, stag=0, t_ms=np.zeros(4))
+    for k in range(warmup, warmup + steps):
+        d = s.staggered_step(ph, ws["table"], J, state, load[k], sig, **TOLS)
+        tot["cg"] += d["cg_iters"]
+        tot["pcg"] += d["pcg_iters"]
+        tot["newton"] += d["newton_iters"]
+        tot["stag"] += d["stagger_iters"]
+        tot["t_ms"] += np.array(d["t_ms"])
+        homog.append(d["sigma_mean"])
+        log("[%s] timed inc %d: cg %d pcg %d newton %d stag %d err %.2e  <s11> %.4f MPa" % (
+            prec, k, d["cg_iters"], d["pcg_iters"], d["newton_iters"], d["stagger_iters"],
+            d["err"], d["sigma_mean"][0]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # after the timed region: one more increment with per-kernel event timers,
+    # then back-to-back launches of each kernel class for its duration
+    s.profile(True)
+    k = warmup + steps
+    d = s.staggered_step(ph, ws["table"], J, state, load[k], sig, **TOLS)
+    prof = s.profile(False)
+    b2b = {}
+    for nm in KERNEL_CLASSES:
+        b2b[nm] = s.time_kernel(nm, reps=30)
+    s.close()
+    return dict(seconds=t1 - t0, tot=tot, homog=np.array(homog), prof=prof, b2b=b2b)
+
+
+def cpu_baseline(ws, iters):
+    """The oracle, as it stands, on a bounded sample of the same workload: the
+    first Newton system at E11 = 0.01 from a uniform strain guess, `iters`
+    Galerkin CG iterations and `iters` Helmholtz PCG iterations (field 0)."""
+    from oracle import galerkin, helmholtz, material, spectral, staggered
+    shape, J = ws["shape"], ws["nfields"]
+    N = int(np.prod(shape))
+    mask, E, S = ws["load"][9]
+    eps = np.zeros((6,) + shape)
+    eps[0] = E[0]
+    eps[1] = eps[2] = -0.5 * E[0]
+    D = np.zeros((J,) + shape)
+    st = material.constitutive(eps, np.zeros((6,) + shape), np.zeros(shape), D, ws["phase"],
+                               ws["table"], J)
+    q = spectral.projection_symbol(shape)
+    b = -galerkin.project(st["sigma"], q, mask)
+    C = st["C"]
+    t0 = time.perf_counter()
+    galerkin.cg(lambda p: galerkin.project(material.apply_tangent(C, p), q, mask), b, 1e-30, iters)
+    t_cg = time.perf_counter() - t0
+    ell2 = staggered.ell2_field(ws["phase"], ws["table"], 0)
+    t0 = time.perf_counter()
+    helmholtz.helmholtz_solve(st["alpha"][0], ell2, tol=1e-30, maxit=iters)
+    t_h = time.perf_counter() - t0
+    return dict(value=N * 2 * iters / (t_cg + t_h), unit=UNIT, cores=1, kind="oracle",
+                sample="128^3 RVE, first Newton system at E11=0.01 (uniform strain guess): "
+                       "%d Galerkin CG + %d Helmholtz PCG iterations of the numpy oracle "
+                       "(single-threaded numpy FFT); %.1f s CG + %.1f s PCG" % (
+                           iters, iters, t_cg, t_h),
+                galerkin_cg=N * iters / t_cg, helmholtz_pcg=N * iters / t_h,
+                host_threads_available=len(os.sched_getaffinity(0)))
+
+
+def stored_traffic(kernel, form):
+    """HBM bytes per launch from committed counter runs, valid only while the
+    kernel source is unchanged since they were taken."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    src = os.path.join(ROOT, "paper_2103_04770_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft_device.hpp"):
+        h.update(open(os.path.join(src, f), "rb").read())
+    k = rec.get("kernels", {}).get("%s/%s" % (form, kernel))
+    if not k or rec.get("source_sha256") != h.hexdigest():
+        return None
+    return k.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128, help="grid size (128 is the benchmark)")
+    ap.add_argument("--forms", default="fp64,fp32", help="comma list of fp64, fp32")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="also run a device copy of MB megabytes (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (the batched and multi-GPU "
+              "forms are not part of it); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2103_04770_amd import microstructure as ms, load_library
+
+    load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        nbytes = args.copy_calibration * (1 << 20)
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        bb = torch.empty_like(a)
+        for _ in range(3):
+            bb.copy_(a)
+        torch.cuda.synchronize()
+        del a, bb
+    ws = ms.workload("spheres_two_fields_%d" % args.n)
+    N = int(np.prod(ws["shape"]))
+    vf = float(ws["phase"].mean())
+    log("workload %s: N=%d, particle vf=%.3f" % (ws["name"], N, vf))
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    res = {}
+    need = args.warmup + args.steps + 1
+    while len(ws["load"]) < need:
+        ws["load"].append(ms.uniaxial_mixed(3, 1e-3 * (len(ws["load"]) + 1)))
+    for f in forms:
+        res[f] = run_form(ws, f, args.warmup, args.steps)
+    main_form = "fp64" if "fp64" in res else forms[0]
+    r = res[main_form]
+    iters = r["tot"]["cg"] + r["tot"]["pcg"]
+    value = N * iters / r["seconds"]
+    # per-kernel table: in-flow event times of one profiled increment, and the
+    # back-to-back duration of each class; roofline on the class with the
+    # largest in-flow total
+    ms_k, n_k = r["prof"]
+    names = [load_library().fftg_kernel_name(i).decode() for i in range(len(ms_k))]
+    fp32main = main_form == "fp32"
+    kernels = {}
+    for nm, t, cnt in zip(names, ms_k, n_k):
+        if cnt == 0:
+            continue
+        b = kernel_bytes(nm, args.n, 6, 3, 2, fp32main)
+        ent = dict(inflow_total_ms=round(t, 3), launches=int(cnt),
+                   inflow_avg_us=round(t / cnt * 1e3, 2))
+        if nm in r["b2b"]:
+            us = r["b2b"][nm] * 1e3
+            ent["avg_us"] = round(us, 2)
+            ent["algo_GBps"] = round(b / (us * 1e-6) / 1e9, 1)
+        kernels[nm] = ent
+    dom = max((k for k in kernels if k in r["b2b"]), key=lambda k: kernels[k]["inflow_total_ms"])
+    bpl = kernel_bytes(dom, args.n, 6, 3, 2, fp32main)
+    ach = bpl / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+    tr = stored_traffic(dom, main_form)
+    roof = dict(bound="hbm", kernel=dom, achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(ach / PEAK_HBM_GBS, 4), traffic=tr, algorithmic_bytes_per_launch=bpl,
+                avg_us=kernels[dom]["avg_us"])
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r["seconds"] / args.steps, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if main_form == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "spheres_two_fields_%d" % args.n,
+                   "grid": [args.n] * 3, "voxels": N, "particle_vf": round(vf, 4),
+                   "nfields": 2, "increments": "uniaxial mixed control, dE11 = 1e-3",
+                   "timed_increments": [args.warmup + 1, args.warmup + args.steps],
+                   "tolerances": TOLS},
+        "loops": {
+            "galerkin_cg": dict(iters=r["tot"]["cg"],
+                                voxel_iters_per_s=round(N * r["tot"]["cg"] / (r["tot"]["t_ms"][1] / 1e3), 1)),
+            "helmholtz_pcg": dict(iters=r["tot"]["pcg"],
+                                  voxel_iters_per_s=round(N * r["tot"]["pcg"] / max(r["tot"]["t_ms"][2] / 1e3, 1e-9), 1)),
+            "newton_iters": r["tot"]["newton"], "stagger_iters": r["tot"]["stag"],
+            "t_ms": [round(x, 1) for x in r["tot"]["t_ms"]]},
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if "fp32" in res and main_form != "fp32":
+        r32 = res["fp32"]
+        it32 = r32["tot"]["cg"] + r32["tot"]["pcg"]
+        ref = r["homog"]
+        err = float(np.max(np.abs(r32["homog"] - ref)) / np.max(np.abs(ref)))
+        k32 = {}
+        for nm, us in r32["b2b"].items():
+            b = kernel_bytes(nm, args.n, 6, 3, 2, True)
+            k32[nm] = dict(avg_us=round(us * 1e3, 2), algo_GBps=round(b / (us * 1e-3) / 1e9, 1))
+        out["fp32_refined"] = dict(
+            value=round(N * it32 / r32["seconds"], 1),
+            ms_per_step=round(1e3 * r32["seconds"] / args.steps, 2),
+            cg_iters=r32["tot"]["cg"], pcg_iters=r32["tot"]["pcg"],
+            newton_iters=r32["tot"]["newton"],
+            homog_stress_rel_err_vs_fp64=err, kernels=k32)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

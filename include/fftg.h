@@ -15,8 +15,8 @@
  *
  * Conventions shared by every entry point
  *   Grid       N1 x N2 x N3 voxels (N3 = 1 in 2D plane strain), voxel size h.
- *              Every N_i must be 1 or of the form 2^a 3^b with N_i <= 1024, and
- *              N1 must be even.  N = N1 N2 N3.
+ *              Every N_i must be of the form 2^a 3^b, at most 256 in 3D and 512
+ *              in 2D, and N1 must be even.  N = N1 N2 N3.
  *   Fields     FP64, contiguous, component-major [comp][z][y][x] (x fastest).
  *   Tensors    Mandel order (11, 22, 33, sqrt2*23, sqrt2*13, sqrt2*12) in 3D,
  *              (11, 22, sqrt2*12) in 2D; c = 6 (3D) or 3 (2D) components.
@@ -201,6 +201,23 @@ fftg_status fftg_apply_galerkin(fftg_handle* h, const fftg_macro* target, const 
  * operator of Algorithm 2 taken back to real space). */
 fftg_status fftg_apply_helmholtz(fftg_handle* h, const double* ell2, const double* u,
                                  double* out);
+
+/* ---- kernel timing ---- */
+
+#define FFTG_NKERNELS 16
+/* Per-kernel-class GPU time, measured with HIP events recorded on the
+ * handle's stream around every launch while profiling is on.  Returns (when
+ * non-NULL) the milliseconds and launch counts accumulated since profiling was
+ * last enabled, then: enable = 1 clears the counters and (re)starts, enable =
+ * 0 stops.  Class names: fftg_kernel_name(id), 0 <= id < FFTG_NKERNELS. */
+fftg_status fftg_profile(fftg_handle* h, int enable, double* ms, long long* launches);
+const char* fftg_kernel_name(int id);
+/* Average GPU time of one launch of kernel class `kid`, launched `reps` times
+ * back to back on the handle's stream between one pair of HIP events, on the
+ * handle's own workspace, zeroed first (the passes do the same work whatever
+ * the values).  The workspace contents, the stored tangent included, are lost:
+ * fftg_apply_galerkin needs a new fftg_constitutive afterwards. */
+fftg_status fftg_time_kernel(fftg_handle* h, int kid, int reps, double* avg_ms);
 
 #ifdef __cplusplus
 }

@@ -97,6 +97,12 @@ def load_library():
         f.restype = ct.c_int
     lib.fftg_last_error.argtypes = [P]
     lib.fftg_last_error.restype = ct.c_char_p
+    lib.fftg_profile.argtypes = [P, I, ct.POINTER(ct.c_double), ct.POINTER(ct.c_longlong)]
+    lib.fftg_profile.restype = ct.c_int
+    lib.fftg_time_kernel.argtypes = [P, I, I, ct.POINTER(ct.c_double)]
+    lib.fftg_time_kernel.restype = ct.c_int
+    lib.fftg_kernel_name.argtypes = [I]
+    lib.fftg_kernel_name.restype = ct.c_char_p
     _LIB = lib
     return lib
 
@@ -277,6 +283,25 @@ class Solver:
         d["sigma_mean"] = np.array(hom[:c])
         d["eps_mean"] = np.array(hom[6:6 + c])
         return d
+
+    def profile(self, enable):
+        """Per-kernel-class GPU time (HIP events on the handle's stream).
+        Returns (ms, launches) accumulated since profiling was last enabled."""
+        n = 16
+        ms = (ct.c_double * n)()
+        cnt = (ct.c_longlong * n)()
+        self._check(self.lib.fftg_profile(self.h, int(bool(enable)), ms, cnt))
+        return list(ms), list(cnt)
+
+    def time_kernel(self, name, reps=50):
+        """Average milliseconds of one launch of a kernel class, back to back."""
+        kid = self.kernel_names().index(name)
+        ms = ct.c_double()
+        self._check(self.lib.fftg_time_kernel(self.h, kid, int(reps), ct.byref(ms)))
+        return ms.value
+
+    def kernel_names(self):
+        return [self.lib.fftg_kernel_name(i).decode() for i in range(16)]
 
     # ---------------------------------------------------------------- helpers
     def state_layout(self, nfields):

@@ -25,6 +25,9 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Smallest relative residual asked of a Krylov solve with FP32 vectors.
+constexpr double kFp32KrylovFloor = 1e-5;
+
 // FFTG_VERBOSE=1 prints one line per Newton correction and per Krylov solve.
 bool verbose() {
   static const bool v = [] {
@@ -70,6 +73,7 @@ struct fftg_handle {
   cpx<double>* spec64 = nullptr;  // FP64 c-component spectrum (stress, residual)
   void* tan = nullptr;            // compact tangent [8][N], work precision
   bool tan_valid = false;
+  unsigned char mask_last[6] = {0, 1, 1, 1, 1, 1};
   double* partials = nullptr;
   size_t npartials = 0;
   double* dsums = nullptr;
@@ -87,6 +91,16 @@ struct fftg_handle {
          *Dj = nullptr, *alph = nullptr, *st1 = nullptr, *sig_k = nullptr;
   void* ell2j = nullptr;  // [J][N] work precision
   hipEvent_t ev[8]{};
+  // per-kernel-class timing (fftg_profile): event pairs resolved at sync points
+  bool prof = false;
+  double kt_ms[FFTG_NKERNELS]{};
+  long long kt_n[FFTG_NKERNELS]{};
+  std::vector<hipEvent_t> evpool;
+  struct Pend {
+    hipEvent_t a, b;
+    int kid;
+  };
+  std::vector<Pend> pend;
   std::string err;
 
   bool fp32() const { return prec == FFTG_FP32_REFINED; }
@@ -188,7 +202,61 @@ void dfree(void*& p) {
   p = nullptr;
 }
 
-void sync(fftg_handle* H) { HIPCHK(hipStreamSynchronize(H->st)); }
+enum Kid {
+  K_GAL_X = 0, K_GAL_YI, K_GAL_YF, K_GAL_OI, K_GAL_OF, K_GAL_RES,
+  K_HLM_X, K_HLM_YI, K_HLM_YF, K_HLM_OI, K_HLM_OF, K_HLM_RES,
+  K_CONST, K_TR_X, K_TR_YZ, K_SMALL
+};
+const char* const kKernelNames[FFTG_NKERNELS] = {
+    "galerkin_x_fused",       "galerkin_y_inv",       "galerkin_y_fwd",
+    "galerkin_outer_dir_inv", "galerkin_outer_dot_fwd", "galerkin_resid",
+    "helmholtz_x_fused",      "helmholtz_y_inv",      "helmholtz_y_fwd",
+    "helmholtz_outer_dir_inv", "helmholtz_outer_div_fwd", "helmholtz_resid",
+    "constitutive",           "transform_x",          "transform_yz",
+    "small"};
+
+void sync(fftg_handle* H) {
+  HIPCHK(hipStreamSynchronize(H->st));
+  for (auto& p : H->pend) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    H->kt_ms[p.kid] += ms;
+    H->kt_n[p.kid] += 1;
+    H->evpool.push_back(p.a);
+    H->evpool.push_back(p.b);
+  }
+  H->pend.clear();
+}
+
+// Scope timer around one kernel launch (active only while profiling).
+struct KT {
+  fftg_handle* H;
+  int kid;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t take() {
+    if (H->evpool.empty()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = H->evpool.back();
+    H->evpool.pop_back();
+    return e;
+  }
+  KT(fftg_handle* h, int k) : H(h), kid(k) {
+    if (H->prof) {
+      a = take();
+      b = take();
+      HIPCHK(hipEventRecord(a, H->st));
+    }
+  }
+  ~KT() {
+    if (a) {
+      (void)hipEventRecord(b, H->st);
+      H->pend.push_back({a, b, kid});
+    }
+  }
+};
 void check_launch() { HIPCHK(hipGetLastError()); }
 
 // read back the control block
@@ -213,43 +281,57 @@ void read_sums(fftg_handle* H, int nb, int nred, double* out) {
 template <typename T>
 void fwd3(fftg_handle* H, int ncomp, const T* in, cpx<T>* out, const KrylovCtl* ctl = nullptr) {
   const Geo& g = H->g;
-  fftg::launch_x_r2c<T>(H->plan[0], TW<T>(H, 0), in, out, (long long)ncomp * g.n2 * g.n3, g.n1,
-                        g.n1h, H->st);
-  if (g.n2 > 1)
+  {
+    KT t(H, K_TR_X);
+    fftg::launch_x_r2c<T>(H->plan[0], TW<T>(H, 0), in, out, (long long)ncomp * g.n2 * g.n3, g.n1,
+                          g.n1h, H->st);
+  }
+  if (g.n2 > 1) {
+    KT t(H, K_TR_YZ);
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), out, (long long)ncomp * g.n3 * g.n1h, g.n1h,
                             (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st);
-  if (g.n3 > 1)
+  }
+  if (g.n3 > 1) {
+    KT t(H, K_TR_YZ);
     fftg::launch_strided<T>(H->plan[2], TW<T>(H, 2), out, (long long)ncomp * g.n2 * g.n1h,
                             (long long)g.n2 * g.n1h, g.Ns, (long long)g.n2 * g.n1h, true, ctl,
                             H->st);
+  }
 }
 
 // in is destroyed; out (=|+=) scale * inverse
 template <typename T, typename TO>
 void inv3(fftg_handle* H, int ncomp, cpx<T>* in, TO* out, T scale, bool acc) {
   const Geo& g = H->g;
-  if (g.n3 > 1)
+  if (g.n3 > 1) {
+    KT t(H, K_TR_YZ);
     fftg::launch_strided<T>(H->plan[2], TW<T>(H, 2), in, (long long)ncomp * g.n2 * g.n1h,
                             (long long)g.n2 * g.n1h, g.Ns, (long long)g.n2 * g.n1h, false,
                             nullptr, H->st);
-  if (g.n2 > 1)
+  }
+  if (g.n2 > 1) {
+    KT t(H, K_TR_YZ);
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), in, (long long)ncomp * g.n3 * g.n1h, g.n1h,
                             (long long)g.n2 * g.n1h, g.n1h, false, nullptr, H->st);
+  }
+  KT t(H, K_TR_X);
   fftg::launch_x_c2r<T, TO>(H->plan[0], TW<T>(H, 0), in, out, (long long)ncomp * g.n2 * g.n3,
                             g.n1, g.n1h, scale, acc, H->st);
 }
 
 // inner (non-outer) passes of an operator application on an ncomp spectrum
 template <typename T>
-void inner_inv(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl) {
+void inner_inv(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int kid) {
   const Geo& g = H->g;
+  KT t(H, kid);
   if (g.ndim == 3 && g.n2 > 1)
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), w, (long long)ncomp * g.n3 * g.n1h, g.n1h,
                             (long long)g.n2 * g.n1h, g.n1h, false, ctl, H->st);
 }
 template <typename T>
-void inner_fwd(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl) {
+void inner_fwd(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int kid) {
   const Geo& g = H->g;
+  KT t(H, kid);
   if (g.ndim == 3 && g.n2 > 1)
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), w, (long long)ncomp * g.n3 * g.n1h, g.n1h,
                             (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st);
@@ -313,6 +395,7 @@ void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double to
   k.rr = bb;
   k.bb = bb;
   k.tol2 = tol * tol * bb;
+  k.rrmin = bb;
   k.maxit = maxit;
   k.done = (bb == 0.0 || maxit <= 0) ? 1 : 0;
   write_ctl(H, k);
@@ -322,18 +405,38 @@ void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double to
   int chunk = 2;
   while (!k.done) {
     for (int it = 0; it < chunk; ++it) {
-      fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr), C<T>(H->kp),
-                                  C<T>(H->kx), C<T>(H->kw), H->ctl, H->st);
-      inner_inv<T>(H, c, C<T>(H->kw), H->ctl);
-      fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
-                                     reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st);
-      inner_fwd<T>(H, c, C<T>(H->kw), H->ctl);
-      const int nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
-                                                 C<T>(H->kw), H->partials, H->ctl, H->st);
-      fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
-      const int nr = fftg::launch_gal_resid<T>(g, c, SY<T>(H), mask, C<T>(H->kr), C<T>(H->kw),
-                                               H->partials, H->ctl, H->st);
-      fftg::launch_fin_beta(H->partials, nr, 1, H->ctl, H->st);
+      {
+        KT t(H, K_GAL_OI);
+        fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr),
+                                    C<T>(H->kp), C<T>(H->kx), C<T>(H->kw), H->ctl, H->st);
+      }
+      inner_inv<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YI);
+      {
+        KT t(H, K_GAL_X);
+        fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
+                                       reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st);
+      }
+      inner_fwd<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YF);
+      int nb;
+      {
+        KT t(H, K_GAL_OF);
+        nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
+                                         C<T>(H->kw), H->partials, H->ctl, H->st);
+      }
+      {
+        KT t(H, K_SMALL);
+        fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
+      }
+      int nr;
+      {
+        KT t(H, K_GAL_RES);
+        nr = fftg::launch_gal_resid<T>(g, c, SY<T>(H), mask, C<T>(H->kr), C<T>(H->kw),
+                                       H->partials, H->ctl, H->st);
+      }
+      {
+        KT t(H, K_SMALL);
+        fftg::launch_fin_beta(H->partials, nr, 1, H->ctl, H->st);
+      }
     }
     check_launch();
     k = read_ctl(H);
@@ -380,6 +483,7 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
     read_sums(H, fftg::launch_sum_ell2<T>(g.N, ell2, H->partials, H->st), 1, &s);
     ell2_ref = s / (double)g.N;
   }
+  if (H->fp32()) tol = std::max(tol, 0.1 * kFp32KrylovFloor);
   KrylovCtl k{};
   k.bb = bb;
   k.tol2 = tol * tol * bb;
@@ -398,10 +502,10 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
   // r = b - L x0
   fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), false, C<T>(H->hr),
                             C<T>(H->hx), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
-  inner_inv<T>(H, nd, C<T>(H->hw), nullptr);
+  inner_inv<T>(H, nd, C<T>(H->hw), nullptr, K_HLM_YI);
   fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, nullptr,
                                   H->st);
-  inner_fwd<T>(H, nd, C<T>(H->hw), nullptr);
+  inner_fwd<T>(H, nd, C<T>(H->hw), nullptr, K_HLM_YF);
   fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hx), C<T>(H->hw),
                             C<T>(H->hAp), nullptr, H->ctl, H->st);
   const int nr0 = fftg::launch_h_resid<T>(g, SY<T>(H), true, C<T>(H->hr), C<T>(H->hb),
@@ -410,25 +514,45 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
   read_sums(H, nr0, 2, s2);
   k.rz = s2[0];
   k.rr = s2[1];
+  k.rrmin = s2[1];
   k.done = (s2[1] <= k.tol2 || maxit <= 0) ? 1 : 0;
   write_ctl(H, k);
   HIPCHK(hipMemsetAsync(H->hp, 0, sizeof(cpx<T>) * g.Ns, H->st));
   int chunk = 2;
   while (!k.done) {
     for (int it = 0; it < chunk; ++it) {
-      fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true, C<T>(H->hr),
-                                C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
-      inner_inv<T>(H, nd, C<T>(H->hw), H->ctl);
-      fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, H->ctl,
-                                      H->st);
-      inner_fwd<T>(H, nd, C<T>(H->hw), H->ctl);
-      const int nb = fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H),
-                                               C<T>(H->hp), C<T>(H->hw), C<T>(H->hAp),
-                                               H->partials, H->ctl, H->st);
-      fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
-      const int nr = fftg::launch_h_resid<T>(g, SY<T>(H), false, C<T>(H->hr), C<T>(H->hb),
-                                             C<T>(H->hAp), H->partials, H->ctl, H->st);
-      fftg::launch_fin_beta(H->partials, nr, 2, H->ctl, H->st);
+      {
+        KT t(H, K_HLM_OI);
+        fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true, C<T>(H->hr),
+                                  C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
+      }
+      inner_inv<T>(H, nd, C<T>(H->hw), H->ctl, K_HLM_YI);
+      {
+        KT t(H, K_HLM_X);
+        fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl,
+                                        H->ctl, H->st);
+      }
+      inner_fwd<T>(H, nd, C<T>(H->hw), H->ctl, K_HLM_YF);
+      int nb;
+      {
+        KT t(H, K_HLM_OF);
+        nb = fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hp),
+                                       C<T>(H->hw), C<T>(H->hAp), H->partials, H->ctl, H->st);
+      }
+      {
+        KT t(H, K_SMALL);
+        fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
+      }
+      int nr;
+      {
+        KT t(H, K_HLM_RES);
+        nr = fftg::launch_h_resid<T>(g, SY<T>(H), false, C<T>(H->hr), C<T>(H->hb), C<T>(H->hAp),
+                                     H->partials, H->ctl, H->st);
+      }
+      {
+        KT t(H, K_SMALL);
+        fftg::launch_fin_beta(H->partials, nr, 2, H->ctl, H->st);
+      }
     }
     check_launch();
     k = read_ctl(H);
@@ -489,8 +613,11 @@ MechOut mechanics(fftg_handle* H, const unsigned char* phase, const MatTable& ta
   int r = 0;
   while (true) {
     auto t0 = std::chrono::steady_clock::now();
-    fftg::launch_constitutive<T>(tab, g, c, J, phase, eps, state_n, D, sigma, st_np1, alpha,
-                                 reinterpret_cast<T*>(H->tan), H->st);
+    {
+      KT t(H, K_CONST);
+      fftg::launch_constitutive<T>(tab, g, c, J, phase, eps, state_n, D, sigma, st_np1, alpha,
+                                   reinterpret_cast<T*>(H->tan), H->st);
+    }
     H->tan_valid = true;
     check_launch();
     sync(H);
@@ -515,7 +642,11 @@ MechOut mechanics(fftg_handle* H, const unsigned char* phase, const MatTable& ta
       break;
     }
     int it = 0, status = 0;
-    galerkin_cg<T>(H, tgt->mask, s2[0], cg->tol, cg->maxit, it, status);
+    // FP32 Krylov vectors cannot push the residual much below 1e-6 of |b|
+    // (rounding of b itself); the FP64 Newton residual refines the rest.
+    const double cgtol = H->fp32() ? std::max(cg->tol, kFp32KrylovFloor) : cg->tol;
+    std::memcpy(H->mask_last, tgt->mask, 6);
+    galerkin_cg<T>(H, tgt->mask, s2[0], cgtol, cg->maxit, it, status);
     if (verbose()) {
       const KrylovCtl kk = *H->hctl;
       std::fprintf(stderr, "[fftg] newton %d relres %.3e |b| %.3e cg %d status %d rr/bb %.3e\n", r,
@@ -610,6 +741,12 @@ void destroy(fftg_handle* H) {
   dfree(H->ell2j);
   for (auto& e : H->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& p : H->pend) {
+    H->evpool.push_back(p.a);
+    H->evpool.push_back(p.b);
+  }
+  for (auto e : H->evpool) (void)hipEventDestroy(e);
+  H->evpool.clear();
 }
 
 fftg_status run_guarded(fftg_handle* H, const std::function<fftg_status()>& f) {
@@ -767,6 +904,120 @@ const char* fftg_last_error(const fftg_handle* H) {
   return H ? H->err.c_str() : g_create_error.c_str();
 }
 
+fftg_status fftg_profile(fftg_handle* H, int enable, double* ms, long long* launches) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    sync(H);
+    if (ms)
+      for (int i = 0; i < FFTG_NKERNELS; ++i) ms[i] = H->kt_ms[i];
+    if (launches)
+      for (int i = 0; i < FFTG_NKERNELS; ++i) launches[i] = H->kt_n[i];
+    if (enable) {
+      for (int i = 0; i < FFTG_NKERNELS; ++i) {
+        H->kt_ms[i] = 0.0;
+        H->kt_n[i] = 0;
+      }
+    }
+    H->prof = enable != 0;
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_time_kernel(fftg_handle* H, int kid, int reps, double* avg_ms) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!avg_ms || reps < 1) throw Fail{FFTG_E_INVALID, "fftg_time_kernel: bad arguments"};
+    const Geo& g = H->g;
+    const int c = H->c;
+    const bool zo = g.ndim == 3;
+    const int oa = outer_axis(H);
+    alloc_helm(H);
+    const size_t cs = 2 * H->wsz() * (size_t)c * g.Ns;
+    for (void* p : {H->kx, H->kr, H->kp, H->kw}) HIPCHK(hipMemsetAsync(p, 0, cs, H->st));
+    const size_t ss = 2 * H->wsz() * (size_t)g.Ns;
+    for (void* p : {H->hx, H->hr, H->hp, H->hAp, H->hb}) HIPCHK(hipMemsetAsync(p, 0, ss, H->st));
+    HIPCHK(hipMemsetAsync(H->hw, 0, ss * g.ndim, H->st));
+    HIPCHK(hipMemsetAsync(H->ell2w, 0, H->wsz() * (size_t)g.N, H->st));
+    HIPCHK(hipMemsetAsync(H->tan, 0, H->wsz() * 8 * (size_t)g.N, H->st));
+    KrylovCtl k{};
+    k.maxit = 1 << 30;
+    write_ctl(H, k);
+    auto launch = [&](auto tag) {
+      using T = decltype(tag);
+      const T scl = T(1.0 / (double)g.N);
+      switch (kid) {
+        case K_GAL_X:
+          fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
+                                         reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st);
+          break;
+        case K_GAL_YI:
+          inner_inv<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YI);
+          break;
+        case K_GAL_YF:
+          inner_fwd<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YF);
+          break;
+        case K_GAL_OI:
+          fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr),
+                                      C<T>(H->kp), C<T>(H->kx), C<T>(H->kw), H->ctl, H->st);
+          break;
+        case K_GAL_OF:
+          fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
+                                      C<T>(H->kw), H->partials, H->ctl, H->st);
+          break;
+        case K_GAL_RES:
+          fftg::launch_gal_resid<T>(g, c, SY<T>(H), H->mask_last, C<T>(H->kr), C<T>(H->kw),
+                                    H->partials, H->ctl, H->st);
+          break;
+        case K_HLM_X:
+          fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw),
+                                          reinterpret_cast<const T*>(H->ell2w), scl, H->ctl,
+                                          H->st);
+          break;
+        case K_HLM_OI:
+          fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true,
+                                    C<T>(H->hr), C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl,
+                                    H->st);
+          break;
+        case K_HLM_OF:
+          fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hp),
+                                    C<T>(H->hw), C<T>(H->hAp), H->partials, H->ctl, H->st);
+          break;
+        case K_HLM_RES:
+          fftg::launch_h_resid<T>(g, SY<T>(H), false, C<T>(H->hr), C<T>(H->hb), C<T>(H->hAp),
+                                  H->partials, H->ctl, H->st);
+          break;
+        default:
+          throw Fail{FFTG_E_UNSUPPORTED, "fftg_time_kernel: kernel class not timeable"};
+      }
+    };
+    const bool was = H->prof;
+    H->prof = false;
+    auto one = [&]() {
+      if (H->fp32())
+        launch(float{});
+      else
+        launch(double{});
+    };
+    one();  // warm
+    check_launch();
+    HIPCHK(hipEventRecord(H->ev[0], H->st));
+    for (int i = 0; i < reps; ++i) one();
+    HIPCHK(hipEventRecord(H->ev[1], H->st));
+    check_launch();
+    sync(H);
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, H->ev[0], H->ev[1]));
+    *avg_ms = ms / reps;
+    H->prof = was;
+    H->tan_valid = false;  // the workspace was overwritten
+    return FFTG_OK;
+  });
+}
+
+const char* fftg_kernel_name(int id) {
+  return (id >= 0 && id < FFTG_NKERNELS) ? kKernelNames[id] : "";
+}
+
 fftg_status fftg_forward(fftg_handle* H, int ncomp, const double* in, double* out) {
   if (!H) return FFTG_E_INVALID;
   return run_guarded(H, [&]() -> fftg_status {
@@ -852,11 +1103,11 @@ fftg_status fftg_apply_galerkin(fftg_handle* H, const fftg_macro* tgt, const dou
       fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
                                    (long long)c * g.n1h, g.n1h, g.Ns, g.n1h, false, nullptr,
                                    H->st);
-    inner_inv<double>(H, c, C<double>(H->kw), nullptr);
+    inner_inv<double>(H, c, C<double>(H->kw), nullptr, K_GAL_YI);
     fftg::launch_x_fused_gal<double, double>(H->plan[0], TW<double>(H, 0), g, c, C<double>(H->kw),
                                              reinterpret_cast<const double*>(H->tan),
                                              1.0 / (double)g.N, nullptr, H->st);
-    inner_fwd<double>(H, c, C<double>(H->kw), nullptr);
+    inner_fwd<double>(H, c, C<double>(H->kw), nullptr, K_GAL_YF);
     if (g.ndim == 3)
       fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
                                    (long long)c * g.n2 * g.n1h, (long long)g.n2 * g.n1h, g.Ns,
@@ -889,10 +1140,10 @@ fftg_status fftg_apply_helmholtz(fftg_handle* H, const double* ell2, const doubl
     fftg::launch_h_dir_inv<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64, false,
                                    C<double>(H->hr), C<double>(H->hx), C<double>(H->hx),
                                    C<double>(H->hw), H->ctl, H->st);
-    inner_inv<double>(H, g.ndim, C<double>(H->hw), nullptr);
+    inner_inv<double>(H, g.ndim, C<double>(H->hw), nullptr, K_HLM_YI);
     fftg::launch_x_fused_helm<double, double>(H->plan[0], TW<double>(H, 0), g, C<double>(H->hw),
                                               ell2, 1.0 / (double)g.N, nullptr, H->st);
-    inner_fwd<double>(H, g.ndim, C<double>(H->hw), nullptr);
+    inner_fwd<double>(H, g.ndim, C<double>(H->hw), nullptr, K_HLM_YF);
     fftg::launch_h_div_fwd<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64,
                                    C<double>(H->hx), C<double>(H->hw), C<double>(H->hAp), nullptr,
                                    H->ctl, H->st);

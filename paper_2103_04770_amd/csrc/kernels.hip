@@ -713,12 +713,18 @@ FFTG_KERNEL void k_fin_beta(const double* __restrict__ partials, int nb, int nre
     ctl->beta = rz / ctl->rz;
     ctl->rz = rz;
     ctl->rr = rr;
+    if (rr < ctl->rrmin) {
+      ctl->rrmin = rr;
+      ctl->itmin = ctl->iters;
+    }
     if (!isfinite(rr) || !isfinite(rz))
       ctl->done = 4;
     else if (rr <= ctl->tol2)
       ctl->done = 1;
     else if (ctl->iters >= ctl->maxit)
       ctl->done = 2;
+    else if (ctl->iters - ctl->itmin >= STAGNATION_WINDOW)
+      ctl->done = 5;
   }
 }
 

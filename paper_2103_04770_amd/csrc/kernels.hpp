@@ -39,10 +39,14 @@ struct KrylovCtl {
   double bb;      // ||b||^2
   double tol2;    // tol^2 ||b||^2
   double ell2ref; // preconditioner length^2 (Helmholtz)
+  double rrmin;   // smallest r.r seen so far, and the iteration it was seen at
+  int itmin;
   int iters, maxit;
-  int done;       // 0 running, 1 converged, 2 max iterations, 3 breakdown, 4 non-finite
-  int pad;
+  int done;       // 0 running, 1 converged, 2 max iterations, 3 breakdown,
+                  // 4 non-finite, 5 stagnated (no new smallest residual for
+                  // STAGNATION_WINDOW iterations: rounding floor reached)
 };
+constexpr int STAGNATION_WINDOW = 100;
 
 struct Mat {
   int model;  // 0 elastic, 1 J2 damage, 2 elastic cracking

@@ -73,6 +73,29 @@ def laminate(shape, axis, fraction_b, phases=(0, 1)):
     return np.where(img, phases[1], phases[0]).astype(np.uint8)
 
 
+def _paint_sphere(img, c, r):
+    """Set to PARTICLE every voxel whose centre lies at periodic minimum-image
+    distance < r from c; returns the number of voxels newly set."""
+    shape = img.shape
+    if 2 * (r + 1.5) >= min(shape):
+        sel = (_periodic_dist2(_centres(shape), c, shape) < r * r) & (img != PARTICLE)
+        img[sel] = PARTICLE
+        return int(sel.sum())
+    idx, off = [], []
+    for ax, n in enumerate(shape):
+        lo = int(np.floor(c[ax] - r - 1.0))
+        hi = int(np.ceil(c[ax] + r + 1.0))
+        i = np.arange(lo, hi + 1)
+        idx.append(np.mod(i, n))
+        off.append(i + 0.5 - c[ax])
+    d2 = (off[0][:, None, None] ** 2 + off[1][None, :, None] ** 2 + off[2][None, None, :] ** 2)
+    sub = img[np.ix_(*idx)]
+    sel = (d2 < r * r) & (sub != PARTICLE)
+    sub[sel] = PARTICLE
+    img[np.ix_(*idx)] = sub
+    return int(sel.sum())
+
+
 def rsa_spheres(shape, seed, radius=None, radius_range=None, count=None,
                 volume_fraction=None, max_tries=1_000_000):
     """Random sequential addition of non-overlapping periodic spheres.
@@ -87,32 +110,29 @@ def rsa_spheres(shape, seed, radius=None, radius_range=None, count=None,
     shape = tuple(int(s) for s in shape)
     rng = np.random.default_rng(seed)
     L = np.asarray(shape, dtype=np.float64)
-    coords = _centres(shape)
     img = np.zeros(shape, dtype=np.uint8)
+    total = img.size
+    filled = 0
     centres, radii = [], []
     tries = 0
     while True:
         if count is not None and len(centres) >= count:
             break
-        if volume_fraction is not None and img.mean() >= volume_fraction:
+        if volume_fraction is not None and filled / total >= volume_fraction:
             break
         if tries >= max_tries:
             raise RuntimeError("rsa_spheres: packing failed after %d tries" % tries)
         tries += 1
         c = rng.uniform(0.0, 1.0, size=3) * L
         r = float(radius) if radius is not None else float(rng.uniform(*radius_range))
-        ok = True
-        for c2, r2 in zip(centres, radii):
-            d = np.abs(c - c2)
+        if centres:
+            d = np.abs(np.asarray(centres) - c)
             d = np.minimum(d, L - d)
-            if float(np.sqrt((d * d).sum())) < r + r2:
-                ok = False
-                break
-        if not ok:
-            continue
+            if np.any(np.sqrt((d * d).sum(axis=1)) < r + np.asarray(radii)):
+                continue
         centres.append(c)
         radii.append(r)
-        img[_periodic_dist2(coords, c, shape) < r * r] = PARTICLE
+        filled += _paint_sphere(img, c, r)
     return img, np.asarray(centres).reshape(-1, 3), np.asarray(radii)
 
 

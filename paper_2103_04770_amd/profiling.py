@@ -1,0 +1,139 @@
+"""Summaries of rocprofv3 output (CSV) for the kernels of this library.
+
+    python -m paper_2103_04770_amd.profiling stats <kernel_stats.csv> --cmd "..."
+    python -m paper_2103_04770_amd.profiling counters <fetch_dir> <write_dir> \
+        --copy-mib 1024 --cmd "..." [--json out.json]
+
+Counter calibration: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled
+by the ratio of the true byte count of a plain device copy of known size to
+what the same counter reports for that copy (the largest copyBuffer dispatch
+of the run).  A kernel's traffic is the mean over its full launches (counter
+>= half of its maximum; launches that returned early because the Krylov
+solve had converged are left out).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+# kernel symbol prefix -> (form, class) for the single-symbol classes
+CLASSES = {
+    "void fftg::k_x_fused_gal<double, double>": ("fp64", "galerkin_x_fused"),
+    "void fftg::k_x_fused_gal<float, float>": ("fp32", "galerkin_x_fused"),
+    "void fftg::k_gal_dir_inv<double>": ("fp64", "galerkin_outer_dir_inv"),
+    "void fftg::k_gal_dir_inv<float>": ("fp32", "galerkin_outer_dir_inv"),
+    "void fftg::k_gal_dot_fwd<double>": ("fp64", "galerkin_outer_dot_fwd"),
+    "void fftg::k_gal_dot_fwd<float>": ("fp32", "galerkin_outer_dot_fwd"),
+    "void fftg::k_gal_resid<double, 6>": ("fp64", "galerkin_resid"),
+    "void fftg::k_gal_resid<float, 6>": ("fp32", "galerkin_resid"),
+    "void fftg::k_x_fused_helm<double, double>": ("fp64", "helmholtz_x_fused"),
+    "void fftg::k_x_fused_helm<float, float>": ("fp32", "helmholtz_x_fused"),
+    "void fftg::k_h_dir_inv<double>": ("fp64", "helmholtz_outer_dir_inv"),
+    "void fftg::k_h_dir_inv<float>": ("fp32", "helmholtz_outer_dir_inv"),
+    "void fftg::k_h_div_fwd<double>": ("fp64", "helmholtz_outer_div_fwd"),
+    "void fftg::k_h_div_fwd<float>": ("fp32", "helmholtz_outer_div_fwd"),
+    "void fftg::k_h_resid<double>": ("fp64", "helmholtz_resid"),
+    "void fftg::k_h_resid<float>": ("fp32", "helmholtz_resid"),
+}
+
+
+def source_sha256():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft_device.hpp"):
+        h.update(open(os.path.join(PKG, "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def short(name):
+    return name.split("(")[0]
+
+
+def stats_text(path, cmd, top=20):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["rocprofv3 --kernel-trace --stats summary", "command: " + cmd, "",
+           "%-52s %7s %12s %10s %7s" % ("kernel", "calls", "total_us", "avg_us", "pct")]
+    for r in rows[:top]:
+        out.append("%-52s %7d %12.1f %10.2f %7.2f" % (
+            short(r["Name"])[:52], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+            float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out) + "\n"
+
+
+def _counter(dirpath, name):
+    path = glob.glob(os.path.join(dirpath, "*counter_collection.csv"))[0]
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == name:
+            agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return agg
+
+
+def _full_mean(v):
+    m = max(v)
+    full = [x for x in v if x >= 0.5 * m]
+    return sum(full) / len(full), len(full)
+
+
+def counters(fetch_dir, write_dir, copy_mib, cmd):
+    F = _counter(fetch_dir, "FETCH_SIZE")
+    W = _counter(write_dir, "WRITE_SIZE")
+    true_kib = copy_mib * 1024.0
+    cf = true_kib / max(F["__amd_rocclr_copyBuffer"])
+    cw = true_kib / max(W["__amd_rocclr_copyBuffer"])
+    lines = ["rocprofv3 --pmc FETCH_SIZE / --pmc WRITE_SIZE (separate runs)",
+             "command: " + cmd,
+             "calibration: %d MiB device copy reads %.0f KiB (FETCH_SIZE) and writes %.0f KiB"
+             " (WRITE_SIZE) -> scale fetch x%.3f, write x%.3f" % (
+                 copy_mib, max(F["__amd_rocclr_copyBuffer"]), max(W["__amd_rocclr_copyBuffer"]),
+                 cf, cw), "",
+             "%-46s %6s %14s %14s %12s" % ("kernel", "full", "fetch_MB", "write_MB", "total_MB")]
+    rec = {"source_sha256": source_sha256(), "fetch_scale": cf, "write_scale": cw,
+           "kernels": {}}
+    for k in sorted(F, key=lambda k: -sum(F[k])):
+        if k.startswith("__amd") or k not in W:
+            continue
+        f, nf = _full_mean(F[k])
+        w, _ = _full_mean(W[k])
+        fb, wb = f * cf * 1024, w * cw * 1024
+        lines.append("%-46s %6d %14.1f %14.1f %12.1f" % (k[:46], nf, fb / 1e6, wb / 1e6,
+                                                          (fb + wb) / 1e6))
+        if k in CLASSES:
+            form, cls = CLASSES[k]
+            rec["kernels"]["%s/%s" % (form, cls)] = dict(bytes_per_launch=round(fb + wb),
+                                                         fetch_bytes=round(fb),
+                                                         write_bytes=round(wb))
+    return "\n".join(lines) + "\n", rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--cmd", required=True)
+    b = sub.add_parser("counters")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("--copy-mib", type=int, required=True)
+    b.add_argument("--cmd", required=True)
+    b.add_argument("--json")
+    args = ap.parse_args()
+    if args.cmd_ == "stats":
+        print(stats_text(args.csv, args.cmd), end="")
+    else:
+        text, rec = counters(args.fetch_dir, args.write_dir, args.copy_mib, args.cmd)
+        print(text, end="")
+        if args.json:
+            json.dump(rec, open(args.json, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -266,3 +266,31 @@ def test_staggered_two_fields_3d():
         assert relerr(state[:c], st_o["eps"]) <= 1e-9
         assert relerr(state[c + 7 + J:], st_o["abar"]) <= 1e-8
     assert res[-1][3]["abar"][1].max() > 5e-4  # the cracking field is active
+
+
+def test_fp32_refined_staggered_matches_oracle_to_1e6():
+    """FP32 Krylov vectors and transforms with FP64 reductions, FP64 Newton
+    residuals and FP64 constitutive update: homogenised stress within 1e-6 of
+    the FP64 oracle."""
+    from paper_2103_04770_amd import FP32_REFINED
+    w = ms.workload("spheres_two_fields_16")
+    w["table"][0]["dC"], w["table"][0]["dR"] = 0.0005, 0.02
+    say("fp32-refined staggered spheres_two_fields_16")
+    shape, J = w["shape"], w["nfields"]
+    tols = dict(cg_tol=1e-10, pcg_tol=1e-10, newton_tol=1e-10, stagger_tol=1e-8)
+    s = solver(shape, prec=FP32_REFINED)
+    st_o = staggered.initial_state(shape, 3, J)
+    state = dev(np.zeros((6 + 7 + 2 * J,) + shape))
+    sig = torch.empty((6,) + shape, dtype=torch.float64, device="cuda")
+    ph = dev(w["phase"], torch.uint8)
+    for e11 in (3e-3, 6e-3):
+        tgt = ms.uniaxial_mixed(3, e11)
+        st_o, sig_o, hom_o, stats_o = staggered.staggered_step(w["phase"], w["table"], J, st_o, tgt,
+                                                               max_stagger=30, **tols)
+        d = s.staggered_step(ph, w["table"], J, state, tgt, sig, max_stagger=30, **tols)
+        say("  fp32", {k: d[k] for k in ("newton_iters", "cg_iters", "pcg_iters", "stagger_iters")},
+            "oracle", stats_o)
+        err = np.abs(d["sigma_mean"] - hom_o["sigma"]).max() / abs(hom_o["sigma"][0])
+        say("  homog err %.2e" % err)
+        assert err <= 1e-6
+        assert d["cg_iters"] < 20 * stats_o["cg_iters"]
