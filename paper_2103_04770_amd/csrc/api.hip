@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <cstdint>
 #include <functional>
 #include <string>
 #include <vector>
@@ -101,6 +102,15 @@ struct fftg_handle {
     int kid;
   };
   std::vector<Pend> pend;
+  // captured Krylov iteration chunks (one graph launch = kGraphIters iterations)
+  hipStream_t cap = nullptr;
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    unsigned long long key = 0;
+  };
+  GraphSlot ggal;
+  GraphSlot ghelm[4];
+  int ghelm_next = 0;
   std::string err;
 
   bool fp32() const { return prec == FFTG_FP32_REFINED; }
@@ -381,6 +391,93 @@ void validate_macro(const fftg_macro* t, int c) {
     if (t->mask[k] > 1) throw Fail{FFTG_E_INVALID, "macro mask entries must be 0 or 1"};
 }
 
+// One Galerkin CG iteration: 6 passes + 2 scalar kernels, all on H->st.
+template <typename T>
+void gal_iteration(fftg_handle* H, const unsigned char* mask) {
+  const Geo& g = H->g;
+  const int c = H->c;
+  const bool zo = g.ndim == 3;
+  const int oa = outer_axis(H);
+  const T scl = T(1.0 / (double)g.N);
+  {
+    KT t(H, K_GAL_OI);
+    fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr), C<T>(H->kp),
+                                C<T>(H->kx), C<T>(H->kw), H->ctl, H->st);
+  }
+  inner_inv<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YI);
+  {
+    KT t(H, K_GAL_X);
+    fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
+                                   reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st);
+  }
+  inner_fwd<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YF);
+  int nb;
+  {
+    KT t(H, K_GAL_OF);
+    nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
+                                     C<T>(H->kw), H->partials, H->ctl, H->st);
+  }
+  {
+    KT t(H, K_SMALL);
+    fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
+  }
+  int nr;
+  {
+    KT t(H, K_GAL_RES);
+    nr = fftg::launch_gal_resid<T>(g, c, SY<T>(H), mask, C<T>(H->kr), C<T>(H->kw), H->partials,
+                                   H->ctl, H->st);
+  }
+  {
+    KT t(H, K_SMALL);
+    fftg::launch_fin_beta(H->partials, nr, 1, H->ctl, H->st);
+  }
+}
+
+// Capture `body` kGraphIters times on the private capture stream into an
+// executable graph.  Every launch inside reads the device control block, so
+// iterations past convergence return at once.
+constexpr int kGraphIters = 8;
+
+template <typename F>
+hipGraphExec_t capture(fftg_handle* H, F body) {
+  hipStream_t saved = H->st;
+  H->st = H->cap;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    try {
+      for (int i = 0; i < kGraphIters; ++i) body();
+    } catch (...) {
+      (void)hipStreamEndCapture(H->cap, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      H->st = saved;
+      throw;
+    }
+    e = hipStreamEndCapture(H->cap, &graph);
+  }
+  H->st = saved;
+  if (e != hipSuccess) throw HipError{std::string("graph capture: ") + hipGetErrorString(e)};
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) throw HipError{std::string("graph instantiate: ") + hipGetErrorString(e)};
+  return ex;
+}
+
+template <typename T>
+hipGraphExec_t gal_graph(fftg_handle* H, const unsigned char* mask) {
+  unsigned long long key = 1ull + (H->fp32() ? 2ull : 0ull);
+  for (int i = 0; i < 6; ++i) key |= (unsigned long long)(mask[i] & 1) << (8 + i);
+  if (H->ggal.exec && H->ggal.key == key) return H->ggal.exec;
+  if (H->ggal.exec) (void)hipGraphExecDestroy(H->ggal.exec);
+  H->ggal.exec = nullptr;
+  unsigned char m[6];
+  std::memcpy(m, mask, 6);
+  H->ggal.exec = capture(H, [&]() { gal_iteration<T>(H, m); });
+  H->ggal.key = key;
+  return H->ggal.exec;
+}
+
 // ------------------------------------------------------------ Galerkin CG
 // Solves G*(K : dx) = b in the half spectrum, b in H->kr, dx -> H->kx.
 template <typename T>
@@ -388,8 +485,6 @@ void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double to
                  int& iters, int& status) {
   const Geo& g = H->g;
   const int c = H->c;
-  const bool zo = g.ndim == 3;
-  const int oa = outer_axis(H);
   KrylovCtl k{};
   k.rz = bb;
   k.rr = bb;
@@ -401,51 +496,81 @@ void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double to
   write_ctl(H, k);
   HIPCHK(hipMemsetAsync(H->kx, 0, sizeof(cpx<T>) * c * g.Ns, H->st));
   HIPCHK(hipMemsetAsync(H->kp, 0, sizeof(cpx<T>) * c * g.Ns, H->st));
-  const T scl = T(1.0 / (double)g.N);
-  int chunk = 2;
-  while (!k.done) {
-    for (int it = 0; it < chunk; ++it) {
-      {
-        KT t(H, K_GAL_OI);
-        fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr),
-                                    C<T>(H->kp), C<T>(H->kx), C<T>(H->kw), H->ctl, H->st);
-      }
-      inner_inv<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YI);
-      {
-        KT t(H, K_GAL_X);
-        fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
-                                       reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st);
-      }
-      inner_fwd<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YF);
-      int nb;
-      {
-        KT t(H, K_GAL_OF);
-        nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
-                                         C<T>(H->kw), H->partials, H->ctl, H->st);
-      }
-      {
-        KT t(H, K_SMALL);
-        fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
-      }
-      int nr;
-      {
-        KT t(H, K_GAL_RES);
-        nr = fftg::launch_gal_resid<T>(g, c, SY<T>(H), mask, C<T>(H->kr), C<T>(H->kw),
-                                       H->partials, H->ctl, H->st);
-      }
-      {
-        KT t(H, K_SMALL);
-        fftg::launch_fin_beta(H->partials, nr, 1, H->ctl, H->st);
-      }
+  if (!H->prof) {
+    hipGraphExec_t ex = gal_graph<T>(H, mask);
+    while (!k.done) {
+      HIPCHK(hipGraphLaunch(ex, H->st));
+      k = read_ctl(H);
     }
-    check_launch();
-    k = read_ctl(H);
-    if (chunk < 16) chunk *= 2;
+  } else {
+    int chunk = 2;
+    while (!k.done) {
+      for (int it = 0; it < chunk; ++it) gal_iteration<T>(H, mask);
+      check_launch();
+      k = read_ctl(H);
+      if (chunk < 16) chunk *= 2;
+    }
   }
   fftg::launch_xfinal<T>(C<T>(H->kx), C<T>(H->kp), (long long)c * g.Ns, H->ctl, H->st);
   check_launch();
   iters = k.iters;
   status = k.done;
+}
+
+// One Helmholtz PCG iteration: 5 passes + 2 scalar kernels, all on H->st.
+template <typename T>
+void helm_iteration(fftg_handle* H, const T* ell2) {
+  const Geo& g = H->g;
+  const bool zo = g.ndim == 3;
+  const int oa = outer_axis(H);
+  const int nd = g.ndim;
+  const T scl = T(1.0 / (double)g.N);
+  {
+    KT t(H, K_HLM_OI);
+    fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true, C<T>(H->hr),
+                              C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
+  }
+  inner_inv<T>(H, nd, C<T>(H->hw), H->ctl, K_HLM_YI);
+  {
+    KT t(H, K_HLM_X);
+    fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl,
+                                    H->ctl, H->st);
+  }
+  inner_fwd<T>(H, nd, C<T>(H->hw), H->ctl, K_HLM_YF);
+  int nb;
+  {
+    KT t(H, K_HLM_OF);
+    nb = fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hp),
+                                   C<T>(H->hw), C<T>(H->hAp), H->partials, H->ctl, H->st);
+  }
+  {
+    KT t(H, K_SMALL);
+    fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
+  }
+  int nr;
+  {
+    KT t(H, K_HLM_RES);
+    nr = fftg::launch_h_resid<T>(g, SY<T>(H), false, C<T>(H->hr), C<T>(H->hb), C<T>(H->hAp),
+                                 H->partials, H->ctl, H->st);
+  }
+  {
+    KT t(H, K_SMALL);
+    fftg::launch_fin_beta(H->partials, nr, 2, H->ctl, H->st);
+  }
+}
+
+template <typename T>
+hipGraphExec_t helm_graph(fftg_handle* H, const T* ell2) {
+  const unsigned long long key = (unsigned long long)(uintptr_t)ell2 | (H->fp32() ? 1ull : 0ull);
+  for (auto& sl : H->ghelm)
+    if (sl.exec && sl.key == key) return sl.exec;
+  auto& sl = H->ghelm[H->ghelm_next];
+  H->ghelm_next = (H->ghelm_next + 1) % 4;
+  if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+  sl.exec = nullptr;
+  sl.exec = capture(H, [&]() { helm_iteration<T>(H, ell2); });
+  sl.key = key;
+  return sl.exec;
 }
 
 // ------------------------------------------------------------ Helmholtz PCG
@@ -518,45 +643,20 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
   k.done = (s2[1] <= k.tol2 || maxit <= 0) ? 1 : 0;
   write_ctl(H, k);
   HIPCHK(hipMemsetAsync(H->hp, 0, sizeof(cpx<T>) * g.Ns, H->st));
-  int chunk = 2;
-  while (!k.done) {
-    for (int it = 0; it < chunk; ++it) {
-      {
-        KT t(H, K_HLM_OI);
-        fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true, C<T>(H->hr),
-                                  C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
-      }
-      inner_inv<T>(H, nd, C<T>(H->hw), H->ctl, K_HLM_YI);
-      {
-        KT t(H, K_HLM_X);
-        fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl,
-                                        H->ctl, H->st);
-      }
-      inner_fwd<T>(H, nd, C<T>(H->hw), H->ctl, K_HLM_YF);
-      int nb;
-      {
-        KT t(H, K_HLM_OF);
-        nb = fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hp),
-                                       C<T>(H->hw), C<T>(H->hAp), H->partials, H->ctl, H->st);
-      }
-      {
-        KT t(H, K_SMALL);
-        fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
-      }
-      int nr;
-      {
-        KT t(H, K_HLM_RES);
-        nr = fftg::launch_h_resid<T>(g, SY<T>(H), false, C<T>(H->hr), C<T>(H->hb), C<T>(H->hAp),
-                                     H->partials, H->ctl, H->st);
-      }
-      {
-        KT t(H, K_SMALL);
-        fftg::launch_fin_beta(H->partials, nr, 2, H->ctl, H->st);
-      }
+  if (!H->prof) {
+    hipGraphExec_t ex = helm_graph<T>(H, ell2);
+    while (!k.done) {
+      HIPCHK(hipGraphLaunch(ex, H->st));
+      k = read_ctl(H);
     }
-    check_launch();
-    k = read_ctl(H);
-    if (chunk < 16) chunk *= 2;
+  } else {
+    int chunk = 2;
+    while (!k.done) {
+      for (int it = 0; it < chunk; ++it) helm_iteration<T>(H, ell2);
+      check_launch();
+      k = read_ctl(H);
+      if (chunk < 16) chunk *= 2;
+    }
   }
   fftg::launch_xfinal<T>(C<T>(H->hx), C<T>(H->hp), g.Ns, H->ctl, H->st);
   inv3<T, double>(H, 1, C<T>(H->hx), abar, scl, false);
@@ -747,6 +847,10 @@ void destroy(fftg_handle* H) {
   }
   for (auto e : H->evpool) (void)hipEventDestroy(e);
   H->evpool.clear();
+  if (H->ggal.exec) (void)hipGraphExecDestroy(H->ggal.exec);
+  for (auto& sl : H->ghelm)
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+  if (H->cap) (void)hipStreamDestroy(H->cap);
 }
 
 fftg_status run_guarded(fftg_handle* H, const std::function<fftg_status()>& f) {
@@ -880,6 +984,7 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
     HIPCHK(hipHostMalloc((void**)&H->hctl, sizeof(KrylovCtl), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * 64, hipHostMallocDefault));
     for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
     return FFTG_OK;
   });
   if (rc != FFTG_OK) {

@@ -188,6 +188,120 @@ __device__ void lds_fft(cpx<T>* buf, const Plan& plan, int nlines, int ld,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compile-time variant for fixed lengths: the radix sequence, the number of
+// lines and the LDS pitch are constants, so every index division becomes a
+// shift or a multiply and the butterfly loops unroll.  The radix rule is the
+// host's: as many 8s as possible (two 4s instead of 8 x 2), then 4 or 2, then 3s.
+constexpr int c_pow(int n, int p) {
+  int c = 0;
+  while (n % p == 0) {
+    n /= p;
+    ++c;
+  }
+  return c;
+}
+constexpr int c_n8(int n) {
+  const int a = c_pow(n, 2);
+  return (a % 3 == 1 && a / 3 >= 1) ? a / 3 - 1 : a / 3;
+}
+constexpr int c_n4(int n) {
+  const int a = c_pow(n, 2);
+  return (a % 3 == 1 && a / 3 >= 1) ? 2 : (a % 3 == 2 ? 1 : 0);
+}
+constexpr int c_n2(int n) {
+  const int a = c_pow(n, 2);
+  return (a % 3 == 1 && a / 3 == 0) ? 1 : 0;
+}
+constexpr int c_nst(int n) { return c_n8(n) + c_n4(n) + c_n2(n) + c_pow(n, 3); }
+constexpr int c_radix(int n, int s) {
+  return s < c_n8(n)                         ? 8
+         : s < c_n8(n) + c_n4(n)             ? 4
+         : s < c_n8(n) + c_n4(n) + c_n2(n)   ? 2
+                                             : 3;
+}
+
+template <typename T, int R, bool FWD, bool LINEFAST, int N, int NL, int LD, int NS>
+__device__ __forceinline__ void stage_c(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
+  constexpr int M = N / R;
+  constexpr int TOTAL = NL * M;
+  constexpr int MAXB = (TOTAL + FFT_THREADS - 1) / FFT_THREADS;
+  const int tid = threadIdx.x;
+  cpx<T> v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = tid + q * FFT_THREADS;
+    if (TOTAL % FFT_THREADS == 0 || b < TOTAL) {
+      const int line = LINEFAST ? b % NL : b / M;
+      const int j = LINEFAST ? b / NL : b % M;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[laddr<LINEFAST>(line, j + r * M, LD)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = tid + q * FFT_THREADS;
+    if (TOTAL % FFT_THREADS == 0 || b < TOTAL) {
+      const int line = LINEFAST ? b % NL : b / M;
+      const int j = LINEFAST ? b / NL : b % M;
+      const int k = j % NS;
+      if (NS > 1) {
+        constexpr int STEP = N / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[k * r * STEP];
+          if (!FWD) w.y = -w.y;
+          v[q][r] = v[q][r] * w;
+        }
+      }
+      if (R == 2) dft2<FWD>(v[q]);
+      if (R == 3) dft3<FWD>(v[q]);
+      if (R == 4) dft4<FWD>(v[q]);
+      if (R == 8) dft8<FWD>(v[q]);
+      const int o = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[laddr<LINEFAST>(line, o + r * NS, LD)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Fixed-length transform of NL lines of length N in LDS (same contract as lds_fft).
+template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int S = 0, int NS = 1>
+__device__ __forceinline__ void lds_fft_c(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
+  if constexpr (S < c_nst(N)) {
+    constexpr int R = c_radix(N, S);
+    stage_c<T, R, FWD, LINEFAST, N, NL, LD, NS>(buf, tw);
+    lds_fft_c<T, FWD, LINEFAST, N, NL, LD, S + 1, NS * R>(buf, tw);
+  }
+}
+
+// LDS budgets of the fixed-length kernels, in complex elements of type T.
+template <typename T>
+constexpr int kElems = 32768 / (int)sizeof(cpx<T>);   // 32 KB
+template <typename T>
+constexpr int kElemsWide = 49152 / (int)sizeof(cpx<T>);  // 48 KB (multi-component tiles)
+
+// Tile shapes shared by kernels and launchers (fixed-length path).
+template <typename T>
+constexpr int fx_pairs(int n) { return kElems<T> / n; }                 // x R2C / C2R
+template <typename T>
+constexpr int fx_fused_lines(int n, int c) {                            // x fused passes
+  return (2 * kElems<T> / (c * n)) - (2 * kElems<T> / (c * n)) % 2;
+}
+template <typename T>
+constexpr int fs_tile(int n) {                                          // y / z passes
+  return kElems<T> / n < FFT_THREADS ? kElems<T> / n : FFT_THREADS;
+}
+constexpr int pow2_floor(int v) {
+  int p = 1;
+  while (2 * p <= v) p *= 2;
+  return p;
+}
+template <typename T>
+constexpr int fs_tile_wide(int n, int nc) { return pow2_floor(kElemsWide<T> / (n * nc)); }
+
 // Deterministic workgroup sum (fixed tree over FFT_THREADS lanes); the result
 // is valid in thread 0.  `red` must hold FFT_THREADS doubles of LDS.
 __device__ __forceinline__ double block_sum(double v, double* red) {

@@ -110,10 +110,18 @@ __device__ __forceinline__ void unpack_forward(const cpx<T>* buf, int p, int k, 
   B = mk(T(0.5) * (Z.y + Zm.y), T(0.5) * (Zm.x - Z.x));
 }
 
-template <typename T>
+// Every transform kernel takes a compile-time length NF: NF > 0 selects the
+// fixed-length path (constant tile shapes, lds_fft_c), NF = 0 the run-time
+// path (tile shapes passed in, lds_fft).
+
+template <typename T, int NF>
 FFTG_KERNEL void k_x_r2c(Plan plan, const cpx<T>* __restrict__ tw, const T* __restrict__ in,
-                         cpx<T>* __restrict__ out, long long S, int n1, int n1h, int P) {
-  __shared__ cpx<T> buf[LDS_ELEMS];
+                         cpx<T>* __restrict__ out, long long S, int n1_rt, int n1h_rt, int P_rt) {
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  const int n1 = FIX ? NF : n1_rt;
+  const int n1h = FIX ? NF / 2 + 1 : n1h_rt;
+  const int P = FIX ? fx_pairs<T>(NF) : P_rt;
   const long long s0 = (long long)blockIdx.x * (2 * P);
   for (int e = threadIdx.x; e < P * n1; e += FFT_THREADS) {
     const int p = e / n1, x = e % n1;
@@ -123,7 +131,10 @@ FFTG_KERNEL void k_x_r2c(Plan plan, const cpx<T>* __restrict__ tw, const T* __re
     buf[p * n1 + x] = mk(a, b);
   }
   __syncthreads();
-  lds_fft<T, true, false>(buf, plan, P, n1, tw);
+  if constexpr (FIX)
+    lds_fft_c<T, true, false, NF, fx_pairs<T>(NF), NF>(buf, tw);
+  else
+    lds_fft<T, true, false>(buf, plan, P, n1, tw);
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
     const int p = e / n1h, k = e % n1h;
     const long long sa = s0 + p, sb = s0 + p + P;
@@ -134,11 +145,15 @@ FFTG_KERNEL void k_x_r2c(Plan plan, const cpx<T>* __restrict__ tw, const T* __re
   }
 }
 
-template <typename T, typename TO>
+template <typename T, typename TO, int NF>
 FFTG_KERNEL void k_x_c2r(Plan plan, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ in,
-                         TO* __restrict__ out, long long S, int n1, int n1h, int P, T scl,
+                         TO* __restrict__ out, long long S, int n1_rt, int n1h_rt, int P_rt, T scl,
                          int acc) {
-  __shared__ cpx<T> buf[LDS_ELEMS];
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  const int n1 = FIX ? NF : n1_rt;
+  const int n1h = FIX ? NF / 2 + 1 : n1h_rt;
+  const int P = FIX ? fx_pairs<T>(NF) : P_rt;
   const long long s0 = (long long)blockIdx.x * (2 * P);
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
     const int p = e / n1h, k = e % n1h;
@@ -148,7 +163,10 @@ FFTG_KERNEL void k_x_c2r(Plan plan, const cpx<T>* __restrict__ tw, const cpx<T>*
     pack_inverse(buf, p, k, n1, A, B);
   }
   __syncthreads();
-  lds_fft<T, false, false>(buf, plan, P, n1, tw);
+  if constexpr (FIX)
+    lds_fft_c<T, false, false, NF, fx_pairs<T>(NF), NF>(buf, tw);
+  else
+    lds_fft<T, false, false>(buf, plan, P, n1, tw);
   for (int e = threadIdx.x; e < P * n1; e += FFT_THREADS) {
     const int p = e / n1, x = e % n1;
     const long long sa = s0 + p, sb = s0 + p + P;
@@ -167,17 +185,20 @@ FFTG_KERNEL void k_x_c2r(Plan plan, const cpx<T>* __restrict__ tw, const cpx<T>*
 // Fused x pass of the Galerkin operator: half spectrum -> real (C2R), then
 // sigma = scale * K : eps per voxel with the compact tangent
 // K:e = a tr(e) I + b dev(e) - (m.e) m, then real -> half spectrum (R2C).
-// A workgroup owns NL whole x-lines with all c components.
-template <typename T, typename TT>
-FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int c, int NL,
+// A workgroup owns NL whole x-lines with all C components; sequence
+// s = comp * NL + line, and sequences s and s + P share one complex line.
+template <typename T, typename TT, int NF, int C>
+FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int NL_rt,
                                cpx<T>* __restrict__ w, const TT* __restrict__ tan, T scl,
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
-  __shared__ cpx<T> buf[LDS_ELEMS];
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
   const long long nlines = (long long)g.n2 * g.n3;
+  const int NL = FIX ? fx_fused_lines<T>(NF, C) : NL_rt;
   const long long line0 = (long long)blockIdx.x * NL;
-  const int n1 = g.n1, n1h = g.n1h;
-  const int R = c * NL, P = R / 2;
+  const int n1 = FIX ? NF : g.n1, n1h = FIX ? NF / 2 + 1 : g.n1h;
+  const int P = C * NL / 2;
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
@@ -187,30 +208,37 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
     pack_inverse(buf, p, k, n1, A, B);
   }
   __syncthreads();
-  lds_fft<T, false, false>(buf, plan, P, n1, tw);
+  if constexpr (FIX)
+    lds_fft_c<T, false, false, NF, C * fx_fused_lines<T>(NF, C) / 2, NF>(buf, tw);
+  else
+    lds_fft<T, false, false>(buf, plan, P, n1, tw);
   T* fb = reinterpret_cast<T*>(buf);
   for (int e = threadIdx.x; e < NL * n1; e += FFT_THREADS) {
     const int l = e / n1, x = e % n1;
     const long long line = line0 + l;
     if (line >= nlines) continue;
     const long long v = line * n1 + x;
-    int slot[6];
-    T ev[6];
-    for (int q = 0; q < c; ++q) {
+    int slot[C];
+    T ev[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
       const int s = q * NL + l;
       slot[q] = s < P ? 2 * (s * n1 + x) : 2 * ((s - P) * n1 + x) + 1;
       ev[q] = fb[slot[q]];
     }
     const T a = (T)tan[v], b = (T)tan[g.N + v];
     T m[6];
+#pragma unroll
     for (int i = 0; i < 6; ++i) m[i] = (T)tan[(2 + i) * g.N + v];
-    T out[6];
-    if (c == 6) {
+    T out[C];
+    if constexpr (C == 6) {
       const T tr = ev[0] + ev[1] + ev[2];
       const T md = m[0] * ev[0] + m[1] * ev[1] + m[2] * ev[2] + m[3] * ev[3] + m[4] * ev[4] +
                    m[5] * ev[5];
       const T dv = tr / T(3);
+#pragma unroll
       for (int i = 0; i < 3; ++i) out[i] = a * tr + b * (ev[i] - dv) - md * m[i];
+#pragma unroll
       for (int i = 3; i < 6; ++i) out[i] = b * ev[i] - md * m[i];
     } else {
       const T tr = ev[0] + ev[1];
@@ -220,10 +248,14 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
       out[1] = a * tr + b * (ev[1] - dv) - md * m[1];
       out[2] = b * ev[2] - md * m[5];
     }
-    for (int q = 0; q < c; ++q) fb[slot[q]] = out[q] * scl;
+#pragma unroll
+    for (int q = 0; q < C; ++q) fb[slot[q]] = out[q] * scl;
   }
   __syncthreads();
-  lds_fft<T, true, false>(buf, plan, P, n1, tw);
+  if constexpr (FIX)
+    lds_fft_c<T, true, false, NF, C * fx_fused_lines<T>(NF, C) / 2, NF>(buf, tw);
+  else
+    lds_fft<T, true, false>(buf, plan, P, n1, tw);
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
@@ -235,19 +267,20 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
   }
 }
 
-// Fused x pass of the Helmholtz operator: C2R of the ndim gradient
+// Fused x pass of the Helmholtz operator: C2R of the ND gradient
 // components, multiply by scale * ell^2(x), R2C.
-template <typename T, typename TL>
-FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int NL,
+template <typename T, typename TL, int NF, int ND>
+FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int NL_rt,
                                 cpx<T>* __restrict__ w, const TL* __restrict__ ell2, T scl,
                                 const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
-  __shared__ cpx<T> buf[LDS_ELEMS];
-  const int c = g.ndim;
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
   const long long nlines = (long long)g.n2 * g.n3;
+  const int NL = FIX ? fx_fused_lines<T>(NF, ND) : NL_rt;
   const long long line0 = (long long)blockIdx.x * NL;
-  const int n1 = g.n1, n1h = g.n1h;
-  const int R = c * NL, P = R / 2;
+  const int n1 = FIX ? NF : g.n1, n1h = FIX ? NF / 2 + 1 : g.n1h;
+  const int P = ND * NL / 2;
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
@@ -257,21 +290,28 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
     pack_inverse(buf, p, k, n1, A, B);
   }
   __syncthreads();
-  lds_fft<T, false, false>(buf, plan, P, n1, tw);
+  if constexpr (FIX)
+    lds_fft_c<T, false, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, NF>(buf, tw);
+  else
+    lds_fft<T, false, false>(buf, plan, P, n1, tw);
   T* fb = reinterpret_cast<T*>(buf);
   for (int e = threadIdx.x; e < NL * n1; e += FFT_THREADS) {
     const int l = e / n1, x = e % n1;
     const long long line = line0 + l;
     if (line >= nlines) continue;
     const T f = (T)ell2[line * n1 + x] * scl;
-    for (int q = 0; q < c; ++q) {
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
       const int s = q * NL + l;
       const int slot = s < P ? 2 * (s * n1 + x) : 2 * ((s - P) * n1 + x) + 1;
       fb[slot] = fb[slot] * f;
     }
   }
   __syncthreads();
-  lds_fft<T, true, false>(buf, plan, P, n1, tw);
+  if constexpr (FIX)
+    lds_fft_c<T, true, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, NF>(buf, tw);
+  else
+    lds_fft<T, true, false>(buf, plan, P, n1, tw);
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
@@ -291,47 +331,50 @@ __device__ __forceinline__ long long line_base(long long L, long long inner, lon
   return (L / inner) * ostride + (L % inner);
 }
 
-template <typename T, bool FWD>
+template <typename T, bool FWD, int NF>
 FFTG_KERNEL void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __restrict__ data,
                            long long nlines, long long inner, long long ostride, long long es,
-                           int TL, const KrylovCtl* __restrict__ ctl) {
+                           int TL_rt, const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
-  __shared__ cpx<T> buf[LDS_ELEMS];
-  const int n = plan.n;
-  const long long L0 = (long long)blockIdx.x * TL;
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
-    buf[t * TL + l] = L < nlines ? data[line_base(L, inner, ostride) + t * es] : mk(T(0), T(0));
-  }
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  const int n = FIX ? NF : plan.n;
+  const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
+  // TL divides FFT_THREADS: each thread stays on line l of the tile
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const long long L = (long long)blockIdx.x * TL + l;
+  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? data[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
-  lds_fft<T, FWD, true>(buf, plan, TL, TL, tw);
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
-    if (L < nlines) data[line_base(L, inner, ostride) + t * es] = buf[t * TL + l];
-  }
+  if constexpr (FIX)
+    lds_fft_c<T, FWD, true, NF, fs_tile<T>(NF), fs_tile<T>(NF)>(buf, tw);
+  else
+    lds_fft<T, FWD, true>(buf, plan, TL, TL, tw);
+  if (lb >= 0)
+    for (int t = t0; t < n; t += dt) data[lb + t * es] = buf[t * TL + l];
 }
 
 // Outer-axis inverse pass of the Galerkin CG (per component):
 //   p <- r + beta p ; x <- x + alpha p_old ; w <- inverse transform of p.
-template <typename T>
+template <typename T, int NF>
 FFTG_KERNEL void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
                                const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
                                cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
-                               long long inner, long long ostride, long long es, int TL,
+                               long long inner, long long ostride, long long es, int TL_rt,
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl->done) return;
+  constexpr bool FIX = NF > 0;
   const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
-  __shared__ cpx<T> buf[LDS_ELEMS];
-  const int n = plan.n;
-  const long long L0 = (long long)blockIdx.x * TL;
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
+  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  const int n = FIX ? NF : plan.n;
+  const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const long long L = (long long)blockIdx.x * TL + l;
+  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  for (int t = t0; t < n; t += dt) {
     cpx<T> pn = mk(T(0), T(0));
-    if (L < nlines) {
-      const long long gi = line_base(L, inner, ostride) + t * es;
+    if (lb >= 0) {
+      const long long gi = lb + t * es;
       const cpx<T> po = pp[gi];
       x[gi] = x[gi] + scale(po, alpha);
       pn = r[gi] + scale(po, beta);
@@ -340,45 +383,48 @@ FFTG_KERNEL void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
     buf[t * TL + l] = pn;
   }
   __syncthreads();
-  lds_fft<T, false, true>(buf, plan, TL, TL, tw);
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
-    if (L < nlines) w[line_base(L, inner, ostride) + t * es] = buf[t * TL + l];
-  }
+  if constexpr (FIX)
+    lds_fft_c<T, false, true, NF, fs_tile<T>(NF), fs_tile<T>(NF)>(buf, tw);
+  else
+    lds_fft<T, false, true>(buf, plan, TL, TL, tw);
+  if (lb >= 0)
+    for (int t = t0; t < n; t += dt) w[lb + t * es] = buf[t * TL + l];
 }
 
 // Outer-axis forward pass of the Galerkin CG: w <- forward transform of w,
 // and the partial sums of the Hermitian-weighted p.w (= p.Ap, since p lies in
 // the range of the orthogonal projector).
-template <typename T>
+template <typename T, int NF>
 FFTG_KERNEL void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
                                const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
                                long long nlines, long long inner, long long ostride,
-                               long long es, int TL, int n1h, double* __restrict__ partials,
+                               long long es, int TL_rt, int n1h, double* __restrict__ partials,
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl->done) return;
-  __shared__ cpx<T> buf[LDS_ELEMS];
-  __shared__ double red[FFT_THREADS];
-  const int n = plan.n;
-  const long long L0 = (long long)blockIdx.x * TL;
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
-    buf[t * TL + l] = L < nlines ? w[line_base(L, inner, ostride) + t * es] : mk(T(0), T(0));
-  }
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  double* red = reinterpret_cast<double*>(buf);  // reused after the transform (block_sum syncs)
+  const int n = FIX ? NF : plan.n;
+  const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const long long L = (long long)blockIdx.x * TL + l;
+  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? w[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
-  lds_fft<T, true, true>(buf, plan, TL, TL, tw);
+  if constexpr (FIX)
+    lds_fft_c<T, true, true, NF, fs_tile<T>(NF), fs_tile<T>(NF)>(buf, tw);
+  else
+    lds_fft<T, true, true>(buf, plan, TL, TL, tw);
   double acc = 0.0;
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
-    if (L < nlines) {
-      const long long gi = line_base(L, inner, ostride) + t * es;
+  if (lb >= 0) {
+    // every element of a line has the same kx (es is a multiple of n1h)
+    const double wt = hweight((int)(lb % n1h), n1h);
+    for (int t = t0; t < n; t += dt) {
+      const long long gi = lb + t * es;
       const cpx<T> v = buf[t * TL + l];
       w[gi] = v;
       const cpx<T> pv = pp[gi];
-      acc += hweight((int)(gi % n1h), n1h) * ((double)pv.x * (double)v.x + (double)pv.y * (double)v.y);
+      acc += wt * ((double)pv.x * (double)v.x + (double)pv.y * (double)v.y);
     }
   }
   const double s = block_sum(acc, red);
@@ -387,30 +433,34 @@ FFTG_KERNEL void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
 
 // Outer-axis inverse pass of the Helmholtz PCG (single scalar spectrum):
 //   update: p <- M r + beta p ; x <- x + alpha p_old
-//   w_j <- inverse transform of (i q~_j p), j < ndim.
-template <typename T>
+//   w_j <- inverse transform of (i q~_j p), j < ND.
+// The fixed-length path uses a 48 KB tile so that tile rows stay >= 128 B.
+template <typename T, int NF, int ND>
 FFTG_KERNEL void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                              int update, const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
                              cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
-                             long long inner, long long ostride, long long es, int TL,
+                             long long inner, long long ostride, long long es, int TL_rt,
                              const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
-  __shared__ cpx<T> buf[LDS_ELEMS];
-  const int n = plan.n;
-  const int c = g.ndim;
-  const int ld = c * TL;
-  const long long L0 = (long long)blockIdx.x * TL;
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? kElemsWide<T> : LDS_ELEMS];
+  const int n = FIX ? NF : plan.n;
+  const int TL = FIX ? fs_tile_wide<T>(NF, ND) : TL_rt;
+  const int ld = ND * TL;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const long long L = (long long)blockIdx.x * TL + l;
+  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  // lines are (ky, kx) in 3D (z outer) and kx in 2D (y outer)
+  const bool zouter = g.ndim == 3;
+  const int lkx = (int)((L % inner) % g.n1h), lky = (int)((L % inner) / g.n1h);
   const T alpha = ctl ? (T)ctl->alpha : T(0), beta = ctl ? (T)ctl->beta : T(0);
   const T l2 = ctl ? (T)ctl->ell2ref : T(0);
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
+  for (int t = t0; t < n; t += dt) {
     cpx<T> pn = mk(T(0), T(0));
     T q[3] = {T(0), T(0), T(0)};
-    if (L < nlines) {
-      const long long gi = line_base(L, inner, ostride) + t * es;
-      int kx, ky, kz;
-      decode(g, gi, kx, ky, kz);
+    if (lb >= 0) {
+      const long long gi = lb + t * es;
+      const int kx = lkx, ky = zouter ? lky : t, kz = zouter ? t : 0;
       qvec(sym, true, kx, ky, kz, q);
       if (update) {
         const T minv = T(1) / (T(1) + l2 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]));
@@ -423,60 +473,70 @@ FFTG_KERNEL void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
       }
     }
     const cpx<T> ip = mul_i(pn);
-    for (int j = 0; j < c; ++j) buf[t * ld + j * TL + l] = scale(ip, q[j]);
+#pragma unroll
+    for (int j = 0; j < ND; ++j) buf[t * ld + j * TL + l] = scale(ip, q[j]);
   }
   __syncthreads();
-  lds_fft<T, false, true>(buf, plan, ld, ld, tw);
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
-    if (L < nlines) {
-      const long long gi = line_base(L, inner, ostride) + t * es;
-      for (int j = 0; j < c; ++j) w[j * g.Ns + gi] = buf[t * ld + j * TL + l];
+  if constexpr (FIX)
+    lds_fft_c<T, false, true, NF, ND * fs_tile_wide<T>(NF, ND), ND * fs_tile_wide<T>(NF, ND)>(buf,
+                                                                                           tw);
+  else
+    lds_fft<T, false, true>(buf, plan, ld, ld, tw);
+  if (lb >= 0)
+    for (int t = t0; t < n; t += dt) {
+      const long long gi = lb + t * es;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) w[j * g.Ns + gi] = buf[t * ld + j * TL + l];
     }
-  }
 }
 
 // Outer-axis forward pass of the Helmholtz operator:
 //   Ap = p - i sum_j q~_j FFT(w_j) ; partial sums of weighted p.Ap.
-template <typename T>
+template <typename T, int NF, int ND>
 FFTG_KERNEL void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                              const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
                              cpx<T>* __restrict__ Ap, long long nlines, long long inner,
-                             long long ostride, long long es, int TL,
+                             long long ostride, long long es, int TL_rt,
                              double* __restrict__ partials, const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
-  __shared__ cpx<T> buf[LDS_ELEMS];
-  __shared__ double red[FFT_THREADS];
-  const int n = plan.n;
-  const int c = g.ndim;
-  const int ld = c * TL;
-  const long long L0 = (long long)blockIdx.x * TL;
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
-    if (L < nlines) {
-      const long long gi = line_base(L, inner, ostride) + t * es;
-      for (int j = 0; j < c; ++j) buf[t * ld + j * TL + l] = w[j * g.Ns + gi];
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? kElemsWide<T> : LDS_ELEMS];
+  double* red = reinterpret_cast<double*>(buf);  // reused after the transform (block_sum syncs)
+  const int n = FIX ? NF : plan.n;
+  const int TL = FIX ? fs_tile_wide<T>(NF, ND) : TL_rt;
+  const int ld = ND * TL;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const long long L = (long long)blockIdx.x * TL + l;
+  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  const bool zouter = g.ndim == 3;
+  const int lkx = (int)((L % inner) % g.n1h), lky = (int)((L % inner) / g.n1h);
+  for (int t = t0; t < n; t += dt) {
+    if (lb >= 0) {
+      const long long gi = lb + t * es;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) buf[t * ld + j * TL + l] = w[j * g.Ns + gi];
     } else {
-      for (int j = 0; j < c; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
+#pragma unroll
+      for (int j = 0; j < ND; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
     }
   }
   __syncthreads();
-  lds_fft<T, true, true>(buf, plan, ld, ld, tw);
+  if constexpr (FIX)
+    lds_fft_c<T, true, true, NF, ND * fs_tile_wide<T>(NF, ND), ND * fs_tile_wide<T>(NF, ND)>(buf,
+                                                                                          tw);
+  else
+    lds_fft<T, true, true>(buf, plan, ld, ld, tw);
   double acc = 0.0;
-  for (int e = threadIdx.x; e < TL * n; e += FFT_THREADS) {
-    const int l = e % TL, t = e / TL;
-    const long long L = L0 + l;
-    if (L < nlines) {
-      const long long gi = line_base(L, inner, ostride) + t * es;
-      int kx, ky, kz;
-      decode(g, gi, kx, ky, kz);
+  for (int t = t0; t < n; t += dt) {
+    if (lb >= 0) {
+      const long long gi = lb + t * es;
+      const int kx = lkx, ky = zouter ? lky : t, kz = zouter ? t : 0;
       T q[3];
       qvec(sym, true, kx, ky, kz, q);
       const cpx<T> pv = pp[gi];
       cpx<T> div = mk(T(0), T(0));
-      for (int j = 0; j < c; ++j) div = div + scale(buf[t * ld + j * TL + l], q[j]);
+#pragma unroll
+      for (int j = 0; j < ND; ++j) div = div + scale(buf[t * ld + j * TL + l], q[j]);
       const cpx<T> a = pv + mul_mi(div);
       Ap[gi] = a;
       acc += hweight(kx, g.n1h) * ((double)pv.x * (double)a.x + (double)pv.y * (double)a.y);
@@ -998,27 +1058,69 @@ static inline int grid_for(long long n) {
   return (int)b;
 }
 
+// Runs the statement with NF set to the compile-time length matching n
+// (0 = run-time path).
+#define FFTG_DISPATCH_N(n, ...)     \
+  switch (n) {                      \
+    case 16: {                      \
+      constexpr int NF = 16;        \
+      __VA_ARGS__;                  \
+    } break;                        \
+    case 32: {                      \
+      constexpr int NF = 32;        \
+      __VA_ARGS__;                  \
+    } break;                        \
+    case 64: {                      \
+      constexpr int NF = 64;        \
+      __VA_ARGS__;                  \
+    } break;                        \
+    case 128: {                     \
+      constexpr int NF = 128;       \
+      __VA_ARGS__;                  \
+    } break;                        \
+    case 256: {                     \
+      constexpr int NF = 256;       \
+      __VA_ARGS__;                  \
+    } break;                        \
+    default: {                      \
+      constexpr int NF = 0;         \
+      __VA_ARGS__;                  \
+    } break;                        \
+  }
+
+static inline void require(bool ok, const char* what) {
+  if (!ok) throw std::runtime_error(what);
+}
+
 template <typename T>
 void launch_x_r2c(const Plan& p, const cpx<T>* tw, const T* in, cpx<T>* out, long long S,
                   int n1, int n1h, hipStream_t st) {
-  const int P = LDS_ELEMS / n1;
-  const long long nb = (S + 2 * P - 1) / (2 * P);
-  hipLaunchKernelGGL(k_x_r2c<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, in, out,
-                     S, n1, n1h, P);
+  FFTG_DISPATCH_N(n1, {
+    const int P = NF ? fx_pairs<T>(NF) : LDS_ELEMS / n1;
+    const long long nb = (S + 2 * P - 1) / (2 * P);
+    hipLaunchKernelGGL((k_x_r2c<T, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, in,
+                       out, S, n1, n1h, P);
+  })
 }
 
 template <typename T, typename TO>
 void launch_x_c2r(const Plan& p, const cpx<T>* tw, const cpx<T>* in, TO* out, long long S,
                   int n1, int n1h, T scl, bool acc, hipStream_t st) {
-  const int P = LDS_ELEMS / n1;
-  const long long nb = (S + 2 * P - 1) / (2 * P);
-  hipLaunchKernelGGL((k_x_c2r<T, TO>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, in,
-                     out, S, n1, n1h, P, scl, acc ? 1 : 0);
+  FFTG_DISPATCH_N(n1, {
+    const int P = NF ? fx_pairs<T>(NF) : LDS_ELEMS / n1;
+    const long long nb = (S + 2 * P - 1) / (2 * P);
+    hipLaunchKernelGGL((k_x_c2r<T, TO, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
+                       in, out, S, n1, n1h, P, scl, acc ? 1 : 0);
+  })
 }
 
+// Lines per tile of the run-time path: the largest power of two that fits
+// (at most FFT_THREADS), so that it divides the block size.
 static inline int tile_lines(int n, int ncomp) {
-  const int tl = LDS_ELEMS / (n * ncomp);
-  if (tl < 1) throw std::runtime_error("strided pass: line does not fit in LDS");
+  const int cap = LDS_ELEMS / (n * ncomp);
+  if (cap < 1) throw std::runtime_error("strided pass: line does not fit in LDS");
+  int tl = 1;
+  while (2 * tl <= cap && 2 * tl <= FFT_THREADS) tl *= 2;
   return tl;
 }
 
@@ -1026,14 +1128,16 @@ template <typename T>
 void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nlines,
                     long long inner, long long ostride, long long es, bool fwd,
                     const KrylovCtl* ctl, hipStream_t st) {
-  const int TL = tile_lines(p.n, 1);
-  const long long nb = (nlines + TL - 1) / TL;
-  if (fwd)
-    hipLaunchKernelGGL((k_strided<T, true>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
-                       data, nlines, inner, ostride, es, TL, ctl);
-  else
-    hipLaunchKernelGGL((k_strided<T, false>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
-                       data, nlines, inner, ostride, es, TL, ctl);
+  FFTG_DISPATCH_N(p.n, {
+    const int TL = NF ? fs_tile<T>(NF) : tile_lines(p.n, 1);
+    const long long nb = (nlines + TL - 1) / TL;
+    if (fwd)
+      hipLaunchKernelGGL((k_strided<T, true, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+                         tw, data, nlines, inner, ostride, es, TL, ctl);
+    else
+      hipLaunchKernelGGL((k_strided<T, false, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st,
+                         p, tw, data, nlines, inner, ostride, es, TL, ctl);
+  })
 }
 
 // outer axis line geometry for a c-component spectrum
@@ -1058,10 +1162,13 @@ int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
                        hipStream_t st) {
   long long nl, inner, os, es;
   outer_lines(g, c, zouter, nl, inner, os, es);
-  const int TL = tile_lines(p.n, 1);
-  const long long nb = (nl + TL - 1) / TL;
-  hipLaunchKernelGGL(k_gal_dir_inv<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, r, pp,
-                     x, w, nl, inner, os, es, TL, ctl);
+  long long nb = 0;
+  FFTG_DISPATCH_N(p.n, {
+    const int TL = NF ? fs_tile<T>(NF) : tile_lines(p.n, 1);
+    nb = (nl + TL - 1) / TL;
+    hipLaunchKernelGGL((k_gal_dir_inv<T, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+                       tw, r, pp, x, w, nl, inner, os, es, TL, ctl);
+  })
   return (int)nb;
 }
 
@@ -1071,41 +1178,60 @@ int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
                        hipStream_t st) {
   long long nl, inner, os, es;
   outer_lines(g, c, zouter, nl, inner, os, es);
-  const int TL = tile_lines(p.n, 1);
-  const long long nb = (nl + TL - 1) / TL;
-  hipLaunchKernelGGL(k_gal_dot_fwd<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, pp, w,
-                     nl, inner, os, es, TL, g.n1h, partials, ctl);
+  long long nb = 0;
+  FFTG_DISPATCH_N(p.n, {
+    const int TL = NF ? fs_tile<T>(NF) : tile_lines(p.n, 1);
+    nb = (nl + TL - 1) / TL;
+    hipLaunchKernelGGL((k_gal_dot_fwd<T, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+                       tw, pp, w, nl, inner, os, es, TL, g.n1h, partials, ctl);
+  })
   return (int)nb;
 }
 
-static inline void require(bool ok, const char* what) {
-  if (!ok) throw std::runtime_error(what);
+static inline int fused_lines_rt(int n1, int c) {
+  int NL = (2 * LDS_ELEMS) / (c * n1);
+  NL -= NL % 2;
+  if (NL < 2) NL = 2;
+  require((c * NL / 2) * n1 <= LDS_ELEMS, "x pass: line batch does not fit in LDS");
+  return NL;
 }
 
 template <typename T, typename TT>
 void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
                         const TT* tan, T scl, const KrylovCtl* ctl, hipStream_t st) {
-  int NL = (2 * LDS_ELEMS) / (c * g.n1);
-  NL -= NL % 2;
-  if (NL < 2) NL = 2;
-  require((c * NL / 2) * g.n1 <= LDS_ELEMS, "x pass: line batch does not fit in LDS");
   const long long nlines = (long long)g.n2 * g.n3;
-  const long long nb = (nlines + NL - 1) / NL;
-  hipLaunchKernelGGL((k_x_fused_gal<T, TT>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
-                     g, c, NL, w, tan, scl, ctl);
+  FFTG_DISPATCH_N(g.n1, {
+    if (c == 6) {
+      const int NL = NF ? fx_fused_lines<T>(NF, 6) : fused_lines_rt(g.n1, 6);
+      const long long nb = (nlines + NL - 1) / NL;
+      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 6>), dim3((unsigned)nb), dim3(FFT_THREADS), 0,
+                         st, p, tw, g, NL, w, tan, scl, ctl);
+    } else {
+      const int NL = NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
+      const long long nb = (nlines + NL - 1) / NL;
+      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 3>), dim3((unsigned)nb), dim3(FFT_THREADS), 0,
+                         st, p, tw, g, NL, w, tan, scl, ctl);
+    }
+  })
 }
 
 template <typename T, typename TL>
 void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
                          const TL* ell2, T scl, const KrylovCtl* ctl, hipStream_t st) {
-  int NL = (2 * LDS_ELEMS) / (g.ndim * g.n1);
-  NL -= NL % 2;
-  if (NL < 2) NL = 2;
-  require((g.ndim * NL / 2) * g.n1 <= LDS_ELEMS, "x pass: line batch does not fit in LDS");
   const long long nlines = (long long)g.n2 * g.n3;
-  const long long nb = (nlines + NL - 1) / NL;
-  hipLaunchKernelGGL((k_x_fused_helm<T, TL>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw,
-                     g, NL, w, ell2, scl, ctl);
+  FFTG_DISPATCH_N(g.n1, {
+    if (g.ndim == 3) {
+      const int NL = NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
+      const long long nb = (nlines + NL - 1) / NL;
+      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 3>), dim3((unsigned)nb), dim3(FFT_THREADS), 0,
+                         st, p, tw, g, NL, w, ell2, scl, ctl);
+    } else {
+      const int NL = NF ? fx_fused_lines<T>(NF, 2) : fused_lines_rt(g.n1, 2);
+      const long long nb = (nlines + NL - 1) / NL;
+      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 2>), dim3((unsigned)nb), dim3(FFT_THREADS), 0,
+                         st, p, tw, g, NL, w, ell2, scl, ctl);
+    }
+  })
 }
 
 template <typename T>
@@ -1156,10 +1282,20 @@ int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      cpx<T>* w, const KrylovCtl* ctl, hipStream_t st) {
   long long nl, inner, os, es;
   outer_lines(g, 1, zouter, nl, inner, os, es);
-  const int TL = tile_lines(p.n, g.ndim);
-  const long long nb = (nl + TL - 1) / TL;
-  hipLaunchKernelGGL(k_h_dir_inv<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, g, sym,
-                     update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
+  long long nb = 0;
+  FFTG_DISPATCH_N(p.n, {
+    if (g.ndim == 3) {
+      const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
+      nb = (nl + TL - 1) / TL;
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
+    } else {
+      const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
+      nb = (nl + TL - 1) / TL;
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 2>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
+    }
+  })
   return (int)nb;
 }
 
@@ -1169,10 +1305,20 @@ int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      double* partials, const KrylovCtl* ctl, hipStream_t st) {
   long long nl, inner, os, es;
   outer_lines(g, 1, zouter, nl, inner, os, es);
-  const int TL = tile_lines(p.n, g.ndim);
-  const long long nb = (nl + TL - 1) / TL;
-  hipLaunchKernelGGL(k_h_div_fwd<T>, dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p, tw, g, sym,
-                     pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
+  long long nb = 0;
+  FFTG_DISPATCH_N(p.n, {
+    if (g.ndim == 3) {
+      const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
+      nb = (nl + TL - 1) / TL;
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+                         tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
+    } else {
+      const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
+      nb = (nl + TL - 1) / TL;
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 2>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+                         tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
+    }
+  })
   return (int)nb;
 }
 
