@@ -5,8 +5,9 @@ A step is one load increment of the iterated staggered scheme (constitutive
 update, Newton + Galerkin CG, Helmholtz PCG for every non-local field,
 staggered error) on the 128^3 RVE with 25% spheres (radii U(4, 8) voxels),
 a J2-damage matrix and cracking particles (two non-local fields), under
-uniaxial mixed control with increments of 1e-3.  Inputs live in HBM before the
-timed region starts.
+uniaxial mixed control with increments of 1e-3 (E11 = 0.001 ... 0.005, the
+path restarting from the virgin state every five steps).  Inputs live in HBM
+before the timed region starts.
 
 Prints ONE JSON line.  value = voxels x (Galerkin CG + Helmholtz PCG
 iterations) / wall time of the timed steps, for the FP64 form; the
@@ -31,6 +32,7 @@ METRIC = "voxel-Krylov-iters/s and HBM GB/s at 128^3, FP64 vs FP32-refined, at 1
 UNIT = "voxel-Krylov-iters/s"
 PEAK_HBM_GBS = 8000.0
 TOLS = dict(cg_tol=1e-8, pcg_tol=1e-8, newton_tol=1e-8, stagger_tol=1e-6, max_stagger=20)
+PATH_LEN = 5
 
 
 def log(*a):
@@ -67,7 +69,17 @@ def kernel_bytes(name, n, c, nd, J, fp32):
     return table.get(name)
 
 
-def run_form(ws, prec, warmup, steps, profile_kernel=None):
+def step_load(i):
+    """Macro target of step i (warmup steps included).  The load path is five
+    increments of dE11 = 1e-3 from the virgin state; it restarts every
+    PATH_LEN steps, since past E11 = 0.005 this RVE loses its load-carrying
+    capacity (softening and a diverging Newton iteration), where the cost of
+    an increment is no longer bounded."""
+    from paper_2103_04770_amd import microstructure as ms
+    return ms.uniaxial_mixed(3, 1e-3 * ((i % PATH_LEN) + 1))
+
+
+def run_form(ws, prec, warmup, steps):
     import torch
     from paper_2103_04770_amd import Solver, FP64, FP32_REFINED
     shape, J, c = ws["shape"], ws["nfields"], 6
@@ -75,51 +87,66 @@ def run_form(ws, prec, warmup, steps, profile_kernel=None):
     state = torch.zeros((c + 7 + 2 * J,) + shape, dtype=torch.float64, device="cuda")
     sig = torch.empty((c,) + shape, dtype=torch.float64, device="cuda")
     ph = torch.from_numpy(ws["phase"]).cuda()
-    load = ws["load"]
     homog = []
-    for k in range(warmup):
-        d = s.staggered_step(ph, ws["table"], J, state, load[k], sig, **TOLS)
+
+    def step(i):
+        if i % PATH_LEN == 0:
+            state.zero_()
+        return s.staggered_step(ph, ws["table"], J, state, step_load(i), sig, **TOLS)
+
+    for i in range(warmup):
+        d = step(i)
         homog.append(d["sigma_mean"])
-        log("[%s] warmup inc %d: cg %d pcg %d newton %d stag %d err %.2e  %.0f ms" % (
-            prec, k, d["cg_iters"], d["pcg_iters"], d["newton_iters"], d["stagger_iters"],
-            d["err"], sum(d["t_ms"])))
+        log("[%s] warmup step %d (E11 %.3f): cg %d pcg %d newton %d stag %d err %.2e  %.0f ms" % (
+            prec, i, step_load(i)[1][0], d["cg_iters"], d["pcg_iters"], d["newton_iters"],
+            d["stagger_iters"], d["err"], sum(d["t_ms"])))
+    last = warmup + steps - 1
+    saved = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tot = dict(cg=0, pcg=0, newton=0, stag=0, t_ms=np.zeros(4))
-    for k in range(warmup, warmup + steps):
-        d = s.staggered_step(ph, ws["table"], J, state, load[k], sig, **TOLS)
+    for i in range(warmup, warmup + steps):
+        if i == last:
+            # kept for the profiled re-run of this increment after the timed region
+            saved = state.clone()
+        d = step(i)
         tot["cg"] += d["cg_iters"]
         tot["pcg"] += d["pcg_iters"]
         tot["newton"] += d["newton_iters"]
         tot["stag"] += d["stagger_iters"]
         tot["t_ms"] += np.array(d["t_ms"])
         homog.append(d["sigma_mean"])
-        log("[%s] timed inc %d: cg %d pcg %d newton %d stag %d err %.2e  <s11> %.4f MPa" % (
-            prec, k, d["cg_iters"], d["pcg_iters"], d["newton_iters"], d["stagger_iters"],
-            d["err"], d["sigma_mean"][0]))
+        log("[%s] timed step %d (E11 %.3f): cg %d pcg %d newton %d stag %d err %.2e  <s11> %.4f MPa" % (
+            prec, i, step_load(i)[1][0], d["cg_iters"], d["pcg_iters"], d["newton_iters"],
+            d["stagger_iters"], d["err"], d["sigma_mean"][0]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # after the timed region: one more increment with per-kernel event timers,
-    # then back-to-back launches of each kernel class for its duration
+    # after the timed region: the last timed increment again, from the same
+    # state, with per-kernel event timers; then back-to-back launches of each
+    # kernel class
+    state.copy_(saved)
+    del saved
     s.profile(True)
-    k = warmup + steps
-    d = s.staggered_step(ph, ws["table"], J, state, load[k], sig, **TOLS)
+    d = s.staggered_step(ph, ws["table"], J, state, step_load(last), sig, **TOLS)
     prof = s.profile(False)
+    log("[%s] profiled re-run of step %d: cg %d pcg %d (per-kernel events)" % (
+        prec, last, d["cg_iters"], d["pcg_iters"]))
     b2b = {}
     for nm in KERNEL_CLASSES:
         b2b[nm] = s.time_kernel(nm, reps=30)
+    log("[%s] back-to-back kernel timings done" % prec)
     s.close()
     return dict(seconds=t1 - t0, tot=tot, homog=np.array(homog), prof=prof, b2b=b2b)
 
 
 def cpu_baseline(ws, iters):
     """The oracle, as it stands, on a bounded sample of the same workload: the
-    first Newton system at E11 = 0.01 from a uniform strain guess, `iters`
+    first Newton system at E11 = 0.005 from a uniform strain guess, `iters`
     Galerkin CG iterations and `iters` Helmholtz PCG iterations (field 0)."""
     from oracle import galerkin, helmholtz, material, spectral, staggered
     shape, J = ws["shape"], ws["nfields"]
     N = int(np.prod(shape))
-    mask, E, S = ws["load"][9]
+    mask, E, S = step_load(PATH_LEN - 1)
     eps = np.zeros((6,) + shape)
     eps[0] = E[0]
     eps[1] = eps[2] = -0.5 * E[0]
@@ -137,12 +164,32 @@ def cpu_baseline(ws, iters):
     helmholtz.helmholtz_solve(st["alpha"][0], ell2, tol=1e-30, maxit=iters)
     t_h = time.perf_counter() - t0
     return dict(value=N * 2 * iters / (t_cg + t_h), unit=UNIT, cores=1, kind="oracle",
-                sample="128^3 RVE, first Newton system at E11=0.01 (uniform strain guess): "
+                sample="128^3 RVE, first Newton system at E11=0.005 (uniform strain guess): "
                        "%d Galerkin CG + %d Helmholtz PCG iterations of the numpy oracle "
                        "(single-threaded numpy FFT); %.1f s CG + %.1f s PCG" % (
                            iters, iters, t_cg, t_h),
                 galerkin_cg=N * iters / t_cg, helmholtz_pcg=N * iters / t_h,
                 host_threads_available=len(os.sched_getaffinity(0)))
+
+
+def kernel_table(r, fp32, n):
+    from paper_2103_04770_amd import load_library
+    ms_k, n_k = r["prof"]
+    lib = load_library()
+    out = {}
+    for i, (t, cnt) in enumerate(zip(ms_k, n_k)):
+        if cnt == 0:
+            continue
+        nm = lib.fftg_kernel_name(i).decode()
+        avg = t / cnt * 1e3
+        ent = dict(inflow_total_ms=round(t, 3), launches=int(cnt), inflow_avg_us=round(avg, 2))
+        b = kernel_bytes(nm, n, 6, 3, 2, fp32)
+        if b is not None:
+            ent["algo_GBps"] = round(b / (avg * 1e-6) / 1e9, 1)
+        if nm in r["b2b"]:
+            ent["b2b_avg_us"] = round(r["b2b"][nm] * 1e3, 2)
+        out[nm] = ent
+    return out
 
 
 def stored_traffic(kernel, form):
@@ -197,40 +244,28 @@ def main():
     log("workload %s: N=%d, particle vf=%.3f" % (ws["name"], N, vf))
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     res = {}
-    need = args.warmup + args.steps + 1
-    while len(ws["load"]) < need:
-        ws["load"].append(ms.uniaxial_mixed(3, 1e-3 * (len(ws["load"]) + 1)))
+    if args.steps < 1 or args.warmup < 0:
+        sys.exit("bench.py: need --steps >= 1 and --warmup >= 0")
     for f in forms:
         res[f] = run_form(ws, f, args.warmup, args.steps)
     main_form = "fp64" if "fp64" in res else forms[0]
     r = res[main_form]
     iters = r["tot"]["cg"] + r["tot"]["pcg"]
     value = N * iters / r["seconds"]
-    # per-kernel table: in-flow event times of one profiled increment, and the
+    # per-kernel table: in-flow event times of one profiled increment run
+    # right after the timed region (every launch a full one), and the
     # back-to-back duration of each class; roofline on the class with the
-    # largest in-flow total
-    ms_k, n_k = r["prof"]
-    names = [load_library().fftg_kernel_name(i).decode() for i in range(len(ms_k))]
-    fp32main = main_form == "fp32"
-    kernels = {}
-    for nm, t, cnt in zip(names, ms_k, n_k):
-        if cnt == 0:
-            continue
-        b = kernel_bytes(nm, args.n, 6, 3, 2, fp32main)
-        ent = dict(inflow_total_ms=round(t, 3), launches=int(cnt),
-                   inflow_avg_us=round(t / cnt * 1e3, 2))
-        if nm in r["b2b"]:
-            us = r["b2b"][nm] * 1e3
-            ent["avg_us"] = round(us, 2)
-            ent["algo_GBps"] = round(b / (us * 1e-6) / 1e9, 1)
-        kernels[nm] = ent
-    dom = max((k for k in kernels if k in r["b2b"]), key=lambda k: kernels[k]["inflow_total_ms"])
-    bpl = kernel_bytes(dom, args.n, 6, 3, 2, fp32main)
-    ach = bpl / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+    # largest in-flow total, priced at its in-flow average launch duration
+    kernels = kernel_table(r, main_form == "fp32", args.n)
+    dom = max((k for k in kernels if "algo_GBps" in kernels[k]),
+              key=lambda k: kernels[k]["inflow_total_ms"])
+    bpl = kernel_bytes(dom, args.n, 6, 3, 2, main_form == "fp32")
+    avg = kernels[dom]["inflow_avg_us"]
+    ach = bpl / (avg * 1e-6) / 1e9
     tr = stored_traffic(dom, main_form)
     roof = dict(bound="hbm", kernel=dom, achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(ach / PEAK_HBM_GBS, 4), traffic=tr, algorithmic_bytes_per_launch=bpl,
-                avg_us=kernels[dom]["avg_us"])
+                avg_us=avg, launches=kernels[dom]["launches"])
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -239,8 +274,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "spheres_two_fields_%d" % args.n,
                    "grid": [args.n] * 3, "voxels": N, "particle_vf": round(vf, 4),
-                   "nfields": 2, "increments": "uniaxial mixed control, dE11 = 1e-3",
-                   "timed_increments": [args.warmup + 1, args.warmup + args.steps],
+                   "nfields": 2,
+                   "load_path": "uniaxial mixed control, dE11 = 1e-3 per step, "
+                                "restarting from the virgin state every %d steps" % PATH_LEN,
+                   "timed_steps": [args.warmup, args.warmup + args.steps - 1],
                    "tolerances": TOLS},
         "loops": {
             "galerkin_cg": dict(iters=r["tot"]["cg"],
@@ -257,10 +294,7 @@ def main():
         it32 = r32["tot"]["cg"] + r32["tot"]["pcg"]
         ref = r["homog"]
         err = float(np.max(np.abs(r32["homog"] - ref)) / np.max(np.abs(ref)))
-        k32 = {}
-        for nm, us in r32["b2b"].items():
-            b = kernel_bytes(nm, args.n, 6, 3, 2, True)
-            k32[nm] = dict(avg_us=round(us * 1e3, 2), algo_GBps=round(b / (us * 1e-3) / 1e9, 1))
+        k32 = kernel_table(r32, True, args.n)
         out["fp32_refined"] = dict(
             value=round(N * it32 / r32["seconds"], 1),
             ms_per_step=round(1e3 * r32["seconds"] / args.steps, 2),

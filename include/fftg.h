@@ -209,7 +209,9 @@ fftg_status fftg_apply_helmholtz(fftg_handle* h, const double* ell2, const doubl
  * handle's stream around every launch while profiling is on.  Returns (when
  * non-NULL) the milliseconds and launch counts accumulated since profiling was
  * last enabled, then: enable = 1 clears the counters and (re)starts, enable =
- * 0 stops.  Class names: fftg_kernel_name(id), 0 <= id < FFTG_NKERNELS. */
+ * 0 stops.  Class names: fftg_kernel_name(id), 0 <= id < FFTG_NKERNELS.
+ * While profiling, Krylov loops run without HIP graphs, and launches of
+ * iterations past convergence (which return at once) are not counted. */
 fftg_status fftg_profile(fftg_handle* h, int enable, double* ms, long long* launches);
 const char* fftg_kernel_name(int id);
 /* Average GPU time of one launch of kernel class `kid`, launched `reps` times

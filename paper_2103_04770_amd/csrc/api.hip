@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -100,7 +101,9 @@ struct fftg_handle {
   struct Pend {
     hipEvent_t a, b;
     int kid;
+    int iter;  // iteration index inside a profiled Krylov chunk, -1 outside
   };
+  int kt_iter = -1;
   std::vector<Pend> pend;
   // captured Krylov iteration chunks (one graph launch = kGraphIters iterations)
   hipStream_t cap = nullptr;
@@ -225,13 +228,18 @@ const char* const kKernelNames[FFTG_NKERNELS] = {
     "constitutive",           "transform_x",          "transform_yz",
     "small"};
 
-void sync(fftg_handle* H) {
+// Waits for the stream, then books the timed launches; launches of Krylov
+// chunk iterations at index >= keep (run past convergence, so they returned
+// at once) are not booked.
+void sync(fftg_handle* H, int keep = INT_MAX) {
   HIPCHK(hipStreamSynchronize(H->st));
   for (auto& p : H->pend) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
-    H->kt_ms[p.kid] += ms;
-    H->kt_n[p.kid] += 1;
+    if (p.iter < keep) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+      H->kt_ms[p.kid] += ms;
+      H->kt_n[p.kid] += 1;
+    }
     H->evpool.push_back(p.a);
     H->evpool.push_back(p.b);
   }
@@ -263,16 +271,19 @@ struct KT {
   ~KT() {
     if (a) {
       (void)hipEventRecord(b, H->st);
-      H->pend.push_back({a, b, kid});
+      H->pend.push_back({a, b, kid, H->kt_iter});
     }
   }
 };
 void check_launch() { HIPCHK(hipGetLastError()); }
 
 // read back the control block
-KrylovCtl read_ctl(fftg_handle* H) {
+// read back the control block; `before` = the iteration count when the
+// profiled chunk just waited for started (-1: not a profiled chunk)
+KrylovCtl read_ctl(fftg_handle* H, int before = -1) {
   HIPCHK(hipMemcpyAsync(H->hctl, H->ctl, sizeof(KrylovCtl), hipMemcpyDeviceToHost, H->st));
-  sync(H);
+  HIPCHK(hipStreamSynchronize(H->st));
+  sync(H, before >= 0 ? H->hctl->iters - before : INT_MAX);
   return *H->hctl;
 }
 void write_ctl(fftg_handle* H, const KrylovCtl& k) {
@@ -505,9 +516,14 @@ void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double to
   } else {
     int chunk = 2;
     while (!k.done) {
-      for (int it = 0; it < chunk; ++it) gal_iteration<T>(H, mask);
+      const int before = k.iters;
+      for (int it = 0; it < chunk; ++it) {
+        H->kt_iter = it;
+        gal_iteration<T>(H, mask);
+      }
+      H->kt_iter = -1;
       check_launch();
-      k = read_ctl(H);
+      k = read_ctl(H, before);
       if (chunk < 16) chunk *= 2;
     }
   }
@@ -652,9 +668,14 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
   } else {
     int chunk = 2;
     while (!k.done) {
-      for (int it = 0; it < chunk; ++it) helm_iteration<T>(H, ell2);
+      const int before = k.iters;
+      for (int it = 0; it < chunk; ++it) {
+        H->kt_iter = it;
+        helm_iteration<T>(H, ell2);
+      }
+      H->kt_iter = -1;
       check_launch();
-      k = read_ctl(H);
+      k = read_ctl(H, before);
       if (chunk < 16) chunk *= 2;
     }
   }

@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output (CSV) for the kernels of this library.
 
-    python -m paper_2103_04770_amd.profiling stats <kernel_stats.csv> --cmd "..."
+    python -m paper_2103_04770_amd.profiling stats <kernel_stats.csv> --trace <kernel_trace.csv> --cmd "..."
     python -m paper_2103_04770_amd.profiling counters <fetch_dir> <write_dir> \
         --copy-mib 1024 --cmd "..." [--json out.json]
 
@@ -23,25 +23,27 @@ import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 
-# kernel symbol prefix -> (form, class) for the single-symbol classes
+# kernel template name -> class (the y passes share k_strided with the
+# transforms and cannot be told apart by name)
 CLASSES = {
-    "void fftg::k_x_fused_gal<double, double>": ("fp64", "galerkin_x_fused"),
-    "void fftg::k_x_fused_gal<float, float>": ("fp32", "galerkin_x_fused"),
-    "void fftg::k_gal_dir_inv<double>": ("fp64", "galerkin_outer_dir_inv"),
-    "void fftg::k_gal_dir_inv<float>": ("fp32", "galerkin_outer_dir_inv"),
-    "void fftg::k_gal_dot_fwd<double>": ("fp64", "galerkin_outer_dot_fwd"),
-    "void fftg::k_gal_dot_fwd<float>": ("fp32", "galerkin_outer_dot_fwd"),
-    "void fftg::k_gal_resid<double, 6>": ("fp64", "galerkin_resid"),
-    "void fftg::k_gal_resid<float, 6>": ("fp32", "galerkin_resid"),
-    "void fftg::k_x_fused_helm<double, double>": ("fp64", "helmholtz_x_fused"),
-    "void fftg::k_x_fused_helm<float, float>": ("fp32", "helmholtz_x_fused"),
-    "void fftg::k_h_dir_inv<double>": ("fp64", "helmholtz_outer_dir_inv"),
-    "void fftg::k_h_dir_inv<float>": ("fp32", "helmholtz_outer_dir_inv"),
-    "void fftg::k_h_div_fwd<double>": ("fp64", "helmholtz_outer_div_fwd"),
-    "void fftg::k_h_div_fwd<float>": ("fp32", "helmholtz_outer_div_fwd"),
-    "void fftg::k_h_resid<double>": ("fp64", "helmholtz_resid"),
-    "void fftg::k_h_resid<float>": ("fp32", "helmholtz_resid"),
+    "k_x_fused_gal": "galerkin_x_fused",
+    "k_gal_dir_inv": "galerkin_outer_dir_inv",
+    "k_gal_dot_fwd": "galerkin_outer_dot_fwd",
+    "k_gal_resid": "galerkin_resid",
+    "k_x_fused_helm": "helmholtz_x_fused",
+    "k_h_dir_inv": "helmholtz_outer_dir_inv",
+    "k_h_div_fwd": "helmholtz_outer_div_fwd",
+    "k_h_resid": "helmholtz_resid",
 }
+
+
+def classify(name):
+    """'void fftg::k_gal_dir_inv<double, 128>' -> ('fp64', 'galerkin_outer_dir_inv')."""
+    base = name.split("<")[0].split("::")[-1]
+    if base not in CLASSES or "<" not in name:
+        return None
+    t = name.split("<", 1)[1].split(",")[0].split(">")[0].strip()
+    return ({"double": "fp64", "float": "fp32"}.get(t), CLASSES[base])
 
 
 def source_sha256():
@@ -55,15 +57,34 @@ def short(name):
     return name.split("(")[0]
 
 
-def stats_text(path, cmd, top=20):
+def _trace_durations(path):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        d[short(r["Kernel_Name"])].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return d
+
+
+def stats_text(path, cmd, trace=None, top=20):
+    """Top kernels by total time.  With the kernel trace, also the mean over
+    full launches (duration >= 20% of the kernel's longest), which leaves out
+    Krylov launches that returned at once past convergence."""
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    dur = _trace_durations(trace) if trace else {}
     out = ["rocprofv3 --kernel-trace --stats summary", "command: " + cmd, "",
-           "%-52s %7s %12s %10s %7s" % ("kernel", "calls", "total_us", "avg_us", "pct")]
+           "%-52s %7s %12s %10s %7s %7s %12s" % ("kernel", "calls", "total_us", "avg_us", "pct",
+                                                 "full", "full_avg_us")]
     for r in rows[:top]:
-        out.append("%-52s %7d %12.1f %10.2f %7.2f" % (
-            short(r["Name"])[:52], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
-            float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+        k = short(r["Name"])
+        full = ""
+        if k in dur:
+            v = dur[k]
+            f = [x for x in v if x >= 0.2 * max(v)]
+            full = "%7d %12.2f" % (len(f), sum(f) / len(f))
+        out.append("%-52s %7d %12.1f %10.2f %7.2f %s" % (
+            k[:52], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+            float(r["AverageNs"]) / 1e3, float(r["Percentage"]), full))
     return "\n".join(out) + "\n"
 
 
@@ -105,8 +126,9 @@ def counters(fetch_dir, write_dir, copy_mib, cmd):
         fb, wb = f * cf * 1024, w * cw * 1024
         lines.append("%-46s %6d %14.1f %14.1f %12.1f" % (k[:46], nf, fb / 1e6, wb / 1e6,
                                                           (fb + wb) / 1e6))
-        if k in CLASSES:
-            form, cls = CLASSES[k]
+        fc = classify(k)
+        if fc and fc[0]:
+            form, cls = fc
             rec["kernels"]["%s/%s" % (form, cls)] = dict(bytes_per_launch=round(fb + wb),
                                                          fetch_bytes=round(fb),
                                                          write_bytes=round(wb))
@@ -119,6 +141,7 @@ def main():
     a = sub.add_parser("stats")
     a.add_argument("csv")
     a.add_argument("--cmd", required=True)
+    a.add_argument("--trace", help="kernel_trace.csv of the same run")
     b = sub.add_parser("counters")
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
@@ -127,7 +150,7 @@ def main():
     b.add_argument("--json")
     args = ap.parse_args()
     if args.cmd_ == "stats":
-        print(stats_text(args.csv, args.cmd), end="")
+        print(stats_text(args.csv, args.cmd, args.trace), end="")
     else:
         text, rec = counters(args.fetch_dir, args.write_dir, args.copy_mib, args.cmd)
         print(text, end="")
