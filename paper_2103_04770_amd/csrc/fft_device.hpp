@@ -277,22 +277,44 @@ __device__ __forceinline__ void lds_fft_c(cpx<T>* buf, const cpx<T>* __restrict_
   }
 }
 
-// LDS budgets of the fixed-length kernels, in complex elements of type T.
+// LDS budgets of the fixed-length kernels (bytes).  A smaller tile leaves
+// room for more workgroups per CU, i.e. more loads in flight.
+#ifndef FFTG_TILE_BYTES
+#define FFTG_TILE_BYTES 32768   // y / z passes, one component per line
+#endif
+#ifndef FFTG_DOT_BYTES
+#define FFTG_DOT_BYTES 16384    // outer Galerkin forward pass with the p.Ap partial sums
+#endif
+#ifndef FFTG_FUSED_BYTES
+#define FFTG_FUSED_BYTES 16384  // x passes fused with the pointwise operator
+#endif
+#ifndef FFTG_WIDE_BYTES
+#define FFTG_WIDE_BYTES 49152   // outer Helmholtz passes, all gradient components
+#endif
+static_assert((FFTG_TILE_BYTES & (FFTG_TILE_BYTES - 1)) == 0 && FFTG_TILE_BYTES >= 4096 &&
+                  (FFTG_DOT_BYTES & (FFTG_DOT_BYTES - 1)) == 0 && FFTG_DOT_BYTES >= 4096,
+              "y/z tile budgets must be powers of two (tile lines must divide the workgroup)");
+static_assert(FFTG_FUSED_BYTES >= 4096 && FFTG_WIDE_BYTES >= 4096, "LDS budgets too small");
 template <typename T>
-constexpr int kElems = 32768 / (int)sizeof(cpx<T>);   // 32 KB
+constexpr int kElems = 32768 / (int)sizeof(cpx<T>);   // plain x R2C / C2R
 template <typename T>
-constexpr int kElemsWide = 49152 / (int)sizeof(cpx<T>);  // 48 KB (multi-component tiles)
+constexpr int kElemsFused = FFTG_FUSED_BYTES / (int)sizeof(cpx<T>);
+template <typename T>
+constexpr int kElemsWide = FFTG_WIDE_BYTES / (int)sizeof(cpx<T>);
 
 // Tile shapes shared by kernels and launchers (fixed-length path).
 template <typename T>
 constexpr int fx_pairs(int n) { return kElems<T> / n; }                 // x R2C / C2R
 template <typename T>
 constexpr int fx_fused_lines(int n, int c) {                            // x fused passes
-  return (2 * kElems<T> / (c * n)) - (2 * kElems<T> / (c * n)) % 2;
+  return (2 * kElemsFused<T> / (c * n)) - (2 * kElemsFused<T> / (c * n)) % 2 < 2
+             ? 2
+             : (2 * kElemsFused<T> / (c * n)) - (2 * kElemsFused<T> / (c * n)) % 2;
 }
-template <typename T>
+template <typename T, int BYTES = FFTG_TILE_BYTES>
 constexpr int fs_tile(int n) {                                          // y / z passes
-  return kElems<T> / n < FFT_THREADS ? kElems<T> / n : FFT_THREADS;
+  return BYTES / (int)sizeof(cpx<T>) / n < FFT_THREADS ? BYTES / (int)sizeof(cpx<T>) / n
+                                                       : FFT_THREADS;
 }
 constexpr int pow2_floor(int v) {
   int p = 1;

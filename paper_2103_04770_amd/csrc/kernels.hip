@@ -193,7 +193,7 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? C * fx_fused_lines<T>(NF, C) / 2 * NF : LDS_ELEMS];
   const long long nlines = (long long)g.n2 * g.n3;
   const int NL = FIX ? fx_fused_lines<T>(NF, C) : NL_rt;
   const long long line0 = (long long)blockIdx.x * NL;
@@ -275,7 +275,7 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
                                 const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? ND * fx_fused_lines<T>(NF, ND) / 2 * NF : LDS_ELEMS];
   const long long nlines = (long long)g.n2 * g.n3;
   const int NL = FIX ? fx_fused_lines<T>(NF, ND) : NL_rt;
   const long long line0 = (long long)blockIdx.x * NL;
@@ -337,7 +337,7 @@ FFTG_KERNEL void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __r
                            int TL_rt, const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? fs_tile<T>(NF) * NF : LDS_ELEMS];
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
   // TL divides FFT_THREADS: each thread stays on line l of the tile
@@ -365,7 +365,7 @@ FFTG_KERNEL void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
   if (ctl->done) return;
   constexpr bool FIX = NF > 0;
   const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
-  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? fs_tile<T>(NF) * NF : LDS_ELEMS];
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
@@ -402,17 +402,17 @@ FFTG_KERNEL void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? kElems<T> : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? fs_tile<T, FFTG_DOT_BYTES>(NF) * NF : LDS_ELEMS];
   double* red = reinterpret_cast<double*>(buf);  // reused after the transform (block_sum syncs)
   const int n = FIX ? NF : plan.n;
-  const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
+  const int TL = FIX ? fs_tile<T, FFTG_DOT_BYTES>(NF) : TL_rt;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
   for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? w[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, true, NF, fs_tile<T>(NF), fs_tile<T>(NF)>(buf, tw);
+    lds_fft_c<T, true, true, NF, fs_tile<T, FFTG_DOT_BYTES>(NF), fs_tile<T, FFTG_DOT_BYTES>(NF)>(buf, tw);
   else
     lds_fft<T, true, true>(buf, plan, TL, TL, tw);
   double acc = 0.0;
@@ -443,7 +443,7 @@ FFTG_KERNEL void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
                              const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? kElemsWide<T> : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? ND * fs_tile_wide<T>(NF, ND) * NF : LDS_ELEMS];
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile_wide<T>(NF, ND) : TL_rt;
   const int ld = ND * TL;
@@ -500,7 +500,7 @@ FFTG_KERNEL void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
                              double* __restrict__ partials, const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? kElemsWide<T> : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? ND * fs_tile_wide<T>(NF, ND) * NF : LDS_ELEMS];
   double* red = reinterpret_cast<double*>(buf);  // reused after the transform (block_sum syncs)
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile_wide<T>(NF, ND) : TL_rt;
@@ -1180,7 +1180,7 @@ int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
   outer_lines(g, c, zouter, nl, inner, os, es);
   long long nb = 0;
   FFTG_DISPATCH_N(p.n, {
-    const int TL = NF ? fs_tile<T>(NF) : tile_lines(p.n, 1);
+    const int TL = NF ? fs_tile<T, FFTG_DOT_BYTES>(NF) : tile_lines(p.n, 1);
     nb = (nl + TL - 1) / TL;
     hipLaunchKernelGGL((k_gal_dot_fwd<T, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
                        tw, pp, w, nl, inner, os, es, TL, g.n1h, partials, ctl);
