@@ -221,17 +221,17 @@ constexpr int c_radix(int n, int s) {
                                              : 3;
 }
 
-template <typename T, int R, bool FWD, bool LINEFAST, int N, int NL, int LD, int NS>
+template <typename T, int R, bool FWD, bool LINEFAST, int N, int NL, int LD, int NS, int NT>
 __device__ __forceinline__ void stage_c(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
   constexpr int M = N / R;
   constexpr int TOTAL = NL * M;
-  constexpr int MAXB = (TOTAL + FFT_THREADS - 1) / FFT_THREADS;
+  constexpr int MAXB = (TOTAL + NT - 1) / NT;
   const int tid = threadIdx.x;
   cpx<T> v[MAXB][R];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int b = tid + q * FFT_THREADS;
-    if (TOTAL % FFT_THREADS == 0 || b < TOTAL) {
+    const int b = tid + q * NT;
+    if (TOTAL % NT == 0 || b < TOTAL) {
       const int line = LINEFAST ? b % NL : b / M;
       const int j = LINEFAST ? b / NL : b % M;
 #pragma unroll
@@ -241,8 +241,8 @@ __device__ __forceinline__ void stage_c(cpx<T>* buf, const cpx<T>* __restrict__ 
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int b = tid + q * FFT_THREADS;
-    if (TOTAL % FFT_THREADS == 0 || b < TOTAL) {
+    const int b = tid + q * NT;
+    if (TOTAL % NT == 0 || b < TOTAL) {
       const int line = LINEFAST ? b % NL : b / M;
       const int j = LINEFAST ? b / NL : b % M;
       const int k = j % NS;
@@ -267,14 +267,20 @@ __device__ __forceinline__ void stage_c(cpx<T>* buf, const cpx<T>* __restrict__ 
   __syncthreads();
 }
 
-// Fixed-length transform of NL lines of length N in LDS (same contract as lds_fft).
-template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int S = 0, int NS = 1>
-__device__ __forceinline__ void lds_fft_c(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
+template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int NT, int S, int NS>
+__device__ __forceinline__ void lds_fft_stages(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
   if constexpr (S < c_nst(N)) {
     constexpr int R = c_radix(N, S);
-    stage_c<T, R, FWD, LINEFAST, N, NL, LD, NS>(buf, tw);
-    lds_fft_c<T, FWD, LINEFAST, N, NL, LD, S + 1, NS * R>(buf, tw);
+    stage_c<T, R, FWD, LINEFAST, N, NL, LD, NS, NT>(buf, tw);
+    lds_fft_stages<T, FWD, LINEFAST, N, NL, LD, NT, S + 1, NS * R>(buf, tw);
   }
+}
+
+// Fixed-length transform of NL lines of length N in LDS by a workgroup of NT
+// threads (same contract as lds_fft).
+template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int NT = FFT_THREADS>
+__device__ __forceinline__ void lds_fft_c(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
+  lds_fft_stages<T, FWD, LINEFAST, N, NL, LD, NT, 0, 1>(buf, tw);
 }
 
 // LDS budgets of the fixed-length kernels (bytes).  A smaller tile leaves
@@ -282,18 +288,14 @@ __device__ __forceinline__ void lds_fft_c(cpx<T>* buf, const cpx<T>* __restrict_
 #ifndef FFTG_TILE_BYTES
 #define FFTG_TILE_BYTES 32768   // y / z passes, one component per line
 #endif
-#ifndef FFTG_DOT_BYTES
-#define FFTG_DOT_BYTES 16384    // outer Galerkin forward pass with the p.Ap partial sums
-#endif
 #ifndef FFTG_FUSED_BYTES
 #define FFTG_FUSED_BYTES 16384  // x passes fused with the pointwise operator
 #endif
 #ifndef FFTG_WIDE_BYTES
 #define FFTG_WIDE_BYTES 49152   // outer Helmholtz passes, all gradient components
 #endif
-static_assert((FFTG_TILE_BYTES & (FFTG_TILE_BYTES - 1)) == 0 && FFTG_TILE_BYTES >= 4096 &&
-                  (FFTG_DOT_BYTES & (FFTG_DOT_BYTES - 1)) == 0 && FFTG_DOT_BYTES >= 4096,
-              "y/z tile budgets must be powers of two (tile lines must divide the workgroup)");
+static_assert((FFTG_TILE_BYTES & (FFTG_TILE_BYTES - 1)) == 0 && FFTG_TILE_BYTES >= 4096,
+              "y/z tile budget must be a power of two (tile lines must divide the workgroup)");
 static_assert(FFTG_FUSED_BYTES >= 4096 && FFTG_WIDE_BYTES >= 4096, "LDS budgets too small");
 template <typename T>
 constexpr int kElems = 32768 / (int)sizeof(cpx<T>);   // plain x R2C / C2R
@@ -311,6 +313,25 @@ constexpr int fx_fused_lines(int n, int c) {                            // x fus
              ? 2
              : (2 * kElemsFused<T> / (c * n)) - (2 * kElemsFused<T> / (c * n)) % 2;
 }
+// Workgroup size of the fixed-length y / z passes: more threads over the same
+// tile keep more loads in flight without shrinking the tile rows.
+#ifndef FFTG_STRIDED_THREADS
+#define FFTG_STRIDED_THREADS 512
+#endif
+#ifndef FFTG_WIDE_THREADS
+#define FFTG_WIDE_THREADS 512
+#endif
+constexpr int kStridedThreads = FFTG_STRIDED_THREADS;
+constexpr int kWideThreads = FFTG_WIDE_THREADS;
+static_assert((kStridedThreads == 256 || kStridedThreads == 512) &&
+                  (kWideThreads == 256 || kWideThreads == 512),
+              "outer-pass workgroup sizes");
+// Outer Galerkin forward pass with the p.Ap partial sums (measured best:
+// FP64 a 32 KB tile over 512 threads, FP32 a 16 KB tile over 256 threads).
+template <typename T>
+constexpr int kDotBytes = sizeof(T) == 8 ? 32768 : 16384;
+template <typename T>
+constexpr int kDotThreads = sizeof(T) == 8 ? 512 : 256;
 template <typename T, int BYTES = FFTG_TILE_BYTES>
 constexpr int fs_tile(int n) {                                          // y / z passes
   return BYTES / (int)sizeof(cpx<T>) / n < FFT_THREADS ? BYTES / (int)sizeof(cpx<T>) / n
@@ -324,14 +345,15 @@ constexpr int pow2_floor(int v) {
 template <typename T>
 constexpr int fs_tile_wide(int n, int nc) { return pow2_floor(kElemsWide<T> / (n * nc)); }
 
-// Deterministic workgroup sum (fixed tree over FFT_THREADS lanes); the result
-// is valid in thread 0.  `red` must hold FFT_THREADS doubles of LDS.
+// Deterministic workgroup sum (fixed tree over NT lanes); the result is valid
+// in thread 0.  `red` must hold NT doubles of LDS.
+template <int NT = FFT_THREADS>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   const int tid = threadIdx.x;
   __syncthreads();
   red[tid] = v;
   __syncthreads();
-  for (int s = FFT_THREADS / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }

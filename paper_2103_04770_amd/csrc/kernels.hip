@@ -10,6 +10,7 @@
 namespace fftg {
 
 #define FFTG_KERNEL __global__ __launch_bounds__(FFT_THREADS)
+#define FFTG_KERNEL_WIDE __global__ __launch_bounds__(512)
 
 // Hermitian weight of a half-spectrum coefficient: its mirror image is not
 // stored except on the planes kx = 0 and kx = n1/2.
@@ -332,22 +333,23 @@ __device__ __forceinline__ long long line_base(long long L, long long inner, lon
 }
 
 template <typename T, bool FWD, int NF>
-FFTG_KERNEL void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __restrict__ data,
+FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __restrict__ data,
                            long long nlines, long long inner, long long ostride, long long es,
                            int TL_rt, const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
   __shared__ cpx<T> buf[FIX ? fs_tile<T>(NF) * NF : LDS_ELEMS];
+  constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
-  // TL divides FFT_THREADS: each thread stays on line l of the tile
-  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  // TL divides NT: each thread stays on line l of the tile
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
   for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? data[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, FWD, true, NF, fs_tile<T>(NF), fs_tile<T>(NF)>(buf, tw);
+    lds_fft_c<T, FWD, true, NF, fs_tile<T>(NF), fs_tile<T>(NF), NT>(buf, tw);
   else
     lds_fft<T, FWD, true>(buf, plan, TL, TL, tw);
   if (lb >= 0)
@@ -357,7 +359,7 @@ FFTG_KERNEL void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __r
 // Outer-axis inverse pass of the Galerkin CG (per component):
 //   p <- r + beta p ; x <- x + alpha p_old ; w <- inverse transform of p.
 template <typename T, int NF>
-FFTG_KERNEL void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
+FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
                                const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
                                cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
                                long long inner, long long ostride, long long es, int TL_rt,
@@ -366,9 +368,10 @@ FFTG_KERNEL void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
   constexpr bool FIX = NF > 0;
   const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
   __shared__ cpx<T> buf[FIX ? fs_tile<T>(NF) * NF : LDS_ELEMS];
+  constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
-  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
   for (int t = t0; t < n; t += dt) {
@@ -384,7 +387,7 @@ FFTG_KERNEL void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, true, NF, fs_tile<T>(NF), fs_tile<T>(NF)>(buf, tw);
+    lds_fft_c<T, false, true, NF, fs_tile<T>(NF), fs_tile<T>(NF), NT>(buf, tw);
   else
     lds_fft<T, false, true>(buf, plan, TL, TL, tw);
   if (lb >= 0)
@@ -395,24 +398,27 @@ FFTG_KERNEL void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
 // and the partial sums of the Hermitian-weighted p.w (= p.Ap, since p lies in
 // the range of the orthogonal projector).
 template <typename T, int NF>
-FFTG_KERNEL void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
+FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
                                const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
                                long long nlines, long long inner, long long ostride,
                                long long es, int TL_rt, int n1h, double* __restrict__ partials,
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? fs_tile<T, FFTG_DOT_BYTES>(NF) * NF : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? fs_tile<T, kDotBytes<T>>(NF) * NF : LDS_ELEMS];
+  constexpr int NT = FIX ? kDotThreads<T> : FFT_THREADS;
+  static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
   double* red = reinterpret_cast<double*>(buf);  // reused after the transform (block_sum syncs)
   const int n = FIX ? NF : plan.n;
-  const int TL = FIX ? fs_tile<T, FFTG_DOT_BYTES>(NF) : TL_rt;
-  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const int TL = FIX ? fs_tile<T, kDotBytes<T>>(NF) : TL_rt;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
   for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? w[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, true, NF, fs_tile<T, FFTG_DOT_BYTES>(NF), fs_tile<T, FFTG_DOT_BYTES>(NF)>(buf, tw);
+    lds_fft_c<T, true, true, NF, fs_tile<T, kDotBytes<T>>(NF), fs_tile<T, kDotBytes<T>>(NF),
+              NT>(buf, tw);
   else
     lds_fft<T, true, true>(buf, plan, TL, TL, tw);
   double acc = 0.0;
@@ -427,7 +433,7 @@ FFTG_KERNEL void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
       acc += wt * ((double)pv.x * (double)v.x + (double)pv.y * (double)v.y);
     }
   }
-  const double s = block_sum(acc, red);
+  const double s = block_sum<NT>(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
@@ -436,7 +442,7 @@ FFTG_KERNEL void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
 //   w_j <- inverse transform of (i q~_j p), j < ND.
 // The fixed-length path uses a 48 KB tile so that tile rows stay >= 128 B.
 template <typename T, int NF, int ND>
-FFTG_KERNEL void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
+FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                              int update, const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
                              cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
                              long long inner, long long ostride, long long es, int TL_rt,
@@ -445,9 +451,10 @@ FFTG_KERNEL void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
   constexpr bool FIX = NF > 0;
   __shared__ cpx<T> buf[FIX ? ND * fs_tile_wide<T>(NF, ND) * NF : LDS_ELEMS];
   const int n = FIX ? NF : plan.n;
+  constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
   const int TL = FIX ? fs_tile_wide<T>(NF, ND) : TL_rt;
   const int ld = ND * TL;
-  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
   // lines are (ky, kx) in 3D (z outer) and kx in 2D (y outer)
@@ -478,8 +485,8 @@ FFTG_KERNEL void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, true, NF, ND * fs_tile_wide<T>(NF, ND), ND * fs_tile_wide<T>(NF, ND)>(buf,
-                                                                                           tw);
+    lds_fft_c<T, false, true, NF, ND * fs_tile_wide<T>(NF, ND), ND * fs_tile_wide<T>(NF, ND),
+              NT>(buf, tw);
   else
     lds_fft<T, false, true>(buf, plan, ld, ld, tw);
   if (lb >= 0)
@@ -493,7 +500,7 @@ FFTG_KERNEL void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
 // Outer-axis forward pass of the Helmholtz operator:
 //   Ap = p - i sum_j q~_j FFT(w_j) ; partial sums of weighted p.Ap.
 template <typename T, int NF, int ND>
-FFTG_KERNEL void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
+FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                              const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
                              cpx<T>* __restrict__ Ap, long long nlines, long long inner,
                              long long ostride, long long es, int TL_rt,
@@ -503,9 +510,11 @@ FFTG_KERNEL void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
   __shared__ cpx<T> buf[FIX ? ND * fs_tile_wide<T>(NF, ND) * NF : LDS_ELEMS];
   double* red = reinterpret_cast<double*>(buf);  // reused after the transform (block_sum syncs)
   const int n = FIX ? NF : plan.n;
+  constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
+  static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
   const int TL = FIX ? fs_tile_wide<T>(NF, ND) : TL_rt;
   const int ld = ND * TL;
-  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = FFT_THREADS / TL;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
   const bool zouter = g.ndim == 3;
@@ -522,8 +531,8 @@ FFTG_KERNEL void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, true, NF, ND * fs_tile_wide<T>(NF, ND), ND * fs_tile_wide<T>(NF, ND)>(buf,
-                                                                                          tw);
+    lds_fft_c<T, true, true, NF, ND * fs_tile_wide<T>(NF, ND), ND * fs_tile_wide<T>(NF, ND),
+              NT>(buf, tw);
   else
     lds_fft<T, true, true>(buf, plan, ld, ld, tw);
   double acc = 0.0;
@@ -542,7 +551,7 @@ FFTG_KERNEL void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sy
       acc += hweight(kx, g.n1h) * ((double)pv.x * (double)a.x + (double)pv.y * (double)a.y);
     }
   }
-  const double s = block_sum(acc, red);
+  const double s = block_sum<NT>(acc, red);
   if (partials && threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
@@ -1130,13 +1139,14 @@ void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nli
                     const KrylovCtl* ctl, hipStream_t st) {
   FFTG_DISPATCH_N(p.n, {
     const int TL = NF ? fs_tile<T>(NF) : tile_lines(p.n, 1);
+    const int NT = NF ? kStridedThreads : FFT_THREADS;
     const long long nb = (nlines + TL - 1) / TL;
     if (fwd)
-      hipLaunchKernelGGL((k_strided<T, true, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
-                         tw, data, nlines, inner, ostride, es, TL, ctl);
+      hipLaunchKernelGGL((k_strided<T, true, NF>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw,
+                         data, nlines, inner, ostride, es, TL, ctl);
     else
-      hipLaunchKernelGGL((k_strided<T, false, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st,
-                         p, tw, data, nlines, inner, ostride, es, TL, ctl);
+      hipLaunchKernelGGL((k_strided<T, false, NF>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw,
+                         data, nlines, inner, ostride, es, TL, ctl);
   })
 }
 
@@ -1165,9 +1175,10 @@ int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
   long long nb = 0;
   FFTG_DISPATCH_N(p.n, {
     const int TL = NF ? fs_tile<T>(NF) : tile_lines(p.n, 1);
+    const int NT = NF ? kStridedThreads : FFT_THREADS;
     nb = (nl + TL - 1) / TL;
-    hipLaunchKernelGGL((k_gal_dir_inv<T, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
-                       tw, r, pp, x, w, nl, inner, os, es, TL, ctl);
+    hipLaunchKernelGGL((k_gal_dir_inv<T, NF>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw, r, pp,
+                       x, w, nl, inner, os, es, TL, ctl);
   })
   return (int)nb;
 }
@@ -1180,9 +1191,9 @@ int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
   outer_lines(g, c, zouter, nl, inner, os, es);
   long long nb = 0;
   FFTG_DISPATCH_N(p.n, {
-    const int TL = NF ? fs_tile<T, FFTG_DOT_BYTES>(NF) : tile_lines(p.n, 1);
+    const int TL = NF ? fs_tile<T, kDotBytes<T>>(NF) : tile_lines(p.n, 1);
     nb = (nl + TL - 1) / TL;
-    hipLaunchKernelGGL((k_gal_dot_fwd<T, NF>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+    hipLaunchKernelGGL((k_gal_dot_fwd<T, NF>), dim3((unsigned)nb), dim3(NF ? kDotThreads<T> : FFT_THREADS), 0, st, p,
                        tw, pp, w, nl, inner, os, es, TL, g.n1h, partials, ctl);
   })
   return (int)nb;
@@ -1287,12 +1298,12 @@ int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
     if (g.ndim == 3) {
       const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
       nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
                          tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
     } else {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
       nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 2>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 2>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
                          tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
     }
   })
@@ -1310,12 +1321,12 @@ int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
     if (g.ndim == 3) {
       const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
       nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
                          tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
     } else {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
       nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 2>), dim3((unsigned)nb), dim3(FFT_THREADS), 0, st, p,
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 2>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
                          tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
     }
   })
