@@ -18,11 +18,15 @@ __device__ __forceinline__ double hweight(int kx, int n1h) {
   return (kx == 0 || kx == n1h - 1) ? 1.0 : 2.0;
 }
 
+// Frequency indices of half-spectrum coefficient gi (gi < 2^31: grids are at
+// most 256^3, so 32-bit division is exact and far cheaper than 64-bit).
 __device__ __forceinline__ void decode(const Geo& g, long long gi, int& kx, int& ky, int& kz) {
-  kx = (int)(gi % g.n1h);
-  long long r = gi / g.n1h;
-  ky = (int)(r % g.n2);
-  kz = (int)((r / g.n2) % g.n3);
+  const unsigned u = (unsigned)gi, n1h = (unsigned)g.n1h, n2 = (unsigned)g.n2;
+  const unsigned r = u / n1h;
+  kx = (int)(u - r * n1h);
+  const unsigned s = r / n2;
+  ky = (int)(r - s * n2);
+  kz = (int)(s % (unsigned)g.n3);
 }
 
 template <typename T>

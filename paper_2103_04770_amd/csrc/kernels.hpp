@@ -60,7 +60,7 @@ struct MatTable {
   Mat m[16];
 };
 
-constexpr int RED_BLOCKS = 1024;  // largest grid of the pointwise reduction kernels
+constexpr int RED_BLOCKS = 2048;  // largest grid of the pointwise kernels
 // Every reduction launcher returns its block count; the finalisers take it.
 
 // ---------------------------------------------------------------- launchers
