@@ -103,10 +103,13 @@ def set_strain_means(eps, mask, Emac):
 
 def fftg_solve(phase, table, D, epsp_n, kappa_n, target, eps0, h=1.0,
                scheme=spectral.ROTATED, cg_tol=1e-8, cg_maxit=5000,
-               newton_tol=1e-8, newton_maxit=50, nfields=None):
+               newton_tol=1e-8, newton_maxit=50, nfields=None, newton_div=0):
     """Mechanics at frozen damage (Algorithm 1, step (i)).
 
     target = (mask, E, S) Mandel; eps0 (c, *S) initial guess.
+    newton_div > 0: give up (not converged) once the Newton residual has grown
+    in newton_div consecutive corrections (used by the adaptive load driver,
+    where a diverging increment is cut back instead of iterated to the end).
     Returns dict(eps, sigma, epsp, kappa, alpha, newton_iters, cg_iters,
     relres, converged)."""
     mask, Emac, Smac = target
@@ -123,15 +126,20 @@ def fftg_solve(phase, table, D, epsp_n, kappa_n, target, eps0, h=1.0,
     cg_total = 0
     converged = False
     relres = np.inf
+    grown = 0
     r = 0
     while True:
         st = material.constitutive(eps, epsp_n, kappa_n, D, phase, table, J)
         b = -project(st["sigma"] - Sbar_f, q, mask)
         nb = np.sqrt((b * b).sum())
         ns = np.sqrt((st["sigma"] * st["sigma"]).sum())
+        prev = relres
         relres = nb / max(ns, sref * np.sqrt(N))
+        grown = grown + 1 if (r >= 1 and relres > prev) else 0
         if r >= 1 and relres <= newton_tol:
             converged = True
+            break
+        if newton_div > 0 and grown >= newton_div:
             break
         if r >= newton_maxit:
             break

@@ -35,9 +35,14 @@ def ell2_field(phase, table, j):
 def staggered_step(phase, table, nfields, state, target, h=1.0,
                    scheme=spectral.ROTATED, cg_tol=1e-8, cg_maxit=5000,
                    pcg_tol=1e-8, pcg_maxit=2000, newton_tol=1e-8,
-                   newton_maxit=50, stagger_tol=1e-6, max_stagger=20):
+                   newton_maxit=50, stagger_tol=1e-6, max_stagger=20,
+                   newton_div=0, abort_on_mech_failure=False):
     """state: dict(eps (c,*S), epsp (6,*S), kappa S, hist (J,*S), abar (J,*S)).
-    Returns (new_state, sigma, homog dict(sigma=<sigma>, eps=<eps>), stats)."""
+    newton_div: see galerkin.fftg_solve.  abort_on_mech_failure: leave the
+    loop as soon as a mechanics solve does not converge (the increment is then
+    reported as not converged; the adaptive load driver cuts it back).
+    Returns (new_state, sigma, homog dict(sigma=<sigma>, eps=<eps>), stats);
+    stats["mech_converged"] tells whether the last mechanics solve converged."""
     mask, Emac, Smac = target
     S = phase.shape
     N = int(np.prod(S))
@@ -48,16 +53,21 @@ def staggered_step(phase, table, nfields, state, target, h=1.0,
     abar_k = state["abar"].copy()
     ell2 = [ell2_field(phase, table, j) for j in range(J)]
     stats = dict(stagger_iters=0, newton_iters=0, cg_iters=0, pcg_iters=0, err=np.inf,
-                 converged=False)
+                 converged=False, mech_converged=False)
     mech = None
     for k in range(max_stagger):
         D = material.damage_from_nonlocal(phase, table, abar_k, hist_n)
         mech = galerkin.fftg_solve(phase, table, D, epsp_n, kappa_n, target, eps_k,
                                    h=h, scheme=scheme, cg_tol=cg_tol, cg_maxit=cg_maxit,
                                    newton_tol=newton_tol, newton_maxit=newton_maxit,
-                                   nfields=J)
+                                   nfields=J, newton_div=newton_div)
         stats["newton_iters"] += mech["newton_iters"]
         stats["cg_iters"] += mech["cg_iters"]
+        stats["mech_converged"] = mech["converged"]
+        if abort_on_mech_failure and not mech["converged"]:
+            stats["stagger_iters"] = k + 1
+            eps_k = mech["eps"]
+            break
         abar_new = np.empty_like(abar_k)
         for j in range(J):
             hs = helmholtz.helmholtz_solve(mech["alpha"][j], ell2[j], h=h, scheme=scheme,
