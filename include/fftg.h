@@ -12,6 +12,7 @@
  *                       eq. LhelmFourier, eq. preconditioner, Algorithm 2).
  *   - staggered_step  : one load increment of the iterated staggered scheme
  *                       (Sec. 3.2, Algorithm 1).
+ *   - fftg_drive      : variable-increment loading with cutback (Sec. 4.2).
  *
  * Conventions shared by every entry point
  *   Grid       N1 x N2 x N3 voxels (N3 = 1 in 2D plane strain), voxel size h.
@@ -172,6 +173,57 @@ fftg_status staggered_step(fftg_handle* h, const unsigned char* phase, const fft
                            double newton_tol, int newton_maxit, double stagger_tol,
                            int max_stagger_iters, double* sigma_out, double* homog_out,
                            fftg_stats* stats);
+
+/* ---- adaptive load driver ---- */
+
+/* Variable-increment loading (Sec. 4.2: the strain increment is reduced where
+ * the response softens, down to a smallest admissible increment).  The macro
+ * target is proportional to a load factor t: E(t) = t E_end on the
+ * strain-controlled components, S(t) = t S_end on the stress-controlled ones
+ * (mask of target_end).  An attempt t -> t' = min(t + dt, t_end) runs one
+ * staggered increment (as staggered_step) that stops early when a mechanics
+ * solve fails or Newton's residual grows newton_div times in a row; it is
+ * accepted when ERR <= stagger_tol and the last Newton solve converged
+ * (then dt <- min(grow dt, dt_max)).  A rejected attempt restores the state
+ * and the stress and halves dt; the run stops once dt < dt_min. */
+typedef struct {
+  double t;         /* in: load factor of `state`; out: load factor reached */
+  double t_end;     /* load factor to reach (t = 1 is target_end itself) */
+  double dt;        /* in: first increment to try; out: the next one to try */
+  double dt_min;    /* smallest admissible increment (> 0) */
+  double dt_max;    /* largest increment (> 0) */
+  double grow;      /* growth factor after an accepted increment (>= 1) */
+  int max_attempts; /* attempts allowed in this call */
+  int newton_div;   /* Newton divergence guard: consecutive residual increases (0 = off) */
+  int reason;       /* out: 0 t_end reached, 1 dt < dt_min, 2 attempts used up, 3 records full */
+  int attempts;     /* out: attempts made in this call */
+} fftg_drive_opts;
+
+typedef struct {
+  double t;          /* load factor of the accepted increment */
+  double homog[12];  /* <sigma>, <eps> as staggered_step's homog_out */
+  double err;        /* staggered error of its last pass */
+  int cutbacks;      /* rejected attempts just before it */
+  int stagger_iters, newton_iters, cg_iters, pcg_iters;
+  double ms;         /* wall time of the accepted attempt */
+} fftg_drive_record;
+
+/*   state       dev packed state as in staggered_step; in at opts->t, out at
+ *               the last accepted increment
+ *   sigma_out   dev [c][N] stress of the last accepted increment (left as
+ *               passed in when none was accepted)
+ *   records     host [max_records], one per accepted increment; *n_records
+ *               of them are written
+ * (state, opts->t, opts->dt) is the driver's whole position: a later call
+ * with them continues the same run (checkpoint / resume).  Returns FFTG_OK
+ * when t_end was reached, FFTG_NOT_CONVERGED when it stopped for another
+ * reason (opts->reason); invalid options give FFTG_E_INVALID. */
+fftg_status fftg_drive(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
+                       int nphase, int nfields, double* state, const fftg_macro* target_end,
+                       const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
+                       double newton_tol, int newton_maxit, double stagger_tol,
+                       int max_stagger_iters, fftg_drive_opts* opts, double* sigma_out,
+                       fftg_drive_record* records, int max_records, int* n_records);
 
 /* ---- single-operator entry points (same kernels as the solvers) ---- */
 

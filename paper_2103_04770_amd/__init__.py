@@ -9,3 +9,4 @@ fallback: importing `Solver` without a built library raises.
 from .binding import (FFTGError, Solver, phase_table, FP64, FP32_REFINED, ROTATED, SPECTRAL,  # noqa: F401
                       lib_path, load_library)
 from . import microstructure  # noqa: F401
+from .driver import LoadDriver  # noqa: F401

@@ -48,6 +48,19 @@ class KrylovOpts(ct.Structure):
     _fields_ = [("tol", ct.c_double), ("maxit", ct.c_int)]
 
 
+class DriveOpts(ct.Structure):
+    _fields_ = [("t", ct.c_double), ("t_end", ct.c_double), ("dt", ct.c_double),
+                ("dt_min", ct.c_double), ("dt_max", ct.c_double), ("grow", ct.c_double),
+                ("max_attempts", ct.c_int), ("newton_div", ct.c_int), ("reason", ct.c_int),
+                ("attempts", ct.c_int)]
+
+
+class DriveRecord(ct.Structure):
+    _fields_ = [("t", ct.c_double), ("homog", ct.c_double * 12), ("err", ct.c_double),
+                ("cutbacks", ct.c_int), ("stagger_iters", ct.c_int), ("newton_iters", ct.c_int),
+                ("cg_iters", ct.c_int), ("pcg_iters", ct.c_int), ("ms", ct.c_double)]
+
+
 class Stats(ct.Structure):
     _fields_ = [("newton_iters", ct.c_int), ("cg_iters", ct.c_int), ("pcg_iters", ct.c_int),
                 ("stagger_iters", ct.c_int), ("relres", ct.c_double), ("err", ct.c_double),
@@ -90,6 +103,9 @@ def load_library():
         "staggered_step": [P, P, ct.POINTER(Phase), I, I, P, ct.POINTER(Macro),
                            ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D, I, D, I, P,
                            ct.POINTER(ct.c_double), ct.POINTER(Stats)],
+        "fftg_drive": [P, P, ct.POINTER(Phase), I, I, P, ct.POINTER(Macro),
+                       ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D, I, D, I,
+                       ct.POINTER(DriveOpts), P, ct.POINTER(DriveRecord), I, ct.POINTER(I)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -283,6 +299,38 @@ class Solver:
         d["sigma_mean"] = np.array(hom[:c])
         d["eps_mean"] = np.array(hom[6:6 + c])
         return d
+
+    def fftg_drive(self, phase, table, nfields, state, target_end, sigma_out, t=0.0, t_end=1.0,
+                   dt=0.1, dt_min=1e-5, dt_max=1.0, grow=1.5, max_attempts=1000,
+                   max_records=1000, newton_div=3, cg_tol=1e-8, cg_maxit=5000, pcg_tol=1e-8,
+                   pcg_maxit=2000, newton_tol=1e-8, newton_maxit=50, stagger_tol=1e-6,
+                   max_stagger=20):
+        """Variable-increment loading from load factor t towards t_end (see
+        fftg_drive in include/fftg.h).  Returns dict(t, dt, reason, attempts,
+        converged, records) with one record dict per accepted increment."""
+        f64 = self.torch.float64
+        tab = phase_table(table)
+        m = _macro(target_end)
+        o = DriveOpts(float(t), float(t_end), float(dt), float(dt_min), float(dt_max),
+                      float(grow), int(max_attempts), int(newton_div), 0, 0)
+        recs = (DriveRecord * max(1, int(max_records)))()
+        n = ct.c_int(0)
+        ok = self._check(self.lib.fftg_drive(
+            self.h, _ptr(phase, self.torch.uint8, self.N, "phase"), tab, len(table), nfields,
+            _ptr(state, f64, (self.c + 7 + 2 * nfields) * self.N, "state"), ct.byref(m),
+            ct.byref(KrylovOpts(cg_tol, cg_maxit)), ct.byref(KrylovOpts(pcg_tol, pcg_maxit)),
+            float(newton_tol), int(newton_maxit), float(stagger_tol), int(max_stagger),
+            ct.byref(o), _ptr(sigma_out, f64, self.c * self.N, "sigma_out"), recs,
+            int(max_records), ct.byref(n)))
+        c = self.c
+        records = []
+        for r in recs[: n.value]:
+            records.append(dict(t=r.t, sigma=np.array(r.homog[:c]), eps=np.array(r.homog[6:6 + c]),
+                                err=r.err, cutbacks=r.cutbacks, stagger_iters=r.stagger_iters,
+                                newton_iters=r.newton_iters, cg_iters=r.cg_iters,
+                                pcg_iters=r.pcg_iters, ms=r.ms))
+        return dict(t=o.t, dt=o.dt, reason=o.reason, attempts=o.attempts, converged=ok,
+                    records=records)
 
     def profile(self, enable):
         """Per-kernel-class GPU time (HIP events on the handle's stream).

@@ -92,6 +92,9 @@ struct fftg_handle {
   double *eps_k = nullptr, *eps_prev = nullptr, *ab_k = nullptr, *ab_prev = nullptr,
          *Dj = nullptr, *alph = nullptr, *st1 = nullptr, *sig_k = nullptr;
   void* ell2j = nullptr;  // [J][N] work precision
+  // adaptive driver: copy of the packed state and the stress before an attempt
+  double* drive_bak = nullptr;
+  size_t drive_bak_n = 0;
   hipEvent_t ev[8]{};
   // per-kernel-class timing (fftg_profile): event pairs resolved at sync points
   bool prof = false;
@@ -711,10 +714,12 @@ template <typename T>
 MechOut mechanics(fftg_handle* H, const unsigned char* phase, const MatTable& tab, int J,
                   const double* D, const double* state_n, const fftg_macro* tgt, double* eps,
                   double* sigma, double* st_np1, double* alpha, const fftg_krylov_opts* cg,
-                  double ntol, int nmaxit) {
+                  double ntol, int nmaxit, int newton_div = 0) {
   const Geo& g = H->g;
   const int c = H->c;
   MechOut o;
+  o.relres = HUGE_VAL;
+  int grown = 0;  // consecutive corrections after which the residual grew
   // move the strain-controlled means to their targets
   double mean[6], delta[6] = {0, 0, 0, 0, 0, 0};
   comp_means(H, c, eps, mean);
@@ -751,10 +756,16 @@ MechOut mechanics(fftg_handle* H, const unsigned char* phase, const MatTable& ta
     double s2[2];
     read_sums(H, nr, 2, s2);
     const double nb = std::sqrt(s2[0] / (double)g.N), ns = std::sqrt(s2[1] / (double)g.N);
+    const double prev = o.relres;
     o.relres = nb / std::max(ns, sref * sqN);
     if (!std::isfinite(o.relres)) throw Fail{FFTG_E_NONFINITE, "non-finite Newton residual"};
+    grown = (r >= 1 && o.relres > prev) ? grown + 1 : 0;
     if (r >= 1 && o.relres <= ntol) {
       o.converged = true;
+      o.t_cg += wall_ms(t0);
+      break;
+    }
+    if (newton_div > 0 && grown >= newton_div) {
       o.t_cg += wall_ms(t0);
       break;
     }
@@ -860,6 +871,7 @@ void destroy(fftg_handle* H) {
   dfree((void*&)H->st1);
   dfree((void*&)H->sig_k);
   dfree(H->ell2j);
+  dfree((void*&)H->drive_bak);
   for (auto& e : H->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& p : H->pend) {
@@ -891,6 +903,144 @@ fftg_status run_guarded(fftg_handle* H, const std::function<fftg_status()>& f) {
 }  // namespace
 
 // ============================================================ C ABI
+// One increment of Algorithm 1 on a validated call.  abort_on_mech: leave
+// the staggered loop as soon as a mechanics solve fails (adaptive driver);
+// newton_div: Newton divergence guard (0 = off).
+struct StaggerOut {
+  fftg_stats stats{};
+  bool converged = false;  // ERR <= stagger_tol
+  bool mech_ok = false;    // the last mechanics solve converged
+};
+
+StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTable& t, int J,
+                        double* state, const fftg_macro* target, const fftg_krylov_opts* cg,
+                        const fftg_krylov_opts* pcg, double newton_tol, int newton_maxit,
+                        double stagger_tol, int max_stagger_iters, double* sigma_out,
+                        double* homog_out, bool abort_on_mech, int newton_div) {
+  StaggerOut out;
+  auto t_all = std::chrono::steady_clock::now();
+  const Geo& g = H->g;
+  const int c = H->c;
+  const long long N = g.N;
+  alloc_stagger(H, J);
+  alloc_helm(H);
+  double* s_eps = state;
+  double* s_epsp = state + (long long)c * N;  // eps_p (6) followed by kappa (1)
+  double* s_hist = state + (long long)(c + 7) * N;
+  double* s_abar = state + (long long)(c + 7 + J) * N;
+  HIPCHK(hipMemcpyAsync(H->eps_k, s_eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
+  if (J > 0)
+    HIPCHK(hipMemcpyAsync(H->ab_k, s_abar, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
+                          H->st));
+  for (int j = 0; j < J; ++j) {
+    if (H->fp32())
+      fftg::launch_ell2<float>(t, N, j, phase, reinterpret_cast<float*>(H->ell2j) + j * N, H->st);
+    else
+      fftg::launch_ell2<double>(t, N, j, phase, reinterpret_cast<double*>(H->ell2j) + j * N,
+                                H->st);
+  }
+  fftg_stats acc{};
+  bool converged = false;
+  int k = 0;
+  double err = 0.0;
+  for (k = 0; k < max_stagger_iters; ++k) {
+    if (J > 0) fftg::launch_damage(t, N, J, phase, H->ab_k, s_hist, H->Dj, H->st);
+    HIPCHK(hipMemcpyAsync(H->eps_prev, H->eps_k, sizeof(double) * c * N,
+                          hipMemcpyDeviceToDevice, H->st));
+    MechOut o = H->fp32()
+                    ? mechanics<float>(H, phase, t, J, H->Dj, s_epsp, target, H->eps_k,
+                                       H->sig_k, H->st1, H->alph, cg, newton_tol, newton_maxit, newton_div)
+                    : mechanics<double>(H, phase, t, J, H->Dj, s_epsp, target, H->eps_k,
+                                        H->sig_k, H->st1, H->alph, cg, newton_tol,
+                                        newton_maxit, newton_div);
+    acc.newton_iters += o.newton;
+    out.mech_ok = o.converged;
+    acc.cg_iters += o.cg;
+    acc.relres = o.relres;
+    acc.t_ms[0] += o.t_const;
+    acc.t_ms[1] += o.t_cg;
+    if (abort_on_mech && !o.converged) {
+      acc.stagger_iters = k + 1;
+      break;
+    }
+    auto th = std::chrono::steady_clock::now();
+    if (J > 0)
+      HIPCHK(hipMemcpyAsync(H->ab_prev, H->ab_k, sizeof(double) * J * N,
+                            hipMemcpyDeviceToDevice, H->st));
+    for (int j = 0; j < J; ++j) {
+      int it = 0, status = 0;
+      double rel = 0.0;
+      if (H->fp32())
+        helmholtz_pcg<float>(H, H->alph + j * N, reinterpret_cast<const float*>(H->ell2j) + j * N,
+                             -1.0, H->ab_k + j * N, pcg->tol, pcg->maxit, it, rel, status);
+      else
+        helmholtz_pcg<double>(H, H->alph + j * N,
+                              reinterpret_cast<const double*>(H->ell2j) + j * N, -1.0,
+                              H->ab_k + j * N, pcg->tol, pcg->maxit, it, rel, status);
+      if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
+      if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+      acc.pcg_iters += it;
+    }
+    sync(H);
+    acc.t_ms[2] += wall_ms(th);
+    // staggered error (Algorithm 1 (iii))
+    const int nbe = fftg::launch_stagger_err(N, c, J, H->eps_k, H->eps_prev, H->ab_k,
+                                             H->ab_prev, H->partials, H->st);
+    // block partials: [0] max of |d eps|^2, then per field sum d^2, sum abar^2
+    std::vector<double> part((size_t)nbe * (1 + 2 * J));
+    HIPCHK(hipMemcpyAsync(part.data(), H->partials, sizeof(double) * part.size(),
+                          hipMemcpyDeviceToHost, H->st));
+    sync(H);
+    double mx = 0.0;
+    for (int b = 0; b < nbe; ++b) mx = std::max(mx, part[b]);
+    double mean[6];
+    comp_means(H, c, H->eps_k, mean);
+    double mn = 0.0;
+    for (int i = 0; i < c; ++i) mn += mean[i] * mean[i];
+    mn = std::sqrt(mn);
+    err = std::sqrt(mx) / (mn > 0.0 ? mn : 1.0);
+    for (int j = 0; j < J; ++j) {
+      double d2 = 0.0, a2 = 0.0;
+      for (int b = 0; b < nbe; ++b) {
+        d2 += part[(size_t)(1 + 2 * j) * nbe + b];
+        a2 += part[(size_t)(2 + 2 * j) * nbe + b];
+      }
+      if (d2 > 0.0) err = std::max(err, std::sqrt(d2) / std::max(std::sqrt(a2), 1e-12 * std::sqrt((double)N)));
+    }
+    acc.stagger_iters = k + 1;
+    acc.err = err;
+    if (err <= stagger_tol) {
+      converged = true;
+      break;
+    }
+  }
+  // commit the increment
+  HIPCHK(hipMemcpyAsync(s_eps, H->eps_k, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
+  HIPCHK(hipMemcpyAsync(s_epsp, H->st1, sizeof(double) * 7 * N, hipMemcpyDeviceToDevice, H->st));
+  if (J > 0) {
+    fftg::launch_vmax((long long)J * N, s_hist, H->ab_k, H->st);
+    HIPCHK(hipMemcpyAsync(s_abar, H->ab_k, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
+                          H->st));
+  }
+  HIPCHK(hipMemcpyAsync(sigma_out, H->sig_k, sizeof(double) * c * N, hipMemcpyDeviceToDevice,
+                        H->st));
+  double ms[6], me[6];
+  comp_means(H, c, H->sig_k, ms);
+  comp_means(H, c, H->eps_k, me);
+  for (int i = 0; i < 12; ++i) homog_out[i] = 0.0;
+  for (int i = 0; i < c; ++i) {
+    homog_out[i] = ms[i];
+    homog_out[6 + i] = me[i];
+  }
+  check_launch();
+  sync(H);
+  const double tot = wall_ms(t_all);
+  acc.t_ms[3] = std::max(0.0, tot - acc.t_ms[0] - acc.t_ms[1] - acc.t_ms[2]);
+  out.stats = acc;
+  out.converged = converged;
+  return out;
+}
+
 extern "C" {
 
 fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** out) {
@@ -1355,122 +1505,105 @@ fftg_status staggered_step(fftg_handle* H, const unsigned char* phase, const fft
     if (!phase || !state || !cg || !pcg || !sigma_out || !homog_out)
       throw Fail{FFTG_E_INVALID, "staggered_step: null pointer"};
     if (max_stagger_iters < 1) throw Fail{FFTG_E_INVALID, "max_stagger_iters must be >= 1"};
-    auto t_all = std::chrono::steady_clock::now();
+    const MatTable t = make_table(tab, nphase, nfields);
+    const StaggerOut o = stagger_core(H, phase, t, nfields, state, target, cg, pcg, newton_tol,
+                                      newton_maxit, stagger_tol, max_stagger_iters, sigma_out,
+                                      homog_out, false, 0);
+    if (stats) *stats = o.stats;
+    return o.converged ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+}
+
+
+fftg_status fftg_drive(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
+                       int nphase, int nfields, double* state, const fftg_macro* target_end,
+                       const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
+                       double newton_tol, int newton_maxit, double stagger_tol,
+                       int max_stagger_iters, fftg_drive_opts* opts, double* sigma_out,
+                       fftg_drive_record* records, int max_records, int* n_records) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, nfields);
+    validate_macro(target_end, H->c);
+    if (!phase || !state || !cg || !pcg || !opts || !sigma_out || !n_records ||
+        (max_records > 0 && !records))
+      throw Fail{FFTG_E_INVALID, "fftg_drive: null pointer"};
+    if (max_stagger_iters < 1) throw Fail{FFTG_E_INVALID, "max_stagger_iters must be >= 1"};
+    if (!(opts->dt > 0.0) || !(opts->dt_min > 0.0) || !(opts->dt_max > 0.0) ||
+        !(opts->grow >= 1.0) || max_records < 0 || opts->max_attempts < 0 ||
+        opts->newton_div < 0 || !std::isfinite(opts->t) || !std::isfinite(opts->t_end))
+      throw Fail{FFTG_E_INVALID, "fftg_drive: bad options"};
     const Geo& g = H->g;
     const int c = H->c, J = nfields;
-    const long long N = g.N;
-    alloc_stagger(H, J);
-    alloc_helm(H);
-    MatTable t = make_table(tab, nphase, J);
-    double* s_eps = state;
-    double* s_epsp = state + (long long)c * N;  // eps_p (6) followed by kappa (1)
-    double* s_hist = state + (long long)(c + 7) * N;
-    double* s_abar = state + (long long)(c + 7 + J) * N;
-    HIPCHK(hipMemcpyAsync(H->eps_k, s_eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
-    if (J > 0)
-      HIPCHK(hipMemcpyAsync(H->ab_k, s_abar, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
-                            H->st));
-    for (int j = 0; j < J; ++j) {
-      if (H->fp32())
-        fftg::launch_ell2<float>(t, N, j, phase, reinterpret_cast<float*>(H->ell2j) + j * N, H->st);
-      else
-        fftg::launch_ell2<double>(t, N, j, phase, reinterpret_cast<double*>(H->ell2j) + j * N,
-                                  H->st);
+    const size_t nstate = (size_t)(c + 7 + 2 * J) * (size_t)g.N;
+    const size_t nsig = (size_t)c * (size_t)g.N;
+    if (H->drive_bak_n < nstate + nsig) {
+      dfree((void*&)H->drive_bak);
+      H->drive_bak = (double*)dalloc(sizeof(double) * (nstate + nsig));
+      H->drive_bak_n = nstate + nsig;
     }
-    fftg_stats acc{};
-    bool converged = false;
-    int k = 0;
-    double err = 0.0;
-    for (k = 0; k < max_stagger_iters; ++k) {
-      if (J > 0) fftg::launch_damage(t, N, J, phase, H->ab_k, s_hist, H->Dj, H->st);
-      HIPCHK(hipMemcpyAsync(H->eps_prev, H->eps_k, sizeof(double) * c * N,
-                            hipMemcpyDeviceToDevice, H->st));
-      MechOut o = H->fp32()
-                      ? mechanics<float>(H, phase, t, J, H->Dj, s_epsp, target, H->eps_k,
-                                         H->sig_k, H->st1, H->alph, cg, newton_tol, newton_maxit)
-                      : mechanics<double>(H, phase, t, J, H->Dj, s_epsp, target, H->eps_k,
-                                          H->sig_k, H->st1, H->alph, cg, newton_tol,
-                                          newton_maxit);
-      acc.newton_iters += o.newton;
-      acc.cg_iters += o.cg;
-      acc.relres = o.relres;
-      acc.t_ms[0] += o.t_const;
-      acc.t_ms[1] += o.t_cg;
-      auto th = std::chrono::steady_clock::now();
-      if (J > 0)
-        HIPCHK(hipMemcpyAsync(H->ab_prev, H->ab_k, sizeof(double) * J * N,
-                              hipMemcpyDeviceToDevice, H->st));
-      for (int j = 0; j < J; ++j) {
-        int it = 0, status = 0;
-        double rel = 0.0;
-        if (H->fp32())
-          helmholtz_pcg<float>(H, H->alph + j * N, reinterpret_cast<const float*>(H->ell2j) + j * N,
-                               -1.0, H->ab_k + j * N, pcg->tol, pcg->maxit, it, rel, status);
-        else
-          helmholtz_pcg<double>(H, H->alph + j * N,
-                                reinterpret_cast<const double*>(H->ell2j) + j * N, -1.0,
-                                H->ab_k + j * N, pcg->tol, pcg->maxit, it, rel, status);
-        if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
-        if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
-        acc.pcg_iters += it;
-      }
-      sync(H);
-      acc.t_ms[2] += wall_ms(th);
-      // staggered error (Algorithm 1 (iii))
-      const int nbe = fftg::launch_stagger_err(N, c, J, H->eps_k, H->eps_prev, H->ab_k,
-                                               H->ab_prev, H->partials, H->st);
-      // block partials: [0] max of |d eps|^2, then per field sum d^2, sum abar^2
-      std::vector<double> part((size_t)nbe * (1 + 2 * J));
-      HIPCHK(hipMemcpyAsync(part.data(), H->partials, sizeof(double) * part.size(),
-                            hipMemcpyDeviceToHost, H->st));
-      sync(H);
-      double mx = 0.0;
-      for (int b = 0; b < nbe; ++b) mx = std::max(mx, part[b]);
-      double mean[6];
-      comp_means(H, c, H->eps_k, mean);
-      double mn = 0.0;
-      for (int i = 0; i < c; ++i) mn += mean[i] * mean[i];
-      mn = std::sqrt(mn);
-      err = std::sqrt(mx) / (mn > 0.0 ? mn : 1.0);
-      for (int j = 0; j < J; ++j) {
-        double d2 = 0.0, a2 = 0.0;
-        for (int b = 0; b < nbe; ++b) {
-          d2 += part[(size_t)(1 + 2 * j) * nbe + b];
-          a2 += part[(size_t)(2 + 2 * j) * nbe + b];
-        }
-        if (d2 > 0.0) err = std::max(err, std::sqrt(d2) / std::max(std::sqrt(a2), 1e-12 * std::sqrt((double)N)));
-      }
-      acc.stagger_iters = k + 1;
-      acc.err = err;
-      if (err <= stagger_tol) {
-        converged = true;
+    const MatTable t = make_table(tab, nphase, J);
+    double tl = opts->t, dt = opts->dt;
+    int recs = 0, attempts = 0, cut = 0, reason = 0;
+    while (tl < opts->t_end) {
+      if (recs >= max_records) {
+        reason = 3;
         break;
       }
+      if (attempts >= opts->max_attempts) {
+        reason = 2;
+        break;
+      }
+      const double tn = dt >= opts->t_end - tl ? opts->t_end : tl + dt;
+      fftg_macro tgt = *target_end;
+      for (int k = 0; k < 6; ++k) {
+        tgt.E[k] = tn * target_end->E[k];
+        tgt.S[k] = tn * target_end->S[k];
+      }
+      HIPCHK(hipMemcpyAsync(H->drive_bak, state, sizeof(double) * nstate,
+                            hipMemcpyDeviceToDevice, H->st));
+      HIPCHK(hipMemcpyAsync(H->drive_bak + nstate, sigma_out, sizeof(double) * nsig,
+                            hipMemcpyDeviceToDevice, H->st));
+      ++attempts;
+      auto t0 = std::chrono::steady_clock::now();
+      double homog[12];
+      const StaggerOut o =
+          stagger_core(H, phase, t, J, state, &tgt, cg, pcg, newton_tol, newton_maxit,
+                       stagger_tol, max_stagger_iters, sigma_out, homog, true, opts->newton_div);
+      if (o.converged && o.mech_ok) {
+        tl = tn;
+        fftg_drive_record& r = records[recs++];
+        r.t = tn;
+        for (int i = 0; i < 12; ++i) r.homog[i] = homog[i];
+        r.err = o.stats.err;
+        r.cutbacks = cut;
+        r.stagger_iters = o.stats.stagger_iters;
+        r.newton_iters = o.stats.newton_iters;
+        r.cg_iters = o.stats.cg_iters;
+        r.pcg_iters = o.stats.pcg_iters;
+        r.ms = wall_ms(t0);
+        cut = 0;
+        dt = std::min(dt * opts->grow, opts->dt_max);
+      } else {
+        HIPCHK(hipMemcpyAsync(state, H->drive_bak, sizeof(double) * nstate,
+                              hipMemcpyDeviceToDevice, H->st));
+        HIPCHK(hipMemcpyAsync(sigma_out, H->drive_bak + nstate, sizeof(double) * nsig,
+                              hipMemcpyDeviceToDevice, H->st));
+        ++cut;
+        dt = dt / 2.0;
+        if (dt < opts->dt_min) {
+          reason = 1;
+          break;
+        }
+      }
     }
-    // commit the increment
-    HIPCHK(hipMemcpyAsync(s_eps, H->eps_k, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
-    HIPCHK(hipMemcpyAsync(s_epsp, H->st1, sizeof(double) * 7 * N, hipMemcpyDeviceToDevice, H->st));
-    if (J > 0) {
-      fftg::launch_vmax((long long)J * N, s_hist, H->ab_k, H->st);
-      HIPCHK(hipMemcpyAsync(s_abar, H->ab_k, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
-                            H->st));
-    }
-    HIPCHK(hipMemcpyAsync(sigma_out, H->sig_k, sizeof(double) * c * N, hipMemcpyDeviceToDevice,
-                          H->st));
-    double ms[6], me[6];
-    comp_means(H, c, H->sig_k, ms);
-    comp_means(H, c, H->eps_k, me);
-    for (int i = 0; i < 12; ++i) homog_out[i] = 0.0;
-    for (int i = 0; i < c; ++i) {
-      homog_out[i] = ms[i];
-      homog_out[6 + i] = me[i];
-    }
-    check_launch();
     sync(H);
-    const double tot = wall_ms(t_all);
-    acc.t_ms[3] = std::max(0.0, tot - acc.t_ms[0] - acc.t_ms[1] - acc.t_ms[2]);
-    if (stats) *stats = acc;
-    return converged ? FFTG_OK : FFTG_NOT_CONVERGED;
+    opts->t = tl;
+    opts->dt = dt;
+    opts->reason = reason;
+    opts->attempts = attempts;
+    *n_records = recs;
+    return reason == 0 ? FFTG_OK : FFTG_NOT_CONVERGED;
   });
 }
 

@@ -1,0 +1,135 @@
+"""The adaptive load driver (fftg_drive, Sec. 4.2) against the oracle's, and
+its checkpoint / resume through LoadDriver."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import driver as odriver, staggered  # noqa: E402
+from paper_2103_04770_amd import microstructure as ms  # noqa: E402
+
+TOLS = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rve(n=8, seed=1, dC=0.001, dR=0.05):
+    S = (n, n, n)
+    rng = np.random.default_rng(seed)
+    phase = (rng.uniform(size=S) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_elastic(ell=[1.0])]
+    table[0]["dC"], table[0]["dR"] = dC, dR
+    return S, phase, table
+
+
+def _solver(S):
+    from paper_2103_04770_amd import Solver
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return Solver(tuple(reversed(S)))
+
+
+def _gpu_drive(S, phase, table, tgt, **kw):
+    s = _solver(S)
+    state = torch.zeros((6 + 7 + 2,) + S, dtype=torch.float64, device="cuda")
+    sig = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
+    out = s.fftg_drive(torch.from_numpy(phase).cuda(), table, 1, state, tgt, sig, **kw)
+    torch.cuda.synchronize()
+    out["state"] = state.cpu().numpy()
+    return out
+
+
+def _compare(g, o, S, label):
+    tg = [r["t"] for r in g["records"]]
+    to = [r["t"] for r in o["records"]]
+    say(label, "gpu t", tg, "reason", g["reason"], "| oracle t", to, "reason", o["reason"])
+    say(label, "gpu cut", [r["cutbacks"] for r in g["records"]],
+        "oracle cut", [r["cutbacks"] for r in o["records"]])
+    assert tg == to
+    assert [r["cutbacks"] for r in g["records"]] == [r["cutbacks"] for r in o["records"]]
+    assert g["reason"] == o["reason"] and g["t"] == o["t"] and g["dt"] == o["dt"]
+    for a, b in zip(g["records"], o["records"]):
+        assert np.abs(a["sigma"] - b["sigma"]).max() <= 1e-9 * np.abs(b["sigma"]).max()
+        assert np.abs(a["eps"] - b["eps"]).max() <= 1e-10 * np.abs(b["eps"]).max()
+    eps_o = o["state"]["eps"]
+    assert np.abs(g["state"][:6] - eps_o).max() <= 1e-9 * np.abs(eps_o).max()
+
+
+def test_drive_cutbacks_match_oracle():
+    """Damage sets in early (eps_C = 1e-3) and three staggered passes are not
+    enough to converge an increment that starts it: attempts are cut back
+    until the run reaches the smallest increment.  Every accept/reject
+    decision has a wide margin (rejected ERR >= 7e-7, accepted <= 1e-11
+    against a tolerance of 1e-8)."""
+    S, phase, table = _rve()
+    tgt = ms.uniaxial_mixed(3, 0.02)
+    kw = dict(dt=0.3, dt_min=1e-3, max_stagger=3, stagger_tol=1e-8, **TOLS)
+    say("drive cutbacks 8^3")
+    g = _gpu_drive(S, phase, table, tgt, **kw)
+    o = odriver.drive(phase, table, 1, staggered.initial_state(S, 3, 1), tgt, **kw)
+    assert o["reason"] == odriver.FLOOR and len(o["records"]) >= 3
+    assert not g["converged"]
+    _compare(g, o, S, "cutbacks")
+
+
+def test_drive_to_the_end_matches_oracle():
+    """No damage (thresholds out of reach): the driver grows its increment and
+    reaches the end of the path."""
+    S, phase, table = _rve(n=12, seed=4, dC=1.0, dR=2.0)
+    tgt = ms.uniaxial_mixed(3, 0.01)
+    kw = dict(dt=0.2, grow=1.5, dt_max=0.3, max_stagger=4, stagger_tol=1e-9, **TOLS)
+    say("drive to end 12^3")
+    g = _gpu_drive(S, phase, table, tgt, **kw)
+    o = odriver.drive(phase, table, 1, staggered.initial_state(S, 3, 1), tgt, **kw)
+    assert o["reason"] == odriver.REACHED and g["converged"]
+    _compare(g, o, S, "end")
+
+
+def test_checkpoint_resume_repeats_the_run(tmp_path):
+    from paper_2103_04770_amd.driver import LoadDriver
+    S, phase, table = _rve(n=8, seed=2, dC=0.004, dR=0.1)
+    tgt = ms.uniaxial_mixed(3, 0.012)
+    opts = dict(dt_min=1e-2, max_stagger=6, stagger_tol=1e-8, **TOLS)
+    ph = torch.from_numpy(phase).cuda()
+    say("checkpoint/resume 8^3")
+    full = LoadDriver(_solver(S), ph, table, 1, tgt, dt=0.25, **opts)
+    full.run()
+    ck = str(tmp_path / "drive.npz")
+    part = LoadDriver(_solver(S), ph, table, 1, tgt, dt=0.25, **opts)
+    part.run(chunk=2, checkpoint=ck)          # runs to the end, checkpoint after each chunk
+    assert [r["t"] for r in part.records] == [r["t"] for r in full.records]
+    # stop early, then resume from the file with a fresh solver
+    first = LoadDriver(_solver(S), ph, table, 1, tgt, dt=0.25, **opts)
+    out = first.solver.fftg_drive(ph, table, 1, first.state, first.target_end, first.sigma,
+                                  t=0.0, dt=0.25, max_records=2, **opts)
+    first.t, first.dt, first.records = out["t"], out["dt"], out["records"]
+    first.save(ck)
+    resumed = LoadDriver.resume(ck, _solver(S), ph, table, 1, tgt, **opts)
+    assert resumed.t == first.t and resumed.dt == first.dt and len(resumed.records) == 2
+    resumed.run()
+    assert [r["t"] for r in resumed.records] == [r["t"] for r in full.records]
+    assert resumed.reason == full.reason
+    assert torch.equal(resumed.state, full.state) and torch.equal(resumed.sigma, full.sigma)
+    say("records", len(full.records), "reason", full.reason, "t", full.t)
+
+
+def test_drive_rejects_bad_options():
+    from paper_2103_04770_amd import FFTGError
+    S, phase, table = _rve(n=4)
+    s = _solver(S)
+    state = torch.zeros((15,) + S, dtype=torch.float64, device="cuda")
+    sig = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
+    ph = torch.from_numpy(phase).cuda()
+    for bad in (dict(dt=0.0), dict(dt_min=-1.0), dict(grow=0.5), dict(newton_div=-1)):
+        with pytest.raises(FFTGError) as e:
+            s.fftg_drive(ph, table, 1, state, ms.uniaxial_mixed(3, 1e-3), sig, **bad)
+        assert e.value.code == -1
+    # nothing to do: already at the end
+    out = s.fftg_drive(ph, table, 1, state, ms.uniaxial_mixed(3, 1e-3), sig, t=1.0)
+    assert out["converged"] and out["records"] == [] and out["attempts"] == 0
