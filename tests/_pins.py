@@ -72,15 +72,25 @@ def _circulants(n, h):
     return Smat, Cmat
 
 
-def dense_helmholtz(shape, ell2, h):
+def dense_gradients(shape, h):
+    """Dense real matrices Q_j (physical axis j) of the rotated first-order
+    derivative with zeroed Nyquist planes, acting on flattened (z, y, x)
+    fields."""
     ndim = len(shape)
     mats = [_circulants(shape[ndim - 1 - j], h) for j in range(ndim)]  # physical order
-    N = int(np.prod(shape))
-    L = np.eye(N)
+    out = []
     for j in range(ndim):
         Q = np.ones((1, 1))
         for ax in range(ndim):            # numpy axis order z, y, x
             pj = ndim - 1 - ax
             Q = np.kron(Q, mats[pj][0] if pj == j else mats[pj][1])
+        out.append(Q)
+    return out
+
+
+def dense_helmholtz(shape, ell2, h):
+    N = int(np.prod(shape))
+    L = np.eye(N)
+    for Q in dense_gradients(shape, h):
         L += Q.T @ np.diag(ell2.reshape(-1)) @ Q
     return L

@@ -1,0 +1,107 @@
+"""Pins of the checker's adjoint gradients: the Helmholtz solve against a
+dense real-space construction (no FFT), the mechanics solve against central
+finite differences of the forward solve."""
+import numpy as np
+import pytest
+
+from oracle import adjoint, galerkin, helmholtz
+from paper_2103_04770_amd import microstructure as ms
+from tests._pins import dense_gradients, dense_helmholtz
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 6), (6, 8)])
+def test_helmholtz_adjoint_equals_dense_gradient(shape):
+    rng = np.random.default_rng(0)
+    alpha = rng.standard_normal(shape)
+    ell2 = rng.uniform(0.0, 3.0, size=shape)
+    w = rng.standard_normal(shape)                  # J = w . abar
+    L = dense_helmholtz(shape, ell2, 1.0)
+    abar = np.linalg.solve(L, alpha.reshape(-1))
+    lam = np.linalg.solve(L, w.reshape(-1))        # L is symmetric
+    Qs = dense_gradients(shape, 1.0)
+    dell2 = -sum((Q @ lam) * (Q @ abar) for Q in Qs)
+    fwd = helmholtz.helmholtz_solve(alpha, ell2, tol=1e-14, maxit=500)
+    r = adjoint.helmholtz_adjoint(fwd["abar"], w, ell2, tol=1e-14, maxit=500)
+    assert np.abs(r["dalpha"].reshape(-1) - lam).max() <= 1e-11 * np.abs(lam).max()
+    assert np.abs(r["dell2"].reshape(-1) - dell2).max() <= 1e-10 * np.abs(dell2).max()
+
+
+def test_helmholtz_phase_length_gradient_by_finite_differences():
+    shape = (6, 6, 6)
+    rng = np.random.default_rng(1)
+    phase = (rng.uniform(size=shape) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_elastic(ell=[0.7])]
+    alpha = np.abs(rng.standard_normal(shape))
+    w = rng.standard_normal(shape)
+
+    def J(ells):
+        ell2 = np.array([e * e for e in ells])[phase]
+        return float((w * helmholtz.helmholtz_solve(alpha, ell2, tol=1e-14,
+                                                    maxit=500)["abar"]).sum())
+    ell2 = np.array([4.0, 0.49])[phase]
+    fwd = helmholtz.helmholtz_solve(alpha, ell2, tol=1e-14, maxit=500)
+    r = adjoint.helmholtz_adjoint(fwd["abar"], w, ell2, tol=1e-14, maxit=500)
+    g = adjoint.phase_length_gradient(r["dell2"], phase, table, 0)
+    hh = 1e-5
+    for q, base in enumerate([2.0, 0.7]):
+        ep, em = [2.0, 0.7], [2.0, 0.7]
+        ep[q] += hh
+        em[q] -= hh
+        fd = (J(ep) - J(em)) / (2 * hh)
+        assert g[q] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_mechanics_adjoint_by_finite_differences():
+    """J = w . eps at the converged strain, D perturbed along a random
+    direction on the damaging voxels (central differences, h = 1e-6)."""
+    S = (6, 6, 6)
+    rng = np.random.default_rng(3)
+    phase = (rng.uniform(size=S) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_elastic(ell=[1.0])]
+    D0 = np.where(phase == 0, rng.uniform(0.1, 0.5, size=S), 0.0)[None]
+    z6, z = np.zeros((6,) + S), np.zeros(S)
+    tgt = ms.uniaxial_mixed(3, 6e-3)
+    w = rng.standard_normal((6,) + S)
+    kw = dict(cg_tol=1e-13, newton_tol=1e-13, newton_maxit=60)
+
+    def solve(D):
+        return galerkin.fftg_solve(phase, table, D, z6, z, tgt, z6.copy(), **kw)
+
+    base = solve(D0)
+    assert base["converged"]
+    r = adjoint.mechanics_adjoint(phase, table, D0, z6, z, tgt, base["eps"], w, 1,
+                                  cg_tol=1e-13)
+    dirn = np.where(phase == 0, rng.standard_normal(S), 0.0)[None]
+    hh = 1e-6
+    jp = float((w * solve(D0 + hh * dirn)["eps"]).sum())
+    jm = float((w * solve(D0 - hh * dirn)["eps"]).sum())
+    fd = (jp - jm) / (2 * hh)
+    ad = float((r["dD"] * dirn).sum())
+    assert ad == pytest.approx(fd, rel=1e-5)
+    # no sensitivity where no damage law acts
+    assert np.all(r["dD"][0][phase == 1] == 0)
+
+
+def test_mechanics_adjoint_mixed_control_by_finite_differences():
+    """Same check in 2D plane strain under pure stress control of the shear."""
+    S = (8, 12)
+    rng = np.random.default_rng(4)
+    phase = (rng.uniform(size=S) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_cracking(ell=[1.0], dfield=0)]
+    D0 = rng.uniform(0.05, 0.4, size=S)[None]
+    z6, z = np.zeros((6,) + S), np.zeros(S)
+    tgt = (np.array([0, 1, 1], np.uint8), np.array([4e-3, 0.0, 0.0]), np.array([0.0, 0.0, 30.0]))
+    w = rng.standard_normal((3,) + S)
+    kw = dict(cg_tol=1e-13, newton_tol=1e-13, newton_maxit=60)
+
+    def solve(D):
+        return galerkin.fftg_solve(phase, table, D, z6, z, tgt, np.zeros((3,) + S), **kw)
+
+    base = solve(D0)
+    r = adjoint.mechanics_adjoint(phase, table, D0, z6, z, tgt, base["eps"], w, 1,
+                                  cg_tol=1e-13)
+    dirn = rng.standard_normal((1,) + S)
+    hh = 1e-6
+    fd = (float((w * solve(D0 + hh * dirn)["eps"]).sum()) -
+          float((w * solve(D0 - hh * dirn)["eps"]).sum())) / (2 * hh)
+    assert float((r["dD"] * dirn).sum()) == pytest.approx(fd, rel=1e-5)
