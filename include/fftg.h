@@ -13,6 +13,8 @@
  *   - staggered_step  : one load increment of the iterated staggered scheme
  *                       (Sec. 3.2, Algorithm 1).
  *   - fftg_drive      : variable-increment loading with cutback (Sec. 4.2).
+ *   - helmholtz_adjoint, fftg_solve_adjoint : gradients of the two solves by
+ *                       implicit differentiation at the converged state.
  *
  * Conventions shared by every entry point
  *   Grid       N1 x N2 x N3 voxels (N3 = 1 in 2D plane strain), voxel size h.
@@ -173,6 +175,39 @@ fftg_status staggered_step(fftg_handle* h, const unsigned char* phase, const fft
                            double newton_tol, int newton_maxit, double stagger_tol,
                            int max_stagger_iters, double* sigma_out, double* homog_out,
                            fftg_stats* stats);
+
+/* ---- adjoints (implicit differentiation at the converged state) ---- */
+
+/* Adjoint of Algorithm 2.  In real space the operator is
+ * L u = u + sum_j G_j^T (ell2 G_j u), G_j = F^-1 diag(i q~_j) F, symmetric
+ * positive definite.  For abar = L^-1 alpha and a scalar J with
+ * gbar = dJ/dabar:
+ *   dalpha = dJ/dalpha = L^-1 gbar   (the same PCG as helmholtz_solve)
+ *   dell2  = dJ/dell2(x) = -sum_j (G_j dalpha)(x) (G_j abar)(x)
+ *   ell2, abar, gbar  dev [N] (abar: the converged solution)
+ *   dalpha            dev [N] in = initial guess, out = dJ/dalpha
+ *   dell2             dev [N] out
+ * FFTG_NOT_CONVERGED: the adjoint PCG stopped at opts->maxit. */
+fftg_status helmholtz_adjoint(fftg_handle* h, const double* ell2, double ell2_ref,
+                              const double* abar, const double* gbar, double* dalpha,
+                              double* dell2, const fftg_krylov_opts* opts, fftg_stats* stats);
+
+/* Adjoint of the mechanics solve at frozen damage (Sec. 3.2.2).  At the
+ * converged strain eps of fftg_solve (same phase, tab, D, state_n, target),
+ * for a scalar J with gbar = dJ/deps:
+ *   mu = (G* K)^-1 G*(gbar) on the admissible space (compatible fluctuations
+ *        and the means of the stress-controlled components), K the consistent
+ *        tangent recomputed at eps, solved by the same CG;
+ *   dD_j(x) = dJ/dD_j(x) = mu(x) : sigma(x) / (1 - D_j(x)) on voxels whose
+ *        phase has a damage law driven by field j (d sigma / dD is minus the
+ *        effective stress), 0 elsewhere.
+ *   eps, gbar  dev [c][N];  mu dev [c][N] out;  dD dev [nfields][N] out
+ *   (may be NULL when nfields = 0). */
+fftg_status fftg_solve_adjoint(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
+                               int nphase, int nfields, const double* D, const double* state_n,
+                               const fftg_macro* target, const double* eps, const double* gbar,
+                               double* mu, double* dD, const fftg_krylov_opts* cg,
+                               fftg_stats* stats);
 
 /* ---- adaptive load driver ---- */
 

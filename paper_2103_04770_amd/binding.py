@@ -103,6 +103,9 @@ def load_library():
         "staggered_step": [P, P, ct.POINTER(Phase), I, I, P, ct.POINTER(Macro),
                            ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D, I, D, I, P,
                            ct.POINTER(ct.c_double), ct.POINTER(Stats)],
+        "helmholtz_adjoint": [P, P, D, P, P, P, P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
+        "fftg_solve_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, ct.POINTER(Macro), P, P, P,
+                               P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
         "fftg_drive": [P, P, ct.POINTER(Phase), I, I, P, ct.POINTER(Macro),
                        ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D, I, D, I,
                        ct.POINTER(DriveOpts), P, ct.POINTER(DriveRecord), I, ct.POINTER(I)],
@@ -298,6 +301,38 @@ class Solver:
         c = self.c
         d["sigma_mean"] = np.array(hom[:c])
         d["eps_mean"] = np.array(hom[6:6 + c])
+        return d
+
+    def helmholtz_adjoint(self, ell2, abar, gbar, dalpha, dell2, tol=1e-8, maxit=1000,
+                          ell2_ref=-1.0):
+        """dalpha <- dJ/dalpha = L^-1 gbar (in: initial guess), dell2 <- dJ/dell2."""
+        f64 = self.torch.float64
+        st = Stats()
+        ok = self._check(self.lib.helmholtz_adjoint(
+            self.h, _ptr(ell2, f64, self.N, "ell2"), float(ell2_ref), _ptr(abar, f64, self.N, "abar"),
+            _ptr(gbar, f64, self.N, "gbar"), _ptr(dalpha, f64, self.N, "dalpha"),
+            _ptr(dell2, f64, self.N, "dell2"), ct.byref(KrylovOpts(tol, maxit)), ct.byref(st)))
+        d = st.as_dict()
+        d["converged"] = ok
+        return d
+
+    def fftg_solve_adjoint(self, phase, table, nfields, D, state_n, target, eps, gbar, mu, dD,
+                           cg_tol=1e-8, cg_maxit=5000):
+        """mu <- (G* K)^-1 G*(gbar) at the converged eps; dD <- dJ/dD."""
+        f64 = self.torch.float64
+        tab = phase_table(table)
+        m = _macro(target)
+        st = Stats()
+        ok = self._check(self.lib.fftg_solve_adjoint(
+            self.h, _ptr(phase, self.torch.uint8, self.N, "phase"), tab, len(table), nfields,
+            _ptr(D, f64, nfields * self.N, "D") if nfields else None,
+            _ptr(state_n, f64, 7 * self.N, "state_n"), ct.byref(m),
+            _ptr(eps, f64, self.c * self.N, "eps"), _ptr(gbar, f64, self.c * self.N, "gbar"),
+            _ptr(mu, f64, self.c * self.N, "mu"),
+            _ptr(dD, f64, nfields * self.N, "dD") if nfields else None,
+            ct.byref(KrylovOpts(cg_tol, cg_maxit)), ct.byref(st)))
+        d = st.as_dict()
+        d["converged"] = ok
         return d
 
     def fftg_drive(self, phase, table, nfields, state, target_end, sigma_out, t=0.0, t_end=1.0,

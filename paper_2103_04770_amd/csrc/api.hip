@@ -94,6 +94,7 @@ struct fftg_handle {
   void* ell2j = nullptr;  // [J][N] work precision
   // adaptive driver: copy of the packed state and the stress before an attempt
   double* drive_bak = nullptr;
+  double* adj_r = nullptr;  // adjoint: two FP64 real scratch fields
   size_t drive_bak_n = 0;
   hipEvent_t ev[8]{};
   // per-kernel-class timing (fftg_profile): event pairs resolved at sync points
@@ -872,6 +873,7 @@ void destroy(fftg_handle* H) {
   dfree((void*&)H->sig_k);
   dfree(H->ell2j);
   dfree((void*&)H->drive_bak);
+  dfree((void*&)H->adj_r);
   for (auto& e : H->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& p : H->pend) {
@@ -903,6 +905,61 @@ fftg_status run_guarded(fftg_handle* H, const std::function<fftg_status()>& f) {
 }  // namespace
 
 // ============================================================ C ABI
+// ------------------------------------------------------------ adjoints
+// dell2(x) = -sum_j (G_j a)(x) (G_j b)(x), G_j = F^-1 diag(i q~_j) F, all in
+// FP64 (spec64 components 0..3 and two real scratch fields as workspace).
+void grad_dot(fftg_handle* H, const double* a, const double* b, double* out) {
+  const Geo& g = H->g;
+  const long long Ns = g.Ns;
+  if (!H->adj_r) H->adj_r = (double*)dalloc(sizeof(double) * 2 * (size_t)g.N);
+  cpx<double>* S = H->spec64;
+  fwd3<double>(H, 1, a, S);
+  fwd3<double>(H, 1, b, S + Ns);
+  for (int j = 0; j < g.ndim; ++j) {
+    fftg::launch_grad_comp<double>(g, H->S64, j, S, S + 2 * Ns, H->st);
+    inv3<double, double>(H, 1, S + 2 * Ns, H->adj_r, 1.0 / (double)g.N, false);
+    fftg::launch_grad_comp<double>(g, H->S64, j, S + Ns, S + 3 * Ns, H->st);
+    inv3<double, double>(H, 1, S + 3 * Ns, H->adj_r + g.N, 1.0 / (double)g.N, false);
+    fftg::launch_sub_prod(g.N, H->adj_r, H->adj_r + g.N, out, j > 0, H->st);
+  }
+  check_launch();
+}
+
+// Adjoint of the mechanics solve at frozen damage: mu = (G* K)^-1 G*(gbar)
+// with the tangent at eps, then dD.
+template <typename T>
+int mech_adjoint(fftg_handle* H, const unsigned char* phase, const MatTable& tab, int J,
+                 const double* D, const double* state_n, const fftg_macro* tgt,
+                 const double* eps, const double* gbar, double* mu, double* dD,
+                 const fftg_krylov_opts* cg, int& status) {
+  const Geo& g = H->g;
+  const int c = H->c;
+  alloc_stagger(H, J);
+  fftg::launch_constitutive<T>(tab, g, c, J, phase, eps, state_n, D, H->sig_k, H->st1, H->alph,
+                               reinterpret_cast<T*>(H->tan), H->st);
+  H->tan_valid = true;
+  // b = -G*(F(-gbar) - 0) = G* F(gbar)
+  fftg::launch_scale((long long)c * g.N, -1.0, gbar, H->eps_prev, H->st);
+  fwd3<double>(H, c, H->eps_prev, H->spec64);
+  fftg::launch_hermitize<double>(g, c, H->spec64, H->st);
+  const double zero6[6] = {0, 0, 0, 0, 0, 0};
+  const int nr = fftg::launch_gal_rhs<T>(g, c, H->S64, tgt->mask, zero6, H->spec64, C<T>(H->kr),
+                                         H->partials, H->st);
+  double s2[2];
+  read_sums(H, nr, 2, s2);
+  const double cgtol = H->fp32() ? std::max(cg->tol, kFp32KrylovFloor) : cg->tol;
+  std::memcpy(H->mask_last, tgt->mask, 6);
+  int it = 0;
+  galerkin_cg<T>(H, tgt->mask, s2[0], cgtol, cg->maxit, it, status);
+  if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Galerkin CG breakdown (p.Ap <= 0)"};
+  if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Galerkin CG"};
+  inv3<T, double>(H, c, C<T>(H->kx), mu, T(1.0 / (double)g.N), false);
+  if (J > 0) fftg::launch_adj_damage(tab, g.N, c, J, phase, D, H->sig_k, mu, dD, H->st);
+  check_launch();
+  sync(H);
+  return it;
+}
+
 // One increment of Algorithm 1 on a validated call.  abort_on_mech: leave
 // the staggered loop as soon as a mechanics solve fails (adaptive driver);
 // newton_div: Newton divergence guard (0 = off).
@@ -1458,6 +1515,66 @@ fftg_status helmholtz_solve(fftg_handle* H, const double* alpha, const double* e
     }
     if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
     if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+    return status == 1 ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+}
+
+fftg_status helmholtz_adjoint(fftg_handle* H, const double* ell2, double ell2_ref,
+                              const double* abar, const double* gbar, double* dalpha,
+                              double* dell2, const fftg_krylov_opts* opts, fftg_stats* stats) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!ell2 || !abar || !gbar || !dalpha || !dell2 || !opts)
+      throw Fail{FFTG_E_INVALID, "helmholtz_adjoint: null pointer"};
+    alloc_helm(H);
+    auto t0 = std::chrono::steady_clock::now();
+    int it = 0, status = 0;
+    double rel = 0.0;
+    if (H->fp32()) {
+      fftg::launch_convert<double, float>(H->g.N, ell2, reinterpret_cast<float*>(H->ell2w), H->st);
+      helmholtz_pcg<float>(H, gbar, reinterpret_cast<const float*>(H->ell2w), ell2_ref, dalpha,
+                           opts->tol, opts->maxit, it, rel, status);
+    } else {
+      helmholtz_pcg<double>(H, gbar, ell2, ell2_ref, dalpha, opts->tol, opts->maxit, it, rel,
+                            status);
+    }
+    if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
+    if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+    grad_dot(H, dalpha, abar, dell2);
+    sync(H);
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->pcg_iters = it;
+      stats->relres = rel;
+      stats->t_ms[2] = wall_ms(t0);
+    }
+    return status == 1 ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+}
+
+fftg_status fftg_solve_adjoint(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
+                               int nphase, int nfields, const double* D, const double* state_n,
+                               const fftg_macro* target, const double* eps, const double* gbar,
+                               double* mu, double* dD, const fftg_krylov_opts* cg,
+                               fftg_stats* stats) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, nfields);
+    validate_macro(target, H->c);
+    if (!phase || !state_n || !eps || !gbar || !mu || !cg || (nfields > 0 && (!D || !dD)))
+      throw Fail{FFTG_E_INVALID, "fftg_solve_adjoint: null pointer"};
+    const MatTable t = make_table(tab, nphase, nfields);
+    auto t0 = std::chrono::steady_clock::now();
+    int status = 0;
+    const int it = H->fp32() ? mech_adjoint<float>(H, phase, t, nfields, D, state_n, target, eps,
+                                                   gbar, mu, dD, cg, status)
+                             : mech_adjoint<double>(H, phase, t, nfields, D, state_n, target,
+                                                    eps, gbar, mu, dD, cg, status);
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->cg_iters = it;
+      stats->t_ms[1] = wall_ms(t0);
+    }
     return status == 1 ? FFTG_OK : FFTG_NOT_CONVERGED;
   });
 }

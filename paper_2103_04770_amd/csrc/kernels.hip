@@ -1063,6 +1063,58 @@ FFTG_KERNEL void k_sum_ell2(long long N, const T* __restrict__ e, double* __rest
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// ============================================================ adjoint helpers
+// out = i q~_j in: gradient component j of the Helmholtz operator's symbol.
+template <typename T>
+FFTG_KERNEL void k_grad_comp(Geo g, Sym<T> sym, int j, const cpx<T>* __restrict__ in,
+                             cpx<T>* __restrict__ out) {
+  for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
+       gi += (long long)gridDim.x * FFT_THREADS) {
+    int kx, ky, kz;
+    decode(g, gi, kx, ky, kz);
+    T q[3];
+    qvec(sym, true, kx, ky, kz, q);
+    out[gi] = mul_i(scale(in[gi], q[j]));
+  }
+}
+
+// out = (acc ? out : 0) - a b
+FFTG_KERNEL void k_sub_prod(long long n, const double* __restrict__ a,
+                            const double* __restrict__ b, double* __restrict__ out, int acc) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < n;
+       v += (long long)gridDim.x * FFT_THREADS)
+    out[v] = (acc ? out[v] : 0.0) - a[v] * b[v];
+}
+
+// y = s x
+FFTG_KERNEL void k_scale(long long n, double s, const double* __restrict__ x,
+                         double* __restrict__ y) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < n;
+       v += (long long)gridDim.x * FFT_THREADS)
+    y[v] = s * x[v];
+}
+
+// dJ/dD_j(x) = mu(x) : sigma(x) / (1 - D_j(x)) where the voxel's phase has a
+// damage law driven by field j (sigma / (1 - D) is the effective stress, and
+// d sigma / dD = -sigma_eff); 0 elsewhere.
+FFTG_KERNEL void k_adj_damage(MatTable tab, long long N, int c, int J,
+                              const unsigned char* __restrict__ phase,
+                              const double* __restrict__ D, const double* __restrict__ sigma,
+                              const double* __restrict__ mu, double* __restrict__ dD) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    double dot = 0.0;
+    for (int i = 0; i < c; ++i) dot += mu[(long long)i * N + v] * sigma[(long long)i * N + v];
+    for (int j = 0; j < J; ++j) {
+      double d = 0.0;
+      if (m.model != 0 && m.dfield == j) d = dot / (1.0 - D[(long long)j * N + v]);
+      dD[(long long)j * N + v] = d;
+    }
+  }
+}
+
 // ============================================================ launchers
 static inline int grid_for(long long n) {
   long long b = (n + FFT_THREADS - 1) / FFT_THREADS;
@@ -1346,6 +1398,27 @@ int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const 
   return nb;
 }
 
+template <typename T>
+void launch_grad_comp(const Geo& g, const Sym<T>& sym, int j, const cpx<T>* in, cpx<T>* out,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_comp<T>, dim3(grid_for(g.Ns)), dim3(FFT_THREADS), 0, st, g, sym, j,
+                     in, out);
+}
+void launch_sub_prod(long long n, const double* a, const double* b, double* out, bool acc,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_sub_prod, dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, a, b, out,
+                     acc ? 1 : 0);
+}
+void launch_scale(long long n, double s, const double* x, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, s, x, y);
+}
+void launch_adj_damage(const MatTable& tab, long long N, int c, int J,
+                       const unsigned char* phase, const double* D, const double* sigma,
+                       const double* mu, double* dD, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_damage, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, c, J,
+                     phase, D, sigma, mu, dD);
+}
+
 void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FFT_THREADS), 0, st, partials, nb, ctl);
 }
@@ -1489,5 +1562,8 @@ template void launch_x_c2r<float, float>(const Plan&, const cpx<float>*, const c
                                          float*, long long, int, int, float, bool, hipStream_t);
 template void launch_convert<double, float>(long long, const double*, float*, hipStream_t);
 template void launch_convert<float, double>(long long, const float*, double*, hipStream_t);
+
+template void launch_grad_comp<double>(const Geo&, const Sym<double>&, int,
+                                       const cpx<double>*, cpx<double>*, hipStream_t);
 
 }  // namespace fftg

@@ -119,6 +119,17 @@ int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const 
 void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st);
 void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st);
 void launch_fin_sums(const double* partials, int nb, int nred, double* out, hipStream_t st);
+
+// adjoint helpers (FP64)
+template <typename T>
+void launch_grad_comp(const Geo& g, const Sym<T>& sym, int j, const cpx<T>* in, cpx<T>* out,
+                      hipStream_t st);
+void launch_sub_prod(long long n, const double* a, const double* b, double* out, bool acc,
+                     hipStream_t st);
+void launch_scale(long long n, double s, const double* x, double* y, hipStream_t st);
+void launch_adj_damage(const MatTable& tab, long long N, int c, int J,
+                       const unsigned char* phase, const double* D, const double* sigma,
+                       const double* mu, double* dD, hipStream_t st);
 template <typename T>
 void launch_xfinal(cpx<T>* x, const cpx<T>* p, long long n, const KrylovCtl* ctl,
                    hipStream_t st);
