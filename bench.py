@@ -173,6 +173,96 @@ def run_driver(name="spheres64_20", e11_end=0.05, dt=0.02, max_attempts=60):
                 accepted_voxel_krylov_iters_per_s=round(N * it / wall, 1))
 
 
+def run_adjoint(ws):
+    """Forward solve and its adjoint on the 128^3 RVE (FP64): the Helmholtz
+    field 0 with a positive random source, and the mechanics at E11 = 0.004
+    with a uniform frozen damage of 0.2 in the matrix."""
+    import torch
+    from paper_2103_04770_amd import Solver, microstructure as ms
+    S, J = ws["shape"], ws["nfields"]
+    N = int(np.prod(S))
+    s = Solver(tuple(reversed(S)))
+    rng = np.random.default_rng(11)
+    ph_np = ws["phase"]
+    ell2 = torch.from_numpy(np.array([float(t["ell"][0]) ** 2 for t in ws["table"]])[ph_np]).cuda()
+    alpha = torch.from_numpy(np.abs(rng.standard_normal(S))).cuda()
+    gbar = torch.from_numpy(rng.standard_normal(S)).cuda()
+    abar = torch.zeros(S, dtype=torch.float64, device="cuda")
+    dal = torch.zeros_like(abar)
+    dl2 = torch.empty_like(abar)
+    out = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = s.helmholtz_solve(alpha, ell2, abar, tol=1e-8)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    a = s.helmholtz_adjoint(ell2, abar, gbar, dal, dl2, tol=1e-8)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["helmholtz"] = dict(forward_ms=round(1e3 * (t1 - t0), 2), adjoint_ms=round(1e3 * (t2 - t1), 2),
+                            forward_iters=f["pcg_iters"], adjoint_iters=a["pcg_iters"])
+    ph = torch.from_numpy(ph_np).cuda()
+    D = torch.from_numpy(np.where(ph_np == 0, 0.2, 0.0)[None].repeat(J, 0)).cuda().contiguous()
+    z7 = torch.zeros((7,) + S, dtype=torch.float64, device="cuda")
+    eps = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
+    sig = torch.empty_like(eps)
+    st1 = torch.empty_like(z7)
+    al = torch.empty((J,) + S, dtype=torch.float64, device="cuda")
+    tgt = ms.uniaxial_mixed(3, 4e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = s.fftg_solve(ph, ws["table"], J, D, z7, tgt, eps, sig, st1, al)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = torch.from_numpy(rng.standard_normal((6,) + S)).cuda()
+    mu = torch.empty_like(eps)
+    dD = torch.empty_like(D)
+    a = s.fftg_solve_adjoint(ph, ws["table"], J, D, z7, tgt, eps, g, mu, dD)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    out["mechanics"] = dict(forward_ms=round(1e3 * (t1 - t0), 2), adjoint_ms=round(1e3 * (t2 - t1), 2),
+                            forward_newton=f["newton_iters"], forward_cg_iters=f["cg_iters"],
+                            adjoint_cg_iters=a["cg_iters"])
+    log("[adjoint] helmholtz fwd %.1f ms / adj %.1f ms; mechanics fwd %.1f ms / adj %.1f ms" % (
+        out["helmholtz"]["forward_ms"], out["helmholtz"]["adjoint_ms"],
+        out["mechanics"]["forward_ms"], out["mechanics"]["adjoint_ms"]))
+    return out
+
+
+def run_batch(count=64, nworkers=8):
+    """One staggered increment (E11 = 1e-3) of 64 RVEs of uneven sizes
+    (edges from {32, 48, 64, 96}, particle fractions U(0.05, 0.30)), FP32-refined,
+    driven one RVE at a time and then by the batched entry point."""
+    import torch
+    from paper_2103_04770_amd import FP32_REFINED, microstructure as ms
+    from paper_2103_04770_amd.batch import RVEBatch
+    rves = ms.batch_workload(count)
+    vox = sum(int(np.prod(r["shape"])) for r in rves)
+    b = RVEBatch(rves, prec=FP32_REFINED)
+    tgt = ms.uniaxial_mixed(3, 1e-3)
+    res = {}
+    for nw in (1, nworkers):
+        b.reset()
+        t0 = time.perf_counter()
+        out = b.step(tgt, nworkers=nw, **TOLS)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        it = sum(o["cg_iters"] + o["pcg_iters"] for o in out)
+        res[nw] = dict(seconds=round(dt, 3), krylov_iters=it,
+                       voxel_krylov_iters_per_s=round(sum(
+                           int(np.prod(r["shape"])) * (o["cg_iters"] + o["pcg_iters"])
+                           for r, o in zip(rves, out)) / dt, 1),
+                       converged=sum(o["converged"] for o in out))
+    b.close()
+    log("[batch] %d RVEs, %d voxels: one at a time %.2f s, %d workers %.2f s" % (
+        count, vox, res[1]["seconds"], nworkers, res[nworkers]["seconds"]))
+    return dict(rves=count, voxels=vox, sizes=[32, 48, 64, 96], form="fp32_refined",
+                increment="E11 = 1e-3 from the virgin state", one_at_a_time=res[1],
+                batched=dict(res[nworkers], workers=nworkers),
+                speedup=round(res[1]["seconds"] / res[nworkers]["seconds"], 3))
+
+
 def cpu_baseline(ws, iters):
     """The oracle, as it stands, on a bounded sample of the same workload: the
     first Newton system at E11 = 0.005 from a uniform strain guess, `iters`
@@ -339,6 +429,8 @@ def main():
             homog_stress_rel_err_vs_fp64=err, kernels=k32)
     if not args.no_driver:
         out["adaptive_driver"] = run_driver()
+        out["adjoint"] = run_adjoint(ws)
+        out["batch"] = run_batch()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_iters)

@@ -13,6 +13,7 @@
  *   - staggered_step  : one load increment of the iterated staggered scheme
  *                       (Sec. 3.2, Algorithm 1).
  *   - fftg_drive      : variable-increment loading with cutback (Sec. 4.2).
+ *   - fftg_batch_step : staggered increments of many independent RVEs at once.
  *   - helmholtz_adjoint, fftg_solve_adjoint : gradients of the two solves by
  *                       implicit differentiation at the converged state.
  *
@@ -259,6 +260,35 @@ fftg_status fftg_drive(fftg_handle* h, const unsigned char* phase, const fftg_ph
                        double newton_tol, int newton_maxit, double stagger_tol,
                        int max_stagger_iters, fftg_drive_opts* opts, double* sigma_out,
                        fftg_drive_record* records, int max_records, int* n_records);
+
+/* ---- batches of independent RVEs ---- */
+
+typedef struct {
+  fftg_handle* h;              /* this RVE's handle: own grid, own stream */
+  const unsigned char* phase;  /* dev [N] */
+  const fftg_phase* tab;       /* host phase table */
+  int nphase, nfields;
+  double* state;               /* dev packed state (staggered_step layout), in/out */
+  fftg_macro target;           /* macro target of this increment */
+  double* sigma_out;           /* dev [c][N] out */
+  double homog_out[12];        /* out, as staggered_step */
+  fftg_stats stats;            /* out */
+  int status;                  /* out: this item's staggered_step return code */
+} fftg_batch_item;
+
+/* One staggered increment (Algorithm 1) of each of n independent RVEs.
+ * nworkers host threads take the items, largest grid first, and drive one
+ * item's handle each at a time; since every handle enqueues on its own
+ * stream, the kernels of different RVEs overlap on the GPU (a small RVE alone
+ * cannot fill the 256 compute units).  Each item gets exactly the result of
+ * staggered_step on its own.  Every item must have a distinct handle
+ * (FFTG_E_INVALID otherwise).  Returns FFTG_OK when every item converged,
+ * FFTG_NOT_CONVERGED when one did not, else the most negative item code; the
+ * per-item codes and error texts (fftg_last_error(item.h)) remain valid. */
+fftg_status fftg_batch_step(fftg_batch_item* items, int n, int nworkers,
+                            const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
+                            double newton_tol, int newton_maxit, double stagger_tol,
+                            int max_stagger_iters);
 
 /* ---- single-operator entry points (same kernels as the solvers) ---- */
 

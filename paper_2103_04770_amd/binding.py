@@ -72,6 +72,13 @@ class Stats(ct.Structure):
                     relres=self.relres, err=self.err, t_ms=list(self.t_ms))
 
 
+class BatchItem(ct.Structure):
+    _fields_ = [("h", ct.c_void_p), ("phase", ct.c_void_p), ("tab", ct.POINTER(Phase)),
+                ("nphase", ct.c_int), ("nfields", ct.c_int), ("state", ct.c_void_p),
+                ("target", Macro), ("sigma_out", ct.c_void_p), ("homog_out", ct.c_double * 12),
+                ("stats", Stats), ("status", ct.c_int)]
+
+
 def lib_path():
     return os.path.join(_PKG, "libfftg.so")
 
@@ -106,6 +113,8 @@ def load_library():
         "helmholtz_adjoint": [P, P, D, P, P, P, P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
         "fftg_solve_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, ct.POINTER(Macro), P, P, P,
                                P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
+        "fftg_batch_step": [ct.POINTER(BatchItem), I, I, ct.POINTER(KrylovOpts),
+                            ct.POINTER(KrylovOpts), D, I, D, I],
         "fftg_drive": [P, P, ct.POINTER(Phase), I, I, P, ct.POINTER(Macro),
                        ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D, I, D, I,
                        ct.POINTER(DriveOpts), P, ct.POINTER(DriveRecord), I, ct.POINTER(I)],

@@ -2,6 +2,8 @@
 // Newton and staggered drivers, and the C ABI declared in include/fftg.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -11,6 +13,7 @@
 #include <cstdint>
 #include <functional>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fftg.h"
@@ -1724,4 +1727,45 @@ fftg_status fftg_drive(fftg_handle* H, const unsigned char* phase, const fftg_ph
   });
 }
 
+
+fftg_status fftg_batch_step(fftg_batch_item* items, int n, int nworkers,
+                            const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
+                            double newton_tol, int newton_maxit, double stagger_tol,
+                            int max_stagger_iters) {
+  if (n < 0 || (n > 0 && !items) || nworkers < 1 || !cg || !pcg) return FFTG_E_INVALID;
+  // every item needs its own handle: a handle is driven by one thread at a time
+  std::vector<fftg_handle*> hs;
+  for (int i = 0; i < n; ++i) {
+    if (!items[i].h) return FFTG_E_INVALID;
+    hs.push_back(items[i].h);
+  }
+  std::sort(hs.begin(), hs.end());
+  if (std::adjacent_find(hs.begin(), hs.end()) != hs.end()) return FFTG_E_INVALID;
+  // largest RVE first (longest-processing-time order balances the workers)
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return items[a].h->g.N > items[b].h->g.N; });
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int k = next.fetch_add(1); k < n; k = next.fetch_add(1)) {
+      fftg_batch_item& it = items[order[k]];
+      it.status = staggered_step(it.h, it.phase, it.tab, it.nphase, it.nfields, it.state,
+                                 &it.target, cg, pcg, newton_tol, newton_maxit, stagger_tol,
+                                 max_stagger_iters, it.sigma_out, it.homog_out, &it.stats);
+    }
+  };
+  const int nw = std::min(nworkers, std::max(n, 1));
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; ++w) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+  fftg_status rc = FFTG_OK;
+  for (int i = 0; i < n; ++i) {
+    const int st = items[i].status;
+    if (st < 0 && (rc >= 0 || st < rc)) rc = (fftg_status)st;
+    if (st == FFTG_NOT_CONVERGED && rc == FFTG_OK) rc = FFTG_NOT_CONVERGED;
+  }
+  return rc;
+}
 }  // extern "C"

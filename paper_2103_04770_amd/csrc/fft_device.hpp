@@ -332,15 +332,17 @@ template <typename T>
 constexpr int kDotBytes = sizeof(T) == 8 ? 32768 : 16384;
 template <typename T>
 constexpr int kDotThreads = sizeof(T) == 8 ? 512 : 256;
-template <typename T, int BYTES = FFTG_TILE_BYTES>
-constexpr int fs_tile(int n) {                                          // y / z passes
-  return BYTES / (int)sizeof(cpx<T>) / n < FFT_THREADS ? BYTES / (int)sizeof(cpx<T>) / n
-                                                       : FFT_THREADS;
-}
 constexpr int pow2_floor(int v) {
   int p = 1;
   while (2 * p <= v) p *= 2;
   return p;
+}
+// lines per y / z tile: a power of two (it must divide the workgroup)
+template <typename T, int BYTES = FFTG_TILE_BYTES>
+constexpr int fs_tile(int n) {                                          // y / z passes
+  return pow2_floor(BYTES / (int)sizeof(cpx<T>) / n) < FFT_THREADS
+             ? pow2_floor(BYTES / (int)sizeof(cpx<T>) / n)
+             : FFT_THREADS;
 }
 template <typename T>
 constexpr int fs_tile_wide(int n, int nc) { return pow2_floor(kElemsWide<T> / (n * nc)); }

@@ -1135,8 +1135,16 @@ static inline int grid_for(long long n) {
       constexpr int NF = 32;        \
       __VA_ARGS__;                  \
     } break;                        \
+    case 48: {                      \
+      constexpr int NF = 48;        \
+      __VA_ARGS__;                  \
+    } break;                        \
     case 64: {                      \
       constexpr int NF = 64;        \
+      __VA_ARGS__;                  \
+    } break;                        \
+    case 96: {                      \
+      constexpr int NF = 96;        \
       __VA_ARGS__;                  \
     } break;                        \
     case 128: {                     \

@@ -227,6 +227,27 @@ def workload(name, seed=None):
     raise KeyError(name)
 
 
+def batch_workload(count=64, seed0=4000, sizes=(32, 48, 64, 96)):
+    """A batch of independent RVEs of uneven sizes: RVE b draws, from
+    numpy.random.default_rng(seed0 + b), its edge N_b uniformly from `sizes`
+    and its particle volume fraction uniformly in [0.05, 0.30]; spheres have
+    radii U(4, 8) voxels (random sequential addition with that generator's
+    next draws).  One non-local field: J2 damage matrix (ell 2), elastic
+    particles (ell 1).  Returns a list of dicts (name, shape, phase, table,
+    nfields)."""
+    out = []
+    table = [matrix_j2_damage(ell=[2.0]), particle_elastic(ell=[1.0])]
+    for b in range(count):
+        rng = np.random.default_rng(seed0 + b)
+        n = int(sizes[int(rng.integers(len(sizes)))])
+        vf = float(rng.uniform(0.05, 0.30))
+        s = int(rng.integers(2 ** 31))
+        phase, _, _ = rsa_spheres((n, n, n), s, radius_range=(4.0, 8.0), volume_fraction=vf)
+        out.append(dict(name="batch_%d_%d" % (b, n), shape=(n, n, n), phase=phase,
+                        table=[dict(t) for t in table], nfields=1, vf_target=vf))
+    return out
+
+
 def random_field(shape, seed, scale=1.0, mean=0.0):
     """Seeded normal random field (float64)."""
     rng = np.random.default_rng(seed)

@@ -52,7 +52,7 @@ def relerr(a, b):
 
 FFT_SHAPES = [(18, 12), (32, 32), (6, 64), (24, 12, 16), (8, 8, 8), (18, 24, 64), (4, 6, 96),
               (3, 9, 12), (1, 4, 8), (2, 128, 128), (128, 6, 16), (16, 256, 4), (6, 64, 256),
-              (3, 32, 128)]
+              (3, 32, 128), (48, 6, 96), (96, 4, 48), (96, 48)]
 
 
 @pytest.mark.parametrize("shape", FFT_SHAPES)
@@ -103,7 +103,8 @@ def _mixed_inputs(shape, seed, nfields=2):
     return phase, table, eps, epsp, kap, D
 
 
-@pytest.mark.parametrize("shape", [(8, 12), (6, 8, 12), (12, 12, 12), (4, 16, 128), (128, 3, 64)])
+@pytest.mark.parametrize("shape", [(8, 12), (6, 8, 12), (12, 12, 12), (4, 16, 128), (128, 3, 64),
+                                   (6, 8, 96), (48, 4, 48)])
 def test_constitutive(shape):
     say("constitutive", shape)
     s = solver(shape)
@@ -132,7 +133,8 @@ def test_constitutive(shape):
     assert relerr(host(out), refo) <= 1e-12
 
 
-@pytest.mark.parametrize("shape", [(12, 18), (8, 12, 16), (16, 16, 16), (4, 32, 128), (128, 6, 64)])
+@pytest.mark.parametrize("shape", [(12, 18), (8, 12, 16), (16, 16, 16), (4, 32, 128), (128, 6, 64),
+                                   (48, 8, 96), (96, 48)])
 def test_apply_helmholtz(shape):
     say("apply_helmholtz", shape)
     s = solver(shape)
@@ -147,7 +149,8 @@ def test_apply_helmholtz(shape):
     assert relerr(host(out), ref) <= 1e-13
 
 
-@pytest.mark.parametrize("shape", [(32, 32), (12, 18), (16, 16, 16), (24, 12, 18), (8, 16, 128)])
+@pytest.mark.parametrize("shape", [(32, 32), (12, 18), (16, 16, 16), (24, 12, 18), (8, 16, 128),
+                                   (48, 8, 96)])
 def test_helmholtz_solve(shape):
     say("helmholtz_solve", shape)
     s = solver(shape)
@@ -189,7 +192,8 @@ def _mech_case(shape, seed):
 
 
 @pytest.mark.parametrize("shape,e11", [((32, 32), 5e-3), ((16, 16, 16), 6e-3), ((12, 18, 24), 4e-3),
-                                       ((8, 16, 64), 5e-3), ((128, 32), 5e-3)])
+                                       ((8, 16, 64), 5e-3), ((128, 32), 5e-3),
+                                       ((6, 48, 96), 5e-3)])
 def test_fftg_solve(shape, e11):
     say("fftg_solve", shape)
     s = solver(shape)
