@@ -120,6 +120,13 @@ __device__ __forceinline__ int laddr(int line, int t, int ld) {
   return LINEFAST ? t * ld + line : line * ld + t;
 }
 
+// Line-contiguous layout with one pad slot after every 8 elements: the
+// radix-R Stockham writes (stride R elements across threads) and the
+// contiguous reads then fall into distinct LDS banks.  Line pitch >=
+// n + n / 8.
+__device__ __forceinline__ int paddr(int line, int t, int ld) { return line * ld + t + (t >> 3); }
+constexpr int padded_pitch(int n) { return n + n / 8 + 1; }
+
 template <typename T, int R, bool FWD, bool LINEFAST>
 __device__ __forceinline__ void stage(cpx<T>* buf, int n, int nlines, int ld, int Ns,
                                       const cpx<T>* __restrict__ tw) {
@@ -221,7 +228,8 @@ constexpr int c_radix(int n, int s) {
                                              : 3;
 }
 
-template <typename T, int R, bool FWD, bool LINEFAST, int N, int NL, int LD, int NS, int NT>
+template <typename T, int R, bool FWD, bool LINEFAST, int N, int NL, int LD, int NS, int NT,
+          bool PAD = false>
 __device__ __forceinline__ void stage_c(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
   constexpr int M = N / R;
   constexpr int TOTAL = NL * M;
@@ -235,7 +243,8 @@ __device__ __forceinline__ void stage_c(cpx<T>* buf, const cpx<T>* __restrict__ 
       const int line = LINEFAST ? b % NL : b / M;
       const int j = LINEFAST ? b / NL : b % M;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[laddr<LINEFAST>(line, j + r * M, LD)];
+      for (int r = 0; r < R; ++r)
+        v[q][r] = buf[PAD ? paddr(line, j + r * M, LD) : laddr<LINEFAST>(line, j + r * M, LD)];
     }
   }
   __syncthreads();
@@ -261,26 +270,30 @@ __device__ __forceinline__ void stage_c(cpx<T>* buf, const cpx<T>* __restrict__ 
       if (R == 8) dft8<FWD>(v[q]);
       const int o = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[laddr<LINEFAST>(line, o + r * NS, LD)] = v[q][r];
+      for (int r = 0; r < R; ++r)
+        buf[PAD ? paddr(line, o + r * NS, LD) : laddr<LINEFAST>(line, o + r * NS, LD)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int NT, int S, int NS>
+template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int NT, bool PAD, int S,
+          int NS>
 __device__ __forceinline__ void lds_fft_stages(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
   if constexpr (S < c_nst(N)) {
     constexpr int R = c_radix(N, S);
-    stage_c<T, R, FWD, LINEFAST, N, NL, LD, NS, NT>(buf, tw);
-    lds_fft_stages<T, FWD, LINEFAST, N, NL, LD, NT, S + 1, NS * R>(buf, tw);
+    stage_c<T, R, FWD, LINEFAST, N, NL, LD, NS, NT, PAD>(buf, tw);
+    lds_fft_stages<T, FWD, LINEFAST, N, NL, LD, NT, PAD, S + 1, NS * R>(buf, tw);
   }
 }
 
 // Fixed-length transform of NL lines of length N in LDS by a workgroup of NT
 // threads (same contract as lds_fft).
-template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int NT = FFT_THREADS>
+template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int NT = FFT_THREADS,
+          bool PAD = false>
 __device__ __forceinline__ void lds_fft_c(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
-  lds_fft_stages<T, FWD, LINEFAST, N, NL, LD, NT, 0, 1>(buf, tw);
+  static_assert(!PAD || (!LINEFAST && LD >= N + N / 8), "padded layout: line pitch");
+  lds_fft_stages<T, FWD, LINEFAST, N, NL, LD, NT, PAD, 0, 1>(buf, tw);
 }
 
 // LDS budgets of the fixed-length kernels (bytes).  A smaller tile leaves

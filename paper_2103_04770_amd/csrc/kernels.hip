@@ -95,22 +95,29 @@ __device__ __forceinline__ void project_point(const T q[3], cpx<T>* v) {
 // forward transform A[k] = (Z[k] + conj Z[n-k])/2, B[k] = -i (Z[k] - conj Z[n-k])/2;
 // the inverse rebuilds Z[k] = A[k] + i B[k] and Z[n-k] = conj A[k] + i conj B[k].
 
-template <typename T>
-__device__ __forceinline__ void pack_inverse(cpx<T>* buf, int p, int k, int n1, cpx<T> A,
-                                             cpx<T> B) {
+// element j of complex line p in LDS: contiguous lines of pitch ld, padded
+// (one slot after every 8 elements) when PAD
+template <bool PAD>
+__device__ __forceinline__ int xaddr(int p, int j, int ld) {
+  return PAD ? paddr(p, j, ld) : p * ld + j;
+}
+
+template <bool PAD, typename T>
+__device__ __forceinline__ void pack_inverse(cpx<T>* buf, int p, int k, int n1, int ld,
+                                             cpx<T> A, cpx<T> B) {
   if (k == 0 || 2 * k == n1) {
     A.y = T(0);
     B.y = T(0);
   }
-  buf[p * n1 + k] = mk(A.x - B.y, A.y + B.x);
-  if (k > 0 && 2 * k < n1) buf[p * n1 + (n1 - k)] = mk(A.x + B.y, B.x - A.y);
+  buf[xaddr<PAD>(p, k, ld)] = mk(A.x - B.y, A.y + B.x);
+  if (k > 0 && 2 * k < n1) buf[xaddr<PAD>(p, n1 - k, ld)] = mk(A.x + B.y, B.x - A.y);
 }
 
-template <typename T>
-__device__ __forceinline__ void unpack_forward(const cpx<T>* buf, int p, int k, int n1,
+template <bool PAD, typename T>
+__device__ __forceinline__ void unpack_forward(const cpx<T>* buf, int p, int k, int n1, int ld,
                                                cpx<T>& A, cpx<T>& B) {
-  const cpx<T> Z = buf[p * n1 + k];
-  const cpx<T> Zm = buf[p * n1 + ((n1 - k) % n1)];
+  const cpx<T> Z = buf[xaddr<PAD>(p, k, ld)];
+  const cpx<T> Zm = buf[xaddr<PAD>(p, (n1 - k) % n1, ld)];
   A = mk(T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y));
   B = mk(T(0.5) * (Z.y + Zm.y), T(0.5) * (Zm.x - Z.x));
 }
@@ -144,7 +151,7 @@ FFTG_KERNEL void k_x_r2c(Plan plan, const cpx<T>* __restrict__ tw, const T* __re
     const int p = e / n1h, k = e % n1h;
     const long long sa = s0 + p, sb = s0 + p + P;
     cpx<T> A, B;
-    unpack_forward(buf, p, k, n1, A, B);
+    unpack_forward<false>(buf, p, k, n1, n1, A, B);
     if (sa < S) out[sa * n1h + k] = A;
     if (sb < S) out[sb * n1h + k] = B;
   }
@@ -165,7 +172,7 @@ FFTG_KERNEL void k_x_c2r(Plan plan, const cpx<T>* __restrict__ tw, const cpx<T>*
     const long long sa = s0 + p, sb = s0 + p + P;
     const cpx<T> A = sa < S ? in[sa * n1h + k] : mk(T(0), T(0));
     const cpx<T> B = sb < S ? in[sb * n1h + k] : mk(T(0), T(0));
-    pack_inverse(buf, p, k, n1, A, B);
+    pack_inverse<false>(buf, p, k, n1, n1, A, B);
   }
   __syncthreads();
   if constexpr (FIX)
@@ -198,11 +205,14 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? C * fx_fused_lines<T>(NF, C) / 2 * NF : LDS_ELEMS];
+  // fixed-length path: padded line pitch (conflict-free Stockham stages)
+  constexpr int LDX = FIX ? padded_pitch(NF) : 1;
+  __shared__ cpx<T> buf[FIX ? C * fx_fused_lines<T>(NF, C) / 2 * LDX : LDS_ELEMS];
   const long long nlines = (long long)g.n2 * g.n3;
   const int NL = FIX ? fx_fused_lines<T>(NF, C) : NL_rt;
   const long long line0 = (long long)blockIdx.x * NL;
   const int n1 = FIX ? NF : g.n1, n1h = FIX ? NF / 2 + 1 : g.n1h;
+  const int ld = FIX ? LDX : n1;
   const int P = C * NL / 2;
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
     const int p = e / n1h, k = e % n1h;
@@ -210,11 +220,12 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
     const cpx<T> A = la < nlines ? w[(sa / NL) * g.Ns + la * n1h + k] : mk(T(0), T(0));
     const cpx<T> B = lb < nlines ? w[(sb / NL) * g.Ns + lb * n1h + k] : mk(T(0), T(0));
-    pack_inverse(buf, p, k, n1, A, B);
+    pack_inverse<FIX>(buf, p, k, n1, ld, A, B);
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, false, NF, C * fx_fused_lines<T>(NF, C) / 2, NF>(buf, tw);
+    lds_fft_c<T, false, false, NF, C * fx_fused_lines<T>(NF, C) / 2, LDX, FFT_THREADS, true>(buf,
+                                                                                             tw);
   else
     lds_fft<T, false, false>(buf, plan, P, n1, tw);
   T* fb = reinterpret_cast<T*>(buf);
@@ -228,7 +239,7 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
 #pragma unroll
     for (int q = 0; q < C; ++q) {
       const int s = q * NL + l;
-      slot[q] = s < P ? 2 * (s * n1 + x) : 2 * ((s - P) * n1 + x) + 1;
+      slot[q] = s < P ? 2 * xaddr<FIX>(s, x, ld) : 2 * xaddr<FIX>(s - P, x, ld) + 1;
       ev[q] = fb[slot[q]];
     }
     const T a = (T)tan[v], b = (T)tan[g.N + v];
@@ -258,7 +269,8 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, false, NF, C * fx_fused_lines<T>(NF, C) / 2, NF>(buf, tw);
+    lds_fft_c<T, true, false, NF, C * fx_fused_lines<T>(NF, C) / 2, LDX, FFT_THREADS, true>(buf,
+                                                                                            tw);
   else
     lds_fft<T, true, false>(buf, plan, P, n1, tw);
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
@@ -266,7 +278,7 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
     const int sa = p, sb = p + P;
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
     cpx<T> A, B;
-    unpack_forward(buf, p, k, n1, A, B);
+    unpack_forward<FIX>(buf, p, k, n1, ld, A, B);
     if (la < nlines) w[(sa / NL) * g.Ns + la * n1h + k] = A;
     if (lb < nlines) w[(sb / NL) * g.Ns + lb * n1h + k] = B;
   }
@@ -280,11 +292,13 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
                                 const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? ND * fx_fused_lines<T>(NF, ND) / 2 * NF : LDS_ELEMS];
+  constexpr int LDX = FIX ? padded_pitch(NF) : 1;
+  __shared__ cpx<T> buf[FIX ? ND * fx_fused_lines<T>(NF, ND) / 2 * LDX : LDS_ELEMS];
   const long long nlines = (long long)g.n2 * g.n3;
   const int NL = FIX ? fx_fused_lines<T>(NF, ND) : NL_rt;
   const long long line0 = (long long)blockIdx.x * NL;
   const int n1 = FIX ? NF : g.n1, n1h = FIX ? NF / 2 + 1 : g.n1h;
+  const int ld = FIX ? LDX : n1;
   const int P = ND * NL / 2;
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
     const int p = e / n1h, k = e % n1h;
@@ -292,11 +306,12 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
     const cpx<T> A = la < nlines ? w[(sa / NL) * g.Ns + la * n1h + k] : mk(T(0), T(0));
     const cpx<T> B = lb < nlines ? w[(sb / NL) * g.Ns + lb * n1h + k] : mk(T(0), T(0));
-    pack_inverse(buf, p, k, n1, A, B);
+    pack_inverse<FIX>(buf, p, k, n1, ld, A, B);
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, NF>(buf, tw);
+    lds_fft_c<T, false, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, LDX, FFT_THREADS, true>(
+        buf, tw);
   else
     lds_fft<T, false, false>(buf, plan, P, n1, tw);
   T* fb = reinterpret_cast<T*>(buf);
@@ -308,13 +323,14 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
 #pragma unroll
     for (int q = 0; q < ND; ++q) {
       const int s = q * NL + l;
-      const int slot = s < P ? 2 * (s * n1 + x) : 2 * ((s - P) * n1 + x) + 1;
+      const int slot = s < P ? 2 * xaddr<FIX>(s, x, ld) : 2 * xaddr<FIX>(s - P, x, ld) + 1;
       fb[slot] = fb[slot] * f;
     }
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, NF>(buf, tw);
+    lds_fft_c<T, true, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, LDX, FFT_THREADS, true>(
+        buf, tw);
   else
     lds_fft<T, true, false>(buf, plan, P, n1, tw);
   for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
@@ -322,7 +338,7 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
     const int sa = p, sb = p + P;
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
     cpx<T> A, B;
-    unpack_forward(buf, p, k, n1, A, B);
+    unpack_forward<FIX>(buf, p, k, n1, ld, A, B);
     if (la < nlines) w[(sa / NL) * g.Ns + la * n1h + k] = A;
     if (lb < nlines) w[(sb / NL) * g.Ns + lb * n1h + k] = B;
   }
