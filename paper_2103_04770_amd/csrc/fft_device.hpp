@@ -334,6 +334,11 @@ constexpr int fx_fused_lines(int n, int c) {                            // x fus
 #ifndef FFTG_WIDE_THREADS
 #define FFTG_WIDE_THREADS 512
 #endif
+#ifndef FFTG_FUSED_THREADS
+#define FFTG_FUSED_THREADS 256
+#endif
+constexpr int kFusedThreads = FFTG_FUSED_THREADS;  // fused x passes
+static_assert(kFusedThreads == 128 || kFusedThreads == 256, "x-pass workgroup size");
 constexpr int kStridedThreads = FFTG_STRIDED_THREADS;
 constexpr int kWideThreads = FFTG_WIDE_THREADS;
 static_assert((kStridedThreads == 256 || kStridedThreads == 512) &&

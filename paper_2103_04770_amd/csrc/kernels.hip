@@ -205,6 +205,7 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
+  constexpr int NT = FIX ? kFusedThreads : FFT_THREADS;
   // fixed-length path: padded line pitch (conflict-free Stockham stages)
   constexpr int LDX = FIX ? padded_pitch(NF) : 1;
   __shared__ cpx<T> buf[FIX ? C * fx_fused_lines<T>(NF, C) / 2 * LDX : LDS_ELEMS];
@@ -214,7 +215,7 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
   const int n1 = FIX ? NF : g.n1, n1h = FIX ? NF / 2 + 1 : g.n1h;
   const int ld = FIX ? LDX : n1;
   const int P = C * NL / 2;
-  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+  for (int e = threadIdx.x; e < P * n1h; e += NT) {
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
@@ -224,12 +225,12 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, false, NF, C * fx_fused_lines<T>(NF, C) / 2, LDX, FFT_THREADS, true>(buf,
+    lds_fft_c<T, false, false, NF, C * fx_fused_lines<T>(NF, C) / 2, LDX, NT, true>(buf,
                                                                                              tw);
   else
     lds_fft<T, false, false>(buf, plan, P, n1, tw);
   T* fb = reinterpret_cast<T*>(buf);
-  for (int e = threadIdx.x; e < NL * n1; e += FFT_THREADS) {
+  for (int e = threadIdx.x; e < NL * n1; e += NT) {
     const int l = e / n1, x = e % n1;
     const long long line = line0 + l;
     if (line >= nlines) continue;
@@ -269,11 +270,11 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, false, NF, C * fx_fused_lines<T>(NF, C) / 2, LDX, FFT_THREADS, true>(buf,
+    lds_fft_c<T, true, false, NF, C * fx_fused_lines<T>(NF, C) / 2, LDX, NT, true>(buf,
                                                                                             tw);
   else
     lds_fft<T, true, false>(buf, plan, P, n1, tw);
-  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+  for (int e = threadIdx.x; e < P * n1h; e += NT) {
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
@@ -292,6 +293,7 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
                                 const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
+  constexpr int NT = FIX ? kFusedThreads : FFT_THREADS;
   constexpr int LDX = FIX ? padded_pitch(NF) : 1;
   __shared__ cpx<T> buf[FIX ? ND * fx_fused_lines<T>(NF, ND) / 2 * LDX : LDS_ELEMS];
   const long long nlines = (long long)g.n2 * g.n3;
@@ -300,7 +302,7 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
   const int n1 = FIX ? NF : g.n1, n1h = FIX ? NF / 2 + 1 : g.n1h;
   const int ld = FIX ? LDX : n1;
   const int P = ND * NL / 2;
-  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+  for (int e = threadIdx.x; e < P * n1h; e += NT) {
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
@@ -310,12 +312,12 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, LDX, FFT_THREADS, true>(
+    lds_fft_c<T, false, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, LDX, NT, true>(
         buf, tw);
   else
     lds_fft<T, false, false>(buf, plan, P, n1, tw);
   T* fb = reinterpret_cast<T*>(buf);
-  for (int e = threadIdx.x; e < NL * n1; e += FFT_THREADS) {
+  for (int e = threadIdx.x; e < NL * n1; e += NT) {
     const int l = e / n1, x = e % n1;
     const long long line = line0 + l;
     if (line >= nlines) continue;
@@ -329,11 +331,11 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, LDX, FFT_THREADS, true>(
+    lds_fft_c<T, true, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, LDX, NT, true>(
         buf, tw);
   else
     lds_fft<T, true, false>(buf, plan, P, n1, tw);
-  for (int e = threadIdx.x; e < P * n1h; e += FFT_THREADS) {
+  for (int e = threadIdx.x; e < P * n1h; e += NT) {
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
@@ -1295,12 +1297,14 @@ void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cp
     if (c == 6) {
       const int NL = NF ? fx_fused_lines<T>(NF, 6) : fused_lines_rt(g.n1, 6);
       const long long nb = (nlines + NL - 1) / NL;
-      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 6>), dim3((unsigned)nb), dim3(FFT_THREADS), 0,
+      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 6>), dim3((unsigned)nb),
+                         dim3(NF ? kFusedThreads : FFT_THREADS), 0,
                          st, p, tw, g, NL, w, tan, scl, ctl);
     } else {
       const int NL = NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
       const long long nb = (nlines + NL - 1) / NL;
-      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 3>), dim3((unsigned)nb), dim3(FFT_THREADS), 0,
+      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 3>), dim3((unsigned)nb),
+                         dim3(NF ? kFusedThreads : FFT_THREADS), 0,
                          st, p, tw, g, NL, w, tan, scl, ctl);
     }
   })
@@ -1314,12 +1318,14 @@ void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* 
     if (g.ndim == 3) {
       const int NL = NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
       const long long nb = (nlines + NL - 1) / NL;
-      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 3>), dim3((unsigned)nb), dim3(FFT_THREADS), 0,
+      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 3>), dim3((unsigned)nb),
+                         dim3(NF ? kFusedThreads : FFT_THREADS), 0,
                          st, p, tw, g, NL, w, ell2, scl, ctl);
     } else {
       const int NL = NF ? fx_fused_lines<T>(NF, 2) : fused_lines_rt(g.n1, 2);
       const long long nb = (nlines + NL - 1) / NL;
-      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 2>), dim3((unsigned)nb), dim3(FFT_THREADS), 0,
+      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 2>), dim3((unsigned)nb),
+                         dim3(NF ? kFusedThreads : FFT_THREADS), 0,
                          st, p, tw, g, NL, w, ell2, scl, ctl);
     }
   })
