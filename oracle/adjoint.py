@@ -17,13 +17,16 @@ G*(sigma(eps, D) - Sigma_bar) = 0 with eps - (macro part) compatible; with
 sigma = (1 - D) sigma_eff(eps) in a damaging phase, d sigma / dD = -sigma_eff.
 Linearising, G*(K : deps) = G*(sigma_eff dD) on the admissible space V
 (compatible fluctuations plus means on the stress-controlled components),
-where A = G* K is symmetric positive definite.  For J(eps), gbar = dJ/deps:
-    mu = A^-1 G*(gbar)  (plain CG, as the Newton correction)
-    dJ/dD_j(x) = mu(x) : sigma_eff(x)   for a voxel whose phase is driven by
-                 field j (0 elsewhere),
-since dJ = gbar . deps = (G* gbar) . deps = mu . G*(sigma_eff dD) and mu lies
-in V.  K is the consistent tangent at the converged strain, recomputed from
-the state (Krylov iterates are never stored).
+where A = G* K is symmetric positive definite.  For J(eps, sigma) with
+geps = dJ/deps and gsig = dJ/dsigma (partial derivatives), the strain
+cotangent is g = geps + K gsig (K symmetric), and
+    mu = A^-1 G*(g)  (plain CG, as the Newton correction)
+    dJ/dD_j(x) = (mu(x) - gsig(x)) : sigma_eff(x)   for a voxel whose phase
+                 is driven by field j (0 elsewhere),
+since dJ = g . deps - gsig . sigma_eff dD, g . deps = (G* g) . deps =
+mu . G*(sigma_eff dD), and mu lies in V.  K is the consistent tangent at the
+converged strain, recomputed from the state (Krylov iterates are never
+stored).
 """
 from __future__ import annotations
 
@@ -59,16 +62,38 @@ def phase_length_gradient(dell2, phase, table, j):
                      for q in range(len(table))])
 
 
+def damage_adjoint(phase, table, abar, hist, gD):
+    """gabar = gD dD/dabar for the linear damage law of material.
+    damage_from_nonlocal: slope 1/(dR - dC) where dC < abar < dR below the
+    cap and abar (not the cracking history) drives D; 0 elsewhere (one-sided
+    at the kinks)."""
+    g = np.zeros(abar.shape)
+    for p, ph in enumerate(table):
+        j = ph["dfield"]
+        if j < 0 or ph["model"] == "elastic":
+            continue
+        sel = phase == p
+        a = abar[j][sel]
+        by_abar = np.ones(a.shape, bool) if ph["model"] != "elastic_cracking" else \
+            ~(hist[j][sel] > a)
+        d = (a - ph["dC"]) / (ph["dR"] - ph["dC"])
+        inside = by_abar & (d > 0.0) & (d < ph["dmax"])
+        g[j][sel] = np.where(inside, gD[j][sel] / (ph["dR"] - ph["dC"]), 0.0)
+    return g
+
+
 def mechanics_adjoint(phase, table, D, epsp_n, kappa_n, target, eps, gbar, nfields, h=1.0,
-                      scheme=spectral.ROTATED, cg_tol=1e-8, cg_maxit=5000):
-    """Returns dict(mu, dD, cg_iters) for J(eps), gbar = dJ/deps (c, *S), at the
-    converged strain eps of galerkin.fftg_solve with the same inputs."""
+                      scheme=spectral.ROTATED, cg_tol=1e-8, cg_maxit=5000, gsig=None):
+    """Returns dict(mu, dD, cg_iters) for J(eps, sigma) with gbar = dJ/deps and
+    gsig = dJ/dsigma (c, *S; None = 0), at the converged strain eps of
+    galerkin.fftg_solve with the same inputs."""
     mask = np.asarray(target[0])
     S = phase.shape
     q = spectral.projection_symbol(S, h, scheme)
     st = material.constitutive(eps, epsp_n, kappa_n, D, phase, table, nfields)
     C = st["C"]
-    b = galerkin.project(gbar, q, mask)
+    g = gbar if gsig is None else gbar + material.apply_tangent(C, gsig)
+    b = galerkin.project(g, q, mask)
     mu, it, _, _ = galerkin.cg(lambda p: galerkin.project(material.apply_tangent(C, p), q, mask),
                                b, cg_tol, cg_maxit)
     sig = st["sigma"]
@@ -80,5 +105,6 @@ def mechanics_adjoint(phase, table, D, epsp_n, kappa_n, target, eps, gbar, nfiel
         sel = phase == p
         w = 1.0 - D[j][sel]
         seff = sig[:, sel] / w[None]
-        dD[j][sel] = (mu[:, sel] * seff).sum(axis=0)
+        m = mu[:, sel] if gsig is None else mu[:, sel] - gsig[:, sel]
+        dD[j][sel] = (m * seff).sum(axis=0)
     return dict(mu=mu, dD=dD, cg_iters=it)

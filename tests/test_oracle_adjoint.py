@@ -105,3 +105,98 @@ def test_mechanics_adjoint_mixed_control_by_finite_differences():
     fd = (float((w * solve(D0 + hh * dirn)["eps"]).sum()) -
           float((w * solve(D0 - hh * dirn)["eps"]).sum())) / (2 * hh)
     assert float((r["dD"] * dirn).sum()) == pytest.approx(fd, rel=1e-5)
+
+
+def test_homogenised_stress_gradient_by_finite_differences():
+    """J = <sigma_11> (a function of eps and D through the stress) under
+    uniaxial mixed control: dJ/dD from the adjoint with the stress cotangent
+    against central differences."""
+    S = (6, 6, 8)
+    rng = np.random.default_rng(9)
+    phase = (rng.uniform(size=S) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_elastic(ell=[1.0])]
+    D0 = np.where(phase == 0, rng.uniform(0.1, 0.5, size=S), 0.0)[None]
+    z6, z = np.zeros((6,) + S), np.zeros(S)
+    tgt = ms.uniaxial_mixed(3, 6e-3)
+    N = phase.size
+    kw = dict(cg_tol=1e-13, newton_tol=1e-13, newton_maxit=60)
+
+    def J(D):
+        r = galerkin.fftg_solve(phase, table, D, z6, z, tgt, z6.copy(), **kw)
+        return float(r["sigma"][0].mean()), r
+
+    j0, base = J(D0)
+    gsig = np.zeros((6,) + S)
+    gsig[0] = 1.0 / N
+    r = adjoint.mechanics_adjoint(phase, table, D0, z6, z, tgt, base["eps"], np.zeros((6,) + S),
+                                  1, cg_tol=1e-13, gsig=gsig)
+    dirn = np.where(phase == 0, rng.standard_normal(S), 0.0)[None]
+    hh = 1e-6
+    fd = (J(D0 + hh * dirn)[0] - J(D0 - hh * dirn)[0]) / (2 * hh)
+    assert float((r["dD"] * dirn).sum()) == pytest.approx(fd, rel=1e-5)
+
+
+def _chain_case():
+    S = (6, 8, 8)
+    rng = np.random.default_rng(12)
+    phase = (rng.uniform(size=S) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.001, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    # per-voxel local source: an equivalent plastic strain field concentrated
+    # in the matrix, so that the non-local field crosses the damage onset
+    alpha = np.where(phase == 0, rng.uniform(0.0, 0.02, size=S), 0.0)
+    return S, phase, table, alpha
+
+
+def _chain_forward(S, phase, table, alpha, ells):
+    from oracle import material
+    ell2 = np.array([e * e for e in ells])[phase]
+    abar = helmholtz.helmholtz_solve(alpha, ell2, tol=1e-14, maxit=500)["abar"]
+    hist = np.zeros((1,) + S)
+    D = material.damage_from_nonlocal(phase, table, abar[None], hist)
+    z6, z = np.zeros((6,) + S), np.zeros(S)
+    tgt = ms.uniaxial_mixed(3, 4e-3)
+    m = galerkin.fftg_solve(phase, table, D, z6, z, tgt, z6.copy(), cg_tol=1e-13,
+                            newton_tol=1e-13, newton_maxit=60)
+    return dict(ell2=ell2, abar=abar, D=D, hist=hist, eps=m["eps"], sigma=m["sigma"], tgt=tgt)
+
+
+def test_one_pass_chain_gradients_by_finite_differences():
+    """J1 = <sigma_11>, J2 = <D> through alpha -> abar -> D -> (eps, sigma):
+    the adjoint chain's dJ/d ell_matrix and its derivative along a random
+    source direction against central differences."""
+    S, phase, table, alpha = _chain_case()
+    ells = [2.0, 0.5]
+    f = _chain_forward(S, phase, table, alpha, ells)
+    N = phase.size
+    z6, z = np.zeros((6,) + S), np.zeros(S)
+    assert 0.05 < (f["D"] > 0).mean() < 0.95
+
+    def grads(which):
+        if which == "stress":
+            gsig = np.zeros((6,) + S)
+            gsig[0] = 1.0 / N
+            mech = adjoint.mechanics_adjoint(phase, table, f["D"], z6, z, f["tgt"], f["eps"],
+                                             np.zeros((6,) + S), 1, cg_tol=1e-13, gsig=gsig)
+            gD = mech["dD"]
+        else:
+            gD = np.full((1,) + S, 1.0 / N)
+        ga = adjoint.damage_adjoint(phase, table, f["abar"][None], f["hist"], gD)[0]
+        h = adjoint.helmholtz_adjoint(f["abar"], ga, f["ell2"], tol=1e-14, maxit=500)
+        return h["dalpha"], adjoint.phase_length_gradient(h["dell2"], phase,
+                                                         [dict(t, ell=[e]) for t, e in
+                                                          zip(table, ells)], 0)
+
+    def J(which, a, e):
+        g = _chain_forward(S, phase, table, a, e)
+        return float(g["sigma"][0].mean()) if which == "stress" else float(g["D"].mean())
+
+    rng = np.random.default_rng(13)
+    dirn = np.where(phase == 0, rng.standard_normal(S), 0.0) * 1e-3
+    for which in ("stress", "damage"):
+        dal, dell = grads(which)
+        hh = 1e-4
+        fd_l = (J(which, alpha, [2.0 + hh, 0.5]) - J(which, alpha, [2.0 - hh, 0.5])) / (2 * hh)
+        assert dell[0] == pytest.approx(fd_l, rel=1e-4)
+        ha = 1e-3
+        fd_a = (J(which, alpha + ha * dirn, ells) - J(which, alpha - ha * dirn, ells)) / (2 * ha)
+        assert float((dal * dirn).sum()) == pytest.approx(fd_a, rel=1e-4)
