@@ -173,61 +173,47 @@ def run_driver(name="spheres64_20", e11_end=0.05, dt=0.02, max_attempts=60):
                 accepted_voxel_krylov_iters_per_s=round(N * it / wall, 1))
 
 
-def run_adjoint(ws):
-    """Forward solve and its adjoint on the 128^3 RVE (FP64): the Helmholtz
-    field 0 with a positive random source, and the mechanics at E11 = 0.004
-    with a uniform frozen damage of 0.2 in the matrix."""
+def run_adjoint():
+    """Differentiation at 128^3 on the RVE with 30 spheres of radius 14.94
+    (20%): one pass alpha -> abar -> D -> (eps, sigma) of the library's
+    autograd chain at E11 = 0.004, then the gradients of <sigma_11> and of the
+    mean damage with respect to the per-voxel source and the two per-phase
+    lengths (FP64)."""
     import torch
     from paper_2103_04770_amd import Solver, microstructure as ms
-    S, J = ws["shape"], ws["nfields"]
-    N = int(np.prod(S))
+    from paper_2103_04770_amd import autograd as ag
+    w = ms.workload("spheres30_128")
+    S = w["shape"]
     s = Solver(tuple(reversed(S)))
     rng = np.random.default_rng(11)
-    ph_np = ws["phase"]
-    ell2 = torch.from_numpy(np.array([float(t["ell"][0]) ** 2 for t in ws["table"]])[ph_np]).cuda()
-    alpha = torch.from_numpy(np.abs(rng.standard_normal(S))).cuda()
-    gbar = torch.from_numpy(rng.standard_normal(S)).cuda()
-    abar = torch.zeros(S, dtype=torch.float64, device="cuda")
-    dal = torch.zeros_like(abar)
-    dl2 = torch.empty_like(abar)
-    out = {}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f = s.helmholtz_solve(alpha, ell2, abar, tol=1e-8)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    a = s.helmholtz_adjoint(ell2, abar, gbar, dal, dl2, tol=1e-8)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    out["helmholtz"] = dict(forward_ms=round(1e3 * (t1 - t0), 2), adjoint_ms=round(1e3 * (t2 - t1), 2),
-                            forward_iters=f["pcg_iters"], adjoint_iters=a["pcg_iters"])
-    ph = torch.from_numpy(ph_np).cuda()
-    D = torch.from_numpy(np.where(ph_np == 0, 0.2, 0.0)[None].repeat(J, 0)).cuda().contiguous()
-    z7 = torch.zeros((7,) + S, dtype=torch.float64, device="cuda")
-    eps = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
-    sig = torch.empty_like(eps)
-    st1 = torch.empty_like(z7)
-    al = torch.empty((J,) + S, dtype=torch.float64, device="cuda")
+    ph = torch.from_numpy(w["phase"]).cuda()
+    # local source: an equivalent plastic strain in the matrix crossing the
+    # damage onset (eps_C = 0.03)
+    alpha = torch.from_numpy(np.where(w["phase"] == 0, rng.uniform(0.0, 0.06, size=S),
+                                      0.0)).cuda().requires_grad_(True)
+    ell = torch.tensor([float(t["ell"][0]) for t in w["table"]], dtype=torch.float64,
+                       device="cuda", requires_grad=True)
     tgt = ms.uniaxial_mixed(3, 4e-3)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f = s.fftg_solve(ph, ws["table"], J, D, z7, tgt, eps, sig, st1, al)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    g = torch.from_numpy(rng.standard_normal((6,) + S)).cuda()
-    mu = torch.empty_like(eps)
-    dD = torch.empty_like(D)
-    a = s.fftg_solve_adjoint(ph, ws["table"], J, D, z7, tgt, eps, g, mu, dD)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    out = {}
+    for which in ("sigma11", "mean_damage"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        abar, D, eps, sig = ag.one_pass(s, alpha, ell, ph, w["table"], tgt)
+        J = sig[0].mean() if which == "sigma11" else D.mean()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ga, ge = torch.autograd.grad(J, (alpha, ell))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[which] = dict(J=float(J), forward_ms=round(1e3 * (t1 - t0), 1),
+                          backward_ms=round(1e3 * (t2 - t1), 1),
+                          dJ_dell=[float(v) for v in ge.cpu()],
+                          dJ_dalpha_l2=float(torch.linalg.vector_norm(ga)))
     s.close()
-    out["mechanics"] = dict(forward_ms=round(1e3 * (t1 - t0), 2), adjoint_ms=round(1e3 * (t2 - t1), 2),
-                            forward_newton=f["newton_iters"], forward_cg_iters=f["cg_iters"],
-                            adjoint_cg_iters=a["cg_iters"])
-    log("[adjoint] helmholtz fwd %.1f ms / adj %.1f ms; mechanics fwd %.1f ms / adj %.1f ms" % (
-        out["helmholtz"]["forward_ms"], out["helmholtz"]["adjoint_ms"],
-        out["mechanics"]["forward_ms"], out["mechanics"]["adjoint_ms"]))
-    return out
+    log("[adjoint] <s11> fwd %.0f ms / bwd %.0f ms; <D> fwd %.0f ms / bwd %.0f ms" % (
+        out["sigma11"]["forward_ms"], out["sigma11"]["backward_ms"],
+        out["mean_damage"]["forward_ms"], out["mean_damage"]["backward_ms"]))
+    return dict(workload="spheres30_128", e11=0.004, **out)
 
 
 def run_batch(count=64, nworkers=8):
@@ -429,7 +415,7 @@ def main():
             homog_stress_rel_err_vs_fp64=err, kernels=k32)
     if not args.no_driver:
         out["adaptive_driver"] = run_driver()
-        out["adjoint"] = run_adjoint(ws)
+        out["adjoint"] = run_adjoint()
         out["batch"] = run_batch()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

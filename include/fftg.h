@@ -195,20 +195,43 @@ fftg_status helmholtz_adjoint(fftg_handle* h, const double* ell2, double ell2_re
 
 /* Adjoint of the mechanics solve at frozen damage (Sec. 3.2.2).  At the
  * converged strain eps of fftg_solve (same phase, tab, D, state_n, target),
- * for a scalar J with gbar = dJ/deps:
- *   mu = (G* K)^-1 G*(gbar) on the admissible space (compatible fluctuations
- *        and the means of the stress-controlled components), K the consistent
- *        tangent recomputed at eps, solved by the same CG;
- *   dD_j(x) = dJ/dD_j(x) = mu(x) : sigma(x) / (1 - D_j(x)) on voxels whose
- *        phase has a damage law driven by field j (d sigma / dD is minus the
- *        effective stress), 0 elsewhere.
- *   eps, gbar  dev [c][N];  mu dev [c][N] out;  dD dev [nfields][N] out
- *   (may be NULL when nfields = 0). */
+ * for a scalar J(eps, sigma) with partial derivatives gbar = dJ/deps and
+ * gsig = dJ/dsigma:
+ *   mu = (G* K)^-1 G*(gbar + K gsig) on the admissible space (compatible
+ *        fluctuations and the means of the stress-controlled components), K
+ *        the consistent tangent recomputed at eps, solved by the same CG;
+ *   dD_j(x) = dJ/dD_j(x) = (mu(x) - gsig(x)) : sigma(x) / (1 - D_j(x)) on
+ *        voxels whose phase has a damage law driven by field j (d sigma / dD
+ *        is minus the effective stress), 0 elsewhere.
+ *   eps, gbar  dev [c][N];  gsig dev [c][N] or NULL (= 0);  mu dev [c][N]
+ *   out;  dD dev [nfields][N] out (may be NULL when nfields = 0).
+ * For J = <sigma_11>, gsig = e_11 / N and gbar = 0. */
 fftg_status fftg_solve_adjoint(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
                                int nphase, int nfields, const double* D, const double* state_n,
                                const fftg_macro* target, const double* eps, const double* gbar,
-                               double* mu, double* dD, const fftg_krylov_opts* cg,
-                               fftg_stats* stats);
+                               const double* gsig, double* mu, double* dD,
+                               const fftg_krylov_opts* cg, fftg_stats* stats);
+
+/* Pieces of the differentiable one-pass chain alpha -> abar -> D -> (eps,
+ * sigma) (see paper_2103_04770_amd/autograd.py), all on the handle's grid.
+ *   fftg_damage        D dev [nfields][N] from abar, hist dev [nfields][N]
+ *                      (eq. non-local_damage_lemaitre; cracking phases take
+ *                      max(hist, abar)), the same law staggered_step applies
+ *   fftg_damage_adjoint gabar = gD dD/dabar: slope 1/(dR - dC) strictly inside
+ *                      (dC, dR) below the cap, where abar drives D; 0 elsewhere
+ *   fftg_ell2          ell2 dev [N] = ell_q^2 of `field` on phase q
+ *   fftg_phase_sums    out host [nphase] = sum of f dev [N] over each phase
+ *                      (dJ/d ell_q = 2 ell_q sum_q dJ/dell2) */
+fftg_status fftg_damage(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
+                        int nphase, int nfields, const double* abar, const double* hist,
+                        double* D);
+fftg_status fftg_damage_adjoint(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
+                                int nphase, int nfields, const double* abar, const double* hist,
+                                const double* gD, double* gabar);
+fftg_status fftg_ell2(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
+                      int nphase, int field, double* ell2);
+fftg_status fftg_phase_sums(fftg_handle* h, const unsigned char* phase, int nphase,
+                            const double* f, double* out);
 
 /* ---- adaptive load driver ---- */
 

@@ -1,17 +1,61 @@
-"""torch.autograd wrappers of the two solves of the staggered scheme.
+"""torch.autograd wrappers around the library's solves and their adjoints.
 
-The forward passes call helmholtz_solve / fftg_solve; the backward passes call
-the library's adjoint entry points (implicit differentiation at the converged
-state: nothing of the Krylov iterations is kept).  Every tensor is a CUDA
-float64 tensor on the solver's device, in numpy axis order.
+Forward passes call the library (helmholtz_solve, fftg_solve, fftg_damage,
+fftg_ell2); backward passes call its adjoint entry points (helmholtz_adjoint,
+fftg_solve_adjoint, fftg_damage_adjoint, fftg_phase_sums).  The solves are
+differentiated implicitly at the converged state: nothing of the Krylov
+iterations is kept.  Tensors are CUDA float64 in numpy axis order.
 
-    abar = helmholtz(solver, alpha, ell2)          d/d alpha and d/d ell2
-    eps  = mechanics(solver, D, phase, table, nfields, state_n, target)
-                                                   d/d D (frozen damage)
+    ell2     = ell2_field(solver, ell, phase, table)     d/d ell (per phase)
+    abar     = helmholtz(solver, alpha, ell2)            d/d alpha, d/d ell2
+    D        = damage(solver, abar, phase, table)        d/d abar
+    eps, sig = mechanics(solver, D, phase, table, nfields, state_n, target)
+                                                         d/d D (frozen damage)
+
+one_pass() chains them for one field: the per-voxel local source alpha (e.g.
+the local equivalent plastic strain) and the per-phase lengths give abar, the
+damage, and the strain and stress of the mechanics at that damage, so that
+torch.autograd.grad of <sigma_11> or <D> with respect to alpha and the
+lengths runs entirely through the adjoints.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
+
+
+def _with_lengths(table, ell, field):
+    tab = []
+    for q, t in enumerate(table):
+        t = dict(t)
+        e = list(t["ell"]) + [0.0] * (field + 1 - len(t["ell"]))
+        e[field] = float(ell[q])
+        t["ell"] = e
+        tab.append(t)
+    return tab
+
+
+class _Ell2(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, ell, solver, phase, table, field):
+        tab = _with_lengths(table, ell.detach().cpu().numpy(), field)
+        out = torch.empty(solver.spatial, dtype=torch.float64, device="cuda")
+        solver.fftg_ell2(phase, tab, field, out)
+        ctx.save_for_backward(ell)
+        ctx.args = (solver, phase, len(table))
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (ell,) = ctx.saved_tensors
+        solver, phase, nphase = ctx.args
+        sums = solver.fftg_phase_sums(phase, nphase, g.contiguous())
+        return (2.0 * ell * torch.from_numpy(sums).to(ell), None, None, None, None)
+
+
+def ell2_field(solver, ell, phase, table, field=0):
+    """ell2(x) = ell_q^2 on phase q, differentiable in the per-phase lengths ell."""
+    return _Ell2.apply(ell, solver, phase, table, field)
 
 
 class _Helmholtz(torch.autograd.Function):
@@ -38,6 +82,32 @@ def helmholtz(solver, alpha, ell2, tol=1e-10, maxit=2000):
     return _Helmholtz.apply(alpha, ell2, solver, tol, maxit)
 
 
+class _Damage(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, abar, solver, phase, table, hist):
+        D = torch.empty_like(abar)
+        solver.fftg_damage(phase, table, abar.shape[0], abar.contiguous(), hist, D)
+        ctx.save_for_backward(abar)
+        ctx.args = (solver, phase, table, hist)
+        return D
+
+    @staticmethod
+    def backward(ctx, gD):
+        (abar,) = ctx.saved_tensors
+        solver, phase, table, hist = ctx.args
+        ga = torch.empty_like(abar)
+        solver.fftg_damage_adjoint(phase, table, abar.shape[0], abar, hist, gD.contiguous(), ga)
+        return ga, None, None, None, None
+
+
+def damage(solver, abar, phase, table, hist=None):
+    """Damage fields [J][N] from the non-local fields abar [J][N] (the law of
+    the staggered step), differentiable in abar."""
+    if hist is None:
+        hist = torch.zeros_like(abar)
+    return _Damage.apply(abar, solver, phase, table, hist)
+
+
 class _Mechanics(torch.autograd.Function):
     @staticmethod
     def forward(ctx, D, solver, phase, table, nfields, state_n, target, eps0, opts):
@@ -49,23 +119,38 @@ class _Mechanics(torch.autograd.Function):
                           target, eps, sig, st1, alpha, **opts)
         ctx.save_for_backward(D, eps)
         ctx.args = (solver, phase, table, nfields, state_n, target, opts)
-        return eps
+        return eps, sig
 
     @staticmethod
-    def backward(ctx, geps):
+    def backward(ctx, geps, gsig):
         D, eps = ctx.saved_tensors
         solver, phase, table, nfields, state_n, target, opts = ctx.args
         mu = torch.empty_like(eps)
         dD = torch.empty_like(D)
+        geps = torch.zeros_like(eps) if geps is None else geps.contiguous()
         solver.fftg_solve_adjoint(phase, table, nfields, D.contiguous(), state_n, target, eps,
-                                  geps.contiguous(), mu, dD, cg_tol=opts.get("cg_tol", 1e-8),
-                                  cg_maxit=opts.get("cg_maxit", 5000))
+                                  geps, mu, dD, cg_tol=opts.get("cg_tol", 1e-8),
+                                  cg_maxit=opts.get("cg_maxit", 5000),
+                                  gsig=None if gsig is None else gsig.contiguous())
         return dD, None, None, None, None, None, None, None, None
 
 
 def mechanics(solver, D, phase, table, nfields, state_n, target, eps0=None, **opts):
-    """Converged strain of the mechanics solve at frozen damage D
-    (fftg_solve), differentiable in D."""
+    """(eps, sigma) of the mechanics solve at frozen damage D (fftg_solve),
+    differentiable in D."""
     if eps0 is None:
         eps0 = torch.zeros((solver.c,) + solver.spatial, dtype=torch.float64, device=D.device)
     return _Mechanics.apply(D, solver, phase, table, nfields, state_n, target, eps0, opts)
+
+
+def one_pass(solver, alpha, ell, phase, table, target, field=0, helm_tol=1e-10, **opts):
+    """alpha (local source of `field`, [N]) and per-phase lengths ell ->
+    abar, D, eps, sigma: one pass of the staggered scheme (mechanics at the
+    damage of the non-local field), differentiable in alpha and ell.  The
+    table must have one non-local field (nfields = 1)."""
+    ell2 = ell2_field(solver, ell, phase, table, field)
+    abar = helmholtz(solver, alpha, ell2, tol=helm_tol)
+    D = damage(solver, abar.unsqueeze(0), phase, table)
+    state_n = torch.zeros((7,) + solver.spatial, dtype=torch.float64, device=alpha.device)
+    eps, sig = mechanics(solver, D, phase, table, 1, state_n, target, **opts)
+    return abar, D, eps, sig

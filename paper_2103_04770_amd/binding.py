@@ -112,7 +112,11 @@ def load_library():
                            ct.POINTER(ct.c_double), ct.POINTER(Stats)],
         "helmholtz_adjoint": [P, P, D, P, P, P, P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
         "fftg_solve_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, ct.POINTER(Macro), P, P, P,
-                               P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
+                               P, P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
+        "fftg_damage": [P, P, ct.POINTER(Phase), I, I, P, P, P],
+        "fftg_damage_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, P, P],
+        "fftg_ell2": [P, P, ct.POINTER(Phase), I, I, P],
+        "fftg_phase_sums": [P, P, I, P, ct.POINTER(ct.c_double)],
         "fftg_batch_step": [ct.POINTER(BatchItem), I, I, ct.POINTER(KrylovOpts),
                             ct.POINTER(KrylovOpts), D, I, D, I],
         "fftg_drive": [P, P, ct.POINTER(Phase), I, I, P, ct.POINTER(Macro),
@@ -326,8 +330,9 @@ class Solver:
         return d
 
     def fftg_solve_adjoint(self, phase, table, nfields, D, state_n, target, eps, gbar, mu, dD,
-                           cg_tol=1e-8, cg_maxit=5000):
-        """mu <- (G* K)^-1 G*(gbar) at the converged eps; dD <- dJ/dD."""
+                           cg_tol=1e-8, cg_maxit=5000, gsig=None):
+        """mu <- (G* K)^-1 G*(gbar + K gsig) at the converged eps; dD <- dJ/dD
+        (gbar = dJ/deps, gsig = dJ/dsigma or None)."""
         f64 = self.torch.float64
         tab = phase_table(table)
         m = _macro(target)
@@ -337,12 +342,41 @@ class Solver:
             _ptr(D, f64, nfields * self.N, "D") if nfields else None,
             _ptr(state_n, f64, 7 * self.N, "state_n"), ct.byref(m),
             _ptr(eps, f64, self.c * self.N, "eps"), _ptr(gbar, f64, self.c * self.N, "gbar"),
+            _ptr(gsig, f64, self.c * self.N, "gsig") if gsig is not None else None,
             _ptr(mu, f64, self.c * self.N, "mu"),
             _ptr(dD, f64, nfields * self.N, "dD") if nfields else None,
             ct.byref(KrylovOpts(cg_tol, cg_maxit)), ct.byref(st)))
         d = st.as_dict()
         d["converged"] = ok
         return d
+
+    def fftg_damage(self, phase, table, nfields, abar, hist, D):
+        f64 = self.torch.float64
+        n = nfields * self.N
+        self._check(self.lib.fftg_damage(self.h, _ptr(phase, self.torch.uint8, self.N, "phase"),
+                                         phase_table(table), len(table), nfields,
+                                         _ptr(abar, f64, n, "abar"), _ptr(hist, f64, n, "hist"),
+                                         _ptr(D, f64, n, "D")))
+
+    def fftg_damage_adjoint(self, phase, table, nfields, abar, hist, gD, gabar):
+        f64 = self.torch.float64
+        n = nfields * self.N
+        self._check(self.lib.fftg_damage_adjoint(
+            self.h, _ptr(phase, self.torch.uint8, self.N, "phase"), phase_table(table), len(table),
+            nfields, _ptr(abar, f64, n, "abar"), _ptr(hist, f64, n, "hist"),
+            _ptr(gD, f64, n, "gD"), _ptr(gabar, f64, n, "gabar")))
+
+    def fftg_ell2(self, phase, table, field, ell2):
+        self._check(self.lib.fftg_ell2(self.h, _ptr(phase, self.torch.uint8, self.N, "phase"),
+                                       phase_table(table), len(table), int(field),
+                                       _ptr(ell2, self.torch.float64, self.N, "ell2")))
+
+    def fftg_phase_sums(self, phase, nphase, f):
+        out = (ct.c_double * nphase)()
+        self._check(self.lib.fftg_phase_sums(self.h, _ptr(phase, self.torch.uint8, self.N, "phase"),
+                                             int(nphase), _ptr(f, self.torch.float64, self.N, "f"),
+                                             out))
+        return np.array(out[:])
 
     def fftg_drive(self, phase, table, nfields, state, target_end, sigma_out, t=0.0, t_end=1.0,
                    dt=0.1, dt_min=1e-5, dt_max=1.0, grow=1.5, max_attempts=1000,

@@ -933,16 +933,22 @@ void grad_dot(fftg_handle* H, const double* a, const double* b, double* out) {
 template <typename T>
 int mech_adjoint(fftg_handle* H, const unsigned char* phase, const MatTable& tab, int J,
                  const double* D, const double* state_n, const fftg_macro* tgt,
-                 const double* eps, const double* gbar, double* mu, double* dD,
-                 const fftg_krylov_opts* cg, int& status) {
+                 const double* eps, const double* gbar, const double* gsig, double* mu,
+                 double* dD, const fftg_krylov_opts* cg, int& status) {
   const Geo& g = H->g;
   const int c = H->c;
   alloc_stagger(H, J);
   fftg::launch_constitutive<T>(tab, g, c, J, phase, eps, state_n, D, H->sig_k, H->st1, H->alph,
                                reinterpret_cast<T*>(H->tan), H->st);
   H->tan_valid = true;
-  // b = -G*(F(-gbar) - 0) = G* F(gbar)
-  fftg::launch_scale((long long)c * g.N, -1.0, gbar, H->eps_prev, H->st);
+  // strain cotangent g = gbar + K gsig; b = -G*(F(-g) - 0) = G* F(g)
+  const double* gtot = gbar;
+  if (gsig) {
+    fftg::launch_tangent_apply<T>(g.N, c, reinterpret_cast<const T*>(H->tan), gsig, gbar,
+                                  H->eps_k, H->st);
+    gtot = H->eps_k;
+  }
+  fftg::launch_scale((long long)c * g.N, -1.0, gtot, H->eps_prev, H->st);
   fwd3<double>(H, c, H->eps_prev, H->spec64);
   fftg::launch_hermitize<double>(g, c, H->spec64, H->st);
   const double zero6[6] = {0, 0, 0, 0, 0, 0};
@@ -957,7 +963,7 @@ int mech_adjoint(fftg_handle* H, const unsigned char* phase, const MatTable& tab
   if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Galerkin CG breakdown (p.Ap <= 0)"};
   if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Galerkin CG"};
   inv3<T, double>(H, c, C<T>(H->kx), mu, T(1.0 / (double)g.N), false);
-  if (J > 0) fftg::launch_adj_damage(tab, g.N, c, J, phase, D, H->sig_k, mu, dD, H->st);
+  if (J > 0) fftg::launch_adj_damage(tab, g.N, c, J, phase, D, H->sig_k, mu, gsig, dD, H->st);
   check_launch();
   sync(H);
   return it;
@@ -1558,8 +1564,8 @@ fftg_status helmholtz_adjoint(fftg_handle* H, const double* ell2, double ell2_re
 fftg_status fftg_solve_adjoint(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
                                int nphase, int nfields, const double* D, const double* state_n,
                                const fftg_macro* target, const double* eps, const double* gbar,
-                               double* mu, double* dD, const fftg_krylov_opts* cg,
-                               fftg_stats* stats) {
+                               const double* gsig, double* mu, double* dD,
+                               const fftg_krylov_opts* cg, fftg_stats* stats) {
   if (!H) return FFTG_E_INVALID;
   return run_guarded(H, [&]() -> fftg_status {
     validate_table(tab, nphase, nfields);
@@ -1570,15 +1576,74 @@ fftg_status fftg_solve_adjoint(fftg_handle* H, const unsigned char* phase, const
     auto t0 = std::chrono::steady_clock::now();
     int status = 0;
     const int it = H->fp32() ? mech_adjoint<float>(H, phase, t, nfields, D, state_n, target, eps,
-                                                   gbar, mu, dD, cg, status)
+                                                   gbar, gsig, mu, dD, cg, status)
                              : mech_adjoint<double>(H, phase, t, nfields, D, state_n, target,
-                                                    eps, gbar, mu, dD, cg, status);
+                                                    eps, gbar, gsig, mu, dD, cg, status);
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
       stats->cg_iters = it;
       stats->t_ms[1] = wall_ms(t0);
     }
     return status == 1 ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+}
+
+fftg_status fftg_damage(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
+                        int nphase, int nfields, const double* abar, const double* hist,
+                        double* D) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, nfields);
+    if (nfields < 1 || !phase || !abar || !hist || !D)
+      throw Fail{FFTG_E_INVALID, "fftg_damage: null pointer or no field"};
+    const MatTable t = make_table(tab, nphase, nfields);
+    fftg::launch_damage(t, H->g.N, nfields, phase, abar, hist, D, H->st);
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_damage_adjoint(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
+                                int nphase, int nfields, const double* abar, const double* hist,
+                                const double* gD, double* gabar) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, nfields);
+    if (nfields < 1 || !phase || !abar || !hist || !gD || !gabar)
+      throw Fail{FFTG_E_INVALID, "fftg_damage_adjoint: null pointer or no field"};
+    const MatTable t = make_table(tab, nphase, nfields);
+    fftg::launch_damage_adj(t, H->g.N, nfields, phase, abar, hist, gD, gabar, H->st);
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_ell2(fftg_handle* H, const unsigned char* phase, const fftg_phase* tab,
+                      int nphase, int field, double* ell2) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, FFTG_MAX_FIELDS);
+    if (!phase || !ell2 || field < 0 || field >= FFTG_MAX_FIELDS)
+      throw Fail{FFTG_E_INVALID, "fftg_ell2: null pointer or bad field"};
+    const MatTable t = make_table(tab, nphase, FFTG_MAX_FIELDS);
+    fftg::launch_ell2<double>(t, H->g.N, field, phase, ell2, H->st);
+    check_launch();
+    sync(H);
+    return FFTG_OK;
+  });
+}
+
+fftg_status fftg_phase_sums(fftg_handle* H, const unsigned char* phase, int nphase,
+                            const double* f, double* out) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!phase || !f || !out || nphase < 1 || nphase > FFTG_MAX_PHASES)
+      throw Fail{FFTG_E_INVALID, "fftg_phase_sums: bad arguments"};
+    read_sums(H, fftg::launch_phase_sums(H->g.N, nphase, phase, f, H->partials, H->st), nphase,
+              out);
+    return FFTG_OK;
   });
 }
 

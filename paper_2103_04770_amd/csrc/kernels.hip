@@ -992,6 +992,46 @@ FFTG_KERNEL void k_ell2(MatTable tab, long long N, int j, const unsigned char* _
   }
 }
 
+// Adjoint of k_damage: gabar_j(x) = gD_j(x) dD_j/dabar_j(x).  The law is
+// linear with slope 1 / (dR - dC) strictly inside (dC, dR) while below the
+// cap; elsewhere (and where the cracking history, not abar, drives D) the
+// derivative is 0 (one-sided at the kinks).
+FFTG_KERNEL void k_damage_adj(MatTable tab, long long N, int J,
+                              const unsigned char* __restrict__ phase,
+                              const double* __restrict__ abar, const double* __restrict__ hist,
+                              const double* __restrict__ gD, double* __restrict__ gabar) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    for (int j = 0; j < J; ++j) {
+      double gv = 0.0;
+      if (m.model != 0 && m.dfield == j) {
+        const double a = abar[(long long)j * N + v];
+        const bool by_abar = m.model != 2 || !(hist[(long long)j * N + v] > a);
+        const double d = (a - m.dC) / (m.dR - m.dC);
+        if (by_abar && d > 0.0 && d < m.dmax)
+          gv = gD[(long long)j * N + v] / (m.dR - m.dC);
+      }
+      gabar[(long long)j * N + v] = gv;
+    }
+  }
+}
+
+// Per-phase sums of a real field [N] -> partials [nphase][gridDim].
+FFTG_KERNEL void k_phase_sums(long long N, int nphase, const unsigned char* __restrict__ phase,
+                              const double* __restrict__ f, double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  for (int q = 0; q < nphase; ++q) {
+    double acc = 0.0;
+    for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+         v += (long long)gridDim.x * FFT_THREADS)
+      if (phase[v] == q) acc += f[v];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[(long long)q * gridDim.x + blockIdx.x] = s;
+  }
+}
+
 // Per-component sums of a real field [ncomp][N] -> partials [ncomp][gridDim].
 FFTG_KERNEL void k_comp_sums(long long N, int ncomp, const double* __restrict__ f,
                              double* __restrict__ partials) {
@@ -1096,6 +1136,37 @@ FFTG_KERNEL void k_grad_comp(Geo g, Sym<T> sym, int j, const cpx<T>* __restrict_
   }
 }
 
+// gout = gin + K : gsig per voxel with the compact tangent (a, b, m) of the
+// constitutive update: K:e = a tr(e) I + b dev(e) - (m.e) m (plane strain: the
+// in-plane components, e33 = 0).  gin may be null.
+template <typename TT>
+FFTG_KERNEL void k_tangent_apply(long long N, int c, const TT* __restrict__ tan,
+                                 const double* __restrict__ gsig, const double* __restrict__ gin,
+                                 double* __restrict__ gout) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const double a = (double)tan[v], b = (double)tan[N + v];
+    double m[6], e[6], o[6];
+    for (int i = 0; i < 6; ++i) m[i] = (double)tan[(2 + i) * N + v];
+    for (int i = 0; i < c; ++i) e[i] = gsig[(long long)i * N + v];
+    if (c == 6) {
+      const double tr = e[0] + e[1] + e[2];
+      const double md = m[0] * e[0] + m[1] * e[1] + m[2] * e[2] + m[3] * e[3] + m[4] * e[4] +
+                        m[5] * e[5];
+      for (int i = 0; i < 3; ++i) o[i] = a * tr + b * (e[i] - tr / 3.0) - md * m[i];
+      for (int i = 3; i < 6; ++i) o[i] = b * e[i] - md * m[i];
+    } else {
+      const double tr = e[0] + e[1];
+      const double md = m[0] * e[0] + m[1] * e[1] + m[5] * e[2];
+      o[0] = a * tr + b * (e[0] - tr / 3.0) - md * m[0];
+      o[1] = a * tr + b * (e[1] - tr / 3.0) - md * m[1];
+      o[2] = b * e[2] - md * m[5];
+    }
+    for (int i = 0; i < c; ++i)
+      gout[(long long)i * N + v] = (gin ? gin[(long long)i * N + v] : 0.0) + o[i];
+  }
+}
+
 // out = (acc ? out : 0) - a b
 FFTG_KERNEL void k_sub_prod(long long n, const double* __restrict__ a,
                             const double* __restrict__ b, double* __restrict__ out, int acc) {
@@ -1112,19 +1183,22 @@ FFTG_KERNEL void k_scale(long long n, double s, const double* __restrict__ x,
     y[v] = s * x[v];
 }
 
-// dJ/dD_j(x) = mu(x) : sigma(x) / (1 - D_j(x)) where the voxel's phase has a
-// damage law driven by field j (sigma / (1 - D) is the effective stress, and
-// d sigma / dD = -sigma_eff); 0 elsewhere.
+// dJ/dD_j(x) = (mu(x) - gsig(x)) : sigma(x) / (1 - D_j(x)) where the voxel's
+// phase has a damage law driven by field j (sigma / (1 - D) is the effective
+// stress, and d sigma / dD = -sigma_eff); 0 elsewhere.  gsig may be null.
 FFTG_KERNEL void k_adj_damage(MatTable tab, long long N, int c, int J,
                               const unsigned char* __restrict__ phase,
                               const double* __restrict__ D, const double* __restrict__ sigma,
-                              const double* __restrict__ mu, double* __restrict__ dD) {
+                              const double* __restrict__ mu, const double* __restrict__ gsig,
+                              double* __restrict__ dD) {
   for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
        v += (long long)gridDim.x * FFT_THREADS) {
     const int ph = phase[v];
     const Mat m = tab.m[ph < tab.nphase ? ph : 0];
     double dot = 0.0;
-    for (int i = 0; i < c; ++i) dot += mu[(long long)i * N + v] * sigma[(long long)i * N + v];
+    for (int i = 0; i < c; ++i)
+      dot += (mu[(long long)i * N + v] - (gsig ? gsig[(long long)i * N + v] : 0.0)) *
+             sigma[(long long)i * N + v];
     for (int j = 0; j < J; ++j) {
       double d = 0.0;
       if (m.model != 0 && m.dfield == j) d = dot / (1.0 - D[(long long)j * N + v]);
@@ -1442,11 +1516,30 @@ void launch_sub_prod(long long n, const double* a, const double* b, double* out,
 void launch_scale(long long n, double s, const double* x, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, s, x, y);
 }
+void launch_damage_adj(const MatTable& tab, long long N, int J, const unsigned char* phase,
+                       const double* abar, const double* hist, const double* gD, double* gabar,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_damage_adj, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, J, phase,
+                     abar, hist, gD, gabar);
+}
+int launch_phase_sums(long long N, int nphase, const unsigned char* phase, const double* f,
+                      double* partials, hipStream_t st) {
+  const int nb = grid_for(N);
+  hipLaunchKernelGGL(k_phase_sums, dim3(nb), dim3(FFT_THREADS), 0, st, N, nphase, phase, f,
+                     partials);
+  return nb;
+}
 void launch_adj_damage(const MatTable& tab, long long N, int c, int J,
                        const unsigned char* phase, const double* D, const double* sigma,
-                       const double* mu, double* dD, hipStream_t st) {
+                       const double* mu, const double* gsig, double* dD, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_damage, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, c, J,
-                     phase, D, sigma, mu, dD);
+                     phase, D, sigma, mu, gsig, dD);
+}
+template <typename TT>
+void launch_tangent_apply(long long N, int c, const TT* tan, const double* gsig,
+                          const double* gin, double* gout, hipStream_t st) {
+  hipLaunchKernelGGL(k_tangent_apply<TT>, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, N, c, tan,
+                     gsig, gin, gout);
 }
 
 void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st) {
@@ -1595,5 +1688,9 @@ template void launch_convert<float, double>(long long, const float*, double*, hi
 
 template void launch_grad_comp<double>(const Geo&, const Sym<double>&, int,
                                        const cpx<double>*, cpx<double>*, hipStream_t);
+template void launch_tangent_apply<double>(long long, int, const double*, const double*,
+                                           const double*, double*, hipStream_t);
+template void launch_tangent_apply<float>(long long, int, const float*, const double*,
+                                          const double*, double*, hipStream_t);
 
 }  // namespace fftg

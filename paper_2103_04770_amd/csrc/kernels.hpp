@@ -129,7 +129,15 @@ void launch_sub_prod(long long n, const double* a, const double* b, double* out,
 void launch_scale(long long n, double s, const double* x, double* y, hipStream_t st);
 void launch_adj_damage(const MatTable& tab, long long N, int c, int J,
                        const unsigned char* phase, const double* D, const double* sigma,
-                       const double* mu, double* dD, hipStream_t st);
+                       const double* mu, const double* gsig, double* dD, hipStream_t st);
+void launch_damage_adj(const MatTable& tab, long long N, int J, const unsigned char* phase,
+                       const double* abar, const double* hist, const double* gD, double* gabar,
+                       hipStream_t st);
+int launch_phase_sums(long long N, int nphase, const unsigned char* phase, const double* f,
+                      double* partials, hipStream_t st);
+template <typename TT>
+void launch_tangent_apply(long long N, int c, const TT* tan, const double* gsig,
+                          const double* gin, double* gout, hipStream_t st);
 template <typename T>
 void launch_xfinal(cpx<T>* x, const cpx<T>* p, long long n, const KrylovCtl* ctl,
                    hipStream_t st);

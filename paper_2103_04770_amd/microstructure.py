@@ -207,6 +207,16 @@ def workload(name, seed=None):
         load = [uniaxial_mixed(3, 1e-3 * (k + 1)) for k in range(50)]
         return dict(name=name, shape=shape, ndim=3, phase=phase, table=table, nfields=1,
                     load=load, max_stagger=20)
+    if name == "spheres30_128":
+        # 128^3, 30 identical spheres of radius 14.94 voxels (20%, RSA seed 5);
+        # lengths 0.05 L in the matrix and 0.001 L in the particles; one field.
+        shape = (128, 128, 128)
+        s = 5 if seed is None else seed
+        phase, _, _ = rsa_spheres(shape, s, radius=14.94, count=30)
+        table = [matrix_j2_damage(ell=[6.4]), particle_elastic(ell=[0.128])]
+        load = [uniaxial_mixed(3, 2e-3 * (k + 1)) for k in range(20)]
+        return dict(name=name, shape=shape, ndim=3, phase=phase, table=table, nfields=1,
+                    load=load, max_stagger=20)
     if name.startswith("spheres_two_fields_"):
         # n^3 (128 for the full size), 25% spheres with radii U(4, 8) (RSA,
         # seed 3; radii scaled by n/64 below 64^3);

@@ -118,11 +118,54 @@ def test_autograd_mechanics_gradient():
     s = solver(shape)
     D_t = dev(D).requires_grad_(True)
     opts = dict(cg_tol=1e-13, newton_tol=1e-13, newton_maxit=60)
-    eps = ag.mechanics(s, D_t, dev(phase, torch.uint8), table, 1, dev(np.zeros((7,) + shape)),
-                       tgt, **opts)
+    eps, _ = ag.mechanics(s, D_t, dev(phase, torch.uint8), table, 1,
+                          dev(np.zeros((7,) + shape)), tgt, **opts)
     J = (dev(w) * eps).sum()
     (gD,) = torch.autograd.grad(J, (D_t,))
     z6, z = np.zeros((6,) + shape), np.zeros(shape)
     fwd = galerkin.fftg_solve(phase, table, D, z6, z, tgt, np.zeros((c,) + shape), **opts)
     ref = adjoint.mechanics_adjoint(phase, table, D, z6, z, tgt, fwd["eps"], w, 1, cg_tol=1e-13)
     assert np.abs(gD.cpu().numpy() - ref["dD"]).max() <= 1e-8 * np.abs(ref["dD"]).max()
+
+
+def test_one_pass_chain_gradients_match_oracle():
+    """<sigma_11> and <D> through alpha -> abar -> D -> (eps, sigma) with the
+    library's autograd chain: gradients with respect to the per-voxel source
+    and the per-phase lengths against the oracle's adjoint chain."""
+    from paper_2103_04770_amd import autograd as ag
+    from tests.test_oracle_adjoint import _chain_case, _chain_forward
+    S, phase, table, alpha = _chain_case()
+    say("one-pass chain", S)
+    ells = [2.0, 0.5]
+    f = _chain_forward(S, phase, table, alpha, ells)
+    N = phase.size
+    z6, z = np.zeros((6,) + S), np.zeros(S)
+    tab = [dict(t, ell=[e]) for t, e in zip(table, ells)]
+    refs = {}
+    for which in ("stress", "damage"):
+        if which == "stress":
+            gsig = np.zeros((6,) + S)
+            gsig[0] = 1.0 / N
+            gD = adjoint.mechanics_adjoint(phase, table, f["D"], z6, z, f["tgt"], f["eps"],
+                                           np.zeros((6,) + S), 1, cg_tol=1e-13, gsig=gsig)["dD"]
+        else:
+            gD = np.full((1,) + S, 1.0 / N)
+        ga = adjoint.damage_adjoint(phase, table, f["abar"][None], f["hist"], gD)[0]
+        h = adjoint.helmholtz_adjoint(f["abar"], ga, f["ell2"], tol=1e-14, maxit=500)
+        refs[which] = (h["dalpha"], adjoint.phase_length_gradient(h["dell2"], phase, tab, 0))
+    s = solver(S)
+    ph = dev(phase, torch.uint8)
+    for which in ("stress", "damage"):
+        a_t = dev(alpha).requires_grad_(True)
+        e_t = torch.tensor(ells, dtype=torch.float64, device="cuda", requires_grad=True)
+        abar, D, eps, sig = ag.one_pass(s, a_t, e_t, ph, table, f["tgt"], helm_tol=1e-14,
+                                        cg_tol=1e-13, newton_tol=1e-13, newton_maxit=60)
+        if which == "stress":
+            assert np.abs(sig.detach().cpu().numpy() - f["sigma"]).max() <= 1e-9 * np.abs(
+                f["sigma"]).max()
+        J = sig[0].mean() if which == "stress" else D.mean()
+        ga, ge = torch.autograd.grad(J, (a_t, e_t))
+        ra, re = refs[which]
+        say(which, "dJ/dell gpu", ge.cpu().numpy(), "oracle", re)
+        assert np.abs(ga.cpu().numpy() - ra).max() <= 1e-7 * np.abs(ra).max()
+        assert np.allclose(ge.cpu().numpy(), re, rtol=1e-7, atol=1e-12 * np.abs(re).max())
