@@ -205,7 +205,7 @@ def run_adjoint():
         ga, ge = torch.autograd.grad(J, (alpha, ell))
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out[which] = dict(J=float(J), forward_ms=round(1e3 * (t1 - t0), 1),
+        out[which] = dict(J=float(J.detach()), forward_ms=round(1e3 * (t1 - t0), 1),
                           backward_ms=round(1e3 * (t2 - t1), 1),
                           dJ_dell=[float(v) for v in ge.cpu()],
                           dJ_dalpha_l2=float(torch.linalg.vector_norm(ga)))
