@@ -329,7 +329,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-driver", action="store_true",
-                    help="skip the adaptive-driver run on the 64^3 RVE")
+                    help="skip the adaptive-driver, adjoint-chain and batch runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
