@@ -13,6 +13,9 @@ computes, written to be checked against the paper by eye:
   material   J2 return mapping on the effective stress with frozen damage,
              consistent tangent, linear damage laws (Sec. 2.1.2, Sec. 2.2.3,
              appendix A.2)
+  gtn        Gurson-Tvergaard-Needleman matrix at frozen porosity and its
+             porosity update (Sec. 2.1.1, non-local Gurson extension,
+             appendix A.1)
   galerkin   FFT-Galerkin projection with mixed macroscopic control, the
              Newton + CG mechanical solver (Sec. 3.2.2)
   helmholtz  generalised Helmholtz operator in Fourier space and its
@@ -24,4 +27,4 @@ Transforms use numpy.fft on the full complex spectrum (fftn / ifftn) as a
 library primitive; Krylov solvers run in the plain real-space (mechanics) or
 full-spectrum Hermitian (Helmholtz) inner product.
 """
-from . import spectral, mandel, material, galerkin, helmholtz, staggered  # noqa: F401
+from . import spectral, mandel, gtn, material, galerkin, helmholtz, staggered  # noqa: F401

@@ -70,6 +70,8 @@ def damage_adjoint(phase, table, abar, hist, gD):
     g = np.zeros(abar.shape)
     for p, ph in enumerate(table):
         j = ph["dfield"]
+        if ph["model"] == "gtn":
+            raise NotImplementedError("adjoint of the Gurson porosity update")
         if j < 0 or ph["model"] == "elastic":
             continue
         sel = phase == p
@@ -100,6 +102,8 @@ def mechanics_adjoint(phase, table, D, epsp_n, kappa_n, target, eps, gbar, nfiel
     dD = np.zeros((nfields,) + S)
     for p, ph in enumerate(table):
         j = ph["dfield"]
+        if ph["model"] == "gtn":
+            raise NotImplementedError("adjoint of the Gurson return at frozen porosity")
         if j < 0 or ph["model"] == "elastic":
             continue
         sel = phase == p

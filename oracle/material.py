@@ -21,15 +21,23 @@ The cracking phase (an elastic phase with an equivalent-strain damage driven
 by its own non-local field) is not part of the paper: its local source is the
 Mazars equivalent strain sqrt(sum <e_i>_+^2) of the principal strains e_i.
 
+Gurson-Tvergaard-Needleman matrix ('gtn', module gtn): two non-local
+fields, j = dfield (matrix plastic strain e0) and j + 1 (trace of eps_p); the
+frozen "damage" of field j is the porosity f, which enters the yield function
+instead of a stiffness factor (sigma is not scaled by 1 - f).  The scalar
+state slot holds e0 and hist_j holds the committed porosity f_n.
+
 Local sources alpha_j (Sec. 2.2.1: alpha_q = 0 outside the phase that owns it):
   j2_damage phase with dfield = j  -> alpha_j = eps_p (equivalent plastic strain)
   cracking phase with dfield = j   -> alpha_j = Mazars equivalent strain
+  gtn phase with dfield = j        -> alpha_j = e0, alpha_{j+1} = tr(eps_p)
   everything else                  -> 0
 """
 from __future__ import annotations
 
 import numpy as np
 
+from . import gtn
 from .mandel import identity, expand_plane, PLANE_IDX
 
 SQ32 = np.sqrt(1.5)
@@ -107,22 +115,42 @@ def mazars_equivalent(eps6):
     return np.sqrt((wp * wp).sum(axis=1))
 
 
-def damage_from_nonlocal(phase, table, abar, hist):
+def damage_from_nonlocal(phase, table, abar, hist, abar_n=None):
     """Frozen damage fields D_j(x) from the non-local fields abar_j.
 
     abar, hist: (J, *S).  D_j is nonzero only in voxels of a damaging phase
-    whose driving field is j; returns (J, *S)."""
+    whose driving field is j; returns (J, *S).  A gtn phase takes the
+    porosity update from the committed fields abar_n and porosity hist_j."""
     D = np.zeros(abar.shape)
     for p, ph in enumerate(table):
         j = ph["dfield"]
         if j < 0 or ph["model"] == "elastic":
             continue
         sel = phase == p
+        if ph["model"] == "gtn":
+            an = np.zeros(abar.shape) if abar_n is None else abar_n
+            D[j][sel] = gtn.porosity_update(hist[j][sel], abar[j][sel], an[j][sel],
+                                            abar[j + 1][sel], an[j + 1][sel], ph)
+            continue
         a = abar[j][sel]
         if ph["model"] == "elastic_cracking":
             a = np.maximum(hist[j][sel], a)
         D[j][sel] = np.clip((a - ph["dC"]) / (ph["dR"] - ph["dC"]), 0.0, ph["dmax"])
     return D
+
+
+def commit_history(phase, table, abar, hist_n, abar_n):
+    """History fields at the end of an increment: max(hist, abar) (the
+    cracking law's irreversibility), except the porosity slot of a gtn phase,
+    which takes the porosity f_{n+1} of the final non-local fields."""
+    hist = np.maximum(hist_n, abar)
+    for p, ph in enumerate(table):
+        if ph["model"] == "gtn":
+            j = ph["dfield"]
+            sel = phase == p
+            hist[j][sel] = gtn.porosity_update(hist_n[j][sel], abar[j][sel], abar_n[j][sel],
+                                               abar[j + 1][sel], abar_n[j + 1][sel], ph)
+    return hist
 
 
 def constitutive(eps, epsp_n, kappa_n, D, phase, table, nfields):
@@ -158,6 +186,14 @@ def constitutive(eps, epsp_n, kappa_n, D, phase, table, nfields):
             kappa[sel] = k
             if mat["dfield"] >= 0:
                 alpha[mat["dfield"], sel] = k
+        elif mat["model"] == "gtn":
+            j = mat["dfield"]
+            s, ep, k, Cg, _ = gtn.return_map(e6[:, sel], ep_n[:, sel], k_n[sel], Dj[j, sel], mat)
+            C = 0.5 * (Cg + np.swapaxes(Cg, 0, 1))
+            epsp[:, sel] = ep
+            kappa[sel] = k
+            alpha[j, sel] = k
+            alpha[j + 1, sel] = ep[0] + ep[1] + ep[2]
         else:
             K, mu = lame(mat["E"], mat["nu"])
             Ce = elastic_tangent(K, mu)
@@ -166,7 +202,8 @@ def constitutive(eps, epsp_n, kappa_n, D, phase, table, nfields):
             if mat["model"] == "elastic_cracking" and mat["dfield"] >= 0:
                 alpha[mat["dfield"], sel] = mazars_equivalent(e6[:, sel])
         j = mat["dfield"]
-        w = 1.0 - Dj[j, sel] if (j >= 0 and mat["model"] != "elastic") else np.ones(sel.size)
+        w = 1.0 - Dj[j, sel] if (j >= 0 and mat["model"] not in ("elastic", "gtn")) \
+            else np.ones(sel.size)
         sig6[:, sel] = w[None] * s
         C6[:, :, sel] = w[None, None] * C
     if c == 3:

@@ -17,7 +17,8 @@ Per increment n -> n+1, with macro targets (mask, E, S) at t_{n+1}:
   meaning used.)  The field error is taken as 0 when the field did not
   change, and its denominator is floored at 1e-12 sqrt(N).
   commit: the state at t_{n+1} is the last iterate; the cracking history is
-  hist <- max(hist, abar).
+  hist <- max(hist, abar), and a Gurson phase stores its porosity f_{n+1}
+  of the final non-local fields in its first history slot.
 With max_iters = 1 this is the "simple staggered" variant (one pass).
 """
 from __future__ import annotations
@@ -56,7 +57,7 @@ def staggered_step(phase, table, nfields, state, target, h=1.0,
                  converged=False, mech_converged=False)
     mech = None
     for k in range(max_stagger):
-        D = material.damage_from_nonlocal(phase, table, abar_k, hist_n)
+        D = material.damage_from_nonlocal(phase, table, abar_k, hist_n, state["abar"])
         mech = galerkin.fftg_solve(phase, table, D, epsp_n, kappa_n, target, eps_k,
                                    h=h, scheme=scheme, cg_tol=cg_tol, cg_maxit=cg_maxit,
                                    newton_tol=newton_tol, newton_maxit=newton_maxit,
@@ -91,7 +92,8 @@ def staggered_step(phase, table, nfields, state, target, h=1.0,
             stats["converged"] = True
             break
     new_state = dict(eps=eps_k, epsp=mech["epsp"], kappa=mech["kappa"],
-                     hist=np.maximum(hist_n, abar_k), abar=abar_k)
+                     hist=material.commit_history(phase, table, abar_k, hist_n, state["abar"]),
+                     abar=abar_k)
     sig = mech["sigma"]
     c = sig.shape[0]
     homog = dict(sigma=np.array([sig[i].mean() for i in range(c)]),

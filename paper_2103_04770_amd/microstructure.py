@@ -12,7 +12,7 @@ periodic minimum-image distance from its centre to the inclusion centre is
 strictly less than the radius.
 
 Phase tables are lists of plain dicts with the keys
-  model   : 'elastic' | 'j2_damage' | 'elastic_cracking'
+  model   : 'elastic' | 'j2_damage' | 'elastic_cracking' | 'gtn'
   E, nu   : Young's modulus [MPa] and Poisson ratio
   sy, H   : initial yield stress and linear plastic hardening modulus [MPa]
             (flow stress sy + H * eps_p, Sec. 2.1.2 / Sec. 4)
@@ -21,6 +21,13 @@ Phase tables are lists of plain dicts with the keys
   dC, dR, dmax : damage law thresholds and cap
   ell     : list with one characteristic length per non-local field,
             in units of h (Sec. 2.2.1, per-phase lengths)
+A 'gtn' phase (Gurson-Tvergaard-Needleman matrix, Sec. 2.1.1) also carries
+  n       : exponent of the Aravas hardening law (eq. aravas)
+  q1, q2, q3, fC, fF, fN, eN, sN : yield-surface, coalescence and nucleation
+            parameters (eq. yield_gurson, effective_porosity, nucleation)
+  fu      : cap of the effective porosity (Sec. 4)
+and drives two consecutive non-local fields, dfield (matrix plastic strain)
+and dfield + 1 (trace of the plastic strain).
 Tensors are in Mandel order (11, 22, 33, sqrt2*23, sqrt2*13, sqrt2*12) in 3D
 and (11, 22, sqrt2*12) in 2D plane strain.
 """
@@ -143,6 +150,16 @@ def matrix_j2_damage(ell, dfield=0, E=70000.0, nu=0.3, sy=300.0, H=500.0,
                      dC=0.03, dR=0.2, dmax=0.99):
     return dict(model="j2_damage", E=E, nu=nu, sy=sy, H=H, dfield=dfield,
                 dC=dC, dR=dR, dmax=dmax, ell=list(ell))
+
+
+def matrix_gtn(ell, dfield=0, E=70000.0, nu=0.33, sy=200.0, n=0.1, q1=1.5, q2=1.0, q3=2.25,
+               fC=0.15, fF=0.25, fN=0.04, eN=0.1, sN=0.05, fu=0.6):
+    """Gurson matrix with the parameters of the paper's 3D examples (Sec. 4.2:
+    Al alloy, Aravas hardening with n = 0.1, f* capped at 0.6).  `ell` needs
+    a length for fields dfield and dfield + 1."""
+    return dict(model="gtn", E=E, nu=nu, sy=sy, H=0.0, dfield=dfield, dC=0.0, dR=1.0,
+                dmax=0.0, n=n, q1=q1, q2=q2, q3=q3, fC=fC, fF=fF, fN=fN, eN=eN, sN=sN,
+                fu=fu, ell=list(ell))
 
 
 def particle_elastic(ell, E=400000.0, nu=0.2):
