@@ -71,8 +71,27 @@ typedef enum { FFTG_ROTATED = 0, FFTG_SPECTRAL = 1 } fftg_scheme;
  * ELASTIC_CRACKING isotropic elasticity with sigma = (1-D) C:eps,
  *                  D = clip((max(hist, abar) - dC)/(dR - dC), 0, dmax); local
  *                  source = Mazars equivalent strain sqrt(sum <e_i>_+^2).  Not in
- *                  the paper: a second damage mechanism with its own field. */
-typedef enum { FFTG_ELASTIC = 0, FFTG_J2_DAMAGE = 1, FFTG_ELASTIC_CRACKING = 2 } fftg_model;
+ *                  the paper: a second damage mechanism with its own field.
+ * GTN              non-local Gurson-Tvergaard-Needleman matrix (Sec. 2.1.1 and
+ *                  the non-local Gurson extension; appendix A.1): yield
+ *                  (q/s0)^2 + 2 q1 f* cosh(3 q2 sm/(2 s0)) - 1 - q3 f*^2 <= 0
+ *                  (sm = tr(sigma)/3), normality, matrix plastic strain e0 from
+ *                  the plastic work sigma:d eps_p = (1 - f) s0 de0, Aravas
+ *                  hardening s0/sy = (s0/sy + 3 mu e0/sy)^n_hard, effective
+ *                  porosity f*(f) capped at fu.  It drives TWO non-local fields:
+ *                  dfield (source e0) and dfield + 1 (source tr eps_p).  Its
+ *                  "damage" is the porosity f, fixed within a mechanics solve by
+ *                  the non-local fields (backward Euler of the porosity rate,
+ *                  f_{n+1} = (f_n + A_N(ebar) d ebar + d trbar)/(1 + d trbar),
+ *                  clamped at 0); f enters the yield function, the stress is not
+ *                  scaled.  In the packed state its kappa slot holds e0 and
+ *                  hist[dfield] the committed porosity f_n (initial porosity). */
+typedef enum {
+  FFTG_ELASTIC = 0,
+  FFTG_J2_DAMAGE = 1,
+  FFTG_ELASTIC_CRACKING = 2,
+  FFTG_GTN = 3
+} fftg_model;
 
 #define FFTG_MAX_FIELDS 4
 #define FFTG_MAX_PHASES 16
@@ -92,6 +111,13 @@ typedef struct {
   int dfield;                   /* non-local field driving this phase's damage, -1 none */
   double dC, dR, dmax;          /* damage law thresholds and cap */
   double ell[FFTG_MAX_FIELDS];  /* characteristic length of field j inside this phase */
+  /* FFTG_GTN only (ignored otherwise): Aravas hardening exponent n_hard in
+   * (0, 1); yield-surface coefficients q1, q2, q3 > 0; coalescence fC < fF;
+   * nucleation fN >= 0, mean strain eN, spread sN > 0 (Chu-Needleman); cap
+   * fu of f*, with the elastic domain non-empty at f* = fu
+   * (1 + q3 fu^2 - 2 q1 fu > 0, fu < q1/q3).  sy is the initial yield stress
+   * (> 0); H is not used. */
+  double n_hard, q1, q2, q3, fC, fF, fN, eN, sN, fu;
 } fftg_phase;
 
 /* Mixed macroscopic control (Sec. 3.1): mask[k] = 1 -> component k is
@@ -133,7 +159,8 @@ const char* fftg_last_error(const fftg_handle* h);
  *   phase     dev u8 [N], phase id of every voxel (< nphase)
  *   tab       host [nphase] phase table
  *   D         dev [nfields][N] frozen damage per field (a voxel takes the field
- *             its phase names); may be NULL when nfields = 0
+ *             its phase names; for a GTN phase, D[dfield] is the frozen
+ *             porosity f); may be NULL when nfields = 0
  *   state_n   dev [7][N]: eps_p (6 Mandel comps) and kappa = eq. plastic strain
  *             at t_n
  *   target    host macro targets at t_{n+1}
@@ -205,7 +232,9 @@ fftg_status helmholtz_adjoint(fftg_handle* h, const double* ell2, double ell2_re
  *        is minus the effective stress), 0 elsewhere.
  *   eps, gbar  dev [c][N];  gsig dev [c][N] or NULL (= 0);  mu dev [c][N]
  *   out;  dD dev [nfields][N] out (may be NULL when nfields = 0).
- * For J = <sigma_11>, gsig = e_11 / N and gbar = 0. */
+ * For J = <sigma_11>, gsig = e_11 / N and gbar = 0.
+ * Tables with a GTN phase: FFTG_E_UNSUPPORTED (its stress does not depend on
+ * the frozen field through a stiffness factor). */
 fftg_status fftg_solve_adjoint(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
                                int nphase, int nfields, const double* D, const double* state_n,
                                const fftg_macro* target, const double* eps, const double* gbar,
@@ -221,7 +250,9 @@ fftg_status fftg_solve_adjoint(fftg_handle* h, const unsigned char* phase, const
  *                      (dC, dR) below the cap, where abar drives D; 0 elsewhere
  *   fftg_ell2          ell2 dev [N] = ell_q^2 of `field` on phase q
  *   fftg_phase_sums    out host [nphase] = sum of f dev [N] over each phase
- *                      (dJ/d ell_q = 2 ell_q sum_q dJ/dell2) */
+ *                      (dJ/d ell_q = 2 ell_q sum_q dJ/dell2)
+ * fftg_damage and fftg_damage_adjoint return FFTG_E_UNSUPPORTED for tables
+ * with a GTN phase (its porosity update needs the committed fields too). */
 fftg_status fftg_damage(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
                         int nphase, int nfields, const double* abar, const double* hist,
                         double* D);

@@ -142,8 +142,16 @@ def _residual_and_jacobian(x, q_tr, sm_tr, e0_n, f, fs, mat, K, mu):
 
 
 def _solve3(Jx, b):
-    """Solve Jx y = b for each voxel (Jx (3, 3, M), b (3, M))."""
-    return np.linalg.solve(np.moveaxis(Jx, -1, 0), np.moveaxis(b, -1, 0)[..., None])[..., 0].T
+    """Solve Jx y = b for each voxel (Jx (3, 3, M), b (3, M)); y = 0 where Jx
+    is singular or not finite (states far outside any converged solution,
+    e.g. inside a diverging Newton iteration)."""
+    A = np.moveaxis(Jx, -1, 0)
+    det = np.linalg.det(A)
+    ok = np.isfinite(det) & (det != 0.0) & np.isfinite(b).all(axis=0)
+    y = np.zeros(b.shape)
+    if ok.any():
+        y[:, ok] = np.linalg.solve(A[ok], np.moveaxis(b[:, ok], -1, 0)[..., None])[..., 0].T
+    return y
 
 
 def illinois(fun, a, b, fa, fb, maxit=200):

@@ -16,7 +16,8 @@ _LIB = None
 
 FP64, FP32_REFINED = 0, 1
 ROTATED, SPECTRAL = 0, 1
-_MODELS = {"elastic": 0, "j2_damage": 1, "elastic_cracking": 2}
+_MODELS = {"elastic": 0, "j2_damage": 1, "elastic_cracking": 2, "gtn": 3}
+_GTN_KEYS = ("n", "q1", "q2", "q3", "fC", "fF", "fN", "eN", "sN", "fu")
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_INVALID", -2: "E_UNSUPPORTED", -3: "E_HIP",
           -4: "E_BREAKDOWN", -5: "E_NONFINITE"}
@@ -37,7 +38,11 @@ class Phase(ct.Structure):
     _fields_ = [("model", ct.c_int), ("E", ct.c_double), ("nu", ct.c_double),
                 ("sy", ct.c_double), ("H", ct.c_double), ("dfield", ct.c_int),
                 ("dC", ct.c_double), ("dR", ct.c_double), ("dmax", ct.c_double),
-                ("ell", ct.c_double * 4)]
+                ("ell", ct.c_double * 4),
+                ("n_hard", ct.c_double), ("q1", ct.c_double), ("q2", ct.c_double),
+                ("q3", ct.c_double), ("fC", ct.c_double), ("fF", ct.c_double),
+                ("fN", ct.c_double), ("eN", ct.c_double), ("sN", ct.c_double),
+                ("fu", ct.c_double)]
 
 
 class Macro(ct.Structure):
@@ -151,6 +156,9 @@ def phase_table(table):
         ell = list(ph["ell"]) + [0.0] * (4 - len(ph["ell"]))
         for j in range(4):
             a.ell[j] = float(ell[j])
+        if ph["model"] == "gtn":
+            for k in _GTN_KEYS:
+                setattr(a, "n_hard" if k == "n" else k, float(ph[k]))
     return arr
 
 

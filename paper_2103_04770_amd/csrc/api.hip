@@ -382,9 +382,30 @@ MatTable make_table(const fftg_phase* tab, int nphase, int J) {
     m.dR = q.dR;
     m.dmax = q.dmax;
     for (int j = 0; j < FFTG_MAX_FIELDS; ++j) m.ell2[j] = q.ell[j] * q.ell[j];
+    if (q.model == FFTG_GTN) {
+      t.gtn = 1;
+      m.n = q.n_hard;
+      m.q1 = q.q1;
+      m.q2 = q.q2;
+      m.q3 = q.q3;
+      m.fC = q.fC;
+      m.fF = q.fF;
+      m.fN = q.fN;
+      m.eN = q.eN;
+      m.sN = q.sN;
+      m.fu = q.fu;
+      // porosity at which the yield surface shrinks to the origin
+      m.fV = (q.q1 + std::sqrt(std::max(q.q1 * q.q1 - q.q3, 0.0))) / q.q3;
+    }
   }
   (void)J;
   return t;
+}
+
+bool has_gtn(const fftg_phase* tab, int nphase) {
+  for (int p = 0; p < nphase; ++p)
+    if (tab[p].model == FFTG_GTN) return true;
+  return false;
 }
 
 void validate_table(const fftg_phase* tab, int nphase, int nfields) {
@@ -394,10 +415,19 @@ void validate_table(const fftg_phase* tab, int nphase, int nfields) {
     throw Fail{FFTG_E_INVALID, "nfields outside [0, 4]"};
   for (int p = 0; p < nphase; ++p) {
     const fftg_phase& q = tab[p];
-    if (q.model < 0 || q.model > 2) throw Fail{FFTG_E_INVALID, "unknown phase model"};
+    if (q.model < 0 || q.model > 3) throw Fail{FFTG_E_INVALID, "unknown phase model"};
     if (!(q.E > 0) || !(q.nu > -1.0 && q.nu < 0.5))
       throw Fail{FFTG_E_INVALID, "phase elastic constants out of range"};
     if (q.dfield >= nfields) throw Fail{FFTG_E_INVALID, "phase dfield >= nfields"};
+    if (q.model == FFTG_GTN) {
+      if (q.dfield < 0 || q.dfield + 1 >= nfields)
+        throw Fail{FFTG_E_INVALID, "a Gurson phase needs fields dfield and dfield + 1"};
+      if (!(q.sy > 0) || !(q.n_hard > 0 && q.n_hard < 1) || !(q.q1 > 0) || !(q.q2 > 0) ||
+          !(q.q3 > 0) || !(q.fC >= 0 && q.fF > q.fC) || !(q.fN >= 0) || !(q.sN > 0) ||
+          !(q.fu >= 0 && q.fu < q.q1 / q.q3 && 1.0 + q.q3 * q.fu * q.fu - 2.0 * q.q1 * q.fu > 0))
+        throw Fail{FFTG_E_INVALID, "Gurson parameters out of range"};
+      continue;
+    }
     if (q.model != FFTG_ELASTIC && q.dfield >= 0 && !(q.dR > q.dC))
       throw Fail{FFTG_E_INVALID, "damage law needs dR > dC"};
   }
@@ -1010,7 +1040,7 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
   int k = 0;
   double err = 0.0;
   for (k = 0; k < max_stagger_iters; ++k) {
-    if (J > 0) fftg::launch_damage(t, N, J, phase, H->ab_k, s_hist, H->Dj, H->st);
+    if (J > 0) fftg::launch_damage(t, N, J, phase, H->ab_k, s_hist, s_abar, H->Dj, H->st);
     HIPCHK(hipMemcpyAsync(H->eps_prev, H->eps_k, sizeof(double) * c * N,
                           hipMemcpyDeviceToDevice, H->st));
     MechOut o = H->fp32()
@@ -1084,7 +1114,7 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
   HIPCHK(hipMemcpyAsync(s_eps, H->eps_k, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
   HIPCHK(hipMemcpyAsync(s_epsp, H->st1, sizeof(double) * 7 * N, hipMemcpyDeviceToDevice, H->st));
   if (J > 0) {
-    fftg::launch_vmax((long long)J * N, s_hist, H->ab_k, H->st);
+    fftg::launch_commit_hist(t, N, J, phase, H->ab_k, s_abar, s_hist, H->st);
     HIPCHK(hipMemcpyAsync(s_abar, H->ab_k, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
                           H->st));
   }
@@ -1572,6 +1602,8 @@ fftg_status fftg_solve_adjoint(fftg_handle* H, const unsigned char* phase, const
     validate_macro(target, H->c);
     if (!phase || !state_n || !eps || !gbar || !mu || !cg || (nfields > 0 && (!D || !dD)))
       throw Fail{FFTG_E_INVALID, "fftg_solve_adjoint: null pointer"};
+    if (has_gtn(tab, nphase))
+      throw Fail{FFTG_E_UNSUPPORTED, "fftg_solve_adjoint: no adjoint of the Gurson return"};
     const MatTable t = make_table(tab, nphase, nfields);
     auto t0 = std::chrono::steady_clock::now();
     int status = 0;
@@ -1596,8 +1628,10 @@ fftg_status fftg_damage(fftg_handle* H, const unsigned char* phase, const fftg_p
     validate_table(tab, nphase, nfields);
     if (nfields < 1 || !phase || !abar || !hist || !D)
       throw Fail{FFTG_E_INVALID, "fftg_damage: null pointer or no field"};
+    if (has_gtn(tab, nphase))
+      throw Fail{FFTG_E_UNSUPPORTED, "fftg_damage: Gurson phases need the committed fields"};
     const MatTable t = make_table(tab, nphase, nfields);
-    fftg::launch_damage(t, H->g.N, nfields, phase, abar, hist, D, H->st);
+    fftg::launch_damage(t, H->g.N, nfields, phase, abar, hist, nullptr, D, H->st);
     check_launch();
     sync(H);
     return FFTG_OK;
@@ -1612,6 +1646,8 @@ fftg_status fftg_damage_adjoint(fftg_handle* H, const unsigned char* phase, cons
     validate_table(tab, nphase, nfields);
     if (nfields < 1 || !phase || !abar || !hist || !gD || !gabar)
       throw Fail{FFTG_E_INVALID, "fftg_damage_adjoint: null pointer or no field"};
+    if (has_gtn(tab, nphase))
+      throw Fail{FFTG_E_UNSUPPORTED, "fftg_damage_adjoint: no adjoint of the Gurson porosity"};
     const MatTable t = make_table(tab, nphase, nfields);
     fftg::launch_damage_adj(t, H->g.N, nfields, phase, abar, hist, gD, gabar, H->st);
     check_launch();

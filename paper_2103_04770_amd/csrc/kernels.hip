@@ -857,12 +857,233 @@ __device__ void principal3(const double e[6], double lam[3]) {
   lam[1] = 3.0 * qm - lam[0] - lam[2];
 }
 
+// ============================================================ Gurson (GTN)
+// Aravas hardening s0/sy = (s0/sy + 3 mu e0/sy)^n.  y = s0/sy is the root of
+// y - (y + c e0)^n, c = 3 mu/sy; Newton from y = 1 + c e0, where that function
+// is positive, increasing and convex, so the iterates fall monotonically onto
+// the root.  Returns s0 and ds0/de0 (differentiating the law).
+__device__ void gtn_flow(const Mat& m, double e0, double& s0, double& h) {
+  const double ce = 3.0 * m.mu / m.sy * e0;
+  double y = 1.0 + ce;
+  for (int it = 0; it < 60; ++it) {
+    const double z = y + ce;
+    const double zn = pow(z, m.n);
+    const double step = (y - zn) / (1.0 - m.n * zn / z);
+    y -= step;
+    if (fabs(step) <= 1e-15 * y) break;
+  }
+  const double zn1 = m.n * pow(y + ce, m.n - 1.0);
+  s0 = m.sy * y;
+  h = 3.0 * m.mu * zn1 / (1.0 - zn1);
+}
+
+// Effective porosity: f below fC, linear from fC to fV on [fC, fF), fV beyond;
+// capped at fu.
+__device__ double gtn_fstar(const Mat& m, double f) {
+  const double fs =
+      f < m.fC ? f : (f < m.fF ? m.fC + (m.fV - m.fC) / (m.fF - m.fC) * (f - m.fC) : m.fV);
+  return fs < m.fu ? fs : m.fu;
+}
+
+// Yield function in the Mises stress q and the mean stress sm.
+__device__ double gtn_phi(const Mat& m, double q, double sm, double s0, double fs) {
+  const double r = q / s0;
+  return r * r + 2.0 * m.q1 * fs * cosh(1.5 * m.q2 * sm / s0) - (1.0 + m.q3 * fs * fs);
+}
+
+// Porosity at the end of the increment from the non-local fields e (matrix
+// plastic strain) and t (trace of the plastic strain) at n+1 and n: backward
+// Euler of the non-local porosity rate, Chu-Needleman nucleation taken at the
+// end-of-step e; clamped at 0.
+__device__ double gtn_porosity(const Mat& m, double fn, double e, double en, double t,
+                               double tn) {
+  const double z = (e - m.eN) / m.sN;
+  const double An = m.fN / (m.sN * 2.5066282746310002) * exp(-0.5 * z * z);
+  const double dt = t - tn;
+  const double f = (fn + An * (e - en) + dt) / (1.0 + dt);
+  return f > 0.0 ? f : 0.0;
+}
+
+// Root of fun on the bracket [a, b] (fa fb <= 0): regula falsi with the
+// Illinois modification (Dowell & Jarratt 1971), bisecting whenever the
+// secant point leaves the bracket; stops at an exact zero or a bracket a few
+// ulps wide.
+template <typename F>
+__device__ double bracket_root(F fun, double a, double b, double fa, double fb) {
+  if (fb == 0.0) return b;
+  if (fa == 0.0 || a == b) return a;
+  bool kept_a = false;  // the previous step kept a (replaced b)
+  for (int it = 0; it < 200; ++it) {
+    const double den = fb - fa;
+    double c = den != 0.0 ? b - fb * (b - a) / den : 0.5 * (a + b);
+    if (!(c > fmin(a, b) && c < fmax(a, b))) c = 0.5 * (a + b);
+    const double fc = fun(c);
+    if (fc == 0.0) return c;
+    if ((fc > 0.0) == (fb > 0.0)) {
+      if (kept_a) fa *= 0.5;
+      kept_a = true;
+    } else {
+      a = b;
+      fa = fb;
+      kept_a = false;
+    }
+    b = c;
+    fb = fc;
+    if (fabs(b - a) <= 8.881784197001252e-16 * fmax(fabs(b), 1e-300)) return b;
+  }
+  return b;
+}
+
+// Return onto the yield surface of flow stress s0 with fixed f*: the point
+// (q(sm), sm) of the surface where the plastic strain increment
+// u N + v I/3, u = (q_tr - q)/(3 mu), v = (sm_tr - sm)/K, is normal to it.
+// Outside the surface the normality residual changes sign between sm = 0 and
+// sm_tr (clamped to the apex |sm| = acosh((1 + q3 f*^2)/(2 q1 f*))/kap, where
+// q = 0); a surface that contains the trial point returns it unchanged.
+__device__ void gtn_project(const Mat& m, double q_tr, double sm_tr, double s0, double fs,
+                            double& q, double& sm) {
+  if (gtn_phi(m, q_tr, sm_tr, s0, fs) <= 0.0) {
+    q = q_tr;
+    sm = sm_tr;
+    return;
+  }
+  const double kap = 1.5 * m.q2 / s0;
+  const double b2 = 2.0 * m.q1 * fs, a1 = 1.0 + m.q3 * fs * fs;
+  const double apex = b2 > 0.0 ? acosh(fmax(a1 / b2, 1.0)) / kap : INFINITY;
+  const double K = m.K, mu3 = 3.0 * m.mu, is02 = 2.0 / (s0 * s0);
+  auto qsurf = [=](double x) {
+    const double g = a1 - b2 * cosh(kap * x);
+    return g > 0.0 ? s0 * sqrt(g) : 0.0;
+  };
+  auto gfun = [=](double x) {
+    const double qs = qsurf(x);
+    return (q_tr - qs) / mu3 * b2 * kap * sinh(kap * x) - (sm_tr - x) / K * qs * is02;
+  };
+  const bool clamped = fabs(sm_tr) >= apex;
+  const double end = clamped ? copysign(apex, sm_tr) : sm_tr;
+  const double fend = clamped ? q_tr / mu3 * b2 * kap * sinh(kap * end) : gfun(end);
+  sm = bracket_root(gfun, 0.0, end, gfun(0.0), fend);
+  q = (clamped && sm == end) ? 0.0 : qsurf(sm);
+}
+
+// Backward-Euler Gurson update at frozen porosity f for one voxel.  The
+// plastic strain increment is u N + v I/3 (N = 3 s_tr/(2 q_tr)), the matrix
+// plastic strain grows by w with (1 - f) s0(e0_n + w) w = q u + sm v (plastic
+// work).  For a given w the stress is the normal return onto the surface of
+// s0(e0_n + w); the work residual is negative at w = 0 and non-negative at
+// w_hi = (q u + sm v)|_{w=0} / ((1 - f) s0(e0_n)).  The compact tangent
+// [a, b, m] (K:e = a tr(e) I + b dev(e) - (m.e) m) is the consistent one from
+// the linearised local equations
+//   F1 = s0 (u dphi/dsm - v dphi/dq), F2 = phi, F3 = (1 - f) w - (q u + sm v)/s0
+// in (q_tr, sm_tr): with A_q = du/dq_tr, B_q = du/dsm_tr, A_v = dv/dq_tr,
+// B_v = dv/dsm_tr and theta = q/q_tr,
+//   K_t = 2 mu theta I_dev + K (1 - K B_v) I(x)I
+//         + 4 mu/3 (1 - 3 mu A_q - theta) N(x)N - mu K (A_v + B_q)(N(x)I + I(x)N)
+// (symmetrised), written as a I(x)I + b I_dev - m(x)m with m = alpha N + beta I.
+// Where the N(x)N coefficient is not negative (trial stress many times the
+// flow stress), or the volumetric-deviatoric coupling would need an
+// ill-conditioned beta, the tangent drops those terms: Newton then converges
+// more slowly to the same solution.
+__device__ void gtn_update(const Mat& m, const double e[6], double ep[6], double& e0,
+                           double f, double s[6], double& ta, double& tb, double tm[6]) {
+  const double K = m.K, mu = m.mu;
+  double ee[6];
+  for (int i = 0; i < 6; ++i) ee[i] = e[i] - ep[i];
+  const double tr = ee[0] + ee[1] + ee[2];
+  double st[6], ss = 0.0;
+  for (int i = 0; i < 6; ++i) {
+    st[i] = 2.0 * mu * (ee[i] - (i < 3 ? tr / 3.0 : 0.0));
+    ss += st[i] * st[i];
+  }
+  const double q_tr = sqrt(1.5 * ss), sm_tr = K * tr;
+  const double fs = gtn_fstar(m, f);
+  double s0n, hn;
+  gtn_flow(m, e0, s0n, hn);
+  ta = K;
+  tb = 2.0 * mu;
+  for (int i = 0; i < 6; ++i) tm[i] = 0.0;
+  if (!(gtn_phi(m, q_tr, sm_tr, s0n, fs) > 0.0)) {
+    for (int i = 0; i < 6; ++i) s[i] = st[i] + (i < 3 ? sm_tr : 0.0);
+    return;
+  }
+  const double e0n = e0, w1f = 1.0 - f;
+  auto work = [&](double w) {
+    double s0, h, q, sm;
+    gtn_flow(m, e0n + w, s0, h);
+    gtn_project(m, q_tr, sm_tr, s0, fs, q, sm);
+    return w1f * s0 * w - (q * (q_tr - q) / (3.0 * mu) + sm * (sm_tr - sm) / K);
+  };
+  const double f0 = work(0.0);
+  const double whi = -f0 / (w1f * s0n);
+  const double w = bracket_root(work, 0.0, whi, f0, work(whi));
+  double s0, h, q, sm;
+  gtn_flow(m, e0n + w, s0, h);
+  gtn_project(m, q_tr, sm_tr, s0, fs, q, sm);
+  const double u = (q_tr - q) / (3.0 * mu), v = (sm_tr - sm) / K;
+  double N[6];
+  for (int i = 0; i < 6; ++i) N[i] = q_tr > 0.0 ? 1.5 * st[i] / q_tr : 0.0;
+  for (int i = 0; i < 6; ++i) {
+    ep[i] += u * N[i] + (i < 3 ? v / 3.0 : 0.0);
+    s[i] = st[i] - 2.0 * mu * u * N[i] + (i < 3 ? sm : 0.0);
+  }
+  e0 = e0n + w;
+  // local Jacobian dF/d(u, v, w) and dF/d(q_tr, sm_tr) at the solution
+  const double q1 = m.q1, q2 = m.q2;
+  const double t = 1.5 * q2 * sm / s0, tq = 1.5 * q2 / s0;
+  const double sh = sinh(t), ch = cosh(t), A = 3.0 * q1 * q2 * fs;
+  // rows: partials in (u, v, w) held directly, then q, sm, s0
+  const double d[3][6] = {
+      {A * sh, -2.0 * q / s0, 0.0, -2.0 * v / s0, A * u * ch * tq,
+       -A * u * ch * t / s0 + 2.0 * v * q / (s0 * s0)},
+      {0.0, 0.0, 0.0, 2.0 * q / (s0 * s0), 2.0 * q1 * fs * sh * tq,
+       -2.0 * q * q / (s0 * s0 * s0) - 2.0 * q1 * fs * sh * t / s0},
+      {-q / s0, -sm / s0, w1f, -u / s0, -v / s0, (q * u + sm * v) / (s0 * s0)}};
+  double J[3][3], R[3][2];
+  for (int i = 0; i < 3; ++i) {
+    J[i][0] = d[i][0] - 3.0 * mu * d[i][3];
+    J[i][1] = d[i][1] - K * d[i][4];
+    J[i][2] = d[i][2] + h * d[i][5];
+    R[i][0] = -d[i][3];
+    R[i][1] = -d[i][4];
+  }
+  // X = J^-1 R by cofactors (rows u, v, w; columns q_tr, sm_tr)
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  const double inv[2][3] = {
+      {c00 / det, (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det,
+       (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det},
+      {c01 / det, (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det,
+       (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det}};
+  double X[2][2];  // X[0] = (A_q, B_q), X[1] = (A_v, B_v)
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 2; ++k)
+      X[r][k] = inv[r][0] * R[0][k] + inv[r][1] * R[1][k] + inv[r][2] * R[2][k];
+  const double th = q_tr > 0.0 ? q / q_tr : 1.0;
+  const double Avol = K * (1.0 - K * X[1][1]);
+  const double Cnn = 4.0 * mu / 3.0 * (1.0 - 3.0 * mu * X[0][0] - th);
+  const double Cni = -mu * K * (X[1][0] + X[0][1]);
+  tb = 2.0 * mu * th;
+  ta = Avol;
+  if (Cnn < 0.0 && isfinite(det) && det != 0.0) {
+    const double al = sqrt(-Cnn);
+    double be = -Cni / al;
+    if (!(be * be <= 1e3 * Avol)) be = 0.0;
+    ta = Avol + be * be;
+    for (int i = 0; i < 6; ++i) tm[i] = al * N[i] + (i < 3 ? be : 0.0);
+  }
+}
+
 // Per voxel: backward-Euler J2 radial return on the effective stress with
 // linear hardening, frozen damage, sigma = (1-D) sigma_eff, compact consistent
 // tangent (1-D){K, 2 mu theta, 2 mu theta_bar, n} stored as
 // [a, b, m0..m5] with K:e = a tr(e) I + b dev(e) - (m.e) m, m = sqrt(c) n;
-// local sources per field.  Elastic phases: sigma = (1-D) C:e.
-template <typename TT>
+// local sources per field.  Elastic phases: sigma = (1-D) C:e.  With GTN set,
+// Gurson phases take gtn_update at the frozen porosity D[dfield] (no stress
+// scaling) and feed fields dfield (matrix plastic strain) and dfield + 1
+// (trace of the plastic strain).
+template <typename TT, bool GTN>
 FFTG_KERNEL void k_constitutive(MatTable tab, Geo g, int c, int J,
                                 const unsigned char* __restrict__ phase,
                                 const double* __restrict__ eps, const double* __restrict__ st_n,
@@ -891,7 +1112,11 @@ FFTG_KERNEL void k_constitutive(MatTable tab, Geo g, int c, int J,
     double kap = st_n[6 * N + v];
     const double K = m.K, mu = m.mu;
     double s[6], tb = 2.0 * mu, tc = 0.0, nv[6] = {0, 0, 0, 0, 0, 0};
-    if (m.model == 1) {
+    double ta_g = 0.0, tm_g[6];
+    const bool gtn = GTN && m.model == 3;
+    if (gtn) {
+      gtn_update(m, e, ep, kap, D[(long long)m.dfield * N + v], s, ta_g, tb, tm_g);
+    } else if (m.model == 1) {
       double ee[6];
       for (int i = 0; i < 6; ++i) ee[i] = e[i] - ep[i];
       const double tr = ee[0] + ee[1] + ee[2];
@@ -924,7 +1149,8 @@ FFTG_KERNEL void k_constitutive(MatTable tab, Geo g, int c, int J,
       for (int i = 0; i < 3; ++i) s[i] += (K - 2.0 * mu / 3.0) * tr;
     }
     double dmg = 0.0;
-    if (m.model != 0 && m.dfield >= 0 && m.dfield < J) dmg = D[(long long)m.dfield * N + v];
+    if (!gtn && m.model != 0 && m.dfield >= 0 && m.dfield < J)
+      dmg = D[(long long)m.dfield * N + v];
     const double w1 = 1.0 - dmg;
     if (c == 6) {
       for (int i = 0; i < 6; ++i) sigma[i * N + v] = w1 * s[i];
@@ -935,13 +1161,22 @@ FFTG_KERNEL void k_constitutive(MatTable tab, Geo g, int c, int J,
     }
     for (int i = 0; i < 6; ++i) st_np1[i * N + v] = ep[i];
     st_np1[6 * N + v] = kap;
-    tan[v] = (TT)(w1 * K);
-    tan[N + v] = (TT)(w1 * tb);
-    const double sc = sqrt(w1 * tc);
-    for (int i = 0; i < 6; ++i) tan[(2 + i) * N + v] = (TT)(sc * nv[i]);
+    if (gtn) {
+      tan[v] = (TT)ta_g;
+      tan[N + v] = (TT)tb;
+      for (int i = 0; i < 6; ++i) tan[(2 + i) * N + v] = (TT)tm_g[i];
+    } else {
+      tan[v] = (TT)(w1 * K);
+      tan[N + v] = (TT)(w1 * tb);
+      const double sc = sqrt(w1 * tc);
+      for (int i = 0; i < 6; ++i) tan[(2 + i) * N + v] = (TT)(sc * nv[i]);
+    }
     for (int j = 0; j < J; ++j) {
       double a = 0.0;
-      if (j == m.dfield) {
+      if (gtn) {
+        if (j == m.dfield) a = kap;
+        else if (j == m.dfield + 1) a = ep[0] + ep[1] + ep[2];
+      } else if (j == m.dfield) {
         if (m.model == 1) {
           a = kap;
         } else if (m.model == 2) {
@@ -958,17 +1193,24 @@ FFTG_KERNEL void k_constitutive(MatTable tab, Geo g, int c, int J,
   }
 }
 
-// D_j(x) from the non-local fields (damage laws of the phase models).
+// D_j(x) from the non-local fields (damage laws of the phase models).  A
+// Gurson phase takes the porosity f_{n+1} from the fields abar (n+1) and
+// abar_n (n) of its two fields and the committed porosity hist[dfield].
 FFTG_KERNEL void k_damage(MatTable tab, long long N, int J, const unsigned char* __restrict__ phase,
                           const double* __restrict__ abar, const double* __restrict__ hist,
-                          double* __restrict__ D) {
+                          const double* __restrict__ abar_n, double* __restrict__ D) {
   for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
        v += (long long)gridDim.x * FFT_THREADS) {
     const int ph = phase[v];
     const Mat m = tab.m[ph < tab.nphase ? ph : 0];
     for (int j = 0; j < J; ++j) {
       double d = 0.0;
-      if (m.model != 0 && m.dfield == j) {
+      if (m.model == 3) {
+        if (j == m.dfield) {
+          const long long i0 = (long long)j * N + v, i1 = i0 + N;
+          d = gtn_porosity(m, hist[i0], abar[i0], abar_n[i0], abar[i1], abar_n[i1]);
+        }
+      } else if (m.model != 0 && m.dfield == j) {
         double a = abar[(long long)j * N + v];
         if (m.model == 2) {
           const double hv = hist[(long long)j * N + v];
@@ -978,6 +1220,30 @@ FFTG_KERNEL void k_damage(MatTable tab, long long N, int J, const unsigned char*
         d = d < 0.0 ? 0.0 : (d > m.dmax ? m.dmax : d);
       }
       D[(long long)j * N + v] = d;
+    }
+  }
+}
+
+// End of an increment: hist <- max(hist, abar) (cracking irreversibility),
+// except the porosity slot of a Gurson phase, which takes f_{n+1} of the final
+// fields (read before it is overwritten: the same element).
+FFTG_KERNEL void k_commit_hist(MatTable tab, long long N, int J,
+                               const unsigned char* __restrict__ phase,
+                               const double* __restrict__ abar, const double* __restrict__ abar_n,
+                               double* __restrict__ hist) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    for (int j = 0; j < J; ++j) {
+      const long long i0 = (long long)j * N + v;
+      if (m.model == 3 && j == m.dfield) {
+        const long long i1 = i0 + N;
+        hist[i0] = gtn_porosity(m, hist[i0], abar[i0], abar_n[i0], abar[i1], abar_n[i1]);
+      } else {
+        const double a = abar[i0];
+        if (a > hist[i0]) hist[i0] = a;
+      }
     }
   }
 }
@@ -1576,14 +1842,25 @@ void launch_constitutive(const MatTable& tab, const Geo& g, int c, int J,
                          const unsigned char* phase, const double* eps, const double* st_n,
                          const double* D, double* sigma, double* st_np1, double* alpha, TT* tan,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_constitutive<TT>, dim3(grid_for(g.N)), dim3(FFT_THREADS), 0, st, tab, g, c,
-                     J, phase, eps, st_n, D, sigma, st_np1, alpha, tan);
+  if (tab.gtn)
+    hipLaunchKernelGGL((k_constitutive<TT, true>), dim3(grid_for(g.N)), dim3(FFT_THREADS), 0, st,
+                       tab, g, c, J, phase, eps, st_n, D, sigma, st_np1, alpha, tan);
+  else
+    hipLaunchKernelGGL((k_constitutive<TT, false>), dim3(grid_for(g.N)), dim3(FFT_THREADS), 0, st,
+                       tab, g, c, J, phase, eps, st_n, D, sigma, st_np1, alpha, tan);
 }
 
 void launch_damage(const MatTable& tab, long long N, int J, const unsigned char* phase,
-                   const double* abar, const double* hist, double* D, hipStream_t st) {
+                   const double* abar, const double* hist, const double* abar_n, double* D,
+                   hipStream_t st) {
   hipLaunchKernelGGL(k_damage, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, J, phase, abar,
-                     hist, D);
+                     hist, abar_n, D);
+}
+
+void launch_commit_hist(const MatTable& tab, long long N, int J, const unsigned char* phase,
+                        const double* abar, const double* abar_n, double* hist, hipStream_t st) {
+  hipLaunchKernelGGL(k_commit_hist, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, J, phase,
+                     abar, abar_n, hist);
 }
 
 template <typename TL>

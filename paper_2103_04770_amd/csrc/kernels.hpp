@@ -49,14 +49,17 @@ struct KrylovCtl {
 constexpr int STAGNATION_WINDOW = 100;
 
 struct Mat {
-  int model;  // 0 elastic, 1 J2 damage, 2 elastic cracking
+  int model;  // 0 elastic, 1 J2 damage, 2 elastic cracking, 3 Gurson (GTN)
   int dfield;
   double K, mu, sy, H, dC, dR, dmax;
   double ell2[4];
+  // Gurson only: hardening exponent, yield-surface coefficients, coalescence,
+  // nucleation, cap of f* and the porosity fV at which the surface vanishes
+  double n, q1, q2, q3, fC, fF, fN, eN, sN, fu, fV;
 };
 struct MatTable {
   int nphase;
-  int pad;
+  int gtn;  // 1 when some phase is a Gurson matrix
   Mat m[16];
 };
 
@@ -153,7 +156,10 @@ void launch_constitutive(const MatTable& tab, const Geo& g, int c, int J,
                          const double* D, double* sigma, double* state_np1, double* alpha,
                          TT* tan, hipStream_t st);
 void launch_damage(const MatTable& tab, long long N, int J, const unsigned char* phase,
-                   const double* abar, const double* hist, double* D, hipStream_t st);
+                   const double* abar, const double* hist, const double* abar_n, double* D,
+                   hipStream_t st);
+void launch_commit_hist(const MatTable& tab, long long N, int J, const unsigned char* phase,
+                        const double* abar, const double* abar_n, double* hist, hipStream_t st);
 template <typename TL>
 void launch_ell2(const MatTable& tab, long long N, int j, const unsigned char* phase, TL* ell2,
                  hipStream_t st);
