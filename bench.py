@@ -249,6 +249,46 @@ def run_batch(count=64, nworkers=8):
                 speedup=round(res[1]["seconds"] / res[nworkers]["seconds"], 3))
 
 
+def run_gtn(name="gtn_spheres30_128", steps=6):
+    """The Gurson matrix (two non-local fields, Sec. 4.2 parameters) on the
+    30-sphere 128^3 RVE: `steps` staggered increments of 1e-3 from the virgin
+    state (FP64, production tolerances); Krylov throughput, the share of the
+    constitutive update in the wall time and the porosity reached."""
+    import torch
+    from paper_2103_04770_amd import Solver, microstructure as ms
+    w = ms.workload(name)
+    S, J = w["shape"], w["nfields"]
+    N = int(np.prod(S))
+    s = Solver(tuple(reversed(S)))
+    state = torch.zeros((6 + 7 + 2 * J,) + S, dtype=torch.float64, device="cuda")
+    sig = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
+    ph = torch.from_numpy(w["phase"]).cuda()
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ti = time.perf_counter()
+        d = s.staggered_step(ph, w["table"], J, state, w["load"][k], sig, **TOLS)
+        recs.append(dict(e11=1e-3 * (k + 1), sigma11=float(d["sigma_mean"][0]),
+                         cg=d["cg_iters"], pcg=d["pcg_iters"], newton=d["newton_iters"],
+                         stagger=d["stagger_iters"], converged=bool(d["converged"]),
+                         t_ms=[round(v, 2) for v in d["t_ms"]],
+                         wall_ms=round(1e3 * (time.perf_counter() - ti), 1)))
+        log("[gtn] E11 %.3f: cg %d pcg %d newton %d stag %d  <s11> %.1f MPa  %.0f ms" % (
+            recs[-1]["e11"], d["cg_iters"], d["pcg_iters"], d["newton_iters"],
+            d["stagger_iters"], d["sigma_mean"][0], recs[-1]["wall_ms"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fmax = float(state[6 + 7].max())
+    s.close()
+    it = sum(r["cg"] + r["pcg"] for r in recs)
+    tc = sum(r["t_ms"][0] for r in recs)
+    return dict(workload=name, increments=steps, form="fp64", wall_s=round(wall, 3),
+                voxel_krylov_iters_per_s=round(N * it / wall, 1),
+                constitutive_share=round(tc / (1e3 * wall), 4), max_porosity=fmax,
+                records=recs)
+
+
 def cpu_baseline(ws, iters):
     """The oracle, as it stands, on a bounded sample of the same workload: the
     first Newton system at E11 = 0.005 from a uniform strain guess, `iters`
@@ -417,6 +457,7 @@ def main():
         out["adaptive_driver"] = run_driver()
         out["adjoint"] = run_adjoint()
         out["batch"] = run_batch()
+        out["gtn"] = run_gtn()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_iters)

@@ -864,7 +864,9 @@ __device__ void principal3(const double e[6], double lam[3]) {
 // the root.  Returns s0 and ds0/de0 (differentiating the law).
 __device__ void gtn_flow(const Mat& m, double e0, double& s0, double& h) {
   const double ce = 3.0 * m.mu / m.sy * e0;
-  double y = 1.0 + ce;
+  // (1 + 2 ce)^n lies between the root and 1 + ce when n <= 1/2, so the
+  // monotone descent starts much closer to the root
+  double y = m.n <= 0.5 ? pow(1.0 + 2.0 * ce, m.n) : 1.0 + ce;
   for (int it = 0; it < 60; ++it) {
     const double z = y + ce;
     const double zn = pow(z, m.n);
@@ -966,17 +968,77 @@ __device__ void gtn_project(const Mat& m, double q_tr, double sm_tr, double s0, 
   q = (clamped && sm == end) ? 0.0 : qsurf(sm);
 }
 
+// Local Gurson equations at x = (u, v, w) for a trial state (q_tr, sm_tr):
+//   F1 = s0 (u dphi/dsm - v dphi/dq), F2 = phi, F3 = (1 - f) w - (q u + sm v)/s0
+// with q = q_tr - 3 mu u, sm = sm_tr - K v, s0 = s0(e0_n + w); also
+// J = dF/dx and R = -dF/d(q_tr, sm_tr).  Returns max(|F1|/xs, |F2|, |F3|/xs),
+// xs the largest increment (F1 and F3 are strain-sized, F2 is O(1)).
+__device__ double gtn_system(const Mat& m, double q_tr, double sm_tr, double e0n, double f,
+                             double fs, double u, double v, double w, double F[3],
+                             double J[3][3], double R[3][2], double& q, double& sm) {
+  const double K = m.K, mu = m.mu, q1 = m.q1, q2 = m.q2;
+  double s0, h;
+  gtn_flow(m, e0n + w, s0, h);
+  q = q_tr - 3.0 * mu * u;
+  sm = sm_tr - K * v;
+  const double t = 1.5 * q2 * sm / s0, tq = 1.5 * q2 / s0;
+  const double sh = sinh(t), ch = cosh(t), A = 3.0 * q1 * q2 * fs;
+  const double is0 = 1.0 / s0;
+  F[0] = A * u * sh - 2.0 * v * q * is0;
+  F[1] = q * q * is0 * is0 + 2.0 * q1 * fs * ch - (1.0 + m.q3 * fs * fs);
+  F[2] = (1.0 - f) * w - (q * u + sm * v) * is0;
+  // partial derivatives: in (u, v, w) held directly, then in q, sm, s0
+  const double d[3][6] = {
+      {A * sh, -2.0 * q * is0, 0.0, -2.0 * v * is0, A * u * ch * tq,
+       -A * u * ch * t * is0 + 2.0 * v * q * is0 * is0},
+      {0.0, 0.0, 0.0, 2.0 * q * is0 * is0, 2.0 * q1 * fs * sh * tq,
+       -2.0 * q * q * is0 * is0 * is0 - 2.0 * q1 * fs * sh * t * is0},
+      {-q * is0, -sm * is0, 1.0 - f, -u * is0, -v * is0, (q * u + sm * v) * is0 * is0}};
+  for (int i = 0; i < 3; ++i) {
+    J[i][0] = d[i][0] - 3.0 * mu * d[i][3];
+    J[i][1] = d[i][1] - K * d[i][4];
+    J[i][2] = d[i][2] + h * d[i][5];
+    R[i][0] = -d[i][3];
+    R[i][1] = -d[i][4];
+  }
+  const double xs = fmax(fmax(fabs(u), fabs(v)), fmax(fabs(w), 1e-12));
+  return fmax(fmax(fabs(F[0]) / xs, fabs(F[1])), fabs(F[2]) / xs);
+}
+
+// Solve the 3x3 system J y = b by cofactors; false when J is singular.
+__device__ bool solve3(const double J[3][3], const double b[3], double y[3]) {
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  if (!(det != 0.0) || !isfinite(det)) return false;
+  const double id = 1.0 / det;
+  const double inv[3][3] = {
+      {c00, J[0][2] * J[2][1] - J[0][1] * J[2][2], J[0][1] * J[1][2] - J[0][2] * J[1][1]},
+      {c01, J[0][0] * J[2][2] - J[0][2] * J[2][0], J[0][2] * J[1][0] - J[0][0] * J[1][2]},
+      {c02, J[0][1] * J[2][0] - J[0][0] * J[2][1], J[0][0] * J[1][1] - J[0][1] * J[1][0]}};
+  for (int r = 0; r < 3; ++r) y[r] = id * (inv[r][0] * b[0] + inv[r][1] * b[1] + inv[r][2] * b[2]);
+  return true;
+}
+
 // Backward-Euler Gurson update at frozen porosity f for one voxel.  The
 // plastic strain increment is u N + v I/3 (N = 3 s_tr/(2 q_tr)), the matrix
 // plastic strain grows by w with (1 - f) s0(e0_n + w) w = q u + sm v (plastic
-// work).  For a given w the stress is the normal return onto the surface of
-// s0(e0_n + w); the work residual is negative at w = 0 and non-negative at
-// w_hi = (q u + sm v)|_{w=0} / ((1 - f) s0(e0_n)).  The compact tangent
-// [a, b, m] (K:e = a tr(e) I + b dev(e) - (m.e) m) is the consistent one from
-// the linearised local equations
-//   F1 = s0 (u dphi/dsm - v dphi/dq), F2 = phi, F3 = (1 - f) w - (q u + sm v)/s0
-// in (q_tr, sm_tr): with A_q = du/dq_tr, B_q = du/dsm_tr, A_v = dv/dq_tr,
-// B_v = dv/dsm_tr and theta = q/q_tr,
+// work).
+//
+// Fast path: damped Newton on (F1, F2, F3) = 0 from the J2-like estimate,
+// accepted only when it converges to an admissible point (u >= 0, w >= 0,
+// q >= 0, v of the sign of sm, i.e. a non-negative plastic multiplier):
+// the return is unique there, so that point is the solution.
+// Fallback (any other case): nested bracketed roots.  For a given w the stress
+// is the normal return onto the surface of s0(e0_n + w); the work residual is
+// negative at w = 0 and non-negative at
+// w_hi = (q u + sm v)|_{w=0} / ((1 - f) s0(e0_n)).
+//
+// The compact tangent [a, b, m] (K:e = a tr(e) I + b dev(e) - (m.e) m) is the
+// consistent one from the linearised local equations in (q_tr, sm_tr): with
+// A_q = du/dq_tr, B_q = du/dsm_tr, A_v = dv/dq_tr, B_v = dv/dsm_tr and
+// theta = q/q_tr,
 //   K_t = 2 mu theta I_dev + K (1 - K B_v) I(x)I
 //         + 4 mu/3 (1 - 3 mu A_q - theta) N(x)N - mu K (A_v + B_q)(N(x)I + I(x)N)
 // (symmetrised), written as a I(x)I + b I_dev - m(x)m with m = alpha N + beta I.
@@ -1007,19 +1069,66 @@ __device__ void gtn_update(const Mat& m, const double e[6], double ep[6], double
     return;
   }
   const double e0n = e0, w1f = 1.0 - f;
-  auto work = [&](double w) {
-    double s0, h, q, sm;
+  double F[3], J[3][3], R[3][2], q, sm;
+  // ---- fast path
+  double u = fmax(q_tr - s0n, 0.0) / (3.0 * mu + hn), v = 0.0, w = u / w1f;
+  bool ok = false;
+  double r = gtn_system(m, q_tr, sm_tr, e0n, f, fs, u, v, w, F, J, R, q, sm);
+  for (int it = 0; it < 16 && !ok; ++it) {
+    double dx[3];
+    const double nb[3] = {-F[0], -F[1], -F[2]};
+    if (!solve3(J, nb, dx)) break;
+    double lam = 1.0, un = u, vn = v, wn = w, rn = r;
+    double Fn[3], Jn[3][3], Rn[3][2], qn, smn;
+    bool dec = false;
+    for (int k = 0; k < 8; ++k) {
+      un = fmin(fmax(u + lam * dx[0], 0.0), q_tr / (3.0 * mu));
+      vn = v + lam * dx[1];
+      wn = fmax(w + lam * dx[2], 0.0);
+      rn = gtn_system(m, q_tr, sm_tr, e0n, f, fs, un, vn, wn, Fn, Jn, Rn, qn, smn);
+      if (rn < r) {
+        dec = true;
+        break;
+      }
+      lam *= 0.5;
+    }
+    if (!dec) break;
+    u = un;
+    v = vn;
+    w = wn;
+    r = rn;
+    q = qn;
+    sm = smn;
+    for (int i = 0; i < 3; ++i) {
+      F[i] = Fn[i];
+      R[i][0] = Rn[i][0];
+      R[i][1] = Rn[i][1];
+      for (int k = 0; k < 3; ++k) J[i][k] = Jn[i][k];
+    }
+    ok = r <= 1e-14;
+  }
+  // a plastic multiplier of the wrong sign shows as v opposite to sm (beyond
+  // the rounding left in v when f* = 0 and the flow is deviatoric)
+  ok = ok && u >= 0.0 && w >= 0.0 && q >= 0.0 &&
+       !(v * sm < 0.0 && fabs(v) > 1e-12 * fmax(u, w));
+  if (!ok) {
+    // ---- fallback: nested bracketed roots
+    auto work = [&](double ww) {
+      double s0, h, qq, ss2;
+      gtn_flow(m, e0n + ww, s0, h);
+      gtn_project(m, q_tr, sm_tr, s0, fs, qq, ss2);
+      return w1f * s0 * ww - (qq * (q_tr - qq) / (3.0 * mu) + ss2 * (sm_tr - ss2) / K);
+    };
+    const double f0 = work(0.0);
+    const double whi = -f0 / (w1f * s0n);
+    w = bracket_root(work, 0.0, whi, f0, work(whi));
+    double s0, h;
     gtn_flow(m, e0n + w, s0, h);
     gtn_project(m, q_tr, sm_tr, s0, fs, q, sm);
-    return w1f * s0 * w - (q * (q_tr - q) / (3.0 * mu) + sm * (sm_tr - sm) / K);
-  };
-  const double f0 = work(0.0);
-  const double whi = -f0 / (w1f * s0n);
-  const double w = bracket_root(work, 0.0, whi, f0, work(whi));
-  double s0, h, q, sm;
-  gtn_flow(m, e0n + w, s0, h);
-  gtn_project(m, q_tr, sm_tr, s0, fs, q, sm);
-  const double u = (q_tr - q) / (3.0 * mu), v = (sm_tr - sm) / K;
+    u = (q_tr - q) / (3.0 * mu);
+    v = (sm_tr - sm) / K;
+    gtn_system(m, q_tr, sm_tr, e0n, f, fs, u, v, w, F, J, R, q, sm);
+  }
   double N[6];
   for (int i = 0; i < 6; ++i) N[i] = q_tr > 0.0 ? 1.5 * st[i] / q_tr : 0.0;
   for (int i = 0; i < 6; ++i) {
@@ -1027,46 +1136,24 @@ __device__ void gtn_update(const Mat& m, const double e[6], double ep[6], double
     s[i] = st[i] - 2.0 * mu * u * N[i] + (i < 3 ? sm : 0.0);
   }
   e0 = e0n + w;
-  // local Jacobian dF/d(u, v, w) and dF/d(q_tr, sm_tr) at the solution
-  const double q1 = m.q1, q2 = m.q2;
-  const double t = 1.5 * q2 * sm / s0, tq = 1.5 * q2 / s0;
-  const double sh = sinh(t), ch = cosh(t), A = 3.0 * q1 * q2 * fs;
-  // rows: partials in (u, v, w) held directly, then q, sm, s0
-  const double d[3][6] = {
-      {A * sh, -2.0 * q / s0, 0.0, -2.0 * v / s0, A * u * ch * tq,
-       -A * u * ch * t / s0 + 2.0 * v * q / (s0 * s0)},
-      {0.0, 0.0, 0.0, 2.0 * q / (s0 * s0), 2.0 * q1 * fs * sh * tq,
-       -2.0 * q * q / (s0 * s0 * s0) - 2.0 * q1 * fs * sh * t / s0},
-      {-q / s0, -sm / s0, w1f, -u / s0, -v / s0, (q * u + sm * v) / (s0 * s0)}};
-  double J[3][3], R[3][2];
-  for (int i = 0; i < 3; ++i) {
-    J[i][0] = d[i][0] - 3.0 * mu * d[i][3];
-    J[i][1] = d[i][1] - K * d[i][4];
-    J[i][2] = d[i][2] + h * d[i][5];
-    R[i][0] = -d[i][3];
-    R[i][1] = -d[i][4];
+  // tangent: X = J^-1 R, rows (u, v), columns (q_tr, sm_tr)
+  double X[2][2];
+  bool okj = true;
+  for (int k = 0; k < 2; ++k) {
+    const double b[3] = {R[0][k], R[1][k], R[2][k]};
+    double y[3];
+    okj = okj && solve3(J, b, y);
+    X[0][k] = y[0];
+    X[1][k] = y[1];
   }
-  // X = J^-1 R by cofactors (rows u, v, w; columns q_tr, sm_tr)
-  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-  const double inv[2][3] = {
-      {c00 / det, (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det,
-       (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det},
-      {c01 / det, (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det,
-       (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det}};
-  double X[2][2];  // X[0] = (A_q, B_q), X[1] = (A_v, B_v)
-  for (int r = 0; r < 2; ++r)
-    for (int k = 0; k < 2; ++k)
-      X[r][k] = inv[r][0] * R[0][k] + inv[r][1] * R[1][k] + inv[r][2] * R[2][k];
+  if (!okj) return;  // elastic tangent
   const double th = q_tr > 0.0 ? q / q_tr : 1.0;
   const double Avol = K * (1.0 - K * X[1][1]);
   const double Cnn = 4.0 * mu / 3.0 * (1.0 - 3.0 * mu * X[0][0] - th);
   const double Cni = -mu * K * (X[1][0] + X[0][1]);
   tb = 2.0 * mu * th;
   ta = Avol;
-  if (Cnn < 0.0 && isfinite(det) && det != 0.0) {
+  if (Cnn < 0.0) {
     const double al = sqrt(-Cnn);
     double be = -Cni / al;
     if (!(be * be <= 1e3 * Avol)) be = 0.0;

@@ -234,6 +234,20 @@ def workload(name, seed=None):
         load = [uniaxial_mixed(3, 2e-3 * (k + 1)) for k in range(20)]
         return dict(name=name, shape=shape, ndim=3, phase=phase, table=table, nfields=1,
                     load=load, max_stagger=20)
+    if name.startswith("gtn_spheres30_"):
+        # the 30-sphere RVE (radius 0.1167 L, 20%, RSA seed 5) at n^3 with the
+        # Gurson matrix of Sec. 4.2 (two non-local fields: matrix plastic
+        # strain and trace of the plastic strain, lengths 0.05 L in the matrix
+        # and 0.001 L in the particles); increments of 1e-3.
+        n = int(name.rsplit("_", 1)[1])
+        shape = (n, n, n)
+        s = 5 if seed is None else seed
+        phase, _, _ = rsa_spheres(shape, s, radius=14.94 * n / 128.0, count=30)
+        lm, lp = 0.05 * n, 0.001 * n
+        table = [matrix_gtn(ell=[lm, lm], dfield=0), particle_elastic(ell=[lp, lp])]
+        load = [uniaxial_mixed(3, 1e-3 * (k + 1)) for k in range(40)]
+        return dict(name=name, shape=shape, ndim=3, phase=phase, table=table, nfields=2,
+                    load=load, max_stagger=20)
     if name.startswith("spheres_two_fields_"):
         # n^3 (128 for the full size), 25% spheres with radii U(4, 8) (RSA,
         # seed 3; radii scaled by n/64 below 64^3);
