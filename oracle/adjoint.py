@@ -32,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import galerkin, helmholtz, material, spectral
+from . import galerkin, helmholtz, mandel, material, spectral
 
 
 def grad_fields(u, qt):
@@ -112,3 +112,92 @@ def mechanics_adjoint(phase, table, D, epsp_n, kappa_n, target, eps, gbar, nfiel
         m = mu[:, sel] if gsig is None else mu[:, sel] - gsig[:, sel]
         dD[j][sel] = (m * seff).sum(axis=0)
     return dict(mu=mu, dD=dD, cg_iters=it)
+
+
+def source_derivative(eps, epsp_n, kappa_n, phase, table, nfields):
+    """d alpha_j / d eps per voxel, (J, c, *S): for a j2_damage phase driven by
+    field j the source is eps_p(eq) = kappa_n + dk with
+    dk = (sqrt(3/2) ||s_tr|| - sy - H kappa_n)/(3 mu + H) where plastic, so
+    d alpha / d eps = sqrt(3/2) 2 mu n / (3 mu + H), n the unit deviatoric
+    trial direction (0 where elastic).  Cracking phases are not covered."""
+    c = eps.shape[0]
+    S = eps.shape[1:]
+    e6 = mandel.expand_plane(eps) if c == 3 else eps
+    I = mandel.identity(6).reshape((6,) + (1,) * len(S))
+    out = np.zeros((nfields, 6) + S)
+    for p, ph in enumerate(table):
+        j = ph["dfield"]
+        if ph["model"] == "elastic_cracking" and j >= 0:
+            raise NotImplementedError("source derivative of the cracking phase")
+        if ph["model"] != "j2_damage" or j < 0:
+            continue
+        K, mu = material.lame(ph["E"], ph["nu"])
+        ee = e6 - epsp_n
+        tr = ee[0] + ee[1] + ee[2]
+        s = 2.0 * mu * (ee - tr / 3.0 * I)
+        ns = np.sqrt((s * s).sum(axis=0))
+        plastic = (phase == p) & (np.sqrt(1.5) * ns - (ph["sy"] + ph["H"] * kappa_n) > 0.0)
+        g = np.where(plastic, np.sqrt(1.5) * 2.0 * mu / (3.0 * mu + ph["H"])
+                     / np.where(ns > 0, ns, 1.0), 0.0)
+        out[j] += g[None] * s
+    if c == 3:
+        out = out[:, mandel.PLANE_IDX]
+    return out
+
+
+def staggered_adjoint(phase, table, nfields, state_n, eps, abar, target, g_eps=None,
+                      g_sig=None, g_abar=None, g_D=None, h=1.0, scheme=spectral.ROTATED,
+                      cg_tol=1e-12, pcg_tol=1e-12, tol=1e-12, maxit=200):
+    """Gradient of J(eps, sigma, abar, D) at a converged staggered increment
+    (Algorithm 1 at its fixed point: mechanics at D(abar), Helmholtz with the
+    sources alpha(eps)) with respect to the squared lengths ell2_j(x).
+
+    Linearising both equations, a change of ell2 moves abar by
+    dabar = -(I - T)^-1 L^-1 dL abar, with the staggered map
+    T = L^-1 alpha' A^-1 G* sigma_eff D' (A = G* K).  Hence
+        dJ/dell2_j(x) = -sum_i (G_i lam_j)(x) (G_i abar_j)(x),  lam = L^-1 z,
+    where z solves the transposed staggered fixed point
+        z = hv + T^T z,   T^T z = D' (sigma_eff : A^-1 G*(alpha'^T L^-1 z)),
+        hv = D' ((mu0 - g_sig) : sigma_eff + g_D) + g_abar,
+        mu0 = A^-1 G*(g_eps + K g_sig)
+    (the damage term is mechanics_adjoint's dD, the damage-law slope D' is
+    damage_adjoint's).  Iterated like the forward scheme until
+    ||z_new - z|| <= tol ||z_new||.  Returns dict(dell2 (J, *S), lam, z, iters)."""
+    S = phase.shape
+    c = eps.shape[0]
+    J = nfields
+    zf = np.zeros((c,) + S)
+    g_eps = zf if g_eps is None else g_eps
+    D = material.damage_from_nonlocal(phase, table, abar, state_n["hist"], state_n["abar"])
+    ell2 = [np.array([float(t["ell"][j]) ** 2 for t in table])[phase] for j in range(J)]
+    m0 = mechanics_adjoint(phase, table, D, state_n["epsp"], state_n["kappa"], target, eps, g_eps,
+                           J, h=h, scheme=scheme, cg_tol=cg_tol, gsig=g_sig)
+    gD = m0["dD"] if g_D is None else m0["dD"] + g_D
+    hv = damage_adjoint(phase, table, abar, state_n["hist"], gD)
+    if g_abar is not None:
+        hv = hv + g_abar
+    dadx = source_derivative(eps, state_n["epsp"], state_n["kappa"], phase, table, J)
+    z = hv.copy()
+    lam = np.zeros((J,) + S)
+    it = 0
+    for it in range(1, maxit + 1):
+        for j in range(J):
+            lam[j] = helmholtz.helmholtz_solve(z[j], ell2[j], h=h, scheme=scheme, x0=lam[j],
+                                               tol=pcg_tol, maxit=5000)["abar"]
+        rhs = (lam[:, None] * dadx).sum(axis=0)
+        m = mechanics_adjoint(phase, table, D, state_n["epsp"], state_n["kappa"], target, eps,
+                              rhs, J, h=h, scheme=scheme, cg_tol=cg_tol)
+        z_new = hv + damage_adjoint(phase, table, abar, state_n["hist"], m["dD"])
+        dz = float(np.sqrt(((z_new - z) ** 2).sum()))
+        nz = float(np.sqrt((z_new ** 2).sum()))
+        z = z_new
+        if dz <= tol * max(nz, 1e-300):
+            break
+    for j in range(J):
+        lam[j] = helmholtz.helmholtz_solve(z[j], ell2[j], h=h, scheme=scheme, x0=lam[j],
+                                           tol=pcg_tol, maxit=5000)["abar"]
+    _, qt = spectral.symbols(S, h, scheme)
+    qt = [np.broadcast_to(v, S) for v in qt]
+    dell2 = np.stack([-sum(a * b for a, b in zip(grad_fields(lam[j], qt), grad_fields(abar[j], qt)))
+                      for j in range(J)])
+    return dict(dell2=dell2, lam=lam, z=z, iters=it)

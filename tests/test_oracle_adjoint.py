@@ -200,3 +200,95 @@ def test_one_pass_chain_gradients_by_finite_differences():
         ha = 1e-3
         fd_a = (J(which, alpha + ha * dirn, ells) - J(which, alpha - ha * dirn, ells)) / (2 * ha)
         assert float((dal * dirn).sum()) == pytest.approx(fd_a, rel=1e-4)
+
+
+def _stag_case():
+    S = (12, 16)
+    rng = np.random.default_rng(21)
+    phase = (rng.uniform(size=S) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    return S, phase, table
+
+
+STAG_TOLS = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, newton_maxit=60,
+                 stagger_tol=1e-13, max_stagger=300)
+
+
+def _stag_increment(phase, table, st_n, e11):
+    from oracle import staggered
+    st, sig, hom, stats = staggered.staggered_step(phase, table, 1, st_n,
+                                                   ms.uniaxial_mixed(phase.ndim, e11), **STAG_TOLS)
+    assert stats["converged"]
+    return st, sig, hom, stats
+
+
+def test_source_derivative_by_finite_differences():
+    """d kappa / d eps of the J2 return (the local source of the matrix field)
+    against central differences of the constitutive update."""
+    from oracle import material
+    S = (4, 6)
+    rng = np.random.default_rng(3)
+    phase = (rng.uniform(size=S) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_elastic(ell=[0.5])]
+    eps = rng.normal(scale=4e-3, size=(3,) + S)
+    epsp = rng.normal(scale=1e-3, size=(6,) + S)
+    epsp[:3] -= epsp[:3].mean(axis=0)
+    kap = np.abs(rng.normal(scale=2e-3, size=S))
+    D = np.zeros((1,) + S)
+    d = adjoint.source_derivative(eps, epsp, kap, phase, table, 1)
+    h = 1e-8
+    for k in range(3):
+        ep, em = eps.copy(), eps.copy()
+        ep[k] += h
+        em[k] -= h
+        fd = (material.constitutive(ep, epsp, kap, D, phase, table, 1)["alpha"]
+              - material.constitutive(em, epsp, kap, D, phase, table, 1)["alpha"]) / (2 * h)
+        assert np.abs(fd[0] - d[0, k]).max() <= 1e-6 * np.abs(d[0]).max()
+    assert np.abs(d[0]).max() > 0
+
+
+@pytest.mark.parametrize("which", ["sigma11", "mean_damage", "mean_abar"])
+def test_staggered_adjoint_by_finite_differences(which):
+    """Gradient of J after a converged staggered increment (damage active,
+    damage feeding back into the local source through the mechanics) with
+    respect to the per-phase lengths, against central differences of the
+    converged increment."""
+    from oracle import staggered
+    S, phase, table = _stag_case()
+    st0 = staggered.initial_state(S, 2, 1)
+    st_n, _, _, _ = _stag_increment(phase, table, st0, 3e-3)
+    e11 = 5e-3
+    st, sig, hom, stats = _stag_increment(phase, table, st_n, e11)
+    assert stats["stagger_iters"] > 2        # a real fixed point, not one pass
+    N = phase.size
+    kw = {}
+    if which == "sigma11":
+        g = np.zeros((3,) + S)
+        g[0] = 1.0 / N
+        kw["g_sig"] = g
+    elif which == "mean_damage":
+        kw["g_D"] = np.full((1,) + S, 1.0 / N)
+    else:
+        kw["g_abar"] = np.full((1,) + S, 1.0 / N)
+    r = adjoint.staggered_adjoint(phase, table, 1, st_n, st["eps"], st["abar"],
+                                  ms.uniaxial_mixed(2, e11), **kw)
+    grad = adjoint.phase_length_gradient(r["dell2"][0], phase, table, 0)
+
+    def J(tab):
+        from oracle import material
+        s2, sg, hm, _ = _stag_increment(phase, tab, st_n, e11)
+        if which == "sigma11":
+            return hm["sigma"][0]
+        if which == "mean_damage":
+            return material.damage_from_nonlocal(phase, tab, s2["abar"], st_n["hist"]).mean()
+        return s2["abar"].mean()
+
+    for q in range(2):
+        hq = 1e-4 * table[q]["ell"][0]
+        tp = [dict(t) for t in table]
+        tm = [dict(t) for t in table]
+        tp[q]["ell"] = [table[q]["ell"][0] + hq]
+        tm[q]["ell"] = [table[q]["ell"][0] - hq]
+        fd = (J(tp) - J(tm)) / (2 * hq)
+        assert grad[q] == pytest.approx(fd, rel=2e-4, abs=1e-6 * abs(grad).max())
+    assert r["iters"] > 2
