@@ -241,6 +241,36 @@ fftg_status fftg_solve_adjoint(fftg_handle* h, const unsigned char* phase, const
                                const double* gsig, double* mu, double* dD,
                                const fftg_krylov_opts* cg, fftg_stats* stats);
 
+/* Adjoint of a converged staggered increment (Algorithm 1 at its fixed
+ * point: mechanics at D(abar), Helmholtz with the sources alpha(eps)).  For a
+ * scalar J(eps, sigma, abar, D) with partial derivatives g_eps, g_sig (dev
+ * [c][N]), g_abar, g_D (dev [nfields][N]; each may be NULL = 0), returns
+ *   dell2  dev [nfields][N]: dJ/dell2_j(x), with the damage feeding back into
+ *          the local sources through the mechanics (total derivative at the
+ *          fixed point); dJ/d ell_q = 2 ell_q sum over phase q (fftg_phase_sums)
+ *   lam    dev [nfields][N] or NULL: the Helmholtz adjoint fields L^-1 z.
+ * Linearising both equations, a change of ell2 moves abar by
+ * -(I - T)^-1 L^-1 dL abar with the staggered map T = L^-1 alpha' A^-1 G*
+ * sigma_eff D' (A = G* K); so dell2_j = -sum_i (G_i lam_j)(G_i abar_j),
+ * lam = L^-1 z, where z solves the transposed staggered fixed point
+ *   z = h + D' (sigma_eff : A^-1 G*(alpha'^T L^-1 z)),
+ *   h = D' ((mu0 - g_sig) : sigma_eff + g_D) + g_abar,  mu0 = A^-1 G*(g_eps + K g_sig),
+ * iterated (one Helmholtz PCG per field and one Galerkin CG per pass) until
+ * ||z_new - z|| <= tol ||z_new|| or maxit passes (then FFTG_NOT_CONVERGED).
+ *   state_n    dev packed state at t_n (staggered_step's input)
+ *   state_np1  dev packed state at t_{n+1} (its output): eps and abar are read
+ * stats: cg_iters, pcg_iters, stagger_iters = passes, err = last change.
+ * Sources covered: the J2 damage matrix (d alpha/d eps of its return).  Tables
+ * with a Gurson phase or a driven cracking phase: FFTG_E_UNSUPPORTED. */
+fftg_status fftg_staggered_adjoint(fftg_handle* h, const unsigned char* phase,
+                                   const fftg_phase* tab, int nphase, int nfields,
+                                   const double* state_n, const double* state_np1,
+                                   const fftg_macro* target, const double* g_eps,
+                                   const double* g_sig, const double* g_abar, const double* g_D,
+                                   double* dell2, double* lam, const fftg_krylov_opts* cg,
+                                   const fftg_krylov_opts* pcg, double tol, int maxit,
+                                   fftg_stats* stats);
+
 /* Pieces of the differentiable one-pass chain alpha -> abar -> D -> (eps,
  * sigma) (see paper_2103_04770_amd/autograd.py), all on the handle's grid.
  *   fftg_damage        D dev [nfields][N] from abar, hist dev [nfields][N]

@@ -118,6 +118,9 @@ def load_library():
         "helmholtz_adjoint": [P, P, D, P, P, P, P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
         "fftg_solve_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, ct.POINTER(Macro), P, P, P,
                                P, P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
+        "fftg_staggered_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, ct.POINTER(Macro), P, P,
+                                   P, P, P, P, ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D,
+                                   I, ct.POINTER(Stats)],
         "fftg_damage": [P, P, ct.POINTER(Phase), I, I, P, P, P],
         "fftg_damage_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, P, P],
         "fftg_ell2": [P, P, ct.POINTER(Phase), I, I, P],
@@ -354,6 +357,29 @@ class Solver:
             _ptr(mu, f64, self.c * self.N, "mu"),
             _ptr(dD, f64, nfields * self.N, "dD") if nfields else None,
             ct.byref(KrylovOpts(cg_tol, cg_maxit)), ct.byref(st)))
+        d = st.as_dict()
+        d["converged"] = ok
+        return d
+
+    def fftg_staggered_adjoint(self, phase, table, nfields, state_n, state_np1, target, dell2,
+                               lam=None, g_eps=None, g_sig=None, g_abar=None, g_D=None,
+                               cg_tol=1e-10, cg_maxit=5000, pcg_tol=1e-10, pcg_maxit=5000,
+                               tol=1e-10, maxit=200):
+        """dell2 <- dJ/dell2_j(x) of a converged staggered increment (total
+        derivative at the fixed point); lam <- the Helmholtz adjoint fields."""
+        f64 = self.torch.float64
+        n = nfields * self.N
+        nst = (self.c + 7 + 2 * nfields) * self.N
+        m = _macro(target)
+        st = Stats()
+        opt = lambda t, k, name: _ptr(t, f64, k, name) if t is not None else None  # noqa: E731
+        ok = self._check(self.lib.fftg_staggered_adjoint(
+            self.h, _ptr(phase, self.torch.uint8, self.N, "phase"), phase_table(table), len(table),
+            nfields, _ptr(state_n, f64, nst, "state_n"), _ptr(state_np1, f64, nst, "state_np1"),
+            ct.byref(m), opt(g_eps, self.c * self.N, "g_eps"), opt(g_sig, self.c * self.N, "g_sig"),
+            opt(g_abar, n, "g_abar"), opt(g_D, n, "g_D"), _ptr(dell2, f64, n, "dell2"),
+            opt(lam, n, "lam"), ct.byref(KrylovOpts(cg_tol, cg_maxit)),
+            ct.byref(KrylovOpts(pcg_tol, pcg_maxit)), float(tol), int(maxit), ct.byref(st)))
         d = st.as_dict()
         d["converged"] = ok
         return d

@@ -1335,6 +1335,79 @@ FFTG_KERNEL void k_commit_hist(MatTable tab, long long N, int J,
   }
 }
 
+// Transposed source derivative: out = sum_j lam_j (d alpha_j / d eps) at the
+// converged strain, [c][N].  For a J2 damage phase driven by field j the
+// source is kappa_n + dk with dk = (sqrt(3/2) ||s_tr|| - sy - H kappa_n)/(3 mu + H)
+// where plastic, so d alpha_j / d eps = sqrt(3/2) 2 mu s_tr / ((3 mu + H) ||s_tr||)
+// (0 where elastic and in every other phase).
+FFTG_KERNEL void k_source_adj(MatTable tab, long long N, int c, int J,
+                              const unsigned char* __restrict__ phase,
+                              const double* __restrict__ eps, const double* __restrict__ st_n,
+                              const double* __restrict__ lam, double* __restrict__ out) {
+  const double sq32 = 1.2247448713915890490986420373529;
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    double o[6] = {0, 0, 0, 0, 0, 0};
+    if (m.model == 1 && m.dfield >= 0 && m.dfield < J) {
+      double ee[6];
+      if (c == 6) {
+        for (int i = 0; i < 6; ++i) ee[i] = eps[i * N + v];
+      } else {
+        ee[0] = eps[v];
+        ee[1] = eps[N + v];
+        ee[2] = ee[3] = ee[4] = 0.0;
+        ee[5] = eps[2 * N + v];
+      }
+      for (int i = 0; i < 6; ++i) ee[i] -= st_n[i * N + v];
+      const double tr = ee[0] + ee[1] + ee[2];
+      double sd[6], ns2 = 0.0;
+      for (int i = 0; i < 6; ++i) {
+        sd[i] = 2.0 * m.mu * (ee[i] - (i < 3 ? tr / 3.0 : 0.0));
+        ns2 += sd[i] * sd[i];
+      }
+      const double ns = sqrt(ns2);
+      if (sq32 * ns - (m.sy + m.H * st_n[6 * N + v]) > 0.0) {
+        const double gf = lam[(long long)m.dfield * N + v] * sq32 * 2.0 * m.mu /
+                          ((3.0 * m.mu + m.H) * ns);
+        for (int i = 0; i < 6; ++i) o[i] = gf * sd[i];
+      }
+    }
+    if (c == 6) {
+      for (int i = 0; i < 6; ++i) out[i * N + v] = o[i];
+    } else {
+      out[v] = o[0];
+      out[N + v] = o[1];
+      out[2 * N + v] = o[5];
+    }
+  }
+}
+
+// partials [0][block] = sum (a - b)^2, [1][block] = sum a^2
+FFTG_KERNEL void k_diff2(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                         double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  double d2 = 0.0, a2 = 0.0;
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * FFT_THREADS) {
+    const double d = a[i] - b[i];
+    d2 += d * d;
+    a2 += a[i] * a[i];
+  }
+  double s = block_sum(d2, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  s = block_sum(a2, red);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s;
+}
+
+FFTG_KERNEL void k_axpby(long long n, double a, const double* __restrict__ x, double b,
+                         const double* __restrict__ y, double* __restrict__ out) {
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * FFT_THREADS)
+    out[i] = a * x[i] + b * y[i];
+}
+
 template <typename TL>
 FFTG_KERNEL void k_ell2(MatTable tab, long long N, int j, const unsigned char* __restrict__ phase,
                         TL* __restrict__ ell2) {
@@ -1942,6 +2015,24 @@ void launch_damage(const MatTable& tab, long long N, int J, const unsigned char*
                    hipStream_t st) {
   hipLaunchKernelGGL(k_damage, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, J, phase, abar,
                      hist, abar_n, D);
+}
+
+void launch_source_adj(const MatTable& tab, long long N, int c, int J, const unsigned char* phase,
+                       const double* eps, const double* state_n, const double* lam, double* out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_source_adj, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, c, J,
+                     phase, eps, state_n, lam, out);
+}
+
+int launch_diff2(long long n, const double* a, const double* b, double* partials, hipStream_t st) {
+  const int nb = grid_for(n);
+  hipLaunchKernelGGL(k_diff2, dim3(nb), dim3(FFT_THREADS), 0, st, n, a, b, partials);
+  return nb;
+}
+
+void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, a, x, b, y, out);
 }
 
 void launch_commit_hist(const MatTable& tab, long long N, int J, const unsigned char* phase,

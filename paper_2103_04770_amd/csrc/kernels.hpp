@@ -158,6 +158,12 @@ void launch_constitutive(const MatTable& tab, const Geo& g, int c, int J,
 void launch_damage(const MatTable& tab, long long N, int J, const unsigned char* phase,
                    const double* abar, const double* hist, const double* abar_n, double* D,
                    hipStream_t st);
+void launch_source_adj(const MatTable& tab, long long N, int c, int J, const unsigned char* phase,
+                       const double* eps, const double* state_n, const double* lam, double* out,
+                       hipStream_t st);
+int launch_diff2(long long n, const double* a, const double* b, double* partials, hipStream_t st);
+void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
+                  hipStream_t st);
 void launch_commit_hist(const MatTable& tab, long long N, int J, const unsigned char* phase,
                         const double* abar, const double* abar_n, double* hist, hipStream_t st);
 template <typename TL>

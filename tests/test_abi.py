@@ -44,3 +44,40 @@ def test_create_rejects_bad_grids_without_touching_the_gpu():
         assert not h.value
         assert lib.fftg_last_error(None)
     assert codes == [-2, -2, -1, -2, -2]
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of the public structs have the sizes and
+    field offsets the C compiler gives the header's declarations."""
+    import shutil
+    import subprocess
+    from paper_2103_04770_amd import binding
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    checks = {
+        "fftg_phase": (binding.Phase, ["model", "E", "dfield", "dmax", "ell", "n_hard", "q1",
+                                       "sN", "fu"]),
+        "fftg_macro": (binding.Macro, ["mask", "E", "S"]),
+        "fftg_stats": (binding.Stats, ["newton_iters", "relres", "err", "t_ms"]),
+        "fftg_drive_opts": (binding.DriveOpts, None),
+        "fftg_drive_record": (binding.DriveRecord, None),
+        "fftg_batch_item": (binding.BatchItem, None),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fftg.h"', "int main(void) {"]
+    for cname, (_, fields) in checks.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in fields or []:
+            cf = {"n_hard": "n_hard"}.get(f, f)
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, cf))
+    lines.append("return 0; }")
+    src = tmp_path / "sz.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sz"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for cname, (cls, fields) in checks.items():
+        assert int(out[cname]) == ctypes.sizeof(cls), cname
+        for f in fields or []:
+            assert int(out["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)

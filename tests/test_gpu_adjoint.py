@@ -169,3 +169,68 @@ def test_one_pass_chain_gradients_match_oracle():
         say(which, "dJ/dell gpu", ge.cpu().numpy(), "oracle", re)
         assert np.abs(ga.cpu().numpy() - ra).max() <= 1e-7 * np.abs(ra).max()
         assert np.allclose(ge.cpu().numpy(), re, rtol=1e-7, atol=1e-12 * np.abs(re).max())
+
+
+def _pack(st):
+    return np.concatenate([st["eps"], st["epsp"], st["kappa"][None], st["hist"], st["abar"]])
+
+
+@pytest.mark.parametrize("shape,which", [((12, 16), "sigma11"), ((12, 16), "mean_damage"),
+                                         ((6, 8, 8), "sigma11"), ((6, 8, 8), "mean_abar")])
+def test_staggered_adjoint_matches_oracle(shape, which):
+    """fftg_staggered_adjoint at a converged increment (damage active, fed
+    back into the source through the mechanics) against the oracle's
+    transposed staggered fixed point."""
+    from oracle import staggered
+    from tests.test_oracle_adjoint import STAG_TOLS
+    say("staggered adjoint", shape, which)
+    rng = np.random.default_rng(21)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    nd = len(shape)
+    c = 6 if nd == 3 else 3
+    st_n, _, _, _ = staggered.staggered_step(phase, table, 1, staggered.initial_state(shape, nd, 1),
+                                             ms.uniaxial_mixed(nd, 3e-3), **STAG_TOLS)
+    tgt = ms.uniaxial_mixed(nd, 5e-3)
+    st, _, _, stats = staggered.staggered_step(phase, table, 1, st_n, tgt, **STAG_TOLS)
+    assert stats["converged"] and stats["stagger_iters"] > 2
+    N = phase.size
+    kw, kg = {}, {}
+    if which == "sigma11":
+        g = np.zeros((c,) + shape)
+        g[0] = 1.0 / N
+        kw["g_sig"], kg["g_sig"] = g, dev(g)
+    elif which == "mean_damage":
+        g = np.full((1,) + shape, 1.0 / N)
+        kw["g_D"], kg["g_D"] = g, dev(g)
+    else:
+        g = np.full((1,) + shape, 1.0 / N)
+        kw["g_abar"], kg["g_abar"] = g, dev(g)
+    ref = adjoint.staggered_adjoint(phase, table, 1, st_n, st["eps"], st["abar"], tgt, **kw)
+    s = solver(shape)
+    dl = torch.empty((1,) + shape, dtype=torch.float64, device="cuda")
+    lam = torch.empty((1,) + shape, dtype=torch.float64, device="cuda")
+    d = s.fftg_staggered_adjoint(dev(phase, torch.uint8), table, 1, dev(_pack(st_n)), dev(_pack(st)),
+                                 tgt, dl, lam=lam, cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12,
+                                 maxit=300, **kg)
+    say("  gpu passes", d["stagger_iters"], "cg", d["cg_iters"], "pcg", d["pcg_iters"],
+        "oracle passes", ref["iters"])
+    assert d["converged"]
+    got = dl.cpu().numpy()
+    assert np.abs(got - ref["dell2"]).max() <= 1e-8 * np.abs(ref["dell2"]).max()
+    assert np.abs(lam.cpu().numpy() - ref["lam"]).max() <= 1e-8 * np.abs(ref["lam"]).max()
+    gq = adjoint.phase_length_gradient(got[0], phase, table, 0)
+    rq = adjoint.phase_length_gradient(ref["dell2"][0], phase, table, 0)
+    assert np.allclose(gq, rq, rtol=1e-8)
+
+
+def test_staggered_adjoint_rejects_uncovered_sources():
+    from paper_2103_04770_amd.binding import FFTGError
+    shape = (8, 8, 8)
+    s = solver(shape)
+    table = [ms.matrix_j2_damage(ell=[2.0, 0.1], dfield=0), ms.particle_cracking(ell=[0.1, 1.0])]
+    z = dev(np.zeros((6 + 7 + 4,) + shape))
+    with pytest.raises(FFTGError, match="UNSUPPORTED"):
+        s.fftg_staggered_adjoint(dev(np.zeros(shape), torch.uint8), table, 2, z, z,
+                                 ms.uniaxial_mixed(3, 1e-3),
+                                 torch.empty((2,) + shape, dtype=torch.float64, device="cuda"))
