@@ -422,6 +422,14 @@ const char* fftg_kernel_name(int id);
  * fftg_apply_galerkin needs a new fftg_constitutive afterwards. */
 fftg_status fftg_time_kernel(fftg_handle* h, int kid, int reps, double* avg_ms);
 
+/* HBM reference rate: a streaming copy of nbytes (a multiple of 16, both
+ * pointers 16-byte aligned, dev) from src to dst with one 16-byte load and
+ * store per lane, `reps` back-to-back copies between one event pair on the
+ * handle's stream, for a few grid sizes; *gbps = 2 nbytes reps / best time.
+ * Use buffers well above the 256 MB last-level cache. */
+fftg_status fftg_copy_rate(fftg_handle* h, const void* src, void* dst, long long nbytes, int reps,
+                           double* gbps);
+
 #ifdef __cplusplus
 }
 #endif

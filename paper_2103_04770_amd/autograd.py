@@ -12,6 +12,10 @@ iterations is kept.  Tensors are CUDA float64 in numpy axis order.
     eps, sig = mechanics(solver, D, phase, table, nfields, state_n, target)
                                                          d/d D (frozen damage)
 
+staggered_increment() differentiates a whole converged increment of the
+staggered scheme (the damage feeding back into the local sources through the
+mechanics) in the per-phase lengths, through fftg_staggered_adjoint.
+
 one_pass() chains them for one field: the per-voxel local source alpha (e.g.
 the local equivalent plastic strain) and the per-phase lengths give abar, the
 damage, and the strain and stress of the mechanics at that damage, so that
@@ -154,3 +158,47 @@ def one_pass(solver, alpha, ell, phase, table, target, field=0, helm_tol=1e-10, 
     state_n = torch.zeros((7,) + solver.spatial, dtype=torch.float64, device=alpha.device)
     eps, sig = mechanics(solver, D, phase, table, 1, state_n, target, **opts)
     return abar, D, eps, sig
+
+
+class _StaggeredIncrement(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, ell, solver, phase, table, nfields, state_n, target, field, opts):
+        tab = _with_lengths(table, ell.detach().cpu().numpy(), field)
+        state = state_n.detach().clone().contiguous()
+        sig = torch.empty((solver.c,) + solver.spatial, dtype=torch.float64, device="cuda")
+        d = solver.staggered_step(phase, tab, nfields, state, target, sig, **opts)
+        if not d["converged"]:
+            raise RuntimeError("staggered increment did not converge: %s" % d)
+        c = solver.c
+        abar = state[c + 7 + nfields:].clone()
+        ctx.save_for_backward(ell, state_n, state)
+        ctx.args = (solver, phase, tab, nfields, target, field, opts, len(table))
+        return sig, abar
+
+    @staticmethod
+    def backward(ctx, gsig, gabar):
+        ell, state_n, state = ctx.saved_tensors
+        solver, phase, tab, nfields, target, field, opts, nphase = ctx.args
+        dell2 = torch.empty((nfields,) + solver.spatial, dtype=torch.float64, device="cuda")
+        tol = min(opts.get("stagger_tol", 1e-6), 1e-8)
+        d = solver.fftg_staggered_adjoint(
+            phase, tab, nfields, state_n.contiguous(), state, target, dell2,
+            g_sig=None if gsig is None else gsig.contiguous(),
+            g_abar=None if gabar is None else gabar.contiguous(),
+            cg_tol=opts.get("cg_tol", 1e-8), pcg_tol=opts.get("pcg_tol", 1e-8), tol=tol,
+            maxit=opts.get("max_stagger", 20) * 10)
+        if not d["converged"]:
+            raise RuntimeError("staggered adjoint did not converge: %s" % d)
+        sums = solver.fftg_phase_sums(phase, nphase, dell2[field].contiguous())
+        return (2.0 * ell * torch.from_numpy(sums).to(ell), None, None, None, None, None, None,
+                None, None)
+
+
+def staggered_increment(solver, ell, phase, table, nfields, state_n, target, field=0, **opts):
+    """One converged staggered increment from the packed state_n (returns the
+    stress field and the non-local fields at t_{n+1}), differentiable in the
+    per-phase lengths `ell` of `field` (the total derivative at the fixed
+    point).  Sources covered by the adjoint: the J2 damage matrix."""
+    return _StaggeredIncrement.apply(ell, solver, phase, table, nfields, state_n, target, field,
+                                     opts)
+

@@ -139,6 +139,8 @@ def load_library():
     lib.fftg_last_error.restype = ct.c_char_p
     lib.fftg_profile.argtypes = [P, I, ct.POINTER(ct.c_double), ct.POINTER(ct.c_longlong)]
     lib.fftg_profile.restype = ct.c_int
+    lib.fftg_copy_rate.argtypes = [P, P, P, ct.c_longlong, I, ct.POINTER(ct.c_double)]
+    lib.fftg_copy_rate.restype = ct.c_int
     lib.fftg_time_kernel.argtypes = [P, I, I, ct.POINTER(ct.c_double)]
     lib.fftg_time_kernel.restype = ct.c_int
     lib.fftg_kernel_name.argtypes = [I]
@@ -404,6 +406,17 @@ class Solver:
         self._check(self.lib.fftg_ell2(self.h, _ptr(phase, self.torch.uint8, self.N, "phase"),
                                        phase_table(table), len(table), int(field),
                                        _ptr(ell2, self.torch.float64, self.N, "ell2")))
+
+    def fftg_copy_rate(self, src, dst, reps=20):
+        """GB/s of the library's streaming copy src -> dst (same-size tensors)."""
+        nb = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != nb or not (src.is_cuda and dst.is_cuda):
+            raise ValueError("fftg_copy_rate: two CUDA tensors of the same byte size")
+        out = ct.c_double()
+        self._check(self.lib.fftg_copy_rate(self.h, ct.c_void_p(src.data_ptr()),
+                                            ct.c_void_p(dst.data_ptr()), nb, int(reps),
+                                            ct.byref(out)))
+        return out.value
 
     def fftg_phase_sums(self, phase, nphase, f):
         out = (ct.c_double * nphase)()

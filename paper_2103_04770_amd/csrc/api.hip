@@ -1298,6 +1298,36 @@ fftg_status fftg_profile(fftg_handle* H, int enable, double* ms, long long* laun
   });
 }
 
+fftg_status fftg_copy_rate(fftg_handle* H, const void* src, void* dst, long long nbytes,
+                           int reps, double* gbps) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    if (!src || !dst || !gbps || reps < 1 || nbytes < 16 || nbytes % 16 != 0 ||
+        (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+      throw Fail{FFTG_E_INVALID, "fftg_copy_rate: bad arguments"};
+    const long long n16 = nbytes / 16;
+    int best_blocks = 0;
+    float best = 0.0f;
+    // a few grid sizes (multiples of the compute-unit count); keep the fastest
+    for (int blocks : {1024, 2048, 4096, 8192}) {
+      fftg::launch_stream_copy(src, dst, n16, blocks, H->st);  // warm-up
+      HIPCHK(hipEventRecord(H->ev[0], H->st));
+      for (int r = 0; r < reps; ++r) fftg::launch_stream_copy(src, dst, n16, blocks, H->st);
+      HIPCHK(hipEventRecord(H->ev[1], H->st));
+      HIPCHK(hipEventSynchronize(H->ev[1]));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, H->ev[0], H->ev[1]));
+      if (best_blocks == 0 || ms < best) {
+        best = ms;
+        best_blocks = blocks;
+      }
+    }
+    check_launch();
+    *gbps = 2.0 * (double)nbytes * reps / (best * 1e-3) / 1e9;
+    return FFTG_OK;
+  });
+}
+
 fftg_status fftg_time_kernel(fftg_handle* H, int kid, int reps, double* avg_ms) {
   if (!H) return FFTG_E_INVALID;
   return run_guarded(H, [&]() -> fftg_status {

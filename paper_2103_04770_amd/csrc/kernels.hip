@@ -1384,6 +1384,15 @@ FFTG_KERNEL void k_source_adj(MatTable tab, long long N, int c, int J,
   }
 }
 
+// Streaming copy of n16 16-byte words (the HBM reference rate): one 16-byte
+// load and store per lane per step, grid-stride over the buffer.
+FFTG_KERNEL void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                               long long n16) {
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n16;
+       i += (long long)gridDim.x * FFT_THREADS)
+    dst[i] = src[i];
+}
+
 // partials [0][block] = sum (a - b)^2, [1][block] = sum a^2
 FFTG_KERNEL void k_diff2(long long n, const double* __restrict__ a, const double* __restrict__ b,
                          double* __restrict__ partials) {
@@ -2022,6 +2031,11 @@ void launch_source_adj(const MatTable& tab, long long N, int c, int J, const uns
                        hipStream_t st) {
   hipLaunchKernelGGL(k_source_adj, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, c, J,
                      phase, eps, state_n, lam, out);
+}
+
+void launch_stream_copy(const void* src, void* dst, long long n16, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(FFT_THREADS), 0, st,
+                     reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), n16);
 }
 
 int launch_diff2(long long n, const double* a, const double* b, double* partials, hipStream_t st) {

@@ -161,6 +161,7 @@ void launch_damage(const MatTable& tab, long long N, int J, const unsigned char*
 void launch_source_adj(const MatTable& tab, long long N, int c, int J, const unsigned char* phase,
                        const double* eps, const double* state_n, const double* lam, double* out,
                        hipStream_t st);
+void launch_stream_copy(const void* src, void* dst, long long n16, int blocks, hipStream_t st);
 int launch_diff2(long long n, const double* a, const double* b, double* partials, hipStream_t st);
 void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
                   hipStream_t st);

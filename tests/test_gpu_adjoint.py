@@ -234,3 +234,35 @@ def test_staggered_adjoint_rejects_uncovered_sources():
         s.fftg_staggered_adjoint(dev(np.zeros(shape), torch.uint8), table, 2, z, z,
                                  ms.uniaxial_mixed(3, 1e-3),
                                  torch.empty((2,) + shape, dtype=torch.float64, device="cuda"))
+
+
+def test_autograd_staggered_increment_matches_oracle_gradient():
+    """torch.autograd through a whole converged increment: d<sigma_11>/d ell
+    (per phase) equals the oracle's adjoint of the converged increment."""
+    from oracle import staggered
+    from paper_2103_04770_amd import autograd as ag
+    from tests.test_oracle_adjoint import STAG_TOLS
+    shape = (6, 8, 8)
+    say("autograd staggered increment", shape)
+    rng = np.random.default_rng(21)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    st_n, _, _, _ = staggered.staggered_step(phase, table, 1, staggered.initial_state(shape, 3, 1),
+                                             ms.uniaxial_mixed(3, 3e-3), **STAG_TOLS)
+    tgt = ms.uniaxial_mixed(3, 5e-3)
+    st, _, hom, _ = staggered.staggered_step(phase, table, 1, st_n, tgt, **STAG_TOLS)
+    g = np.zeros((6,) + shape)
+    g[0] = 1.0 / phase.size
+    ref = adjoint.staggered_adjoint(phase, table, 1, st_n, st["eps"], st["abar"], tgt, g_sig=g)
+    rq = adjoint.phase_length_gradient(ref["dell2"][0], phase, table, 0)
+    s = solver(shape)
+    ell = torch.tensor([2.0, 0.5], dtype=torch.float64, device="cuda", requires_grad=True)
+    opts = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, newton_maxit=60,
+                stagger_tol=1e-12, max_stagger=300)
+    sig, abar = ag.staggered_increment(s, ell, dev(phase, torch.uint8), table, 1,
+                                       dev(_pack(st_n)), tgt, **opts)
+    J = sig[0].mean()
+    assert float(J.detach()) == pytest.approx(hom["sigma"][0], rel=1e-9)
+    (ge,) = torch.autograd.grad(J, (ell,))
+    say("  dJ/dell gpu", ge.cpu().numpy(), "oracle", rq)
+    assert np.allclose(ge.cpu().numpy(), rq, rtol=1e-7)
