@@ -273,13 +273,17 @@ def run_batch(count=64, nworkers=8):
                            int(np.prod(r["shape"])) * (o["cg_iters"] + o["pcg_iters"])
                            for r, o in zip(rves, out)) / dt, 1),
                        converged=sum(o["converged"] for o in out))
+    tiles = {}
+    for r, sv in zip(rves, b.solvers):
+        tiles.setdefault(str(r["shape"][0]), list(sv.tile_config()[:2]))
     b.close()
     log("[batch] %d RVEs, %d voxels: one at a time %.2f s, %d workers %.2f s" % (
         count, vox, res[1]["seconds"], nworkers, res[nworkers]["seconds"]))
     return dict(rves=count, voxels=vox, sizes=[32, 48, 64, 96], form="fp32_refined",
                 increment="E11 = 1e-3 from the virgin state", one_at_a_time=res[1],
                 batched=dict(res[nworkers], workers=nworkers),
-                speedup=round(res[1]["seconds"] / res[nworkers]["seconds"], 3))
+                speedup=round(res[1]["seconds"] / res[nworkers]["seconds"], 3),
+                tile_shifts_by_edge=tiles)
 
 
 def run_gtn(name="gtn_spheres30_128", steps=6):

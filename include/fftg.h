@@ -422,6 +422,16 @@ const char* fftg_kernel_name(int id);
  * fftg_apply_galerkin needs a new fftg_constitutive afterwards. */
 fftg_status fftg_time_kernel(fftg_handle* h, int kid, int reps, double* avg_ms);
 
+/* Tile autotuner result of this handle.  At creation the library times the
+ * inner y pass and the outer inverse Galerkin pass back to back with tile
+ * budgets of 32, 16 and 8 KB (shift 0, 1, 2) and keeps the fastest (a smaller
+ * tile only when >= 3% faster; results are bitwise identical for every
+ * choice).  times_ms (may be NULL) receives 6 averages: y pass shifts 0..2,
+ * then outer pass shifts 0..2 (0 where not timed).  The environment variable
+ * FFTG_TILE_SHIFT=0|1|2 fixes both shifts instead of timing. */
+fftg_status fftg_tile_config(const fftg_handle* h, int* yz_shift, int* outer_shift,
+                             double* times_ms);
+
 /* HBM reference rate: a streaming copy of nbytes (a multiple of 16, both
  * pointers 16-byte aligned, dev) from src to dst with one 16-byte load and
  * store per lane, `reps` back-to-back copies between one event pair on the

@@ -139,6 +139,8 @@ def load_library():
     lib.fftg_last_error.restype = ct.c_char_p
     lib.fftg_profile.argtypes = [P, I, ct.POINTER(ct.c_double), ct.POINTER(ct.c_longlong)]
     lib.fftg_profile.restype = ct.c_int
+    lib.fftg_tile_config.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(ct.c_double)]
+    lib.fftg_tile_config.restype = ct.c_int
     lib.fftg_copy_rate.argtypes = [P, P, P, ct.c_longlong, I, ct.POINTER(ct.c_double)]
     lib.fftg_copy_rate.restype = ct.c_int
     lib.fftg_time_kernel.argtypes = [P, I, I, ct.POINTER(ct.c_double)]
@@ -406,6 +408,13 @@ class Solver:
         self._check(self.lib.fftg_ell2(self.h, _ptr(phase, self.torch.uint8, self.N, "phase"),
                                        phase_table(table), len(table), int(field),
                                        _ptr(ell2, self.torch.float64, self.N, "ell2")))
+
+    def tile_config(self):
+        """(yz_shift, outer_shift, times_ms[6]) chosen by the tile autotuner."""
+        a, b = ct.c_int(), ct.c_int()
+        t = (ct.c_double * 6)()
+        self._check(self.lib.fftg_tile_config(self.h, ct.byref(a), ct.byref(b), t))
+        return a.value, b.value, list(t)
 
     def fftg_copy_rate(self, src, dst, reps=20):
         """GB/s of the library's streaming copy src -> dst (same-size tensors)."""

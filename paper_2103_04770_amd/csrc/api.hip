@@ -99,6 +99,10 @@ struct fftg_handle {
   double* drive_bak = nullptr;
   double* adj_r = nullptr;  // adjoint: two FP64 real scratch fields
   double* sadj = nullptr;   // staggered adjoint: (2c + 5J) FP64 real fields
+  // tile-budget shifts of the fixed-length strided passes (inner y passes,
+  // outer-axis passes), chosen at creation by timing; times of each choice
+  int tsh_y = 0, tsh_o = 0;
+  double tune_ms[2][3] = {{0, 0, 0}, {0, 0, 0}};
   int sadjJ = 0;
   size_t drive_bak_n = 0;
   hipEvent_t ev[8]{};
@@ -307,6 +311,10 @@ void read_sums(fftg_handle* H, int nb, int nred, double* out) {
   for (int i = 0; i < nred; ++i) out[i] = H->hsums[i];
 }
 
+// tile shift of a strided pass along plan axis a (1 = y, 2 = z): the outer
+// axis (z in 3D, y in 2D) takes the outer-pass choice, y in 3D the inner one
+int tsh(const fftg_handle* H, int a) { return a == (H->g.ndim == 3 ? 2 : 1) ? H->tsh_o : H->tsh_y; }
+
 // ------------------------------------------------------------ 3D transforms
 template <typename T>
 void fwd3(fftg_handle* H, int ncomp, const T* in, cpx<T>* out, const KrylovCtl* ctl = nullptr) {
@@ -319,13 +327,13 @@ void fwd3(fftg_handle* H, int ncomp, const T* in, cpx<T>* out, const KrylovCtl* 
   if (g.n2 > 1) {
     KT t(H, K_TR_YZ);
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), out, (long long)ncomp * g.n3 * g.n1h, g.n1h,
-                            (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st);
+                            (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st, tsh(H, 1));
   }
   if (g.n3 > 1) {
     KT t(H, K_TR_YZ);
     fftg::launch_strided<T>(H->plan[2], TW<T>(H, 2), out, (long long)ncomp * g.n2 * g.n1h,
                             (long long)g.n2 * g.n1h, g.Ns, (long long)g.n2 * g.n1h, true, ctl,
-                            H->st);
+                            H->st, tsh(H, 2));
   }
 }
 
@@ -337,12 +345,12 @@ void inv3(fftg_handle* H, int ncomp, cpx<T>* in, TO* out, T scale, bool acc) {
     KT t(H, K_TR_YZ);
     fftg::launch_strided<T>(H->plan[2], TW<T>(H, 2), in, (long long)ncomp * g.n2 * g.n1h,
                             (long long)g.n2 * g.n1h, g.Ns, (long long)g.n2 * g.n1h, false,
-                            nullptr, H->st);
+                            nullptr, H->st, tsh(H, 2));
   }
   if (g.n2 > 1) {
     KT t(H, K_TR_YZ);
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), in, (long long)ncomp * g.n3 * g.n1h, g.n1h,
-                            (long long)g.n2 * g.n1h, g.n1h, false, nullptr, H->st);
+                            (long long)g.n2 * g.n1h, g.n1h, false, nullptr, H->st, tsh(H, 1));
   }
   KT t(H, K_TR_X);
   fftg::launch_x_c2r<T, TO>(H->plan[0], TW<T>(H, 0), in, out, (long long)ncomp * g.n2 * g.n3,
@@ -356,7 +364,7 @@ void inner_inv(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int k
   KT t(H, kid);
   if (g.ndim == 3 && g.n2 > 1)
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), w, (long long)ncomp * g.n3 * g.n1h, g.n1h,
-                            (long long)g.n2 * g.n1h, g.n1h, false, ctl, H->st);
+                            (long long)g.n2 * g.n1h, g.n1h, false, ctl, H->st, H->tsh_y);
 }
 template <typename T>
 void inner_fwd(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int kid) {
@@ -364,7 +372,7 @@ void inner_fwd(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int k
   KT t(H, kid);
   if (g.ndim == 3 && g.n2 > 1)
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), w, (long long)ncomp * g.n3 * g.n1h, g.n1h,
-                            (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st);
+                            (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st, H->tsh_y);
 }
 int outer_axis(fftg_handle* H) { return H->g.ndim == 3 ? 2 : 1; }
 
@@ -452,7 +460,7 @@ void gal_iteration(fftg_handle* H, const unsigned char* mask) {
   {
     KT t(H, K_GAL_OI);
     fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr), C<T>(H->kp),
-                                C<T>(H->kx), C<T>(H->kw), H->ctl, H->st);
+                                C<T>(H->kx), C<T>(H->kw), H->ctl, H->st, H->tsh_o);
   }
   inner_inv<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YI);
   {
@@ -1140,7 +1148,47 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
   return out;
 }
 
+// Tile autotuner: time the inner y pass and the outer inverse Galerkin pass
+// back to back with each tile budget (32, 16, 8 KB for the fixed-length
+// kernels) and keep the fastest; a smaller budget is taken only when it is at
+// least 3% faster.  The per-line arithmetic does not depend on the tile, so
+// results are bitwise the same for every choice.  FFTG_TILE_SHIFT=0|1|2 fixes
+// the choice instead.
+void tune_tiles(fftg_handle* H) {
+  const char* e = std::getenv("FFTG_TILE_SHIFT");
+  if (e && e[0] >= '0' && e[0] <= '2' && e[1] == '\0') {
+    H->tsh_y = H->tsh_o = e[0] - '0';
+    return;
+  }
+  const int kids[2] = {K_GAL_YI, K_GAL_OI};
+  for (int k = 0; k < 2; ++k) {
+    int& sh = k == 0 ? H->tsh_y : H->tsh_o;
+    if (k == 0 && !(H->g.ndim == 3 && H->g.n2 > 1)) continue;  // no inner pass
+    int best = 0;
+    for (int v = 0; v < 3; ++v) {
+      sh = v;
+      double ms = 0.0;
+      if (fftg_time_kernel(H, kids[k], 10, &ms) != FFTG_OK || !(ms > 0.0)) ms = HUGE_VAL;
+      H->tune_ms[k][v] = ms;
+      if (ms < 0.97 * H->tune_ms[k][best]) best = v;
+    }
+    sh = best;
+  }
+  H->err.clear();
+}
+
 extern "C" {
+
+fftg_status fftg_tile_config(const fftg_handle* H, int* yz_shift, int* outer_shift,
+                             double* times_ms) {
+  if (!H || !yz_shift || !outer_shift) return FFTG_E_INVALID;
+  *yz_shift = H->tsh_y;
+  *outer_shift = H->tsh_o;
+  if (times_ms)
+    for (int k = 0; k < 2; ++k)
+      for (int v = 0; v < 3; ++v) times_ms[3 * k + v] = H->tune_ms[k][v];
+  return FFTG_OK;
+}
 
 fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** out) {
   g_create_error.clear();
@@ -1257,6 +1305,7 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
     HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
     return FFTG_OK;
   });
+  if (rc == FFTG_OK) tune_tiles(H);
   if (rc != FFTG_OK) {
     g_create_error = H->err;
     destroy(H);
@@ -1363,7 +1412,7 @@ fftg_status fftg_time_kernel(fftg_handle* H, int kid, int reps, double* avg_ms) 
           break;
         case K_GAL_OI:
           fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr),
-                                      C<T>(H->kp), C<T>(H->kx), C<T>(H->kw), H->ctl, H->st);
+                                      C<T>(H->kp), C<T>(H->kx), C<T>(H->kw), H->ctl, H->st, H->tsh_o);
           break;
         case K_GAL_OF:
           fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
@@ -1503,11 +1552,11 @@ fftg_status fftg_apply_galerkin(fftg_handle* H, const fftg_macro* tgt, const dou
     if (g.ndim == 3)
       fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
                                    (long long)c * g.n2 * g.n1h, (long long)g.n2 * g.n1h, g.Ns,
-                                   (long long)g.n2 * g.n1h, false, nullptr, H->st);
+                                   (long long)g.n2 * g.n1h, false, nullptr, H->st, H->tsh_o);
     else
       fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
                                    (long long)c * g.n1h, g.n1h, g.Ns, g.n1h, false, nullptr,
-                                   H->st);
+                                   H->st, H->tsh_o);
     inner_inv<double>(H, c, C<double>(H->kw), nullptr, K_GAL_YI);
     fftg::launch_x_fused_gal<double, double>(H->plan[0], TW<double>(H, 0), g, c, C<double>(H->kw),
                                              reinterpret_cast<const double*>(H->tan),
@@ -1516,11 +1565,11 @@ fftg_status fftg_apply_galerkin(fftg_handle* H, const fftg_macro* tgt, const dou
     if (g.ndim == 3)
       fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
                                    (long long)c * g.n2 * g.n1h, (long long)g.n2 * g.n1h, g.Ns,
-                                   (long long)g.n2 * g.n1h, true, nullptr, H->st);
+                                   (long long)g.n2 * g.n1h, true, nullptr, H->st, H->tsh_o);
     else
       fftg::launch_strided<double>(H->plan[oa], TW<double>(H, oa), C<double>(H->kw),
                                    (long long)c * g.n1h, g.n1h, g.Ns, g.n1h, true, nullptr,
-                                   H->st);
+                                   H->st, H->tsh_o);
     fftg::launch_project<double>(g, c, H->S64, tgt->mask, C<double>(H->kw), H->st);
     inv3<double, double>(H, c, C<double>(H->kw), out, 1.0 / (double)g.N, false);
     check_launch();

@@ -354,16 +354,18 @@ __device__ __forceinline__ long long line_base(long long L, long long inner, lon
   return (L / inner) * ostride + (L % inner);
 }
 
-template <typename T, bool FWD, int NF>
+// SH: tile budget FFTG_TILE_BYTES >> SH (chosen per handle by timing).
+template <typename T, bool FWD, int NF, int SH>
 FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __restrict__ data,
                            long long nlines, long long inner, long long ostride, long long es,
                            int TL_rt, const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? fs_tile<T>(NF) * NF : LDS_ELEMS];
+  constexpr int TB = FFTG_TILE_BYTES >> SH;
+  __shared__ cpx<T> buf[FIX ? fs_tile<T, TB>(NF) * NF : LDS_ELEMS];
   constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
   const int n = FIX ? NF : plan.n;
-  const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
+  const int TL = FIX ? fs_tile<T, TB>(NF) : TL_rt;
   // TL divides NT: each thread stays on line l of the tile
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
@@ -371,7 +373,7 @@ FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>
   for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? data[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, FWD, true, NF, fs_tile<T>(NF), fs_tile<T>(NF), NT>(buf, tw);
+    lds_fft_c<T, FWD, true, NF, fs_tile<T, TB>(NF), fs_tile<T, TB>(NF), NT>(buf, tw);
   else
     lds_fft<T, FWD, true>(buf, plan, TL, TL, tw);
   if (lb >= 0)
@@ -380,7 +382,7 @@ FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>
 
 // Outer-axis inverse pass of the Galerkin CG (per component):
 //   p <- r + beta p ; x <- x + alpha p_old ; w <- inverse transform of p.
-template <typename T, int NF>
+template <typename T, int NF, int SH>
 FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
                                const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
                                cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
@@ -388,11 +390,12 @@ FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl->done) return;
   constexpr bool FIX = NF > 0;
+  constexpr int TB = FFTG_TILE_BYTES >> SH;
   const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
-  __shared__ cpx<T> buf[FIX ? fs_tile<T>(NF) * NF : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? fs_tile<T, TB>(NF) * NF : LDS_ELEMS];
   constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
   const int n = FIX ? NF : plan.n;
-  const int TL = FIX ? fs_tile<T>(NF) : TL_rt;
+  const int TL = FIX ? fs_tile<T, TB>(NF) : TL_rt;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
@@ -409,7 +412,7 @@ FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, true, NF, fs_tile<T>(NF), fs_tile<T>(NF), NT>(buf, tw);
+    lds_fft_c<T, false, true, NF, fs_tile<T, TB>(NF), fs_tile<T, TB>(NF), NT>(buf, tw);
   else
     lds_fft<T, false, true>(buf, plan, TL, TL, tw);
   if (lb >= 0)
@@ -1724,21 +1727,38 @@ static inline int tile_lines(int n, int ncomp) {
   return tl;
 }
 
+// tile-budget shift of the fixed-length strided kernels (0, 1, 2)
+#define FFTG_DISPATCH_SH(sh, ...)   \
+  switch (sh) {                     \
+    case 1: {                       \
+      constexpr int SH = 1;         \
+      __VA_ARGS__;                  \
+    } break;                        \
+    case 2: {                       \
+      constexpr int SH = 2;         \
+      __VA_ARGS__;                  \
+    } break;                        \
+    default: {                      \
+      constexpr int SH = 0;         \
+      __VA_ARGS__;                  \
+    }                               \
+  }
+
 template <typename T>
 void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nlines,
                     long long inner, long long ostride, long long es, bool fwd,
-                    const KrylovCtl* ctl, hipStream_t st) {
-  FFTG_DISPATCH_N(p.n, {
-    const int TL = NF ? fs_tile<T>(NF) : tile_lines(p.n, 1);
+                    const KrylovCtl* ctl, hipStream_t st, int sh) {
+  FFTG_DISPATCH_N(p.n, FFTG_DISPATCH_SH(NF ? sh : 0, {
+    const int TL = NF ? fs_tile<T, (FFTG_TILE_BYTES >> SH)>(NF) : tile_lines(p.n, 1);
     const int NT = NF ? kStridedThreads : FFT_THREADS;
     const long long nb = (nlines + TL - 1) / TL;
     if (fwd)
-      hipLaunchKernelGGL((k_strided<T, true, NF>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw,
+      hipLaunchKernelGGL((k_strided<T, true, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw,
                          data, nlines, inner, ostride, es, TL, ctl);
     else
-      hipLaunchKernelGGL((k_strided<T, false, NF>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw,
-                         data, nlines, inner, ostride, es, TL, ctl);
-  })
+      hipLaunchKernelGGL((k_strided<T, false, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p,
+                         tw, data, nlines, inner, ostride, es, TL, ctl);
+  }))
 }
 
 // outer axis line geometry for a c-component spectrum
@@ -1760,17 +1780,17 @@ static inline void outer_lines(const Geo& g, int ncomp, bool zouter, long long& 
 template <typename T>
 int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, const KrylovCtl* ctl,
-                       hipStream_t st) {
+                       hipStream_t st, int sh) {
   long long nl, inner, os, es;
   outer_lines(g, c, zouter, nl, inner, os, es);
   long long nb = 0;
-  FFTG_DISPATCH_N(p.n, {
-    const int TL = NF ? fs_tile<T>(NF) : tile_lines(p.n, 1);
+  FFTG_DISPATCH_N(p.n, FFTG_DISPATCH_SH(NF ? sh : 0, {
+    const int TL = NF ? fs_tile<T, (FFTG_TILE_BYTES >> SH)>(NF) : tile_lines(p.n, 1);
     const int NT = NF ? kStridedThreads : FFT_THREADS;
     nb = (nl + TL - 1) / TL;
-    hipLaunchKernelGGL((k_gal_dir_inv<T, NF>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw, r, pp,
-                       x, w, nl, inner, os, es, TL, ctl);
-  })
+    hipLaunchKernelGGL((k_gal_dir_inv<T, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw, r,
+                       pp, x, w, nl, inner, os, es, TL, ctl);
+  }))
   return (int)nb;
 }
 
@@ -2104,9 +2124,11 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st) {
   template void launch_x_r2c<T>(const Plan&, const cpx<T>*, const T*, cpx<T>*, long long, int,  \
                                 int, hipStream_t);                                               \
   template void launch_strided<T>(const Plan&, const cpx<T>*, cpx<T>*, long long, long long,     \
-                                  long long, long long, bool, const KrylovCtl*, hipStream_t);    \
+                                  long long, long long, bool, const KrylovCtl*, hipStream_t,     \
+                                  int);                                                          \
   template int launch_gal_dir_inv<T>(const Plan&, const cpx<T>*, const Geo&, int, bool, cpx<T>*, \
-                                     cpx<T>*, cpx<T>*, cpx<T>*, const KrylovCtl*, hipStream_t);  \
+                                     cpx<T>*, cpx<T>*, cpx<T>*, const KrylovCtl*, hipStream_t,   \
+                                     int);                                                       \
   template int launch_gal_dot_fwd<T>(const Plan&, const cpx<T>*, const Geo&, int, bool,          \
                                      const cpx<T>*, cpx<T>*, double*, const KrylovCtl*,          \
                                      hipStream_t);                                               \

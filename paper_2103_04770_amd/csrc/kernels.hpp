@@ -76,13 +76,13 @@ void launch_x_c2r(const Plan& p, const cpx<T>* tw, const cpx<T>* in, TO* out, lo
 template <typename T>
 void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nlines,
                     long long inner, long long ostride, long long es, bool fwd,
-                    const KrylovCtl* ctl, hipStream_t st);
+                    const KrylovCtl* ctl, hipStream_t st, int sh = 0);
 
 // Galerkin CG passes
 template <typename T>
 int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, const KrylovCtl* ctl,
-                       hipStream_t st);
+                       hipStream_t st, int sh = 0);
 template <typename T>
 int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        const cpx<T>* pp, cpx<T>* w, double* partials, const KrylovCtl* ctl,

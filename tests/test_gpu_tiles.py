@@ -1,0 +1,75 @@
+"""The tile autotuner: valid choices, and bitwise-identical results for every
+tile budget of the strided passes."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2103_04770_amd import microstructure as ms  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(shape_np, shift=None, **kw):
+    from paper_2103_04770_amd import Solver
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    old = os.environ.pop("FFTG_TILE_SHIFT", None)
+    if shift is not None:
+        os.environ["FFTG_TILE_SHIFT"] = str(shift)
+    try:
+        return Solver(tuple(reversed(shape_np)), **kw)
+    finally:
+        os.environ.pop("FFTG_TILE_SHIFT", None)
+        if old is not None:
+            os.environ["FFTG_TILE_SHIFT"] = old
+
+
+@pytest.mark.parametrize("shape,fp32", [((32, 32, 32), True), ((48, 48, 48), False),
+                                        ((64, 64, 64), False), ((24, 36), False)])
+def test_autotuner_choices(shape, fp32):
+    from paper_2103_04770_amd import FP32_REFINED
+    kw = dict(prec=FP32_REFINED) if fp32 else {}
+    s = _solver(shape, **kw)
+    y, o, t = s.tile_config()
+    say("tiles", shape, "fp32" if fp32 else "fp64", "y", y, "outer", o, ["%.4f" % v for v in t])
+    assert y in (0, 1, 2) and o in (0, 1, 2)
+    assert all(v > 0 for v in t[3:])
+    if len(shape) == 3:
+        assert all(v > 0 for v in t[:3])
+    s.close()
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_results_do_not_depend_on_the_tile(fp32):
+    """One staggered increment with every strided pass at tile shift 0 and at
+    shift 2: states, stresses and iteration counts bitwise equal."""
+    from paper_2103_04770_amd import FP32_REFINED
+    w = ms.workload("spheres_two_fields_16")
+    w["table"][0]["dC"], w["table"][0]["dR"] = 0.0005, 0.02
+    shape, J = w["shape"], w["nfields"]
+    kw = dict(prec=FP32_REFINED) if fp32 else {}
+    ph = torch.from_numpy(w["phase"]).cuda()
+    out = []
+    for shift in (0, 2):
+        s = _solver(shape, shift=shift, **kw)
+        assert s.tile_config()[:2] == (shift, shift)
+        state = torch.zeros((6 + 7 + 2 * J,) + shape, dtype=torch.float64, device="cuda")
+        sig = torch.empty((6,) + shape, dtype=torch.float64, device="cuda")
+        d = None
+        for e11 in (3e-3, 6e-3):
+            d = s.staggered_step(ph, w["table"], J, state, ms.uniaxial_mixed(3, e11), sig)
+        torch.cuda.synchronize()
+        out.append((state.cpu().numpy(), sig.cpu().numpy(), d))
+        s.close()
+    (a, sa, da), (b, sb, db) = out
+    assert np.array_equal(a, b) and np.array_equal(sa, sb)
+    for k in ("cg_iters", "pcg_iters", "newton_iters", "stagger_iters"):
+        assert da[k] == db[k]
