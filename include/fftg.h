@@ -256,7 +256,8 @@ fftg_status fftg_solve_adjoint(fftg_handle* h, const unsigned char* phase, const
  *   z = h + D' (sigma_eff : A^-1 G*(alpha'^T L^-1 z)),
  *   h = D' ((mu0 - g_sig) : sigma_eff + g_D) + g_abar,  mu0 = A^-1 G*(g_eps + K g_sig),
  * iterated (one Helmholtz PCG per field and one Galerkin CG per pass) until
- * ||z_new - z|| <= tol ||z_new|| or maxit passes (then FFTG_NOT_CONVERGED).
+ * ||z_new - z|| <= tol ||z_new|| or maxit passes (then FFTG_NOT_CONVERGED, as
+ * when an inner Krylov solve stops at its own maxit).
  *   state_n    dev packed state at t_n (staggered_step's input)
  *   state_np1  dev packed state at t_{n+1} (its output): eps and abar are read
  * stats: cg_iters, pcg_iters, stagger_iters = passes, err = last change.
@@ -424,11 +425,11 @@ fftg_status fftg_time_kernel(fftg_handle* h, int kid, int reps, double* avg_ms);
 
 /* Tile autotuner result of this handle.  At creation the library times the
  * inner y pass and the outer inverse Galerkin pass back to back with tile
- * budgets of 32, 16 and 8 KB (shift 0, 1, 2) and keeps the fastest (a smaller
- * tile only when >= 3% faster; results are bitwise identical for every
- * choice).  times_ms (may be NULL) receives 6 averages: y pass shifts 0..2,
- * then outer pass shifts 0..2 (0 where not timed).  The environment variable
- * FFTG_TILE_SHIFT=0|1|2 fixes both shifts instead of timing. */
+ * budgets of 32, 16, 8 and 64 KB (codes 0, 1, 2, 3) and keeps the fastest
+ * (another than 32 KB only when >= 3% faster; results are bitwise identical
+ * for every choice).  times_ms (may be NULL) receives 8 averages: y pass codes
+ * 0..3, then outer pass codes 0..3 (0 where not timed).  The environment
+ * variable FFTG_TILE_SHIFT=0|1|2|3 fixes both codes instead of timing. */
 fftg_status fftg_tile_config(const fftg_handle* h, int* yz_shift, int* outer_shift,
                              double* times_ms);
 

@@ -410,9 +410,10 @@ class Solver:
                                        _ptr(ell2, self.torch.float64, self.N, "ell2")))
 
     def tile_config(self):
-        """(yz_shift, outer_shift, times_ms[6]) chosen by the tile autotuner."""
+        """(yz_code, outer_code, times_ms[8]) chosen by the tile autotuner
+        (codes 0..3 = 32, 16, 8, 64 KB tiles)."""
         a, b = ct.c_int(), ct.c_int()
-        t = (ct.c_double * 6)()
+        t = (ct.c_double * 8)()
         self._check(self.lib.fftg_tile_config(self.h, ct.byref(a), ct.byref(b), t))
         return a.value, b.value, list(t)
 

@@ -102,7 +102,7 @@ struct fftg_handle {
   // tile-budget shifts of the fixed-length strided passes (inner y passes,
   // outer-axis passes), chosen at creation by timing; times of each choice
   int tsh_y = 0, tsh_o = 0;
-  double tune_ms[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  double tune_ms[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
   int sadjJ = 0;
   size_t drive_bak_n = 0;
   hipEvent_t ev[8]{};
@@ -1149,14 +1149,14 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
 }
 
 // Tile autotuner: time the inner y pass and the outer inverse Galerkin pass
-// back to back with each tile budget (32, 16, 8 KB for the fixed-length
-// kernels) and keep the fastest; a smaller budget is taken only when it is at
-// least 3% faster.  The per-line arithmetic does not depend on the tile, so
-// results are bitwise the same for every choice.  FFTG_TILE_SHIFT=0|1|2 fixes
-// the choice instead.
+// back to back with each tile budget (code 0..3 = 32, 16, 8, 64 KB for the
+// fixed-length kernels) and keep the fastest; another budget than 32 KB is
+// taken only when it is at least 3% faster.  The per-line arithmetic does not
+// depend on the tile, so results are bitwise the same for every choice.
+// FFTG_TILE_SHIFT=0|1|2|3 fixes the choice instead.
 void tune_tiles(fftg_handle* H) {
   const char* e = std::getenv("FFTG_TILE_SHIFT");
-  if (e && e[0] >= '0' && e[0] <= '2' && e[1] == '\0') {
+  if (e && e[0] >= '0' && e[0] <= '3' && e[1] == '\0') {
     H->tsh_y = H->tsh_o = e[0] - '0';
     return;
   }
@@ -1165,7 +1165,7 @@ void tune_tiles(fftg_handle* H) {
     int& sh = k == 0 ? H->tsh_y : H->tsh_o;
     if (k == 0 && !(H->g.ndim == 3 && H->g.n2 > 1)) continue;  // no inner pass
     int best = 0;
-    for (int v = 0; v < 3; ++v) {
+    for (int v = 0; v < 4; ++v) {
       sh = v;
       double ms = 0.0;
       if (fftg_time_kernel(H, kids[k], 10, &ms) != FFTG_OK || !(ms > 0.0)) ms = HUGE_VAL;
@@ -1186,7 +1186,7 @@ fftg_status fftg_tile_config(const fftg_handle* H, int* yz_shift, int* outer_shi
   *outer_shift = H->tsh_o;
   if (times_ms)
     for (int k = 0; k < 2; ++k)
-      for (int v = 0; v < 3; ++v) times_ms[3 * k + v] = H->tune_ms[k][v];
+      for (int v = 0; v < 4; ++v) times_ms[4 * k + v] = H->tune_ms[k][v];
   return FFTG_OK;
 }
 
@@ -1755,11 +1755,13 @@ fftg_status fftg_staggered_adjoint(fftg_handle* H, const unsigned char* phase,
     }
     fftg_stats acc{};
     int status = 0;
+    bool inner_capped = false;  // an inner Krylov solve stopped at its maxit
     auto mech = [&](const double* gb, const double* gs) {
       const int it = H->fp32() ? mech_adjoint<float>(H, phase, t, J, H->Dj, epsp_n, target, eps, gb,
                                                      gs, mu, dD, cg, status)
                                : mech_adjoint<double>(H, phase, t, J, H->Dj, epsp_n, target, eps,
                                                       gb, gs, mu, dD, cg, status);
+      inner_capped = inner_capped || status == 2;
       acc.cg_iters += it;
       acc.newton_iters += 1;
     };
@@ -1775,6 +1777,7 @@ fftg_status fftg_staggered_adjoint(fftg_handle* H, const unsigned char* phase,
                                 -1.0, x + j * N, pcg->tol, pcg->maxit, it, rel, st);
         if (st == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
         if (st == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+        inner_capped = inner_capped || st == 2;
         acc.pcg_iters += it;
       }
     };
@@ -1821,7 +1824,7 @@ fftg_status fftg_staggered_adjoint(fftg_handle* H, const unsigned char* phase,
       stats->err = err;
       stats->t_ms[3] = wall_ms(t0);
     }
-    return converged ? FFTG_OK : FFTG_NOT_CONVERGED;
+    return converged && !inner_capped ? FFTG_OK : FFTG_NOT_CONVERGED;
   });
 }
 

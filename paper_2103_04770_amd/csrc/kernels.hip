@@ -354,14 +354,19 @@ __device__ __forceinline__ long long line_base(long long L, long long inner, lon
   return (L / inner) * ostride + (L % inner);
 }
 
-// SH: tile budget FFTG_TILE_BYTES >> SH (chosen per handle by timing).
+// SH: tile budget code (chosen per handle by timing): FFTG_TILE_BYTES >> SH
+// for SH = 0, 1, 2, twice FFTG_TILE_BYTES for SH = 3 (gfx950 workgroups may
+// hold up to 160 KB of LDS).
+template <int SH>
+constexpr int tile_budget() { return SH == 3 ? 2 * FFTG_TILE_BYTES : FFTG_TILE_BYTES >> SH; }
+
 template <typename T, bool FWD, int NF, int SH>
 FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __restrict__ data,
                            long long nlines, long long inner, long long ostride, long long es,
                            int TL_rt, const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  constexpr int TB = FFTG_TILE_BYTES >> SH;
+  constexpr int TB = tile_budget<SH>();
   __shared__ cpx<T> buf[FIX ? fs_tile<T, TB>(NF) * NF : LDS_ELEMS];
   constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
   const int n = FIX ? NF : plan.n;
@@ -390,7 +395,7 @@ FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
                                const KrylovCtl* __restrict__ ctl) {
   if (ctl->done) return;
   constexpr bool FIX = NF > 0;
-  constexpr int TB = FFTG_TILE_BYTES >> SH;
+  constexpr int TB = tile_budget<SH>();
   const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
   __shared__ cpx<T> buf[FIX ? fs_tile<T, TB>(NF) * NF : LDS_ELEMS];
   constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
@@ -1727,7 +1732,7 @@ static inline int tile_lines(int n, int ncomp) {
   return tl;
 }
 
-// tile-budget shift of the fixed-length strided kernels (0, 1, 2)
+// tile-budget code of the fixed-length strided kernels (0..3, tile_budget)
 #define FFTG_DISPATCH_SH(sh, ...)   \
   switch (sh) {                     \
     case 1: {                       \
@@ -1736,6 +1741,10 @@ static inline int tile_lines(int n, int ncomp) {
     } break;                        \
     case 2: {                       \
       constexpr int SH = 2;         \
+      __VA_ARGS__;                  \
+    } break;                        \
+    case 3: {                       \
+      constexpr int SH = 3;         \
       __VA_ARGS__;                  \
     } break;                        \
     default: {                      \
@@ -1749,7 +1758,7 @@ void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nli
                     long long inner, long long ostride, long long es, bool fwd,
                     const KrylovCtl* ctl, hipStream_t st, int sh) {
   FFTG_DISPATCH_N(p.n, FFTG_DISPATCH_SH(NF ? sh : 0, {
-    const int TL = NF ? fs_tile<T, (FFTG_TILE_BYTES >> SH)>(NF) : tile_lines(p.n, 1);
+    const int TL = NF ? fs_tile<T, tile_budget<SH>()>(NF) : tile_lines(p.n, 1);
     const int NT = NF ? kStridedThreads : FFT_THREADS;
     const long long nb = (nlines + TL - 1) / TL;
     if (fwd)
@@ -1785,7 +1794,7 @@ int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
   outer_lines(g, c, zouter, nl, inner, os, es);
   long long nb = 0;
   FFTG_DISPATCH_N(p.n, FFTG_DISPATCH_SH(NF ? sh : 0, {
-    const int TL = NF ? fs_tile<T, (FFTG_TILE_BYTES >> SH)>(NF) : tile_lines(p.n, 1);
+    const int TL = NF ? fs_tile<T, tile_budget<SH>()>(NF) : tile_lines(p.n, 1);
     const int NT = NF ? kStridedThreads : FFT_THREADS;
     nb = (nl + TL - 1) / TL;
     hipLaunchKernelGGL((k_gal_dir_inv<T, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw, r,
