@@ -43,10 +43,11 @@ class LoadDriver:
         self.records = []
         self.reason = None
 
-    def run(self, t_end=1.0, chunk=None, checkpoint=None, max_attempts=1000):
+    def run(self, t_end=1.0, chunk=None, checkpoint=None, max_attempts=1000, on_records=None):
         """Advance to t_end (or until the driver stops).  With `chunk`, the
         library is called for at most `chunk` accepted increments at a time and
-        the checkpoint (if a path is given) is rewritten after every call."""
+        the checkpoint (if a path is given) is rewritten after every call;
+        `on_records(records)` then receives each call's new records."""
         while True:
             out = self.solver.fftg_drive(self.phase, self.table, self.nfields, self.state,
                                          self.target_end, self.sigma, t=self.t, t_end=t_end,
@@ -56,6 +57,8 @@ class LoadDriver:
             self.records.extend(out["records"])
             if checkpoint:
                 self.save(checkpoint)
+            if on_records is not None:
+                on_records(out["records"])
             if out["reason"] != 3:   # not just a full record buffer
                 return out["reason"]
 

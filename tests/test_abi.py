@@ -81,3 +81,21 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert int(out[cname]) == ctypes.sizeof(cls), cname
         for f in fields or []:
             assert int(out["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)
+
+
+def test_run_config_round_trip_and_byte_model():
+    """The run configuration survives JSON, rejects unknown keys, and the
+    per-iteration byte model equals the fused-pass counts at 128^3."""
+    from paper_2103_04770_amd.run import RunConfig, bytes_per_iteration
+    cfg = RunConfig(workload="spheres64_20", e11_end=0.02, precision="fp32_refined",
+                    table_overrides=[{"dC": 0.001}], log="x.jsonl")
+    back = RunConfig.from_json(cfg.to_json())
+    assert back == cfg
+    with pytest.raises(ValueError):
+        RunConfig.from_json('{"workload": "spheres64_20", "bogus": 1}')
+    Ns, N = 128 * 128 * 65, 128 ** 3
+    g, h = bytes_per_iteration((128, 128, 128), "fp64")
+    assert g == 18 * 6 * Ns * 16 + 8 * N * 8
+    assert h == (6 + 12 + 8 + 5 + 3) * Ns * 16 + N * 8
+    g2, _ = bytes_per_iteration((32, 32), "fp32_refined")
+    assert g2 == 14 * 3 * 32 * 17 * 8 + 8 * 32 * 32 * 4

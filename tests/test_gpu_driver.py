@@ -133,3 +133,34 @@ def test_drive_rejects_bad_options():
     # nothing to do: already at the end
     out = s.fftg_drive(ph, table, 1, state, ms.uniaxial_mixed(3, 1e-3), sig, t=1.0)
     assert out["converged"] and out["records"] == [] and out["attempts"] == 0
+
+
+def test_json_runner_logs_every_increment(tmp_path):
+    """python -m paper_2103_04770_amd.run: one JSON line per accepted
+    increment, the same responses as the driver called directly."""
+    import json
+    from paper_2103_04770_amd import run as runmod
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("json runner")
+    cfg = runmod.RunConfig(workload="disc2d_32", e11_end=0.01, log=str(tmp_path / "r.jsonl"),
+                           checkpoint=str(tmp_path / "r.npz"), chunk=2,
+                           driver=dict(dt=0.25, dt_min=1e-3, grow=1.5))
+    reason, n = runmod.run(cfg)
+    lines = [json.loads(l) for l in open(cfg.log)]
+    say("  reason", reason, "increments", n, [round(l["t"], 4) for l in lines])
+    assert reason == 0 and n == len(lines) > 0
+    assert lines[-1]["t"] == 1.0 and all(len(l["sigma"]) == 3 for l in lines)
+    assert all(l["cg_iters"] > 0 and l["galerkin_bytes_per_iter"] > 0 for l in lines)
+    # the same path through fftg_drive directly
+    from paper_2103_04770_amd import Solver, microstructure as ms
+    w = ms.workload("disc2d_32")
+    s = Solver(tuple(reversed(w["shape"])))
+    state = torch.zeros((3 + 7 + 2,) + w["shape"], dtype=torch.float64, device="cuda")
+    sig = torch.zeros((3,) + w["shape"], dtype=torch.float64, device="cuda")
+    out = s.fftg_drive(torch.from_numpy(w["phase"]).cuda(), w["table"], 1, state,
+                       ms.uniaxial_mixed(2, 0.01), sig, dt=0.25, dt_min=1e-3, grow=1.5,
+                       **cfg.tolerances)
+    assert [r["t"] for r in out["records"]] == [l["t"] for l in lines]
+    for r, l in zip(out["records"], lines):
+        assert np.allclose(r["sigma"], l["sigma"], rtol=0, atol=0)

@@ -154,3 +154,34 @@ def test_not_converged_is_a_warning_with_last_iterate():
     assert not d["converged"] and d["pcg_iters"] == 1
     # one PCG step from zero: x = (r.z / p.Ap) z with z = M b
     assert np.isfinite(ab.cpu().numpy()).all() and np.abs(ab.cpu().numpy()).max() > 0
+
+
+def test_non_finite_input_is_reported():
+    """A NaN in the frozen damage makes the stress non-finite: FFTG_E_NONFINITE
+    (forced from the host; every kernel still runs to completion)."""
+    from paper_2103_04770_amd import FFTGError
+    shape = (8, 8, 8)
+    say("nan damage")
+    s = solver(shape)
+    phase = np.zeros(shape, np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0])]
+    D = np.zeros((1,) + shape)
+    D[0, 3, 4, 5] = np.nan
+    with pytest.raises(FFTGError) as e:
+        mech(s, shape, phase, table, 1, D, ms.uniaxial_mixed(3, 1e-3))
+    assert e.value.code == -5
+
+
+def test_zero_stiffness_is_a_breakdown():
+    """Fully damaged material (frozen D = 1, zero tangent) under an imposed
+    mean stress: p.Ap = 0 in the first CG step, FFTG_E_BREAKDOWN."""
+    from paper_2103_04770_amd import FFTGError
+    shape = (8, 8, 8)
+    say("zero stiffness")
+    s = solver(shape)
+    phase = np.zeros(shape, np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0])]
+    tgt = (np.ones(6, np.uint8), np.zeros(6), np.array([100.0, 0, 0, 0, 0, 0]))
+    with pytest.raises(FFTGError) as e:
+        mech(s, shape, phase, table, 1, np.ones((1,) + shape), tgt)
+    assert e.value.code == -4
