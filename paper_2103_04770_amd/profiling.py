@@ -127,11 +127,13 @@ def counters(fetch_dir, write_dir, copy_mib, cmd):
         lines.append("%-46s %6d %14.1f %14.1f %12.1f" % (k[:46], nf, fb / 1e6, wb / 1e6,
                                                           (fb + wb) / 1e6))
         fc = classify(k)
-        if fc and fc[0]:
-            form, cls = fc
-            rec["kernels"]["%s/%s" % (form, cls)] = dict(bytes_per_launch=round(fb + wb),
-                                                         fetch_bytes=round(fb),
-                                                         write_bytes=round(wb))
+        key = "%s/%s" % fc if fc and fc[0] else None
+        # several instantiations share a class (grid lengths, tile budgets of
+        # the autotuner's trial launches): keep the one that moved the most
+        # bytes over the run, i.e. the benchmark's own (first in this order)
+        if key and key not in rec["kernels"]:
+            rec["kernels"][key] = dict(kernel=k, bytes_per_launch=round(fb + wb),
+                                       fetch_bytes=round(fb), write_bytes=round(wb))
     return "\n".join(lines) + "\n", rec
 
 
