@@ -300,3 +300,36 @@ def test_fp32_refined_staggered_matches_oracle_to_1e6():
         say("  homog err %.2e" % err)
         assert err <= 1e-6
         assert d["cg_iters"] < 20 * stats_o["cg_iters"]
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16), (24, 18)])
+def test_staggered_spectral_scheme_and_voxel_size(shape):
+    """Two staggered increments with the SPECTRAL derivative symbols and a
+    voxel size h = 0.5 (lengths in the same unit), damage active: states and
+    homogenised stress against the oracle run with the same scheme and h."""
+    from paper_2103_04770_amd import SPECTRAL
+    say("staggered spectral h=0.5", shape)
+    rng = np.random.default_rng(17)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[1.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.25])]
+    nd = len(shape)
+    c = 6 if nd == 3 else 3
+    tols = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11, stagger_tol=1e-10)
+    s = solver(shape, scheme=SPECTRAL, h=0.5)
+    st_o = staggered.initial_state(shape, nd, 1)
+    state = dev(np.zeros((c + 7 + 2,) + shape))
+    sig = torch.empty((c,) + shape, dtype=torch.float64, device="cuda")
+    ph = dev(phase, torch.uint8)
+    for e11 in (3e-3, 4e-3):
+        tgt = ms.uniaxial_mixed(nd, e11)
+        st_o, sig_o, hom_o, stats_o = staggered.staggered_step(
+            phase, table, 1, st_o, tgt, h=0.5, scheme=spectral.SPECTRAL, max_stagger=60, **tols)
+        d = s.staggered_step(ph, table, 1, state, tgt, sig, max_stagger=60, **tols)
+        say("  e11", e11, "gpu", d["stagger_iters"], d["cg_iters"], "oracle", stats_o["stagger_iters"],
+            stats_o["cg_iters"])
+        assert d["converged"] and stats_o["converged"]
+        h = host(state)
+        assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-9 * abs(hom_o["sigma"][0])
+        assert relerr(h[:c], st_o["eps"]) <= 1e-9
+        assert relerr(h[c + 7 + 1:], st_o["abar"]) <= 1e-8
+    assert st_o["abar"].max() > table[0]["dC"]       # damage active
