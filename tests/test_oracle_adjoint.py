@@ -292,3 +292,30 @@ def test_staggered_adjoint_by_finite_differences(which):
         fd = (J(tp) - J(tm)) / (2 * hq)
         assert grad[q] == pytest.approx(fd, rel=2e-4, abs=1e-6 * abs(grad).max())
     assert r["iters"] > 2
+
+
+def test_staggered_adjoint_3d_by_finite_differences():
+    """The converged-increment adjoint in 3D (J = <sigma_11>) against central
+    differences of converged increments."""
+    from oracle import staggered
+    S = (6, 8, 8)
+    rng = np.random.default_rng(21)
+    phase = (rng.uniform(size=S) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    st_n, _, _, _ = _stag_increment(phase, table, staggered.initial_state(S, 3, 1), 3e-3)
+    st, _, _, stats = _stag_increment(phase, table, st_n, 5e-3)
+    assert stats["stagger_iters"] > 2
+    g = np.zeros((6,) + S)
+    g[0] = 1.0 / phase.size
+    r = adjoint.staggered_adjoint(phase, table, 1, st_n, st["eps"], st["abar"],
+                                  ms.uniaxial_mixed(3, 5e-3), g_sig=g)
+    grad = adjoint.phase_length_gradient(r["dell2"][0], phase, table, 0)
+    for q in range(2):
+        hq = 1e-4 * table[q]["ell"][0]
+        vals = []
+        for sgn in (1, -1):
+            tb = [dict(t) for t in table]
+            tb[q]["ell"] = [table[q]["ell"][0] + sgn * hq]
+            vals.append(_stag_increment(phase, tb, st_n, 5e-3)[2]["sigma"][0])
+        fd = (vals[0] - vals[1]) / (2 * hq)
+        assert grad[q] == pytest.approx(fd, rel=2e-4, abs=1e-6 * abs(grad).max())

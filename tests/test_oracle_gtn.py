@@ -269,3 +269,31 @@ def test_staggered_homogeneous_equals_local_porosity_driver():
         assert st["abar"][1].mean() == pytest.approx(ep[:3].sum(), rel=1e-8)
         epn, e0n, trn, fn = ep, e0, float(ep[:3].sum()), f
     assert fn > 0.01          # porosity did grow over the path
+
+
+def test_homogeneous_plane_strain_equals_one_point_driver():
+    """2D plane strain (eps33 = eps13 = eps23 = 0) with a frozen porosity:
+    the homogeneous Gurson RVE under E11 with sigma22 = sigma12 = 0 equals a
+    one-point driver solving sigma22(e22) = 0 on the 3D return map."""
+    m = _mat()
+    S = (4, 6)
+    phase = np.zeros(S, np.uint8)
+    for f, e11 in ((0.0, 4e-3), (0.12, 6e-3)):
+        D = np.zeros((2,) + S)
+        D[0] = f
+        out = galerkin.fftg_solve(phase, [m], D, np.zeros((6,) + S), np.zeros(S),
+                                  ms.uniaxial_mixed(2, e11), np.zeros((3,) + S),
+                                  cg_tol=1e-13, newton_tol=1e-12, newton_maxit=60, nfields=2)
+        assert out["converged"]
+
+        def ret(e22):
+            e = np.array([[e11], [e22], [0.0], [0.0], [0.0], [0.0]])
+            return gtn.return_map(e, np.zeros((6, 1)), np.zeros(1), np.array([f]), m)
+
+        e22 = brentq(lambda x: ret(x)[0][1, 0], -1.5 * e11, 0.5 * e11, xtol=1e-300, rtol=1e-15)
+        sig, ep, e0, _, _ = ret(e22)
+        assert out["sigma"][0].mean() == pytest.approx(sig[0, 0], rel=1e-10)
+        assert out["eps"][1].mean() == pytest.approx(e22, rel=1e-9)
+        assert out["kappa"].mean() == pytest.approx(e0[0], rel=1e-9, abs=1e-14)
+        # the out-of-plane stress the plane-strain constraint carries
+        assert sig[2, 0] != 0.0
