@@ -115,11 +115,16 @@ def mechanics_adjoint(phase, table, D, epsp_n, kappa_n, target, eps, gbar, nfiel
 
 
 def source_derivative(eps, epsp_n, kappa_n, phase, table, nfields):
-    """d alpha_j / d eps per voxel, (J, c, *S): for a j2_damage phase driven by
-    field j the source is eps_p(eq) = kappa_n + dk with
-    dk = (sqrt(3/2) ||s_tr|| - sy - H kappa_n)/(3 mu + H) where plastic, so
-    d alpha / d eps = sqrt(3/2) 2 mu n / (3 mu + H), n the unit deviatoric
-    trial direction (0 where elastic).  Cracking phases are not covered."""
+    """d alpha_j / d eps per voxel, (J, c, *S).
+
+    j2_damage phase driven by field j: the source is eps_p(eq) = kappa_n + dk
+    with dk = (sqrt(3/2) ||s_tr|| - sy - H kappa_n)/(3 mu + H) where plastic,
+    so d alpha / d eps = sqrt(3/2) 2 mu n / (3 mu + H), n the unit deviatoric
+    trial direction (0 where elastic).
+    elastic_cracking phase: the source is the Mazars equivalent strain
+    alpha = ||<eps>_+|| (positive part of the strain tensor), whose gradient
+    is <eps>_+ / alpha (alpha^2 / 2 has gradient <eps>_+); 0 where alpha = 0.
+    The positive part comes from numpy's symmetric eigen-solver."""
     c = eps.shape[0]
     S = eps.shape[1:]
     e6 = mandel.expand_plane(eps) if c == 3 else eps
@@ -128,7 +133,15 @@ def source_derivative(eps, epsp_n, kappa_n, phase, table, nfields):
     for p, ph in enumerate(table):
         j = ph["dfield"]
         if ph["model"] == "elastic_cracking" and j >= 0:
-            raise NotImplementedError("source derivative of the cracking phase")
+            sel = phase == p
+            T = mandel.to_tensor(e6[:, sel])                     # (3, 3, m)
+            w, V = np.linalg.eigh(np.moveaxis(T, -1, 0))       # (m, 3), (m, 3, 3)
+            wp = np.maximum(w, 0.0)
+            pos = np.einsum("mik,mk,mjk->ijm", V, wp, V)         # <eps>_+ (3, 3, m)
+            a = np.sqrt((wp * wp).sum(axis=1))
+            g = mandel.from_tensor(pos) / np.where(a > 0, a, 1.0)[None]
+            out[j][:, sel] += np.where(a > 0, 1.0, 0.0)[None] * g
+            continue
         if ph["model"] != "j2_damage" or j < 0:
             continue
         K, mu = material.lame(ph["E"], ph["nu"])

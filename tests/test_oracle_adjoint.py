@@ -319,3 +319,66 @@ def test_staggered_adjoint_3d_by_finite_differences():
             vals.append(_stag_increment(phase, tb, st_n, 5e-3)[2]["sigma"][0])
         fd = (vals[0] - vals[1]) / (2 * hq)
         assert grad[q] == pytest.approx(fd, rel=2e-4, abs=1e-6 * abs(grad).max())
+
+
+def test_cracking_source_derivative_by_finite_differences():
+    """d alpha / d eps of the Mazars equivalent strain (cracking phase)
+    against central differences of the constitutive sources, 3D and 2D."""
+    from oracle import material
+    rng = np.random.default_rng(4)
+    table = [ms.elastic_phase(70000.0, 0.3, ell=(1.0, 1.0)),
+             ms.particle_cracking(ell=[1.0, 1.0], dfield=1)]
+    for S, c in (((4, 5, 3), 6), ((5, 6), 3)):
+        phase = (rng.uniform(size=S) < 0.6).astype(np.uint8)
+        eps = rng.normal(scale=3e-3, size=(c,) + S)
+        z6, z = np.zeros((6,) + S), np.zeros(S)
+        D = np.zeros((2,) + S)
+        d = adjoint.source_derivative(eps, z6, z, phase, table, 2)
+        h = 1e-9
+        for k in range(c):
+            ep, em = eps.copy(), eps.copy()
+            ep[k] += h
+            em[k] -= h
+            fd = (material.constitutive(ep, z6, z, D, phase, table, 2)["alpha"]
+                  - material.constitutive(em, z6, z, D, phase, table, 2)["alpha"]) / (2 * h)
+            assert np.abs(fd[1] - d[1, k]).max() <= 1e-5 * np.abs(d[1]).max()
+        assert np.abs(d[1]).max() > 0 and np.abs(d[0]).max() == 0
+
+
+def test_staggered_adjoint_two_fields_by_finite_differences():
+    """The converged-increment adjoint with both sources of the benchmark
+    table (J2 damage matrix on field 0, particle cracking on field 1):
+    d<sigma_11>/d ell for every phase and field against central differences."""
+    from oracle import staggered
+    S = (10, 12)
+    rng = np.random.default_rng(23)
+    phase = (rng.uniform(size=S) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0, 0.04], dfield=0, dC=0.0005, dR=0.02),
+             ms.particle_cracking(ell=[0.04, 1.0], dfield=1, k0=5e-4, kf=5e-3)]
+
+    def inc(tab, st_n, e11):
+        st, sig, hom, stats = staggered.staggered_step(phase, tab, 2, st_n,
+                                                       ms.uniaxial_mixed(2, e11), **STAG_TOLS)
+        assert stats["converged"]
+        return st, hom
+
+    st_n, _ = inc(table, staggered.initial_state(S, 2, 2), 2e-3)
+    st, hom = inc(table, st_n, 3e-3)
+    assert st["abar"][1].max() > 5e-4        # cracking field past its threshold
+    g = np.zeros((3,) + S)
+    g[0] = 1.0 / phase.size
+    r = adjoint.staggered_adjoint(phase, table, 2, st_n, st["eps"], st["abar"],
+                                  ms.uniaxial_mixed(2, 3e-3), g_sig=g)
+    for j in range(2):
+        grad = adjoint.phase_length_gradient(r["dell2"][j], phase, table, j)
+        for q in range(2):
+            e0 = table[q]["ell"][j]
+            hq = 1e-4 * e0
+            vals = []
+            for sgn in (1, -1):
+                tb = [dict(t, ell=list(t["ell"])) for t in table]
+                tb[q]["ell"][j] = e0 + sgn * hq
+                vals.append(inc(tb, st_n, 3e-3)[1]["sigma"][0])
+            fd = (vals[0] - vals[1]) / (2 * hq)
+            assert grad[q] == pytest.approx(fd, rel=5e-4, abs=1e-5 * max(abs(grad).max(), 1e-9))
+
