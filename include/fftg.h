@@ -261,8 +261,9 @@ fftg_status fftg_solve_adjoint(fftg_handle* h, const unsigned char* phase, const
  *   state_n    dev packed state at t_n (staggered_step's input)
  *   state_np1  dev packed state at t_{n+1} (its output): eps and abar are read
  * stats: cg_iters, pcg_iters, stagger_iters = passes, err = last change.
- * Sources covered: the J2 damage matrix (d alpha/d eps of its return).  Tables
- * with a Gurson phase or a driven cracking phase: FFTG_E_UNSUPPORTED. */
+ * Sources covered: the J2 damage matrix (d alpha/d eps of its return) and the
+ * cracking phase (Mazars equivalent strain, gradient <eps>_+ / alpha).  Tables
+ * with a Gurson phase: FFTG_E_UNSUPPORTED. */
 fftg_status fftg_staggered_adjoint(fftg_handle* h, const unsigned char* phase,
                                    const fftg_phase* tab, int nphase, int nfields,
                                    const double* state_n, const double* state_np1,

@@ -1716,10 +1716,8 @@ fftg_status fftg_staggered_adjoint(fftg_handle* H, const unsigned char* phase,
     validate_macro(target, H->c);
     if (!phase || !state_n || !state_np1 || !dell2 || !cg || !pcg || nfields < 1 || maxit < 1)
       throw Fail{FFTG_E_INVALID, "fftg_staggered_adjoint: null pointer, no field or maxit < 1"};
-    for (int p = 0; p < nphase; ++p)
-      if (tab[p].model == FFTG_GTN || (tab[p].model == FFTG_ELASTIC_CRACKING && tab[p].dfield >= 0))
-        throw Fail{FFTG_E_UNSUPPORTED,
-                   "fftg_staggered_adjoint: Gurson and cracking sources are not covered"};
+    if (has_gtn(tab, nphase))
+      throw Fail{FFTG_E_UNSUPPORTED, "fftg_staggered_adjoint: Gurson sources are not covered"};
     auto t0 = std::chrono::steady_clock::now();
     const Geo& g = H->g;
     const int c = H->c, J = nfields;

@@ -1343,11 +1343,57 @@ FFTG_KERNEL void k_commit_hist(MatTable tab, long long N, int J,
   }
 }
 
+// Positive part <A>_+ of a symmetric 3x3 tensor (Mandel in and out) from its
+// eigenvalues l0 >= l1 >= l2 and the eigenprojection of the eigenvalue group
+// that is separated by the sign change:
+//   one positive (l0 > 0 >= l1):  <A>_+ = l0 (A - l1 I)(A - l2 I) / ((l0 - l1)(l0 - l2))
+//   two positive (l1 > 0 >= l2):  <A>_+ = A - l2 (A - l0 I)(A - l1 I) / ((l2 - l0)(l2 - l1))
+// The denominators are bounded below by l0^2 and l0 l1, so no gap between
+// eigenvalues of the same sign enters.
+__device__ void positive_part(const double e[6], const double lam[3], double out[6]) {
+  const double r2 = 1.4142135623730950488016887242097, ir2 = 0.70710678118654752440084436210485;
+  if (lam[2] >= 0.0) {
+    for (int i = 0; i < 6; ++i) out[i] = e[i];
+    return;
+  }
+  if (lam[0] <= 0.0) {
+    for (int i = 0; i < 6; ++i) out[i] = 0.0;
+    return;
+  }
+  const double A[3][3] = {{e[0], e[5] * ir2, e[4] * ir2},
+                          {e[5] * ir2, e[1], e[3] * ir2},
+                          {e[4] * ir2, e[3] * ir2, e[2]}};
+  const bool one = !(lam[1] > 0.0);
+  // product (A - a I)(A - b I) with the two other eigenvalues
+  const double a = one ? lam[1] : lam[0], b = one ? lam[2] : lam[1];
+  const double lk = one ? lam[0] : lam[2];
+  double M[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double sum = 0.0;
+      for (int k = 0; k < 3; ++k)
+        sum += (A[i][k] - (i == k ? a : 0.0)) * (A[k][j] - (k == j ? b : 0.0));
+      M[i][j] = sum;
+    }
+  const double f = lk / ((lk - a) * (lk - b));
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[i][j] = one ? f * M[i][j] : A[i][j] - f * M[i][j];
+  out[0] = P[0][0];
+  out[1] = P[1][1];
+  out[2] = P[2][2];
+  out[3] = r2 * 0.5 * (P[1][2] + P[2][1]);
+  out[4] = r2 * 0.5 * (P[0][2] + P[2][0]);
+  out[5] = r2 * 0.5 * (P[0][1] + P[1][0]);
+}
+
 // Transposed source derivative: out = sum_j lam_j (d alpha_j / d eps) at the
 // converged strain, [c][N].  For a J2 damage phase driven by field j the
 // source is kappa_n + dk with dk = (sqrt(3/2) ||s_tr|| - sy - H kappa_n)/(3 mu + H)
 // where plastic, so d alpha_j / d eps = sqrt(3/2) 2 mu s_tr / ((3 mu + H) ||s_tr||)
-// (0 where elastic and in every other phase).
+// (0 where elastic).  For a cracking phase the source is the Mazars
+// equivalent strain alpha = ||<eps>_+||, with gradient <eps>_+ / alpha (0 where
+// alpha = 0).  Other phases contribute nothing.
 FFTG_KERNEL void k_source_adj(MatTable tab, long long N, int c, int J,
                               const unsigned char* __restrict__ phase,
                               const double* __restrict__ eps, const double* __restrict__ st_n,
@@ -1358,7 +1404,27 @@ FFTG_KERNEL void k_source_adj(MatTable tab, long long N, int c, int J,
     const int ph = phase[v];
     const Mat m = tab.m[ph < tab.nphase ? ph : 0];
     double o[6] = {0, 0, 0, 0, 0, 0};
-    if (m.model == 1 && m.dfield >= 0 && m.dfield < J) {
+    if (m.model == 2 && m.dfield >= 0 && m.dfield < J) {
+      double e[6];
+      if (c == 6) {
+        for (int i = 0; i < 6; ++i) e[i] = eps[i * N + v];
+      } else {
+        e[0] = eps[v];
+        e[1] = eps[N + v];
+        e[2] = e[3] = e[4] = 0.0;
+        e[5] = eps[2 * N + v];
+      }
+      double lam3[3], pp[6];
+      principal3(e, lam3);
+      double s2 = 0.0;
+      for (int i = 0; i < 3; ++i)
+        if (lam3[i] > 0.0) s2 += lam3[i] * lam3[i];
+      if (s2 > 0.0) {
+        positive_part(e, lam3, pp);
+        const double gf = lam[(long long)m.dfield * N + v] / sqrt(s2);
+        for (int i = 0; i < 6; ++i) o[i] = gf * pp[i];
+      }
+    } else if (m.model == 1 && m.dfield >= 0 && m.dfield < J) {
       double ee[6];
       if (c == 6) {
         for (int i = 0; i < 6; ++i) ee[i] = eps[i * N + v];

@@ -228,7 +228,7 @@ def test_staggered_adjoint_rejects_uncovered_sources():
     from paper_2103_04770_amd.binding import FFTGError
     shape = (8, 8, 8)
     s = solver(shape)
-    table = [ms.matrix_j2_damage(ell=[2.0, 0.1], dfield=0), ms.particle_cracking(ell=[0.1, 1.0])]
+    table = [ms.matrix_gtn(ell=[2.0, 2.0]), ms.particle_elastic(ell=[0.1, 0.1])]
     z = dev(np.zeros((6 + 7 + 4,) + shape))
     with pytest.raises(FFTGError, match="UNSUPPORTED"):
         s.fftg_staggered_adjoint(dev(np.zeros(shape), torch.uint8), table, 2, z, z,
@@ -266,3 +266,38 @@ def test_autograd_staggered_increment_matches_oracle_gradient():
     (ge,) = torch.autograd.grad(J, (ell,))
     say("  dJ/dell gpu", ge.cpu().numpy(), "oracle", rq)
     assert np.allclose(ge.cpu().numpy(), rq, rtol=1e-7)
+
+
+@pytest.mark.parametrize("shape", [(12, 16), (6, 8, 12)])
+def test_staggered_adjoint_two_fields_matches_oracle(shape):
+    """Both sources of the benchmark table (J2 damage matrix on field 0,
+    particle cracking on field 1, cracking active): dJ/dell2 of both fields
+    against the oracle's transposed fixed point."""
+    from oracle import staggered
+    from tests.test_oracle_adjoint import STAG_TOLS
+    say("staggered adjoint two fields", shape)
+    rng = np.random.default_rng(23)
+    phase = (rng.uniform(size=shape) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0, 0.04], dfield=0, dC=0.0005, dR=0.02),
+             ms.particle_cracking(ell=[0.04, 1.0], dfield=1, k0=5e-4, kf=5e-3)]
+    nd = len(shape)
+    c = 6 if nd == 3 else 3
+    st_n, _, _, _ = staggered.staggered_step(phase, table, 2, staggered.initial_state(shape, nd, 2),
+                                             ms.uniaxial_mixed(nd, 2e-3), **STAG_TOLS)
+    tgt = ms.uniaxial_mixed(nd, 3e-3)
+    st, _, _, stats = staggered.staggered_step(phase, table, 2, st_n, tgt, **STAG_TOLS)
+    assert stats["converged"] and st["abar"][1].max() > 5e-4
+    g = np.zeros((c,) + shape)
+    g[0] = 1.0 / phase.size
+    ref = adjoint.staggered_adjoint(phase, table, 2, st_n, st["eps"], st["abar"], tgt, g_sig=g)
+    s = solver(shape)
+    dl = torch.empty((2,) + shape, dtype=torch.float64, device="cuda")
+    d = s.fftg_staggered_adjoint(dev(phase, torch.uint8), table, 2, dev(_pack(st_n)), dev(_pack(st)),
+                                 tgt, dl, g_sig=dev(g), cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12,
+                                 maxit=300)
+    say("  gpu passes", d["stagger_iters"], "oracle passes", ref["iters"])
+    assert d["converged"]
+    got = dl.cpu().numpy()
+    for j in range(2):
+        assert np.abs(got[j] - ref["dell2"][j]).max() <= 1e-8 * np.abs(ref["dell2"][j]).max()
+
