@@ -287,6 +287,58 @@ def run_adjoint():
     return dict(workload="spheres30_128", e11=0.004, **out)
 
 
+def run_c5(forms=("fp64", "fp32")):
+    """The differentiation workload of the 30-sphere RVE (128^3, 20%,
+    lengths 0.05 L / 0.001 L): 20 staggered increments of dE11 = 2e-3 to
+    E11 = 0.04 (through the peak and into softening), then the total derivative
+    of <sigma_11> at the last converged increment with respect to the two
+    per-phase lengths; FP64 and FP32-refined."""
+    import torch
+    from paper_2103_04770_amd import FP32_REFINED, FP64, Solver, microstructure as ms
+    w = ms.workload("spheres30_128")
+    S, J = w["shape"], w["nfields"]
+    tols = dict(TOLS, max_stagger=100)
+    out = {}
+    for form in forms:
+        s = Solver(tuple(reversed(S)), prec=FP64 if form == "fp64" else FP32_REFINED)
+        ph = torch.from_numpy(w["phase"]).cuda()
+        state = torch.zeros((6 + 7 + 2 * J,) + S, dtype=torch.float64, device="cuda")
+        sig = torch.empty((6,) + S, dtype=torch.float64, device="cuda")
+        curve = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(20):
+            state_n = state.clone()
+            d = s.staggered_step(ph, w["table"], J, state, w["load"][k], sig, **tols)
+            curve.append(round(float(d["sigma_mean"][0]), 3))
+            if not d["converged"]:
+                break
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
+        g[0] = 1.0 / float(np.prod(S))
+        dl = torch.empty((J,) + S, dtype=torch.float64, device="cuda")
+        a = s.fftg_staggered_adjoint(ph, w["table"], J, state_n, state, w["load"][k], dl, g_sig=g,
+                                     cg_tol=1e-8, pcg_tol=1e-8, tol=1e-6, maxit=300)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sums = s.fftg_phase_sums(ph, 2, dl[0].contiguous())
+        s.close()
+        out[form] = dict(increments=k + 1, e11_reached=float(w["load"][k][1][0]),
+                         all_converged=bool(d["converged"]), sigma11_curve=curve,
+                         path_s=round(t1 - t0, 3), adjoint_s=round(t2 - t1, 3),
+                         adjoint_passes=a["stagger_iters"], adjoint_converged=bool(a["converged"]),
+                         dJ_dell=[2.0 * float(t["ell"][0]) * float(v)
+                                  for t, v in zip(w["table"], sums)])
+        log("[c5] %s: %d increments to E11 %.3f in %.1f s, peak <s11> %.1f MPa; gradient %.2f s, "
+            "d<s11>/d ell = %s" % (form, k + 1, w["load"][k][1][0], t1 - t0, max(curve), t2 - t1,
+                                   ["%.5f" % v for v in out[form]["dJ_dell"]]))
+    if "fp64" in out and "fp32" in out:
+        a64, a32 = np.array(out["fp64"]["dJ_dell"]), np.array(out["fp32"]["dJ_dell"])
+        out["fp32_gradient_rel_err_vs_fp64"] = float(np.abs(a32 - a64).max() / np.abs(a64).max())
+    return dict(workload="spheres30_128", path="20 x dE11 = 2e-3 to 0.04", **out)
+
+
 def run_adjoint_two_fields():
     """The benchmark RVE itself (spheres_two_fields_128: J2 damage matrix on
     field 0, particle cracking on field 1): the converged increment
@@ -505,6 +557,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-driver", action="store_true",
                     help="skip the adaptive-driver, adjoint-chain and batch runs")
+    ap.add_argument("--c5", action="store_true",
+                    help="also run the differentiation workload: 20 increments to E11 = 0.04 "
+                         "on the 30-sphere RVE and the gradient at the last one (FP64, FP32)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -606,6 +661,8 @@ def main():
         out["adjoint"] = run_adjoint()
         out["batch"] = run_batch()
         out["gtn"] = run_gtn()
+    if args.c5:
+        out["c5_path_gradient"] = run_c5()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_iters)
