@@ -213,4 +213,144 @@ def staggered_adjoint(phase, table, nfields, state_n, eps, abar, target, g_eps=N
     qt = [np.broadcast_to(v, S) for v in qt]
     dell2 = np.stack([-sum(a * b for a, b in zip(grad_fields(lam[j], qt), grad_fields(abar[j], qt)))
                       for j in range(J)])
-    return dict(dell2=dell2, lam=lam, z=z, iters=it)
+    # total mechanics adjoint: mu = A^-1 G*(g_eps + K g_sig + alpha'^T lam)
+    rhs = g_eps + (lam[:, None] * dadx).sum(axis=0)
+    mu = mechanics_adjoint(phase, table, D, state_n["epsp"], state_n["kappa"], target, eps, rhs, J,
+                           h=h, scheme=scheme, cg_tol=cg_tol, gsig=g_sig)["mu"]
+    return dict(dell2=dell2, lam=lam, z=z, iters=it, mu=mu, D=D)
+
+
+def history_partials(eps, epsp_n, kappa_n, phase, table):
+    """Partial derivatives of the J2 return (linear hardening) of every voxel
+    with respect to its strain and its history, in 6-component Mandel form:
+      dk_de   (6, M)    d kappa_{n+1} / d eps   = sqrt(3/2) 2 mu n / (3 mu + H)
+      dk_dkn  (M,)      d kappa_{n+1} / d kappa_n = 3 mu / (3 mu + H)
+      dep_de  (6, 6, M) d eps_p,{n+1} / d eps
+                        = 3 mu/(3 mu + H) n(x)n + sqrt(3/2) dk 2 mu/||s|| (I_dev - n(x)n)
+      dep_dkn (6, M)    d eps_p,{n+1} / d kappa_n = -sqrt(3/2) H/(3 mu + H) n
+      ds_dkn  (6, M)    d sigma_eff / d kappa_n = 2 mu sqrt(3/2) H/(3 mu + H) n
+    where plastic (n the unit deviatoric trial direction, dk the increment);
+    elastic voxels and other phases keep their history (dk_dkn = 1, rest 0).
+    Since the return depends on eps - eps_p,n, the derivatives in eps_p,n are
+    minus those in eps (and d sigma_eff / d eps_p,n = -C_tangent)."""
+    M = eps.shape[1]
+    I6 = mandel.identity(6)
+    Idev = np.eye(6) - np.outer(I6, I6) / 3.0
+    out = dict(dk_de=np.zeros((6, M)), dk_dkn=np.ones(M), dep_de=np.zeros((6, 6, M)),
+               dep_dkn=np.zeros((6, M)), ds_dkn=np.zeros((6, M)))
+    for p, ph in enumerate(table):
+        if ph["model"] != "j2_damage":
+            continue
+        sel = np.nonzero(phase == p)[0]
+        K, mu = material.lame(ph["E"], ph["nu"])
+        H = ph["H"]
+        ee = eps[:, sel] - epsp_n[:, sel]
+        tr = ee[0] + ee[1] + ee[2]
+        s = 2.0 * mu * (ee - tr / 3.0 * I6[:, None])
+        ns = np.sqrt((s * s).sum(axis=0))
+        f = np.sqrt(1.5) * ns - (ph["sy"] + H * kappa_n[sel])
+        pl = f > 0.0
+        idx = sel[pl]
+        n = s[:, pl] / ns[pl]
+        dk = f[pl] / (3.0 * mu + H)
+        a = 3.0 * mu / (3.0 * mu + H)
+        out["dk_de"][:, idx] = np.sqrt(1.5) * 2.0 * mu / (3.0 * mu + H) * n
+        out["dk_dkn"][idx] = a
+        nn = np.einsum("im,jm->ijm", n, n)
+        out["dep_de"][:, :, idx] = a * nn + (np.sqrt(1.5) * dk * 2.0 * mu / ns[pl])[None, None] * (
+            Idev[:, :, None] - nn)
+        out["dep_dkn"][:, idx] = -np.sqrt(1.5) * H / (3.0 * mu + H) * n
+        out["ds_dkn"][:, idx] = 2.0 * mu * np.sqrt(1.5) * H / (3.0 * mu + H) * n
+    return out
+
+
+def increment_adjoint(phase, table, nfields, state_n, state_np1, target, g_sig=None,
+                      g_epsp=None, g_kappa=None, **kw):
+    """Adjoint of one converged staggered increment with respect to the
+    squared lengths and to the plastic history it started from.
+
+    J depends on this increment through sigma (g_sig, c comps) and through the
+    committed plastic state eps_p,{n+1}, kappa_{n+1} (cotangents g_epsp (6),
+    g_kappa, coming from later increments).  The committed-state cotangents
+    become a strain cotangent g_eps = dep_de^T g_epsp + dk_de g_kappa; the
+    coupled adjoint (staggered_adjoint) then gives mu and lam, and the history
+    cotangents are (sigma = (1 - D) sigma_eff, alpha = kappa_{n+1} on the
+    phase's field)
+      dJ/d eps_p,n = (1 - D) C_eff^T (mu - g_sig) - lam dk_de
+                     + (I - dep_de)^T g_epsp - dk_de g_kappa
+      dJ/d kappa_n = (1 - D) ds_dkn . (g_sig - mu) + lam dk_dkn
+                     + dep_dkn . g_epsp + dk_dkn g_kappa
+    (a parameter theta entering sigma at fixed strain contributes
+    (g_sig - mu) . d sigma/d theta, one entering the source lam d alpha/d theta).
+    Returns dict(dell2, g_epsp_n (6, *S), g_kappa_n (*S), iters)."""
+    S = phase.shape
+    M = phase.size
+    eps = state_np1["eps"]
+    c = eps.shape[0]
+    for ph in table:
+        if ph["model"] not in ("elastic", "j2_damage"):
+            raise NotImplementedError("history adjoint: J2 damage and elastic phases only")
+    e6 = (mandel.expand_plane(eps) if c == 3 else eps).reshape(6, M)
+    ep_n = state_n["epsp"].reshape(6, M)
+    k_n = state_n["kappa"].reshape(M)
+    hp = history_partials(e6, ep_n, k_n, phase.reshape(M), table)
+    cidx = mandel.PLANE_IDX if c == 3 else list(range(6))
+    ge = np.zeros((6, M))
+    if g_epsp is not None:
+        ge += np.einsum("ijm,im->jm", hp["dep_de"], g_epsp.reshape(6, M))
+    if g_kappa is not None:
+        ge += hp["dk_de"] * g_kappa.reshape(M)[None]
+    g_eps = ge[cidx].reshape((c,) + S)
+    r = staggered_adjoint(phase, table, nfields, state_n, eps, state_np1["abar"], target,
+                          g_eps=g_eps, g_sig=g_sig, **kw)
+    mu = r["mu"].reshape(c, M)
+    gs = np.zeros((c, M)) if g_sig is None else g_sig.reshape(c, M)
+    w6 = np.zeros((6, M))
+    w6[cidx] = mu - gs                                # mu - g_sig, zero off-plane in 2D
+    # (1 - D) C_eff and the source field of each voxel
+    C6 = np.zeros((6, 6, M))
+    for p, ph in enumerate(table):
+        sel = np.nonzero(phase.reshape(M) == p)[0]
+        if ph["model"] == "j2_damage":
+            C6[:, :, sel] = material.j2_return_map(e6[:, sel], ep_n[:, sel], k_n[sel], ph["E"],
+                                                   ph["nu"], ph["sy"], ph["H"])[3]
+        else:
+            K, mu_ = material.lame(ph["E"], ph["nu"])
+            C6[:, :, sel] = material.elastic_tangent(K, mu_)[:, :, None]
+    w1 = np.ones(M)
+    lam_v = np.zeros(M)
+    for p, ph in enumerate(table):
+        sel = phase.reshape(M) == p
+        j = ph["dfield"]
+        if ph["model"] == "j2_damage" and j >= 0:
+            w1[sel] = 1.0 - r["D"][j].reshape(M)[sel]
+            lam_v[sel] = r["lam"][j].reshape(M)[sel]
+    gep = w1[None] * np.einsum("ijm,im->jm", C6, w6) - lam_v[None] * hp["dk_de"]
+    gk = -w1 * (hp["ds_dkn"] * w6).sum(axis=0) + lam_v * hp["dk_dkn"]
+    if g_epsp is not None:
+        gp = g_epsp.reshape(6, M)
+        gep += gp - np.einsum("ijm,im->jm", hp["dep_de"], gp)
+        gk += (hp["dep_dkn"] * gp).sum(axis=0)
+    if g_kappa is not None:
+        gkap = g_kappa.reshape(M)
+        gep -= hp["dk_de"] * gkap[None]
+        gk += hp["dk_dkn"] * gkap
+    return dict(dell2=r["dell2"], g_epsp_n=gep.reshape((6,) + S), g_kappa_n=gk.reshape(S),
+                iters=r["iters"])
+
+
+def path_gradient(phase, table, nfields, states, targets, g_sig, **kw):
+    """dJ/d ell2_j(x) of J = g_sig . sigma after the last of a sequence of
+    converged staggered increments, through the whole path: states[k] is the
+    state before increment k (states[-1] after the last), targets[k] its
+    macro target.  Walks the increments backwards, passing the plastic-history
+    cotangents from each increment to the one before (increment_adjoint)."""
+    n = len(targets)
+    ge = gk = None
+    dell2 = 0.0
+    for k in range(n - 1, -1, -1):
+        r = increment_adjoint(phase, table, nfields, states[k], states[k + 1], targets[k],
+                              g_sig=g_sig if k == n - 1 else None, g_epsp=ge, g_kappa=gk, **kw)
+        dell2 = dell2 + r["dell2"]
+        ge, gk = r["g_epsp_n"], r["g_kappa_n"]
+    return dell2

@@ -382,3 +382,115 @@ def test_staggered_adjoint_two_fields_by_finite_differences():
             fd = (vals[0] - vals[1]) / (2 * hq)
             assert grad[q] == pytest.approx(fd, rel=5e-4, abs=1e-5 * max(abs(grad).max(), 1e-9))
 
+
+
+def test_history_partials_by_finite_differences():
+    """Derivatives of the J2 return in the strain and in the plastic history
+    against central differences of the return map."""
+    from oracle import material
+    rng = np.random.default_rng(9)
+    M = 40
+    ph = ms.matrix_j2_damage(ell=[1.0])
+    eps = rng.normal(scale=4e-3, size=(6, M))
+    epn = rng.normal(scale=1e-3, size=(6, M))
+    epn[:3] -= epn[:3].mean(axis=0)
+    kn = np.abs(rng.normal(scale=2e-3, size=M))
+    phase = np.zeros(M, np.uint8)
+    hp = adjoint.history_partials(eps, epn, kn, phase, [ph])
+
+    def rm(e, p, k):
+        s, ep, kap, C = material.j2_return_map(e, p, k, ph["E"], ph["nu"], ph["sy"], ph["H"])
+        return s, ep, kap
+
+    h = 1e-8
+    for i in range(6):
+        d = np.zeros((6, 1))
+        d[i] = h
+        sp, epp, kp = rm(eps + d, epn, kn)
+        sm, epm, km = rm(eps - d, epn, kn)
+        assert np.allclose((kp - km) / (2 * h), hp["dk_de"][i], rtol=1e-5, atol=1e-6)
+        assert np.allclose((epp - epm) / (2 * h), hp["dep_de"][:, i], rtol=1e-5, atol=1e-6)
+        # eps_p,n enters through eps - eps_p,n only
+        sp, epp, kp = rm(eps, epn + d, kn)
+        sm, epm, km = rm(eps, epn - d, kn)
+        assert np.allclose((kp - km) / (2 * h), -hp["dk_de"][i], rtol=1e-5, atol=1e-6)
+    hk = 1e-9
+    sp, epp, kp = rm(eps, epn, kn + hk)
+    sm, epm, km = rm(eps, epn, kn - hk)
+    assert np.allclose((kp - km) / (2 * hk), hp["dk_dkn"], rtol=1e-6)
+    assert np.allclose((epp - epm) / (2 * hk), hp["dep_dkn"], rtol=1e-5, atol=1e-6)
+    assert np.allclose((sp - sm) / (2 * hk), hp["ds_dkn"], rtol=1e-5, atol=1e-3)
+    assert (hp["dk_dkn"] < 1).sum() > M // 4          # plastic voxels present
+
+
+def _path(phase, table, e11s, ells=None):
+    from oracle import staggered
+    tab = [dict(t) for t in table]
+    if ells is not None:
+        for t, e in zip(tab, ells):
+            t["ell"] = [e]
+    st = staggered.initial_state(phase.shape, phase.ndim, 1)
+    states, targets = [st], []
+    hom = None
+    for e in e11s:
+        tgt = ms.uniaxial_mixed(phase.ndim, e)
+        st, sig, hom, stats = staggered.staggered_step(phase, tab, 1, st, tgt, **STAG_TOLS)
+        assert stats["converged"]
+        states.append(st)
+        targets.append(tgt)
+    return states, targets, hom
+
+
+def test_increment_adjoint_history_by_finite_differences():
+    """Cotangents of the plastic history (eps_p,n and kappa_n) of one
+    converged increment, J = <sigma_11>, against directional central
+    differences of the increment."""
+    from oracle import staggered
+    S, phase, table = _stag_case()
+    states, targets, _ = _path(phase, table, [3e-3, 5e-3])
+    st_n, st = states[1], states[2]
+    c = 3
+    g = np.zeros((c,) + S)
+    g[0] = 1.0 / phase.size
+    r = adjoint.increment_adjoint(phase, table, 1, st_n, st, targets[1], g_sig=g)
+    rng = np.random.default_rng(2)
+    de = rng.standard_normal((6,) + S) * (phase == 0)
+    dk = np.abs(rng.standard_normal(S)) * (phase == 0)
+
+    def J(stn):
+        return staggered.staggered_step(phase, table, 1, stn, targets[1],
+                                        **STAG_TOLS)[2]["sigma"][0]
+
+    for name, pert, grad in (("epsp", de, r["g_epsp_n"]), ("kappa", dk, r["g_kappa_n"])):
+        h = 1e-7
+        sp = dict(st_n, **{name: st_n[name] + h * pert})
+        sm = dict(st_n, **{name: st_n[name] - h * pert})
+        fd = (J(sp) - J(sm)) / (2 * h)
+        assert float((grad * pert).sum()) == pytest.approx(fd, rel=2e-4), name
+
+
+def test_path_gradient_by_finite_differences():
+    """d<sigma_11>/d ell after a three-increment path, through the history of
+    every increment, against central differences of the whole path; it
+    differs from the last increment's own total derivative."""
+    S, phase, table = _stag_case()
+    e11s = [2e-3, 4e-3, 6e-3]
+    states, targets, hom = _path(phase, table, e11s)
+    g = np.zeros((3,) + S)
+    g[0] = 1.0 / phase.size
+    dl = adjoint.path_gradient(phase, table, 1, states, targets, g)
+    grad = adjoint.phase_length_gradient(dl[0], phase, table, 0)
+    last = adjoint.staggered_adjoint(phase, table, 1, states[-2], states[-1]["eps"],
+                                     states[-1]["abar"], targets[-1], g_sig=g)
+    one = adjoint.phase_length_gradient(last["dell2"][0], phase, table, 0)
+    ells = [t["ell"][0] for t in table]
+    for q in range(2):
+        hq = 1e-4 * ells[q]
+        vals = []
+        for sgn in (1, -1):
+            e = list(ells)
+            e[q] += sgn * hq
+            vals.append(_path(phase, table, e11s, e)[2]["sigma"][0])
+        fd = (vals[0] - vals[1]) / (2 * hq)
+        assert grad[q] == pytest.approx(fd, rel=5e-4, abs=1e-6 * abs(grad).max())
+    assert np.abs(grad - one).max() > 1e-3 * np.abs(grad).max()
