@@ -277,7 +277,8 @@ def increment_adjoint(phase, table, nfields, state_n, state_np1, target, g_sig=N
     cotangents are (sigma = (1 - D) sigma_eff, alpha = kappa_{n+1} on the
     phase's field)
       dJ/d eps_p,n = (1 - D) C_eff^T (mu - g_sig) - lam dk_de
-                     + (I - dep_de)^T g_epsp - dk_de g_kappa
+                     + (I - dep_de)^T g_epsp - dk_de g_kappa   (J2 voxels; an elastic
+                     voxel passes g_epsp through: its stress ignores eps_p,n)
       dJ/d kappa_n = (1 - D) ds_dkn . (g_sig - mu) + lam dk_dkn
                      + dep_dkn . g_epsp + dk_dkn g_kappa
     (a parameter theta entering sigma at fixed strain contributes
@@ -307,16 +308,15 @@ def increment_adjoint(phase, table, nfields, state_n, state_np1, target, g_sig=N
     gs = np.zeros((c, M)) if g_sig is None else g_sig.reshape(c, M)
     w6 = np.zeros((6, M))
     w6[cidx] = mu - gs                                # mu - g_sig, zero off-plane in 2D
-    # (1 - D) C_eff and the source field of each voxel
+    # (1 - D) C_eff of the J2 phases; an elastic phase's stress does not
+    # depend on eps_p,n (it acts on the total strain), its history only passes
+    # through
     C6 = np.zeros((6, 6, M))
     for p, ph in enumerate(table):
         sel = np.nonzero(phase.reshape(M) == p)[0]
         if ph["model"] == "j2_damage":
             C6[:, :, sel] = material.j2_return_map(e6[:, sel], ep_n[:, sel], k_n[sel], ph["E"],
                                                    ph["nu"], ph["sy"], ph["H"])[3]
-        else:
-            K, mu_ = material.lame(ph["E"], ph["nu"])
-            C6[:, :, sel] = material.elastic_tangent(K, mu_)[:, :, None]
     w1 = np.ones(M)
     lam_v = np.zeros(M)
     for p, ph in enumerate(table):
