@@ -15,6 +15,9 @@ iterations is kept.  Tensors are CUDA float64 in numpy axis order.
 staggered_increment() differentiates a whole converged increment of the
 staggered scheme (the damage feeding back into the local sources through the
 mechanics) in the per-phase lengths, through fftg_staggered_adjoint.
+staggered_path() differentiates a whole load path of such increments (every
+increment's plastic history carried into the next), walking them backwards
+with fftg_increment_adjoint (path_gradient).
 
 one_pass() chains them for one field: the per-voxel local source alpha (e.g.
 the local equivalent plastic strain) and the per-phase lengths give abar, the
@@ -202,3 +205,74 @@ def staggered_increment(solver, ell, phase, table, nfields, state_n, target, fie
     return _StaggeredIncrement.apply(ell, solver, phase, table, nfields, state_n, target, field,
                                      opts)
 
+
+
+def path_gradient(solver, phase, table, nfields, states, targets, g_sig, cg_tol=1e-10,
+                  pcg_tol=1e-10, tol=1e-10, maxit=200):
+    """dJ/dell2_j(x) (nfields, *S) of J = g_sig . sigma after the last
+    increment of a converged load path: states[k] is the packed state before
+    increment k (states[-1] after the last), targets[k] its macro target.
+    The increments are walked last to first; each fftg_increment_adjoint call
+    returns the cotangents of the plastic history its increment started from,
+    which the call for the increment before receives.  Returns (dell2, stats
+    of every call, last first)."""
+    S = solver.spatial
+    f64 = dict(dtype=torch.float64, device="cuda")
+    total = torch.zeros((nfields,) + S, **f64)
+    dl = torch.empty((nfields,) + S, **f64)
+    ge, gk = None, None
+    gen, gkn = torch.empty((6,) + S, **f64), torch.empty(S, **f64)
+    log = []
+    for k in range(len(targets) - 1, -1, -1):
+        d = solver.fftg_increment_adjoint(
+            phase, table, nfields, states[k], states[k + 1], targets[k], dl, gen, gkn,
+            g_sig=g_sig if k == len(targets) - 1 else None, g_epsp=ge, g_kappa=gk,
+            cg_tol=cg_tol, pcg_tol=pcg_tol, tol=tol, maxit=maxit)
+        if not d["converged"]:
+            raise RuntimeError("increment adjoint %d did not converge: %s" % (k, d))
+        log.append(d)
+        total += dl
+        if ge is None:
+            ge, gk = torch.empty_like(gen), torch.empty_like(gkn)
+        ge, gen = gen, ge
+        gk, gkn = gkn, gk
+    return total, log
+
+
+class _StaggeredPath(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, ell, solver, phase, table, nfields, state_0, targets, field, opts):
+        tab = _with_lengths(table, ell.detach().cpu().numpy(), field)
+        state = state_0.detach().clone().contiguous()
+        sig = torch.empty((solver.c,) + solver.spatial, dtype=torch.float64, device="cuda")
+        states = [state.clone()]
+        for k, tgt in enumerate(targets):
+            d = solver.staggered_step(phase, tab, nfields, state, tgt, sig, **opts)
+            if not d["converged"]:
+                raise RuntimeError("increment %d did not converge: %s" % (k, d))
+            states.append(state.clone())
+        ctx.save_for_backward(ell)
+        ctx.args = (solver, phase, tab, nfields, states, targets, field, opts, len(table))
+        return sig
+
+    @staticmethod
+    def backward(ctx, gsig):
+        (ell,) = ctx.saved_tensors
+        solver, phase, tab, nfields, states, targets, field, opts, nphase = ctx.args
+        dell2, _ = path_gradient(solver, phase, tab, nfields, states, targets, gsig.contiguous(),
+                                 cg_tol=opts.get("cg_tol", 1e-8), pcg_tol=opts.get("pcg_tol", 1e-8),
+                                 tol=min(opts.get("stagger_tol", 1e-6), 1e-8),
+                                 maxit=opts.get("max_stagger", 20) * 10)
+        sums = solver.fftg_phase_sums(phase, nphase, dell2[field].contiguous())
+        return (2.0 * ell * torch.from_numpy(sums).to(ell), None, None, None, None, None, None,
+                None, None)
+
+
+def staggered_path(solver, ell, phase, table, nfields, state_0, targets, field=0, **opts):
+    """The stress field after a load path of converged staggered increments
+    (macro targets `targets`, from the packed state_0), differentiable in the
+    per-phase lengths `ell` of `field` through the whole path.  Keeps every
+    increment's packed state on the device.  Phases covered: J2 damage
+    (linear hardening) and elastic."""
+    return _StaggeredPath.apply(ell, solver, phase, table, nfields, state_0, list(targets), field,
+                                opts)

@@ -99,6 +99,7 @@ struct fftg_handle {
   double* drive_bak = nullptr;
   double* adj_r = nullptr;  // adjoint: two FP64 real scratch fields
   double* sadj = nullptr;   // staggered adjoint: (2c + 5J) FP64 real fields
+  double* hadj = nullptr;   // increment adjoint: strain cotangent of the history (c fields)
   // tile-budget shifts of the fixed-length strided passes (inner y passes,
   // outer-axis passes), chosen at creation by timing; times of each choice
   int tsh_y = 0, tsh_o = 0;
@@ -918,6 +919,7 @@ void destroy(fftg_handle* H) {
   dfree((void*&)H->drive_bak);
   dfree((void*&)H->adj_r);
   dfree((void*&)H->sadj);
+  dfree((void*&)H->hadj);
   for (auto& e : H->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& p : H->pend) {
@@ -1176,6 +1178,133 @@ void tune_tiles(fftg_handle* H) {
   }
   H->err.clear();
 }
+
+namespace {
+
+// Coupled adjoint of a converged staggered increment on a validated call
+// (J2 damage, cracking and elastic phases).  Leaves lam (J x N) and, with
+// total_mu, the total mechanics adjoint mu = A^-1 G*(g_eps + K g_sig +
+// alpha'^T lam) (c x N) in the handle's adjoint buffers; dell2 receives
+// -sum_i G_i lam_j G_i abar_j.
+struct AdjOut {
+  fftg_stats stats{};
+  bool converged = false;
+  bool inner_capped = false;
+  const double* lam = nullptr;
+  const double* mu = nullptr;
+};
+
+AdjOut stag_adjoint_core(fftg_handle* H, const unsigned char* phase, const MatTable& t, int J,
+                         const double* state_n, const double* state_np1,
+                         const fftg_macro* target, const double* g_eps, const double* g_sig,
+                         const double* g_abar, const double* g_D, double* dell2,
+                         const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg, double tol,
+                         int maxit, bool total_mu) {
+  AdjOut out;
+  const Geo& g = H->g;
+  const int c = H->c;
+  const long long N = g.N;
+  alloc_stagger(H, J);
+  alloc_helm(H);
+  if (H->sadjJ < J) {
+    dfree((void*&)H->sadj);
+    H->sadj = (double*)dalloc(sizeof(double) * (size_t)(2 * c + 5 * J) * N);
+    H->sadjJ = J;
+  }
+  double* mu = H->sadj;
+  double* rhs = mu + (long long)c * N;
+  double* dD = rhs + (long long)c * N;
+  double* hv = dD + (long long)J * N;
+  double* z = hv + (long long)J * N;
+  double* zn = z + (long long)J * N;
+  double* lam = zn + (long long)J * N;
+  const double* epsp_n = state_n + (long long)c * N;  // eps_p (6), kappa
+  const double* hist_n = state_n + (long long)(c + 7) * N;
+  const double* abar_n = state_n + (long long)(c + 7 + J) * N;
+  const double* eps = state_np1;
+  const double* abar = state_np1 + (long long)(c + 7 + J) * N;
+  // frozen damage of the converged state, squared lengths per field
+  fftg::launch_damage(t, N, J, phase, abar, hist_n, abar_n, H->Dj, H->st);
+  for (int j = 0; j < J; ++j) {
+    if (H->fp32())
+      fftg::launch_ell2<float>(t, N, j, phase, reinterpret_cast<float*>(H->ell2j) + j * N, H->st);
+    else
+      fftg::launch_ell2<double>(t, N, j, phase, reinterpret_cast<double*>(H->ell2j) + j * N,
+                                H->st);
+  }
+  fftg_stats& acc = out.stats;
+  int status = 0;
+  auto mech = [&](const double* gb, const double* gs) {
+    const int it = H->fp32() ? mech_adjoint<float>(H, phase, t, J, H->Dj, epsp_n, target, eps, gb,
+                                                   gs, mu, dD, cg, status)
+                             : mech_adjoint<double>(H, phase, t, J, H->Dj, epsp_n, target, eps,
+                                                    gb, gs, mu, dD, cg, status);
+    out.inner_capped = out.inner_capped || status == 2;
+    acc.cg_iters += it;
+    acc.newton_iters += 1;
+  };
+  auto helm = [&](const double* src, double* x) {
+    for (int j = 0; j < J; ++j) {
+      int it = 0, st = 0;
+      double rel = 0.0;
+      if (H->fp32())
+        helmholtz_pcg<float>(H, src + j * N, reinterpret_cast<const float*>(H->ell2j) + j * N,
+                             -1.0, x + j * N, pcg->tol, pcg->maxit, it, rel, st);
+      else
+        helmholtz_pcg<double>(H, src + j * N, reinterpret_cast<const double*>(H->ell2j) + j * N,
+                              -1.0, x + j * N, pcg->tol, pcg->maxit, it, rel, st);
+      if (st == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
+      if (st == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+      out.inner_capped = out.inner_capped || st == 2;
+      acc.pcg_iters += it;
+    }
+  };
+  // hv = D' ((mu0 - g_sig) : sigma_eff + g_D) + g_abar, mu0 = A^-1 G*(g_eps + K g_sig)
+  if (g_eps)
+    HIPCHK(hipMemcpyAsync(rhs, g_eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
+  else
+    fftg::launch_scale((long long)c * N, 0.0, eps, rhs, H->st);
+  mech(rhs, g_sig);
+  if (g_D) fftg::launch_axpby((long long)J * N, 1.0, dD, 1.0, g_D, dD, H->st);
+  fftg::launch_damage_adj(t, N, J, phase, abar, hist_n, dD, hv, H->st);
+  if (g_abar) fftg::launch_axpby((long long)J * N, 1.0, hv, 1.0, g_abar, hv, H->st);
+  HIPCHK(hipMemcpyAsync(z, hv, sizeof(double) * J * N, hipMemcpyDeviceToDevice, H->st));
+  fftg::launch_scale((long long)J * N, 0.0, hv, lam, H->st);
+  // transposed staggered fixed point z <- hv + D' (sigma_eff : A^-1 G*(alpha'^T L^-1 z))
+  int k = 0;
+  double err = 0.0;
+  for (k = 1; k <= maxit; ++k) {
+    helm(z, lam);
+    fftg::launch_source_adj(t, N, c, J, phase, eps, epsp_n, lam, rhs, H->st);
+    mech(rhs, nullptr);
+    fftg::launch_damage_adj(t, N, J, phase, abar, hist_n, dD, zn, H->st);
+    fftg::launch_axpby((long long)J * N, 1.0, hv, 1.0, zn, zn, H->st);
+    double s2[2];
+    read_sums(H, fftg::launch_diff2((long long)J * N, zn, z, H->partials, H->st), 2, s2);
+    std::swap(z, zn);
+    err = std::sqrt(s2[0]) / std::max(std::sqrt(s2[1]), 1e-300);
+    if (!std::isfinite(err)) throw Fail{FFTG_E_NONFINITE, "non-finite adjoint iterate"};
+    if (err <= tol) {
+      out.converged = true;
+      break;
+    }
+  }
+  helm(z, lam);
+  for (int j = 0; j < J; ++j) grad_dot(H, lam + j * N, abar + j * N, dell2 + j * N);
+  if (total_mu) {
+    // mu = A^-1 G*(g_eps + K g_sig + alpha'^T lam)
+    fftg::launch_source_adj(t, N, c, J, phase, eps, epsp_n, lam, rhs, H->st);
+    if (g_eps) fftg::launch_axpby((long long)c * N, 1.0, rhs, 1.0, g_eps, rhs, H->st);
+    mech(rhs, g_sig);
+    out.mu = mu;
+  }
+  acc.stagger_iters = out.converged ? k : maxit;
+  acc.err = err;
+  out.lam = lam;
+  return out;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1719,110 +1848,65 @@ fftg_status fftg_staggered_adjoint(fftg_handle* H, const unsigned char* phase,
     if (has_gtn(tab, nphase))
       throw Fail{FFTG_E_UNSUPPORTED, "fftg_staggered_adjoint: Gurson sources are not covered"};
     auto t0 = std::chrono::steady_clock::now();
-    const Geo& g = H->g;
-    const int c = H->c, J = nfields;
-    const long long N = g.N;
-    alloc_stagger(H, J);
-    alloc_helm(H);
-    if (H->sadjJ < J) {
-      dfree((void*&)H->sadj);
-      H->sadj = (double*)dalloc(sizeof(double) * (size_t)(2 * c + 5 * J) * N);
-      H->sadjJ = J;
-    }
-    double* mu = H->sadj;
-    double* rhs = mu + (long long)c * N;
-    double* dD = rhs + (long long)c * N;
-    double* hv = dD + (long long)J * N;
-    double* z = hv + (long long)J * N;
-    double* zn = z + (long long)J * N;
-    double* lam = zn + (long long)J * N;
-    const double* epsp_n = state_n + (long long)c * N;  // eps_p (6), kappa
-    const double* hist_n = state_n + (long long)(c + 7) * N;
-    const double* abar_n = state_n + (long long)(c + 7 + J) * N;
-    const double* eps = state_np1;
-    const double* abar = state_np1 + (long long)(c + 7 + J) * N;
-    const MatTable t = make_table(tab, nphase, J);
-    // frozen damage of the converged state, squared lengths per field
-    fftg::launch_damage(t, N, J, phase, abar, hist_n, abar_n, H->Dj, H->st);
-    for (int j = 0; j < J; ++j) {
-      if (H->fp32())
-        fftg::launch_ell2<float>(t, N, j, phase, reinterpret_cast<float*>(H->ell2j) + j * N, H->st);
-      else
-        fftg::launch_ell2<double>(t, N, j, phase, reinterpret_cast<double*>(H->ell2j) + j * N,
-                                  H->st);
-    }
-    fftg_stats acc{};
-    int status = 0;
-    bool inner_capped = false;  // an inner Krylov solve stopped at its maxit
-    auto mech = [&](const double* gb, const double* gs) {
-      const int it = H->fp32() ? mech_adjoint<float>(H, phase, t, J, H->Dj, epsp_n, target, eps, gb,
-                                                     gs, mu, dD, cg, status)
-                               : mech_adjoint<double>(H, phase, t, J, H->Dj, epsp_n, target, eps,
-                                                      gb, gs, mu, dD, cg, status);
-      inner_capped = inner_capped || status == 2;
-      acc.cg_iters += it;
-      acc.newton_iters += 1;
-    };
-    auto helm = [&](const double* src, double* x) {
-      for (int j = 0; j < J; ++j) {
-        int it = 0, st = 0;
-        double rel = 0.0;
-        if (H->fp32())
-          helmholtz_pcg<float>(H, src + j * N, reinterpret_cast<const float*>(H->ell2j) + j * N,
-                               -1.0, x + j * N, pcg->tol, pcg->maxit, it, rel, st);
-        else
-          helmholtz_pcg<double>(H, src + j * N, reinterpret_cast<const double*>(H->ell2j) + j * N,
-                                -1.0, x + j * N, pcg->tol, pcg->maxit, it, rel, st);
-        if (st == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
-        if (st == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
-        inner_capped = inner_capped || st == 2;
-        acc.pcg_iters += it;
-      }
-    };
-    // hv = D' ((mu0 - g_sig) : sigma_eff + g_D) + g_abar, mu0 = A^-1 G*(g_eps + K g_sig)
-    if (g_eps)
-      HIPCHK(hipMemcpyAsync(rhs, g_eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
-    else
-      fftg::launch_scale((long long)c * N, 0.0, eps, rhs, H->st);
-    mech(rhs, g_sig);
-    if (g_D) fftg::launch_axpby((long long)J * N, 1.0, dD, 1.0, g_D, dD, H->st);
-    fftg::launch_damage_adj(t, N, J, phase, abar, hist_n, dD, hv, H->st);
-    if (g_abar) fftg::launch_axpby((long long)J * N, 1.0, hv, 1.0, g_abar, hv, H->st);
-    HIPCHK(hipMemcpyAsync(z, hv, sizeof(double) * J * N, hipMemcpyDeviceToDevice, H->st));
-    fftg::launch_scale((long long)J * N, 0.0, hv, lam, H->st);
-    // transposed staggered fixed point z <- hv + D' (sigma_eff : A^-1 G*(alpha'^T L^-1 z))
-    bool converged = false;
-    int k = 0;
-    double err = 0.0;
-    for (k = 1; k <= maxit; ++k) {
-      helm(z, lam);
-      fftg::launch_source_adj(t, N, c, J, phase, eps, epsp_n, lam, rhs, H->st);
-      mech(rhs, nullptr);
-      fftg::launch_damage_adj(t, N, J, phase, abar, hist_n, dD, zn, H->st);
-      fftg::launch_axpby((long long)J * N, 1.0, hv, 1.0, zn, zn, H->st);
-      double s2[2];
-      read_sums(H, fftg::launch_diff2((long long)J * N, zn, z, H->partials, H->st), 2, s2);
-      std::swap(z, zn);
-      err = std::sqrt(s2[0]) / std::max(std::sqrt(s2[1]), 1e-300);
-      if (!std::isfinite(err)) throw Fail{FFTG_E_NONFINITE, "non-finite adjoint iterate"};
-      if (err <= tol) {
-        converged = true;
-        break;
-      }
-    }
-    helm(z, lam);
-    for (int j = 0; j < J; ++j) grad_dot(H, lam + j * N, abar + j * N, dell2 + j * N);
+    const MatTable t = make_table(tab, nphase, nfields);
+    const AdjOut r = stag_adjoint_core(H, phase, t, nfields, state_n, state_np1, target, g_eps,
+                                       g_sig, g_abar, g_D, dell2, cg, pcg, tol, maxit, false);
     if (lam_out)
-      HIPCHK(hipMemcpyAsync(lam_out, lam, sizeof(double) * J * N, hipMemcpyDeviceToDevice, H->st));
+      HIPCHK(hipMemcpyAsync(lam_out, r.lam, sizeof(double) * nfields * H->g.N,
+                            hipMemcpyDeviceToDevice, H->st));
     check_launch();
     sync(H);
     if (stats) {
-      *stats = acc;
-      stats->stagger_iters = converged ? k : maxit;
-      stats->err = err;
+      *stats = r.stats;
       stats->t_ms[3] = wall_ms(t0);
     }
-    return converged && !inner_capped ? FFTG_OK : FFTG_NOT_CONVERGED;
+    return r.converged && !r.inner_capped ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+}
+
+fftg_status fftg_increment_adjoint(fftg_handle* H, const unsigned char* phase,
+                                   const fftg_phase* tab, int nphase, int nfields,
+                                   const double* state_n, const double* state_np1,
+                                   const fftg_macro* target, const double* g_sig,
+                                   const double* g_epsp, const double* g_kappa, double* dell2,
+                                   double* g_epsp_n, double* g_kappa_n,
+                                   const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
+                                   double tol, int maxit, fftg_stats* stats) {
+  if (!H) return FFTG_E_INVALID;
+  return run_guarded(H, [&]() -> fftg_status {
+    validate_table(tab, nphase, nfields);
+    validate_macro(target, H->c);
+    if (!phase || !state_n || !state_np1 || !dell2 || !g_epsp_n || !g_kappa_n || !cg || !pcg ||
+        nfields < 1 || maxit < 1)
+      throw Fail{FFTG_E_INVALID, "fftg_increment_adjoint: null pointer, no field or maxit < 1"};
+    for (int p = 0; p < nphase; ++p)
+      if (tab[p].model != FFTG_ELASTIC && tab[p].model != FFTG_J2_DAMAGE)
+        throw Fail{FFTG_E_UNSUPPORTED,
+                   "fftg_increment_adjoint: J2 damage and elastic phases only"};
+    auto t0 = std::chrono::steady_clock::now();
+    const int c = H->c, J = nfields;
+    const long long N = H->g.N;
+    const MatTable t = make_table(tab, nphase, J);
+    const double* epsp_n = state_n + (long long)c * N;
+    const double* eps = state_np1;
+    // strain cotangent of the committed plastic state
+    const double* g_eps = nullptr;
+    if (g_epsp || g_kappa) {
+      if (!H->hadj) H->hadj = (double*)dalloc(sizeof(double) * (size_t)c * N);
+      fftg::launch_hist_out_cot(t, N, c, phase, eps, epsp_n, g_epsp, g_kappa, H->hadj, H->st);
+      g_eps = H->hadj;
+    }
+    const AdjOut r = stag_adjoint_core(H, phase, t, J, state_n, state_np1, target, g_eps, g_sig,
+                                       nullptr, nullptr, dell2, cg, pcg, tol, maxit, true);
+    fftg::launch_hist_in_cot(t, N, c, J, phase, eps, epsp_n, H->Dj, r.mu, g_sig, r.lam, g_epsp,
+                             g_kappa, g_epsp_n, g_kappa_n, H->st);
+    check_launch();
+    sync(H);
+    if (stats) {
+      *stats = r.stats;
+      stats->t_ms[3] = wall_ms(t0);
+    }
+    return r.converged && !r.inner_capped ? FFTG_OK : FFTG_NOT_CONVERGED;
   });
 }
 

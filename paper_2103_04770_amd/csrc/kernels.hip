@@ -1467,6 +1467,168 @@ FFTG_KERNEL void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict_
     dst[i] = src[i];
 }
 
+// J2 return of one voxel (linear hardening) re-evaluated at the converged
+// strain for the history adjoint: unit deviatoric trial direction n, plastic
+// flag, and the scalars of the derivatives
+//   d kappa/d eps = gk n,  d eps_p/d eps = a n(x)n + b (I_dev - n(x)n),
+//   d kappa/d kappa_n = kk,  d eps_p/d kappa_n = pk n,  d sigma_eff/d kappa_n = sk n,
+//   C_eff = K I(x)I + 2 mu theta I_dev - 2 mu theta_bar n(x)n.
+struct HistJ2 {
+  double n[6];
+  bool plastic;
+  double gk, a, b, kk, pk, sk, th, thb;
+};
+
+__device__ HistJ2 hist_j2(const Mat& m, const double e[6], const double* st_n, long long N,
+                          long long v) {
+  const double sq32 = 1.2247448713915890490986420373529;
+  HistJ2 r{};
+  double ee[6];
+  for (int i = 0; i < 6; ++i) ee[i] = e[i] - st_n[i * N + v];
+  const double tr = ee[0] + ee[1] + ee[2];
+  double ns2 = 0.0;
+  for (int i = 0; i < 6; ++i) {
+    r.n[i] = 2.0 * m.mu * (ee[i] - (i < 3 ? tr / 3.0 : 0.0));
+    ns2 += r.n[i] * r.n[i];
+  }
+  const double ns = sqrt(ns2);
+  const double f = sq32 * ns - (m.sy + m.H * st_n[6 * N + v]);
+  r.plastic = f > 0.0;
+  r.kk = 1.0;
+  r.th = 1.0;
+  if (!r.plastic) return r;
+  for (int i = 0; i < 6; ++i) r.n[i] /= ns;
+  const double h3 = 3.0 * m.mu + m.H;
+  const double dk = f / h3;
+  r.gk = sq32 * 2.0 * m.mu / h3;
+  r.a = 3.0 * m.mu / h3;
+  r.b = sq32 * dk * 2.0 * m.mu / ns;
+  r.kk = r.a;
+  r.pk = -sq32 * m.H / h3;
+  r.sk = 2.0 * m.mu * sq32 * m.H / h3;
+  r.th = 1.0 - 2.0 * m.mu * sq32 * dk / ns;
+  r.thb = 1.0 / (1.0 + m.H / (3.0 * m.mu)) - (1.0 - r.th);
+  return r;
+}
+
+__device__ inline void load_strain6(const double* eps, int c, long long N, long long v,
+                                    double e[6]) {
+  if (c == 6) {
+    for (int i = 0; i < 6; ++i) e[i] = eps[i * N + v];
+  } else {
+    e[0] = eps[v];
+    e[1] = eps[N + v];
+    e[2] = e[3] = e[4] = 0.0;
+    e[5] = eps[2 * N + v];
+  }
+}
+
+// (a n(x)n + b (I_dev - n(x)n)) g for a deviatoric unit n
+__device__ inline void dep_apply(const HistJ2& h, const double g[6], double out[6]) {
+  double ng = 0.0;
+  for (int i = 0; i < 6; ++i) ng += h.n[i] * g[i];
+  const double tg = (g[0] + g[1] + g[2]) / 3.0;
+  for (int i = 0; i < 6; ++i)
+    out[i] = h.a * ng * h.n[i] + h.b * (g[i] - (i < 3 ? tg : 0.0) - ng * h.n[i]);
+}
+
+// Strain cotangent from the cotangents of the committed plastic state of the
+// J2 voxels: g_eps = (d eps_p/d eps)^T g_epsp + (d kappa/d eps) g_kappa
+// (0 elsewhere).  g_epsp [6][N], g_kappa [N] may be null.
+FFTG_KERNEL void k_hist_out_cot(MatTable tab, long long N, int c,
+                                const unsigned char* __restrict__ phase,
+                                const double* __restrict__ eps, const double* __restrict__ st_n,
+                                const double* __restrict__ g_epsp,
+                                const double* __restrict__ g_kappa, double* __restrict__ g_eps) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    double o[6] = {0, 0, 0, 0, 0, 0};
+    if (m.model == 1) {
+      double e[6];
+      load_strain6(eps, c, N, v, e);
+      const HistJ2 h = hist_j2(m, e, st_n, N, v);
+      if (h.plastic) {
+        if (g_epsp) {
+          double g[6];
+          for (int i = 0; i < 6; ++i) g[i] = g_epsp[i * N + v];
+          dep_apply(h, g, o);
+        }
+        if (g_kappa)
+          for (int i = 0; i < 6; ++i) o[i] += h.gk * h.n[i] * g_kappa[v];
+      }
+    }
+    if (c == 6) {
+      for (int i = 0; i < 6; ++i) g_eps[i * N + v] = o[i];
+    } else {
+      g_eps[v] = o[0];
+      g_eps[N + v] = o[1];
+      g_eps[2 * N + v] = o[5];
+    }
+  }
+}
+
+// Cotangents of the plastic history an increment started from, at its
+// converged state: with w = mu - g_sig (mu the total mechanics adjoint) and
+// lam the Helmholtz adjoint of the voxel's field,
+//   g_epsp_n  = (1 - D) C_eff w - lam d kappa/d eps + g_epsp - (d eps_p/d eps)^T g_epsp
+//               - (d kappa/d eps) g_kappa
+//   g_kappa_n = -(1 - D) (d sigma_eff/d kappa_n) . w + lam d kappa/d kappa_n
+//               + (d eps_p/d kappa_n) . g_epsp + (d kappa/d kappa_n) g_kappa
+// on J2 damage voxels; other phases pass g_epsp, g_kappa through (their stress
+// acts on the total strain).
+FFTG_KERNEL void k_hist_in_cot(MatTable tab, long long N, int c, int J,
+                               const unsigned char* __restrict__ phase,
+                               const double* __restrict__ eps, const double* __restrict__ st_n,
+                               const double* __restrict__ D, const double* __restrict__ mu,
+                               const double* __restrict__ g_sig, const double* __restrict__ lam,
+                               const double* __restrict__ g_epsp,
+                               const double* __restrict__ g_kappa,
+                               double* __restrict__ g_epsp_n, double* __restrict__ g_kappa_n) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    double gp[6], gpo[6];
+    for (int i = 0; i < 6; ++i) gp[i] = g_epsp ? g_epsp[i * N + v] : 0.0;
+    const double gkap = g_kappa ? g_kappa[v] : 0.0;
+    for (int i = 0; i < 6; ++i) gpo[i] = gp[i];
+    double gko = gkap;
+    if (m.model == 1) {
+      double e[6];
+      load_strain6(eps, c, N, v, e);
+      const HistJ2 h = hist_j2(m, e, st_n, N, v);
+      double w[6] = {0, 0, 0, 0, 0, 0};
+      const int idx[6] = {0, 1, 5, 2, 3, 4};
+      for (int k = 0; k < c; ++k) {
+        const int i = c == 6 ? k : idx[k];
+        w[i] = mu[(long long)k * N + v] - (g_sig ? g_sig[(long long)k * N + v] : 0.0);
+      }
+      const bool fld = m.dfield >= 0 && m.dfield < J;
+      const double w1 = fld ? 1.0 - D[(long long)m.dfield * N + v] : 1.0;
+      const double lv = fld ? lam[(long long)m.dfield * N + v] : 0.0;
+      // C_eff w
+      const double trw = w[0] + w[1] + w[2];
+      double nw = 0.0;
+      for (int i = 0; i < 6; ++i) nw += h.n[i] * w[i];
+      double cw[6];
+      for (int i = 0; i < 6; ++i)
+        cw[i] = (i < 3 ? m.K * trw : 0.0) + 2.0 * m.mu * h.th * (w[i] - (i < 3 ? trw / 3.0 : 0.0)) -
+                2.0 * m.mu * h.thb * nw * h.n[i];
+      double dg[6] = {0, 0, 0, 0, 0, 0};
+      if (h.plastic) dep_apply(h, gp, dg);
+      double ngp = 0.0;
+      for (int i = 0; i < 6; ++i) ngp += h.n[i] * gp[i];
+      for (int i = 0; i < 6; ++i)
+        gpo[i] = w1 * cw[i] - lv * h.gk * h.n[i] + gp[i] - dg[i] - h.gk * h.n[i] * gkap;
+      gko = -w1 * h.sk * nw + lv * h.kk + h.pk * ngp + h.kk * gkap;
+    }
+    for (int i = 0; i < 6; ++i) g_epsp_n[i * N + v] = gpo[i];
+    g_kappa_n[v] = gko;
+  }
+}
+
 // partials [0][block] = sum (a - b)^2, [1][block] = sum a^2
 FFTG_KERNEL void k_diff2(long long n, const double* __restrict__ a, const double* __restrict__ b,
                          double* __restrict__ partials) {
@@ -2126,6 +2288,23 @@ void launch_source_adj(const MatTable& tab, long long N, int c, int J, const uns
                        hipStream_t st) {
   hipLaunchKernelGGL(k_source_adj, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, c, J,
                      phase, eps, state_n, lam, out);
+}
+
+void launch_hist_out_cot(const MatTable& tab, long long N, int c, const unsigned char* phase,
+                         const double* eps, const double* state_n, const double* g_epsp,
+                         const double* g_kappa, double* g_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_hist_out_cot, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, c,
+                     phase, eps, state_n, g_epsp, g_kappa, g_eps);
+}
+
+void launch_hist_in_cot(const MatTable& tab, long long N, int c, int J, const unsigned char* phase,
+                        const double* eps, const double* state_n, const double* D,
+                        const double* mu, const double* g_sig, const double* lam,
+                        const double* g_epsp, const double* g_kappa, double* g_epsp_n,
+                        double* g_kappa_n, hipStream_t st) {
+  hipLaunchKernelGGL(k_hist_in_cot, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, c, J,
+                     phase, eps, state_n, D, mu, g_sig, lam, g_epsp, g_kappa, g_epsp_n,
+                     g_kappa_n);
 }
 
 void launch_stream_copy(const void* src, void* dst, long long n16, int blocks, hipStream_t st) {

@@ -162,6 +162,14 @@ void launch_source_adj(const MatTable& tab, long long N, int c, int J, const uns
                        const double* eps, const double* state_n, const double* lam, double* out,
                        hipStream_t st);
 void launch_stream_copy(const void* src, void* dst, long long n16, int blocks, hipStream_t st);
+void launch_hist_out_cot(const MatTable& tab, long long N, int c, const unsigned char* phase,
+                         const double* eps, const double* state_n, const double* g_epsp,
+                         const double* g_kappa, double* g_eps, hipStream_t st);
+void launch_hist_in_cot(const MatTable& tab, long long N, int c, int J, const unsigned char* phase,
+                        const double* eps, const double* state_n, const double* D,
+                        const double* mu, const double* g_sig, const double* lam,
+                        const double* g_epsp, const double* g_kappa, double* g_epsp_n,
+                        double* g_kappa_n, hipStream_t st);
 int launch_diff2(long long n, const double* a, const double* b, double* partials, hipStream_t st);
 void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
                   hipStream_t st);

@@ -301,3 +301,111 @@ def test_staggered_adjoint_two_fields_matches_oracle(shape):
     for j in range(2):
         assert np.abs(got[j] - ref["dell2"][j]).max() <= 1e-8 * np.abs(ref["dell2"][j]).max()
 
+
+
+@pytest.mark.parametrize("shape", [(12, 16), (6, 8, 8)])
+def test_increment_adjoint_matches_oracle(shape):
+    """fftg_increment_adjoint at a converged increment with history
+    cotangents coming in (random g_epsp, g_kappa, J = <sigma_11>): dJ/dell2
+    and the cotangents of the starting history against the oracle."""
+    from oracle import staggered
+    from tests.test_oracle_adjoint import STAG_TOLS
+    say("increment adjoint", shape)
+    rng = np.random.default_rng(21)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    nd = len(shape)
+    c = 6 if nd == 3 else 3
+    st_n, _, _, _ = staggered.staggered_step(phase, table, 1, staggered.initial_state(shape, nd, 1),
+                                             ms.uniaxial_mixed(nd, 3e-3), **STAG_TOLS)
+    tgt = ms.uniaxial_mixed(nd, 5e-3)
+    st, _, _, stats = staggered.staggered_step(phase, table, 1, st_n, tgt, **STAG_TOLS)
+    assert stats["converged"]
+    g = np.zeros((c,) + shape)
+    g[0] = 1.0 / phase.size
+    gp = rng.standard_normal((6,) + shape) / phase.size
+    gk = rng.standard_normal(shape) / phase.size
+    ref = adjoint.increment_adjoint(phase, table, 1, st_n, st, tgt, g_sig=g, g_epsp=gp, g_kappa=gk,
+                                    cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12, maxit=300)
+    s = solver(shape)
+    dl = torch.empty((1,) + shape, dtype=torch.float64, device="cuda")
+    gpn = torch.empty((6,) + shape, dtype=torch.float64, device="cuda")
+    gkn = torch.empty(shape, dtype=torch.float64, device="cuda")
+    d = s.fftg_increment_adjoint(dev(phase, torch.uint8), table, 1, dev(_pack(st_n)),
+                                 dev(_pack(st)), tgt, dl, gpn, gkn, g_sig=dev(g), g_epsp=dev(gp),
+                                 g_kappa=dev(gk), cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12,
+                                 maxit=300)
+    say("  gpu passes", d["stagger_iters"], "oracle passes", ref["iters"])
+    assert d["converged"]
+    for name, got, want in (("dell2", dl, ref["dell2"]), ("g_epsp_n", gpn, ref["g_epsp_n"]),
+                            ("g_kappa_n", gkn, ref["g_kappa_n"])):
+        got = got.cpu().numpy()
+        err = np.abs(got - want).max() / np.abs(want).max()
+        say("  ", name, "rel err %.2e" % err)
+        assert err <= 1e-8, name
+    # elastic particles pass the incoming plastic-history cotangents through
+    part = phase == 1
+    assert np.array_equal(gkn.cpu().numpy()[part], gk[part])
+
+
+def test_path_gradient_matches_oracle():
+    """d<sigma_11>/d ell2 after a three-increment path run on the GPU,
+    chained backwards through every increment's plastic history, against the
+    oracle's path gradient on its own path; the per-phase dJ/d ell through
+    torch.autograd (staggered_path) agrees too."""
+    from oracle import staggered
+    from paper_2103_04770_amd import autograd as ag
+    from tests.test_oracle_adjoint import STAG_TOLS
+    shape = (12, 16)
+    say("path gradient", shape)
+    rng = np.random.default_rng(21)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    targets = [ms.uniaxial_mixed(2, e) for e in (2e-3, 4e-3, 6e-3)]
+    st = staggered.initial_state(shape, 2, 1)
+    ostates = [st]
+    for tgt in targets:
+        st, _, hom, stats = staggered.staggered_step(phase, table, 1, st, tgt, **STAG_TOLS)
+        assert stats["converged"]
+        ostates.append(st)
+    g = np.zeros((3,) + shape)
+    g[0] = 1.0 / phase.size
+    ref = adjoint.path_gradient(phase, table, 1, ostates, targets, g, cg_tol=1e-13, pcg_tol=1e-13,
+                                tol=1e-12, maxit=300)
+    rq = adjoint.phase_length_gradient(ref[0], phase, table, 0)
+    s = solver(shape)
+    ph = dev(phase, torch.uint8)
+    opts = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, newton_maxit=60,
+                stagger_tol=1e-13, max_stagger=300)
+    state = dev(np.zeros((3 + 7 + 2,) + shape))
+    sig = torch.empty((3,) + shape, dtype=torch.float64, device="cuda")
+    states = [state.clone()]
+    for tgt in targets:
+        assert s.staggered_step(ph, table, 1, state, tgt, sig, **opts)["converged"]
+        states.append(state.clone())
+    dl, log = ag.path_gradient(s, ph, table, 1, states, targets, dev(g), cg_tol=1e-13,
+                               pcg_tol=1e-13, tol=1e-12, maxit=300)
+    got = dl.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say("  passes", [d["stagger_iters"] for d in log], "rel err %.2e" % err)
+    assert err <= 1e-7
+    ell = torch.tensor([2.0, 0.5], dtype=torch.float64, device="cuda", requires_grad=True)
+    sg = ag.staggered_path(s, ell, ph, table, 1, states[0], targets, **opts)
+    J = sg[0].mean()
+    assert float(J.detach()) == pytest.approx(hom["sigma"][0], rel=1e-9)
+    (ge,) = torch.autograd.grad(J, (ell,))
+    say("  dJ/dell gpu", ge.cpu().numpy(), "oracle", rq)
+    assert np.allclose(ge.cpu().numpy(), rq, rtol=1e-7)
+
+
+def test_increment_adjoint_rejects_uncovered_phases():
+    from paper_2103_04770_amd.binding import FFTGError
+    shape = (8, 8, 8)
+    s = solver(shape)
+    table = [ms.matrix_j2_damage(ell=[2.0, 0.04], dfield=0),
+             ms.particle_cracking(ell=[0.04, 1.0], dfield=1)]
+    z = dev(np.zeros((6 + 7 + 4,) + shape))
+    f = lambda *k: torch.empty(k + shape, dtype=torch.float64, device="cuda")  # noqa: E731
+    with pytest.raises(FFTGError, match="UNSUPPORTED"):
+        s.fftg_increment_adjoint(dev(np.zeros(shape), torch.uint8), table, 2, z, z,
+                                 ms.uniaxial_mixed(3, 1e-3), f(2), f(6), f())
