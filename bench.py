@@ -292,9 +292,10 @@ def run_c5(forms=("fp64", "fp32")):
     lengths 0.05 L / 0.001 L): 20 staggered increments of dE11 = 2e-3 to
     E11 = 0.04 (through the peak and into softening), then the total derivative
     of <sigma_11> at the last converged increment with respect to the two
-    per-phase lengths; FP64 and FP32-refined."""
+    per-phase lengths, at that increment alone and through the whole path
+    (plastic history of every increment); FP64 and FP32-refined."""
     import torch
-    from paper_2103_04770_amd import FP32_REFINED, FP64, Solver, microstructure as ms
+    from paper_2103_04770_amd import FP32_REFINED, FP64, Solver, autograd as ag, microstructure as ms
     w = ms.workload("spheres30_128")
     S, J = w["shape"], w["nfields"]
     tols = dict(TOLS, max_stagger=100)
@@ -305,6 +306,7 @@ def run_c5(forms=("fp64", "fp32")):
         state = torch.zeros((6 + 7 + 2 * J,) + S, dtype=torch.float64, device="cuda")
         sig = torch.empty((6,) + S, dtype=torch.float64, device="cuda")
         curve = []
+        states = [state.clone()]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(20):
@@ -313,6 +315,7 @@ def run_c5(forms=("fp64", "fp32")):
             curve.append(round(float(d["sigma_mean"][0]), 3))
             if not d["converged"]:
                 break
+            states.append(state.clone())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         g = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
@@ -323,19 +326,40 @@ def run_c5(forms=("fp64", "fp32")):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         sums = s.fftg_phase_sums(ph, 2, dl[0].contiguous())
+        rec = dict(increments=k + 1, e11_reached=float(w["load"][k][1][0]),
+                   all_converged=bool(d["converged"]), sigma11_curve=curve,
+                   path_s=round(t1 - t0, 3), adjoint_s=round(t2 - t1, 3),
+                   adjoint_passes=a["stagger_iters"], adjoint_converged=bool(a["converged"]),
+                   dJ_dell=[2.0 * float(t["ell"][0]) * float(v)
+                            for t, v in zip(w["table"], sums)])
+        if d["converged"]:
+            # the same J through the whole path: every increment's plastic
+            # history chained backwards (states of all increments kept in HBM)
+            t3 = time.perf_counter()
+            dlp, alog = ag.path_gradient(s, ph, w["table"], J, states, w["load"][:k + 1], g,
+                                         cg_tol=1e-8, pcg_tol=1e-8, tol=1e-6, maxit=300)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            sp = s.fftg_phase_sums(ph, 2, dlp[0].contiguous())
+            rec.update(path_gradient_s=round(t4 - t3, 3),
+                       path_gradient_passes=[x["stagger_iters"] for x in alog][::-1],
+                       dJ_dell_path=[2.0 * float(t["ell"][0]) * float(v)
+                                     for t, v in zip(w["table"], sp)],
+                       states_gb=round(len(states) * states[0].numel() * 8 / 1e9, 2))
         s.close()
-        out[form] = dict(increments=k + 1, e11_reached=float(w["load"][k][1][0]),
-                         all_converged=bool(d["converged"]), sigma11_curve=curve,
-                         path_s=round(t1 - t0, 3), adjoint_s=round(t2 - t1, 3),
-                         adjoint_passes=a["stagger_iters"], adjoint_converged=bool(a["converged"]),
-                         dJ_dell=[2.0 * float(t["ell"][0]) * float(v)
-                                  for t, v in zip(w["table"], sums)])
+        del states
+        out[form] = rec
         log("[c5] %s: %d increments to E11 %.3f in %.1f s, peak <s11> %.1f MPa; gradient %.2f s, "
-            "d<s11>/d ell = %s" % (form, k + 1, w["load"][k][1][0], t1 - t0, max(curve), t2 - t1,
-                                   ["%.5f" % v for v in out[form]["dJ_dell"]]))
+            "d<s11>/d ell = %s; through the path %s s, %s" % (
+                form, k + 1, w["load"][k][1][0], t1 - t0, max(curve), t2 - t1,
+                ["%.5f" % v for v in rec["dJ_dell"]], rec.get("path_gradient_s"),
+                ["%.5f" % v for v in rec.get("dJ_dell_path", [])]))
     if "fp64" in out and "fp32" in out:
-        a64, a32 = np.array(out["fp64"]["dJ_dell"]), np.array(out["fp32"]["dJ_dell"])
-        out["fp32_gradient_rel_err_vs_fp64"] = float(np.abs(a32 - a64).max() / np.abs(a64).max())
+        for key in ("dJ_dell", "dJ_dell_path"):
+            if key in out["fp64"] and key in out["fp32"]:
+                a64, a32 = np.array(out["fp64"][key]), np.array(out["fp32"][key])
+                out["fp32_rel_err_vs_fp64_" + key] = float(np.abs(a32 - a64).max() /
+                                                           np.abs(a64).max())
     return dict(workload="spheres30_128", path="20 x dE11 = 2e-3 to 0.04", **out)
 
 
