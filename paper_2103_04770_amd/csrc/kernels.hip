@@ -354,6 +354,17 @@ __device__ __forceinline__ long long line_base(long long L, long long inner, lon
   return (L / inner) * ostride + (L % inner);
 }
 
+// Workgroups go to the eight XCDs round-robin in launch order.  xcd_tile()
+// renumbers them so that each XCD takes one contiguous run of tiles: the
+// rows of the half spectrum (n1/2 + 1 points) are not cache-line aligned, so
+// neighbouring tiles of a strided pass share lines at their edges, which are
+// then fetched once into that XCD's L2 rather than once per XCD.  A bijection
+// of [0, nb) for any nb.
+__device__ __forceinline__ long long xcd_tile(long long b, long long nb) {
+  const long long q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // SH: tile budget code (chosen per handle by timing): FFTG_TILE_BYTES >> SH
 // for SH = 0, 1, 2, twice FFTG_TILE_BYTES for SH = 3 (gfx950 workgroups may
 // hold up to 160 KB of LDS).
@@ -373,7 +384,7 @@ FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>
   const int TL = FIX ? fs_tile<T, TB>(NF) : TL_rt;
   // TL divides NT: each thread stays on line l of the tile
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
-  const long long L = (long long)blockIdx.x * TL + l;
+  const long long L = xcd_tile(blockIdx.x, gridDim.x) * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
   for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? data[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
