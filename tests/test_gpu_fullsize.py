@@ -7,6 +7,7 @@ non-local fields), and the constitutive update recomputed by the oracle at
 sampled voxels from the GPU strain and state.
 """
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -158,3 +159,121 @@ def test_fp32_refined_homogenised_stress(run128):
         err = np.abs(a - b).max() / np.abs(b).max()
         say("increment", k, "fp32-refined vs fp64 homogenised stress", err)
         assert err <= 1e-6
+
+
+# ---------------------------------------------------------------- adjoints at 128^3
+# The differentiation workload's RVE (30 spheres, 128^3, lengths 6.4 / 0.128
+# voxels) with the damage thresholds lowered (dC = 5e-4, dR = 0.1) so that
+# damage is active within a few increments (D reaches ~0.05 at E11 = 0.004)
+# while the staggered fixed point still contracts fast enough to be converged
+# to 1e-9 in about ten passes.  The oracle cannot run these
+# increments, so the adjoints are checked against a property that holds at any
+# size: central differences of the GPU forward itself.
+ADJ_TOLS = dict(cg_tol=1e-10, pcg_tol=1e-10, newton_tol=1e-9, stagger_tol=1e-9,
+                max_stagger=60)
+ADJ_E11 = (2e-3, 4e-3, 6e-3)
+
+
+def _adj_table(ell=None):
+    w = ms.workload("spheres30_128")
+    table = [dict(t) for t in w["table"]]
+    table[0].update(dC=5e-4, dR=0.1)
+    if ell is not None:
+        for t, e in zip(table, ell):
+            t["ell"] = [e]
+    return w, table
+
+
+def _adj_path(s, ph, table, e11s, state0=None):
+    """Runs the increments from state0 (virgin if None); returns the packed
+    states before each increment and after the last, and <sigma_11>."""
+    S = tuple(ph.shape)
+    state = (torch.zeros((6 + 7 + 2,) + S, dtype=torch.float64, device="cuda")
+             if state0 is None else state0.clone())
+    sig = torch.empty((6,) + S, dtype=torch.float64, device="cuda")
+    states = [state.clone()]
+    d = None
+    for e in e11s:
+        t0 = time.perf_counter()
+        d = s.staggered_step(ph, table, 1, state, ms.uniaxial_mixed(3, e), sig, **ADJ_TOLS)
+        say("    E11 %.3f: %d passes, %d CG, err %.1e, %.1f s" % (
+            e, d["stagger_iters"], d["cg_iters"], d["err"], time.perf_counter() - t0))
+        assert d["converged"], d
+        states.append(state.clone())
+    return states, float(d["sigma_mean"][0])
+
+
+@pytest.fixture(scope="module")
+def adj128():
+    from paper_2103_04770_amd import Solver
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w, table = _adj_table()
+    s = Solver(tuple(reversed(w["shape"])))
+    ph = torch.from_numpy(w["phase"]).cuda()
+    say("128^3 adjoint path", ADJ_E11)
+    states, J = _adj_path(s, ph, table, ADJ_E11)
+    yield dict(s=s, ph=ph, w=w, table=table, states=states, J=J)
+    s.close()
+
+
+def _fd(adj, q, rel, e11s, state0):
+    ells = [float(t["ell"][0]) for t in adj["table"]]
+    hq = rel * ells[q]
+    vals = []
+    for sgn in (1, -1):
+        e = list(ells)
+        e[q] += sgn * hq
+        _, tab = _adj_table(e)
+        say("  fd phase", q, "sign", sgn)
+        vals.append(_adj_path(adj["s"], adj["ph"], tab, e11s, state0)[1])
+    return (vals[0] - vals[1]) / (2 * hq)
+
+
+def test_increment_adjoint_128_by_central_differences(adj128):
+    """d<sigma_11>/d ell_q of the last increment (E11 0.004 -> 0.006, damage
+    active), its starting state held fixed: fftg_staggered_adjoint against
+    central differences of that GPU increment (h = 1e-3 ell_q)."""
+    from oracle import adjoint  # only to sum per phase
+    a = adj128
+    s, ph, table, states = a["s"], a["ph"], a["table"], a["states"]
+    shape = a["w"]["shape"]
+    g = torch.zeros((6,) + shape, dtype=torch.float64, device="cuda")
+    g[0] = 1.0 / float(np.prod(shape))
+    dl = torch.empty((1,) + shape, dtype=torch.float64, device="cuda")
+    d = s.fftg_staggered_adjoint(ph, table, 1, states[-2], states[-1], ms.uniaxial_mixed(3, ADJ_E11[-1]),
+                                 dl, g_sig=g, cg_tol=1e-10, pcg_tol=1e-10, tol=1e-9, maxit=100)
+    assert d["converged"]
+    grad = adjoint.phase_length_gradient(dl[0].cpu().numpy(), a["w"]["phase"], table, 0)
+    for q in range(2):
+        fd = _fd(a, q, 1e-3, ADJ_E11[-1:], states[-2])
+        say("  phase", q, "adjoint %.6e fd %.6e" % (grad[q], fd))
+        # J converged to ~1e-9 relative: noise of the difference ~3e-7 / (2 h ell_q),
+        # 1e-4 of the matrix derivative, 1e-3 of the particle one (ell 50x smaller)
+        assert grad[q] == pytest.approx(fd, rel=(2e-4, 2e-3)[q])
+
+
+def test_path_gradient_128_by_central_differences(adj128):
+    """d<sigma_11>/d ell_matrix after three increments from the virgin state,
+    through the plastic history of every increment (autograd.path_gradient),
+    against central differences of the whole GPU path; it differs from the
+    last increment's own derivative."""
+    from oracle import adjoint
+    from paper_2103_04770_amd import autograd as ag
+    a = adj128
+    s, ph, table, states = a["s"], a["ph"], a["table"], a["states"]
+    shape = a["w"]["shape"]
+    g = torch.zeros((6,) + shape, dtype=torch.float64, device="cuda")
+    g[0] = 1.0 / float(np.prod(shape))
+    dl, log = ag.path_gradient(s, ph, table, 1, states, [ms.uniaxial_mixed(3, e) for e in ADJ_E11],
+                               g, cg_tol=1e-10, pcg_tol=1e-10, tol=1e-9, maxit=100)
+    grad = adjoint.phase_length_gradient(dl[0].cpu().numpy(), a["w"]["phase"], table, 0)
+    last = torch.empty((1,) + shape, dtype=torch.float64, device="cuda")
+    s.fftg_staggered_adjoint(ph, table, 1, states[-2], states[-1], ms.uniaxial_mixed(3, ADJ_E11[-1]),
+                             last, g_sig=g, cg_tol=1e-10, pcg_tol=1e-10, tol=1e-9, maxit=100)
+    one = adjoint.phase_length_gradient(last[0].cpu().numpy(), a["w"]["phase"], table, 0)
+    fd = _fd(a, 0, 1e-3, ADJ_E11, None)
+    say("  path passes", [d["stagger_iters"] for d in log], "path %.6e last-only %.6e fd %.6e" % (
+        grad[0], one[0], fd))
+    assert grad[0] == pytest.approx(fd, rel=2e-4)
+    assert abs(one[0] - fd) > 10 * abs(grad[0] - fd)
