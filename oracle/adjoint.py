@@ -175,7 +175,8 @@ def staggered_adjoint(phase, table, nfields, state_n, eps, abar, target, g_eps=N
         mu0 = A^-1 G*(g_eps + K g_sig)
     (the damage term is mechanics_adjoint's dD, the damage-law slope D' is
     damage_adjoint's).  Iterated like the forward scheme until
-    ||z_new - z|| <= tol ||z_new||.  Returns dict(dell2 (J, *S), lam, z, iters)."""
+    ||z_new - z|| <= tol ||z_new||.  Returns dict(dell2 (J, *S), lam, z, iters,
+    mu (the total mechanics adjoint), D, zeta (the total damage cotangent dJ/dD))."""
     S = phase.shape
     c = eps.shape[0]
     J = nfields
@@ -213,11 +214,13 @@ def staggered_adjoint(phase, table, nfields, state_n, eps, abar, target, g_eps=N
     qt = [np.broadcast_to(v, S) for v in qt]
     dell2 = np.stack([-sum(a * b for a, b in zip(grad_fields(lam[j], qt), grad_fields(abar[j], qt)))
                       for j in range(J)])
-    # total mechanics adjoint: mu = A^-1 G*(g_eps + K g_sig + alpha'^T lam)
+    # total mechanics adjoint: mu = A^-1 G*(g_eps + K g_sig + alpha'^T lam), and
+    # the total damage cotangent zeta = dJ/dD at the fixed point
     rhs = g_eps + (lam[:, None] * dadx).sum(axis=0)
-    mu = mechanics_adjoint(phase, table, D, state_n["epsp"], state_n["kappa"], target, eps, rhs, J,
-                           h=h, scheme=scheme, cg_tol=cg_tol, gsig=g_sig)["mu"]
-    return dict(dell2=dell2, lam=lam, z=z, iters=it, mu=mu, D=D)
+    mt = mechanics_adjoint(phase, table, D, state_n["epsp"], state_n["kappa"], target, eps, rhs, J,
+                           h=h, scheme=scheme, cg_tol=cg_tol, gsig=g_sig)
+    zeta = mt["dD"] if g_D is None else mt["dD"] + g_D
+    return dict(dell2=dell2, lam=lam, z=z, iters=it, mu=mt["mu"], D=D, zeta=zeta)
 
 
 def history_partials(eps, epsp_n, kappa_n, phase, table):
@@ -265,7 +268,7 @@ def history_partials(eps, epsp_n, kappa_n, phase, table):
 
 
 def increment_adjoint(phase, table, nfields, state_n, state_np1, target, g_sig=None,
-                      g_epsp=None, g_kappa=None, **kw):
+                      g_epsp=None, g_kappa=None, g_hist=None, **kw):
     """Adjoint of one converged staggered increment with respect to the
     squared lengths and to the plastic history it started from.
 
@@ -283,14 +286,23 @@ def increment_adjoint(phase, table, nfields, state_n, state_np1, target, g_sig=N
                      + dep_dkn . g_epsp + dk_dkn g_kappa
     (a parameter theta entering sigma at fixed strain contributes
     (g_sig - mu) . d sigma/d theta, one entering the source lam d alpha/d theta).
-    Returns dict(dell2, g_epsp_n (6, *S), g_kappa_n (*S), iters)."""
+
+    The damage history hist_{n+1} = max(hist_n, abar) (cotangent g_hist, J
+    fields) is read back only by the cracking law D = D(max(hist_n, abar)).
+    Where abar is the max (abar >= hist_n, the damage law's own convention at
+    the tie) g_hist joins the abar cotangent of the fixed point; where hist_n
+    is, it passes to hist_n, and so does the total damage cotangent zeta of
+    a cracking voxel whose history drives D inside the slope band:
+      dJ/d hist_n = g_hist [hist_n > abar] + zeta / (dR - dC) [cracking, hist_n > abar,
+                    0 < (hist_n - dC)/(dR - dC) < dmax]
+    Returns dict(dell2, g_epsp_n (6, *S), g_kappa_n (*S), g_hist_n (J, *S), iters)."""
     S = phase.shape
     M = phase.size
     eps = state_np1["eps"]
     c = eps.shape[0]
     for ph in table:
-        if ph["model"] not in ("elastic", "j2_damage"):
-            raise NotImplementedError("history adjoint: J2 damage and elastic phases only")
+        if ph["model"] not in ("elastic", "j2_damage", "elastic_cracking"):
+            raise NotImplementedError("history adjoint: J2 damage, elastic and cracking phases only")
     e6 = (mandel.expand_plane(eps) if c == 3 else eps).reshape(6, M)
     ep_n = state_n["epsp"].reshape(6, M)
     k_n = state_n["kappa"].reshape(M)
@@ -302,8 +314,11 @@ def increment_adjoint(phase, table, nfields, state_n, state_np1, target, g_sig=N
     if g_kappa is not None:
         ge += hp["dk_de"] * g_kappa.reshape(M)[None]
     g_eps = ge[cidx].reshape((c,) + S)
-    r = staggered_adjoint(phase, table, nfields, state_n, eps, state_np1["abar"], target,
-                          g_eps=g_eps, g_sig=g_sig, **kw)
+    abar = state_np1["abar"]
+    by_hist = state_n["hist"] > abar              # the history, not abar, is the max
+    g_abar = None if g_hist is None else np.where(by_hist, 0.0, g_hist)
+    r = staggered_adjoint(phase, table, nfields, state_n, eps, abar, target,
+                          g_eps=g_eps, g_sig=g_sig, g_abar=g_abar, **kw)
     mu = r["mu"].reshape(c, M)
     gs = np.zeros((c, M)) if g_sig is None else g_sig.reshape(c, M)
     w6 = np.zeros((6, M))
@@ -335,22 +350,33 @@ def increment_adjoint(phase, table, nfields, state_n, state_np1, target, g_sig=N
         gkap = g_kappa.reshape(M)
         gep -= hp["dk_de"] * gkap[None]
         gk += hp["dk_dkn"] * gkap
+    gh = np.zeros(abar.shape) if g_hist is None else np.where(by_hist, g_hist, 0.0)
+    for p, ph in enumerate(table):
+        j = ph["dfield"]
+        if ph["model"] != "elastic_cracking" or j < 0:
+            continue
+        sel = phase == p
+        d = (state_n["hist"][j][sel] - ph["dC"]) / (ph["dR"] - ph["dC"])
+        inside = by_hist[j][sel] & (d > 0.0) & (d < ph["dmax"])
+        gh[j][sel] += np.where(inside, r["zeta"][j][sel] / (ph["dR"] - ph["dC"]), 0.0)
     return dict(dell2=r["dell2"], g_epsp_n=gep.reshape((6,) + S), g_kappa_n=gk.reshape(S),
-                iters=r["iters"])
+                g_hist_n=gh, iters=r["iters"])
 
 
 def path_gradient(phase, table, nfields, states, targets, g_sig, **kw):
     """dJ/d ell2_j(x) of J = g_sig . sigma after the last of a sequence of
     converged staggered increments, through the whole path: states[k] is the
     state before increment k (states[-1] after the last), targets[k] its
-    macro target.  Walks the increments backwards, passing the plastic-history
-    cotangents from each increment to the one before (increment_adjoint)."""
+    macro target.  Walks the increments backwards, passing the history
+    cotangents (plastic state and damage history) from each increment to the
+    one before (increment_adjoint)."""
     n = len(targets)
-    ge = gk = None
+    ge = gk = gh = None
     dell2 = 0.0
     for k in range(n - 1, -1, -1):
         r = increment_adjoint(phase, table, nfields, states[k], states[k + 1], targets[k],
-                              g_sig=g_sig if k == n - 1 else None, g_epsp=ge, g_kappa=gk, **kw)
+                              g_sig=g_sig if k == n - 1 else None, g_epsp=ge, g_kappa=gk,
+                              g_hist=gh, **kw)
         dell2 = dell2 + r["dell2"]
-        ge, gk = r["g_epsp_n"], r["g_kappa_n"]
+        ge, gk, gh = r["g_epsp_n"], r["g_kappa_n"], r["g_hist_n"]
     return dell2

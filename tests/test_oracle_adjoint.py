@@ -494,3 +494,100 @@ def test_path_gradient_by_finite_differences():
         fd = (vals[0] - vals[1]) / (2 * hq)
         assert grad[q] == pytest.approx(fd, rel=5e-4, abs=1e-6 * abs(grad).max())
     assert np.abs(grad - one).max() > 1e-3 * np.abs(grad).max()
+
+
+def _two_field_case():
+    S = (10, 12)
+    rng = np.random.default_rng(23)
+    phase = (rng.uniform(size=S) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0, 0.04], dfield=0, dC=0.0005, dR=0.02),
+             ms.particle_cracking(ell=[0.04, 1.0], dfield=1, k0=5e-4, kf=5e-3)]
+    return S, phase, table
+
+
+def test_increment_adjoint_damage_history_by_finite_differences():
+    """Cotangent of the damage history hist_n (read back by the cracking law
+    through max(hist_n, abar)) of one converged two-field increment, with
+    J = <sigma_11> + sum c . hist_{n+1} (so that an incoming history cotangent
+    is exercised too), against directional central differences in hist_n.
+    The history is raised above abar on some cracking voxels, as after an
+    earlier, larger load, so that it drives their damage."""
+    from oracle import staggered
+    S, phase, table = _two_field_case()
+    st0 = staggered.initial_state(S, 2, 2)
+    st_n = staggered.staggered_step(phase, table, 2, st0, ms.uniaxial_mixed(2, 2e-3),
+                                    **STAG_TOLS)[0]
+    rng = np.random.default_rng(5)
+    crack = phase == 1
+    raise_ = crack & (rng.uniform(size=S) < 0.5)
+    st_n = dict(st_n, hist=st_n["hist"].copy())
+    st_n["hist"][1][raise_] = np.maximum(st_n["hist"][1][raise_], st_n["abar"][1][raise_]) + \
+        rng.uniform(1e-3, 2e-3, size=int(raise_.sum()))
+    tgt = ms.uniaxial_mixed(2, 3e-3)
+    st = staggered.staggered_step(phase, table, 2, st_n, tgt, **STAG_TOLS)[0]
+    by_hist = st_n["hist"][1] > st["abar"][1] + 1e-5
+    assert (by_hist & crack).sum() >= 5 and (~by_hist & crack & (st["abar"][1] > 5e-4)).sum() >= 5
+    g = np.zeros((3,) + S)
+    g[0] = 1.0 / phase.size
+    cw = np.zeros((2,) + S)
+    cw[1] = rng.standard_normal(S) / phase.size
+    r = adjoint.increment_adjoint(phase, table, 2, st_n, st, tgt, g_sig=g, g_hist=cw)
+    dh = np.zeros((2,) + S)
+    dh[1] = np.where(by_hist, rng.uniform(0.5, 1.0, size=S), 0.0)   # stays on its side of the max
+    dh[1] += np.where(~by_hist & ~crack, rng.uniform(0.0, 1.0, size=S), 0.0)
+
+    def J(hist):
+        s2, _, hom, stats = staggered.staggered_step(phase, table, 2, dict(st_n, hist=hist), tgt,
+                                                     **STAG_TOLS)
+        assert stats["converged"]
+        return hom["sigma"][0] + float((cw * s2["hist"]).sum())
+
+    h = 1e-7
+    fd = (J(st_n["hist"] + h * dh) - J(st_n["hist"] - h * dh)) / (2 * h)
+    got = float((r["g_hist_n"] * dh).sum())
+    assert got == pytest.approx(fd, rel=2e-4)
+    assert abs(got) > 1e-3 * abs(float((cw * dh).sum())) + 1e-12
+
+
+def test_path_gradient_with_cracking_and_unloading_by_finite_differences():
+    """d<sigma_11>/d ell of both fields and both phases after a two-field
+    path that loads and partly unloads (E11 2e-3, 3e-3, 2.5e-3): on unloading
+    the cracking voxels' damage stays at its history, so the gradient runs
+    through the damage-history cotangents too.  Against central differences of
+    the whole path."""
+    from oracle import staggered
+    S, phase, table = _two_field_case()
+    e11s = [2e-3, 3e-3, 2.5e-3]
+
+    def path(tab):
+        st = staggered.initial_state(S, 2, 2)
+        states, targets = [st], []
+        hom = None
+        for e in e11s:
+            tgt = ms.uniaxial_mixed(2, e)
+            st, _, hom, stats = staggered.staggered_step(phase, tab, 2, st, tgt, **STAG_TOLS)
+            assert stats["converged"]
+            states.append(st)
+            targets.append(tgt)
+        return states, targets, hom
+
+    states, targets, _ = path(table)
+    held = (states[2]["hist"][1] > states[3]["abar"][1]) & (phase == 1) & \
+        (states[2]["hist"][1] > 5e-4)
+    assert held.sum() >= 5                         # damage held at its history on unloading
+    g = np.zeros((3,) + S)
+    g[0] = 1.0 / phase.size
+    dl = adjoint.path_gradient(phase, table, 2, states, targets, g)
+    for j in range(2):
+        grad = adjoint.phase_length_gradient(dl[j], phase, table, j)
+        for q in range(2):
+            e0 = table[q]["ell"][j]
+            hq = 1e-4 * e0
+            vals = []
+            for sgn in (1, -1):
+                tb = [dict(t, ell=list(t["ell"])) for t in table]
+                tb[q]["ell"][j] = e0 + sgn * hq
+                vals.append(path(tb)[2]["sigma"][0])
+            fd = (vals[0] - vals[1]) / (2 * hq)
+            assert grad[q] == pytest.approx(fd, rel=5e-4, abs=1e-5 * max(abs(grad).max(), 1e-9)), \
+                (j, q)
