@@ -274,14 +274,17 @@ fftg_status fftg_staggered_adjoint(fftg_handle* h, const unsigned char* phase,
                                    fftg_stats* stats);
 
 /* Adjoint of one converged staggered increment with respect to the squared
- * lengths AND to the plastic history it started from, so that increments can
- * be chained backwards along a load path (Sec. 2.1: the J2 return and its
- * history eps_p, kappa; Sec. 2.3 and Algorithm 1: the increment).  A
- * functional J depends on this increment through the stress (g_sig) and
- * through the committed plastic state eps_p,{n+1}, kappa_{n+1} (g_epsp,
- * g_kappa: the history cotangents a later increment returned).  The call
+ * lengths AND to the history it started from, so that increments can be
+ * chained backwards along a load path (Sec. 2.1: the J2 return and its
+ * history eps_p, kappa; Sec. 2.2: the particle cracking law and its damage
+ * history; Sec. 2.3 and Algorithm 1: the increment).  A functional J depends
+ * on this increment through the stress (g_sig), through the committed plastic
+ * state eps_p,{n+1}, kappa_{n+1} (g_epsp, g_kappa) and through the committed
+ * damage history hist_{n+1} = max(hist_n, abar) (g_hist): the history
+ * cotangents a later increment returned.  The call
  *   1. turns g_epsp, g_kappa into a strain cotangent through the derivatives
- *      of the return map at the converged strain,
+ *      of the return map at the converged strain, and g_hist into an abar
+ *      cotangent where abar is the max (abar >= hist_n),
  *   2. runs fftg_staggered_adjoint's coupled adjoint (dell2, lam) and the
  *      total mechanics adjoint mu = A^-1 G*(g_eps + K g_sig + alpha'^T lam),
  *   3. writes the cotangents of the history the increment started from: on a
@@ -292,24 +295,30 @@ fftg_status fftg_staggered_adjoint(fftg_handle* h, const unsigned char* phase,
  *                    + lam dkappa/dkappa_n + deps_p/dkappa_n . g_epsp
  *                    + dkappa/dkappa_n g_kappa
  *      (C_eff the consistent tangent of the return, lam of the phase's field);
- *      an elastic voxel passes g_epsp, g_kappa through unchanged.
+ *      an elastic or cracking voxel passes g_epsp, g_kappa through unchanged;
+ *      and, per field, g_hist_n = g_hist where hist_n > abar, plus
+ *      zeta / (dR - dC) on a cracking voxel whose history drives its damage
+ *      inside the slope band (zeta = dJ/dD, the total damage cotangent).
  * Summing dell2 over the increments of a path, last to first, feeding each
  * call the g_epsp_n, g_kappa_n of the one after it (g_sig only on the last),
  * gives dJ/dell2 of the whole path.
  *   state_n, state_np1 dev packed states before / after the increment
  *   g_sig      dev [c][N] or NULL;  g_epsp dev [6][N] or NULL (Mandel);
- *   g_kappa    dev [N] or NULL
- *   dell2      dev [nfields][N] out;  g_epsp_n dev [6][N] out;  g_kappa_n dev [N] out
+ *   g_kappa    dev [N] or NULL;  g_hist dev [nfields][N] or NULL
+ *   dell2      dev [nfields][N] out;  g_epsp_n dev [6][N] out;  g_kappa_n dev [N] out;
+ *   g_hist_n   dev [nfields][N] out
  *   cg, pcg, tol, maxit, stats as fftg_staggered_adjoint
- * Tables with a phase other than FFTG_ELASTIC or FFTG_J2_DAMAGE (linear
- * hardening) return FFTG_E_UNSUPPORTED; an inner solve at its cap or the
- * fixed point at maxit gives FFTG_NOT_CONVERGED with the outputs written. */
+ * Tables with a Gurson phase return FFTG_E_UNSUPPORTED (J2 damage with linear
+ * hardening, elastic and cracking phases are covered); an inner solve at its
+ * cap or the fixed point at maxit gives FFTG_NOT_CONVERGED with the outputs
+ * written. */
 fftg_status fftg_increment_adjoint(fftg_handle* h, const unsigned char* phase,
                                    const fftg_phase* tab, int nphase, int nfields,
                                    const double* state_n, const double* state_np1,
                                    const fftg_macro* target, const double* g_sig,
-                                   const double* g_epsp, const double* g_kappa, double* dell2,
-                                   double* g_epsp_n, double* g_kappa_n,
+                                   const double* g_epsp, const double* g_kappa,
+                                   const double* g_hist, double* dell2, double* g_epsp_n,
+                                   double* g_kappa_n, double* g_hist_n,
                                    const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
                                    double tol, int maxit, fftg_stats* stats);
 

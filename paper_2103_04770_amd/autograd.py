@@ -206,36 +206,37 @@ def staggered_increment(solver, ell, phase, table, nfields, state_n, target, fie
                                      opts)
 
 
-
 def path_gradient(solver, phase, table, nfields, states, targets, g_sig, cg_tol=1e-10,
                   pcg_tol=1e-10, tol=1e-10, maxit=200):
     """dJ/dell2_j(x) (nfields, *S) of J = g_sig . sigma after the last
     increment of a converged load path: states[k] is the packed state before
     increment k (states[-1] after the last), targets[k] its macro target.
     The increments are walked last to first; each fftg_increment_adjoint call
-    returns the cotangents of the plastic history its increment started from,
-    which the call for the increment before receives.  Returns (dell2, stats
-    of every call, last first)."""
+    returns the cotangents of the history (plastic state, damage history) its
+    increment started from, which the call for the increment before receives.
+    Returns (dell2, stats of every call, last first)."""
     S = solver.spatial
     f64 = dict(dtype=torch.float64, device="cuda")
     total = torch.zeros((nfields,) + S, **f64)
     dl = torch.empty((nfields,) + S, **f64)
-    ge, gk = None, None
-    gen, gkn = torch.empty((6,) + S, **f64), torch.empty(S, **f64)
+    cur = None                                     # (g_epsp, g_kappa, g_hist) coming in
+    nxt = (torch.empty((6,) + S, **f64), torch.empty(S, **f64),
+           torch.empty((nfields,) + S, **f64))
     log = []
     for k in range(len(targets) - 1, -1, -1):
         d = solver.fftg_increment_adjoint(
-            phase, table, nfields, states[k], states[k + 1], targets[k], dl, gen, gkn,
-            g_sig=g_sig if k == len(targets) - 1 else None, g_epsp=ge, g_kappa=gk,
-            cg_tol=cg_tol, pcg_tol=pcg_tol, tol=tol, maxit=maxit)
+            phase, table, nfields, states[k], states[k + 1], targets[k], dl, *nxt,
+            g_sig=g_sig if k == len(targets) - 1 else None,
+            g_epsp=None if cur is None else cur[0], g_kappa=None if cur is None else cur[1],
+            g_hist=None if cur is None else cur[2], cg_tol=cg_tol, pcg_tol=pcg_tol, tol=tol,
+            maxit=maxit)
         if not d["converged"]:
             raise RuntimeError("increment adjoint %d did not converge: %s" % (k, d))
         log.append(d)
         total += dl
-        if ge is None:
-            ge, gk = torch.empty_like(gen), torch.empty_like(gkn)
-        ge, gen = gen, ge
-        gk, gkn = gkn, gk
+        if cur is None:
+            cur = tuple(torch.empty_like(t) for t in nxt)
+        cur, nxt = nxt, cur
     return total, log
 
 
@@ -273,6 +274,6 @@ def staggered_path(solver, ell, phase, table, nfields, state_0, targets, field=0
     (macro targets `targets`, from the packed state_0), differentiable in the
     per-phase lengths `ell` of `field` through the whole path.  Keeps every
     increment's packed state on the device.  Phases covered: J2 damage
-    (linear hardening) and elastic."""
+    (linear hardening), elastic and cracking."""
     return _StaggeredPath.apply(ell, solver, phase, table, nfields, state_0, list(targets), field,
                                 opts)

@@ -122,8 +122,8 @@ def load_library():
                                    P, P, P, P, ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D,
                                    I, ct.POINTER(Stats)],
         "fftg_increment_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, ct.POINTER(Macro), P, P,
-                                   P, P, P, P, ct.POINTER(KrylovOpts), ct.POINTER(KrylovOpts), D,
-                                   I, ct.POINTER(Stats)],
+                                   P, P, P, P, P, P, ct.POINTER(KrylovOpts),
+                                   ct.POINTER(KrylovOpts), D, I, ct.POINTER(Stats)],
         "fftg_damage": [P, P, ct.POINTER(Phase), I, I, P, P, P],
         "fftg_damage_adjoint": [P, P, ct.POINTER(Phase), I, I, P, P, P, P],
         "fftg_ell2": [P, P, ct.POINTER(Phase), I, I, P],
@@ -392,13 +392,14 @@ class Solver:
         return d
 
     def fftg_increment_adjoint(self, phase, table, nfields, state_n, state_np1, target, dell2,
-                               g_epsp_n, g_kappa_n, g_sig=None, g_epsp=None, g_kappa=None,
-                               cg_tol=1e-10, cg_maxit=5000, pcg_tol=1e-10, pcg_maxit=5000,
-                               tol=1e-10, maxit=200):
+                               g_epsp_n, g_kappa_n, g_hist_n, g_sig=None, g_epsp=None,
+                               g_kappa=None, g_hist=None, cg_tol=1e-10, cg_maxit=5000,
+                               pcg_tol=1e-10, pcg_maxit=5000, tol=1e-10, maxit=200):
         """Adjoint of one converged increment: dell2 <- dJ/dell2_j(x) through
-        this increment, g_epsp_n (6, *S), g_kappa_n (*S) <- the cotangents of
-        the plastic history it started from, given g_sig (c, *S) and the
-        cotangents g_epsp, g_kappa of the history it committed."""
+        this increment; g_epsp_n (6, *S), g_kappa_n (*S), g_hist_n (J, *S) <-
+        the cotangents of the plastic state and damage history it started
+        from, given g_sig (c, *S) and the cotangents g_epsp, g_kappa, g_hist of
+        the history it committed."""
         f64 = self.torch.float64
         n = nfields * self.N
         nst = (self.c + 7 + 2 * nfields) * self.N
@@ -409,8 +410,9 @@ class Solver:
             self.h, _ptr(phase, self.torch.uint8, self.N, "phase"), phase_table(table), len(table),
             nfields, _ptr(state_n, f64, nst, "state_n"), _ptr(state_np1, f64, nst, "state_np1"),
             ct.byref(m), opt(g_sig, self.c * self.N, "g_sig"), opt(g_epsp, 6 * self.N, "g_epsp"),
-            opt(g_kappa, self.N, "g_kappa"), _ptr(dell2, f64, n, "dell2"),
+            opt(g_kappa, self.N, "g_kappa"), opt(g_hist, n, "g_hist"), _ptr(dell2, f64, n, "dell2"),
             _ptr(g_epsp_n, f64, 6 * self.N, "g_epsp_n"), _ptr(g_kappa_n, f64, self.N, "g_kappa_n"),
+            _ptr(g_hist_n, f64, n, "g_hist_n"),
             ct.byref(KrylovOpts(cg_tol, cg_maxit)), ct.byref(KrylovOpts(pcg_tol, pcg_maxit)),
             float(tol), int(maxit), ct.byref(st)))
         d = st.as_dict()

@@ -99,7 +99,8 @@ struct fftg_handle {
   double* drive_bak = nullptr;
   double* adj_r = nullptr;  // adjoint: two FP64 real scratch fields
   double* sadj = nullptr;   // staggered adjoint: (2c + 5J) FP64 real fields
-  double* hadj = nullptr;   // increment adjoint: strain cotangent of the history (c fields)
+  double* hadj = nullptr;   // increment adjoint: history cotangents (c + J fields)
+  int hadjJ = 0;
   // tile-budget shifts of the fixed-length strided passes (inner y passes,
   // outer-axis passes), chosen at creation by timing; times of each choice
   int tsh_y = 0, tsh_o = 0;
@@ -1184,7 +1185,8 @@ namespace {
 // Coupled adjoint of a converged staggered increment on a validated call
 // (J2 damage, cracking and elastic phases).  Leaves lam (J x N) and, with
 // total_mu, the total mechanics adjoint mu = A^-1 G*(g_eps + K g_sig +
-// alpha'^T lam) (c x N) in the handle's adjoint buffers; dell2 receives
+// alpha'^T lam) (c x N) and the total damage cotangent zeta = dJ/dD (J x N)
+// in the handle's adjoint buffers; dell2 receives
 // -sum_i G_i lam_j G_i abar_j.
 struct AdjOut {
   fftg_stats stats{};
@@ -1192,6 +1194,7 @@ struct AdjOut {
   bool inner_capped = false;
   const double* lam = nullptr;
   const double* mu = nullptr;
+  const double* zeta = nullptr;  // with total_mu: the total damage cotangent dJ/dD [J][N]
 };
 
 AdjOut stag_adjoint_core(fftg_handle* H, const unsigned char* phase, const MatTable& t, int J,
@@ -1296,7 +1299,9 @@ AdjOut stag_adjoint_core(fftg_handle* H, const unsigned char* phase, const MatTa
     fftg::launch_source_adj(t, N, c, J, phase, eps, epsp_n, lam, rhs, H->st);
     if (g_eps) fftg::launch_axpby((long long)c * N, 1.0, rhs, 1.0, g_eps, rhs, H->st);
     mech(rhs, g_sig);
+    if (g_D) fftg::launch_axpby((long long)J * N, 1.0, dD, 1.0, g_D, dD, H->st);
     out.mu = mu;
+    out.zeta = dD;
   }
   acc.stagger_iters = out.converged ? k : maxit;
   acc.err = err;
@@ -1868,38 +1873,53 @@ fftg_status fftg_increment_adjoint(fftg_handle* H, const unsigned char* phase,
                                    const fftg_phase* tab, int nphase, int nfields,
                                    const double* state_n, const double* state_np1,
                                    const fftg_macro* target, const double* g_sig,
-                                   const double* g_epsp, const double* g_kappa, double* dell2,
-                                   double* g_epsp_n, double* g_kappa_n,
+                                   const double* g_epsp, const double* g_kappa,
+                                   const double* g_hist, double* dell2, double* g_epsp_n,
+                                   double* g_kappa_n, double* g_hist_n,
                                    const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
                                    double tol, int maxit, fftg_stats* stats) {
   if (!H) return FFTG_E_INVALID;
   return run_guarded(H, [&]() -> fftg_status {
     validate_table(tab, nphase, nfields);
     validate_macro(target, H->c);
-    if (!phase || !state_n || !state_np1 || !dell2 || !g_epsp_n || !g_kappa_n || !cg || !pcg ||
-        nfields < 1 || maxit < 1)
+    if (!phase || !state_n || !state_np1 || !dell2 || !g_epsp_n || !g_kappa_n || !g_hist_n ||
+        !cg || !pcg || nfields < 1 || maxit < 1)
       throw Fail{FFTG_E_INVALID, "fftg_increment_adjoint: null pointer, no field or maxit < 1"};
     for (int p = 0; p < nphase; ++p)
-      if (tab[p].model != FFTG_ELASTIC && tab[p].model != FFTG_J2_DAMAGE)
+      if (tab[p].model == FFTG_GTN)
         throw Fail{FFTG_E_UNSUPPORTED,
-                   "fftg_increment_adjoint: J2 damage and elastic phases only"};
+                   "fftg_increment_adjoint: no adjoint of the Gurson return and porosity"};
     auto t0 = std::chrono::steady_clock::now();
     const int c = H->c, J = nfields;
     const long long N = H->g.N;
     const MatTable t = make_table(tab, nphase, J);
     const double* epsp_n = state_n + (long long)c * N;
+    const double* hist_n = state_n + (long long)(c + 7) * N;
     const double* eps = state_np1;
-    // strain cotangent of the committed plastic state
+    const double* abar = state_np1 + (long long)(c + 7 + J) * N;
+    if (H->hadjJ < J) {
+      dfree((void*&)H->hadj);
+      H->hadj = (double*)dalloc(sizeof(double) * (size_t)(c + J) * N);
+      H->hadjJ = J;
+    }
+    // strain cotangent of the committed plastic state; abar cotangent of the
+    // committed damage history where abar is its max
     const double* g_eps = nullptr;
     if (g_epsp || g_kappa) {
-      if (!H->hadj) H->hadj = (double*)dalloc(sizeof(double) * (size_t)c * N);
       fftg::launch_hist_out_cot(t, N, c, phase, eps, epsp_n, g_epsp, g_kappa, H->hadj, H->st);
       g_eps = H->hadj;
     }
+    const double* g_abar = nullptr;
+    if (g_hist) {
+      double* ga = H->hadj + (long long)c * N;
+      fftg::launch_hist_split((long long)J * N, abar, hist_n, g_hist, ga, H->st);
+      g_abar = ga;
+    }
     const AdjOut r = stag_adjoint_core(H, phase, t, J, state_n, state_np1, target, g_eps, g_sig,
-                                       nullptr, nullptr, dell2, cg, pcg, tol, maxit, true);
+                                       g_abar, nullptr, dell2, cg, pcg, tol, maxit, true);
     fftg::launch_hist_in_cot(t, N, c, J, phase, eps, epsp_n, H->Dj, r.mu, g_sig, r.lam, g_epsp,
                              g_kappa, g_epsp_n, g_kappa_n, H->st);
+    fftg::launch_hist_damage_cot(t, N, J, phase, abar, hist_n, r.zeta, g_hist, g_hist_n, H->st);
     check_launch();
     sync(H);
     if (stats) {

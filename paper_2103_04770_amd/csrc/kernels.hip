@@ -1700,6 +1700,47 @@ FFTG_KERNEL void k_damage_adj(MatTable tab, long long N, int J,
   }
 }
 
+// Damage-history cotangents of an increment (hist_{n+1} = max(hist_n, abar),
+// read back by the cracking law through the same max).  With the history the
+// max (hist_n > abar, the damage law's tie convention):
+//   g_abar  = g_hist where abar is the max, 0 elsewhere            (k_hist_split)
+//   g_hist_n = g_hist where hist_n is the max, plus zeta / (dR - dC) on a
+//              cracking voxel of the field whose history drives D inside the
+//              slope band                                           (k_hist_damage_cot)
+// zeta: the total damage cotangent [J][N].  g_hist may be null (zero).
+FFTG_KERNEL void k_hist_split(long long n, const double* __restrict__ abar,
+                              const double* __restrict__ hist_n,
+                              const double* __restrict__ g_hist, double* __restrict__ g_abar) {
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * FFT_THREADS)
+    g_abar[i] = hist_n[i] > abar[i] ? 0.0 : g_hist[i];
+}
+
+FFTG_KERNEL void k_hist_damage_cot(MatTable tab, long long N, int J,
+                                   const unsigned char* __restrict__ phase,
+                                   const double* __restrict__ abar,
+                                   const double* __restrict__ hist_n,
+                                   const double* __restrict__ zeta,
+                                   const double* __restrict__ g_hist,
+                                   double* __restrict__ g_hist_n) {
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS) {
+    const int ph = phase[v];
+    const Mat m = tab.m[ph < tab.nphase ? ph : 0];
+    for (int j = 0; j < J; ++j) {
+      const long long i = (long long)j * N + v;
+      const double h = hist_n[i];
+      const bool by_hist = h > abar[i];
+      double gv = by_hist && g_hist ? g_hist[i] : 0.0;
+      if (m.model == 2 && m.dfield == j && by_hist) {
+        const double d = (h - m.dC) / (m.dR - m.dC);
+        if (d > 0.0 && d < m.dmax) gv += zeta[i] / (m.dR - m.dC);
+      }
+      g_hist_n[i] = gv;
+    }
+  }
+}
+
 // Per-phase sums of a real field [N] -> partials [nphase][gridDim].
 FFTG_KERNEL void k_phase_sums(long long N, int nphase, const unsigned char* __restrict__ phase,
                               const double* __restrict__ f, double* __restrict__ partials) {
@@ -2316,6 +2357,19 @@ void launch_hist_in_cot(const MatTable& tab, long long N, int c, int J, const un
   hipLaunchKernelGGL(k_hist_in_cot, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, c, J,
                      phase, eps, state_n, D, mu, g_sig, lam, g_epsp, g_kappa, g_epsp_n,
                      g_kappa_n);
+}
+
+void launch_hist_split(long long n, const double* abar, const double* hist_n,
+                       const double* g_hist, double* g_abar, hipStream_t st) {
+  hipLaunchKernelGGL(k_hist_split, dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, abar, hist_n,
+                     g_hist, g_abar);
+}
+
+void launch_hist_damage_cot(const MatTable& tab, long long N, int J, const unsigned char* phase,
+                            const double* abar, const double* hist_n, const double* zeta,
+                            const double* g_hist, double* g_hist_n, hipStream_t st) {
+  hipLaunchKernelGGL(k_hist_damage_cot, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, J,
+                     phase, abar, hist_n, zeta, g_hist, g_hist_n);
 }
 
 void launch_stream_copy(const void* src, void* dst, long long n16, int blocks, hipStream_t st) {

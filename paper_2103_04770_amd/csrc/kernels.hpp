@@ -170,6 +170,11 @@ void launch_hist_in_cot(const MatTable& tab, long long N, int c, int J, const un
                         const double* mu, const double* g_sig, const double* lam,
                         const double* g_epsp, const double* g_kappa, double* g_epsp_n,
                         double* g_kappa_n, hipStream_t st);
+void launch_hist_split(long long n, const double* abar, const double* hist_n,
+                       const double* g_hist, double* g_abar, hipStream_t st);
+void launch_hist_damage_cot(const MatTable& tab, long long N, int J, const unsigned char* phase,
+                            const double* abar, const double* hist_n, const double* zeta,
+                            const double* g_hist, double* g_hist_n, hipStream_t st);
 int launch_diff2(long long n, const double* a, const double* b, double* partials, hipStream_t st);
 void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
                   hipStream_t st);

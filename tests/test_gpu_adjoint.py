@@ -325,18 +325,23 @@ def test_increment_adjoint_matches_oracle(shape):
     g[0] = 1.0 / phase.size
     gp = rng.standard_normal((6,) + shape) / phase.size
     gk = rng.standard_normal(shape) / phase.size
+    gh = rng.standard_normal((1,) + shape) / phase.size
     ref = adjoint.increment_adjoint(phase, table, 1, st_n, st, tgt, g_sig=g, g_epsp=gp, g_kappa=gk,
-                                    cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12, maxit=300)
+                                    g_hist=gh, cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12, maxit=300)
     s = solver(shape)
     dl = torch.empty((1,) + shape, dtype=torch.float64, device="cuda")
     gpn = torch.empty((6,) + shape, dtype=torch.float64, device="cuda")
     gkn = torch.empty(shape, dtype=torch.float64, device="cuda")
+    ghn = torch.empty((1,) + shape, dtype=torch.float64, device="cuda")
     d = s.fftg_increment_adjoint(dev(phase, torch.uint8), table, 1, dev(_pack(st_n)),
-                                 dev(_pack(st)), tgt, dl, gpn, gkn, g_sig=dev(g), g_epsp=dev(gp),
-                                 g_kappa=dev(gk), cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12,
-                                 maxit=300)
+                                 dev(_pack(st)), tgt, dl, gpn, gkn, ghn, g_sig=dev(g),
+                                 g_epsp=dev(gp), g_kappa=dev(gk), g_hist=dev(gh), cg_tol=1e-13,
+                                 pcg_tol=1e-13, tol=1e-12, maxit=300)
     say("  gpu passes", d["stagger_iters"], "oracle passes", ref["iters"])
     assert d["converged"]
+    # no cracking phase: the committed history is read by nothing, and where
+    # hist_n stays the max its cotangent passes through bit for bit
+    assert np.array_equal(ghn.cpu().numpy(), ref["g_hist_n"])
     for name, got, want in (("dell2", dl, ref["dell2"]), ("g_epsp_n", gpn, ref["g_epsp_n"]),
                             ("g_kappa_n", gkn, ref["g_kappa_n"])):
         got = got.cpu().numpy()
@@ -402,13 +407,111 @@ def test_increment_adjoint_rejects_uncovered_phases():
     from paper_2103_04770_amd.binding import FFTGError
     shape = (8, 8, 8)
     s = solver(shape)
-    table = [ms.matrix_j2_damage(ell=[2.0, 0.04], dfield=0),
-             ms.particle_cracking(ell=[0.04, 1.0], dfield=1)]
+    table = [ms.matrix_gtn(ell=[2.0, 2.0]), ms.particle_elastic(ell=[0.1, 0.1])]
     z = dev(np.zeros((6 + 7 + 4,) + shape))
     f = lambda *k: torch.empty(k + shape, dtype=torch.float64, device="cuda")  # noqa: E731
     with pytest.raises(FFTGError, match="UNSUPPORTED"):
         s.fftg_increment_adjoint(dev(np.zeros(shape), torch.uint8), table, 2, z, z,
-                                 ms.uniaxial_mixed(3, 1e-3), f(2), f(6), f())
+                                 ms.uniaxial_mixed(3, 1e-3), f(2), f(6), f(), f(2))
+
+
+def _two_field_case(shape):
+    rng = np.random.default_rng(23)
+    phase = (rng.uniform(size=shape) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0, 0.04], dfield=0, dC=0.0005, dR=0.02),
+             ms.particle_cracking(ell=[0.04, 1.0], dfield=1, k0=5e-4, kf=5e-3)]
+    return phase, table
+
+
+@pytest.mark.parametrize("shape", [(12, 16), (6, 8, 12)])
+def test_increment_adjoint_damage_history_matches_oracle(shape):
+    """Two fields (J2 damage matrix, particle cracking) with the history
+    raised above abar on some cracking voxels, so that it drives their damage,
+    and random incoming history cotangents: dJ/dell2 and the cotangents of
+    the plastic state and damage history against the oracle."""
+    from oracle import staggered
+    from tests.test_oracle_adjoint import STAG_TOLS
+    say("increment adjoint, damage history", shape)
+    phase, table = _two_field_case(shape)
+    nd = len(shape)
+    c = 6 if nd == 3 else 3
+    st_n = staggered.staggered_step(phase, table, 2, staggered.initial_state(shape, nd, 2),
+                                    ms.uniaxial_mixed(nd, 2e-3), **STAG_TOLS)[0]
+    rng = np.random.default_rng(5)
+    raise_ = (phase == 1) & (rng.uniform(size=shape) < 0.5)
+    st_n = dict(st_n, hist=st_n["hist"].copy())
+    st_n["hist"][1][raise_] = np.maximum(st_n["hist"][1][raise_], st_n["abar"][1][raise_]) + \
+        rng.uniform(1e-3, 2e-3, size=int(raise_.sum()))
+    tgt = ms.uniaxial_mixed(nd, 3e-3)
+    st, _, _, stats = staggered.staggered_step(phase, table, 2, st_n, tgt, **STAG_TOLS)
+    assert stats["converged"]
+    g = np.zeros((c,) + shape)
+    g[0] = 1.0 / phase.size
+    N = phase.size
+    gp = rng.standard_normal((6,) + shape) / N
+    gk = rng.standard_normal(shape) / N
+    gh = rng.standard_normal((2,) + shape) / N
+    kw = dict(cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12, maxit=300)
+    ref = adjoint.increment_adjoint(phase, table, 2, st_n, st, tgt, g_sig=g, g_epsp=gp, g_kappa=gk,
+                                    g_hist=gh, **kw)
+    s = solver(shape)
+    f = lambda *k: torch.empty(k + shape, dtype=torch.float64, device="cuda")  # noqa: E731
+    dl, gpn, gkn, ghn = f(2), f(6), f(), f(2)
+    d = s.fftg_increment_adjoint(dev(phase, torch.uint8), table, 2, dev(_pack(st_n)),
+                                 dev(_pack(st)), tgt, dl, gpn, gkn, ghn, g_sig=dev(g),
+                                 g_epsp=dev(gp), g_kappa=dev(gk), g_hist=dev(gh), **kw)
+    say("  gpu passes", d["stagger_iters"], "oracle passes", ref["iters"])
+    assert d["converged"]
+    held = (st_n["hist"][1] > st["abar"][1]) & (phase == 1)
+    assert held.sum() >= 5
+    for name, got, want in (("dell2", dl, ref["dell2"]), ("g_epsp_n", gpn, ref["g_epsp_n"]),
+                            ("g_kappa_n", gkn, ref["g_kappa_n"]), ("g_hist_n", ghn, ref["g_hist_n"])):
+        got = got.cpu().numpy()
+        for j in range(want.shape[0] if name in ("dell2", "g_hist_n") else 1):
+            w = want[j] if name in ("dell2", "g_hist_n") else want
+            gg = got[j] if name in ("dell2", "g_hist_n") else got
+            err = np.abs(gg - w).max() / max(np.abs(w).max(), 1e-300)
+            say("  ", name, j, "rel err %.2e" % err)
+            assert err <= 1e-8, (name, j)
+
+
+def test_path_gradient_with_cracking_and_unloading_matches_oracle():
+    """A two-field path that loads and partly unloads (E11 2e-3, 3e-3,
+    2.5e-3; the cracking damage is held at its history on unloading), run on
+    the GPU: the path gradient of <sigma_11> for both fields against the
+    oracle's on its own path."""
+    from oracle import staggered
+    from paper_2103_04770_amd import autograd as ag
+    from tests.test_oracle_adjoint import STAG_TOLS
+    shape = (12, 16)
+    say("path gradient, cracking and unloading", shape)
+    phase, table = _two_field_case(shape)
+    targets = [ms.uniaxial_mixed(2, e) for e in (2e-3, 3e-3, 2.5e-3)]
+    st = staggered.initial_state(shape, 2, 2)
+    ostates = [st]
+    for tgt in targets:
+        st = staggered.staggered_step(phase, table, 2, st, tgt, **STAG_TOLS)[0]
+        ostates.append(st)
+    g = np.zeros((3,) + shape)
+    g[0] = 1.0 / phase.size
+    kw = dict(cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12, maxit=300)
+    ref = adjoint.path_gradient(phase, table, 2, ostates, targets, g, **kw)
+    s = solver(shape)
+    ph = dev(phase, torch.uint8)
+    opts = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, newton_maxit=60,
+                stagger_tol=1e-13, max_stagger=300)
+    state = dev(np.zeros((3 + 7 + 4,) + shape))
+    sig = torch.empty((3,) + shape, dtype=torch.float64, device="cuda")
+    states = [state.clone()]
+    for tgt in targets:
+        assert s.staggered_step(ph, table, 2, state, tgt, sig, **opts)["converged"]
+        states.append(state.clone())
+    dl, log = ag.path_gradient(s, ph, table, 2, states, targets, dev(g), **kw)
+    got = dl.cpu().numpy()
+    for j in range(2):
+        err = np.abs(got[j] - ref[j]).max() / np.abs(ref[j]).max()
+        say("  field", j, "passes", [x["stagger_iters"] for x in log], "rel err %.2e" % err)
+        assert err <= 1e-7
 
 
 def test_path_gradient_fp32_refined_matches_oracle():
