@@ -363,6 +363,51 @@ def run_c5(forms=("fp64", "fp32")):
     return dict(workload="spheres30_128", path="20 x dE11 = 2e-3 to 0.04", **out)
 
 
+def run_two_field_path_gradient(n_inc=4):
+    """The benchmark RVE itself (spheres_two_fields_128: J2 damage matrix on
+    field 0, particle cracking on field 1), FP64: the first n_inc increments
+    of the benchmark path (E11 = 1e-3 ... n_inc 1e-3), then d<sigma_11>/d ell
+    of both fields through the whole path (plastic state and damage history
+    of every increment chained backwards)."""
+    import torch
+    from paper_2103_04770_amd import Solver, autograd as ag, microstructure as ms
+    w = ms.workload("spheres_two_fields_128")
+    S, J = w["shape"], w["nfields"]
+    s = Solver(tuple(reversed(S)))
+    ph = torch.from_numpy(w["phase"]).cuda()
+    state = torch.zeros((6 + 7 + 2 * J,) + S, dtype=torch.float64, device="cuda")
+    sig = torch.empty((6,) + S, dtype=torch.float64, device="cuda")
+    tols = dict(TOLS, max_stagger=100)
+    states, targets, conv = [state.clone()], [], True
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_inc):
+        d = s.staggered_step(ph, w["table"], J, state, step_load(k), sig, **tols)
+        conv = conv and bool(d["converged"])
+        states.append(state.clone())
+        targets.append(step_load(k))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
+    g[0] = 1.0 / float(np.prod(S))
+    dl, alog = ag.path_gradient(s, ph, w["table"], J, states, targets, g, cg_tol=1e-8,
+                                pcg_tol=1e-8, tol=1e-6, maxit=200)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    grads = []
+    for j in range(J):
+        sums = s.fftg_phase_sums(ph, len(w["table"]), dl[j].contiguous())
+        grads.append([2.0 * float(t["ell"][j]) * float(v) for t, v in zip(w["table"], sums)])
+    s.close()
+    log("[c5] benchmark RVE, two fields: %d increments in %.1f s, path gradient %.1f s, "
+        "d<s11>/d ell by field %s" % (n_inc, t1 - t0, t2 - t1, grads))
+    return dict(workload="spheres_two_fields_128", increments=n_inc,
+                e11_end=1e-3 * n_inc, all_converged=conv, path_s=round(t1 - t0, 3),
+                path_gradient_s=round(t2 - t1, 3),
+                adjoint_passes=[x["stagger_iters"] for x in alog][::-1],
+                dJ_dell_by_field=grads)
+
+
 def run_adjoint_two_fields():
     """The benchmark RVE itself (spheres_two_fields_128: J2 damage matrix on
     field 0, particle cracking on field 1): the converged increment
@@ -706,6 +751,7 @@ def main():
         out["gtn"] = run_gtn()
     if args.c5:
         out["c5_path_gradient"] = run_c5()
+        out["two_field_path_gradient"] = run_two_field_path_gradient()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_iters)
