@@ -59,10 +59,12 @@ def kernel_bytes(name, n, c, nd, J, fp32):
         "galerkin_outer_dot_fwd": 3 * c * Ns * zc,
         "galerkin_resid": 3 * c * Ns * zc,
         "helmholtz_x_fused": 2 * nd * Ns * zc + N * zr,
-        "helmholtz_y_inv": 2 * nd * Ns * zc,
-        "helmholtz_y_fwd": 2 * nd * Ns * zc,
-        "helmholtz_outer_dir_inv": (5 + nd) * Ns * zc,
-        "helmholtz_outer_div_fwd": (nd + 2) * Ns * zc,
+        # 3D: the outer passes transform two fields; the y passes map two
+        # fields to the three gradient components and back
+        "helmholtz_y_inv": (2 + nd) * Ns * zc,
+        "helmholtz_y_fwd": (nd + 2) * Ns * zc,
+        "helmholtz_outer_dir_inv": (5 + 2) * Ns * zc,
+        "helmholtz_outer_div_fwd": (2 + 2) * Ns * zc,
         "helmholtz_resid": 3 * Ns * zc,
         "constitutive": N * (1 + 8 * (2 * c + 14 + 2 * J) + 8 * zr),
     }

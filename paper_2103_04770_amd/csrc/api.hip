@@ -378,6 +378,22 @@ void inner_fwd(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int k
 }
 int outer_axis(fftg_handle* H) { return H->g.ndim == 3 ? 2 : 1; }
 
+// y passes of the Helmholtz operator on its gradient buffer: the split form
+// (two fields to three and back, launch_h_y_split) where the outer passes
+// use it, the plain per-component passes otherwise.
+template <typename T>
+void helm_inner(fftg_handle* H, bool fwd, cpx<T>* w, const KrylovCtl* ctl, int kid) {
+  const Geo& g = H->g;
+  if (fftg::helm_split(g)) {
+    KT t(H, kid);
+    fftg::launch_h_y_split<T>(H->plan[1], TW<T>(H, 1), g, SY<T>(H), w, fwd, ctl, H->st);
+  } else if (fwd) {
+    inner_fwd<T>(H, g.ndim, w, ctl, kid);
+  } else {
+    inner_inv<T>(H, g.ndim, w, ctl, kid);
+  }
+}
+
 MatTable make_table(const fftg_phase* tab, int nphase, int J) {
   MatTable t{};
   t.nphase = nphase;
@@ -588,20 +604,19 @@ void helm_iteration(fftg_handle* H, const T* ell2) {
   const Geo& g = H->g;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
-  const int nd = g.ndim;
   const T scl = T(1.0 / (double)g.N);
   {
     KT t(H, K_HLM_OI);
     fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true, C<T>(H->hr),
                               C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
   }
-  inner_inv<T>(H, nd, C<T>(H->hw), H->ctl, K_HLM_YI);
+  helm_inner<T>(H, false, C<T>(H->hw), H->ctl, K_HLM_YI);
   {
     KT t(H, K_HLM_X);
     fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl,
                                     H->ctl, H->st);
   }
-  inner_fwd<T>(H, nd, C<T>(H->hw), H->ctl, K_HLM_YF);
+  helm_inner<T>(H, true, C<T>(H->hw), H->ctl, K_HLM_YF);
   int nb;
   {
     KT t(H, K_HLM_OF);
@@ -647,7 +662,6 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
   const Geo& g = H->g;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
-  const int nd = g.ndim;
   const T scl = T(1.0 / (double)g.N);
   // b = F(alpha)
   const T* ain;
@@ -692,10 +706,10 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
   // r = b - L x0
   fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), false, C<T>(H->hr),
                             C<T>(H->hx), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
-  inner_inv<T>(H, nd, C<T>(H->hw), nullptr, K_HLM_YI);
+  helm_inner<T>(H, false, C<T>(H->hw), nullptr, K_HLM_YI);
   fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, nullptr,
                                   H->st);
-  inner_fwd<T>(H, nd, C<T>(H->hw), nullptr, K_HLM_YF);
+  helm_inner<T>(H, true, C<T>(H->hw), nullptr, K_HLM_YF);
   fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hx), C<T>(H->hw),
                             C<T>(H->hAp), nullptr, H->ctl, H->st);
   const int nr0 = fftg::launch_h_resid<T>(g, SY<T>(H), true, C<T>(H->hr), C<T>(H->hb),
@@ -1728,10 +1742,10 @@ fftg_status fftg_apply_helmholtz(fftg_handle* H, const double* ell2, const doubl
     fftg::launch_h_dir_inv<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64, false,
                                    C<double>(H->hr), C<double>(H->hx), C<double>(H->hx),
                                    C<double>(H->hw), H->ctl, H->st);
-    inner_inv<double>(H, g.ndim, C<double>(H->hw), nullptr, K_HLM_YI);
+    helm_inner<double>(H, false, C<double>(H->hw), nullptr, K_HLM_YI);
     fftg::launch_x_fused_helm<double, double>(H->plan[0], TW<double>(H, 0), g, C<double>(H->hw),
                                               ell2, 1.0 / (double)g.N, nullptr, H->st);
-    inner_fwd<double>(H, g.ndim, C<double>(H->hw), nullptr, K_HLM_YF);
+    helm_inner<double>(H, true, C<double>(H->hw), nullptr, K_HLM_YF);
     fftg::launch_h_div_fwd<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64,
                                    C<double>(H->hx), C<double>(H->hw), C<double>(H->hAp), nullptr,
                                    H->ctl, H->st);

@@ -482,7 +482,13 @@ FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
 //   update: p <- M r + beta p ; x <- x + alpha p_old
 //   w_j <- inverse transform of (i q~_j p), j < ND.
 // The fixed-length path uses a 48 KB tile so that tile rows stay >= 128 B.
-template <typename T, int NF, int ND>
+//
+// SPLIT (3D): the modified frequencies factor per axis, q_x = f_x c_y c_z,
+// q_y = c_x f_y c_z, q_z = c_x c_y f_z, and on a z line only the z factors
+// vary.  So the pass transforms two fields instead of three,
+//   w_0 = Z^-1(i c_z p),  w_1 = Z^-1(i c_x c_y f_z p),
+// and the y pass (k_h_y_split) forms the three gradient components from them.
+template <typename T, int NF, int ND, bool SPLIT>
 FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                              int update, const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
                              cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
@@ -490,11 +496,12 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
                              const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? ND * fs_tile_wide<T>(NF, ND) * NF : LDS_ELEMS];
+  constexpr int NC = SPLIT ? 2 : ND;  // fields transformed
+  __shared__ cpx<T> buf[FIX ? NC * fs_tile_wide<T>(NF, NC) * NF : LDS_ELEMS];
   const int n = FIX ? NF : plan.n;
   constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
-  const int TL = FIX ? fs_tile_wide<T>(NF, ND) : TL_rt;
-  const int ld = ND * TL;
+  const int TL = FIX ? fs_tile_wide<T>(NF, NC) : TL_rt;
+  const int ld = NC * TL;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
@@ -521,12 +528,23 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
       }
     }
     const cpx<T> ip = mul_i(pn);
+    if constexpr (SPLIT) {
+      T f0 = T(0), f1 = T(0);
+      if (lb >= 0) {
+        const T* b = sym.base;
+        f0 = b[sym.cs[2] + t];
+        f1 = b[sym.cs[0] + lkx] * b[sym.cs[1] + lky] * b[sym.gq[2] + t];
+      }
+      buf[t * ld + l] = scale(ip, f0);
+      buf[t * ld + TL + l] = scale(ip, f1);
+    } else {
 #pragma unroll
-    for (int j = 0; j < ND; ++j) buf[t * ld + j * TL + l] = scale(ip, q[j]);
+      for (int j = 0; j < ND; ++j) buf[t * ld + j * TL + l] = scale(ip, q[j]);
+    }
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, true, NF, ND * fs_tile_wide<T>(NF, ND), ND * fs_tile_wide<T>(NF, ND),
+    lds_fft_c<T, false, true, NF, NC * fs_tile_wide<T>(NF, NC), NC * fs_tile_wide<T>(NF, NC),
               NT>(buf, tw);
   else
     lds_fft<T, false, true>(buf, plan, ld, ld, tw);
@@ -534,13 +552,78 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
     for (int t = t0; t < n; t += dt) {
       const long long gi = lb + t * es;
 #pragma unroll
-      for (int j = 0; j < ND; ++j) w[j * g.Ns + gi] = buf[t * ld + j * TL + l];
+      for (int j = 0; j < NC; ++j) w[j * g.Ns + gi] = buf[t * ld + j * TL + l];
     }
+}
+
+// y pass of the split Helmholtz operator (3D), lines (z, kx) of the
+// half spectrum.  Inverse: from w_0, w_1 of k_h_dir_inv<SPLIT> forms and
+// transforms the three gradient components
+//   Y^-1(f_x c_y w_0), Y^-1(c_x f_y w_0), Y^-1(w_1)  -> w_0, w_1, w_2.
+// Forward: transforms w_0, w_1, w_2 and folds the x and y components,
+//   u = f_x c_y Y(w_0) + c_x f_y Y(w_1),  v = c_x c_y Y(w_2)  -> w_0, w_1,
+// which the outer forward pass (k_h_div_fwd<SPLIT>) finishes with c_z, f_z.
+template <typename T, bool FWD, int NF>
+FFTG_KERNEL_WIDE void k_h_y_split(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
+                                  cpx<T>* __restrict__ w, long long nlines, int TL_rt,
+                                  const KrylovCtl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  constexpr bool FIX = NF > 0;
+  __shared__ cpx<T> buf[FIX ? 3 * fs_tile_wide<T>(NF, 3) * NF : LDS_ELEMS];
+  const int n = FIX ? NF : plan.n;
+  constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
+  const int TL = FIX ? fs_tile_wide<T>(NF, 3) : TL_rt;
+  const int ld = 3 * TL;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
+  const long long L = xcd_tile(blockIdx.x, gridDim.x) * TL + l;
+  const long long inner = g.n1h, es = g.n1h;
+  const long long lb = L < nlines ? line_base(L, inner, (long long)g.n2 * g.n1h) : -1;
+  const int kx = (int)(L % inner);
+  const T* b = sym.base;
+  const T fx = lb >= 0 ? b[sym.gq[0] + kx] : T(0), cx = lb >= 0 ? b[sym.cs[0] + kx] : T(0);
+  for (int t = t0; t < n; t += dt) {
+    if (lb < 0) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
+      continue;
+    }
+    const long long gi = lb + t * es;
+    if constexpr (FWD) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) buf[t * ld + j * TL + l] = w[j * g.Ns + gi];
+    } else {
+      const cpx<T> a = w[gi], bb = w[g.Ns + gi];
+      const T fy = b[sym.gq[1] + t], cy = b[sym.cs[1] + t];
+      buf[t * ld + l] = scale(a, fx * cy);
+      buf[t * ld + TL + l] = scale(a, cx * fy);
+      buf[t * ld + 2 * TL + l] = bb;
+    }
+  }
+  __syncthreads();
+  if constexpr (FIX)
+    lds_fft_c<T, FWD, true, NF, 3 * fs_tile_wide<T>(NF, 3), 3 * fs_tile_wide<T>(NF, 3), NT>(buf,
+                                                                                            tw);
+  else
+    lds_fft<T, FWD, true>(buf, plan, ld, ld, tw);
+  if (lb < 0) return;
+  for (int t = t0; t < n; t += dt) {
+    const long long gi = lb + t * es;
+    if constexpr (FWD) {
+      const T fy = b[sym.gq[1] + t], cy = b[sym.cs[1] + t];
+      w[gi] = scale(buf[t * ld + l], fx * cy) + scale(buf[t * ld + TL + l], cx * fy);
+      w[g.Ns + gi] = scale(buf[t * ld + 2 * TL + l], cx * cy);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) w[j * g.Ns + gi] = buf[t * ld + j * TL + l];
+    }
+  }
 }
 
 // Outer-axis forward pass of the Helmholtz operator:
 //   Ap = p - i sum_j q~_j FFT(w_j) ; partial sums of weighted p.Ap.
-template <typename T, int NF, int ND>
+// SPLIT (3D): w_0, w_1 are the u, v of k_h_y_split, and
+// sum_j q_j FFT(w_j) = c_z Z(u) + f_z Z(v).
+template <typename T, int NF, int ND, bool SPLIT>
 FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                              const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
                              cpx<T>* __restrict__ Ap, long long nlines, long long inner,
@@ -548,13 +631,14 @@ FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo 
                              double* __restrict__ partials, const KrylovCtl* __restrict__ ctl) {
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
-  __shared__ cpx<T> buf[FIX ? ND * fs_tile_wide<T>(NF, ND) * NF : LDS_ELEMS];
+  constexpr int NC = SPLIT ? 2 : ND;  // fields transformed
+  __shared__ cpx<T> buf[FIX ? NC * fs_tile_wide<T>(NF, NC) * NF : LDS_ELEMS];
   double* red = reinterpret_cast<double*>(buf);  // reused after the transform (block_sum syncs)
   const int n = FIX ? NF : plan.n;
   constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
   static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
-  const int TL = FIX ? fs_tile_wide<T>(NF, ND) : TL_rt;
-  const int ld = ND * TL;
+  const int TL = FIX ? fs_tile_wide<T>(NF, NC) : TL_rt;
+  const int ld = NC * TL;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = (long long)blockIdx.x * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
@@ -564,15 +648,15 @@ FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo 
     if (lb >= 0) {
       const long long gi = lb + t * es;
 #pragma unroll
-      for (int j = 0; j < ND; ++j) buf[t * ld + j * TL + l] = w[j * g.Ns + gi];
+      for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = w[j * g.Ns + gi];
     } else {
 #pragma unroll
-      for (int j = 0; j < ND; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
+      for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
     }
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, true, NF, ND * fs_tile_wide<T>(NF, ND), ND * fs_tile_wide<T>(NF, ND),
+    lds_fft_c<T, true, true, NF, NC * fs_tile_wide<T>(NF, NC), NC * fs_tile_wide<T>(NF, NC),
               NT>(buf, tw);
   else
     lds_fft<T, true, true>(buf, plan, ld, ld, tw);
@@ -581,12 +665,18 @@ FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo 
     if (lb >= 0) {
       const long long gi = lb + t * es;
       const int kx = lkx, ky = zouter ? lky : t, kz = zouter ? t : 0;
-      T q[3];
-      qvec(sym, true, kx, ky, kz, q);
       const cpx<T> pv = pp[gi];
       cpx<T> div = mk(T(0), T(0));
+      if constexpr (SPLIT) {
+        const T* b = sym.base;
+        div = scale(buf[t * ld + l], b[sym.cs[2] + kz]) +
+              scale(buf[t * ld + TL + l], b[sym.gq[2] + kz]);
+      } else {
+        T q[3];
+        qvec(sym, true, kx, ky, kz, q);
 #pragma unroll
-      for (int j = 0; j < ND; ++j) div = div + scale(buf[t * ld + j * TL + l], q[j]);
+        for (int j = 0; j < ND; ++j) div = div + scale(buf[t * ld + j * TL + l], q[j]);
+      }
       const cpx<T> a = pv + mul_mi(div);
       Ap[gi] = a;
       acc += hweight(kx, g.n1h) * ((double)pv.x * (double)a.x + (double)pv.y * (double)a.y);
@@ -2199,19 +2289,43 @@ int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
   outer_lines(g, 1, zouter, nl, inner, os, es);
   long long nb = 0;
   FFTG_DISPATCH_N(p.n, {
-    if (g.ndim == 3) {
+    if (helm_split(g)) {
+      const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
+      nb = (nl + TL - 1) / TL;
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3, true>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
+    } else if (g.ndim == 3) {
       const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
       nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3, false>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
                          tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
     } else {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
       nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 2>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 2, false>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
                          tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
     }
   })
   return (int)nb;
+}
+
+template <typename T>
+void launch_h_y_split(const Plan& p, const cpx<T>* tw, const Geo& g, const Sym<T>& sym,
+                      cpx<T>* w, bool fwd, const KrylovCtl* ctl, hipStream_t st) {
+  require(helm_split(g), "split Helmholtz y pass: 3D grids with n2 > 1 only");
+  const long long nl = (long long)g.n3 * g.n1h;
+  FFTG_DISPATCH_N(p.n, {
+    const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
+    const long long nb = (nl + TL - 1) / TL;
+    if (fwd)
+      hipLaunchKernelGGL((k_h_y_split<T, true, NF>), dim3((unsigned)nb),
+                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, w, nl, TL,
+                         ctl);
+    else
+      hipLaunchKernelGGL((k_h_y_split<T, false, NF>), dim3((unsigned)nb),
+                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, w, nl, TL,
+                         ctl);
+  })
 }
 
 template <typename T>
@@ -2222,15 +2336,20 @@ int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
   outer_lines(g, 1, zouter, nl, inner, os, es);
   long long nb = 0;
   FFTG_DISPATCH_N(p.n, {
-    if (g.ndim == 3) {
+    if (helm_split(g)) {
+      const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
+      nb = (nl + TL - 1) / TL;
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3, true>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+                         tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
+    } else if (g.ndim == 3) {
       const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
       nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3, false>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
                          tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
     } else {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
       nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 2>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 2, false>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
                          tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
     }
   })
@@ -2465,6 +2584,8 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st) {
   template int launch_h_div_fwd<T>(const Plan&, const cpx<T>*, const Geo&, bool, const Sym<T>&,  \
                                    const cpx<T>*, cpx<T>*, cpx<T>*, double*, const KrylovCtl*,   \
                                    hipStream_t);                                                 \
+  template void launch_h_y_split<T>(const Plan&, const cpx<T>*, const Geo&, const Sym<T>&,      \
+                                    cpx<T>*, bool, const KrylovCtl*, hipStream_t);               \
   template int launch_h_resid<T>(const Geo&, const Sym<T>&, bool, cpx<T>*, const cpx<T>*,       \
                                   const cpx<T>*, double*, const KrylovCtl*, hipStream_t);        \
   template void launch_xfinal<T>(cpx<T>*, const cpx<T>*, long long, const KrylovCtl*,            \

@@ -102,7 +102,13 @@ template <typename T>
 void launch_project(const Geo& g, int c, const Sym<T>& sym, const unsigned char* mask6,
                     cpx<T>* data, hipStream_t st);
 
-// Helmholtz PCG passes
+// Helmholtz PCG passes.  On 3D grids with n2 > 1 (helm_split) the outer
+// passes transform two fields instead of three and launch_h_y_split, in
+// place of the plain y passes, forms and folds the gradient components.
+inline bool helm_split(const Geo& g) { return g.ndim == 3 && g.n2 > 1; }
+template <typename T>
+void launch_h_y_split(const Plan& p, const cpx<T>* tw, const Geo& g, const Sym<T>& sym,
+                      cpx<T>* w, bool fwd, const KrylovCtl* ctl, hipStream_t st);
 template <typename T>
 int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, bool update, const cpx<T>* r, cpx<T>* pp, cpx<T>* x,

@@ -40,10 +40,15 @@ CLASSES = {
 def classify(name):
     """'void fftg::k_gal_dir_inv<double, 128>' -> ('fp64', 'galerkin_outer_dir_inv')."""
     base = name.split("<")[0].split("::")[-1]
-    if base not in CLASSES or "<" not in name:
+    if "<" not in name:
         return None
-    t = name.split("<", 1)[1].split(",")[0].split(">")[0].strip()
-    return ({"double": "fp64", "float": "fp32"}.get(t), CLASSES[base])
+    args = [a.strip() for a in name.split("<", 1)[1].rsplit(">", 1)[0].split(",")]
+    prec = {"double": "fp64", "float": "fp32"}.get(args[0])
+    if base == "k_h_y_split" and len(args) > 1:
+        return (prec, "helmholtz_y_fwd" if args[1] == "true" else "helmholtz_y_inv")
+    if base not in CLASSES:
+        return None
+    return (prec, CLASSES[base])
 
 
 def source_sha256():

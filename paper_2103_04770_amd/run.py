@@ -85,9 +85,13 @@ def bytes_per_iteration(shape, prec):
     # x fused (2c z + tangent), y inverse and forward (2c each), outer
     # direction/inverse (6c), outer forward/dot (3c), residual (3c)
     gal = (14 + (4 if inner else 0)) * c * Ns * z + 8 * N * r
-    # x fused (2d z + ell2), y inverse and forward (2d each), outer
-    # direction/inverse (5 + d), outer divergence/dot (d + 2), residual (3)
-    helm = (2 * ndim + (4 * ndim if inner else 0) + (5 + ndim) + (ndim + 2) + 3) * Ns * z + N * r
+    # x fused (2d z + ell2); 3D: y inverse and forward (2 + d each), outer
+    # direction/inverse (5 + 2) and divergence/dot (2 + 2), the outer passes
+    # transforming two fields; 2D: outer (5 + d) and (d + 2); residual (3)
+    if inner:
+        helm = (2 * ndim + 2 * (2 + ndim) + 7 + 4 + 3) * Ns * z + N * r
+    else:
+        helm = (2 * ndim + (5 + ndim) + (ndim + 2) + 3) * Ns * z + N * r
     return gal, helm
 
 

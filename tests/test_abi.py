@@ -96,6 +96,7 @@ def test_run_config_round_trip_and_byte_model():
     Ns, N = 128 * 128 * 65, 128 ** 3
     g, h = bytes_per_iteration((128, 128, 128), "fp64")
     assert g == 18 * 6 * Ns * 16 + 8 * N * 8
-    assert h == (6 + 12 + 8 + 5 + 3) * Ns * 16 + N * 8
+    # x pass 6, y passes 5 + 5, outer passes 7 + 4 (two fields), residual 3
+    assert h == (6 + 10 + 7 + 4 + 3) * Ns * 16 + N * 8
     g2, _ = bytes_per_iteration((32, 32), "fp32_refined")
     assert g2 == 14 * 3 * 32 * 17 * 8 + 8 * 32 * 32 * 4
