@@ -563,3 +563,41 @@ def test_path_gradient_fp32_refined_matches_oracle():
     say("  passes", [d["stagger_iters"] for d in log], "rel err %.2e" % err, "dJ/dell", gq, rq)
     assert err <= 1e-4
     assert np.allclose(gq, rq, rtol=1e-4)
+
+
+def test_increment_adjoint_error_paths():
+    """Host-side failure handling of fftg_increment_adjoint: a missing output
+    is INVALID; a fixed point cut at maxit = 1 returns NOT_CONVERGED (a
+    warning: the outputs are written, finite)."""
+    import ctypes as ct
+    from oracle import staggered
+    from paper_2103_04770_amd.binding import FFTGError, KrylovOpts, _macro, phase_table
+    from tests.test_oracle_adjoint import STAG_TOLS
+    shape = (12, 16)
+    rng = np.random.default_rng(21)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    st_n = staggered.staggered_step(phase, table, 1, staggered.initial_state(shape, 2, 1),
+                                    ms.uniaxial_mixed(2, 3e-3), **STAG_TOLS)[0]
+    tgt = ms.uniaxial_mixed(2, 5e-3)
+    st = staggered.staggered_step(phase, table, 1, st_n, tgt, **STAG_TOLS)[0]
+    s = solver(shape)
+    f = lambda *k: torch.empty(k + shape, dtype=torch.float64, device="cuda")  # noqa: E731
+    g = torch.zeros((3,) + shape, dtype=torch.float64, device="cuda")
+    g[0] = 1.0 / phase.size
+    args = (dev(phase, torch.uint8), table, 1, dev(_pack(st_n)), dev(_pack(st)), tgt)
+    dl, gpn, gkn, ghn = f(1), f(6), f(), f(1)
+    # g_hist_n missing: rejected by the library before any launch
+    m = _macro(tgt)
+    rc = s.lib.fftg_increment_adjoint(
+        s.h, args[0].data_ptr(), phase_table(table), len(table), 1, args[3].data_ptr(),
+        args[4].data_ptr(), ct.byref(m), None, None, None, None, dl.data_ptr(), gpn.data_ptr(),
+        gkn.data_ptr(), None, ct.byref(KrylovOpts(1e-8, 100)), ct.byref(KrylovOpts(1e-8, 100)),
+        1e-8, 10, None)
+    with pytest.raises(FFTGError, match="INVALID"):
+        s._check(rc)
+    d = s.fftg_increment_adjoint(*args, dl, gpn, gkn, ghn, g_sig=g, cg_tol=1e-12, pcg_tol=1e-12,
+                                 tol=1e-14, maxit=1)
+    assert not d["converged"] and d["stagger_iters"] == 1
+    for t in (dl, gpn, gkn, ghn):
+        assert torch.isfinite(t).all()
