@@ -17,6 +17,7 @@ import argparse
 import collections
 import csv
 import glob
+import gzip
 import hashlib
 import json
 import os
@@ -64,7 +65,8 @@ def short(name):
 
 def _trace_durations(path):
     d = collections.defaultdict(list)
-    for r in csv.DictReader(open(path)):
+    fh = gzip.open(path, "rt") if path.endswith(".gz") else open(path)
+    for r in csv.DictReader(fh):
         d[short(r["Kernel_Name"])].append(
             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     return d
@@ -142,6 +144,37 @@ def counters(fetch_dir, write_dir, copy_mib, cmd):
     return "\n".join(lines) + "\n", rec
 
 
+def rates(trace, fetch_dir, write_dir, copy_mib, cmd_trace, cmd_counters, peak_gbs=8000.0,
+          top=24):
+    """Achieved HBM rate of every pass: counter bytes of a full launch (the
+    counter runs, calibrated on a device copy) over the mean duration of the
+    full launches of the same kernel (the kernel-trace run), against the
+    nominal peak.  Kernels are joined by their full template name."""
+    dur = _trace_durations(trace)
+    F = _counter(fetch_dir, "FETCH_SIZE")
+    W = _counter(write_dir, "WRITE_SIZE")
+    cf = copy_mib * 1024.0 / max(F["__amd_rocclr_copyBuffer"])
+    cw = copy_mib * 1024.0 / max(W["__amd_rocclr_copyBuffer"])
+    rows = []
+    for k, v in dur.items():
+        if k not in F or k not in W or k.startswith("__amd"):
+            continue
+        full = [x for x in v if x >= 0.2 * max(v)]
+        us = sum(full) / len(full)
+        mb = (_full_mean(F[k])[0] * cf + _full_mean(W[k])[0] * cw) * 1024.0 / 1e6
+        rows.append((sum(full), k, len(full), us, mb, mb / us * 1e3))
+    rows.sort(reverse=True)
+    out = ["HBM rate per pass: rocprofv3 counter bytes / rocprofv3 kernel duration",
+           "durations: " + cmd_trace, "bytes: " + cmd_counters,
+           "full launches only (duration >= 20%% of the kernel's longest; bytes: counters >= 50%%"
+           " of the kernel's largest); peak %.0f GB/s" % peak_gbs, "",
+           "%-52s %6s %10s %10s %10s %7s" % ("kernel", "full", "avg_us", "MB", "GB/s", "of_peak")]
+    for _, k, n, us, mb, gbs in rows[:top]:
+        out.append("%-52s %6d %10.2f %10.1f %10.0f %7.3f" % (k[:52], n, us, mb, gbs,
+                                                            gbs / peak_gbs))
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_", required=True)
@@ -155,7 +188,18 @@ def main():
     b.add_argument("--copy-mib", type=int, required=True)
     b.add_argument("--cmd", required=True)
     b.add_argument("--json")
+    c = sub.add_parser("rates")
+    c.add_argument("trace")
+    c.add_argument("fetch_dir")
+    c.add_argument("write_dir")
+    c.add_argument("--copy-mib", type=int, required=True)
+    c.add_argument("--cmd-trace", required=True)
+    c.add_argument("--cmd-counters", required=True)
     args = ap.parse_args()
+    if args.cmd_ == "rates":
+        print(rates(args.trace, args.fetch_dir, args.write_dir, args.copy_mib, args.cmd_trace,
+                    args.cmd_counters), end="")
+        return
     if args.cmd_ == "stats":
         print(stats_text(args.csv, args.cmd, args.trace), end="")
     else:
