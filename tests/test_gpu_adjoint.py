@@ -601,3 +601,44 @@ def test_increment_adjoint_error_paths():
     assert not d["converged"] and d["stagger_iters"] == 1
     for t in (dl, gpn, gkn, ghn):
         assert torch.isfinite(t).all()
+
+
+def test_path_gradient_spectral_scheme_and_voxel_size():
+    """The path gradient with the SPECTRAL derivative symbols and a voxel
+    size h = 0.5 (lengths in the same unit), two increments with damage
+    active: against the oracle's path gradient with the same scheme and h."""
+    from oracle import spectral, staggered
+    from paper_2103_04770_amd import SPECTRAL, autograd as ag
+    shape = (12, 16)
+    say("path gradient spectral h=0.5", shape)
+    rng = np.random.default_rng(17)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[1.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.25])]
+    tols = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, stagger_tol=1e-12, max_stagger=200)
+    targets = [ms.uniaxial_mixed(2, e) for e in (3e-3, 4e-3)]
+    st = staggered.initial_state(shape, 2, 1)
+    ostates = [st]
+    for tgt in targets:
+        st, _, _, stats = staggered.staggered_step(phase, table, 1, st, tgt, h=0.5,
+                                                   scheme=spectral.SPECTRAL, **tols)
+        assert stats["converged"]
+        ostates.append(st)
+    assert st["abar"].max() > table[0]["dC"]
+    g = np.zeros((3,) + shape)
+    g[0] = 1.0 / phase.size
+    kw = dict(cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12, maxit=300)
+    ref = adjoint.path_gradient(phase, table, 1, ostates, targets, g, h=0.5,
+                                scheme=spectral.SPECTRAL, **kw)
+    s = solver(shape, scheme=SPECTRAL, h=0.5)
+    ph = dev(phase, torch.uint8)
+    state = dev(np.zeros((3 + 7 + 2,) + shape))
+    sig = torch.empty((3,) + shape, dtype=torch.float64, device="cuda")
+    states = [state.clone()]
+    for tgt in targets:
+        assert s.staggered_step(ph, table, 1, state, tgt, sig, **tols)["converged"]
+        states.append(state.clone())
+    dl, log = ag.path_gradient(s, ph, table, 1, states, targets, dev(g), **kw)
+    got = dl.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say("  passes", [x["stagger_iters"] for x in log], "rel err %.2e" % err)
+    assert err <= 1e-7
