@@ -591,3 +591,45 @@ def test_path_gradient_with_cracking_and_unloading_by_finite_differences():
             fd = (vals[0] - vals[1]) / (2 * hq)
             assert grad[q] == pytest.approx(fd, rel=5e-4, abs=1e-5 * max(abs(grad).max(), 1e-9)), \
                 (j, q)
+
+
+def test_path_gradient_spectral_scheme_and_voxel_size_by_finite_differences():
+    """The path gradient with the SPECTRAL derivative symbols and a voxel
+    size h = 0.5 (two increments, damage active), against central differences
+    of the whole path in both per-phase lengths."""
+    from oracle import spectral, staggered
+    S = (12, 16)
+    rng = np.random.default_rng(17)
+    phase = (rng.uniform(size=S) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[1.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.25])]
+    tols = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, stagger_tol=1e-12, max_stagger=200)
+    targets = [ms.uniaxial_mixed(2, e) for e in (3e-3, 4e-3)]
+
+    def path(tab):
+        st = staggered.initial_state(S, 2, 1)
+        states, hom = [st], None
+        for tgt in targets:
+            st, _, hom, stats = staggered.staggered_step(phase, tab, 1, st, tgt, h=0.5,
+                                                         scheme=spectral.SPECTRAL, **tols)
+            assert stats["converged"]
+            states.append(st)
+        return states, hom
+
+    states, _ = path(table)
+    assert states[-1]["abar"].max() > table[0]["dC"]
+    g = np.zeros((3,) + S)
+    g[0] = 1.0 / phase.size
+    dl = adjoint.path_gradient(phase, table, 1, states, targets, g, h=0.5,
+                               scheme=spectral.SPECTRAL, cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12,
+                               maxit=300)
+    grad = adjoint.phase_length_gradient(dl[0], phase, table, 0)
+    for q in range(2):
+        e0 = table[q]["ell"][0]
+        hq = 1e-4 * e0
+        vals = []
+        for sgn in (1, -1):
+            tb = [dict(t, ell=list(t["ell"])) for t in table]
+            tb[q]["ell"][0] = e0 + sgn * hq
+            vals.append(path(tb)[1]["sigma"][0])
+        fd = (vals[0] - vals[1]) / (2 * hq)
+        assert grad[q] == pytest.approx(fd, rel=5e-4, abs=1e-6 * abs(grad).max())
