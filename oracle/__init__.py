@@ -22,6 +22,10 @@ computes, written to be checked against the paper by eye:
              preconditioned CG (Sec. 3.2.3, Algorithm 2)
   staggered  one load increment of the iterated staggered scheme
              (Sec. 3.2, Algorithm 1)
+  driver     variable load increments with cutbacks (a reading of Sec. 4.2)
+  adjoint    implicit adjoints of the converged solves, of a converged
+             staggered increment and of a whole load path (gradients in the
+             per-phase lengths)
 
 Transforms use numpy.fft on the full complex spectrum (fftn / ifftn) as a
 library primitive; Krylov solvers run in the plain real-space (mechanics) or
