@@ -596,7 +596,19 @@ def cpu_baseline(ws, iters):
                        "(single-threaded numpy FFT); %.1f s CG + %.1f s PCG" % (
                            iters, iters, t_cg, t_h),
                 galerkin_cg=N * iters / t_cg, helmholtz_pcg=N * iters / t_h,
-                host_threads_available=len(os.sched_getaffinity(0)))
+                host_threads_available=len(os.sched_getaffinity(0)), cpu_model=cpu_model())
+
+
+def cpu_model():
+    """The host processor's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def kernel_table(r, fp32, n):
