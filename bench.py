@@ -209,7 +209,12 @@ def run_driver(name="spheres64_20", e11_end=0.05, dt=0.02, max_attempts=60):
                 cutbacks=sum(r["cutbacks"] for r in rec), wall_s=round(wall, 3),
                 peak_sigma11=max((r["sigma"][0] for r in rec), default=0.0),
                 final_sigma11=rec[-1]["sigma"][0] if rec else 0.0,
-                accepted_voxel_krylov_iters_per_s=round(N * it / wall, 1))
+                accepted_voxel_krylov_iters_per_s=round(N * it / wall, 1),
+                # the homogenised curve with the Krylov counts of every accepted increment
+                curve=[dict(e11=round(r["t"] * e11_end, 6), sigma11=round(r["sigma"][0], 3),
+                            cg=int(r["cg_iters"]), pcg=int(r["pcg_iters"]),
+                            newton=int(r["newton_iters"]), stagger=int(r["stagger_iters"]),
+                            cutbacks=int(r["cutbacks"])) for r in rec])
 
 
 def run_adjoint():
