@@ -666,13 +666,15 @@ def main():
                     help="skip the adaptive-driver, adjoint-chain and batch runs")
     ap.add_argument("--c5", action="store_true",
                     help="also run the differentiation workload: 20 increments to E11 = 0.04 "
-                         "on the 30-sphere RVE and the gradient at the last one (FP64, FP32)")
+                         "on the 30-sphere RVE, the gradient at the last one and through the "
+                         "whole path (FP64, FP32), and the path gradient on the two-field RVE")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (the batched and multi-GPU "
-              "forms are not part of it); got --gpus %d" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single device, and "
+              "splitting an RVE or a batch over several GPUs is not implemented; got --gpus %d"
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2103_04770_amd import microstructure as ms, load_library
