@@ -12,7 +12,9 @@ options.  The run goes through LoadDriver (the library's fftg_drive), so it
 can checkpoint and resume.  Every accepted increment appends one line to the
 log: load factor, <sigma>, <eps>, iteration counts, staggered error, cutbacks,
 wall time, and the algorithmic bytes one Galerkin CG and one Helmholtz PCG
-iteration move on this grid.
+iteration move on this grid.  With "gradient": true the driver keeps every
+increment's state and a last line gives d<sigma_11>/d ell per field and phase
+at the end of the path, through every increment of the run.
 """
 from __future__ import annotations
 
@@ -43,6 +45,7 @@ class RunConfig:
     log: str = "run.jsonl"
     checkpoint: Optional[str] = None
     chunk: int = 1
+    gradient: bool = False                   # d<sigma_11>/d ell through the run at its end
 
     @classmethod
     def from_json(cls, path_or_text):
@@ -115,9 +118,10 @@ def run(cfg: RunConfig):
     dt = opts.pop("dt", 0.02)
     opts.update(cfg.tolerances)
     if cfg.checkpoint and os.path.exists(cfg.checkpoint):
-        drv = LoadDriver.resume(cfg.checkpoint, solver, phase, table, J, tgt, **opts)
+        drv = LoadDriver.resume(cfg.checkpoint, solver, phase, table, J, tgt,
+                                keep_states=cfg.gradient, **opts)
     else:
-        drv = LoadDriver(solver, phase, table, J, tgt, dt=dt, **opts)
+        drv = LoadDriver(solver, phase, table, J, tgt, dt=dt, keep_states=cfg.gradient, **opts)
     gal_b, helm_b = bytes_per_iteration(shape, cfg.precision)
     n0 = len(drv.records)
     with open(cfg.log, "a" if n0 else "w") as log:
@@ -136,6 +140,12 @@ def run(cfg: RunConfig):
 
         drv.run(t_end=cfg.t_end, chunk=cfg.chunk, checkpoint=cfg.checkpoint,
                 max_attempts=cfg.max_attempts, on_records=write)
+        grad = None
+        if cfg.gradient and len(drv.records) > n0:
+            _, grad = drv.path_gradient()
+            log.write(json.dumps(dict(workload=cfg.workload, gradient="d<sigma_11>/d ell",
+                                      from_t=drv.state_t[0], to_t=drv.state_t[-1],
+                                      dJ_dell_by_field=grad)) + "\n")
     solver.close()
     return drv.reason, len(drv.records) - n0
 

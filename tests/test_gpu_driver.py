@@ -164,3 +164,43 @@ def test_json_runner_logs_every_increment(tmp_path):
     assert [r["t"] for r in out["records"]] == [l["t"] for l in lines]
     for r, l in zip(out["records"], lines):
         assert np.allclose(r["sigma"], l["sigma"], rtol=0, atol=0)
+
+
+def test_driver_path_gradient_matches_oracle():
+    """LoadDriver(keep_states=True).path_gradient(): d<sigma_11>/d ell2
+    through the increments the adaptive driver accepted (the second one grown
+    by the driver), against the oracle's path gradient along the same
+    increments."""
+    from oracle import adjoint
+    from paper_2103_04770_amd.driver import LoadDriver
+    shape = (12, 16)
+    rng = np.random.default_rng(21)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.5])]
+    tols = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, stagger_tol=1e-12,
+                max_stagger=300)
+    s = _solver(shape)
+    ph = torch.from_numpy(phase).cuda()
+    drv = LoadDriver(s, ph, table, 1, ms.uniaxial_mixed(2, 6e-3), dt=0.4, dt_min=1e-3, grow=1.5,
+                     keep_states=True, **tols)
+    reason = drv.run(t_end=1.0)
+    say("driver path gradient: t", drv.state_t, "reason", reason)
+    assert reason == 0 and len(drv.states) == len(drv.records) + 1 >= 3
+    dl, per = drv.path_gradient(cg_tol=1e-13, pcg_tol=1e-13, tol=1e-12, maxit=300)
+    targets = drv.targets()
+    st = staggered.initial_state(shape, 2, 1)
+    ostates = [st]
+    for tgt in targets:
+        st, _, _, stats = staggered.staggered_step(phase, table, 1, st, tgt, **tols)
+        assert stats["converged"]
+        ostates.append(st)
+    g = np.zeros((3,) + shape)
+    g[0] = 1.0 / phase.size
+    ref = adjoint.path_gradient(phase, table, 1, ostates, targets, g, cg_tol=1e-13,
+                                pcg_tol=1e-13, tol=1e-12, maxit=300)
+    got = dl.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    rq = adjoint.phase_length_gradient(ref[0], phase, table, 0)
+    say("  rel err %.2e" % err, "dJ/dell", per[0], rq)
+    assert err <= 1e-7
+    assert np.allclose(per[0], rq, rtol=1e-7)
