@@ -204,3 +204,25 @@ def test_driver_path_gradient_matches_oracle():
     say("  rel err %.2e" % err, "dJ/dell", per[0], rq)
     assert err <= 1e-7
     assert np.allclose(per[0], rq, rtol=1e-7)
+
+
+def test_json_runner_gradient_line(tmp_path):
+    """RunConfig(gradient=True): after the increment lines, one line with
+    d<sigma_11>/d ell per field and phase through the whole run, equal to
+    LoadDriver.path_gradient on the same run."""
+    import json
+    from paper_2103_04770_amd import run as runmod
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    # E11 = 0.004 stays below the loss of stability of this disc (near 0.0057,
+    # where the transposed staggered iteration no longer contracts)
+    cfg = runmod.RunConfig(workload="disc2d_32", e11_end=0.004, log=str(tmp_path / "g.jsonl"),
+                           gradient=True, table_overrides=[{"dC": 0.001, "dR": 0.05}],
+                           driver=dict(dt=0.25, dt_min=1e-3, grow=1.5))
+    reason, n = runmod.run(cfg)
+    lines = [json.loads(l) for l in open(cfg.log)]
+    say("json runner gradient", reason, n, lines[-1])
+    assert reason == 0 and len(lines) == n + 1
+    g = lines[-1]["dJ_dell_by_field"]
+    assert lines[-1]["from_t"] == 0.0 and lines[-1]["to_t"] == 1.0
+    assert len(g) == 1 and len(g[0]) == 2 and all(np.isfinite(g[0])) and abs(g[0][0]) > 0
