@@ -76,7 +76,7 @@ struct fftg_handle {
   // Galerkin workspace (work precision), c-component half spectra
   void *kx = nullptr, *kr = nullptr, *kp = nullptr, *kw = nullptr;
   cpx<double>* spec64 = nullptr;  // FP64 c-component spectrum (stress, residual)
-  void* tan = nullptr;            // compact tangent [8][N], work precision
+  void* tan = nullptr;            // compact tangent [N][8] (a, b, m0..m5), work precision
   bool tan_valid = false;
   unsigned char mask_last[6] = {0, 1, 1, 1, 1, 1};
   double* partials = nullptr;

@@ -243,10 +243,11 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
       slot[q] = s < P ? 2 * xaddr<FIX>(s, x, ld) : 2 * xaddr<FIX>(s - P, x, ld) + 1;
       ev[q] = fb[slot[q]];
     }
-    const T a = (T)tan[v], b = (T)tan[g.N + v];
+    const TT* tv = tan + 8 * v;  // [a, b, m0..m5] of the voxel, contiguous
+    const T a = (T)tv[0], b = (T)tv[1];
     T m[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) m[i] = (T)tan[(2 + i) * g.N + v];
+    for (int i = 0; i < 6; ++i) m[i] = (T)tv[2 + i];
     T out[C];
     if constexpr (C == 6) {
       const T tr = ev[0] + ev[1] + ev[2];
@@ -1357,15 +1358,16 @@ FFTG_KERNEL void k_constitutive(MatTable tab, Geo g, int c, int J,
     }
     for (int i = 0; i < 6; ++i) st_np1[i * N + v] = ep[i];
     st_np1[6 * N + v] = kap;
+    TT* tv = tan + 8 * v;  // [a, b, m0..m5] of the voxel, contiguous
     if (gtn) {
-      tan[v] = (TT)ta_g;
-      tan[N + v] = (TT)tb;
-      for (int i = 0; i < 6; ++i) tan[(2 + i) * N + v] = (TT)tm_g[i];
+      tv[0] = (TT)ta_g;
+      tv[1] = (TT)tb;
+      for (int i = 0; i < 6; ++i) tv[2 + i] = (TT)tm_g[i];
     } else {
-      tan[v] = (TT)(w1 * K);
-      tan[N + v] = (TT)(w1 * tb);
+      tv[0] = (TT)(w1 * K);
+      tv[1] = (TT)(w1 * tb);
       const double sc = sqrt(w1 * tc);
-      for (int i = 0; i < 6; ++i) tan[(2 + i) * N + v] = (TT)(sc * nv[i]);
+      for (int i = 0; i < 6; ++i) tv[2 + i] = (TT)(sc * nv[i]);
     }
     for (int j = 0; j < J; ++j) {
       double a = 0.0;
@@ -1958,9 +1960,10 @@ FFTG_KERNEL void k_tangent_apply(long long N, int c, const TT* __restrict__ tan,
                                  double* __restrict__ gout) {
   for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
        v += (long long)gridDim.x * FFT_THREADS) {
-    const double a = (double)tan[v], b = (double)tan[N + v];
+    const TT* tv = tan + 8 * v;
+    const double a = (double)tv[0], b = (double)tv[1];
     double m[6], e[6], o[6];
-    for (int i = 0; i < 6; ++i) m[i] = (double)tan[(2 + i) * N + v];
+    for (int i = 0; i < 6; ++i) m[i] = (double)tv[2 + i];
     for (int i = 0; i < c; ++i) e[i] = gsig[(long long)i * N + v];
     if (c == 6) {
       const double tr = e[0] + e[1] + e[2];
