@@ -550,6 +550,39 @@ def run_batch(count=64, nworkers=8):
                 path_to_e11_0p01=path, tile_shifts_by_edge=tiles)
 
 
+def run_gtn_drive(name="gtn_spheres30_64", e11_end=0.05, max_records=200):
+    """The Gurson RVE (30 spheres, 64^3) under the adaptive driver from the
+    virgin state towards E11 = 0.05 (FP64, production tolerances, at most 30
+    staggered passes per increment), for at most `max_records` accepted
+    increments: porosity growth, increment sizes and the homogenised curve."""
+    import torch
+    from paper_2103_04770_amd import Solver, microstructure as ms
+    w = ms.workload(name)
+    S, J = w["shape"], w["nfields"]
+    s = Solver(tuple(reversed(S)))
+    state = torch.zeros((6 + 7 + 2 * J,) + S, dtype=torch.float64, device="cuda")
+    sig = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
+    ph = torch.from_numpy(w["phase"]).cuda()
+    recs, fmax = [], []
+    t, dt, reason = 0.0, 0.02, 3
+    t0 = time.perf_counter()
+    while reason == 3 and len(recs) < max_records:
+        out = s.fftg_drive(ph, w["table"], J, state, ms.uniaxial_mixed(3, e11_end), sig, t=t, dt=dt,
+                           dt_min=2e-4, max_records=10, max_attempts=400,
+                           **dict(TOLS, max_stagger=30))
+        t, dt, reason = out["t"], out["dt"], out["reason"]
+        recs += out["records"]
+        fmax.append((round(t * e11_end, 6), round(state[6 + 7].max().item(), 4)))
+        log("[gtn drive] E11 %.5f, %d increments, max porosity %.4f, %.1f s" % (
+            t * e11_end, len(recs), fmax[-1][1], time.perf_counter() - t0))
+    wall = time.perf_counter() - t0
+    s.close()
+    return dict(workload=name, e11_reached=t * e11_end, reason=reason, accepted=len(recs),
+                wall_s=round(wall, 3), porosity_max_by_e11=fmax,
+                curve=[(round(r["t"] * e11_end, 6), round(float(r["sigma"][0]), 2),
+                        int(r["stagger_iters"]), int(r["cutbacks"])) for r in recs])
+
+
 def run_gtn(name="gtn_spheres30_128", steps=6):
     """The Gurson matrix (two non-local fields, Sec. 4.2 parameters) on the
     30-sphere 128^3 RVE: `steps` staggered increments of 1e-3 from the virgin
@@ -703,6 +736,9 @@ def main():
                     help="also run the differentiation workload: 20 increments to E11 = 0.04 "
                          "on the 30-sphere RVE, the gradient at the last one and through the "
                          "whole path (FP64, FP32), and the path gradient on the two-field RVE")
+    ap.add_argument("--gtn-drive", action="store_true",
+                    help="also drive the 64^3 Gurson RVE adaptively towards E11 = 0.05 "
+                         "(200 increments, about 1.5 min)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -809,6 +845,8 @@ def main():
     if args.c5:
         out["c5_path_gradient"] = run_c5()
         out["two_field_path_gradient"] = run_two_field_path_gradient()
+    if args.gtn_drive:
+        out["gtn_drive"] = run_gtn_drive()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_iters)
