@@ -226,3 +226,29 @@ def test_json_runner_gradient_line(tmp_path):
     g = lines[-1]["dJ_dell_by_field"]
     assert lines[-1]["from_t"] == 0.0 and lines[-1]["to_t"] == 1.0
     assert len(g) == 1 and len(g[0]) == 2 and all(np.isfinite(g[0])) and abs(g[0][0]) > 0
+
+
+def test_drive_fp32_refined_matches_fp64():
+    """The adaptive driver on an FP32-refined handle: the same accepted load
+    factors as on an FP64 handle (the decisions have wide margins) and
+    homogenised stresses within 1e-6 of the FP64 run at every increment."""
+    from paper_2103_04770_amd import FP32_REFINED, Solver
+    S, phase, table = _rve(n=12, seed=4, dC=0.001, dR=0.05)
+    tgt = ms.uniaxial_mixed(3, 0.012)
+    kw = dict(dt=0.25, dt_min=1e-3, grow=1.5, max_attempts=40, cg_tol=1e-10, pcg_tol=1e-10,
+              newton_tol=1e-9, stagger_tol=1e-6, max_stagger=40)
+    res = {}
+    for name, prec in (("fp64", None), ("fp32", FP32_REFINED)):
+        if not torch.cuda.is_available():
+            pytest.skip("no GPU")
+        s = Solver(tuple(reversed(S))) if prec is None else Solver(tuple(reversed(S)), prec=prec)
+        state = torch.zeros((6 + 7 + 2,) + S, dtype=torch.float64, device="cuda")
+        sig = torch.zeros((6,) + S, dtype=torch.float64, device="cuda")
+        res[name] = s.fftg_drive(torch.from_numpy(phase).cuda(), table, 1, state, tgt, sig, **kw)
+        s.close()
+    t64 = [r["t"] for r in res["fp64"]["records"]]
+    t32 = [r["t"] for r in res["fp32"]["records"]]
+    say("driver fp64 t", t64, res["fp64"]["reason"], "| fp32 t", t32, res["fp32"]["reason"])
+    assert t64 == t32 and res["fp64"]["reason"] == res["fp32"]["reason"] == 0
+    for a, b in zip(res["fp32"]["records"], res["fp64"]["records"]):
+        assert np.abs(a["sigma"] - b["sigma"]).max() <= 1e-6 * np.abs(b["sigma"]).max()
