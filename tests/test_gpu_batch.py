@@ -33,20 +33,24 @@ def _rves():
     return out
 
 
-def test_batch_equals_each_rve_alone():
-    from paper_2103_04770_amd import Solver
+@pytest.mark.parametrize("form", ["fp64", "fp32_refined"])
+def test_batch_equals_each_rve_alone(form):
+    """Every member of the batch (both precision forms) is bitwise equal to
+    the same increments run alone: states, stresses and iteration counts."""
+    from paper_2103_04770_amd import FP32_REFINED, FP64, Solver
     from paper_2103_04770_amd.batch import RVEBatch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    prec = FP64 if form == "fp64" else FP32_REFINED
     rves = _rves()
-    say("batch of", [r["shape"][0] for r in rves])
-    batch = RVEBatch(rves)
+    say("batch of", [r["shape"][0] for r in rves], form)
+    batch = RVEBatch(rves, prec=prec)
     loads = [ms.uniaxial_mixed(3, 3e-3), ms.uniaxial_mixed(3, 6e-3)]
     res = [batch.step(tgt, nworkers=3, **TOLS) for tgt in loads]
     torch.cuda.synchronize()
     for i, r in enumerate(rves):
         S = r["shape"]
-        s = Solver(tuple(reversed(S)))
+        s = Solver(tuple(reversed(S)), prec=prec)
         state = torch.zeros((15,) + S, dtype=torch.float64, device="cuda")
         sig = torch.empty((6,) + S, dtype=torch.float64, device="cuda")
         ph = torch.from_numpy(r["phase"]).cuda()
