@@ -100,3 +100,36 @@ def test_run_config_round_trip_and_byte_model():
     assert h == (6 + 10 + 7 + 4 + 3) * Ns * 16 + N * 8
     g2, _ = bytes_per_iteration((32, 32), "fp32_refined")
     assert g2 == 14 * 3 * 32 * 17 * 8 + 8 * 32 * 32 * 4
+
+
+def test_profiling_summaries_on_synthetic_csv(tmp_path):
+    """Host logic of the rocprofv3 summaries: kernel classes (the split
+    Helmholtz y pass by direction), counter calibration against the device
+    copy and the per-pass HBM rate, on small hand-made CSV files."""
+    from paper_2103_04770_amd import profiling as pr
+    assert pr.classify("void fftg::k_h_y_split<double, true, 128>") == ("fp64", "helmholtz_y_fwd")
+    assert pr.classify("void fftg::k_h_y_split<float, false, 64>") == ("fp32", "helmholtz_y_inv")
+    assert pr.classify("void fftg::k_gal_dir_inv<double, 128, 0>") == ("fp64",
+                                                                       "galerkin_outer_dir_inv")
+    assert pr.classify("fftg::k_stream_copy") is None
+    k = "void fftg::k_gal_resid<double, 6>"
+    trace = tmp_path / "trace.csv"
+    q = '"%s"' % k                       # rocprofv3 quotes the names (they hold commas)
+    trace.write_text("Kernel_Name,Start_Timestamp,End_Timestamp\n"
+                     "%s,0,50000\n%s,100000,150000\n%s,200000,201000\n" % (q, q, q))
+    for name, counter, copy_kib, kib in (("f", "FETCH_SIZE", 512.0, 150.0),
+                                         ("w", "WRITE_SIZE", 1024.0, 100.0)):
+        d = tmp_path / name
+        d.mkdir()
+        (d / "run_counter_collection.csv").write_text(
+            "Kernel_Name,Counter_Name,Counter_Value\n"
+            "__amd_rocclr_copyBuffer,%s,%f\n%s,%s,%f\n%s,%s,%f\n" % (
+                counter, copy_kib, q, counter, kib, q, counter, kib))
+    text = pr.rates(str(trace), str(tmp_path / "f"), str(tmp_path / "w"), 1, "t", "c")
+    row = [l for l in text.splitlines() if l.startswith(k)][0].split()
+    # two full launches of 50 us (the 1 us one is left out); fetch scaled x2
+    # (1 MiB copy read as 512 KiB), write x1: (300 + 100) KiB per launch
+    full, us, mb, gbs = int(row[-5]), float(row[-4]), float(row[-3]), float(row[-2])
+    assert full == 2 and us == pytest.approx(50.0)
+    assert mb == pytest.approx(400 * 1024 / 1e6, abs=0.05)
+    assert gbs == pytest.approx(400 * 1024 / 50e-6 / 1e9, abs=0.5)   # printed to 1 GB/s
