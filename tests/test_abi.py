@@ -133,3 +133,13 @@ def test_profiling_summaries_on_synthetic_csv(tmp_path):
     assert full == 2 and us == pytest.approx(50.0)
     assert mb == pytest.approx(400 * 1024 / 1e6, abs=0.05)
     assert gbs == pytest.approx(400 * 1024 / 50e-6 / 1e9, abs=0.5)   # printed to 1 GB/s
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message before touching a GPU."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
