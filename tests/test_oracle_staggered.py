@@ -71,3 +71,78 @@ def test_simple_staggered_is_one_pass():
     assert stats["stagger_iters"] == 1
     assert abs(hom["eps"][0] - 5e-3) < 1e-15
     assert abs(hom["sigma"][1]) < 1e-5 * hom["sigma"][0]
+
+
+# ---------------------------------------------------------------------------
+# Irreversibility of the particle cracking law (reading C10: the cracking
+# damage is driven by the history kappa = max over the path of the non-local
+# equivalent strain; the history committed at the end of an increment is
+# max(hist_n, abar_{n+1})).
+#
+# Closed form for a homogeneous cracking RVE under uniaxial mixed control
+# (E11 prescribed, every other mean stress zero): whatever the damage, the
+# strain is uniform with eps22 = eps33 = -nu E11 (uniaxial stress of an
+# isotropic solid scaled by 1 - D), so the Mazars equivalent strain is
+# sqrt(<eps_i>_+^2) = E11 for E11 > 0; a constant source gives abar = E11
+# exactly (the Helmholtz operator maps constants to themselves); hence
+# hist_{n+1} = max(hist_n, E11), D = clip((hist - k0)/(kf - k0), 0, dmax) and
+# <sigma_11> = (1 - D) E E11.
+# ---------------------------------------------------------------------------
+_CRACK_PATH = (4e-3, 2e-3, 3e-3, 5e-3)   # load, unload, reload below the peak, past it
+
+
+def _cracking_path_against_hand_values():
+    """Runs the oracle along _CRACK_PATH on a homogeneous cracking RVE and
+    returns the list of mismatches against the hand values (empty = pass)."""
+    S = (4, 4, 4)
+    phase = np.zeros(S, dtype=np.uint8)
+    mat = ms.particle_cracking(ell=[1.5], dfield=0)
+    table = [mat]
+    E, k0, kf = mat["E"], mat["dC"], mat["dR"]
+    st = staggered.initial_state(S, 3, 1)
+    peak = 0.0
+    bad = []
+    for e11 in _CRACK_PATH:
+        st, sig, hom, stats = staggered.staggered_step(phase, table, 1, st,
+                                                       ms.uniaxial_mixed(3, e11),
+                                                       stagger_tol=1e-12, **TOLS)
+        peak = max(peak, e11)
+        D = min(max((peak - k0) / (kf - k0), 0.0), mat["dmax"])
+        if not stats["converged"]:
+            bad.append((e11, "not converged"))
+        if np.abs(st["abar"][0] - e11).max() > 1e-14:
+            bad.append((e11, "abar", float(np.abs(st["abar"][0] - e11).max())))
+        if np.abs(st["hist"][0] - peak).max() > 1e-14:
+            bad.append((e11, "hist", float(np.abs(st["hist"][0] - peak).max())))
+        s11 = (1.0 - D) * E * e11
+        if np.abs(sig[0] - s11).max() > 1e-11 * s11:
+            bad.append((e11, "sigma11", float(np.abs(sig[0] - s11).max()), s11))
+        if abs(hom["sigma"][0] - s11) > 1e-11 * s11:
+            bad.append((e11, "<sigma11>", float(hom["sigma"][0]), s11))
+    return bad
+
+
+def test_cracking_history_is_the_running_maximum():
+    """Load, unload, reload below the previous peak, reload past it: the
+    committed history is the running maximum of the non-local equivalent
+    strain voxel by voxel, and the damage stays at D(history) on unloading."""
+    assert _cracking_path_against_hand_values() == []
+
+
+def test_cracking_history_pin_catches_wrong_commits(monkeypatch):
+    """Planted mistakes in the checker's history commit (the history taken
+    as the new field alone, or as the previous increment's field) fail the
+    pin above."""
+    from oracle import material
+
+    def no_max(phase, table, abar, hist_n, abar_n):
+        return abar.copy()
+
+    def previous_field(phase, table, abar, hist_n, abar_n):
+        return abar_n.copy()
+
+    for wrong in (no_max, previous_field):
+        monkeypatch.setattr(material, "commit_history", wrong)
+        assert _cracking_path_against_hand_values() != []
+    monkeypatch.undo()
+    assert _cracking_path_against_hand_values() == []
