@@ -27,8 +27,8 @@ computes, written to be checked against the paper by eye:
              staggered increment and of a whole load path (gradients in the
              per-phase lengths)
 
-Transforms use numpy.fft on the full complex spectrum (fftn / ifftn) as a
-library primitive; Krylov solvers run in the plain real-space (mechanics) or
+Transforms use scipy.fft on the full complex spectrum (spectral.fftn /
+spectral.ifftn, threaded over the process's cores) as a library primitive; Krylov solvers run in the plain real-space (mechanics) or
 full-spectrum Hermitian (Helmholtz) inner product.
 """
 from . import spectral, mandel, gtn, material, galerkin, helmholtz, staggered  # noqa: F401

@@ -37,8 +37,8 @@ from . import galerkin, helmholtz, mandel, material, spectral
 
 def grad_fields(u, qt):
     """Real gradient components G_j u (j in physical order) of a real field."""
-    uh = np.fft.fftn(u)
-    return [np.real(np.fft.ifftn(1j * qj * uh)) for qj in qt]
+    uh = spectral.fftn(u)
+    return [np.real(spectral.ifftn(1j * qj * uh)) for qj in qt]
 
 
 def helmholtz_adjoint(abar, gbar, ell2, h=1.0, scheme=spectral.ROTATED, ell2_ref=-1.0,

@@ -15,8 +15,8 @@ used here is:
     it) runs one staggered increment (staggered.staggered_step) with the
     Newton divergence guard and abort-on-failure switched on;
   * the increment is accepted when the staggered error met its tolerance and
-    the last mechanics solve converged; then t <- t', dt <- min(grow dt,
-    dt_max);
+    every inner solve of the last pass (the mechanics and each Helmholtz
+    PCG) converged; then t <- t', dt <- min(grow dt, dt_max);
   * otherwise the state is restored, dt <- dt / 2, and the driver stops once
     dt < dt_min (reason 1);
   * it also stops after max_attempts attempts (reason 2) or max_records
@@ -75,7 +75,7 @@ def drive(phase, table, nfields, state, target_end, t0=0.0, t_end=1.0, dt=0.1,
         tn = t_end if dt >= t_end - t else t + dt
         attempts += 1
         new_state, hom, stats = step(copy.deepcopy(state), target_at(target_end, tn))
-        if stats["converged"] and stats["mech_converged"]:
+        if stats["converged"] and stats.get("inner_converged", stats["mech_converged"]):
             state = new_state
             t = tn
             records.append(dict(t=t, sigma=np.asarray(hom["sigma"]), eps=np.asarray(hom["eps"]),

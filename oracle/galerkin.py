@@ -42,7 +42,7 @@ def project(tau, q, mask):
     S = tau.shape[1:]
     ndim = len(S)
     ax = _axes(ndim)
-    th = np.fft.fftn(tau, axes=ax)
+    th = spectral.fftn(tau, axes=ax)
     T = mandel.to_tensor(th)                          # (d, d, *S)
     qv = np.stack([np.broadcast_to(qj, S) for qj in q])  # (d, *S)
     q2 = (qv * qv).sum(axis=0)
@@ -54,7 +54,7 @@ def project(tau, q, mask):
     out = mandel.from_tensor(P)
     zero = (slice(None),) + (0,) * ndim
     out[zero] = np.asarray(mask, dtype=np.float64) * th[zero]
-    return np.real(np.fft.ifftn(out, axes=ax))
+    return np.real(spectral.ifftn(out, axes=ax))
 
 
 def cg(apply_A, b, tol, maxit):

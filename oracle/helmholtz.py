@@ -25,8 +25,8 @@ def operator(u_hat, ell2, qt):
     S = u_hat.shape
     out = u_hat.copy()
     for qj in qt:
-        g = np.fft.ifftn(1j * qj * u_hat)      # i q~_j u_hat -> real gradient field
-        hh = np.fft.fftn(ell2 * np.real(g))
+        g = spectral.ifftn(1j * qj * u_hat)      # i q~_j u_hat -> real gradient field
+        hh = spectral.fftn(ell2 * np.real(g))
         out = out - 1j * qj * hh
     return out
 
@@ -78,8 +78,8 @@ def helmholtz_solve(alpha, ell2, h=1.0, scheme=spectral.ROTATED, ell2_ref=-1.0,
         ell2_ref = float(np.mean(ell2))
     q2 = sum(v * v for v in qt)
     Minv = 1.0 / (1.0 + ell2_ref * q2)
-    b = np.fft.fftn(alpha)
-    xh0 = np.fft.fftn(x0) if x0 is not None else np.zeros_like(b)
+    b = spectral.fftn(alpha)
+    xh0 = spectral.fftn(x0) if x0 is not None else np.zeros_like(b)
     x, it, rel, ok = pcg(lambda u: operator(u, ell2, qt), lambda r: Minv * r,
                          b, xh0, tol, maxit)
-    return dict(abar=np.real(np.fft.ifftn(x)), iters=it, relres=rel, converged=ok)
+    return dict(abar=np.real(spectral.ifftn(x)), iters=it, relres=rel, converged=ok)

@@ -19,10 +19,27 @@ mirror image.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft
 
 ROTATED = "rotated"
 SPECTRAL = "spectral"
+
+# Threads of the library FFT (scipy.fft): every core this process may run on.
+WORKERS = len(os.sched_getaffinity(0))
+
+
+def fftn(x, axes=None):
+    """Unnormalised DFT X[k] = sum_n x[n] exp(-2 pi i k.n / N) over `axes`
+    (all by default), the library primitive of every transform here."""
+    return scipy.fft.fftn(x, axes=axes, workers=WORKERS)
+
+
+def ifftn(X, axes=None):
+    """Inverse of fftn, normalised by 1/N."""
+    return scipy.fft.ifftn(X, axes=axes, workers=WORKERS)
 
 
 def theta_1d(n):

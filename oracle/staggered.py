@@ -43,7 +43,9 @@ def staggered_step(phase, table, nfields, state, target, h=1.0,
     loop as soon as a mechanics solve does not converge (the increment is then
     reported as not converged; the adaptive load driver cuts it back).
     Returns (new_state, sigma, homog dict(sigma=<sigma>, eps=<eps>), stats);
-    stats["mech_converged"] tells whether the last mechanics solve converged."""
+    stats["mech_converged"] tells whether the last mechanics solve converged,
+    stats["inner_converged"] whether every inner solve of the last pass (the
+    Newton iteration and each Helmholtz PCG) met its stop test."""
     mask, Emac, Smac = target
     S = phase.shape
     N = int(np.prod(S))
@@ -54,7 +56,7 @@ def staggered_step(phase, table, nfields, state, target, h=1.0,
     abar_k = state["abar"].copy()
     ell2 = [ell2_field(phase, table, j) for j in range(J)]
     stats = dict(stagger_iters=0, newton_iters=0, cg_iters=0, pcg_iters=0, err=np.inf,
-                 converged=False, mech_converged=False)
+                 converged=False, mech_converged=False, inner_converged=False)
     mech = None
     for k in range(max_stagger):
         D = material.damage_from_nonlocal(phase, table, abar_k, hist_n, state["abar"])
@@ -65,16 +67,20 @@ def staggered_step(phase, table, nfields, state, target, h=1.0,
         stats["newton_iters"] += mech["newton_iters"]
         stats["cg_iters"] += mech["cg_iters"]
         stats["mech_converged"] = mech["converged"]
+        stats["inner_converged"] = False
         if abort_on_mech_failure and not mech["converged"]:
             stats["stagger_iters"] = k + 1
             eps_k = mech["eps"]
             break
         abar_new = np.empty_like(abar_k)
+        inner_ok = bool(mech["converged"])
         for j in range(J):
             hs = helmholtz.helmholtz_solve(mech["alpha"][j], ell2[j], h=h, scheme=scheme,
                                            x0=abar_k[j], tol=pcg_tol, maxit=pcg_maxit)
             abar_new[j] = hs["abar"]
             stats["pcg_iters"] += hs["iters"]
+            inner_ok = inner_ok and bool(hs["converged"])
+        stats["inner_converged"] = inner_ok
         eps_new = mech["eps"]
         de = eps_new - eps_k
         mean_norm = np.sqrt(sum(float(eps_new[i].mean()) ** 2 for i in range(eps_new.shape[0])))
