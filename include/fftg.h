@@ -143,6 +143,9 @@ typedef struct {
   double relres;      /* last Newton residual ratio (fftg_solve) or PCG ratio */
   double err;         /* last staggered error ERR (Algorithm 1 (iii)) */
   double t_ms[4];     /* wall time: constitutive, Galerkin CG, Helmholtz PCG, other */
+  int inner_converged; /* staggered_step, fftg_drive: 1 when every inner solve of the
+                        * last staggered pass met its stop test (the Newton iteration
+                        * of step (i) and each Helmholtz PCG of step (ii)), else 0 */
 } fftg_stats;
 
 /* Create a solver for one grid.  `hip_stream` is a hipStream_t (NULL = the
@@ -196,7 +199,15 @@ fftg_status helmholtz_solve(fftg_handle* h, const double* alpha, const double* e
  *   sigma_out  dev [c][N] stress at t_{n+1}
  *   homog_out  host [12]: <sigma> (first c of 6 slots), <eps> (slots 6..6+c)
  * max_stagger_iters = 1 is the "simple staggered" single pass.  The loop
- * stops when ERR <= stagger_tol. */
+ * stops when ERR <= stagger_tol.  FFTG_OK needs both ERR <= stagger_tol and
+ * every inner solve of the last pass at its own tolerance (Algorithm 1 (i),
+ * (ii); Algorithm 2's ConjGrad test): a Newton iteration cut at newton_maxit
+ * or a Helmholtz PCG cut at its maxit (or stalled at its rounding floor)
+ * gives FFTG_NOT_CONVERGED with stats->inner_converged = 0, even when the
+ * staggered error passed.
+ * Every entry point that takes `phase` checks on the device that each id is
+ * below nphase (FFTG_E_INVALID otherwise); a phase with a damage law needs
+ * 0 <= dmax < 1. */
 fftg_status staggered_step(fftg_handle* h, const unsigned char* phase, const fftg_phase* tab,
                            int nphase, int nfields, double* state, const fftg_macro* target,
                            const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
@@ -354,8 +365,9 @@ fftg_status fftg_phase_sums(fftg_handle* h, const unsigned char* phase, int npha
  * (mask of target_end).  An attempt t -> t' = min(t + dt, t_end) runs one
  * staggered increment (as staggered_step) that stops early when a mechanics
  * solve fails or Newton's residual grows newton_div times in a row; it is
- * accepted when ERR <= stagger_tol and the last Newton solve converged
- * (then dt <- min(grow dt, dt_max)).  A rejected attempt restores the state
+ * accepted when ERR <= stagger_tol and every inner solve of its last pass
+ * converged (the Newton iteration and each Helmholtz PCG; then
+ * dt <- min(grow dt, dt_max)).  A rejected attempt restores the state
  * and the stress and halves dt; the run stops once dt < dt_min. */
 typedef struct {
   double t;         /* in: load factor of `state`; out: load factor reached */

@@ -69,12 +69,13 @@ class DriveRecord(ct.Structure):
 class Stats(ct.Structure):
     _fields_ = [("newton_iters", ct.c_int), ("cg_iters", ct.c_int), ("pcg_iters", ct.c_int),
                 ("stagger_iters", ct.c_int), ("relres", ct.c_double), ("err", ct.c_double),
-                ("t_ms", ct.c_double * 4)]
+                ("t_ms", ct.c_double * 4), ("inner_converged", ct.c_int)]
 
     def as_dict(self):
         return dict(newton_iters=self.newton_iters, cg_iters=self.cg_iters,
                     pcg_iters=self.pcg_iters, stagger_iters=self.stagger_iters,
-                    relres=self.relres, err=self.err, t_ms=list(self.t_ms))
+                    relres=self.relres, err=self.err, t_ms=list(self.t_ms),
+                    inner_converged=bool(self.inner_converged))
 
 
 class BatchItem(ct.Structure):

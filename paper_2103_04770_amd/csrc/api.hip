@@ -14,6 +14,7 @@
 #include <functional>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "fftg.h"
@@ -32,6 +33,12 @@ thread_local std::string g_create_error;
 
 // Smallest relative residual asked of a Krylov solve with FP32 vectors.
 constexpr double kFp32KrylovFloor = 1e-5;
+// A Krylov loop with FP32 vectors stops as stagnated when its residual has
+// not reached a new minimum for this many iterations (its rounding floor).
+// FP64 loops have no such test: like the paper's ConjGrad they run to the
+// tolerance or to maxit (the residual of CG on an ill-conditioned operator
+// can rise for hundreds of iterations while the error still falls).
+constexpr int kFp32StagnationWindow = 400;
 
 // FFTG_VERBOSE=1 prints one line per Newton correction and per Krylov solve.
 bool verbose() {
@@ -95,6 +102,7 @@ struct fftg_handle {
   double *eps_k = nullptr, *eps_prev = nullptr, *ab_k = nullptr, *ab_prev = nullptr,
          *Dj = nullptr, *alph = nullptr, *st1 = nullptr, *sig_k = nullptr;
   void* ell2j = nullptr;  // [J][N] work precision
+  double* ell2j64 = nullptr;  // [J][N] FP64 copy (FP32-refined handles: refinement residuals)
   // adaptive driver: copy of the packed state and the stress before an attempt
   double* drive_bak = nullptr;
   double* adj_r = nullptr;  // adjoint: two FP64 real scratch fields
@@ -458,7 +466,18 @@ void validate_table(const fftg_phase* tab, int nphase, int nfields) {
     }
     if (q.model != FFTG_ELASTIC && q.dfield >= 0 && !(q.dR > q.dC))
       throw Fail{FFTG_E_INVALID, "damage law needs dR > dC"};
+    // the stiffness factor 1 - D must stay positive (the adjoints divide by it)
+    if (q.model != FFTG_ELASTIC && q.dfield >= 0 && !(q.dmax >= 0.0 && q.dmax < 1.0))
+      throw Fail{FFTG_E_INVALID, "damage law needs 0 <= dmax < 1"};
   }
+}
+
+// Every phase id must index the table: counted on the device, one read-back.
+void validate_phase(fftg_handle* H, const unsigned char* phase, int nphase) {
+  if (!phase) throw Fail{FFTG_E_INVALID, "null phase array"};
+  double bad = 0.0;
+  read_sums(H, fftg::launch_count_bad_phase(H->g.N, nphase, phase, H->partials, H->st), 1, &bad);
+  if (bad != 0.0) throw Fail{FFTG_E_INVALID, "phase id >= nphase in the phase array"};
 }
 
 void validate_macro(const fftg_macro* t, int c) {
@@ -568,7 +587,8 @@ void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double to
   k.tol2 = tol * tol * bb;
   k.rrmin = bb;
   k.maxit = maxit;
-  k.done = (bb == 0.0 || maxit <= 0) ? 1 : 0;
+  k.window = std::is_same<T, float>::value ? kFp32StagnationWindow : 0;
+  k.done = bb == 0.0 ? 1 : (maxit <= 0 ? 2 : 0);
   write_ctl(H, k);
   HIPCHK(hipMemsetAsync(H->kx, 0, sizeof(cpx<T>) * c * g.Ns, H->st));
   HIPCHK(hipMemsetAsync(H->kp, 0, sizeof(cpx<T>) * c * g.Ns, H->st));
@@ -654,72 +674,47 @@ hipGraphExec_t helm_graph(fftg_handle* H, const T* ell2) {
 }
 
 // ------------------------------------------------------------ Helmholtz PCG
-// Solves L x = b for a scalar field; alpha, abar FP64 [N]; ell2 work precision [N].
+// PCG of Algorithm 2 on the half spectrum in work precision T: b in H->hb
+// (weighted |b|^2 = bb), x0 in H->hx (x0_zero: x0 = 0, H->hx is cleared);
+// on return H->hx holds x.  Stops at ||r|| <= tol ||b||, maxit, a stall or a
+// breakdown (KrylovCtl::done).
 template <typename T>
-void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double ell2_ref,
-                   double* abar, double tol, int maxit, int& iters, double& relres,
-                   int& status) {
+KrylovCtl helm_krylov(fftg_handle* H, const T* ell2, double ell2_ref, double bb, double tol,
+                      int maxit, bool x0_zero) {
   const Geo& g = H->g;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
   const T scl = T(1.0 / (double)g.N);
-  // b = F(alpha)
-  const T* ain;
-  if (H->fp32()) {
-    fftg::launch_convert<double, float>(g.N, alpha, reinterpret_cast<float*>(H->rtmp), H->st);
-    ain = reinterpret_cast<const T*>(H->rtmp);
-  } else {
-    ain = reinterpret_cast<const T*>(alpha);
-  }
-  fwd3<T>(H, 1, ain, C<T>(H->hb));
-  fftg::launch_hermitize<T>(g, 1, C<T>(H->hb), H->st);
-  double bb;
-  read_sums(H, fftg::launch_wnorm2<T>(g, 1, C<T>(H->hb), H->partials, H->st), 1, &bb);
-  if (bb == 0.0) {
-    HIPCHK(hipMemsetAsync(abar, 0, sizeof(double) * g.N, H->st));
-    iters = 0;
-    relres = 0.0;
-    status = 1;
-    return;
-  }
-  if (!(ell2_ref > 0.0)) {
-    double s;
-    read_sums(H, fftg::launch_sum_ell2<T>(g.N, ell2, H->partials, H->st), 1, &s);
-    ell2_ref = s / (double)g.N;
-  }
-  if (H->fp32()) tol = std::max(tol, 0.1 * kFp32KrylovFloor);
   KrylovCtl k{};
   k.bb = bb;
   k.tol2 = tol * tol * bb;
   k.maxit = maxit;
+  k.window = std::is_same<T, float>::value ? kFp32StagnationWindow : 0;
   k.ell2ref = ell2_ref;
   write_ctl(H, k);
-  // x0 = F(abar)
-  const T* xin;
-  if (H->fp32()) {
-    fftg::launch_convert<double, float>(g.N, abar, reinterpret_cast<float*>(H->rtmp), H->st);
-    xin = reinterpret_cast<const T*>(H->rtmp);
+  if (x0_zero) {
+    // r = b - 0 (H->hx doubles as the zero operator output)
+    HIPCHK(hipMemsetAsync(H->hx, 0, sizeof(cpx<T>) * g.Ns, H->st));
   } else {
-    xin = reinterpret_cast<const T*>(abar);
+    // r = b - L x0
+    fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), false, C<T>(H->hr),
+                              C<T>(H->hx), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
+    helm_inner<T>(H, false, C<T>(H->hw), nullptr, K_HLM_YI);
+    fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, nullptr,
+                                    H->st);
+    helm_inner<T>(H, true, C<T>(H->hw), nullptr, K_HLM_YF);
+    fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hx),
+                              C<T>(H->hw), C<T>(H->hAp), nullptr, H->ctl, H->st);
   }
-  fwd3<T>(H, 1, xin, C<T>(H->hx));
-  // r = b - L x0
-  fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), false, C<T>(H->hr),
-                            C<T>(H->hx), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
-  helm_inner<T>(H, false, C<T>(H->hw), nullptr, K_HLM_YI);
-  fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, nullptr,
-                                  H->st);
-  helm_inner<T>(H, true, C<T>(H->hw), nullptr, K_HLM_YF);
-  fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hx), C<T>(H->hw),
-                            C<T>(H->hAp), nullptr, H->ctl, H->st);
   const int nr0 = fftg::launch_h_resid<T>(g, SY<T>(H), true, C<T>(H->hr), C<T>(H->hb),
-                                          C<T>(H->hAp), H->partials, H->ctl, H->st);
+                                          x0_zero ? C<T>(H->hx) : C<T>(H->hAp), H->partials,
+                                          H->ctl, H->st);
   double s2[2];
   read_sums(H, nr0, 2, s2);
   k.rz = s2[0];
   k.rr = s2[1];
   k.rrmin = s2[1];
-  k.done = (s2[1] <= k.tol2 || maxit <= 0) ? 1 : 0;
+  k.done = (s2[1] <= k.tol2 || maxit <= 0) ? (s2[1] <= k.tol2 ? 1 : 2) : 0;
   write_ctl(H, k);
   HIPCHK(hipMemsetAsync(H->hp, 0, sizeof(cpx<T>) * g.Ns, H->st));
   if (!H->prof) {
@@ -743,7 +738,40 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
     }
   }
   fftg::launch_xfinal<T>(C<T>(H->hx), C<T>(H->hp), g.Ns, H->ctl, H->st);
-  inv3<T, double>(H, 1, C<T>(H->hx), abar, scl, false);
+  check_launch();
+  return k;
+}
+
+// preconditioner length^2: the given one, else the volume mean of ell2
+template <typename T>
+double ell2_reference(fftg_handle* H, const T* ell2, double ell2_ref) {
+  if (ell2_ref > 0.0) return ell2_ref;
+  double s;
+  read_sums(H, fftg::launch_sum_ell2<T>(H->g.N, ell2, H->partials, H->st), 1, &s);
+  return s / (double)H->g.N;
+}
+
+// FP64 handles: solves L abar = alpha for a scalar field (alpha, abar FP64
+// [N], abar in = x0), the whole PCG in FP64.
+void helmholtz_pcg64(fftg_handle* H, const double* alpha, const double* ell2, double ell2_ref,
+                     double* abar, double tol, int maxit, int& iters, double& relres,
+                     int& status) {
+  const Geo& g = H->g;
+  fwd3<double>(H, 1, alpha, C<double>(H->hb));
+  fftg::launch_hermitize<double>(g, 1, C<double>(H->hb), H->st);
+  double bb;
+  read_sums(H, fftg::launch_wnorm2<double>(g, 1, C<double>(H->hb), H->partials, H->st), 1, &bb);
+  if (bb == 0.0) {
+    HIPCHK(hipMemsetAsync(abar, 0, sizeof(double) * g.N, H->st));
+    iters = 0;
+    relres = 0.0;
+    status = 1;
+    return;
+  }
+  ell2_ref = ell2_reference<double>(H, ell2, ell2_ref);
+  fwd3<double>(H, 1, abar, C<double>(H->hx));
+  const KrylovCtl k = helm_krylov<double>(H, ell2, ell2_ref, bb, tol, maxit, false);
+  inv3<double, double>(H, 1, C<double>(H->hx), abar, 1.0 / (double)g.N, false);
   check_launch();
   if (verbose())
     std::fprintf(stderr, "[fftg] pcg iters %d status %d rr/bb %.3e ell2ref %.4g\n", k.iters,
@@ -751,6 +779,116 @@ void helmholtz_pcg(fftg_handle* H, const double* alpha, const T* ell2, double el
   iters = k.iters;
   relres = std::sqrt(k.rr / bb);
   status = k.done;
+}
+
+// FP64 application of the Helmholtz operator on the half spectrum, Ap = L x,
+// through the same fused passes as the PCG (w: three gradient fields).
+void helm_apply64(fftg_handle* H, const cpx<double>* x, cpx<double>* w, cpx<double>* Ap,
+                  const double* ell2) {
+  const Geo& g = H->g;
+  const bool zo = g.ndim == 3;
+  const int oa = outer_axis(H);
+  cpx<double>* xm = const_cast<cpx<double>*>(x);  // read only (update = false)
+  fftg::launch_h_dir_inv<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64, false, nullptr,
+                                 xm, xm, w, nullptr, H->st);
+  helm_inner<double>(H, false, w, nullptr, K_HLM_YI);
+  fftg::launch_x_fused_helm<double, double>(H->plan[0], TW<double>(H, 0), g, w, ell2,
+                                            1.0 / (double)g.N, nullptr, H->st);
+  helm_inner<double>(H, true, w, nullptr, K_HLM_YF);
+  fftg::launch_h_div_fwd<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64, x, w, Ap,
+                                 nullptr, nullptr, H->st);
+}
+
+// Largest number of FP64 refinement sweeps of one FP32-refined Helmholtz solve.
+constexpr int kHelmSweeps = 30;
+
+// FP32-refined handles: iterative refinement of Algorithm 2 (Sec. 3.2.3).
+// x and b live in FP64 on the half spectrum; each sweep forms the FP64
+// residual r = b - L x with the FP64 operator (FP64 ell2), solves L d = r
+// with the FP32 PCG (b rounded to FP32, d0 = 0), and adds d to x in FP64.
+// It stops when the FP64 residual meets ||r|| <= tol ||b|| (status 1), when
+// the FP32 iterations reach maxit (2), on a breakdown (3, 4), or when a sweep
+// no longer halves the FP64 residual (5: the attainable accuracy is reached).
+void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32,
+                       const double* ell2_64, double ell2_ref, double* abar, double tol,
+                       int maxit, int& iters, double& relres, int& status) {
+  const Geo& g = H->g;
+  const long long Ns = g.Ns;
+  cpx<double>* S = H->spec64;  // [0] b, [1] x, [2..4] gradient fields, [5] L x
+  cpx<double>* b = S;
+  cpx<double>* x = S + Ns;
+  cpx<double>* w = S + 2 * Ns;
+  cpx<double>* Ax = S + 5 * Ns;
+  fwd3<double>(H, 1, alpha, b);
+  fftg::launch_hermitize<double>(g, 1, b, H->st);
+  double bb;
+  read_sums(H, fftg::launch_wnorm2<double>(g, 1, b, H->partials, H->st), 1, &bb);
+  iters = 0;
+  if (bb == 0.0) {
+    HIPCHK(hipMemsetAsync(abar, 0, sizeof(double) * g.N, H->st));
+    relres = 0.0;
+    status = 1;
+    return;
+  }
+  ell2_ref = ell2_reference<float>(H, ell2_32, ell2_ref);
+  fwd3<double>(H, 1, abar, x);
+  fftg::launch_hermitize<double>(g, 1, x, H->st);
+  double rr = HUGE_VAL, rr_prev = HUGE_VAL;
+  status = 0;
+  for (int sweep = 0;; ++sweep) {
+    helm_apply64(H, x, w, Ax, ell2_64);
+    read_sums(H, fftg::launch_h_refine_resid(g, b, Ax, C<float>(H->hb), H->partials, H->st), 1,
+              &rr);
+    if (!std::isfinite(rr)) throw Fail{FFTG_E_NONFINITE, "non-finite Helmholtz residual"};
+    if (rr <= tol * tol * bb) {
+      status = 1;
+      break;
+    }
+    if (sweep > 0 && !(rr < 0.25 * rr_prev)) {
+      status = 5;
+      break;
+    }
+    if (iters >= maxit || sweep >= kHelmSweeps) {
+      status = 2;
+      break;
+    }
+    rr_prev = rr;
+    // the correction only has to bring ||r|| below tol ||b|| (with a margin);
+    // FP32 vectors do not resolve more than ~1e-5 of their right-hand side
+    const double tin = std::max(kFp32KrylovFloor, 0.5 * tol * std::sqrt(bb / rr));
+    const KrylovCtl k =
+        helm_krylov<float>(H, ell2_32, ell2_ref, rr, std::min(tin, 0.5), maxit - iters, true);
+    iters += k.iters;
+    if (k.done == 3) {
+      status = 3;
+      break;
+    }
+    if (k.done == 4) {
+      status = 4;
+      break;
+    }
+    fftg::launch_acc_wide<float>(2 * Ns, reinterpret_cast<const float*>(H->hx),
+                                 reinterpret_cast<double*>(x), H->st);
+  }
+  inv3<double, double>(H, 1, x, abar, 1.0 / (double)g.N, false);
+  check_launch();
+  if (verbose())
+    std::fprintf(stderr, "[fftg] refined pcg iters %d status %d rr/bb %.3e ell2ref %.4g\n",
+                 iters, status, rr / bb, ell2_ref);
+  relres = std::sqrt(rr / bb);
+}
+
+// Algorithm 2 on the handle's precision: ell2w is the work-precision ell2
+// (FP32 on FP32-refined handles), ell2_64 the FP64 one (read by the FP64
+// residuals of the refinement; equal to ell2w on FP64 handles).
+void helm_solve(fftg_handle* H, const double* alpha, const void* ell2w, const double* ell2_64,
+                double ell2_ref, double* abar, double tol, int maxit, int& iters, double& relres,
+                int& status) {
+  if (H->fp32())
+    helmholtz_refined(H, alpha, reinterpret_cast<const float*>(ell2w), ell2_64, ell2_ref, abar,
+                      tol, maxit, iters, relres, status);
+  else
+    helmholtz_pcg64(H, alpha, ell2_64, ell2_ref, abar, tol, maxit, iters, relres, status);
 }
 
 // ------------------------------------------------------------ mechanics
@@ -858,6 +996,28 @@ MechOut mechanics(fftg_handle* H, const unsigned char* phase, const MatTable& ta
 }
 
 // ------------------------------------------------------------ workspace
+// squared lengths of every field on the grid: work precision in H->ell2j, and
+// FP64 in H->ell2j64 on FP32-refined handles
+void fill_ell2(fftg_handle* H, const MatTable& t, int J, const unsigned char* phase) {
+  const long long N = H->g.N;
+  for (int j = 0; j < J; ++j) {
+    if (H->fp32()) {
+      fftg::launch_ell2<float>(t, N, j, phase, reinterpret_cast<float*>(H->ell2j) + j * N, H->st);
+      fftg::launch_ell2<double>(t, N, j, phase, H->ell2j64 + j * N, H->st);
+    } else {
+      fftg::launch_ell2<double>(t, N, j, phase, reinterpret_cast<double*>(H->ell2j) + j * N,
+                                H->st);
+    }
+  }
+}
+// field j's squared lengths: work precision, FP64
+const void* ell2w_of(fftg_handle* H, int j) {
+  return static_cast<const char*>(H->ell2j) + H->wsz() * (size_t)j * (size_t)H->g.N;
+}
+const double* ell2d_of(fftg_handle* H, int j) {
+  return (H->fp32() ? H->ell2j64 : reinterpret_cast<const double*>(H->ell2j)) + (long long)j * H->g.N;
+}
+
 void alloc_helm(fftg_handle* H) {
   if (H->hx) return;
   const Geo& g = H->g;
@@ -882,6 +1042,7 @@ void alloc_stagger(fftg_handle* H, int J) {
   dfree((void*&)H->st1);
   dfree((void*&)H->sig_k);
   dfree(H->ell2j);
+  dfree((void*&)H->ell2j64);
   const size_t N = H->g.N;
   const size_t Jm = J > 0 ? J : 1;
   H->eps_k = (double*)dalloc(sizeof(double) * H->c * N);
@@ -893,6 +1054,7 @@ void alloc_stagger(fftg_handle* H, int J) {
   H->alph = (double*)dalloc(sizeof(double) * Jm * N);
   H->st1 = (double*)dalloc(sizeof(double) * 7 * N);
   H->ell2j = dalloc(H->wsz() * Jm * N);
+  if (H->fp32()) H->ell2j64 = (double*)dalloc(sizeof(double) * Jm * N);
   H->stJ = J;
 }
 
@@ -931,6 +1093,7 @@ void destroy(fftg_handle* H) {
   dfree((void*&)H->st1);
   dfree((void*&)H->sig_k);
   dfree(H->ell2j);
+  dfree((void*&)H->ell2j64);
   dfree((void*&)H->drive_bak);
   dfree((void*&)H->adj_r);
   dfree((void*&)H->sadj);
@@ -1034,6 +1197,7 @@ struct StaggerOut {
   fftg_stats stats{};
   bool converged = false;  // ERR <= stagger_tol
   bool mech_ok = false;    // the last mechanics solve converged
+  bool inner_ok = false;   // every inner solve of the last pass met its stop test
 };
 
 StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTable& t, int J,
@@ -1056,13 +1220,7 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
   if (J > 0)
     HIPCHK(hipMemcpyAsync(H->ab_k, s_abar, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
                           H->st));
-  for (int j = 0; j < J; ++j) {
-    if (H->fp32())
-      fftg::launch_ell2<float>(t, N, j, phase, reinterpret_cast<float*>(H->ell2j) + j * N, H->st);
-    else
-      fftg::launch_ell2<double>(t, N, j, phase, reinterpret_cast<double*>(H->ell2j) + j * N,
-                                H->st);
-  }
+  fill_ell2(H, t, J, phase);
   fftg_stats acc{};
   bool converged = false;
   int k = 0;
@@ -1079,6 +1237,7 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
                                         newton_maxit, newton_div);
     acc.newton_iters += o.newton;
     out.mech_ok = o.converged;
+    out.inner_ok = o.converged;
     acc.cg_iters += o.cg;
     acc.relres = o.relres;
     acc.t_ms[0] += o.t_const;
@@ -1094,15 +1253,12 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
     for (int j = 0; j < J; ++j) {
       int it = 0, status = 0;
       double rel = 0.0;
-      if (H->fp32())
-        helmholtz_pcg<float>(H, H->alph + j * N, reinterpret_cast<const float*>(H->ell2j) + j * N,
-                             -1.0, H->ab_k + j * N, pcg->tol, pcg->maxit, it, rel, status);
-      else
-        helmholtz_pcg<double>(H, H->alph + j * N,
-                              reinterpret_cast<const double*>(H->ell2j) + j * N, -1.0,
-                              H->ab_k + j * N, pcg->tol, pcg->maxit, it, rel, status);
+      helm_solve(H, H->alph + j * N, ell2w_of(H, j), ell2d_of(H, j), -1.0, H->ab_k + j * N,
+                 pcg->tol, pcg->maxit, it, rel, status);
       if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
       if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+      // maxit (2) or a stall at the rounding floor (5): not at tolerance
+      out.inner_ok = out.inner_ok && status == 1;
       acc.pcg_iters += it;
     }
     sync(H);
@@ -1160,6 +1316,7 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
   sync(H);
   const double tot = wall_ms(t_all);
   acc.t_ms[3] = std::max(0.0, tot - acc.t_ms[0] - acc.t_ms[1] - acc.t_ms[2]);
+  acc.inner_converged = out.inner_ok ? 1 : 0;
   out.stats = acc;
   out.converged = converged;
   return out;
@@ -1242,13 +1399,7 @@ AdjOut stag_adjoint_core(fftg_handle* H, const unsigned char* phase, const MatTa
   const double* abar = state_np1 + (long long)(c + 7 + J) * N;
   // frozen damage of the converged state, squared lengths per field
   fftg::launch_damage(t, N, J, phase, abar, hist_n, abar_n, H->Dj, H->st);
-  for (int j = 0; j < J; ++j) {
-    if (H->fp32())
-      fftg::launch_ell2<float>(t, N, j, phase, reinterpret_cast<float*>(H->ell2j) + j * N, H->st);
-    else
-      fftg::launch_ell2<double>(t, N, j, phase, reinterpret_cast<double*>(H->ell2j) + j * N,
-                                H->st);
-  }
+  fill_ell2(H, t, J, phase);
   fftg_stats& acc = out.stats;
   int status = 0;
   auto mech = [&](const double* gb, const double* gs) {
@@ -1264,15 +1415,11 @@ AdjOut stag_adjoint_core(fftg_handle* H, const unsigned char* phase, const MatTa
     for (int j = 0; j < J; ++j) {
       int it = 0, st = 0;
       double rel = 0.0;
-      if (H->fp32())
-        helmholtz_pcg<float>(H, src + j * N, reinterpret_cast<const float*>(H->ell2j) + j * N,
-                             -1.0, x + j * N, pcg->tol, pcg->maxit, it, rel, st);
-      else
-        helmholtz_pcg<double>(H, src + j * N, reinterpret_cast<const double*>(H->ell2j) + j * N,
-                              -1.0, x + j * N, pcg->tol, pcg->maxit, it, rel, st);
+      helm_solve(H, src + j * N, ell2w_of(H, j), ell2d_of(H, j), -1.0, x + j * N, pcg->tol,
+                 pcg->maxit, it, rel, st);
       if (st == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
       if (st == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
-      out.inner_capped = out.inner_capped || st == 2;
+      out.inner_capped = out.inner_capped || st == 2 || st == 5;
       acc.pcg_iters += it;
     }
   };
@@ -1670,6 +1817,7 @@ fftg_status fftg_constitutive(fftg_handle* H, const unsigned char* phase, const 
     validate_table(tab, nphase, nfields);
     if (!phase || !state_n || !eps || !sigma || !state_np1 || (nfields > 0 && (!D || !alpha)))
       throw Fail{FFTG_E_INVALID, "fftg_constitutive: null pointer"};
+    validate_phase(H, phase, nphase);
     MatTable t = make_table(tab, nphase, nfields);
     if (H->fp32())
       fftg::launch_constitutive<float>(t, H->g, H->c, nfields, phase, eps, state_n, D, sigma,
@@ -1767,14 +1915,10 @@ fftg_status helmholtz_solve(fftg_handle* H, const double* alpha, const double* e
     auto t0 = std::chrono::steady_clock::now();
     int it = 0, status = 0;
     double rel = 0.0;
-    if (H->fp32()) {
+    if (H->fp32())
       fftg::launch_convert<double, float>(H->g.N, ell2, reinterpret_cast<float*>(H->ell2w), H->st);
-      helmholtz_pcg<float>(H, alpha, reinterpret_cast<const float*>(H->ell2w), ell2_ref, abar,
-                           opts->tol, opts->maxit, it, rel, status);
-    } else {
-      helmholtz_pcg<double>(H, alpha, ell2, ell2_ref, abar, opts->tol, opts->maxit, it, rel,
-                            status);
-    }
+    helm_solve(H, alpha, H->fp32() ? H->ell2w : ell2, ell2, ell2_ref, abar, opts->tol,
+               opts->maxit, it, rel, status);
     sync(H);
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
@@ -1799,14 +1943,10 @@ fftg_status helmholtz_adjoint(fftg_handle* H, const double* ell2, double ell2_re
     auto t0 = std::chrono::steady_clock::now();
     int it = 0, status = 0;
     double rel = 0.0;
-    if (H->fp32()) {
+    if (H->fp32())
       fftg::launch_convert<double, float>(H->g.N, ell2, reinterpret_cast<float*>(H->ell2w), H->st);
-      helmholtz_pcg<float>(H, gbar, reinterpret_cast<const float*>(H->ell2w), ell2_ref, dalpha,
-                           opts->tol, opts->maxit, it, rel, status);
-    } else {
-      helmholtz_pcg<double>(H, gbar, ell2, ell2_ref, dalpha, opts->tol, opts->maxit, it, rel,
-                            status);
-    }
+    helm_solve(H, gbar, H->fp32() ? H->ell2w : ell2, ell2, ell2_ref, dalpha, opts->tol,
+               opts->maxit, it, rel, status);
     if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
     if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
     grad_dot(H, dalpha, abar, dell2);
@@ -1832,6 +1972,7 @@ fftg_status fftg_solve_adjoint(fftg_handle* H, const unsigned char* phase, const
     validate_macro(target, H->c);
     if (!phase || !state_n || !eps || !gbar || !mu || !cg || (nfields > 0 && (!D || !dD)))
       throw Fail{FFTG_E_INVALID, "fftg_solve_adjoint: null pointer"};
+    validate_phase(H, phase, nphase);
     if (has_gtn(tab, nphase))
       throw Fail{FFTG_E_UNSUPPORTED, "fftg_solve_adjoint: no adjoint of the Gurson return"};
     const MatTable t = make_table(tab, nphase, nfields);
@@ -1864,6 +2005,7 @@ fftg_status fftg_staggered_adjoint(fftg_handle* H, const unsigned char* phase,
     validate_macro(target, H->c);
     if (!phase || !state_n || !state_np1 || !dell2 || !cg || !pcg || nfields < 1 || maxit < 1)
       throw Fail{FFTG_E_INVALID, "fftg_staggered_adjoint: null pointer, no field or maxit < 1"};
+    validate_phase(H, phase, nphase);
     if (has_gtn(tab, nphase))
       throw Fail{FFTG_E_UNSUPPORTED, "fftg_staggered_adjoint: Gurson sources are not covered"};
     auto t0 = std::chrono::steady_clock::now();
@@ -1899,6 +2041,7 @@ fftg_status fftg_increment_adjoint(fftg_handle* H, const unsigned char* phase,
     if (!phase || !state_n || !state_np1 || !dell2 || !g_epsp_n || !g_kappa_n || !g_hist_n ||
         !cg || !pcg || nfields < 1 || maxit < 1)
       throw Fail{FFTG_E_INVALID, "fftg_increment_adjoint: null pointer, no field or maxit < 1"};
+    validate_phase(H, phase, nphase);
     for (int p = 0; p < nphase; ++p)
       if (tab[p].model == FFTG_GTN)
         throw Fail{FFTG_E_UNSUPPORTED,
@@ -1952,6 +2095,7 @@ fftg_status fftg_damage(fftg_handle* H, const unsigned char* phase, const fftg_p
     validate_table(tab, nphase, nfields);
     if (nfields < 1 || !phase || !abar || !hist || !D)
       throw Fail{FFTG_E_INVALID, "fftg_damage: null pointer or no field"};
+    validate_phase(H, phase, nphase);
     if (has_gtn(tab, nphase))
       throw Fail{FFTG_E_UNSUPPORTED, "fftg_damage: Gurson phases need the committed fields"};
     const MatTable t = make_table(tab, nphase, nfields);
@@ -1970,6 +2114,7 @@ fftg_status fftg_damage_adjoint(fftg_handle* H, const unsigned char* phase, cons
     validate_table(tab, nphase, nfields);
     if (nfields < 1 || !phase || !abar || !hist || !gD || !gabar)
       throw Fail{FFTG_E_INVALID, "fftg_damage_adjoint: null pointer or no field"};
+    validate_phase(H, phase, nphase);
     if (has_gtn(tab, nphase))
       throw Fail{FFTG_E_UNSUPPORTED, "fftg_damage_adjoint: no adjoint of the Gurson porosity"};
     const MatTable t = make_table(tab, nphase, nfields);
@@ -1987,6 +2132,7 @@ fftg_status fftg_ell2(fftg_handle* H, const unsigned char* phase, const fftg_pha
     validate_table(tab, nphase, FFTG_MAX_FIELDS);
     if (!phase || !ell2 || field < 0 || field >= FFTG_MAX_FIELDS)
       throw Fail{FFTG_E_INVALID, "fftg_ell2: null pointer or bad field"};
+    validate_phase(H, phase, nphase);
     const MatTable t = make_table(tab, nphase, FFTG_MAX_FIELDS);
     fftg::launch_ell2<double>(t, H->g.N, field, phase, ell2, H->st);
     check_launch();
@@ -2001,6 +2147,7 @@ fftg_status fftg_phase_sums(fftg_handle* H, const unsigned char* phase, int npha
   return run_guarded(H, [&]() -> fftg_status {
     if (!phase || !f || !out || nphase < 1 || nphase > FFTG_MAX_PHASES)
       throw Fail{FFTG_E_INVALID, "fftg_phase_sums: bad arguments"};
+    validate_phase(H, phase, nphase);
     read_sums(H, fftg::launch_phase_sums(H->g.N, nphase, phase, f, H->partials, H->st), nphase,
               out);
     return FFTG_OK;
@@ -2019,6 +2166,7 @@ fftg_status fftg_solve(fftg_handle* H, const unsigned char* phase, const fftg_ph
     if (!phase || !state_n || !eps || !sigma || !state_np1 || !cg ||
         (nfields > 0 && (!D || !alpha)))
       throw Fail{FFTG_E_INVALID, "fftg_solve: null pointer"};
+    validate_phase(H, phase, nphase);
     MatTable t = make_table(tab, nphase, nfields);
     MechOut o = H->fp32() ? mechanics<float>(H, phase, t, nfields, D, state_n, target, eps, sigma,
                                              state_np1, alpha, cg, newton_tol, newton_maxit)
@@ -2049,13 +2197,14 @@ fftg_status staggered_step(fftg_handle* H, const unsigned char* phase, const fft
     validate_macro(target, H->c);
     if (!phase || !state || !cg || !pcg || !sigma_out || !homog_out)
       throw Fail{FFTG_E_INVALID, "staggered_step: null pointer"};
+    validate_phase(H, phase, nphase);
     if (max_stagger_iters < 1) throw Fail{FFTG_E_INVALID, "max_stagger_iters must be >= 1"};
     const MatTable t = make_table(tab, nphase, nfields);
     const StaggerOut o = stagger_core(H, phase, t, nfields, state, target, cg, pcg, newton_tol,
                                       newton_maxit, stagger_tol, max_stagger_iters, sigma_out,
                                       homog_out, false, 0);
     if (stats) *stats = o.stats;
-    return o.converged ? FFTG_OK : FFTG_NOT_CONVERGED;
+    return o.converged && o.inner_ok ? FFTG_OK : FFTG_NOT_CONVERGED;
   });
 }
 
@@ -2073,6 +2222,7 @@ fftg_status fftg_drive(fftg_handle* H, const unsigned char* phase, const fftg_ph
     if (!phase || !state || !cg || !pcg || !opts || !sigma_out || !n_records ||
         (max_records > 0 && !records))
       throw Fail{FFTG_E_INVALID, "fftg_drive: null pointer"};
+    validate_phase(H, phase, nphase);
     if (max_stagger_iters < 1) throw Fail{FFTG_E_INVALID, "max_stagger_iters must be >= 1"};
     if (!(opts->dt > 0.0) || !(opts->dt_min > 0.0) || !(opts->dt_max > 0.0) ||
         !(opts->grow >= 1.0) || max_records < 0 || opts->max_attempts < 0 ||
@@ -2115,7 +2265,7 @@ fftg_status fftg_drive(fftg_handle* H, const unsigned char* phase, const fftg_ph
       const StaggerOut o =
           stagger_core(H, phase, t, J, state, &tgt, cg, pcg, newton_tol, newton_maxit,
                        stagger_tol, max_stagger_iters, sigma_out, homog, true, opts->newton_div);
-      if (o.converged && o.mech_ok) {
+      if (o.converged && o.inner_ok) {
         tl = tn;
         fftg_drive_record& r = records[recs++];
         r.t = tn;

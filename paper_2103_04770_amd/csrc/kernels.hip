@@ -924,7 +924,7 @@ FFTG_KERNEL void k_fin_beta(const double* __restrict__ partials, int nb, int nre
       ctl->done = 1;
     else if (ctl->iters >= ctl->maxit)
       ctl->done = 2;
-    else if (ctl->iters - ctl->itmin >= STAGNATION_WINDOW)
+    else if (ctl->window > 0 && ctl->iters - ctl->itmin >= ctl->window)
       ctl->done = 5;
   }
 }
@@ -1847,6 +1847,20 @@ FFTG_KERNEL void k_phase_sums(long long N, int nphase, const unsigned char* __re
   }
 }
 
+// Number of voxels whose phase id is >= nphase -> partials [gridDim] (exact:
+// counts stay far below 2^53).
+FFTG_KERNEL void k_count_bad_phase(long long N, int nphase,
+                                   const unsigned char* __restrict__ phase,
+                                   double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  double acc = 0.0;
+  for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
+       v += (long long)gridDim.x * FFT_THREADS)
+    acc += phase[v] >= nphase ? 1.0 : 0.0;
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 // Per-component sums of a real field [ncomp][N] -> partials [ncomp][gridDim].
 FFTG_KERNEL void k_comp_sums(long long N, int ncomp, const double* __restrict__ f,
                              double* __restrict__ partials) {
@@ -1923,6 +1937,32 @@ FFTG_KERNEL void k_convert(long long n, const TA* __restrict__ a, TB* __restrict
   for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
        i += (long long)gridDim.x * FFT_THREADS)
     b[i] = (TB)a[i];
+}
+
+// b <- b + a, widening a to FP64 (the FP64 accumulation of an FP32 correction).
+template <typename TA>
+FFTG_KERNEL void k_acc_wide(long long n, const TA* __restrict__ a, double* __restrict__ b) {
+  for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * FFT_THREADS)
+    b[i] += (double)a[i];
+}
+
+// FP64 residual of an iterative-refinement sweep of the Helmholtz solve:
+// r = b - Ap on the half spectrum, stored rounded to FP32 as the right-hand
+// side of the next FP32 correction solve; partials: weighted |r|^2 in FP64.
+FFTG_KERNEL void k_h_refine_resid(Geo g, const cpx<double>* __restrict__ b,
+                                  const cpx<double>* __restrict__ Ap, cpx<float>* __restrict__ r32,
+                                  double* __restrict__ partials) {
+  __shared__ double red[FFT_THREADS];
+  double acc = 0.0;
+  for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
+       gi += (long long)gridDim.x * FFT_THREADS) {
+    const cpx<double> r = b[gi] - Ap[gi];
+    r32[gi] = mk((float)r.x, (float)r.y);
+    acc += hweight((int)(gi % g.n1h), g.n1h) * (r.x * r.x + r.y * r.y);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 template <typename T>
@@ -2388,6 +2428,13 @@ void launch_damage_adj(const MatTable& tab, long long N, int J, const unsigned c
   hipLaunchKernelGGL(k_damage_adj, dim3(grid_for(N)), dim3(FFT_THREADS), 0, st, tab, N, J, phase,
                      abar, hist, gD, gabar);
 }
+int launch_count_bad_phase(long long N, int nphase, const unsigned char* phase,
+                           double* partials, hipStream_t st) {
+  const int nb = grid_for(N);
+  hipLaunchKernelGGL(k_count_bad_phase, dim3(nb), dim3(FFT_THREADS), 0, st, N, nphase, phase,
+                     partials);
+  return nb;
+}
 int launch_phase_sums(long long N, int nphase, const unsigned char* phase, const double* f,
                       double* partials, hipStream_t st) {
   const int nb = grid_for(N);
@@ -2551,6 +2598,20 @@ void launch_vmax(long long n, double* a, const double* b, hipStream_t st) {
 template <typename TA, typename TB>
 void launch_convert(long long n, const TA* a, TB* b, hipStream_t st) {
   hipLaunchKernelGGL((k_convert<TA, TB>), dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, a, b);
+}
+
+template <typename TA>
+void launch_acc_wide(long long n, const TA* a, double* b, hipStream_t st) {
+  hipLaunchKernelGGL((k_acc_wide<TA>), dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, n, a, b);
+}
+template void launch_acc_wide<float>(long long, const float*, double*, hipStream_t);
+
+int launch_h_refine_resid(const Geo& g, const cpx<double>* b, const cpx<double>* Ap,
+                          cpx<float>* r32, double* partials, hipStream_t st) {
+  const int nb = grid_for(g.Ns);
+  hipLaunchKernelGGL(k_h_refine_resid, dim3(nb), dim3(FFT_THREADS), 0, st, g, b, Ap, r32,
+                     partials);
+  return nb;
 }
 
 template <typename T>

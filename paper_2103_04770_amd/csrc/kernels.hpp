@@ -42,11 +42,11 @@ struct KrylovCtl {
   double rrmin;   // smallest r.r seen so far, and the iteration it was seen at
   int itmin;
   int iters, maxit;
+  int window;     // stagnation window (0: none)
   int done;       // 0 running, 1 converged, 2 max iterations, 3 breakdown,
                   // 4 non-finite, 5 stagnated (no new smallest residual for
-                  // STAGNATION_WINDOW iterations: rounding floor reached)
+                  // `window` iterations: the rounding floor of FP32 vectors)
 };
-constexpr int STAGNATION_WINDOW = 100;
 
 struct Mat {
   int model;  // 0 elastic, 1 J2 damage, 2 elastic cracking, 3 Gurson (GTN)
@@ -144,6 +144,8 @@ void launch_damage_adj(const MatTable& tab, long long N, int J, const unsigned c
                        hipStream_t st);
 int launch_phase_sums(long long N, int nphase, const unsigned char* phase, const double* f,
                       double* partials, hipStream_t st);
+int launch_count_bad_phase(long long N, int nphase, const unsigned char* phase,
+                           double* partials, hipStream_t st);
 template <typename TT>
 void launch_tangent_apply(long long N, int c, const TT* tan, const double* gsig,
                           const double* gin, double* gout, hipStream_t st);
@@ -201,5 +203,9 @@ template <typename TA, typename TB>
 void launch_convert(long long n, const TA* a, TB* b, hipStream_t st);
 template <typename T>
 int launch_sum_ell2(long long N, const T* ell2, double* partials, hipStream_t st);
+template <typename TA>
+void launch_acc_wide(long long n, const TA* a, double* b, hipStream_t st);
+int launch_h_refine_resid(const Geo& g, const cpx<double>* b, const cpx<double>* Ap,
+                          cpx<float>* r32, double* partials, hipStream_t st);
 
 }  // namespace fftg

@@ -59,7 +59,8 @@ def test_ctypes_structs_match_the_header(tmp_path):
         "fftg_phase": (binding.Phase, ["model", "E", "dfield", "dmax", "ell", "n_hard", "q1",
                                        "sN", "fu"]),
         "fftg_macro": (binding.Macro, ["mask", "E", "S"]),
-        "fftg_stats": (binding.Stats, ["newton_iters", "relres", "err", "t_ms"]),
+        "fftg_stats": (binding.Stats, ["newton_iters", "relres", "err", "t_ms",
+                                        "inner_converged"]),
         "fftg_drive_opts": (binding.DriveOpts, None),
         "fftg_drive_record": (binding.DriveRecord, None),
         "fftg_batch_item": (binding.BatchItem, None),

@@ -1,0 +1,102 @@
+"""Converged staggered increments of the 64^3 RVE with 20 spheres (one
+non-local field, J2 damage matrix, elastic particles) against the oracle,
+element by element over the whole grid, at the parity tolerances (Krylov
+1e-12, Newton 1e-11, staggered 1e-11 on both sides; Algorithm 1 (iii),
+Algorithm 2's ConjGrad test, Sec. 3.2.2).  Then the FP32-refined form of the
+same increment against the same FP64 oracle fields: FP32 transforms and
+Krylov vectors, FP64 reductions, the FP64 Newton residual and the FP64
+residual of every Helmholtz refinement sweep.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import staggered  # noqa: E402
+from paper_2103_04770_amd import microstructure as ms  # noqa: E402
+
+TIGHT = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11, stagger_tol=1e-11, max_stagger=100)
+E11 = 2e-3  # plastic matrix, the non-local field active
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def c2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = ms.workload("spheres64_20")
+    S, J = w["shape"], w["nfields"]
+    say("oracle: 64^3, 20 spheres, E11 = %g from the virgin state (parity tolerances)" % E11)
+    st, sig, hom, stats = staggered.staggered_step(w["phase"], w["table"], J,
+                                                   staggered.initial_state(S, 3, J),
+                                                   ms.uniaxial_mixed(3, E11), **TIGHT)
+    say("  oracle", stats)
+    assert stats["converged"] and stats["inner_converged"]
+    return dict(w=w, st=st, sig=sig, hom=hom, stats=stats)
+
+
+def _gpu(c2, prec, tols):
+    from paper_2103_04770_amd import FP32_REFINED, FP64, Solver
+    w = c2["w"]
+    S, J = w["shape"], w["nfields"]
+    s = Solver(tuple(reversed(S)), prec=FP64 if prec == "fp64" else FP32_REFINED)
+    state = torch.zeros((6 + 7 + 2 * J,) + S, dtype=torch.float64, device="cuda")
+    sig = torch.empty((6,) + S, dtype=torch.float64, device="cuda")
+    d = s.staggered_step(torch.from_numpy(w["phase"]).cuda(), w["table"], J, state,
+                         ms.uniaxial_mixed(3, E11), sig, **tols)
+    torch.cuda.synchronize()
+    s.close()
+    say("  gpu", prec, {k: d[k] for k in ("stagger_iters", "newton_iters", "cg_iters",
+                                          "pcg_iters", "err", "inner_converged")})
+    return d, state.cpu().numpy(), sig.cpu().numpy()
+
+
+def test_c2_increment_fp64_matches_oracle_everywhere(c2):
+    d, st, sig = _gpu(c2, "fp64", TIGHT)
+    o = c2["st"]
+    J = c2["w"]["nfields"]
+    assert d["converged"] and d["inner_converged"]
+    assert d["stagger_iters"] == c2["stats"]["stagger_iters"]
+    errs = dict(eps=relerr(st[:6], o["eps"]), sigma=relerr(sig, c2["sig"]),
+                epsp=relerr(st[6:12], o["epsp"]), kappa=relerr(st[12], o["kappa"]),
+                abar=relerr(st[13 + J:], o["abar"]),
+                homog=float(np.abs(d["sigma_mean"] - c2["hom"]["sigma"]).max() /
+                            abs(c2["hom"]["sigma"][0])))
+    say("  fp64 vs oracle (max-norm relative):", {k: "%.1e" % v for k, v in errs.items()})
+    assert (o["kappa"] > 0).sum() > 1000 and o["abar"].max() > 0  # plastic, field active
+    for k, v in errs.items():
+        assert v <= 1e-10, k
+
+
+def test_c2_increment_fp32_refined_matches_oracle(c2):
+    """FP32-refined against the FP64 oracle at the same tight tolerances: the
+    FP64 outer loops (Newton residual, Helmholtz refinement sweeps, staggered
+    error) carry the fields to FP64 accuracy; homogenised stress within 1e-9,
+    every field within 1e-8 (relative L2)."""
+    d, st, sig = _gpu(c2, "fp32", TIGHT)
+    o = c2["st"]
+    J = c2["w"]["nfields"]
+    assert d["converged"] and d["inner_converged"]
+    homog = float(np.abs(d["sigma_mean"] - c2["hom"]["sigma"]).max() / abs(c2["hom"]["sigma"][0]))
+    errs = dict(eps=rel_l2(st[:6], o["eps"]), sigma=rel_l2(sig, c2["sig"]),
+                kappa=rel_l2(st[12], o["kappa"]), abar=rel_l2(st[13 + J:], o["abar"]))
+    say("  fp32-refined vs oracle: homog %.1e, rel L2" % homog,
+        {k: "%.1e" % v for k, v in errs.items()})
+    assert homog <= 1e-9
+    for k, v in errs.items():
+        assert v <= 1e-8, k

@@ -185,3 +185,51 @@ def test_zero_stiffness_is_a_breakdown():
     with pytest.raises(FFTGError) as e:
         mech(s, shape, phase, table, 1, np.ones((1,) + shape), tgt)
     assert e.value.code == -4
+
+
+def test_staggered_error_met_with_a_capped_inner_solve_is_not_converged():
+    """Algorithm 1 stops on ERR <= TOL, but the increment is only converged
+    when the inner solves of its last pass met their own tolerances
+    (Algorithm 2's ConjGrad test).  With one PCG iteration per Helmholtz solve
+    the staggered error falls below a loose tolerance while every PCG is cut
+    at maxit: FFTG_NOT_CONVERGED, inner_converged = 0 (forced from the host)."""
+    shape = (12, 12, 12)
+    say("capped inner PCG")
+    s = solver(shape)
+    phase = (np.random.default_rng(6).uniform(size=shape) < 0.3).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_elastic(ell=[1.0])]
+    state = dev(np.zeros((6 + 7 + 2,) + shape))
+    sig = torch.empty((6,) + shape, dtype=torch.float64, device="cuda")
+    ph = dev(phase, torch.uint8)
+    d = s.staggered_step(ph, table, 1, state, ms.uniaxial_mixed(3, 6e-3), sig, pcg_maxit=1,
+                         stagger_tol=5e-2, max_stagger=50)
+    say("  ", {k: d[k] for k in ("stagger_iters", "err", "pcg_iters", "inner_converged")})
+    assert d["err"] <= 5e-2
+    assert not d["inner_converged"] and not d["converged"]
+    # the same increment with uncapped solves converges
+    state.zero_()
+    d = s.staggered_step(ph, table, 1, state, ms.uniaxial_mixed(3, 6e-3), sig, stagger_tol=5e-2,
+                         max_stagger=50)
+    assert d["inner_converged"] and d["converged"]
+
+
+def test_phase_ids_and_damage_cap_are_validated():
+    """A phase id >= nphase anywhere in the phase array (checked on the device)
+    and a damage cap dmax >= 1 are FFTG_E_INVALID."""
+    from paper_2103_04770_amd import FFTGError
+    shape = (8, 8, 8)
+    say("phase ids, dmax")
+    s = solver(shape)
+    table = [ms.matrix_j2_damage(ell=[2.0]), ms.particle_elastic(ell=[1.0])]
+    phase = np.zeros(shape, np.uint8)
+    phase[7, 7, 7] = 2
+    with pytest.raises(FFTGError) as e:
+        mech(s, shape, phase, table, 1, np.zeros((1,) + shape), ms.uniaxial_mixed(3, 1e-3))
+    assert e.value.code == -1
+    phase[7, 7, 7] = 1
+    d, _, _ = mech(s, shape, phase, table, 1, np.zeros((1,) + shape), ms.uniaxial_mixed(3, 1e-3))
+    assert d["converged"]
+    with pytest.raises(FFTGError) as e:
+        mech(s, shape, phase, [dict(table[0], dmax=1.0), table[1]], 1, np.zeros((1,) + shape),
+             ms.uniaxial_mixed(3, 1e-3))
+    assert e.value.code == -1

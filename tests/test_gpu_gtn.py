@@ -109,7 +109,7 @@ def test_gtn_staggered_matches_oracle(shape):
     table = _table(fN=0.04, eN=0.02, sN=0.01)
     J = 2
     c = 6 if len(shape) == 3 else 3
-    tols = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11, stagger_tol=1e-10)
+    tols = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, stagger_tol=1e-12)
     s = solver(shape)
     st_o = staggered.initial_state(shape, len(shape), J)
     state = dev(np.zeros((c + 7 + 2 * J,) + shape))
@@ -118,19 +118,21 @@ def test_gtn_staggered_matches_oracle(shape):
     for e11 in (3e-3, 6e-3, 9e-3):
         tgt = ms.uniaxial_mixed(len(shape), e11)
         st_o, sig_o, hom_o, stats_o = staggered.staggered_step(phase, table, J, st_o, tgt,
-                                                               max_stagger=40, **tols)
-        d = s.staggered_step(ph, table, J, state, tgt, sig, max_stagger=40, **tols)
+                                                               max_stagger=80, **tols)
+        d = s.staggered_step(ph, table, J, state, tgt, sig, max_stagger=80, **tols)
         say("  e11", e11, "gpu", {k: d[k] for k in ("newton_iters", "cg_iters", "pcg_iters",
                                                     "stagger_iters", "err")}, "oracle", stats_o)
         assert d["converged"] and stats_o["converged"]
         h = host(state)
-        assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-9 * abs(hom_o["sigma"][0])
-        assert relerr(host(sig), sig_o) <= 1e-9
-        assert relerr(h[:c], st_o["eps"]) <= 1e-9
-        assert relerr(h[c:c + 6], st_o["epsp"]) <= 1e-8
-        assert relerr(h[c + 6], st_o["kappa"]) <= 1e-8
-        assert relerr(h[c + 7:c + 7 + J], st_o["hist"]) <= 1e-8
-        assert relerr(h[c + 7 + J:], st_o["abar"]) <= 1e-8
+        errs = dict(homog=float(np.abs(d["sigma_mean"] - hom_o["sigma"]).max() /
+                                abs(hom_o["sigma"][0])),
+                    sigma=relerr(host(sig), sig_o), eps=relerr(h[:c], st_o["eps"]),
+                    epsp=relerr(h[c:c + 6], st_o["epsp"]), e0=relerr(h[c + 6], st_o["kappa"]),
+                    porosity=relerr(h[c + 7:c + 7 + J], st_o["hist"]),
+                    abar=relerr(h[c + 7 + J:], st_o["abar"]))
+        say("  errors", {k: "%.1e" % v for k, v in errs.items()})
+        for k, v in errs.items():
+            assert v <= 1e-10, k
     assert st_o["hist"][0].max() > 0.01          # porosity grew
 
 

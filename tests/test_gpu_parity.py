@@ -50,6 +50,11 @@ def relerr(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+# Tolerances of the converged-solve parity cases, on both sides: the fixed
+# point is then reached to ~1e-12, so two correct solvers agree to 1e-10.
+TIGHT = dict(cg_tol=1e-13, pcg_tol=1e-13, newton_tol=1e-12, stagger_tol=1e-12)
+
+
 FFT_SHAPES = [(18, 12), (32, 32), (6, 64), (24, 12, 16), (8, 8, 8), (18, 24, 64), (4, 6, 96),
               (3, 9, 12), (1, 4, 8), (2, 128, 128), (128, 6, 16), (16, 256, 4), (6, 64, 256),
               (3, 32, 128), (48, 6, 96), (96, 4, 48), (96, 48)]
@@ -246,14 +251,13 @@ def test_staggered_disc2d_config():
     """The 32x32 plane-strain disc, one increment to E11 = 5e-3, one staggered pass."""
     w = ms.workload("disc2d_32")
     say("staggered disc2d_32")
-    tols = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11, stagger_tol=1e-10)
-    res, c, J = _run_staggered(w, 1, tols)
+    res, c, J = _run_staggered(w, 1, TIGHT)
     d, state, sig, st_o, sig_o, hom_o, stats_o = res[0]
     assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-10 * abs(hom_o["sigma"][0])
     assert relerr(sig, sig_o) <= 1e-10
     assert relerr(state[:c], st_o["eps"]) <= 1e-10
-    assert relerr(state[c + 7 + J:], st_o["abar"]) <= 1e-9
-    assert relerr(state[c + 6], st_o["kappa"]) <= 1e-9
+    assert relerr(state[c + 7 + J:], st_o["abar"]) <= 1e-10
+    assert relerr(state[c + 6], st_o["kappa"]) <= 1e-10
 
 
 def test_staggered_two_fields_3d():
@@ -263,14 +267,15 @@ def test_staggered_two_fields_3d():
     w["table"][0]["dC"], w["table"][0]["dR"] = 0.0005, 0.02
     w["table"][1]["dC"], w["table"][1]["dR"] = 5e-4, 5e-3
     say("staggered spheres_two_fields_16")
-    tols = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11, stagger_tol=1e-9)
     w["load"] = [ms.uniaxial_mixed(3, 3e-3), ms.uniaxial_mixed(3, 6e-3)]
-    res, c, J = _run_staggered(w, 30, tols, ninc=2)
+    res, c, J = _run_staggered(w, 60, TIGHT, ninc=2)
     for d, state, sig, st_o, sig_o, hom_o, stats_o in res:
-        assert d["stagger_iters"] == stats_o["stagger_iters"]
-        assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-9 * abs(hom_o["sigma"][0])
-        assert relerr(state[:c], st_o["eps"]) <= 1e-9
-        assert relerr(state[c + 7 + J:], st_o["abar"]) <= 1e-8
+        assert d["converged"] and stats_o["converged"]
+        assert abs(d["stagger_iters"] - stats_o["stagger_iters"]) <= 1
+        assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-10 * abs(hom_o["sigma"][0])
+        assert relerr(sig, sig_o) <= 1e-10
+        assert relerr(state[:c], st_o["eps"]) <= 1e-10
+        assert relerr(state[c + 7 + J:], st_o["abar"]) <= 1e-10
     assert res[-1][3]["abar"][1].max() > 5e-4  # the cracking field is active
 
 
@@ -314,7 +319,7 @@ def test_staggered_spectral_scheme_and_voxel_size(shape):
     table = [ms.matrix_j2_damage(ell=[1.0], dC=0.0005, dR=0.02), ms.particle_elastic(ell=[0.25])]
     nd = len(shape)
     c = 6 if nd == 3 else 3
-    tols = dict(cg_tol=1e-12, pcg_tol=1e-12, newton_tol=1e-11, stagger_tol=1e-10)
+    tols = TIGHT
     s = solver(shape, scheme=SPECTRAL, h=0.5)
     st_o = staggered.initial_state(shape, nd, 1)
     state = dev(np.zeros((c + 7 + 2,) + shape))
@@ -329,7 +334,7 @@ def test_staggered_spectral_scheme_and_voxel_size(shape):
             stats_o["cg_iters"])
         assert d["converged"] and stats_o["converged"]
         h = host(state)
-        assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-9 * abs(hom_o["sigma"][0])
-        assert relerr(h[:c], st_o["eps"]) <= 1e-9
-        assert relerr(h[c + 7 + 1:], st_o["abar"]) <= 1e-8
+        assert np.abs(d["sigma_mean"] - hom_o["sigma"]).max() <= 1e-10 * abs(hom_o["sigma"][0])
+        assert relerr(h[:c], st_o["eps"]) <= 1e-10
+        assert relerr(h[c + 7 + 1:], st_o["abar"]) <= 1e-10
     assert st_o["abar"].max() > table[0]["dC"]       # damage active

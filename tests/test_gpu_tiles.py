@@ -74,3 +74,37 @@ def test_results_do_not_depend_on_the_tile(fp32):
         assert np.array_equal(a, b) and np.array_equal(sa, sb)
         for k in ("cg_iters", "pcg_iters", "newton_iters", "stagger_iters"):
             assert da[k] == db[k]
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_results_do_not_depend_on_the_tile_128_lines(fp32):
+    """The fixed-length 128-point strided kernels (the benchmark's y and z
+    passes) at every tile budget code 0..3, on a grid with 128-point y and z
+    axes: one staggered increment with damage active, bitwise equal states,
+    stresses and iteration counts."""
+    from paper_2103_04770_amd import FP32_REFINED
+    shape = (128, 128, 16)
+    rng = np.random.default_rng(31)
+    phase = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    table = [ms.matrix_j2_damage(ell=[3.0, 0.03], dfield=0, dC=0.0005, dR=0.02),
+             ms.particle_cracking(ell=[0.06, 1.5], dfield=1)]
+    J = 2
+    kw = dict(prec=FP32_REFINED) if fp32 else {}
+    ph = torch.from_numpy(phase).cuda()
+    out = []
+    for shift in (0, 1, 2, 3):
+        say("tile code", shift, "fp32" if fp32 else "fp64", shape)
+        s = _solver(shape, shift=shift, **kw)
+        assert s.tile_config()[:2] == (shift, shift)
+        state = torch.zeros((6 + 7 + 2 * J,) + shape, dtype=torch.float64, device="cuda")
+        sig = torch.empty((6,) + shape, dtype=torch.float64, device="cuda")
+        d = s.staggered_step(ph, table, J, state, ms.uniaxial_mixed(3, 5e-3), sig, max_stagger=40)
+        torch.cuda.synchronize()
+        out.append((state.cpu().numpy(), sig.cpu().numpy(), d))
+        s.close()
+    a, sa, da = out[0]
+    assert da["stagger_iters"] > 1
+    for b, sb, db in out[1:]:
+        assert np.array_equal(a, b) and np.array_equal(sa, sb)
+        for k in ("cg_iters", "pcg_iters", "newton_iters", "stagger_iters"):
+            assert da[k] == db[k]
