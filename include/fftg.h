@@ -215,6 +215,29 @@ fftg_status staggered_step(fftg_handle* h, const unsigned char* phase, const fft
                            int max_stagger_iters, double* sigma_out, double* homog_out,
                            fftg_stats* stats);
 
+/* Allocation-free Algorithm 2, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same PCG as helmholtz_solve on an FP64 grid, with
+ * no handle: the transform tables, spectra, Krylov vectors, reduction partials
+ * and control block live in one static device array of 36 MiB that the
+ * library holds on each GPU it runs on until the process ends; the call makes
+ * no hipMalloc, hipFree or other device-memory allocation.  Its iterations are launched
+ * directly (no HIP graph is instantiated); the call returns after its outputs
+ * are valid.
+ *   grid      host: as for fftg_create; prec must be FFTG_FP64; at most
+ *             262144 voxels (64^3), else FFTG_E_UNSUPPORTED
+ *   hip_stream  the hipStream_t to enqueue on (NULL = the default stream)
+ *   alpha, ell2, ell2_ref, abar, opts, stats  as helmholtz_solve
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (each call writes all it reads): calls that overlap on one GPU, from
+ * several host threads or streams, race and must be serialised by the caller.
+ * Tile budgets are the fixed default (no autotuning).  Error text:
+ * helmholtz_noalloc_last_error() (per host thread). */
+fftg_status helmholtz_solve_noalloc(const fftg_grid* grid, void* hip_stream, const double* alpha,
+                                    const double* ell2, double ell2_ref, double* abar,
+                                    const fftg_krylov_opts* opts, fftg_stats* stats);
+const char* helmholtz_noalloc_last_error(void);
+
 /* ---- adjoints (implicit differentiation at the converged state) ---- */
 
 /* Adjoint of Algorithm 2.  In real space the operator is

@@ -111,6 +111,8 @@ def load_library():
         "fftg_apply_galerkin": [P, ct.POINTER(Macro), P, P],
         "fftg_apply_helmholtz": [P, P, P, P],
         "helmholtz_solve": [P, P, P, D, P, ct.POINTER(KrylovOpts), ct.POINTER(Stats)],
+        "helmholtz_solve_noalloc": [ct.POINTER(Grid), P, P, P, D, P, ct.POINTER(KrylovOpts),
+                                    ct.POINTER(Stats)],
         "fftg_solve": [P, P, ct.POINTER(Phase), I, I, P, P, ct.POINTER(Macro), P, P, P, P,
                        ct.POINTER(KrylovOpts), D, I, ct.POINTER(Stats)],
         "staggered_step": [P, P, ct.POINTER(Phase), I, I, P, ct.POINTER(Macro),
@@ -141,6 +143,8 @@ def load_library():
         f.restype = ct.c_int
     lib.fftg_last_error.argtypes = [P]
     lib.fftg_last_error.restype = ct.c_char_p
+    lib.helmholtz_noalloc_last_error.argtypes = []
+    lib.helmholtz_noalloc_last_error.restype = ct.c_char_p
     lib.fftg_profile.argtypes = [P, I, ct.POINTER(ct.c_double), ct.POINTER(ct.c_longlong)]
     lib.fftg_profile.restype = ct.c_int
     lib.fftg_tile_config.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(ct.c_double)]
@@ -196,6 +200,33 @@ def _ptr(t, dtype, numel=None, name="array"):
     if numel is not None and t.numel() != numel:
         raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
     return ct.c_void_p(t.data_ptr())
+
+
+def helmholtz_solve_noalloc(alpha, ell2, abar, h=1.0, scheme=ROTATED, tol=1e-8, maxit=1000,
+                            ell2_ref=-1.0, stream=None):
+    """Algorithm 2 through the allocation-free entry point (no handle; FP64;
+    at most 64^3 voxels).  alpha, ell2, abar: contiguous float64 CUDA tensors
+    of the grid's numpy shape (z, y, x) or (y, x); abar in = initial guess,
+    out = solution.  Returns the stats dict with "converged"."""
+    import torch
+    lib = load_library()
+    shape = tuple(reversed(alpha.shape))
+    nd = len(shape)
+    n = list(shape) + [1] * (3 - nd)
+    N = int(np.prod(n))
+    g = Grid(nd, (ct.c_int * 3)(*n), float(h), int(scheme), FP64)
+    st = torch.cuda.current_stream() if stream is None else stream
+    stats = Stats()
+    f64 = torch.float64
+    rc = lib.helmholtz_solve_noalloc(ct.byref(g), ct.c_void_p(st.cuda_stream),
+                                     _ptr(alpha, f64, N, "alpha"), _ptr(ell2, f64, N, "ell2"),
+                                     float(ell2_ref), _ptr(abar, f64, N, "abar"),
+                                     ct.byref(KrylovOpts(tol, maxit)), ct.byref(stats))
+    if rc < 0:
+        raise FFTGError(rc, lib.helmholtz_noalloc_last_error().decode())
+    d = stats.as_dict()
+    d["converged"] = rc == 0
+    return d
 
 
 class Solver:

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <cstdint>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -139,6 +140,9 @@ struct fftg_handle {
   int ghelm_next = 0;
   std::string err;
 
+  // Krylov loops launch their iterations directly instead of through HIP
+  // graphs (the allocation-free entry point: instantiating a graph allocates)
+  bool nograph = false;
   bool fp32() const { return prec == FFTG_FP32_REFINED; }
   size_t wsz() const { return fp32() ? sizeof(float) : sizeof(double); }
 };
@@ -717,7 +721,7 @@ KrylovCtl helm_krylov(fftg_handle* H, const T* ell2, double ell2_ref, double bb,
   k.done = (s2[1] <= k.tol2 || maxit <= 0) ? (s2[1] <= k.tol2 ? 1 : 2) : 0;
   write_ctl(H, k);
   HIPCHK(hipMemsetAsync(H->hp, 0, sizeof(cpx<T>) * g.Ns, H->st));
-  if (!H->prof) {
+  if (!H->prof && !H->nograph) {
     hipGraphExec_t ex = helm_graph<T>(H, ell2);
     while (!k.done) {
       HIPCHK(hipGraphLaunch(ex, H->st));
@@ -2302,6 +2306,167 @@ fftg_status fftg_drive(fftg_handle* H, const unsigned char* phase, const fftg_ph
   });
 }
 
+
+}  // extern "C"
+
+// ------------------------------------------------------------ allocation-free Helmholtz solve
+// Device memory of helmholtz_solve_noalloc: one static array per GPU, held
+// until the process ends.  Host code must never pass `scratch` itself to a
+// kernel or a copy (on the host it is only a stand-in for the symbol): it uses
+// the device address hipGetSymbolAddress returns for the current device.
+constexpr long long kNoallocMaxVoxels = 64LL * 64 * 64;
+constexpr size_t kNoallocBytes = (size_t)36 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+thread_local std::string g_noalloc_error;
+
+// device address of `scratch` on the current device, looked up once per device
+void* scratch_address() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Fail{FFTG_E_UNSUPPORTED, "device index above 63"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw HipError{std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// bump allocator over the scratch array (256-byte aligned slices)
+struct Carve {
+  char* base;
+  size_t off = 0, cap;
+  void* take(size_t bytes) {
+    const size_t b = (bytes + 255) & ~(size_t)255;
+    if (off + b > cap) throw Fail{FFTG_E_UNSUPPORTED, "helmholtz_solve_noalloc: scratch too small"};
+    void* p = base + off;
+    off += b;
+    return p;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+fftg_status helmholtz_solve_noalloc(const fftg_grid* grid, void* hip_stream, const double* alpha,
+                                    const double* ell2, double ell2_ref, double* abar,
+                                    const fftg_krylov_opts* opts, fftg_stats* stats) {
+  g_noalloc_error.clear();
+  auto fail = [](fftg_status c, const std::string& m) {
+    g_noalloc_error = m;
+    return c;
+  };
+  if (!grid || !alpha || !ell2 || !abar || !opts)
+    return fail(FFTG_E_INVALID, "helmholtz_solve_noalloc: null pointer");
+  if (grid->ndim != 2 && grid->ndim != 3)
+    return fail(FFTG_E_INVALID, "helmholtz_solve_noalloc: ndim must be 2 or 3");
+  if (grid->prec != FFTG_FP64)
+    return fail(FFTG_E_UNSUPPORTED, "helmholtz_solve_noalloc: FP64 grids only");
+  if (grid->scheme != FFTG_ROTATED && grid->scheme != FFTG_SPECTRAL)
+    return fail(FFTG_E_INVALID, "helmholtz_solve_noalloc: unknown derivative scheme");
+  const int n1 = grid->n[0], n2 = grid->n[1], n3 = grid->ndim == 3 ? grid->n[2] : 1;
+  if (n1 < 2 || n2 < 1 || n3 < 1 || !(grid->h > 0.0) ||
+      (grid->ndim == 2 && grid->n[2] != 1 && grid->n[2] != 0))
+    return fail(FFTG_E_INVALID, "helmholtz_solve_noalloc: bad grid size or voxel size");
+  const int nmax = grid->ndim == 3 ? 256 : 512;
+  if (!smooth23(n1) || !smooth23(n2) || !smooth23(n3) || n1 % 2 != 0 || n1 > nmax ||
+      n2 > nmax || n3 > nmax)
+    return fail(FFTG_E_UNSUPPORTED, "helmholtz_solve_noalloc: unsupported size (need N = "
+                                     "2^a 3^b, N1 even, N <= 256 in 3D, 512 in 2D)");
+  if ((long long)n1 * n2 * n3 > kNoallocMaxVoxels)
+    return fail(FFTG_E_UNSUPPORTED,
+                "helmholtz_solve_noalloc: more than 262144 voxels (64^3), the scratch limit");
+  // a handle on the stack whose workspace is carved from the scratch array;
+  // nothing it points to is freed (destroy() is never called on it)
+  fftg_handle hd;
+  fftg_handle* H = &hd;
+  KrylovCtl hctl_host{};
+  double hsums_host[64];
+  fftg_status rc = run_guarded(H, [&]() -> fftg_status {
+    Carve cv{static_cast<char*>(scratch_address()), 0, kNoallocBytes};
+    Geo& g = H->g;
+    g.ndim = grid->ndim;
+    g.n1 = n1;
+    g.n2 = n2;
+    g.n3 = n3;
+    g.n1h = n1 / 2 + 1;
+    g.N = (long long)n1 * n2 * n3;
+    g.Ns = (long long)g.n1h * n2 * n3;
+    H->c = grid->ndim == 3 ? 6 : 3;
+    H->h = grid->h;
+    H->scheme = grid->scheme;
+    H->prec = FFTG_FP64;
+    H->st = reinterpret_cast<hipStream_t>(hip_stream);
+    H->nograph = true;
+    H->hctl = &hctl_host;
+    H->hsums = hsums_host;
+    const int ns[3] = {n1, n2, n3};
+    std::vector<double> tw[3], pq[3], gq[3], cs[3];
+    for (int a = 0; a < 3; ++a) {
+      H->plan[a] = make_plan(ns[a]);
+      tw[a] = twiddles(ns[a]);
+      H->tw64[a] = static_cast<cpx<double>*>(cv.take(sizeof(double) * tw[a].size()));
+      HIPCHK(hipMemcpyAsync(H->tw64[a], tw[a].data(), sizeof(double) * tw[a].size(),
+                            hipMemcpyHostToDevice, H->st));
+      axis_tables(ns[a], a == 0, grid->h, grid->scheme, pq[a], gq[a], cs[a]);
+    }
+    std::vector<double> all;
+    int off = 0;
+    for (auto* tab : {pq, gq, cs}) {
+      int* dst = tab == pq ? H->S64.pq : tab == gq ? H->S64.gq : H->S64.cs;
+      for (int a = 0; a < 3; ++a) {
+        dst[a] = off;
+        all.insert(all.end(), tab[a].begin(), tab[a].end());
+        off += (int)tab[a].size();
+      }
+    }
+    H->sym64 = static_cast<double*>(cv.take(sizeof(double) * all.size()));
+    HIPCHK(hipMemcpyAsync(H->sym64, all.data(), sizeof(double) * all.size(),
+                          hipMemcpyHostToDevice, H->st));
+    H->S64.base = H->sym64;
+    const size_t ss = sizeof(cpx<double>) * (size_t)g.Ns;
+    H->hx = cv.take(ss);
+    H->hr = cv.take(ss);
+    H->hp = cv.take(ss);
+    H->hAp = cv.take(ss);
+    H->hb = cv.take(ss);
+    H->hw = cv.take(ss * g.ndim);
+    // reductions: at most one partial per outer-axis tile of the divergence
+    // pass (<= Ns), two sets of at most RED_BLOCKS for the pointwise kernels
+    H->npartials = (size_t)std::max<long long>(g.Ns, 2LL * fftg::RED_BLOCKS) + 64;
+    H->partials = static_cast<double*>(cv.take(sizeof(double) * H->npartials));
+    H->dsums = static_cast<double*>(cv.take(sizeof(double) * 64));
+    H->ctl = static_cast<KrylovCtl*>(cv.take(sizeof(KrylovCtl)));
+    int it = 0, status = 0;
+    double rel = 0.0;
+    auto t0 = std::chrono::steady_clock::now();
+    helmholtz_pcg64(H, alpha, ell2, ell2_ref, abar, opts->tol, opts->maxit, it, rel, status);
+    sync(H);
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->pcg_iters = it;
+      stats->relres = rel;
+      stats->t_ms[2] = wall_ms(t0);
+    }
+    if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
+    if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+    return status == 1 ? FFTG_OK : FFTG_NOT_CONVERGED;
+  });
+  if (rc < 0) g_noalloc_error = H->err;
+  return rc;
+}
+
+const char* helmholtz_noalloc_last_error(void) { return g_noalloc_error.c_str(); }
 
 fftg_status fftg_batch_step(fftg_batch_item* items, int n, int nworkers,
                             const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
