@@ -96,8 +96,11 @@ struct fftg_handle {
   // Helmholtz workspace (work precision), scalar half spectra + ndim gradient comps
   void *hx = nullptr, *hr = nullptr, *hp = nullptr, *hAp = nullptr, *hb = nullptr,
        *hw = nullptr;
+  int helm_cap = 0;       // systems the Helmholtz workspace holds (one per field)
   void* rtmp = nullptr;   // real scratch [max(c, 2)][N] in work precision
   void* ell2w = nullptr;  // work-precision ell2 [N]
+  cpx<double>* ref64 = nullptr;  // FP64 refinement workspace, 6 spectra per system
+  int ref64_cap = 0;
   // staggered workspace (FP64)
   int stJ = -1;
   double *eps_k = nullptr, *eps_prev = nullptr, *ab_k = nullptr, *ab_prev = nullptr,
@@ -317,6 +320,20 @@ void write_ctl(fftg_handle* H, const KrylovCtl& k) {
   *H->hctl = k;
   HIPCHK(hipMemcpyAsync(H->ctl, H->hctl, sizeof(KrylovCtl), hipMemcpyHostToDevice, H->st));
 }
+// the control blocks of n systems solved in lockstep; a profiled chunk books
+// the launches of the iterations the most advanced system ran
+void read_ctls(fftg_handle* H, int n, KrylovCtl* out, int before = -1) {
+  HIPCHK(hipMemcpyAsync(H->hctl, H->ctl, sizeof(KrylovCtl) * n, hipMemcpyDeviceToHost, H->st));
+  HIPCHK(hipStreamSynchronize(H->st));
+  int most = 0;
+  for (int s = 0; s < n; ++s) most = std::max(most, H->hctl[s].iters);
+  sync(H, before >= 0 ? most - before : INT_MAX);
+  for (int s = 0; s < n; ++s) out[s] = H->hctl[s];
+}
+void write_ctls(fftg_handle* H, int n, const KrylovCtl* k) {
+  for (int s = 0; s < n; ++s) H->hctl[s] = k[s];
+  HIPCHK(hipMemcpyAsync(H->ctl, H->hctl, sizeof(KrylovCtl) * n, hipMemcpyHostToDevice, H->st));
+}
 // finalise nred sums of partials [nred][nb] and read them back
 void read_sums(fftg_handle* H, int nb, int nred, double* out) {
   fftg::launch_fin_sums(H->partials, nb, nred, H->dsums, H->st);
@@ -393,16 +410,19 @@ int outer_axis(fftg_handle* H) { return H->g.ndim == 3 ? 2 : 1; }
 // y passes of the Helmholtz operator on its gradient buffer: the split form
 // (two fields to three and back, launch_h_y_split) where the outer passes
 // use it, the plain per-component passes otherwise.
+// nsys stacked systems: the gradient buffer is [comp][sys][Ns], so the plain
+// y passes transform ndim * nsys spectra.
 template <typename T>
-void helm_inner(fftg_handle* H, bool fwd, cpx<T>* w, const KrylovCtl* ctl, int kid) {
+void helm_inner(fftg_handle* H, bool fwd, cpx<T>* w, const KrylovCtl* ctl, int kid,
+                int nsys = 1) {
   const Geo& g = H->g;
   if (fftg::helm_split(g)) {
     KT t(H, kid);
-    fftg::launch_h_y_split<T>(H->plan[1], TW<T>(H, 1), g, SY<T>(H), w, fwd, ctl, H->st);
+    fftg::launch_h_y_split<T>(H->plan[1], TW<T>(H, 1), g, SY<T>(H), w, fwd, ctl, H->st, nsys);
   } else if (fwd) {
-    inner_fwd<T>(H, g.ndim, w, ctl, kid);
+    inner_fwd<T>(H, g.ndim * nsys, w, nsys == 1 ? ctl : nullptr, kid);
   } else {
-    inner_inv<T>(H, g.ndim, w, ctl, kid);
+    inner_inv<T>(H, g.ndim * nsys, w, nsys == 1 ? ctl : nullptr, kid);
   }
 }
 
@@ -622,9 +642,10 @@ void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double to
   status = k.done;
 }
 
-// One Helmholtz PCG iteration: 5 passes + 2 scalar kernels, all on H->st.
+// One Helmholtz PCG iteration of nsys stacked systems (one per non-local
+// field, each with its own scalars): 5 passes + 2 scalar kernels, all on H->st.
 template <typename T>
-void helm_iteration(fftg_handle* H, const T* ell2) {
+void helm_iteration(fftg_handle* H, const T* ell2, int nsys) {
   const Geo& g = H->g;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
@@ -632,270 +653,392 @@ void helm_iteration(fftg_handle* H, const T* ell2) {
   {
     KT t(H, K_HLM_OI);
     fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true, C<T>(H->hr),
-                              C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
+                              C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st, nsys);
   }
-  helm_inner<T>(H, false, C<T>(H->hw), H->ctl, K_HLM_YI);
+  helm_inner<T>(H, false, C<T>(H->hw), H->ctl, K_HLM_YI, nsys);
   {
     KT t(H, K_HLM_X);
     fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl,
-                                    H->ctl, H->st);
+                                    H->ctl, H->st, nsys);
   }
-  helm_inner<T>(H, true, C<T>(H->hw), H->ctl, K_HLM_YF);
+  helm_inner<T>(H, true, C<T>(H->hw), H->ctl, K_HLM_YF, nsys);
   int nb;
   {
     KT t(H, K_HLM_OF);
     nb = fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hp),
-                                   C<T>(H->hw), C<T>(H->hAp), H->partials, H->ctl, H->st);
+                                   C<T>(H->hw), C<T>(H->hAp), H->partials, H->ctl, H->st, nsys);
   }
   {
     KT t(H, K_SMALL);
-    fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
+    fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st, nsys);
   }
   int nr;
   {
     KT t(H, K_HLM_RES);
     nr = fftg::launch_h_resid<T>(g, SY<T>(H), false, C<T>(H->hr), C<T>(H->hb), C<T>(H->hAp),
-                                 H->partials, H->ctl, H->st);
+                                 H->partials, H->ctl, H->st, nsys);
   }
   {
     KT t(H, K_SMALL);
-    fftg::launch_fin_beta(H->partials, nr, 2, H->ctl, H->st);
+    fftg::launch_fin_beta(H->partials, nr, 2, H->ctl, H->st, nsys);
   }
 }
 
 template <typename T>
-hipGraphExec_t helm_graph(fftg_handle* H, const T* ell2) {
-  const unsigned long long key = (unsigned long long)(uintptr_t)ell2 | (H->fp32() ? 1ull : 0ull);
+hipGraphExec_t helm_graph(fftg_handle* H, const T* ell2, int nsys) {
+  // buffers are at least 256-byte aligned: the low bits carry the precision
+  // and the system count
+  const unsigned long long key = (unsigned long long)(uintptr_t)ell2 |
+                                 (H->fp32() ? 1ull : 0ull) | ((unsigned long long)nsys << 1);
   for (auto& sl : H->ghelm)
     if (sl.exec && sl.key == key) return sl.exec;
   auto& sl = H->ghelm[H->ghelm_next];
   H->ghelm_next = (H->ghelm_next + 1) % 4;
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
   sl.exec = nullptr;
-  sl.exec = capture(H, [&]() { helm_iteration<T>(H, ell2); });
+  sl.exec = capture(H, [&]() { helm_iteration<T>(H, ell2, nsys); });
   sl.key = key;
   return sl.exec;
 }
 
 // ------------------------------------------------------------ Helmholtz PCG
-// PCG of Algorithm 2 on the half spectrum in work precision T: b in H->hb
-// (weighted |b|^2 = bb), x0 in H->hx (x0_zero: x0 = 0, H->hx is cleared);
-// on return H->hx holds x.  Stops at ||r|| <= tol ||b||, maxit, a stall or a
-// breakdown (KrylovCtl::done).
+// Workspace for nsys stacked Helmholtz systems (scalar spectra [sys][Ns],
+// gradient buffer [comp][sys][Ns]).  Growing it drops the captured graphs,
+// which hold the old buffers.
+void alloc_helm(fftg_handle* H, int nsys = 1) {
+  if (H->hx && H->helm_cap >= nsys) return;
+  const Geo& g = H->g;
+  if (H->hx) {
+    HIPCHK(hipStreamSynchronize(H->st));
+    for (auto& sl : H->ghelm) {
+      if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+      sl.exec = nullptr;
+      sl.key = 0;
+    }
+    for (void** p : {&H->hx, &H->hr, &H->hp, &H->hAp, &H->hb, &H->hw}) dfree(*p);
+  }
+  const size_t cs = 2 * H->wsz() * (size_t)g.Ns * (size_t)nsys;
+  H->hx = dalloc(cs);
+  H->hr = dalloc(cs);
+  H->hp = dalloc(cs);
+  H->hAp = dalloc(cs);
+  H->hb = dalloc(cs);
+  H->hw = dalloc(cs * g.ndim);
+  if (!H->ell2w) H->ell2w = dalloc(H->wsz() * (size_t)g.N);
+  H->helm_cap = nsys;
+}
+
+// PCG of Algorithm 2 on the half spectrum in work precision T for nsys
+// stacked systems in lockstep, each with its own scalars and stop test:
+// b in H->hb (weighted |b_s|^2 = bb[s]), x0 in H->hx (x0_zero: x0 = 0, H->hx
+// is cleared); systems with bb[s] = 0 or tol[s] < 0 start as done.  On
+// return H->hx holds x and k[s] the final control block of system s.
 template <typename T>
-KrylovCtl helm_krylov(fftg_handle* H, const T* ell2, double ell2_ref, double bb, double tol,
-                      int maxit, bool x0_zero) {
+void helm_krylov(fftg_handle* H, const T* ell2, int nsys, const double* ell2_ref,
+                 const double* bb, const double* tol, const int* maxit, bool x0_zero,
+                 KrylovCtl* k) {
   const Geo& g = H->g;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
   const T scl = T(1.0 / (double)g.N);
-  KrylovCtl k{};
-  k.bb = bb;
-  k.tol2 = tol * tol * bb;
-  k.maxit = maxit;
-  k.window = std::is_same<T, float>::value ? kFp32StagnationWindow : 0;
-  k.ell2ref = ell2_ref;
-  write_ctl(H, k);
+  for (int q = 0; q < nsys; ++q) {
+    k[q] = KrylovCtl{};
+    k[q].bb = bb[q];
+    k[q].tol2 = tol[q] * tol[q] * bb[q];
+    k[q].maxit = maxit[q];
+    k[q].window = std::is_same<T, float>::value ? kFp32StagnationWindow : 0;
+    k[q].ell2ref = ell2_ref[q];
+  }
+  write_ctls(H, nsys, k);
   if (x0_zero) {
     // r = b - 0 (H->hx doubles as the zero operator output)
-    HIPCHK(hipMemsetAsync(H->hx, 0, sizeof(cpx<T>) * g.Ns, H->st));
+    HIPCHK(hipMemsetAsync(H->hx, 0, sizeof(cpx<T>) * g.Ns * nsys, H->st));
   } else {
     // r = b - L x0
     fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), false, C<T>(H->hr),
-                              C<T>(H->hx), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st);
-    helm_inner<T>(H, false, C<T>(H->hw), nullptr, K_HLM_YI);
+                              C<T>(H->hx), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st, nsys);
+    helm_inner<T>(H, false, C<T>(H->hw), nullptr, K_HLM_YI, nsys);
     fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, nullptr,
-                                    H->st);
-    helm_inner<T>(H, true, C<T>(H->hw), nullptr, K_HLM_YF);
+                                    H->st, nsys);
+    helm_inner<T>(H, true, C<T>(H->hw), nullptr, K_HLM_YF, nsys);
     fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hx),
-                              C<T>(H->hw), C<T>(H->hAp), nullptr, H->ctl, H->st);
+                              C<T>(H->hw), C<T>(H->hAp), nullptr, H->ctl, H->st, nsys);
   }
   const int nr0 = fftg::launch_h_resid<T>(g, SY<T>(H), true, C<T>(H->hr), C<T>(H->hb),
                                           x0_zero ? C<T>(H->hx) : C<T>(H->hAp), H->partials,
-                                          H->ctl, H->st);
-  double s2[2];
-  read_sums(H, nr0, 2, s2);
-  k.rz = s2[0];
-  k.rr = s2[1];
-  k.rrmin = s2[1];
-  k.done = (s2[1] <= k.tol2 || maxit <= 0) ? (s2[1] <= k.tol2 ? 1 : 2) : 0;
-  write_ctl(H, k);
-  HIPCHK(hipMemsetAsync(H->hp, 0, sizeof(cpx<T>) * g.Ns, H->st));
+                                          H->ctl, H->st, nsys);
+  double s2[2 * FFTG_MAX_FIELDS];
+  read_sums(H, nr0, 2 * nsys, s2);
+  bool all = true;
+  for (int q = 0; q < nsys; ++q) {
+    k[q].rz = s2[2 * q];
+    k[q].rr = s2[2 * q + 1];
+    k[q].rrmin = s2[2 * q + 1];
+    if (bb[q] == 0.0 || tol[q] < 0.0 || s2[2 * q + 1] <= k[q].tol2)
+      k[q].done = 1;
+    else if (maxit[q] <= 0)
+      k[q].done = 2;
+    all = all && k[q].done;
+  }
+  write_ctls(H, nsys, k);
+  HIPCHK(hipMemsetAsync(H->hp, 0, sizeof(cpx<T>) * g.Ns * nsys, H->st));
   if (!H->prof && !H->nograph) {
-    hipGraphExec_t ex = helm_graph<T>(H, ell2);
-    while (!k.done) {
+    hipGraphExec_t ex = helm_graph<T>(H, ell2, nsys);
+    while (!all) {
       HIPCHK(hipGraphLaunch(ex, H->st));
-      k = read_ctl(H);
+      read_ctls(H, nsys, k);
+      all = true;
+      for (int q = 0; q < nsys; ++q) all = all && k[q].done;
     }
   } else {
     int chunk = 2;
-    while (!k.done) {
-      const int before = k.iters;
+    while (!all) {
+      int before = 0;
+      for (int q = 0; q < nsys; ++q) before = std::max(before, k[q].iters);
       for (int it = 0; it < chunk; ++it) {
         H->kt_iter = it;
-        helm_iteration<T>(H, ell2);
+        helm_iteration<T>(H, ell2, nsys);
       }
       H->kt_iter = -1;
       check_launch();
-      k = read_ctl(H, before);
+      read_ctls(H, nsys, k, H->prof ? before : -1);
+      all = true;
+      for (int q = 0; q < nsys; ++q) all = all && k[q].done;
       if (chunk < 16) chunk *= 2;
     }
   }
-  fftg::launch_xfinal<T>(C<T>(H->hx), C<T>(H->hp), g.Ns, H->ctl, H->st);
-  check_launch();
-  return k;
-}
-
-// preconditioner length^2: the given one, else the volume mean of ell2
-template <typename T>
-double ell2_reference(fftg_handle* H, const T* ell2, double ell2_ref) {
-  if (ell2_ref > 0.0) return ell2_ref;
-  double s;
-  read_sums(H, fftg::launch_sum_ell2<T>(H->g.N, ell2, H->partials, H->st), 1, &s);
-  return s / (double)H->g.N;
-}
-
-// FP64 handles: solves L abar = alpha for a scalar field (alpha, abar FP64
-// [N], abar in = x0), the whole PCG in FP64.
-void helmholtz_pcg64(fftg_handle* H, const double* alpha, const double* ell2, double ell2_ref,
-                     double* abar, double tol, int maxit, int& iters, double& relres,
-                     int& status) {
-  const Geo& g = H->g;
-  fwd3<double>(H, 1, alpha, C<double>(H->hb));
-  fftg::launch_hermitize<double>(g, 1, C<double>(H->hb), H->st);
-  double bb;
-  read_sums(H, fftg::launch_wnorm2<double>(g, 1, C<double>(H->hb), H->partials, H->st), 1, &bb);
-  if (bb == 0.0) {
-    HIPCHK(hipMemsetAsync(abar, 0, sizeof(double) * g.N, H->st));
-    iters = 0;
-    relres = 0.0;
-    status = 1;
-    return;
-  }
-  ell2_ref = ell2_reference<double>(H, ell2, ell2_ref);
-  fwd3<double>(H, 1, abar, C<double>(H->hx));
-  const KrylovCtl k = helm_krylov<double>(H, ell2, ell2_ref, bb, tol, maxit, false);
-  inv3<double, double>(H, 1, C<double>(H->hx), abar, 1.0 / (double)g.N, false);
+  fftg::launch_xfinal<T>(C<T>(H->hx), C<T>(H->hp), g.Ns, H->ctl, H->st, nsys);
   check_launch();
   if (verbose())
-    std::fprintf(stderr, "[fftg] pcg iters %d status %d rr/bb %.3e ell2ref %.4g\n", k.iters,
-                 k.done, k.rr / bb, ell2_ref);
-  iters = k.iters;
-  relres = std::sqrt(k.rr / bb);
-  status = k.done;
+    for (int q = 0; q < nsys; ++q)
+      std::fprintf(stderr, "[fftg]   %s pcg system %d/%d: bb %.3e tol %.1e iters %d done %d "
+                   "rr/bb %.3e pAp %.3e\n", std::is_same<T, float>::value ? "fp32" : "fp64", q,
+                   nsys, bb[q], tol[q], k[q].iters, k[q].done, bb[q] > 0 ? k[q].rr / bb[q] : 0.0,
+                   k[q].pAp);
 }
 
-// FP64 application of the Helmholtz operator on the half spectrum, Ap = L x,
-// through the same fused passes as the PCG (w: three gradient fields).
+// preconditioner length^2 of each system: the given one, else the volume
+// mean of its ell2 [sys][N]
+template <typename T>
+void ell2_reference(fftg_handle* H, const T* ell2, double ell2_ref, int nsys, double* out) {
+  if (ell2_ref > 0.0) {
+    for (int q = 0; q < nsys; ++q) out[q] = ell2_ref;
+    return;
+  }
+  read_sums(H, fftg::launch_sum_ell2<T>(H->g.N, ell2, H->partials, H->st, nsys), nsys, out);
+  for (int q = 0; q < nsys; ++q) out[q] /= (double)H->g.N;
+}
+
+// Transforms of nsys stacked scalar fields, one field at a time: the x pass
+// transforms two real lines as one complex line, which would leave rounding
+// of one field's magnitude in the other.
+void fwd_fields(fftg_handle* H, int nsys, const double* in, cpx<double>* out) {
+  for (int q = 0; q < nsys; ++q) fwd3<double>(H, 1, in + q * H->g.N, out + q * H->g.Ns);
+}
+void inv_fields(fftg_handle* H, int nsys, cpx<double>* in, double* out) {
+  for (int q = 0; q < nsys; ++q)
+    inv3<double, double>(H, 1, in + q * H->g.Ns, out + q * H->g.N, 1.0 / (double)H->g.N, false);
+}
+
+// Outcome of one Helmholtz system: PCG iterations, final relative residual,
+// status (KrylovCtl::done codes).
+struct HelmOut {
+  int iters = 0;
+  double relres = 0.0;
+  int status = 0;
+};
+
+// FP64 handles: solves L abar_s = alpha_s for nsys stacked fields (alpha,
+// ell2, abar [sys][N] FP64; abar in = x0), the whole PCG in FP64.
+void helmholtz_pcg64(fftg_handle* H, const double* alpha, const double* ell2, double ell2_ref,
+                     double* abar, double tol, int maxit, int nsys, HelmOut* out) {
+  const Geo& g = H->g;
+  fwd_fields(H, nsys, alpha, C<double>(H->hb));
+  fftg::launch_hermitize<double>(g, nsys, C<double>(H->hb), H->st);
+  double bb[FFTG_MAX_FIELDS], ref[FFTG_MAX_FIELDS], tols[FFTG_MAX_FIELDS];
+  int mits[FFTG_MAX_FIELDS];
+  read_sums(H, fftg::launch_wnorm2<double>(g, 1, C<double>(H->hb), H->partials, H->st, nsys),
+            nsys, bb);
+  ell2_reference<double>(H, ell2, ell2_ref, nsys, ref);
+  fwd_fields(H, nsys, abar, C<double>(H->hx));
+  for (int q = 0; q < nsys; ++q) {
+    tols[q] = tol;
+    mits[q] = maxit;
+    // a zero source has the zero solution
+    if (bb[q] == 0.0)
+      HIPCHK(hipMemsetAsync(C<double>(H->hx) + q * g.Ns, 0, sizeof(cpx<double>) * g.Ns, H->st));
+  }
+  KrylovCtl k[FFTG_MAX_FIELDS];
+  helm_krylov<double>(H, ell2, nsys, ref, bb, tols, mits, false, k);
+  inv_fields(H, nsys, C<double>(H->hx), abar);
+  check_launch();
+  for (int q = 0; q < nsys; ++q) {
+    if (verbose())
+      std::fprintf(stderr, "[fftg] pcg field %d iters %d status %d rr/bb %.3e ell2ref %.4g\n", q,
+                   k[q].iters, k[q].done, bb[q] > 0 ? k[q].rr / bb[q] : 0.0, ref[q]);
+    out[q].iters = k[q].iters;
+    out[q].relres = bb[q] > 0 ? std::sqrt(k[q].rr / bb[q]) : 0.0;
+    out[q].status = k[q].done;
+  }
+}
+
+// FP64 application of the Helmholtz operator on nsys stacked half spectra,
+// Ap = L x, through the same fused passes as the PCG (w: the gradient buffer,
+// [comp][sys][Ns]; ell2 [sys][N]).
 void helm_apply64(fftg_handle* H, const cpx<double>* x, cpx<double>* w, cpx<double>* Ap,
-                  const double* ell2) {
+                  const double* ell2, int nsys) {
   const Geo& g = H->g;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
   cpx<double>* xm = const_cast<cpx<double>*>(x);  // read only (update = false)
   fftg::launch_h_dir_inv<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64, false, nullptr,
-                                 xm, xm, w, nullptr, H->st);
-  helm_inner<double>(H, false, w, nullptr, K_HLM_YI);
+                                 xm, xm, w, nullptr, H->st, nsys);
+  helm_inner<double>(H, false, w, nullptr, K_HLM_YI, nsys);
   fftg::launch_x_fused_helm<double, double>(H->plan[0], TW<double>(H, 0), g, w, ell2,
-                                            1.0 / (double)g.N, nullptr, H->st);
-  helm_inner<double>(H, true, w, nullptr, K_HLM_YF);
+                                            1.0 / (double)g.N, nullptr, H->st, nsys);
+  helm_inner<double>(H, true, w, nullptr, K_HLM_YF, nsys);
   fftg::launch_h_div_fwd<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64, x, w, Ap,
-                                 nullptr, nullptr, H->st);
+                                 nullptr, nullptr, H->st, nsys);
 }
 
 // Largest number of FP64 refinement sweeps of one FP32-refined Helmholtz solve.
 constexpr int kHelmSweeps = 30;
 
-// FP32-refined handles: iterative refinement of Algorithm 2 (Sec. 3.2.3).
-// x and b live in FP64 on the half spectrum; each sweep forms the FP64
-// residual r = b - L x with the FP64 operator (FP64 ell2), solves L d = r
-// with the FP32 PCG (b rounded to FP32, d0 = 0), and adds d to x in FP64.
-// It stops when the FP64 residual meets ||r|| <= tol ||b|| (status 1), when
-// the FP32 iterations reach maxit (2), on a breakdown (3, 4), or when a sweep
-// no longer halves the FP64 residual (5: the attainable accuracy is reached).
+// FP32-refined handles: iterative refinement of Algorithm 2 (Sec. 3.2.3) for
+// nsys stacked fields in lockstep.  x and b live in FP64 on the half
+// spectrum; each sweep forms the FP64 residual r = b - L x with the FP64
+// operator (FP64 ell2), solves L d = r with the FP32 PCG (b rounded to FP32,
+// d0 = 0), and adds d to x in FP64.  A field stops when its FP64 residual
+// meets ||r|| <= tol ||b|| (status 1), when its FP32 iterations reach maxit
+// (2), on a breakdown (3, 4), or when a sweep no longer halves its FP64
+// residual (5: the attainable accuracy is reached); the others go on.
 void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32,
                        const double* ell2_64, double ell2_ref, double* abar, double tol,
-                       int maxit, int& iters, double& relres, int& status) {
+                       int maxit, int nsys, HelmOut* out) {
   const Geo& g = H->g;
   const long long Ns = g.Ns;
-  cpx<double>* S = H->spec64;  // [0] b, [1] x, [2..4] gradient fields, [5] L x
-  cpx<double>* b = S;
-  cpx<double>* x = S + Ns;
-  cpx<double>* w = S + 2 * Ns;
-  cpx<double>* Ax = S + 5 * Ns;
-  fwd3<double>(H, 1, alpha, b);
-  fftg::launch_hermitize<double>(g, 1, b, H->st);
-  double bb;
-  read_sums(H, fftg::launch_wnorm2<double>(g, 1, b, H->partials, H->st), 1, &bb);
-  iters = 0;
-  if (bb == 0.0) {
-    HIPCHK(hipMemsetAsync(abar, 0, sizeof(double) * g.N, H->st));
-    relres = 0.0;
-    status = 1;
-    return;
+  cpx<double>* S = H->spec64;
+  if (nsys > 1) {
+    if (H->ref64_cap < nsys) {
+      dfree((void*&)H->ref64);
+      H->ref64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * 6 * (size_t)nsys * Ns);
+      H->ref64_cap = nsys;
+    }
+    S = H->ref64;
   }
-  ell2_ref = ell2_reference<float>(H, ell2_32, ell2_ref);
-  fwd3<double>(H, 1, abar, x);
-  fftg::launch_hermitize<double>(g, 1, x, H->st);
-  double rr = HUGE_VAL, rr_prev = HUGE_VAL;
-  status = 0;
-  for (int sweep = 0;; ++sweep) {
-    helm_apply64(H, x, w, Ax, ell2_64);
-    read_sums(H, fftg::launch_h_refine_resid(g, b, Ax, C<float>(H->hb), H->partials, H->st), 1,
-              &rr);
-    if (!std::isfinite(rr)) throw Fail{FFTG_E_NONFINITE, "non-finite Helmholtz residual"};
-    if (rr <= tol * tol * bb) {
-      status = 1;
-      break;
+  // b [sys], x [sys], gradient fields [3][sys], L x [sys]
+  cpx<double>* b = S;
+  cpx<double>* x = S + nsys * Ns;
+  cpx<double>* w = S + 2 * nsys * Ns;
+  cpx<double>* Ax = S + 5 * nsys * Ns;
+  fwd_fields(H, nsys, alpha, b);
+  fftg::launch_hermitize<double>(g, nsys, b, H->st);
+  double bb[FFTG_MAX_FIELDS], ref[FFTG_MAX_FIELDS], rr[FFTG_MAX_FIELDS],
+      rr_prev[FFTG_MAX_FIELDS], tin[FFTG_MAX_FIELDS];
+  int mits[FFTG_MAX_FIELDS];
+  read_sums(H, fftg::launch_wnorm2<double>(g, 1, b, H->partials, H->st, nsys), nsys, bb);
+  ell2_reference<float>(H, ell2_32, ell2_ref, nsys, ref);
+  fwd_fields(H, nsys, abar, x);
+  fftg::launch_hermitize<double>(g, nsys, x, H->st);
+  int active = 0;
+  for (int q = 0; q < nsys; ++q) {
+    out[q] = HelmOut{};
+    rr[q] = 0.0;
+    rr_prev[q] = HUGE_VAL;
+    if (bb[q] == 0.0) {
+      // a zero source has the zero solution
+      HIPCHK(hipMemsetAsync(x + q * Ns, 0, sizeof(cpx<double>) * Ns, H->st));
+      out[q].status = 1;
+    } else {
+      ++active;
     }
-    if (sweep > 0 && !(rr < 0.25 * rr_prev)) {
-      status = 5;
-      break;
+  }
+  for (int sweep = 0; active > 0; ++sweep) {
+    helm_apply64(H, x, w, Ax, ell2_64, nsys);
+    read_sums(H, fftg::launch_h_refine_resid(g, b, Ax, C<float>(H->hb), H->partials, H->st, nsys),
+              nsys, rr);
+    for (int q = 0; q < nsys; ++q) {
+      tin[q] = -1.0;  // no correction for this field
+      mits[q] = 0;
+      if (out[q].status != 0) continue;
+      if (!std::isfinite(rr[q])) throw Fail{FFTG_E_NONFINITE, "non-finite Helmholtz residual"};
+      if (rr[q] <= tol * tol * bb[q])
+        out[q].status = 1;
+      else if (sweep > 0 && !(rr[q] < 0.25 * rr_prev[q]))
+        out[q].status = 5;
+      else if (out[q].iters >= maxit || sweep >= kHelmSweeps)
+        out[q].status = 2;
+      if (out[q].status != 0) {
+        --active;
+        continue;
+      }
+      rr_prev[q] = rr[q];
+      // the correction only has to bring ||r|| below tol ||b|| (with a
+      // margin); FP32 vectors do not resolve more than ~1e-5 of their
+      // right-hand side
+      tin[q] = std::min(0.5, std::max(kFp32KrylovFloor, 0.5 * tol * std::sqrt(bb[q] / rr[q])));
+      mits[q] = maxit - out[q].iters;
     }
-    if (iters >= maxit || sweep >= kHelmSweeps) {
-      status = 2;
-      break;
+    if (active == 0) break;
+    KrylovCtl k[FFTG_MAX_FIELDS];
+    helm_krylov<float>(H, ell2_32, nsys, ref, rr, tin, mits, true, k);
+    for (int q = 0; q < nsys; ++q) {
+      if (tin[q] < 0.0) continue;
+      out[q].iters += k[q].iters;
+      if (k[q].done == 3 || k[q].done == 4) {
+        out[q].status = k[q].done;
+        --active;
+      }
     }
-    rr_prev = rr;
-    // the correction only has to bring ||r|| below tol ||b|| (with a margin);
-    // FP32 vectors do not resolve more than ~1e-5 of their right-hand side
-    const double tin = std::max(kFp32KrylovFloor, 0.5 * tol * std::sqrt(bb / rr));
-    const KrylovCtl k =
-        helm_krylov<float>(H, ell2_32, ell2_ref, rr, std::min(tin, 0.5), maxit - iters, true);
-    iters += k.iters;
-    if (k.done == 3) {
-      status = 3;
-      break;
-    }
-    if (k.done == 4) {
-      status = 4;
-      break;
-    }
-    fftg::launch_acc_wide<float>(2 * Ns, reinterpret_cast<const float*>(H->hx),
+    fftg::launch_acc_wide<float>(2 * Ns * nsys, reinterpret_cast<const float*>(H->hx),
                                  reinterpret_cast<double*>(x), H->st);
   }
-  inv3<double, double>(H, 1, x, abar, 1.0 / (double)g.N, false);
+  inv_fields(H, nsys, x, abar);
   check_launch();
-  if (verbose())
-    std::fprintf(stderr, "[fftg] refined pcg iters %d status %d rr/bb %.3e ell2ref %.4g\n",
-                 iters, status, rr / bb, ell2_ref);
-  relres = std::sqrt(rr / bb);
+  for (int q = 0; q < nsys; ++q) {
+    if (verbose())
+      std::fprintf(stderr, "[fftg] refined pcg field %d iters %d status %d rr/bb %.3e ell2ref %.4g\n",
+                   q, out[q].iters, out[q].status, bb[q] > 0 ? rr[q] / bb[q] : 0.0, ref[q]);
+    out[q].relres = bb[q] > 0 ? std::sqrt(rr[q] / bb[q]) : 0.0;
+  }
 }
 
-// Algorithm 2 on the handle's precision: ell2w is the work-precision ell2
-// (FP32 on FP32-refined handles), ell2_64 the FP64 one (read by the FP64
-// residuals of the refinement; equal to ell2w on FP64 handles).
+// Algorithm 2 for nsys stacked fields on the handle's precision: ell2w is
+// the work-precision ell2 [sys][N] (FP32 on FP32-refined handles), ell2_64
+// the FP64 one (read by the FP64 residuals of the refinement; equal to ell2w
+// on FP64 handles).
 void helm_solve(fftg_handle* H, const double* alpha, const void* ell2w, const double* ell2_64,
-                double ell2_ref, double* abar, double tol, int maxit, int& iters, double& relres,
-                int& status) {
+                double ell2_ref, double* abar, double tol, int maxit, int nsys, HelmOut* out) {
+  if (nsys < 1 || nsys > FFTG_MAX_FIELDS) throw Fail{FFTG_E_INVALID, "1 to 4 Helmholtz fields"};
+  alloc_helm(H, nsys);
   if (H->fp32())
     helmholtz_refined(H, alpha, reinterpret_cast<const float*>(ell2w), ell2_64, ell2_ref, abar,
-                      tol, maxit, iters, relres, status);
+                      tol, maxit, nsys, out);
   else
-    helmholtz_pcg64(H, alpha, ell2_64, ell2_ref, abar, tol, maxit, iters, relres, status);
+    helmholtz_pcg64(H, alpha, ell2_64, ell2_ref, abar, tol, maxit, nsys, out);
 }
 
 // ------------------------------------------------------------ mechanics
+// out (=|+=) F^-1(x) for the Galerkin CG solution x in H->kx.  With FP32
+// Krylov vectors the solution is widened to FP64, projected again with the
+// FP64 G* (its zero frequency: the mask) and transformed back in FP64: the
+// FP32 iteration and an FP32 inverse leave rounding outside the compatible
+// space range(G*) (~1e-7 of the correction), which the FP64 Newton residual
+// G*(sigma - Sbar) cannot see and so would never remove from the strain.
+template <typename T>
+void galerkin_solution(fftg_handle* H, const unsigned char* mask, double* out, bool acc) {
+  const Geo& g = H->g;
+  const int c = H->c;
+  if (std::is_same<T, float>::value) {
+    fftg::launch_convert<float, double>(2LL * c * g.Ns, reinterpret_cast<const float*>(H->kx),
+                                        reinterpret_cast<double*>(H->spec64), H->st);
+    fftg::launch_project<double>(g, c, H->S64, mask, H->spec64, H->st);
+    inv3<double, double>(H, c, H->spec64, out, 1.0 / (double)g.N, acc);
+  } else {
+    inv3<T, double>(H, c, C<T>(H->kx), out, T(1.0 / (double)g.N), acc);
+  }
+}
+
 struct MechOut {
   int newton = 0, cg = 0;
   double relres = 0.0;
@@ -989,7 +1132,7 @@ MechOut mechanics(fftg_handle* H, const unsigned char* phase, const MatTable& ta
     if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Galerkin CG breakdown (p.Ap <= 0)"};
     if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Galerkin CG"};
     o.cg += it;
-    inv3<T, double>(H, c, C<T>(H->kx), eps, T(1.0 / (double)g.N), true);
+    galerkin_solution<T>(H, tgt->mask, eps, true);
     check_launch();
     sync(H);
     o.t_cg += wall_ms(t0);
@@ -1020,19 +1163,6 @@ const void* ell2w_of(fftg_handle* H, int j) {
 }
 const double* ell2d_of(fftg_handle* H, int j) {
   return (H->fp32() ? H->ell2j64 : reinterpret_cast<const double*>(H->ell2j)) + (long long)j * H->g.N;
-}
-
-void alloc_helm(fftg_handle* H) {
-  if (H->hx) return;
-  const Geo& g = H->g;
-  const size_t cs = 2 * H->wsz() * (size_t)g.Ns;
-  H->hx = dalloc(cs);
-  H->hr = dalloc(cs);
-  H->hp = dalloc(cs);
-  H->hAp = dalloc(cs);
-  H->hb = dalloc(cs);
-  H->hw = dalloc(cs * g.ndim);
-  H->ell2w = dalloc(H->wsz() * (size_t)g.N);
 }
 
 void alloc_stagger(fftg_handle* H, int J) {
@@ -1088,6 +1218,7 @@ void destroy(fftg_handle* H) {
   dfree(H->hw);
   dfree(H->rtmp);
   dfree(H->ell2w);
+  dfree((void*&)H->ref64);
   dfree((void*&)H->eps_k);
   dfree((void*&)H->eps_prev);
   dfree((void*&)H->ab_k);
@@ -1187,7 +1318,7 @@ int mech_adjoint(fftg_handle* H, const unsigned char* phase, const MatTable& tab
   galerkin_cg<T>(H, tgt->mask, s2[0], cgtol, cg->maxit, it, status);
   if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Galerkin CG breakdown (p.Ap <= 0)"};
   if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Galerkin CG"};
-  inv3<T, double>(H, c, C<T>(H->kx), mu, T(1.0 / (double)g.N), false);
+  galerkin_solution<T>(H, tgt->mask, mu, false);
   if (J > 0) fftg::launch_adj_damage(tab, g.N, c, J, phase, D, H->sig_k, mu, gsig, dD, H->st);
   check_launch();
   sync(H);
@@ -1254,16 +1385,18 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
     if (J > 0)
       HIPCHK(hipMemcpyAsync(H->ab_prev, H->ab_k, sizeof(double) * J * N,
                             hipMemcpyDeviceToDevice, H->st));
-    for (int j = 0; j < J; ++j) {
-      int it = 0, status = 0;
-      double rel = 0.0;
-      helm_solve(H, H->alph + j * N, ell2w_of(H, j), ell2d_of(H, j), -1.0, H->ab_k + j * N,
-                 pcg->tol, pcg->maxit, it, rel, status);
-      if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
-      if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
-      // maxit (2) or a stall at the rounding floor (5): not at tolerance
-      out.inner_ok = out.inner_ok && status == 1;
-      acc.pcg_iters += it;
+    if (J > 0) {
+      // every field's Helmholtz solve (Algorithm 1 (ii)) at once, in lockstep
+      HelmOut ho[FFTG_MAX_FIELDS];
+      helm_solve(H, H->alph, ell2w_of(H, 0), ell2d_of(H, 0), -1.0, H->ab_k, pcg->tol,
+                 pcg->maxit, J, ho);
+      for (int j = 0; j < J; ++j) {
+        if (ho[j].status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
+        if (ho[j].status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+        // maxit (2) or a stall at the rounding floor (5): not at tolerance
+        out.inner_ok = out.inner_ok && ho[j].status == 1;
+        acc.pcg_iters += ho[j].iters;
+      }
     }
     sync(H);
     acc.t_ms[2] += wall_ms(th);
@@ -1416,17 +1549,17 @@ AdjOut stag_adjoint_core(fftg_handle* H, const unsigned char* phase, const MatTa
     acc.newton_iters += 1;
   };
   auto helm = [&](const double* src, double* x) {
+    // every field at once, in lockstep
+    HelmOut ho[FFTG_MAX_FIELDS];
+    helm_solve(H, src, ell2w_of(H, 0), ell2d_of(H, 0), -1.0, x, pcg->tol, pcg->maxit, J, ho);
     for (int j = 0; j < J; ++j) {
-      int it = 0, st = 0;
-      double rel = 0.0;
-      helm_solve(H, src + j * N, ell2w_of(H, j), ell2d_of(H, j), -1.0, x + j * N, pcg->tol,
-                 pcg->maxit, it, rel, st);
-      if (st == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
-      if (st == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
-      out.inner_capped = out.inner_capped || st == 2 || st == 5;
-      acc.pcg_iters += it;
+      if (ho[j].status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
+      if (ho[j].status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
+      out.inner_capped = out.inner_capped || ho[j].status == 2 || ho[j].status == 5;
+      acc.pcg_iters += ho[j].iters;
     }
   };
+
   // hv = D' ((mu0 - g_sig) : sigma_eff + g_D) + g_abar, mu0 = A^-1 G*(g_eps + K g_sig)
   if (g_eps)
     HIPCHK(hipMemcpyAsync(rhs, g_eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
@@ -1593,12 +1726,17 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
     for (int a = 1; a < 3; ++a) {
       const long long nl = (long long)H->c * g.Ns / std::max(1, ns[a]);
       maxb = std::max(maxb, 2 * (nl + 1));
+      // the Helmholtz passes of up to FFTG_MAX_FIELDS lockstep systems
+      maxb = std::max(maxb, (long long)FFTG_MAX_FIELDS * (g.Ns / std::max(1, ns[a]) + 1));
     }
     H->npartials = (size_t)maxb;
     H->partials = (double*)dalloc(sizeof(double) * H->npartials);
     H->dsums = (double*)dalloc(sizeof(double) * 64);
-    H->ctl = (KrylovCtl*)dalloc(sizeof(KrylovCtl));
-    HIPCHK(hipHostMalloc((void**)&H->hctl, sizeof(KrylovCtl), hipHostMallocDefault));
+    // one Krylov control block per system of a lockstep solve (Helmholtz:
+    // one per non-local field)
+    H->ctl = (KrylovCtl*)dalloc(sizeof(KrylovCtl) * FFTG_MAX_FIELDS);
+    HIPCHK(hipHostMalloc((void**)&H->hctl, sizeof(KrylovCtl) * FFTG_MAX_FIELDS,
+                         hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * 64, hipHostMallocDefault));
     for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
@@ -1921,8 +2059,12 @@ fftg_status helmholtz_solve(fftg_handle* H, const double* alpha, const double* e
     double rel = 0.0;
     if (H->fp32())
       fftg::launch_convert<double, float>(H->g.N, ell2, reinterpret_cast<float*>(H->ell2w), H->st);
+    HelmOut ho;
     helm_solve(H, alpha, H->fp32() ? H->ell2w : ell2, ell2, ell2_ref, abar, opts->tol,
-               opts->maxit, it, rel, status);
+               opts->maxit, 1, &ho);
+    it = ho.iters;
+    rel = ho.relres;
+    status = ho.status;
     sync(H);
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
@@ -1949,8 +2091,12 @@ fftg_status helmholtz_adjoint(fftg_handle* H, const double* ell2, double ell2_re
     double rel = 0.0;
     if (H->fp32())
       fftg::launch_convert<double, float>(H->g.N, ell2, reinterpret_cast<float*>(H->ell2w), H->st);
+    HelmOut ho;
     helm_solve(H, gbar, H->fp32() ? H->ell2w : ell2, ell2, ell2_ref, dalpha, opts->tol,
-               opts->maxit, it, rel, status);
+               opts->maxit, 1, &ho);
+    it = ho.iters;
+    rel = ho.relres;
+    status = ho.status;
     if (status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
     if (status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
     grad_dot(H, dalpha, abar, dell2);
@@ -2450,7 +2596,11 @@ fftg_status helmholtz_solve_noalloc(const fftg_grid* grid, void* hip_stream, con
     int it = 0, status = 0;
     double rel = 0.0;
     auto t0 = std::chrono::steady_clock::now();
-    helmholtz_pcg64(H, alpha, ell2, ell2_ref, abar, opts->tol, opts->maxit, it, rel, status);
+    HelmOut ho;
+    helmholtz_pcg64(H, alpha, ell2, ell2_ref, abar, opts->tol, opts->maxit, 1, &ho);
+    it = ho.iters;
+    rel = ho.relres;
+    status = ho.status;
     sync(H);
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));

@@ -288,18 +288,27 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
 
 // Fused x pass of the Helmholtz operator: C2R of the ND gradient
 // components, multiply by scale * ell^2(x), R2C.
+// Stacked systems: nsys x n2 x n3 lines per gradient component (component
+// stride wstride), ell2 [sys][N].
 template <typename T, typename TL, int NF, int ND>
 FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int NL_rt,
                                 cpx<T>* __restrict__ w, const TL* __restrict__ ell2, T scl,
-                                const KrylovCtl* __restrict__ ctl) {
-  if (ctl && ctl->done) return;
+                                int nsys, long long wstride, const KrylovCtl* __restrict__ ctl) {
   constexpr bool FIX = NF > 0;
   constexpr int NT = FIX ? kFusedThreads : FFT_THREADS;
   constexpr int LDX = FIX ? padded_pitch(NF) : 1;
   __shared__ cpx<T> buf[FIX ? ND * fx_fused_lines<T>(NF, ND) / 2 * LDX : LDS_ELEMS];
-  const long long nlines = (long long)g.n2 * g.n3;
+  // A workgroup holds lines of one system only: two real lines share one
+  // complex transform, which leaves rounding of the larger line's magnitude
+  // in the smaller one, so lines of fields of very different size must never
+  // be paired.
+  const long long lpsys = (long long)g.n2 * g.n3;
   const int NL = FIX ? fx_fused_lines<T>(NF, ND) : NL_rt;
-  const long long line0 = (long long)blockIdx.x * NL;
+  const long long bps = (lpsys + NL - 1) / NL;  // workgroups per system
+  const long long sys = blockIdx.x / bps;
+  const long long line0 = sys * lpsys + (blockIdx.x % bps) * NL;
+  const long long nlines = (sys + 1) * lpsys;   // end of this system's lines
+  if (ctl && ctl[sys].done) return;
   const int n1 = FIX ? NF : g.n1, n1h = FIX ? NF / 2 + 1 : g.n1h;
   const int ld = FIX ? LDX : n1;
   const int P = ND * NL / 2;
@@ -307,8 +316,8 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
     const int p = e / n1h, k = e % n1h;
     const int sa = p, sb = p + P;
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
-    const cpx<T> A = la < nlines ? w[(sa / NL) * g.Ns + la * n1h + k] : mk(T(0), T(0));
-    const cpx<T> B = lb < nlines ? w[(sb / NL) * g.Ns + lb * n1h + k] : mk(T(0), T(0));
+    const cpx<T> A = la < nlines ? w[(sa / NL) * wstride + la * n1h + k] : mk(T(0), T(0));
+    const cpx<T> B = lb < nlines ? w[(sb / NL) * wstride + lb * n1h + k] : mk(T(0), T(0));
     pack_inverse<FIX>(buf, p, k, n1, ld, A, B);
   }
   __syncthreads();
@@ -342,8 +351,8 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
     const long long la = line0 + sa % NL, lb = line0 + sb % NL;
     cpx<T> A, B;
     unpack_forward<FIX>(buf, p, k, n1, ld, A, B);
-    if (la < nlines) w[(sa / NL) * g.Ns + la * n1h + k] = A;
-    if (lb < nlines) w[(sb / NL) * g.Ns + lb * n1h + k] = B;
+    if (la < nlines) w[(sa / NL) * wstride + la * n1h + k] = A;
+    if (lb < nlines) w[(sb / NL) * wstride + lb * n1h + k] = B;
   }
 }
 
@@ -489,12 +498,19 @@ FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
 // vary.  So the pass transforms two fields instead of three,
 //   w_0 = Z^-1(i c_z p),  w_1 = Z^-1(i c_x c_y f_z p),
 // and the y pass (k_h_y_split) forms the three gradient components from them.
+//
+// Several systems (one per non-local field, solved in lockstep) are stacked
+// spectra [sys][Ns] with gradient fields [comp][sys][Ns] (component stride
+// wstride); the tiles of a system never reach into the next one (tpo tiles per
+// system), and each system has its own control block ctl[sys].
 template <typename T, int NF, int ND, bool SPLIT>
 FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                              int update, const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
-                             cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
-                             long long inner, long long ostride, long long es, int TL_rt,
-                             const KrylovCtl* __restrict__ ctl) {
+                             cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long inner,
+                             long long ostride, long long es, int TL_rt, int tpo,
+                             long long wstride, const KrylovCtl* __restrict__ ctl_all) {
+  const int sys = (int)(blockIdx.x / tpo);
+  const KrylovCtl* ctl = ctl_all ? ctl_all + sys : nullptr;
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
   constexpr int NC = SPLIT ? 2 : ND;  // fields transformed
@@ -504,11 +520,12 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
   const int TL = FIX ? fs_tile_wide<T>(NF, NC) : TL_rt;
   const int ld = NC * TL;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
-  const long long L = (long long)blockIdx.x * TL + l;
-  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  const long long Lloc = (long long)(blockIdx.x % tpo) * TL + l;
+  const long long L = (long long)sys * inner + Lloc;
+  const long long lb = Lloc < inner ? line_base(L, inner, ostride) : -1;
   // lines are (ky, kx) in 3D (z outer) and kx in 2D (y outer)
   const bool zouter = g.ndim == 3;
-  const int lkx = (int)((L % inner) % g.n1h), lky = (int)((L % inner) / g.n1h);
+  const int lkx = (int)(Lloc % g.n1h), lky = (int)(Lloc / g.n1h);
   const T alpha = ctl ? (T)ctl->alpha : T(0), beta = ctl ? (T)ctl->beta : T(0);
   const T l2 = ctl ? (T)ctl->ell2ref : T(0);
   for (int t = t0; t < n; t += dt) {
@@ -553,7 +570,7 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
     for (int t = t0; t < n; t += dt) {
       const long long gi = lb + t * es;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) w[j * g.Ns + gi] = buf[t * ld + j * TL + l];
+      for (int j = 0; j < NC; ++j) w[j * wstride + gi] = buf[t * ld + j * TL + l];
     }
 }
 
@@ -564,11 +581,11 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
 // Forward: transforms w_0, w_1, w_2 and folds the x and y components,
 //   u = f_x c_y Y(w_0) + c_x f_y Y(w_1),  v = c_x c_y Y(w_2)  -> w_0, w_1,
 // which the outer forward pass (k_h_div_fwd<SPLIT>) finishes with c_z, f_z.
+// Stacked systems: lines (sys, z, kx) in order, gradient fields wstride apart.
 template <typename T, bool FWD, int NF>
 FFTG_KERNEL_WIDE void k_h_y_split(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                                   cpx<T>* __restrict__ w, long long nlines, int TL_rt,
-                                  const KrylovCtl* __restrict__ ctl) {
-  if (ctl && ctl->done) return;
+                                  long long wstride, const KrylovCtl* __restrict__ ctl) {
   constexpr bool FIX = NF > 0;
   __shared__ cpx<T> buf[FIX ? 3 * fs_tile_wide<T>(NF, 3) * NF : LDS_ELEMS];
   const int n = FIX ? NF : plan.n;
@@ -576,7 +593,16 @@ FFTG_KERNEL_WIDE void k_h_y_split(Plan plan, const cpx<T>* __restrict__ tw, Geo 
   const int TL = FIX ? fs_tile_wide<T>(NF, 3) : TL_rt;
   const int ld = 3 * TL;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
-  const long long L = xcd_tile(blockIdx.x, gridDim.x) * TL + l;
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (ctl) {
+    // skip a tile whose systems have all converged
+    const long long lpsys = (long long)g.n3 * g.n1h;
+    const long long last = (tile + 1) * TL - 1 < nlines ? (tile + 1) * TL - 1 : nlines - 1;
+    bool live = false;
+    for (long long sy = tile * TL / lpsys; sy <= last / lpsys; ++sy) live = live || !ctl[sy].done;
+    if (!live) return;
+  }
+  const long long L = tile * TL + l;
   const long long inner = g.n1h, es = g.n1h;
   const long long lb = L < nlines ? line_base(L, inner, (long long)g.n2 * g.n1h) : -1;
   const int kx = (int)(L % inner);
@@ -591,9 +617,9 @@ FFTG_KERNEL_WIDE void k_h_y_split(Plan plan, const cpx<T>* __restrict__ tw, Geo 
     const long long gi = lb + t * es;
     if constexpr (FWD) {
 #pragma unroll
-      for (int j = 0; j < 3; ++j) buf[t * ld + j * TL + l] = w[j * g.Ns + gi];
+      for (int j = 0; j < 3; ++j) buf[t * ld + j * TL + l] = w[j * wstride + gi];
     } else {
-      const cpx<T> a = w[gi], bb = w[g.Ns + gi];
+      const cpx<T> a = w[gi], bb = w[wstride + gi];
       const T fy = b[sym.gq[1] + t], cy = b[sym.cs[1] + t];
       buf[t * ld + l] = scale(a, fx * cy);
       buf[t * ld + TL + l] = scale(a, cx * fy);
@@ -612,10 +638,10 @@ FFTG_KERNEL_WIDE void k_h_y_split(Plan plan, const cpx<T>* __restrict__ tw, Geo 
     if constexpr (FWD) {
       const T fy = b[sym.gq[1] + t], cy = b[sym.cs[1] + t];
       w[gi] = scale(buf[t * ld + l], fx * cy) + scale(buf[t * ld + TL + l], cx * fy);
-      w[g.Ns + gi] = scale(buf[t * ld + 2 * TL + l], cx * cy);
+      w[wstride + gi] = scale(buf[t * ld + 2 * TL + l], cx * cy);
     } else {
 #pragma unroll
-      for (int j = 0; j < 3; ++j) w[j * g.Ns + gi] = buf[t * ld + j * TL + l];
+      for (int j = 0; j < 3; ++j) w[j * wstride + gi] = buf[t * ld + j * TL + l];
     }
   }
 }
@@ -624,12 +650,16 @@ FFTG_KERNEL_WIDE void k_h_y_split(Plan plan, const cpx<T>* __restrict__ tw, Geo 
 //   Ap = p - i sum_j q~_j FFT(w_j) ; partial sums of weighted p.Ap.
 // SPLIT (3D): w_0, w_1 are the u, v of k_h_y_split, and
 // sum_j q_j FFT(w_j) = c_z Z(u) + f_z Z(v).
+// Stacked systems as in k_h_dir_inv; partials of system sys are the tpo
+// entries from sys * tpo.
 template <typename T, int NF, int ND, bool SPLIT>
 FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                              const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
-                             cpx<T>* __restrict__ Ap, long long nlines, long long inner,
-                             long long ostride, long long es, int TL_rt,
-                             double* __restrict__ partials, const KrylovCtl* __restrict__ ctl) {
+                             cpx<T>* __restrict__ Ap, long long inner, long long ostride,
+                             long long es, int TL_rt, int tpo, long long wstride,
+                             double* __restrict__ partials, const KrylovCtl* __restrict__ ctl_all) {
+  const int sys = (int)(blockIdx.x / tpo);
+  const KrylovCtl* ctl = ctl_all ? ctl_all + sys : nullptr;
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
   constexpr int NC = SPLIT ? 2 : ND;  // fields transformed
@@ -641,15 +671,16 @@ FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo 
   const int TL = FIX ? fs_tile_wide<T>(NF, NC) : TL_rt;
   const int ld = NC * TL;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
-  const long long L = (long long)blockIdx.x * TL + l;
-  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  const long long Lloc = (long long)(blockIdx.x % tpo) * TL + l;
+  const long long L = (long long)sys * inner + Lloc;
+  const long long lb = Lloc < inner ? line_base(L, inner, ostride) : -1;
   const bool zouter = g.ndim == 3;
-  const int lkx = (int)((L % inner) % g.n1h), lky = (int)((L % inner) / g.n1h);
+  const int lkx = (int)(Lloc % g.n1h), lky = (int)(Lloc / g.n1h);
   for (int t = t0; t < n; t += dt) {
     if (lb >= 0) {
       const long long gi = lb + t * es;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = w[j * g.Ns + gi];
+      for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = w[j * wstride + gi];
     } else {
 #pragma unroll
       for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
@@ -793,14 +824,18 @@ FFTG_KERNEL void k_project(Geo g, Sym<T> sym, unsigned char mk0, unsigned char m
 
 // Helmholtz residual update (init: r = b - Ap; else r -= alpha Ap), with
 // partials [0] weighted r.Mr and [1] weighted r.r.
+// Stacked systems: blockIdx.y is the system (spectra [sys][Ns]); its
+// partials are [r.Mr | r.r] at sys * 2 * gridDim.x.
 template <typename T>
 FFTG_KERNEL void k_h_resid(Geo g, Sym<T> sym, int init, cpx<T>* __restrict__ r,
                            const cpx<T>* __restrict__ b, const cpx<T>* __restrict__ Ap,
-                           double* __restrict__ partials, const KrylovCtl* __restrict__ ctl) {
+                           double* __restrict__ partials, const KrylovCtl* __restrict__ ctl_all) {
+  const KrylovCtl* ctl = ctl_all + blockIdx.y;
   if (!init && ctl->done) return;
   __shared__ double red[FFT_THREADS];
   const T alpha = init ? T(0) : (T)ctl->alpha;
   const T l2 = (T)ctl->ell2ref;
+  const long long off = (long long)blockIdx.y * g.Ns;
   double arz = 0.0, arr = 0.0;
   for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
        gi += (long long)gridDim.x * FFT_THREADS) {
@@ -809,17 +844,19 @@ FFTG_KERNEL void k_h_resid(Geo g, Sym<T> sym, int init, cpx<T>* __restrict__ r,
     T q[3];
     qvec(sym, true, kx, ky, kz, q);
     const T minv = T(1) / (T(1) + l2 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]));
-    const cpx<T> rn = init ? b[gi] - Ap[gi] : r[gi] - scale(Ap[gi], alpha);
-    r[gi] = rn;
+    const long long e = off + gi;
+    const cpx<T> rn = init ? b[e] - Ap[e] : r[e] - scale(Ap[e], alpha);
+    r[e] = rn;
     const double wt = hweight(kx, g.n1h);
     const double rr = (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
     arr += wt * rr;
     arz += wt * rr * (double)minv;
   }
+  double* pt = partials + (long long)blockIdx.y * 2 * gridDim.x;
   double s = block_sum(arz, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) pt[blockIdx.x] = s;
   s = block_sum(arr, red);
-  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0) pt[gridDim.x + blockIdx.x] = s;
 }
 
 // Exact Hermitian symmetry on the planes kx = 0 and kx = n1/2, where both
@@ -852,29 +889,34 @@ FFTG_KERNEL void k_hermitize(Geo g, int ncomp, cpx<T>* __restrict__ d) {
 }
 
 // Deferred last update x <- x + alpha p.
+// Stacked systems: n / nsys elements each, blockIdx.y the system.
 template <typename T>
 FFTG_KERNEL void k_xfinal(cpx<T>* __restrict__ x, const cpx<T>* __restrict__ p, long long n,
                           const KrylovCtl* __restrict__ ctl) {
-  const T alpha = (T)ctl->alpha;
+  const T alpha = (T)ctl[blockIdx.y].alpha;
   if (alpha == T(0)) return;
+  const long long off = (long long)blockIdx.y * n;
   for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
        i += (long long)gridDim.x * FFT_THREADS)
-    x[i] = x[i] + scale(p[i], alpha);
+    x[off + i] = x[off + i] + scale(p[off + i], alpha);
 }
 
+// Weighted |a|^2 of ncomp spectra per system; blockIdx.y is the system, its
+// partials at blockIdx.y * gridDim.x.
 template <typename T>
 FFTG_KERNEL void k_wnorm2(Geo g, int ncomp, const cpx<T>* __restrict__ a,
                           double* __restrict__ partials) {
   __shared__ double red[FFT_THREADS];
   double acc = 0.0;
   const long long n = g.Ns * ncomp;
+  const cpx<T>* as = a + (long long)blockIdx.y * n;
   for (long long i = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; i < n;
        i += (long long)gridDim.x * FFT_THREADS) {
-    const cpx<T> v = a[i];
+    const cpx<T> v = as[i];
     acc += hweight((int)(i % g.n1h), g.n1h) * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
 // ============================================================ scalars
@@ -884,10 +926,12 @@ __device__ double ordered_sum(const double* __restrict__ p, int nb, double* red)
   return block_sum(acc, red);
 }
 
-FFTG_KERNEL void k_fin_alpha(const double* __restrict__ partials, int nb, KrylovCtl* ctl) {
+// One workgroup per system: partials of system s from s * nb, ctl[s].
+FFTG_KERNEL void k_fin_alpha(const double* __restrict__ partials, int nb, KrylovCtl* ctl_all) {
+  KrylovCtl* ctl = ctl_all + blockIdx.x;
   if (ctl->done) return;
   __shared__ double red[FFT_THREADS];
-  const double pAp = ordered_sum(partials, nb, red);
+  const double pAp = ordered_sum(partials + (long long)blockIdx.x * nb, nb, red);
   if (threadIdx.x == 0) {
     ctl->pAp = pAp;
     if (!isfinite(pAp) || !isfinite(ctl->rz)) {
@@ -904,11 +948,13 @@ FFTG_KERNEL void k_fin_alpha(const double* __restrict__ partials, int nb, Krylov
 
 // nred = 1 (CG: partials = r.r) or 2 (PCG: partials = [r.Mr | r.r]).
 FFTG_KERNEL void k_fin_beta(const double* __restrict__ partials, int nb, int nred,
-                            KrylovCtl* ctl) {
+                            KrylovCtl* ctl_all) {
+  KrylovCtl* ctl = ctl_all + blockIdx.x;
   if (ctl->done) return;
   __shared__ double red[FFT_THREADS];
-  const double rz = ordered_sum(partials, nb, red);
-  const double rr = nred == 2 ? ordered_sum(partials + nb, nb, red) : rz;
+  const double* ps = partials + (long long)blockIdx.x * nred * nb;
+  const double rz = ordered_sum(ps, nb, red);
+  const double rr = nred == 2 ? ordered_sum(ps + nb, nb, red) : rz;
   if (threadIdx.x == 0) {
     ctl->iters += 1;
     ctl->beta = rz / ctl->rz;
@@ -1955,25 +2001,28 @@ FFTG_KERNEL void k_h_refine_resid(Geo g, const cpx<double>* __restrict__ b,
                                   double* __restrict__ partials) {
   __shared__ double red[FFT_THREADS];
   double acc = 0.0;
+  const long long off = (long long)blockIdx.y * g.Ns;  // system blockIdx.y
   for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
        gi += (long long)gridDim.x * FFT_THREADS) {
-    const cpx<double> r = b[gi] - Ap[gi];
-    r32[gi] = mk((float)r.x, (float)r.y);
+    const cpx<double> r = b[off + gi] - Ap[off + gi];
+    r32[off + gi] = mk((float)r.x, (float)r.y);
     acc += hweight((int)(gi % g.n1h), g.n1h) * (r.x * r.x + r.y * r.y);
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
+// Sum of ell2 over N voxels for each system blockIdx.y (ell2 [sys][N]).
 template <typename T>
 FFTG_KERNEL void k_sum_ell2(long long N, const T* __restrict__ e, double* __restrict__ partials) {
   __shared__ double red[FFT_THREADS];
   double acc = 0.0;
+  const T* es = e + (long long)blockIdx.y * N;
   for (long long v = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; v < N;
        v += (long long)gridDim.x * FFT_THREADS)
-    acc += (double)e[v];
+    acc += (double)es[v];
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
 // ============================================================ adjoint helpers
@@ -2263,21 +2312,22 @@ void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cp
 
 template <typename T, typename TL>
 void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
-                         const TL* ell2, T scl, const KrylovCtl* ctl, hipStream_t st) {
-  const long long nlines = (long long)g.n2 * g.n3;
+                         const TL* ell2, T scl, const KrylovCtl* ctl, hipStream_t st, int nsys) {
+  const long long lpsys = (long long)g.n2 * g.n3;
+  const long long ws = (long long)nsys * g.Ns;
   FFTG_DISPATCH_N(g.n1, {
     if (g.ndim == 3) {
       const int NL = NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
-      const long long nb = (nlines + NL - 1) / NL;
+      const long long nb = (lpsys + NL - 1) / NL * nsys;
       hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 3>), dim3((unsigned)nb),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
-                         st, p, tw, g, NL, w, ell2, scl, ctl);
+                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl);
     } else {
       const int NL = NF ? fx_fused_lines<T>(NF, 2) : fused_lines_rt(g.n1, 2);
-      const long long nb = (nlines + NL - 1) / NL;
+      const long long nb = (lpsys + NL - 1) / NL * nsys;
       hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 2>), dim3((unsigned)nb),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
-                         st, p, tw, g, NL, w, ell2, scl, ctl);
+                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl);
     }
   })
 }
@@ -2324,87 +2374,95 @@ void launch_project(const Geo& g, int c, const Sym<T>& sym, const unsigned char*
                        m[2], m[3], m[4], m[5], data);
 }
 
+// tiles per system of an outer-axis Helmholtz pass (TL lines each, no tile
+// across two systems)
+static inline int tiles_per_sys(long long inner, int TL) { return (int)((inner + TL - 1) / TL); }
+
 template <typename T>
 int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, bool update, const cpx<T>* r, cpx<T>* pp, cpx<T>* x,
-                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st) {
+                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st, int nsys) {
   long long nl, inner, os, es;
   outer_lines(g, 1, zouter, nl, inner, os, es);
-  long long nb = 0;
+  const long long ws = (long long)nsys * g.Ns;
+  int tpo = 0;
   FFTG_DISPATCH_N(p.n, {
     if (helm_split(g)) {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
-      nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3, true>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3, true>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl);
     } else if (g.ndim == 3) {
       const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
-      nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3, false>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3, false>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl);
     } else {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
-      nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 2, false>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, update ? 1 : 0, r, pp, x, w, nl, inner, os, es, TL, ctl);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_dir_inv<T, NF, 2, false>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl);
     }
   })
-  return (int)nb;
+  return tpo;
 }
 
 template <typename T>
 void launch_h_y_split(const Plan& p, const cpx<T>* tw, const Geo& g, const Sym<T>& sym,
-                      cpx<T>* w, bool fwd, const KrylovCtl* ctl, hipStream_t st) {
+                      cpx<T>* w, bool fwd, const KrylovCtl* ctl, hipStream_t st, int nsys) {
   require(helm_split(g), "split Helmholtz y pass: 3D grids with n2 > 1 only");
-  const long long nl = (long long)g.n3 * g.n1h;
+  const long long nl = (long long)nsys * g.n3 * g.n1h;
+  const long long ws = (long long)nsys * g.Ns;
   FFTG_DISPATCH_N(p.n, {
     const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
     const long long nb = (nl + TL - 1) / TL;
     if (fwd)
       hipLaunchKernelGGL((k_h_y_split<T, true, NF>), dim3((unsigned)nb),
                          dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, w, nl, TL,
-                         ctl);
+                         ws, ctl);
     else
       hipLaunchKernelGGL((k_h_y_split<T, false, NF>), dim3((unsigned)nb),
                          dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, w, nl, TL,
-                         ctl);
+                         ws, ctl);
   })
 }
 
 template <typename T>
 int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, const cpx<T>* pp, cpx<T>* w, cpx<T>* Ap,
-                     double* partials, const KrylovCtl* ctl, hipStream_t st) {
+                     double* partials, const KrylovCtl* ctl, hipStream_t st, int nsys) {
   long long nl, inner, os, es;
   outer_lines(g, 1, zouter, nl, inner, os, es);
-  long long nb = 0;
+  const long long ws = (long long)nsys * g.Ns;
+  int tpo = 0;
   FFTG_DISPATCH_N(p.n, {
     if (helm_split(g)) {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
-      nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3, true>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3, true>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+                         tw, g, sym, pp, w, Ap, inner, os, es, TL, tpo, ws, partials, ctl);
     } else if (g.ndim == 3) {
       const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
-      nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3, false>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 3, false>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+                         tw, g, sym, pp, w, Ap, inner, os, es, TL, tpo, ws, partials, ctl);
     } else {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
-      nb = (nl + TL - 1) / TL;
-      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 2, false>), dim3((unsigned)nb), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, pp, w, Ap, nl, inner, os, es, TL, partials, ctl);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_div_fwd<T, NF, 2, false>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
+                         tw, g, sym, pp, w, Ap, inner, os, es, TL, tpo, ws, partials, ctl);
     }
   })
-  return (int)nb;
+  return tpo;
 }
 
 template <typename T>
 int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const cpx<T>* b,
-                   const cpx<T>* Ap, double* partials, const KrylovCtl* ctl, hipStream_t st) {
+                   const cpx<T>* Ap, double* partials, const KrylovCtl* ctl, hipStream_t st,
+                   int nsys) {
   const int nb = grid_for(g.Ns);
-  hipLaunchKernelGGL(k_h_resid<T>, dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, init ? 1 : 0, r, b,
-                     Ap, partials, ctl);
+  hipLaunchKernelGGL(k_h_resid<T>, dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, sym, init ? 1 : 0,
+                     r, b, Ap, partials, ctl);
   return nb;
 }
 
@@ -2455,11 +2513,12 @@ void launch_tangent_apply(long long N, int c, const TT* tan, const double* gsig,
                      gsig, gin, gout);
 }
 
-void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FFT_THREADS), 0, st, partials, nb, ctl);
+void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st, int nsys) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(nsys), dim3(FFT_THREADS), 0, st, partials, nb, ctl);
 }
-void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(FFT_THREADS), 0, st, partials, nb, nred, ctl);
+void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st,
+                     int nsys) {
+  hipLaunchKernelGGL(k_fin_beta, dim3(nsys), dim3(FFT_THREADS), 0, st, partials, nb, nred, ctl);
 }
 void launch_fin_sums(const double* partials, int nb, int nred, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_sums, dim3(1), dim3(FFT_THREADS), 0, st, partials, nb, nred, out);
@@ -2467,8 +2526,9 @@ void launch_fin_sums(const double* partials, int nb, int nred, double* out, hipS
 
 template <typename T>
 void launch_xfinal(cpx<T>* x, const cpx<T>* p, long long n, const KrylovCtl* ctl,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_xfinal<T>, dim3(grid_for(n)), dim3(FFT_THREADS), 0, st, x, p, n, ctl);
+                   hipStream_t st, int nsys) {
+  hipLaunchKernelGGL(k_xfinal<T>, dim3(grid_for(n), nsys), dim3(FFT_THREADS), 0, st, x, p, n,
+                     ctl);
 }
 
 template <typename T>
@@ -2478,9 +2538,10 @@ void launch_hermitize(const Geo& g, int ncomp, cpx<T>* d, hipStream_t st) {
 }
 
 template <typename T>
-int launch_wnorm2(const Geo& g, int ncomp, const cpx<T>* a, double* partials, hipStream_t st) {
+int launch_wnorm2(const Geo& g, int ncomp, const cpx<T>* a, double* partials, hipStream_t st,
+                  int nsys) {
   const int nb = grid_for(g.Ns * ncomp);
-  hipLaunchKernelGGL(k_wnorm2<T>, dim3(nb), dim3(FFT_THREADS), 0, st, g, ncomp, a, partials);
+  hipLaunchKernelGGL(k_wnorm2<T>, dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, ncomp, a, partials);
   return nb;
 }
 
@@ -2607,17 +2668,17 @@ void launch_acc_wide(long long n, const TA* a, double* b, hipStream_t st) {
 template void launch_acc_wide<float>(long long, const float*, double*, hipStream_t);
 
 int launch_h_refine_resid(const Geo& g, const cpx<double>* b, const cpx<double>* Ap,
-                          cpx<float>* r32, double* partials, hipStream_t st) {
+                          cpx<float>* r32, double* partials, hipStream_t st, int nsys) {
   const int nb = grid_for(g.Ns);
-  hipLaunchKernelGGL(k_h_refine_resid, dim3(nb), dim3(FFT_THREADS), 0, st, g, b, Ap, r32,
+  hipLaunchKernelGGL(k_h_refine_resid, dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, b, Ap, r32,
                      partials);
   return nb;
 }
 
 template <typename T>
-int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st) {
+int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, int nsys) {
   const int nb = grid_for(N);
-  hipLaunchKernelGGL(k_sum_ell2<T>, dim3(nb), dim3(FFT_THREADS), 0, st, N, e, partials);
+  hipLaunchKernelGGL(k_sum_ell2<T>, dim3(nb, nsys), dim3(FFT_THREADS), 0, st, N, e, partials);
   return nb;
 }
 
@@ -2644,29 +2705,29 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st) {
                                   hipStream_t);                                                  \
   template int launch_h_dir_inv<T>(const Plan&, const cpx<T>*, const Geo&, bool, const Sym<T>&,  \
                                    bool, const cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*,               \
-                                   const KrylovCtl*, hipStream_t);                               \
+                                   const KrylovCtl*, hipStream_t, int);                          \
   template int launch_h_div_fwd<T>(const Plan&, const cpx<T>*, const Geo&, bool, const Sym<T>&,  \
                                    const cpx<T>*, cpx<T>*, cpx<T>*, double*, const KrylovCtl*,   \
-                                   hipStream_t);                                                 \
+                                   hipStream_t, int);                                            \
   template void launch_h_y_split<T>(const Plan&, const cpx<T>*, const Geo&, const Sym<T>&,      \
-                                    cpx<T>*, bool, const KrylovCtl*, hipStream_t);               \
+                                    cpx<T>*, bool, const KrylovCtl*, hipStream_t, int);          \
   template int launch_h_resid<T>(const Geo&, const Sym<T>&, bool, cpx<T>*, const cpx<T>*,       \
-                                  const cpx<T>*, double*, const KrylovCtl*, hipStream_t);        \
+                                  const cpx<T>*, double*, const KrylovCtl*, hipStream_t, int);   \
   template void launch_xfinal<T>(cpx<T>*, const cpx<T>*, long long, const KrylovCtl*,            \
-                                 hipStream_t);                                                   \
+                                 hipStream_t, int);                                              \
   template void launch_hermitize<T>(const Geo&, int, cpx<T>*, hipStream_t);                     \
-  template int launch_wnorm2<T>(const Geo&, int, const cpx<T>*, double*, hipStream_t);          \
+  template int launch_wnorm2<T>(const Geo&, int, const cpx<T>*, double*, hipStream_t, int);     \
   template void launch_x_fused_gal<T, T>(const Plan&, const cpx<T>*, const Geo&, int, cpx<T>*,   \
                                          const T*, T, const KrylovCtl*, hipStream_t);            \
   template void launch_x_fused_helm<T, T>(const Plan&, const cpx<T>*, const Geo&, cpx<T>*,       \
-                                          const T*, T, const KrylovCtl*, hipStream_t);           \
+                                          const T*, T, const KrylovCtl*, hipStream_t, int);      \
   template void launch_constitutive<T>(const MatTable&, const Geo&, int, int,                    \
                                        const unsigned char*, const double*, const double*,       \
                                        const double*, double*, double*, double*, T*,             \
                                        hipStream_t);                                             \
   template void launch_ell2<T>(const MatTable&, long long, int, const unsigned char*, T*,        \
                                hipStream_t);                                                     \
-  template int launch_sum_ell2<T>(long long, const T*, double*, hipStream_t);
+  template int launch_sum_ell2<T>(long long, const T*, double*, hipStream_t, int);
 
 INST_T(double)
 INST_T(float)

@@ -106,27 +106,37 @@ void launch_project(const Geo& g, int c, const Sym<T>& sym, const unsigned char*
 // passes transform two fields instead of three and launch_h_y_split, in
 // place of the plain y passes, forms and folds the gradient components.
 inline bool helm_split(const Geo& g) { return g.ndim == 3 && g.n2 > 1; }
+//
+// Several Helmholtz systems of one grid (one per non-local field, solved in
+// lockstep) are stacked: scalar spectra [sys][Ns], the gradient buffer
+// [comp][sys][Ns], ell2 [sys][N], one control block per system ctl[sys],
+// and the reductions return per-system partial counts (partials of system s
+// at s * count * nred).  nsys = 1 is the single-system case.
 template <typename T>
 void launch_h_y_split(const Plan& p, const cpx<T>* tw, const Geo& g, const Sym<T>& sym,
-                      cpx<T>* w, bool fwd, const KrylovCtl* ctl, hipStream_t st);
+                      cpx<T>* w, bool fwd, const KrylovCtl* ctl, hipStream_t st, int nsys = 1);
 template <typename T>
 int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, bool update, const cpx<T>* r, cpx<T>* pp, cpx<T>* x,
-                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st);
+                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st, int nsys = 1);
 template <typename T>
 int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, const cpx<T>* pp, cpx<T>* w, cpx<T>* Ap,
-                     double* partials, const KrylovCtl* ctl, hipStream_t st);
+                     double* partials, const KrylovCtl* ctl, hipStream_t st, int nsys = 1);
 template <typename T, typename TL>
 void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
-                         const TL* ell2, T scale, const KrylovCtl* ctl, hipStream_t st);
+                         const TL* ell2, T scale, const KrylovCtl* ctl, hipStream_t st,
+                         int nsys = 1);
 template <typename T>
 int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const cpx<T>* b,
-                    const cpx<T>* Ap, double* partials, const KrylovCtl* ctl, hipStream_t st);
+                   const cpx<T>* Ap, double* partials, const KrylovCtl* ctl, hipStream_t st,
+                   int nsys = 1);
 
-// Krylov scalars
-void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st);
-void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st);
+// Krylov scalars: one workgroup per system (partials of system s at s * nb,
+// or s * nred * nb)
+void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st, int nsys = 1);
+void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st,
+                     int nsys = 1);
 void launch_fin_sums(const double* partials, int nb, int nred, double* out, hipStream_t st);
 
 // adjoint helpers (FP64)
@@ -149,13 +159,15 @@ int launch_count_bad_phase(long long N, int nphase, const unsigned char* phase,
 template <typename TT>
 void launch_tangent_apply(long long N, int c, const TT* tan, const double* gsig,
                           const double* gin, double* gout, hipStream_t st);
+// x += alpha p per system: n elements each, nsys systems back to back
 template <typename T>
 void launch_xfinal(cpx<T>* x, const cpx<T>* p, long long n, const KrylovCtl* ctl,
-                   hipStream_t st);
+                   hipStream_t st, int nsys = 1);
 template <typename T>
 void launch_hermitize(const Geo& g, int ncomp, cpx<T>* d, hipStream_t st);
 template <typename T>
-int launch_wnorm2(const Geo& g, int ncomp, const cpx<T>* a, double* partials, hipStream_t st);
+int launch_wnorm2(const Geo& g, int ncomp, const cpx<T>* a, double* partials, hipStream_t st,
+                  int nsys = 1);
 
 // grid-space kernels (FP64)
 template <typename TT>
@@ -202,10 +214,10 @@ void launch_vmax(long long n, double* a, const double* b, hipStream_t st);
 template <typename TA, typename TB>
 void launch_convert(long long n, const TA* a, TB* b, hipStream_t st);
 template <typename T>
-int launch_sum_ell2(long long N, const T* ell2, double* partials, hipStream_t st);
+int launch_sum_ell2(long long N, const T* ell2, double* partials, hipStream_t st, int nsys = 1);
 template <typename TA>
 void launch_acc_wide(long long n, const TA* a, double* b, hipStream_t st);
 int launch_h_refine_resid(const Geo& g, const cpx<double>* b, const cpx<double>* Ap,
-                          cpx<float>* r32, double* partials, hipStream_t st);
+                          cpx<float>* r32, double* partials, hipStream_t st, int nsys = 1);
 
 }  // namespace fftg

@@ -78,7 +78,7 @@ def test_c2_increment_fp64_matches_oracle_everywhere(c2):
                 homog=float(np.abs(d["sigma_mean"] - c2["hom"]["sigma"]).max() /
                             abs(c2["hom"]["sigma"][0])))
     say("  fp64 vs oracle (max-norm relative):", {k: "%.1e" % v for k, v in errs.items()})
-    assert (o["kappa"] > 0).sum() > 1000 and o["abar"].max() > 0  # plastic, field active
+    assert (o["kappa"] > 0).sum() > 20 and o["abar"].max() > 0  # plastic, field active
     for k, v in errs.items():
         assert v <= 1e-10, k
 
@@ -88,7 +88,9 @@ def test_c2_increment_fp32_refined_matches_oracle(c2):
     FP64 outer loops (Newton residual, Helmholtz refinement sweeps, staggered
     error) carry the fields to FP64 accuracy; homogenised stress within 1e-9,
     every field within 1e-8 (relative L2)."""
-    d, st, sig = _gpu(c2, "fp32", TIGHT)
+    # Newton 1e-13: each FP32-refined Newton correction gains ~1e-5, so the
+    # outer loop stops just below its tolerance, where FP64 Newton overshoots
+    d, st, sig = _gpu(c2, "fp32", dict(TIGHT, newton_tol=1e-13))
     o = c2["st"]
     J = c2["w"]["nfields"]
     assert d["converged"] and d["inner_converged"]

@@ -264,10 +264,14 @@ def test_staggered_two_fields_3d():
     """3D spheres with matrix damage and particle cracking fields; two
     increments with damage onset forced by low thresholds."""
     w = ms.workload("spheres_two_fields_16")
-    w["table"][0]["dC"], w["table"][0]["dR"] = 0.0005, 0.02
-    w["table"][1]["dC"], w["table"][1]["dR"] = 5e-4, 5e-3
+    # thresholds low enough for both damage laws to act within two increments
+    # and high enough for the staggered map to contract to 1e-12 (lower ones,
+    # e.g. dR = 0.02 with cracking between 5e-4 and 5e-3, soften so fast that
+    # neither side's fixed-point iteration converges at E11 = 6e-3)
+    w["table"][0]["dC"], w["table"][0]["dR"] = 0.0005, 0.05
+    w["table"][1]["dC"], w["table"][1]["dR"] = 1e-3, 1e-2
     say("staggered spheres_two_fields_16")
-    w["load"] = [ms.uniaxial_mixed(3, 3e-3), ms.uniaxial_mixed(3, 6e-3)]
+    w["load"] = [ms.uniaxial_mixed(3, 3e-3), ms.uniaxial_mixed(3, 5e-3)]
     res, c, J = _run_staggered(w, 60, TIGHT, ninc=2)
     for d, state, sig, st_o, sig_o, hom_o, stats_o in res:
         assert d["converged"] and stats_o["converged"]
@@ -276,7 +280,8 @@ def test_staggered_two_fields_3d():
         assert relerr(sig, sig_o) <= 1e-10
         assert relerr(state[:c], st_o["eps"]) <= 1e-10
         assert relerr(state[c + 7 + J:], st_o["abar"]) <= 1e-10
-    assert res[-1][3]["abar"][1].max() > 5e-4  # the cracking field is active
+    assert res[-1][3]["abar"][1].max() > 1e-3  # the cracking field is active
+    assert res[-1][3]["abar"][0].max() > 5e-4  # and the matrix damage
 
 
 def test_fp32_refined_staggered_matches_oracle_to_1e6():
@@ -285,7 +290,7 @@ def test_fp32_refined_staggered_matches_oracle_to_1e6():
     the FP64 oracle."""
     from paper_2103_04770_amd import FP32_REFINED
     w = ms.workload("spheres_two_fields_16")
-    w["table"][0]["dC"], w["table"][0]["dR"] = 0.0005, 0.02
+    w["table"][0]["dC"], w["table"][0]["dR"] = 0.0005, 0.05
     say("fp32-refined staggered spheres_two_fields_16")
     shape, J = w["shape"], w["nfields"]
     tols = dict(cg_tol=1e-10, pcg_tol=1e-10, newton_tol=1e-10, stagger_tol=1e-8)
@@ -294,11 +299,12 @@ def test_fp32_refined_staggered_matches_oracle_to_1e6():
     state = dev(np.zeros((6 + 7 + 2 * J,) + shape))
     sig = torch.empty((6,) + shape, dtype=torch.float64, device="cuda")
     ph = dev(w["phase"], torch.uint8)
-    for e11 in (3e-3, 6e-3):
+    for e11 in (3e-3, 5e-3):
         tgt = ms.uniaxial_mixed(3, e11)
         st_o, sig_o, hom_o, stats_o = staggered.staggered_step(w["phase"], w["table"], J, st_o, tgt,
-                                                               max_stagger=30, **tols)
-        d = s.staggered_step(ph, w["table"], J, state, tgt, sig, max_stagger=30, **tols)
+                                                               max_stagger=60, **tols)
+        d = s.staggered_step(ph, w["table"], J, state, tgt, sig, max_stagger=60, **tols)
+        assert d["converged"] and stats_o["converged"]
         say("  fp32", {k: d[k] for k in ("newton_iters", "cg_iters", "pcg_iters", "stagger_iters")},
             "oracle", stats_o)
         err = np.abs(d["sigma_mean"] - hom_o["sigma"]).max() / abs(hom_o["sigma"][0])
