@@ -199,11 +199,13 @@ FFTG_KERNEL void k_x_c2r(Plan plan, const cpx<T>* __restrict__ tw, const cpx<T>*
 // K:e = a tr(e) I + b dev(e) - (m.e) m, then real -> half spectrum (R2C).
 // A workgroup owns NL whole x-lines with all C components; sequence
 // s = comp * NL + line, and sequences s and s + P share one complex line.
+//
+// Stacked systems: spectra [sys][comp][Ns], tangent [sys][N][8]; a workgroup
+// holds lines of one system only (system blockIdx.x / bps).
 template <typename T, typename TT, int NF, int C>
 FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int NL_rt,
-                               cpx<T>* __restrict__ w, const TT* __restrict__ tan, T scl,
+                               cpx<T>* __restrict__ w_all, const TT* __restrict__ tan_all, T scl,
                                const KrylovCtl* __restrict__ ctl) {
-  if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
   constexpr int NT = FIX ? kFusedThreads : FFT_THREADS;
   // fixed-length path: padded line pitch (conflict-free Stockham stages)
@@ -211,7 +213,12 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
   __shared__ cpx<T> buf[FIX ? C * fx_fused_lines<T>(NF, C) / 2 * LDX : LDS_ELEMS];
   const long long nlines = (long long)g.n2 * g.n3;
   const int NL = FIX ? fx_fused_lines<T>(NF, C) : NL_rt;
-  const long long line0 = (long long)blockIdx.x * NL;
+  const long long bps = (nlines + NL - 1) / NL;
+  const long long sys = blockIdx.x / bps;
+  if (ctl && ctl[sys].done) return;
+  cpx<T>* __restrict__ w = w_all + sys * C * g.Ns;
+  const TT* __restrict__ tan = tan_all + sys * 8 * g.N;
+  const long long line0 = (blockIdx.x % bps) * NL;
   const int n1 = FIX ? NF : g.n1, n1h = FIX ? NF / 2 + 1 : g.n1h;
   const int ld = FIX ? LDX : n1;
   const int P = C * NL / 2;
@@ -381,20 +388,28 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long nb) {
 template <int SH>
 constexpr int tile_budget() { return SH == 3 ? 2 * FFTG_TILE_BYTES : FFTG_TILE_BYTES >> SH; }
 
+// ctl (optional): the control blocks of the systems the lines belong to,
+// lps lines each; a tile whose systems have all converged returns at once.
 template <typename T, bool FWD, int NF, int SH>
 FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __restrict__ data,
                            long long nlines, long long inner, long long ostride, long long es,
-                           int TL_rt, const KrylovCtl* __restrict__ ctl) {
-  if (ctl && ctl->done) return;
+                           int TL_rt, const KrylovCtl* __restrict__ ctl, long long lps) {
   constexpr bool FIX = NF > 0;
   constexpr int TB = tile_budget<SH>();
   __shared__ cpx<T> buf[FIX ? fs_tile<T, TB>(NF) * NF : LDS_ELEMS];
   constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T, TB>(NF) : TL_rt;
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (ctl) {
+    const long long last = (tile + 1) * TL - 1 < nlines ? (tile + 1) * TL - 1 : nlines - 1;
+    bool live = false;
+    for (long long sy = tile * TL / lps; sy <= last / lps; ++sy) live = live || !ctl[sy].done;
+    if (!live) return;
+  }
   // TL divides NT: each thread stays on line l of the tile
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
-  const long long L = xcd_tile(blockIdx.x, gridDim.x) * TL + l;
+  const long long L = tile * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
   for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? data[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
@@ -408,12 +423,18 @@ FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>
 
 // Outer-axis inverse pass of the Galerkin CG (per component):
 //   p <- r + beta p ; x <- x + alpha p_old ; w <- inverse transform of p.
+//
+// Stacked systems (several RVEs of one grid solved in lockstep): spectra
+// [sys][comp][Ns]; the tiles of a (system, component) slab never reach into
+// the next one (tpo tiles per slab), and system sys uses ctl[sys].
 template <typename T, int NF, int SH>
 FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
                                const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
-                               cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long nlines,
-                               long long inner, long long ostride, long long es, int TL_rt,
-                               const KrylovCtl* __restrict__ ctl) {
+                               cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long inner,
+                               long long ostride, long long es, int TL_rt, int tpo, int ncomp,
+                               const KrylovCtl* __restrict__ ctl_all) {
+  const long long o = blockIdx.x / tpo;  // (system, component) slab
+  const KrylovCtl* ctl = ctl_all + o / ncomp;
   if (ctl->done) return;
   constexpr bool FIX = NF > 0;
   constexpr int TB = tile_budget<SH>();
@@ -423,8 +444,8 @@ FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T, TB>(NF) : TL_rt;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
-  const long long L = (long long)blockIdx.x * TL + l;
-  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  const long long Lloc = (long long)(blockIdx.x % tpo) * TL + l;
+  const long long lb = Lloc < inner ? line_base(o * inner + Lloc, inner, ostride) : -1;
   for (int t = t0; t < n; t += dt) {
     cpx<T> pn = mk(T(0), T(0));
     if (lb >= 0) {
@@ -448,12 +469,16 @@ FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
 // Outer-axis forward pass of the Galerkin CG: w <- forward transform of w,
 // and the partial sums of the Hermitian-weighted p.w (= p.Ap, since p lies in
 // the range of the orthogonal projector).
+// Stacked systems as in k_gal_dir_inv; the partials of system sys are the
+// ncomp * tpo entries from sys * ncomp * tpo.
 template <typename T, int NF>
 FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
                                const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
-                               long long nlines, long long inner, long long ostride,
-                               long long es, int TL_rt, int n1h, double* __restrict__ partials,
-                               const KrylovCtl* __restrict__ ctl) {
+                               long long inner, long long ostride, long long es, int TL_rt,
+                               int tpo, int ncomp, int n1h, double* __restrict__ partials,
+                               const KrylovCtl* __restrict__ ctl_all) {
+  const long long o = blockIdx.x / tpo;
+  const KrylovCtl* ctl = ctl_all + o / ncomp;
   if (ctl->done) return;
   constexpr bool FIX = NF > 0;
   __shared__ cpx<T> buf[FIX ? fs_tile<T, kDotBytes<T>>(NF) * NF : LDS_ELEMS];
@@ -463,8 +488,8 @@ FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T, kDotBytes<T>>(NF) : TL_rt;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
-  const long long L = (long long)blockIdx.x * TL + l;
-  const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
+  const long long Lloc = (long long)(blockIdx.x % tpo) * TL + l;
+  const long long lb = Lloc < inner ? line_base(o * inner + Lloc, inner, ostride) : -1;
   for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? w[lb + t * es] : mk(T(0), T(0));
   __syncthreads();
   if constexpr (FIX)
@@ -720,13 +745,18 @@ FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo 
 
 // ============================================================ pointwise
 // r <- r - alpha G*(w) ; partial sums of weighted |r|^2
+// Stacked systems: blockIdx.y is the system (spectra [sys][comp][Ns]), its
+// partials at blockIdx.y * gridDim.x.
 template <typename T, int C>
 FFTG_KERNEL void k_gal_resid(Geo g, Sym<T> sym, unsigned char mk0, unsigned char mk1,
                              unsigned char mk2, unsigned char mk3, unsigned char mk4,
-                             unsigned char mk5, cpx<T>* __restrict__ r,
-                             const cpx<T>* __restrict__ w, double* __restrict__ partials,
-                             const KrylovCtl* __restrict__ ctl) {
+                             unsigned char mk5, cpx<T>* __restrict__ r_all,
+                             const cpx<T>* __restrict__ w_all, double* __restrict__ partials,
+                             const KrylovCtl* __restrict__ ctl_all) {
+  const KrylovCtl* ctl = ctl_all + blockIdx.y;
   if (ctl->done) return;
+  cpx<T>* __restrict__ r = r_all + (long long)blockIdx.y * C * g.Ns;
+  const cpx<T>* __restrict__ w = w_all + (long long)blockIdx.y * C * g.Ns;
   __shared__ double red[FFT_THREADS];
   const T alpha = (T)ctl->alpha;
   const unsigned char mask[6] = {mk0, mk1, mk2, mk3, mk4, mk5};
@@ -753,20 +783,29 @@ FFTG_KERNEL void k_gal_resid(Geo g, Sym<T> sym, unsigned char mk0, unsigned char
     }
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
 // Newton right-hand side b = -G*(sigma - Sbar) from the FP64 stress spectrum;
 // partials: [0] weighted |b|^2, [1] weighted |sigma_hat|^2.
+// Stacked systems: blockIdx.y is the system; Sb_sys (when given) holds the
+// mean stress targets [sys][6]; partials [sys][2][gridDim.x].
 template <typename T, int C>
 FFTG_KERNEL void k_gal_rhs(Geo g, Sym<double> sym, unsigned char mk0, unsigned char mk1,
                            unsigned char mk2, unsigned char mk3, unsigned char mk4,
                            unsigned char mk5, double s0, double s1, double s2, double s3,
-                           double s4, double s5, const cpx<double>* __restrict__ sh,
-                           cpx<T>* __restrict__ r, double* __restrict__ partials) {
+                           double s4, double s5, const cpx<double>* __restrict__ sh_all,
+                           cpx<T>* __restrict__ r_all, double* __restrict__ partials_all,
+                           const double* __restrict__ Sb_sys) {
   __shared__ double red[FFT_THREADS];
   const unsigned char mask[6] = {mk0, mk1, mk2, mk3, mk4, mk5};
-  const double Sb[6] = {s0, s1, s2, s3, s4, s5};
+  const long long so = (long long)blockIdx.y * C * g.Ns;
+  const cpx<double>* __restrict__ sh = sh_all + so;
+  cpx<T>* __restrict__ r = r_all + so;
+  double* partials = partials_all + (long long)blockIdx.y * 2 * gridDim.x;
+  double Sb[6] = {s0, s1, s2, s3, s4, s5};
+  if (Sb_sys)
+    for (int i = 0; i < 6; ++i) Sb[i] = Sb_sys[6 * blockIdx.y + i];
   double accb = 0.0, accs = 0.0;
   for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
        gi += (long long)gridDim.x * FFT_THREADS) {
@@ -2218,19 +2257,24 @@ static inline int tile_lines(int n, int ncomp) {
 template <typename T>
 void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nlines,
                     long long inner, long long ostride, long long es, bool fwd,
-                    const KrylovCtl* ctl, hipStream_t st, int sh) {
+                    const KrylovCtl* ctl, hipStream_t st, int sh, long long lps) {
+  if (lps <= 0) lps = nlines;
   FFTG_DISPATCH_N(p.n, FFTG_DISPATCH_SH(NF ? sh : 0, {
     const int TL = NF ? fs_tile<T, tile_budget<SH>()>(NF) : tile_lines(p.n, 1);
     const int NT = NF ? kStridedThreads : FFT_THREADS;
     const long long nb = (nlines + TL - 1) / TL;
     if (fwd)
       hipLaunchKernelGGL((k_strided<T, true, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw,
-                         data, nlines, inner, ostride, es, TL, ctl);
+                         data, nlines, inner, ostride, es, TL, ctl, lps);
     else
       hipLaunchKernelGGL((k_strided<T, false, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p,
-                         tw, data, nlines, inner, ostride, es, TL, ctl);
+                         tw, data, nlines, inner, ostride, es, TL, ctl, lps);
   }))
 }
+
+// tiles per slab of an outer-axis pass (TL lines each, no tile across two
+// slabs: systems, or components of a system)
+static inline int tiles_per_sys(long long inner, int TL) { return (int)((inner + TL - 1) / TL); }
 
 // outer axis line geometry for a c-component spectrum
 static inline void outer_lines(const Geo& g, int ncomp, bool zouter, long long& nlines,
@@ -2251,16 +2295,17 @@ static inline void outer_lines(const Geo& g, int ncomp, bool zouter, long long& 
 template <typename T>
 int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, const KrylovCtl* ctl,
-                       hipStream_t st, int sh) {
+                       hipStream_t st, int sh, int nsys) {
   long long nl, inner, os, es;
   outer_lines(g, c, zouter, nl, inner, os, es);
   long long nb = 0;
   FFTG_DISPATCH_N(p.n, FFTG_DISPATCH_SH(NF ? sh : 0, {
     const int TL = NF ? fs_tile<T, tile_budget<SH>()>(NF) : tile_lines(p.n, 1);
     const int NT = NF ? kStridedThreads : FFT_THREADS;
-    nb = (nl + TL - 1) / TL;
+    const int tpo = tiles_per_sys(inner, TL);
+    nb = (long long)tpo * c * nsys;
     hipLaunchKernelGGL((k_gal_dir_inv<T, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw, r,
-                       pp, x, w, nl, inner, os, es, TL, ctl);
+                       pp, x, w, inner, os, es, TL, tpo, c, ctl);
   }))
   return (int)nb;
 }
@@ -2268,17 +2313,18 @@ int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
 template <typename T>
 int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        const cpx<T>* pp, cpx<T>* w, double* partials, const KrylovCtl* ctl,
-                       hipStream_t st) {
+                       hipStream_t st, int nsys) {
   long long nl, inner, os, es;
   outer_lines(g, c, zouter, nl, inner, os, es);
   long long nb = 0;
   FFTG_DISPATCH_N(p.n, {
     const int TL = NF ? fs_tile<T, kDotBytes<T>>(NF) : tile_lines(p.n, 1);
-    nb = (nl + TL - 1) / TL;
+    const int tpo = tiles_per_sys(inner, TL);
+    nb = (long long)tpo * c * nsys;
     hipLaunchKernelGGL((k_gal_dot_fwd<T, NF>), dim3((unsigned)nb), dim3(NF ? kDotThreads<T> : FFT_THREADS), 0, st, p,
-                       tw, pp, w, nl, inner, os, es, TL, g.n1h, partials, ctl);
+                       tw, pp, w, inner, os, es, TL, tpo, c, g.n1h, partials, ctl);
   })
-  return (int)nb;
+  return (int)(nb / nsys);  // partials per system
 }
 
 static inline int fused_lines_rt(int n1, int c) {
@@ -2291,18 +2337,18 @@ static inline int fused_lines_rt(int n1, int c) {
 
 template <typename T, typename TT>
 void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
-                        const TT* tan, T scl, const KrylovCtl* ctl, hipStream_t st) {
+                        const TT* tan, T scl, const KrylovCtl* ctl, hipStream_t st, int nsys) {
   const long long nlines = (long long)g.n2 * g.n3;
   FFTG_DISPATCH_N(g.n1, {
     if (c == 6) {
       const int NL = NF ? fx_fused_lines<T>(NF, 6) : fused_lines_rt(g.n1, 6);
-      const long long nb = (nlines + NL - 1) / NL;
+      const long long nb = (nlines + NL - 1) / NL * nsys;
       hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 6>), dim3((unsigned)nb),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
                          st, p, tw, g, NL, w, tan, scl, ctl);
     } else {
       const int NL = NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
-      const long long nb = (nlines + NL - 1) / NL;
+      const long long nb = (nlines + NL - 1) / NL * nsys;
       hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 3>), dim3((unsigned)nb),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
                          st, p, tw, g, NL, w, tan, scl, ctl);
@@ -2335,13 +2381,13 @@ void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* 
 template <typename T>
 int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char* m,
                      cpx<T>* r, const cpx<T>* w, double* partials, const KrylovCtl* ctl,
-                     hipStream_t st) {
+                     hipStream_t st, int nsys) {
   const int nb = grid_for(g.Ns);
   if (c == 6)
-    hipLaunchKernelGGL((k_gal_resid<T, 6>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
+    hipLaunchKernelGGL((k_gal_resid<T, 6>), dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
                        m[2], m[3], m[4], m[5], r, w, partials, ctl);
   else
-    hipLaunchKernelGGL((k_gal_resid<T, 3>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
+    hipLaunchKernelGGL((k_gal_resid<T, 3>), dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
                        m[2], m[3], m[4], m[5], r, w, partials, ctl);
   return nb;
 }
@@ -2349,16 +2395,16 @@ int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char
 template <typename T>
 int launch_gal_rhs(const Geo& g, int c, const Sym<double>& sym, const unsigned char* m,
                    const double* S, const cpx<double>* sh, cpx<T>* r, double* partials,
-                   hipStream_t st) {
+                   hipStream_t st, int nsys, const double* S_sys) {
   const int nb = grid_for(g.Ns);
   if (c == 6)
-    hipLaunchKernelGGL((k_gal_rhs<T, 6>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
-                       m[2], m[3], m[4], m[5], S[0], S[1], S[2], S[3], S[4], S[5], sh, r,
-                       partials);
+    hipLaunchKernelGGL((k_gal_rhs<T, 6>), dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, sym, m[0],
+                       m[1], m[2], m[3], m[4], m[5], S[0], S[1], S[2], S[3], S[4], S[5], sh, r,
+                       partials, S_sys);
   else
-    hipLaunchKernelGGL((k_gal_rhs<T, 3>), dim3(nb), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
-                       m[2], m[3], m[4], m[5], S[0], S[1], S[2], S[3], S[4], S[5], sh, r,
-                       partials);
+    hipLaunchKernelGGL((k_gal_rhs<T, 3>), dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, sym, m[0],
+                       m[1], m[2], m[3], m[4], m[5], S[0], S[1], S[2], S[3], S[4], S[5], sh, r,
+                       partials, S_sys);
   return nb;
 }
 
@@ -2374,9 +2420,6 @@ void launch_project(const Geo& g, int c, const Sym<T>& sym, const unsigned char*
                        m[2], m[3], m[4], m[5], data);
 }
 
-// tiles per system of an outer-axis Helmholtz pass (TL lines each, no tile
-// across two systems)
-static inline int tiles_per_sys(long long inner, int TL) { return (int)((inner + TL - 1) / TL); }
 
 template <typename T>
 int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
@@ -2688,19 +2731,19 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, i
                                 int, hipStream_t);                                               \
   template void launch_strided<T>(const Plan&, const cpx<T>*, cpx<T>*, long long, long long,     \
                                   long long, long long, bool, const KrylovCtl*, hipStream_t,     \
-                                  int);                                                          \
+                                  int, long long);                                               \
   template int launch_gal_dir_inv<T>(const Plan&, const cpx<T>*, const Geo&, int, bool, cpx<T>*, \
                                      cpx<T>*, cpx<T>*, cpx<T>*, const KrylovCtl*, hipStream_t,   \
-                                     int);                                                       \
+                                     int, int);                                                  \
   template int launch_gal_dot_fwd<T>(const Plan&, const cpx<T>*, const Geo&, int, bool,          \
                                      const cpx<T>*, cpx<T>*, double*, const KrylovCtl*,          \
-                                     hipStream_t);                                               \
+                                     hipStream_t, int);                                          \
   template int launch_gal_resid<T>(const Geo&, int, const Sym<T>&, const unsigned char*,        \
                                     cpx<T>*, const cpx<T>*, double*, const KrylovCtl*,           \
-                                    hipStream_t);                                                \
+                                    hipStream_t, int);                                           \
   template int launch_gal_rhs<T>(const Geo&, int, const Sym<double>&, const unsigned char*,     \
                                   const double*, const cpx<double>*, cpx<T>*, double*,           \
-                                  hipStream_t);                                                  \
+                                  hipStream_t, int, const double*);                              \
   template void launch_project<T>(const Geo&, int, const Sym<T>&, const unsigned char*, cpx<T>*, \
                                   hipStream_t);                                                  \
   template int launch_h_dir_inv<T>(const Plan&, const cpx<T>*, const Geo&, bool, const Sym<T>&,  \
@@ -2718,7 +2761,7 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, i
   template void launch_hermitize<T>(const Geo&, int, cpx<T>*, hipStream_t);                     \
   template int launch_wnorm2<T>(const Geo&, int, const cpx<T>*, double*, hipStream_t, int);     \
   template void launch_x_fused_gal<T, T>(const Plan&, const cpx<T>*, const Geo&, int, cpx<T>*,   \
-                                         const T*, T, const KrylovCtl*, hipStream_t);            \
+                                         const T*, T, const KrylovCtl*, hipStream_t, int);       \
   template void launch_x_fused_helm<T, T>(const Plan&, const cpx<T>*, const Geo&, cpx<T>*,       \
                                           const T*, T, const KrylovCtl*, hipStream_t, int);      \
   template void launch_constitutive<T>(const MatTable&, const Geo&, int, int,                    \

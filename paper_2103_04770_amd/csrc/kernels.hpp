@@ -76,28 +76,35 @@ void launch_x_c2r(const Plan& p, const cpx<T>* tw, const cpx<T>* in, TO* out, lo
 template <typename T>
 void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nlines,
                     long long inner, long long ostride, long long es, bool fwd,
-                    const KrylovCtl* ctl, hipStream_t st, int sh = 0);
+                    const KrylovCtl* ctl, hipStream_t st, int sh = 0, long long lps = 0);
 
-// Galerkin CG passes
+// Galerkin CG passes.  Several systems of one grid (RVEs solved in lockstep)
+// are stacked: spectra [sys][comp][Ns], tangents [sys][N][8], control blocks
+// ctl[sys], partial sums [sys][...] (the int returned is the count per
+// system).
 template <typename T>
 int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, const KrylovCtl* ctl,
-                       hipStream_t st, int sh = 0);
+                       hipStream_t st, int sh = 0, int nsys = 1);
 template <typename T>
 int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        const cpx<T>* pp, cpx<T>* w, double* partials, const KrylovCtl* ctl,
-                       hipStream_t st);
+                       hipStream_t st, int nsys = 1);
 template <typename T, typename TT>
 void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
-                        const TT* tan, T scale, const KrylovCtl* ctl, hipStream_t st);
+                        const TT* tan, T scale, const KrylovCtl* ctl, hipStream_t st,
+                        int nsys = 1);
 template <typename T>
 int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char* mask6,
                       cpx<T>* r, const cpx<T>* w, double* partials, const KrylovCtl* ctl,
-                      hipStream_t st);
+                      hipStream_t st, int nsys = 1);
+// S_sys (optional): per-system mean stress targets [sys][6] in place of Sbar6;
+// partials [sys][2][count].
 template <typename T>
 int launch_gal_rhs(const Geo& g, int c, const Sym<double>& sym, const unsigned char* mask6,
                     const double* Sbar6, const cpx<double>* sig_hat, cpx<T>* r,
-                    double* partials, hipStream_t st);
+                    double* partials, hipStream_t st, int nsys = 1,
+                    const double* S_sys = nullptr);
 template <typename T>
 void launch_project(const Geo& g, int c, const Sym<T>& sym, const unsigned char* mask6,
                     cpx<T>* data, hipStream_t st);
