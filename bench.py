@@ -610,8 +610,11 @@ def run_adjoint_two_fields():
 def run_batch(count=64, nworkers=8):
     """One staggered increment (E11 = 1e-3) of 64 RVEs of uneven sizes
     (edges from {32, 48, 64, 96}, particle fractions U(0.05, 0.30)), FP32-refined,
-    driven one RVE at a time and then by the batched entry point; then the
-    batched loading of every RVE to E11 = 0.01 in 10 increments."""
+    three ways: every RVE alone on its own stream one at a time, the same with
+    `nworkers` host threads overlapping the RVEs, and as lockstep classes
+    (one per edge length, each Krylov iteration one set of launches over the
+    class; classes overlapping on the worker threads).  Then the lockstep
+    loading of every RVE to E11 = 0.01 in 10 increments."""
     import torch
     from paper_2103_04770_amd import FP32_REFINED, microstructure as ms
     from paper_2103_04770_amd.batch import RVEBatch
@@ -620,18 +623,36 @@ def run_batch(count=64, nworkers=8):
     b = RVEBatch(rves, prec=FP32_REFINED)
     tgt = ms.uniaxial_mixed(3, 1e-3)
     res = {}
-    for nw in (1, nworkers):
+    saved = os.environ.get("FFTG_BATCH_LOCKSTEP")
+    outs = {}
+    for mode, nw, lock in (("one_at_a_time", 1, "0"), ("per_rve_streams", nworkers, "0"),
+                           ("lockstep", nworkers, "1")):
+        os.environ["FFTG_BATCH_LOCKSTEP"] = lock
         b.reset()
+        b.step(tgt, nworkers=nw, **TOLS)  # warm-up: graphs, workspaces
+        b.reset()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = b.step(tgt, nworkers=nw, **TOLS)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        outs[mode] = out
         it = sum(o["cg_iters"] + o["pcg_iters"] for o in out)
-        res[nw] = dict(seconds=round(dt, 3), krylov_iters=it,
-                       voxel_krylov_iters_per_s=round(sum(
-                           int(np.prod(r["shape"])) * (o["cg_iters"] + o["pcg_iters"])
-                           for r, o in zip(rves, out)) / dt, 1),
-                       converged=sum(o["converged"] for o in out))
+        res[mode] = dict(seconds=round(dt, 3), workers=nw, krylov_iters=it,
+                         voxel_krylov_iters_per_s=round(sum(
+                             int(np.prod(r["shape"])) * (o["cg_iters"] + o["pcg_iters"])
+                             for r, o in zip(rves, out)) / dt, 1),
+                         converged=sum(o["converged"] for o in out))
+        log("[batch] %s (%d workers): %.3f s, %.3e voxel-Krylov-iters/s" % (
+            mode, nw, dt, res[mode]["voxel_krylov_iters_per_s"]))
+    if saved is None:
+        os.environ.pop("FFTG_BATCH_LOCKSTEP", None)
+    else:
+        os.environ["FFTG_BATCH_LOCKSTEP"] = saved
+    # lockstep and per-RVE runs agree bitwise (same arithmetic per RVE)
+    same = all(a["cg_iters"] == c["cg_iters"] and a["pcg_iters"] == c["pcg_iters"] and
+               np.array_equal(a["sigma_mean"], c["sigma_mean"])
+               for a, c in zip(outs["lockstep"], outs["per_rve_streams"]))
     # the whole loading of every RVE: 10 increments of 1e-3 to E11 = 0.01
     b.reset()
     vit = 0
@@ -653,13 +674,16 @@ def run_batch(count=64, nworkers=8):
     for r, sv in zip(rves, b.solvers):
         tiles.setdefault(str(r["shape"][0]), list(sv.tile_config()[:2]))
     b.close()
-    log("[batch] %d RVEs, %d voxels: one at a time %.2f s, %d workers %.2f s; "
-        "10 increments to E11 = 0.01 in %.2f s (%.2e voxel-Krylov-iters/s)" % (
-            count, vox, res[1]["seconds"], nworkers, res[nworkers]["seconds"], dpath, vit / dpath))
+    log("[batch] %d RVEs, %d voxels: one at a time %.2f s, per-RVE streams %.2f s, lockstep "
+        "%.2f s (results equal: %s); 10 lockstep increments to E11 = 0.01 in %.2f s "
+        "(%.2e voxel-Krylov-iters/s)" % (
+            count, vox, res["one_at_a_time"]["seconds"], res["per_rve_streams"]["seconds"],
+            res["lockstep"]["seconds"], same, dpath, vit / dpath))
     return dict(rves=count, voxels=vox, sizes=[32, 48, 64, 96], form="fp32_refined",
-                increment="E11 = 1e-3 from the virgin state", one_at_a_time=res[1],
-                batched=dict(res[nworkers], workers=nworkers),
-                speedup=round(res[1]["seconds"] / res[nworkers]["seconds"], 3),
+                increment="E11 = 1e-3 from the virgin state", **res,
+                lockstep_equals_per_rve=bool(same),
+                speedup_lockstep_vs_one_at_a_time=round(
+                    res["one_at_a_time"]["seconds"] / res["lockstep"]["seconds"], 3),
                 path_to_e11_0p01=path, tile_shifts_by_edge=tiles)
 
 

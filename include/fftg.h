@@ -447,14 +447,22 @@ typedef struct {
 } fftg_batch_item;
 
 /* One staggered increment (Algorithm 1) of each of n independent RVEs.
- * nworkers host threads take the items, largest grid first, and drive one
- * item's handle each at a time; since every handle enqueues on its own
- * stream, the kernels of different RVEs overlap on the GPU (a small RVE alone
- * cannot fill the 256 compute units).  Each item gets exactly the result of
- * staggered_step on its own.  Every item must have a distinct handle
- * (FFTG_E_INVALID otherwise).  Returns FFTG_OK when every item converged,
- * FFTG_NOT_CONVERGED when one did not, else the most negative item code; the
- * per-item codes and error texts (fftg_last_error(item.h)) remain valid. */
+ * Items of one grid, voxel size, derivative scheme, precision, field count
+ * and macro mask form a class that advances in lockstep on the handle of its
+ * first item (on that handle's stream): every Galerkin CG and Helmholtz PCG
+ * iteration is one set of launches over all RVEs of the class, each RVE with
+ * its own scalars, stop test and targets, and an RVE that has met its test
+ * skipped by every launch.  The class grows that handle's workspace to hold
+ * all its RVEs (kept until the handle is destroyed).  nworkers host threads
+ * take the classes (and lone items), largest first, so that different
+ * classes overlap on the GPU.  FFTG_BATCH_LOCKSTEP=0 in the environment runs
+ * every item alone on its own handle and stream instead.  Either way each
+ * item gets exactly (bitwise) the result of staggered_step on its own.
+ * Every item must have a distinct handle (FFTG_E_INVALID otherwise).
+ * Returns FFTG_OK when every item converged, FFTG_NOT_CONVERGED when one did
+ * not, else the most negative item code; the per-item codes and error texts
+ * (fftg_last_error(item.h)) remain valid.  The handles must not be used by
+ * other threads during the call. */
 fftg_status fftg_batch_step(fftg_batch_item* items, int n, int nworkers,
                             const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
                             double newton_tol, int newton_maxit, double stagger_tol,

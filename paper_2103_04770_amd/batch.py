@@ -2,8 +2,10 @@
 
 Each RVE gets its own Solver on its own HIP stream (default priority), its
 own device state and stress; one call advances every RVE by one staggered
-increment, the library's worker threads driving several RVEs at once so that
-their kernels overlap on the GPU.
+increment.  RVEs of one grid (and precision, field count and macro mask) run
+as one lockstep class on the first one's handle, each Krylov iteration one
+set of launches over all of them; the library's worker threads drive
+several classes at once so that their kernels overlap on the GPU.
 """
 from __future__ import annotations
 
@@ -43,10 +45,12 @@ class RVEBatch:
         self.torch.cuda.synchronize()
 
     def step(self, targets, nworkers=8, cg_tol=1e-8, cg_maxit=5000, pcg_tol=1e-8,
-             pcg_maxit=2000, newton_tol=1e-8, newton_maxit=50, stagger_tol=1e-6, max_stagger=20):
+             pcg_maxit=2000, newton_tol=1e-8, newton_maxit=50, stagger_tol=1e-6, max_stagger=20,
+             strict=True):
         """One staggered increment of every RVE; targets: one (mask, E, S) per
         RVE, or a single one for all.  Returns per-RVE dicts (stats, converged,
-        sigma_mean, eps_mean)."""
+        sigma_mean, eps_mean, status).  strict: raise FFTGError when an RVE
+        failed (else its dict holds the status and the error text)."""
         n = len(self.rves)
         if not isinstance(targets, list):
             targets = [targets] * n
@@ -69,14 +73,19 @@ class RVEBatch:
         for i in range(n):
             it = items[i]
             if it.status < 0:
-                raise FFTGError(it.status, self.lib.fftg_last_error(self.solvers[i].h).decode())
+                msg = self.lib.fftg_last_error(self.solvers[i].h).decode()
+                if strict:
+                    raise FFTGError(it.status, msg)
+                out.append(dict(status=it.status, error=msg, converged=False))
+                continue
             c = self.solvers[i].c
             d = it.stats.as_dict()
             d["converged"] = it.status == 0
+            d["status"] = it.status
             d["sigma_mean"] = np.array(it.homog_out[:c])
             d["eps_mean"] = np.array(it.homog_out[6:6 + c])
             out.append(d)
-        if rc < 0:
+        if rc < 0 and strict:
             raise FFTGError(rc, "batch step failed")
         return out
 

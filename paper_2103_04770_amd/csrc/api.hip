@@ -66,6 +66,16 @@ struct Fail {
   std::string msg;
 };
 
+// Workspace of a lockstep batch class (several RVEs of one grid solved as
+// stacked systems): FP64 fields [sys][comp][N], ell2 [sys][J][N].
+struct BatchWS {
+  int cap_sys = 0, cap_J = 0;
+  double *eps_k = nullptr, *eps_prev = nullptr, *sig_k = nullptr, *st1 = nullptr,
+         *Dj = nullptr, *alph = nullptr, *ab_k = nullptr, *ab_prev = nullptr,
+         *ell2j64 = nullptr;
+  void* ell2j = nullptr;  // work precision
+};
+
 }  // namespace
 
 struct fftg_handle {
@@ -89,10 +99,15 @@ struct fftg_handle {
   unsigned char mask_last[6] = {0, 1, 1, 1, 1, 1};
   double* partials = nullptr;
   size_t npartials = 0;
+  long long psys = 0;  // partial sums one system of a lockstep solve may need
   double* dsums = nullptr;
   KrylovCtl* ctl = nullptr;
   KrylovCtl* hctl = nullptr;  // pinned
   double* hsums = nullptr;    // pinned
+  // control blocks held (and 2 sys_cap + 64 sums); systems the Galerkin
+  // workspace holds (stacked [sys][c][Ns], tangent [sys][N][8])
+  int sys_cap = FFTG_MAX_FIELDS, gal_cap = 1;
+  BatchWS* bws = nullptr;  // lockstep batch class workspace (lead handle of a class)
   // Helmholtz workspace (work precision), scalar half spectra + ndim gradient comps
   void *hx = nullptr, *hr = nullptr, *hp = nullptr, *hAp = nullptr, *hb = nullptr,
        *hw = nullptr;
@@ -342,6 +357,77 @@ void read_sums(fftg_handle* H, int nb, int nred, double* out) {
   for (int i = 0; i < nred; ++i) out[i] = H->hsums[i];
 }
 
+// The captured Krylov graphs hold the workspace pointers: drop them before a
+// buffer they use is reallocated.
+void drop_graphs(fftg_handle* H) {
+  HIPCHK(hipStreamSynchronize(H->st));
+  if (H->ggal.exec) (void)hipGraphExecDestroy(H->ggal.exec);
+  H->ggal.exec = nullptr;
+  H->ggal.key = 0;
+  for (auto& sl : H->ghelm) {
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    sl.exec = nullptr;
+    sl.key = 0;
+  }
+}
+
+// Control blocks, sums and partials for a lockstep solve of n systems.
+void ensure_sys(fftg_handle* H, int n) {
+  const bool ctl_ok = n <= H->sys_cap;
+  const bool part_ok = (size_t)n * (size_t)H->psys <= H->npartials;
+  if (ctl_ok && part_ok) return;
+  if (H->nograph) throw Fail{FFTG_E_UNSUPPORTED, "lockstep solve too large for this workspace"};
+  drop_graphs(H);
+  if (!ctl_ok) {
+    dfree((void*&)H->ctl);
+    dfree((void*&)H->dsums);
+    if (H->hctl) (void)hipHostFree(H->hctl);
+    if (H->hsums) (void)hipHostFree(H->hsums);
+    H->hctl = nullptr;
+    H->hsums = nullptr;
+    H->ctl = (KrylovCtl*)dalloc(sizeof(KrylovCtl) * (size_t)n);
+    H->dsums = (double*)dalloc(sizeof(double) * (2 * (size_t)n + 64));
+    HIPCHK(hipHostMalloc((void**)&H->hctl, sizeof(KrylovCtl) * (size_t)n, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * (2 * (size_t)n + 64),
+                         hipHostMallocDefault));
+    H->sys_cap = n;
+  }
+  if (!part_ok) {
+    dfree((void*&)H->partials);
+    H->npartials = (size_t)n * (size_t)H->psys;
+    H->partials = (double*)dalloc(sizeof(double) * H->npartials);
+  }
+}
+
+void free_bws(fftg_handle* H) {
+  BatchWS* B = H->bws;
+  if (!B) return;
+  for (double** p : {&B->eps_k, &B->eps_prev, &B->sig_k, &B->st1, &B->Dj, &B->alph, &B->ab_k,
+                     &B->ab_prev, &B->ell2j64})
+    dfree((void*&)*p);
+  dfree(B->ell2j);
+  delete B;
+  H->bws = nullptr;
+}
+
+// Galerkin workspace for nsys stacked systems.
+void alloc_gal(fftg_handle* H, int nsys) {
+  if (nsys <= H->gal_cap) return;
+  drop_graphs(H);
+  const Geo& g = H->g;
+  for (void** p : {&H->kx, &H->kr, &H->kp, &H->kw, &H->tan}) dfree(*p);
+  dfree((void*&)H->spec64);
+  const size_t cs_bytes = 2 * H->wsz() * (size_t)H->c * g.Ns * (size_t)nsys;
+  H->kx = dalloc(cs_bytes);
+  H->kr = dalloc(cs_bytes);
+  H->kp = dalloc(cs_bytes);
+  H->kw = dalloc(cs_bytes);
+  H->spec64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * 6 * g.Ns * (size_t)nsys);
+  H->tan = dalloc(H->wsz() * 8 * (size_t)g.N * (size_t)nsys);
+  H->tan_valid = false;
+  H->gal_cap = nsys;
+}
+
 // tile shift of a strided pass along plan axis a (1 = y, 2 = z): the outer
 // axis (z in 3D, y in 2D) takes the outer-pass choice, y in 3D the inner one
 int tsh(const fftg_handle* H, int a) { return a == (H->g.ndim == 3 ? 2 : 1) ? H->tsh_o : H->tsh_y; }
@@ -388,22 +474,26 @@ void inv3(fftg_handle* H, int ncomp, cpx<T>* in, TO* out, T scale, bool acc) {
                             g.n1, g.n1h, scale, acc, H->st);
 }
 
-// inner (non-outer) passes of an operator application on an ncomp spectrum
+// inner (non-outer) passes of an operator application on an ncomp spectrum;
+// ctl: the control blocks of the stacked systems, lps lines each (0: one
+// system)
 template <typename T>
-void inner_inv(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int kid) {
+void inner_inv(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int kid,
+               long long lps = 0) {
   const Geo& g = H->g;
   KT t(H, kid);
   if (g.ndim == 3 && g.n2 > 1)
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), w, (long long)ncomp * g.n3 * g.n1h, g.n1h,
-                            (long long)g.n2 * g.n1h, g.n1h, false, ctl, H->st, H->tsh_y);
+                            (long long)g.n2 * g.n1h, g.n1h, false, ctl, H->st, H->tsh_y, lps);
 }
 template <typename T>
-void inner_fwd(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int kid) {
+void inner_fwd(fftg_handle* H, int ncomp, cpx<T>* w, const KrylovCtl* ctl, int kid,
+               long long lps = 0) {
   const Geo& g = H->g;
   KT t(H, kid);
   if (g.ndim == 3 && g.n2 > 1)
     fftg::launch_strided<T>(H->plan[1], TW<T>(H, 1), w, (long long)ncomp * g.n3 * g.n1h, g.n1h,
-                            (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st, H->tsh_y);
+                            (long long)g.n2 * g.n1h, g.n1h, true, ctl, H->st, H->tsh_y, lps);
 }
 int outer_axis(fftg_handle* H) { return H->g.ndim == 3 ? 2 : 1; }
 
@@ -510,45 +600,48 @@ void validate_macro(const fftg_macro* t, int c) {
     if (t->mask[k] > 1) throw Fail{FFTG_E_INVALID, "macro mask entries must be 0 or 1"};
 }
 
-// One Galerkin CG iteration: 6 passes + 2 scalar kernels, all on H->st.
+// One Galerkin CG iteration of nsys stacked systems (RVEs of one grid, each
+// with its own scalars; spectra [sys][c][Ns], tangent [sys][N][8]): 6 passes
+// + 2 scalar kernels, all on H->st.
 template <typename T>
-void gal_iteration(fftg_handle* H, const unsigned char* mask) {
+void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1) {
   const Geo& g = H->g;
   const int c = H->c;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
   const T scl = T(1.0 / (double)g.N);
+  const long long lps = (long long)c * g.n3 * g.n1h;  // y lines per system
   {
     KT t(H, K_GAL_OI);
     fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr), C<T>(H->kp),
-                                C<T>(H->kx), C<T>(H->kw), H->ctl, H->st, H->tsh_o);
+                                C<T>(H->kx), C<T>(H->kw), H->ctl, H->st, H->tsh_o, nsys);
   }
-  inner_inv<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YI);
+  inner_inv<T>(H, c * nsys, C<T>(H->kw), H->ctl, K_GAL_YI, lps);
   {
     KT t(H, K_GAL_X);
     fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
-                                   reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st);
+                                   reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st, nsys);
   }
-  inner_fwd<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YF);
+  inner_fwd<T>(H, c * nsys, C<T>(H->kw), H->ctl, K_GAL_YF, lps);
   int nb;
   {
     KT t(H, K_GAL_OF);
     nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
-                                     C<T>(H->kw), H->partials, H->ctl, H->st);
+                                     C<T>(H->kw), H->partials, H->ctl, H->st, nsys);
   }
   {
     KT t(H, K_SMALL);
-    fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st);
+    fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st, nsys);
   }
   int nr;
   {
     KT t(H, K_GAL_RES);
     nr = fftg::launch_gal_resid<T>(g, c, SY<T>(H), mask, C<T>(H->kr), C<T>(H->kw), H->partials,
-                                   H->ctl, H->st);
+                                   H->ctl, H->st, nsys);
   }
   {
     KT t(H, K_SMALL);
-    fftg::launch_fin_beta(H->partials, nr, 1, H->ctl, H->st);
+    fftg::launch_fin_beta(H->partials, nr, 1, H->ctl, H->st, nsys);
   }
 }
 
@@ -584,60 +677,82 @@ hipGraphExec_t capture(fftg_handle* H, F body) {
 }
 
 template <typename T>
-hipGraphExec_t gal_graph(fftg_handle* H, const unsigned char* mask) {
+hipGraphExec_t gal_graph(fftg_handle* H, const unsigned char* mask, int nsys) {
   unsigned long long key = 1ull + (H->fp32() ? 2ull : 0ull);
   for (int i = 0; i < 6; ++i) key |= (unsigned long long)(mask[i] & 1) << (8 + i);
+  key |= (unsigned long long)nsys << 16;
   if (H->ggal.exec && H->ggal.key == key) return H->ggal.exec;
   if (H->ggal.exec) (void)hipGraphExecDestroy(H->ggal.exec);
   H->ggal.exec = nullptr;
   unsigned char m[6];
   std::memcpy(m, mask, 6);
-  H->ggal.exec = capture(H, [&]() { gal_iteration<T>(H, m); });
+  H->ggal.exec = capture(H, [&]() { gal_iteration<T>(H, m, nsys); });
   H->ggal.key = key;
   return H->ggal.exec;
 }
 
 // ------------------------------------------------------------ Galerkin CG
-// Solves G*(K : dx) = b in the half spectrum, b in H->kr, dx -> H->kx.
+// Solves G*(K_s : dx_s) = b_s in the half spectrum for nsys stacked systems
+// in lockstep (b in H->kr, dx -> H->kx, [sys][c][Ns]), each with its own
+// scalars and stop test; systems with need[s] = 0 or bb[s] = 0 start as done
+// (dx_s = 0).  k[s]: the final control block of system s.
 template <typename T>
-void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double tol, int maxit,
-                 int& iters, int& status) {
+void galerkin_cg_n(fftg_handle* H, const unsigned char* mask, int nsys, const double* bb,
+                   const unsigned char* need, double tol, int maxit, KrylovCtl* k) {
   const Geo& g = H->g;
   const int c = H->c;
-  KrylovCtl k{};
-  k.rz = bb;
-  k.rr = bb;
-  k.bb = bb;
-  k.tol2 = tol * tol * bb;
-  k.rrmin = bb;
-  k.maxit = maxit;
-  k.window = std::is_same<T, float>::value ? kFp32StagnationWindow : 0;
-  k.done = bb == 0.0 ? 1 : (maxit <= 0 ? 2 : 0);
-  write_ctl(H, k);
-  HIPCHK(hipMemsetAsync(H->kx, 0, sizeof(cpx<T>) * c * g.Ns, H->st));
-  HIPCHK(hipMemsetAsync(H->kp, 0, sizeof(cpx<T>) * c * g.Ns, H->st));
+  bool all = true;
+  for (int q = 0; q < nsys; ++q) {
+    k[q] = KrylovCtl{};
+    k[q].rz = bb[q];
+    k[q].rr = bb[q];
+    k[q].bb = bb[q];
+    k[q].tol2 = tol * tol * bb[q];
+    k[q].rrmin = bb[q];
+    k[q].maxit = maxit;
+    k[q].window = std::is_same<T, float>::value ? kFp32StagnationWindow : 0;
+    k[q].done = (!need[q] || bb[q] == 0.0) ? 1 : (maxit <= 0 ? 2 : 0);
+    all = all && k[q].done;
+  }
+  write_ctls(H, nsys, k);
+  HIPCHK(hipMemsetAsync(H->kx, 0, sizeof(cpx<T>) * c * g.Ns * nsys, H->st));
+  HIPCHK(hipMemsetAsync(H->kp, 0, sizeof(cpx<T>) * c * g.Ns * nsys, H->st));
   if (!H->prof) {
-    hipGraphExec_t ex = gal_graph<T>(H, mask);
-    while (!k.done) {
+    hipGraphExec_t ex = gal_graph<T>(H, mask, nsys);
+    while (!all) {
       HIPCHK(hipGraphLaunch(ex, H->st));
-      k = read_ctl(H);
+      read_ctls(H, nsys, k);
+      all = true;
+      for (int q = 0; q < nsys; ++q) all = all && k[q].done;
     }
   } else {
     int chunk = 2;
-    while (!k.done) {
-      const int before = k.iters;
+    while (!all) {
+      int before = 0;
+      for (int q = 0; q < nsys; ++q) before = std::max(before, k[q].iters);
       for (int it = 0; it < chunk; ++it) {
         H->kt_iter = it;
-        gal_iteration<T>(H, mask);
+        gal_iteration<T>(H, mask, nsys);
       }
       H->kt_iter = -1;
       check_launch();
-      k = read_ctl(H, before);
+      read_ctls(H, nsys, k, before);
+      all = true;
+      for (int q = 0; q < nsys; ++q) all = all && k[q].done;
       if (chunk < 16) chunk *= 2;
     }
   }
-  fftg::launch_xfinal<T>(C<T>(H->kx), C<T>(H->kp), (long long)c * g.Ns, H->ctl, H->st);
+  fftg::launch_xfinal<T>(C<T>(H->kx), C<T>(H->kp), (long long)c * g.Ns, H->ctl, H->st, nsys);
   check_launch();
+}
+
+// One system: b in H->kr, dx -> H->kx.
+template <typename T>
+void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double tol, int maxit,
+                 int& iters, int& status) {
+  const unsigned char need = 1;
+  KrylovCtl k{};
+  galerkin_cg_n<T>(H, mask, 1, &bb, &need, tol, maxit, &k);
   iters = k.iters;
   status = k.done;
 }
@@ -767,8 +882,8 @@ void helm_krylov(fftg_handle* H, const T* ell2, int nsys, const double* ell2_ref
   const int nr0 = fftg::launch_h_resid<T>(g, SY<T>(H), true, C<T>(H->hr), C<T>(H->hb),
                                           x0_zero ? C<T>(H->hx) : C<T>(H->hAp), H->partials,
                                           H->ctl, H->st, nsys);
-  double s2[2 * FFTG_MAX_FIELDS];
-  read_sums(H, nr0, 2 * nsys, s2);
+  std::vector<double> s2(2 * (size_t)nsys);
+  read_sums(H, nr0, 2 * nsys, s2.data());
   bool all = true;
   for (int q = 0; q < nsys; ++q) {
     k[q].rz = s2[2 * q];
@@ -831,13 +946,19 @@ void ell2_reference(fftg_handle* H, const T* ell2, double ell2_ref, int nsys, do
 
 // Transforms of nsys stacked scalar fields, one field at a time: the x pass
 // transforms two real lines as one complex line, which would leave rounding
-// of one field's magnitude in the other.
-void fwd_fields(fftg_handle* H, int nsys, const double* in, cpx<double>* out) {
-  for (int q = 0; q < nsys; ++q) fwd3<double>(H, 1, in + q * H->g.N, out + q * H->g.Ns);
-}
-void inv_fields(fftg_handle* H, int nsys, cpx<double>* in, double* out) {
+// of one field's magnitude in the other.  Fields with skip[q] set are left
+// alone.
+void fwd_fields(fftg_handle* H, int nsys, const double* in, cpx<double>* out,
+                const unsigned char* skip = nullptr) {
   for (int q = 0; q < nsys; ++q)
-    inv3<double, double>(H, 1, in + q * H->g.Ns, out + q * H->g.N, 1.0 / (double)H->g.N, false);
+    if (!skip || !skip[q]) fwd3<double>(H, 1, in + q * H->g.N, out + q * H->g.Ns);
+}
+void inv_fields(fftg_handle* H, int nsys, cpx<double>* in, double* out,
+                const unsigned char* skip = nullptr) {
+  for (int q = 0; q < nsys; ++q)
+    if (!skip || !skip[q])
+      inv3<double, double>(H, 1, in + q * H->g.Ns, out + q * H->g.N, 1.0 / (double)H->g.N,
+                           false);
 }
 
 // Outcome of one Helmholtz system: PCG iterations, final relative residual,
@@ -849,28 +970,34 @@ struct HelmOut {
 };
 
 // FP64 handles: solves L abar_s = alpha_s for nsys stacked fields (alpha,
-// ell2, abar [sys][N] FP64; abar in = x0), the whole PCG in FP64.
+// ell2, abar [sys][N] FP64; abar in = x0), the whole PCG in FP64.  Fields
+// with skip[q] set are not solved and their abar is left alone.
 void helmholtz_pcg64(fftg_handle* H, const double* alpha, const double* ell2, double ell2_ref,
-                     double* abar, double tol, int maxit, int nsys, HelmOut* out) {
+                     double* abar, double tol, int maxit, int nsys, HelmOut* out,
+                     const unsigned char* skip = nullptr) {
   const Geo& g = H->g;
-  fwd_fields(H, nsys, alpha, C<double>(H->hb));
+  fwd_fields(H, nsys, alpha, C<double>(H->hb), skip);
+  std::vector<double> bb(nsys), ref(nsys), tols(nsys);
+  std::vector<int> mits(nsys);
+  for (int q = 0; q < nsys; ++q)
+    if (skip && skip[q])
+      HIPCHK(hipMemsetAsync(C<double>(H->hb) + q * g.Ns, 0, sizeof(cpx<double>) * g.Ns, H->st));
   fftg::launch_hermitize<double>(g, nsys, C<double>(H->hb), H->st);
-  double bb[FFTG_MAX_FIELDS], ref[FFTG_MAX_FIELDS], tols[FFTG_MAX_FIELDS];
-  int mits[FFTG_MAX_FIELDS];
   read_sums(H, fftg::launch_wnorm2<double>(g, 1, C<double>(H->hb), H->partials, H->st, nsys),
-            nsys, bb);
-  ell2_reference<double>(H, ell2, ell2_ref, nsys, ref);
-  fwd_fields(H, nsys, abar, C<double>(H->hx));
+            nsys, bb.data());
+  ell2_reference<double>(H, ell2, ell2_ref, nsys, ref.data());
+  fwd_fields(H, nsys, abar, C<double>(H->hx), skip);
   for (int q = 0; q < nsys; ++q) {
-    tols[q] = tol;
+    tols[q] = skip && skip[q] ? -1.0 : tol;
     mits[q] = maxit;
     // a zero source has the zero solution
     if (bb[q] == 0.0)
       HIPCHK(hipMemsetAsync(C<double>(H->hx) + q * g.Ns, 0, sizeof(cpx<double>) * g.Ns, H->st));
   }
-  KrylovCtl k[FFTG_MAX_FIELDS];
-  helm_krylov<double>(H, ell2, nsys, ref, bb, tols, mits, false, k);
-  inv_fields(H, nsys, C<double>(H->hx), abar);
+  std::vector<KrylovCtl> k(nsys);
+  helm_krylov<double>(H, ell2, nsys, ref.data(), bb.data(), tols.data(), mits.data(), false,
+                      k.data());
+  inv_fields(H, nsys, C<double>(H->hx), abar, skip);
   check_launch();
   for (int q = 0; q < nsys; ++q) {
     if (verbose())
@@ -914,7 +1041,7 @@ constexpr int kHelmSweeps = 30;
 // residual (5: the attainable accuracy is reached); the others go on.
 void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32,
                        const double* ell2_64, double ell2_ref, double* abar, double tol,
-                       int maxit, int nsys, HelmOut* out) {
+                       int maxit, int nsys, HelmOut* out, const unsigned char* skip = nullptr) {
   const Geo& g = H->g;
   const long long Ns = g.Ns;
   cpx<double>* S = H->spec64;
@@ -931,21 +1058,27 @@ void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32
   cpx<double>* x = S + nsys * Ns;
   cpx<double>* w = S + 2 * nsys * Ns;
   cpx<double>* Ax = S + 5 * nsys * Ns;
-  fwd_fields(H, nsys, alpha, b);
+  fwd_fields(H, nsys, alpha, b, skip);
+  for (int q = 0; q < nsys; ++q)
+    if (skip && skip[q]) {
+      HIPCHK(hipMemsetAsync(b + q * Ns, 0, sizeof(cpx<double>) * Ns, H->st));
+      HIPCHK(hipMemsetAsync(x + q * Ns, 0, sizeof(cpx<double>) * Ns, H->st));
+    }
   fftg::launch_hermitize<double>(g, nsys, b, H->st);
-  double bb[FFTG_MAX_FIELDS], ref[FFTG_MAX_FIELDS], rr[FFTG_MAX_FIELDS],
-      rr_prev[FFTG_MAX_FIELDS], tin[FFTG_MAX_FIELDS];
-  int mits[FFTG_MAX_FIELDS];
-  read_sums(H, fftg::launch_wnorm2<double>(g, 1, b, H->partials, H->st, nsys), nsys, bb);
-  ell2_reference<float>(H, ell2_32, ell2_ref, nsys, ref);
-  fwd_fields(H, nsys, abar, x);
+  std::vector<double> bb(nsys), ref(nsys), rr(nsys), rr_prev(nsys), tin(nsys);
+  std::vector<int> mits(nsys);
+  read_sums(H, fftg::launch_wnorm2<double>(g, 1, b, H->partials, H->st, nsys), nsys, bb.data());
+  ell2_reference<float>(H, ell2_32, ell2_ref, nsys, ref.data());
+  fwd_fields(H, nsys, abar, x, skip);
   fftg::launch_hermitize<double>(g, nsys, x, H->st);
   int active = 0;
   for (int q = 0; q < nsys; ++q) {
     out[q] = HelmOut{};
     rr[q] = 0.0;
     rr_prev[q] = HUGE_VAL;
-    if (bb[q] == 0.0) {
+    if (skip && skip[q]) {
+      out[q].status = 1;  // not solved here
+    } else if (bb[q] == 0.0) {
       // a zero source has the zero solution
       HIPCHK(hipMemsetAsync(x + q * Ns, 0, sizeof(cpx<double>) * Ns, H->st));
       out[q].status = 1;
@@ -956,7 +1089,7 @@ void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32
   for (int sweep = 0; active > 0; ++sweep) {
     helm_apply64(H, x, w, Ax, ell2_64, nsys);
     read_sums(H, fftg::launch_h_refine_resid(g, b, Ax, C<float>(H->hb), H->partials, H->st, nsys),
-              nsys, rr);
+              nsys, rr.data());
     for (int q = 0; q < nsys; ++q) {
       tin[q] = -1.0;  // no correction for this field
       mits[q] = 0;
@@ -980,8 +1113,9 @@ void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32
       mits[q] = maxit - out[q].iters;
     }
     if (active == 0) break;
-    KrylovCtl k[FFTG_MAX_FIELDS];
-    helm_krylov<float>(H, ell2_32, nsys, ref, rr, tin, mits, true, k);
+    std::vector<KrylovCtl> k(nsys);
+    helm_krylov<float>(H, ell2_32, nsys, ref.data(), rr.data(), tin.data(), mits.data(), true,
+                       k.data());
     for (int q = 0; q < nsys; ++q) {
       if (tin[q] < 0.0) continue;
       out[q].iters += k[q].iters;
@@ -993,9 +1127,10 @@ void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32
     fftg::launch_acc_wide<float>(2 * Ns * nsys, reinterpret_cast<const float*>(H->hx),
                                  reinterpret_cast<double*>(x), H->st);
   }
-  inv_fields(H, nsys, x, abar);
+  inv_fields(H, nsys, x, abar, skip);
   check_launch();
   for (int q = 0; q < nsys; ++q) {
+    if (skip && skip[q]) continue;
     if (verbose())
       std::fprintf(stderr, "[fftg] refined pcg field %d iters %d status %d rr/bb %.3e ell2ref %.4g\n",
                    q, out[q].iters, out[q].status, bb[q] > 0 ? rr[q] / bb[q] : 0.0, ref[q]);
@@ -1006,16 +1141,18 @@ void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32
 // Algorithm 2 for nsys stacked fields on the handle's precision: ell2w is
 // the work-precision ell2 [sys][N] (FP32 on FP32-refined handles), ell2_64
 // the FP64 one (read by the FP64 residuals of the refinement; equal to ell2w
-// on FP64 handles).
+// on FP64 handles).  skip (optional): fields not to solve (abar untouched).
 void helm_solve(fftg_handle* H, const double* alpha, const void* ell2w, const double* ell2_64,
-                double ell2_ref, double* abar, double tol, int maxit, int nsys, HelmOut* out) {
-  if (nsys < 1 || nsys > FFTG_MAX_FIELDS) throw Fail{FFTG_E_INVALID, "1 to 4 Helmholtz fields"};
+                double ell2_ref, double* abar, double tol, int maxit, int nsys, HelmOut* out,
+                const unsigned char* skip = nullptr) {
+  if (nsys < 1) throw Fail{FFTG_E_INVALID, "no Helmholtz field"};
+  ensure_sys(H, nsys);
   alloc_helm(H, nsys);
   if (H->fp32())
     helmholtz_refined(H, alpha, reinterpret_cast<const float*>(ell2w), ell2_64, ell2_ref, abar,
-                      tol, maxit, nsys, out);
+                      tol, maxit, nsys, out, skip);
   else
-    helmholtz_pcg64(H, alpha, ell2_64, ell2_ref, abar, tol, maxit, nsys, out);
+    helmholtz_pcg64(H, alpha, ell2_64, ell2_ref, abar, tol, maxit, nsys, out, skip);
 }
 
 // ------------------------------------------------------------ mechanics
@@ -1025,18 +1162,25 @@ void helm_solve(fftg_handle* H, const double* alpha, const void* ell2w, const do
 // FP32 iteration and an FP32 inverse leave rounding outside the compatible
 // space range(G*) (~1e-7 of the correction), which the FP64 Newton residual
 // G*(sigma - Sbar) cannot see and so would never remove from the strain.
+// kx: the solution spectrum (work precision), spec: an FP64 c-component
+// spectrum of scratch.
 template <typename T>
-void galerkin_solution(fftg_handle* H, const unsigned char* mask, double* out, bool acc) {
+void galerkin_solution_at(fftg_handle* H, const unsigned char* mask, void* kx,
+                          cpx<double>* spec, double* out, bool acc) {
   const Geo& g = H->g;
   const int c = H->c;
   if (std::is_same<T, float>::value) {
-    fftg::launch_convert<float, double>(2LL * c * g.Ns, reinterpret_cast<const float*>(H->kx),
-                                        reinterpret_cast<double*>(H->spec64), H->st);
-    fftg::launch_project<double>(g, c, H->S64, mask, H->spec64, H->st);
-    inv3<double, double>(H, c, H->spec64, out, 1.0 / (double)g.N, acc);
+    fftg::launch_convert<float, double>(2LL * c * g.Ns, reinterpret_cast<const float*>(kx),
+                                        reinterpret_cast<double*>(spec), H->st);
+    fftg::launch_project<double>(g, c, H->S64, mask, spec, H->st);
+    inv3<double, double>(H, c, spec, out, 1.0 / (double)g.N, acc);
   } else {
-    inv3<T, double>(H, c, C<T>(H->kx), out, T(1.0 / (double)g.N), acc);
+    inv3<T, double>(H, c, C<T>(kx), out, T(1.0 / (double)g.N), acc);
   }
+}
+template <typename T>
+void galerkin_solution(fftg_handle* H, const unsigned char* mask, double* out, bool acc) {
+  galerkin_solution_at<T>(H, mask, H->kx, H->spec64, out, acc);
 }
 
 struct MechOut {
@@ -1230,6 +1374,7 @@ void destroy(fftg_handle* H) {
   dfree(H->ell2j);
   dfree((void*&)H->ell2j64);
   dfree((void*&)H->drive_bak);
+  free_bws(H);
   dfree((void*&)H->adj_r);
   dfree((void*&)H->sadj);
   dfree((void*&)H->hadj);
@@ -1457,6 +1602,445 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
   out.stats = acc;
   out.converged = converged;
   return out;
+}
+
+// ------------------------------------------------------------ lockstep batch
+// Several RVEs of one grid, precision, field count and macro mask (a class)
+// advance through one increment of Algorithm 1 together, stacked on the lead
+// handle's workspace: each Galerkin CG iteration and each Helmholtz PCG
+// iteration is one set of launches over all of them (per-RVE scalars, stop
+// tests and control blocks; an RVE that has met its test returns at once
+// from every launch), while the per-voxel and once-per-Newton-step work runs
+// RVE by RVE.  Every RVE takes exactly the arithmetic of its own
+// staggered_step: no tile, line pair or reduction spans two RVEs.
+
+// One RVE of a class: its item, table and packed state, its slot views of
+// the class workspace, and its progress through the increment.
+struct BSys {
+  fftg_batch_item* it = nullptr;
+  MatTable tab{};
+  int q = 0;  // slot
+  double *s_eps = nullptr, *s_epsp = nullptr, *s_hist = nullptr, *s_abar = nullptr;
+  double *eps = nullptr, *eps_prev = nullptr, *sig = nullptr, *st1 = nullptr, *D = nullptr,
+         *alph = nullptr, *ab = nullptr, *ab_prev = nullptr;
+  void *tan = nullptr, *kx = nullptr, *kr = nullptr;
+  cpx<double>* spec = nullptr;
+  double Sbar[6] = {0, 0, 0, 0, 0, 0};
+  double sref = 1.0;
+  bool live = true;  // still in the staggered loop
+  bool converged = false, inner_ok = false, committed = false;
+  fftg_status fail = FFTG_OK;
+  std::string msg;
+  fftg_stats acc{};
+  // Newton loop of the current pass
+  MechOut o;
+  int r = 0;
+  bool nl = false;
+};
+
+void bsys_fail(BSys& s, fftg_status code, const char* msg) {
+  s.fail = code;
+  s.msg = msg;
+  s.live = false;
+  s.nl = false;
+}
+
+void alloc_bws(fftg_handle* H, int nsys, int J) {
+  const int Jm = std::max(J, 1);
+  if (H->bws && H->bws->cap_sys >= nsys && H->bws->cap_J >= Jm) return;
+  drop_graphs(H);  // the Helmholtz graphs may hold the old ell2
+  free_bws(H);
+  BatchWS* B = new BatchWS();
+  H->bws = B;
+  const size_t N = H->g.N, n = nsys, c = H->c;
+  B->eps_k = (double*)dalloc(sizeof(double) * c * N * n);
+  B->eps_prev = (double*)dalloc(sizeof(double) * c * N * n);
+  B->sig_k = (double*)dalloc(sizeof(double) * c * N * n);
+  B->st1 = (double*)dalloc(sizeof(double) * 7 * N * n);
+  B->Dj = (double*)dalloc(sizeof(double) * Jm * N * n);
+  B->alph = (double*)dalloc(sizeof(double) * Jm * N * n);
+  B->ab_k = (double*)dalloc(sizeof(double) * Jm * N * n);
+  B->ab_prev = (double*)dalloc(sizeof(double) * Jm * N * n);
+  B->ell2j = dalloc(H->wsz() * Jm * N * n);
+  if (H->fp32()) B->ell2j64 = (double*)dalloc(sizeof(double) * Jm * N * n);
+  B->cap_sys = nsys;
+  B->cap_J = Jm;
+}
+
+// The Newton loop of Algorithm 1 (i) for every live RVE of a class (the
+// steps of mechanics(), RVE by RVE, with one lockstep Galerkin CG per Newton
+// step over the RVEs that need a correction).
+template <typename T>
+void mechanics_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* mask,
+                     const fftg_krylov_opts* cg, double ntol, int nmaxit) {
+  const Geo& g = H->g;
+  const int c = H->c;
+  const int n = (int)S.size();
+  const double sqN = std::sqrt((double)g.N);
+  for (auto& s : S) {
+    s.nl = s.live;
+    s.o = MechOut{};
+    s.o.relres = HUGE_VAL;
+    s.r = 0;
+    if (!s.nl) continue;
+    // move the strain-controlled means to their targets
+    double mean[6], delta[6] = {0, 0, 0, 0, 0, 0};
+    comp_means(H, c, s.eps, mean);
+    bool any = false;
+    for (int k = 0; k < c; ++k)
+      if (!mask[k]) {
+        delta[k] = s.it->target.E[k] - mean[k];
+        any = any || delta[k] != 0.0;
+      }
+    if (any) fftg::launch_add_const(g.N, c, s.eps, delta, H->st);
+  }
+  std::vector<double> bb(n, 0.0);
+  std::vector<unsigned char> need(n, 0);
+  std::vector<KrylovCtl> k(n);
+  while (true) {
+    auto t0 = std::chrono::steady_clock::now();
+    bool any = false;
+    for (auto& s : S) {
+      if (!s.nl) continue;
+      any = true;
+      KT t(H, K_CONST);
+      fftg::launch_constitutive<T>(s.tab, g, c, s.it->nfields, s.it->phase, s.eps, s.s_epsp,
+                                   s.D, s.sig, s.st1, s.alph, reinterpret_cast<T*>(s.tan),
+                                   H->st);
+    }
+    if (!any) break;
+    check_launch();
+    sync(H);
+    const double tc = wall_ms(t0);
+    t0 = std::chrono::steady_clock::now();
+    for (auto& s : S) {
+      if (!s.nl) continue;
+      s.o.t_const += tc;
+      fwd3<double>(H, c, s.sig, s.spec);
+      fftg::launch_hermitize<double>(g, c, s.spec, H->st);
+      double* part = H->partials + (long long)s.q * H->psys;
+      const int nr = fftg::launch_gal_rhs<T>(g, c, H->S64, mask, s.Sbar, s.spec, C<T>(s.kr),
+                                             part, H->st);
+      fftg::launch_fin_sums(part, nr, 2, H->dsums + 2 * s.q, H->st);
+    }
+    HIPCHK(hipMemcpyAsync(H->hsums, H->dsums, sizeof(double) * 2 * n, hipMemcpyDeviceToHost,
+                          H->st));
+    sync(H);
+    bool anycg = false;
+    for (auto& s : S) {
+      need[s.q] = 0;
+      if (!s.nl) continue;
+      const double* s2 = H->hsums + 2 * s.q;
+      const double nb = std::sqrt(s2[0] / (double)g.N), ns = std::sqrt(s2[1] / (double)g.N);
+      s.o.relres = nb / std::max(ns, s.sref * sqN);
+      if (!std::isfinite(s.o.relres)) {
+        bsys_fail(s, FFTG_E_NONFINITE, "non-finite Newton residual");
+        continue;
+      }
+      if ((s.r >= 1 && s.o.relres <= ntol) || s.r >= nmaxit) {
+        s.o.converged = s.r >= 1 && s.o.relres <= ntol;
+        s.nl = false;
+        s.o.t_cg += wall_ms(t0);
+        continue;
+      }
+      need[s.q] = 1;
+      bb[s.q] = s2[0];
+      anycg = true;
+    }
+    if (!anycg) break;
+    // FP32 Krylov vectors cannot push the residual much below 1e-6 of |b|;
+    // the FP64 Newton residual refines the rest
+    const double cgtol = H->fp32() ? std::max(cg->tol, kFp32KrylovFloor) : cg->tol;
+    std::memcpy(H->mask_last, mask, 6);
+    galerkin_cg_n<T>(H, mask, n, bb.data(), need.data(), cgtol, cg->maxit, k.data());
+    for (auto& s : S) {
+      if (!need[s.q]) continue;
+      if (k[s.q].done == 3) {
+        bsys_fail(s, FFTG_E_BREAKDOWN, "Galerkin CG breakdown (p.Ap <= 0)");
+        continue;
+      }
+      if (k[s.q].done == 4) {
+        bsys_fail(s, FFTG_E_NONFINITE, "non-finite value in Galerkin CG");
+        continue;
+      }
+      s.o.cg += k[s.q].iters;
+      galerkin_solution_at<T>(H, mask, s.kx, s.spec, s.eps, true);
+    }
+    check_launch();
+    sync(H);
+    const double tcg = wall_ms(t0);
+    for (auto& s : S)
+      if (need[s.q] && s.nl) {
+        s.o.t_cg += tcg;
+        ++s.r;
+      }
+  }
+  for (auto& s : S) s.o.newton = s.r;
+}
+
+// Commit an RVE's increment to its item (the end of stagger_core).
+void commit_bsys(fftg_handle* H, BSys& s, int J, std::chrono::steady_clock::time_point t_all) {
+  const int c = H->c;
+  const long long N = H->g.N;
+  fftg_batch_item& it = *s.it;
+  HIPCHK(hipMemcpyAsync(s.s_eps, s.eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
+  HIPCHK(hipMemcpyAsync(s.s_epsp, s.st1, sizeof(double) * 7 * N, hipMemcpyDeviceToDevice, H->st));
+  if (J > 0) {
+    fftg::launch_commit_hist(s.tab, N, J, it.phase, s.ab, s.s_abar, s.s_hist, H->st);
+    HIPCHK(hipMemcpyAsync(s.s_abar, s.ab, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
+                          H->st));
+  }
+  HIPCHK(hipMemcpyAsync(it.sigma_out, s.sig, sizeof(double) * c * N, hipMemcpyDeviceToDevice,
+                        H->st));
+  double ms[6], me[6];
+  comp_means(H, c, s.sig, ms);
+  comp_means(H, c, s.eps, me);
+  for (int i = 0; i < 12; ++i) it.homog_out[i] = 0.0;
+  for (int i = 0; i < c; ++i) {
+    it.homog_out[i] = ms[i];
+    it.homog_out[6 + i] = me[i];
+  }
+  check_launch();
+  sync(H);
+  const double tot = wall_ms(t_all);
+  s.acc.t_ms[3] = std::max(0.0, tot - s.acc.t_ms[0] - s.acc.t_ms[1] - s.acc.t_ms[2]);
+  s.acc.inner_converged = s.inner_ok ? 1 : 0;
+  it.stats = s.acc;
+  it.status = s.converged && s.inner_ok ? FFTG_OK : FFTG_NOT_CONVERGED;
+  s.committed = true;
+  s.live = false;
+}
+
+// One increment of Algorithm 1 for every RVE of a class (stagger_core's
+// steps, RVE by RVE where they are per voxel, in lockstep for the Krylov
+// solves).  An RVE leaves the loop when its staggered error meets the
+// tolerance (committed at once) or on a failure (not committed).
+template <typename T>
+void stagger_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* mask, int J,
+                   const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg, double ntol,
+                   int nmaxit, double stol, int maxk) {
+  const auto t_all = std::chrono::steady_clock::now();
+  const Geo& g = H->g;
+  const int c = H->c;
+  const long long N = g.N, Ns = g.Ns;
+  const int n = (int)S.size();
+  const int Jm = std::max(J, 1);
+  ensure_sys(H, std::max(n, n * J));
+  alloc_gal(H, n);
+  alloc_bws(H, n, J);
+  if (J > 0) alloc_helm(H, n * J);
+  BatchWS* B = H->bws;
+  const size_t w = H->wsz();
+  for (auto& s : S) {
+    const long long q = s.q;
+    s.eps = B->eps_k + q * c * N;
+    s.eps_prev = B->eps_prev + q * c * N;
+    s.sig = B->sig_k + q * c * N;
+    s.st1 = B->st1 + q * 7 * N;
+    s.D = B->Dj + q * Jm * N;
+    s.alph = B->alph + q * Jm * N;
+    s.ab = B->ab_k + q * Jm * N;
+    s.ab_prev = B->ab_prev + q * Jm * N;
+    s.tan = static_cast<char*>(H->tan) + w * 8 * N * q;
+    s.kx = static_cast<char*>(H->kx) + 2 * w * c * Ns * q;
+    s.kr = static_cast<char*>(H->kr) + 2 * w * c * Ns * q;
+    s.spec = H->spec64 + 6 * Ns * q;
+    double* st = s.it->state;
+    s.s_eps = st;
+    s.s_epsp = st + (long long)c * N;
+    s.s_hist = st + (long long)(c + 7) * N;
+    s.s_abar = st + (long long)(c + 7 + J) * N;
+    HIPCHK(hipMemcpyAsync(s.eps, s.s_eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice,
+                          H->st));
+    if (J > 0)
+      HIPCHK(hipMemcpyAsync(s.ab, s.s_abar, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
+                            H->st));
+    for (int j = 0; j < J; ++j) {
+      const long long o = (q * J + j) * N;
+      if (H->fp32()) {
+        fftg::launch_ell2<float>(s.tab, N, j, s.it->phase, static_cast<float*>(B->ell2j) + o,
+                                 H->st);
+        fftg::launch_ell2<double>(s.tab, N, j, s.it->phase, B->ell2j64 + o, H->st);
+      } else {
+        fftg::launch_ell2<double>(s.tab, N, j, s.it->phase, static_cast<double*>(B->ell2j) + o,
+                                  H->st);
+      }
+    }
+    s.sref = 0.0;
+    for (int p = 0; p < s.tab.nphase; ++p) s.sref = std::max(s.sref, s.tab.m[p].sy);
+    if (!(s.sref > 0.0)) s.sref = 1.0;
+    for (int k = 0; k < 6; ++k) s.Sbar[k] = (k < c && mask[k]) ? s.it->target.S[k] : 0.0;
+  }
+  const double* ell2_64 = H->fp32() ? B->ell2j64 : static_cast<const double*>(B->ell2j);
+  std::vector<unsigned char> skip((size_t)n * Jm, 0);
+  std::vector<HelmOut> ho((size_t)n * Jm);
+  std::vector<std::vector<double>> part(n);
+  std::vector<int> nbe(n, 0);
+  for (int k = 0; k < maxk; ++k) {
+    bool any = false;
+    for (auto& s : S) any = any || s.live;
+    if (!any) break;
+    for (auto& s : S) {
+      if (!s.live) continue;
+      if (J > 0)
+        fftg::launch_damage(s.tab, N, J, s.it->phase, s.ab, s.s_hist, s.s_abar, s.D, H->st);
+      HIPCHK(hipMemcpyAsync(s.eps_prev, s.eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice,
+                            H->st));
+    }
+    mechanics_batch<T>(H, S, mask, cg, ntol, nmaxit);
+    for (auto& s : S) {
+      if (!s.live) continue;
+      s.acc.newton_iters += s.o.newton;
+      s.inner_ok = s.o.converged;
+      s.acc.cg_iters += s.o.cg;
+      s.acc.relres = s.o.relres;
+      s.acc.t_ms[0] += s.o.t_const;
+      s.acc.t_ms[1] += s.o.t_cg;
+    }
+    auto th = std::chrono::steady_clock::now();
+    if (J > 0) {
+      for (auto& s : S) {
+        for (int j = 0; j < J; ++j) skip[(size_t)s.q * J + j] = s.live ? 0 : 1;
+        if (s.live)
+          HIPCHK(hipMemcpyAsync(s.ab_prev, s.ab, sizeof(double) * J * N,
+                                hipMemcpyDeviceToDevice, H->st));
+      }
+      // every field of every live RVE (Algorithm 1 (ii)) in one lockstep solve
+      helm_solve(H, B->alph, B->ell2j, ell2_64, -1.0, B->ab_k, pcg->tol, pcg->maxit, n * J,
+                 ho.data(), skip.data());
+      for (auto& s : S) {
+        if (!s.live) continue;
+        for (int j = 0; j < J && s.live; ++j) {
+          const HelmOut& h = ho[(size_t)s.q * J + j];
+          if (h.status == 3) {
+            bsys_fail(s, FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown");
+          } else if (h.status == 4) {
+            bsys_fail(s, FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG");
+          } else {
+            s.inner_ok = s.inner_ok && h.status == 1;
+            s.acc.pcg_iters += h.iters;
+          }
+        }
+      }
+    }
+    sync(H);
+    const double thm = wall_ms(th);
+    // staggered error (Algorithm 1 (iii)), per RVE
+    for (auto& s : S) {
+      if (!s.live) continue;
+      s.acc.t_ms[2] += thm;
+      nbe[s.q] = fftg::launch_stagger_err(N, c, J, s.eps, s.eps_prev, s.ab, s.ab_prev,
+                                          H->partials + (long long)s.q * H->psys, H->st);
+      part[s.q].resize((size_t)nbe[s.q] * (1 + 2 * J));
+      HIPCHK(hipMemcpyAsync(part[s.q].data(), H->partials + (long long)s.q * H->psys,
+                            sizeof(double) * part[s.q].size(), hipMemcpyDeviceToHost, H->st));
+    }
+    sync(H);
+    for (auto& s : S) {
+      if (!s.live) continue;
+      const int nb = nbe[s.q];
+      const std::vector<double>& pt = part[s.q];
+      double mx = 0.0;
+      for (int b = 0; b < nb; ++b) mx = std::max(mx, pt[b]);
+      double mean[6];
+      comp_means(H, c, s.eps, mean);
+      double mn = 0.0;
+      for (int i = 0; i < c; ++i) mn += mean[i] * mean[i];
+      mn = std::sqrt(mn);
+      double err = std::sqrt(mx) / (mn > 0.0 ? mn : 1.0);
+      for (int j = 0; j < J; ++j) {
+        double d2 = 0.0, a2 = 0.0;
+        for (int b = 0; b < nb; ++b) {
+          d2 += pt[(size_t)(1 + 2 * j) * nb + b];
+          a2 += pt[(size_t)(2 + 2 * j) * nb + b];
+        }
+        if (d2 > 0.0)
+          err = std::max(err, std::sqrt(d2) / std::max(std::sqrt(a2), 1e-12 * std::sqrt((double)N)));
+      }
+      s.acc.stagger_iters = k + 1;
+      s.acc.err = err;
+      if (err <= stol) {
+        s.converged = true;
+        commit_bsys(H, s, J, t_all);
+      }
+    }
+  }
+  for (auto& s : S)
+    if (s.live) commit_bsys(H, s, J, t_all);
+  H->tan_valid = false;  // the tangent buffer holds the class's tangents
+}
+
+// Items that can share a lockstep class: one grid, voxel size, derivative
+// scheme, precision, field count and macro mask.
+bool same_class(const fftg_batch_item& a, const fftg_batch_item& b) {
+  const fftg_handle* x = a.h;
+  const fftg_handle* y = b.h;
+  if (x->g.ndim != y->g.ndim || x->g.n1 != y->g.n1 || x->g.n2 != y->g.n2 || x->g.n3 != y->g.n3 ||
+      x->h != y->h || x->scheme != y->scheme || x->prec != y->prec || a.nfields != b.nfields)
+    return false;
+  for (int k = 0; k < x->c; ++k)
+    if ((a.target.mask[k] != 0) != (b.target.mask[k] != 0)) return false;
+  return true;
+}
+
+// One increment of every item of a class on the first item's handle; the
+// items' codes, stats and results are those of staggered_step on each alone.
+void run_class(fftg_batch_item* items, const std::vector<int>& idx, const fftg_krylov_opts* cg,
+               const fftg_krylov_opts* pcg, double newton_tol, int newton_maxit,
+               double stagger_tol, int max_stagger_iters) {
+  fftg_handle* H = items[idx[0]].h;
+  std::vector<BSys> S;
+  for (int i : idx) {
+    fftg_batch_item& it = items[i];
+    BSys b;
+    const fftg_status rc = run_guarded(it.h, [&]() -> fftg_status {
+      validate_table(it.tab, it.nphase, it.nfields);
+      validate_macro(&it.target, H->c);
+      if (!it.phase || !it.state || !cg || !pcg || !it.sigma_out)
+        throw Fail{FFTG_E_INVALID, "staggered_step: null pointer"};
+      if (max_stagger_iters < 1) throw Fail{FFTG_E_INVALID, "max_stagger_iters must be >= 1"};
+      validate_phase(H, it.phase, it.nphase);
+      b.tab = make_table(it.tab, it.nphase, it.nfields);
+      return FFTG_OK;
+    });
+    if (rc != FFTG_OK) {
+      it.status = rc;
+      continue;
+    }
+    b.it = &it;
+    b.q = (int)S.size();
+    S.push_back(b);
+  }
+  if (S.empty()) return;
+  if (S.size() == 1) {
+    fftg_batch_item& it = *S[0].it;
+    it.status = staggered_step(it.h, it.phase, it.tab, it.nphase, it.nfields, it.state,
+                               &it.target, cg, pcg, newton_tol, newton_maxit, stagger_tol,
+                               max_stagger_iters, it.sigma_out, it.homog_out, &it.stats);
+    return;
+  }
+  const unsigned char* mask = S[0].it->target.mask;
+  const int J = S[0].it->nfields;
+  const fftg_status rc = run_guarded(H, [&]() -> fftg_status {
+    if (H->fp32())
+      stagger_batch<float>(H, S, mask, J, cg, pcg, newton_tol, newton_maxit, stagger_tol,
+                           max_stagger_iters);
+    else
+      stagger_batch<double>(H, S, mask, J, cg, pcg, newton_tol, newton_maxit, stagger_tol,
+                            max_stagger_iters);
+    return FFTG_OK;
+  });
+  const std::string herr = H->err;
+  for (auto& s : S) {
+    if (s.committed) continue;
+    if (s.fail != FFTG_OK) {
+      s.it->status = s.fail;
+      s.it->h->err = s.msg;
+    } else {
+      s.it->status = rc != FFTG_OK ? rc : FFTG_E_HIP;
+      s.it->h->err = herr;
+    }
+  }
 }
 
 // Tile autotuner: time the inner y pass and the outer inverse Galerkin pass
@@ -1721,23 +2305,26 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
     H->spec64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * 6 * g.Ns);
     H->tan = dalloc(H->wsz() * 8 * (size_t)g.N);
     H->rtmp = dalloc(H->wsz() * (size_t)std::max(H->c, 2) * g.N);
-    // partials: largest block count of any reduction
+    // partials: largest block count of any reduction of one system (a
+    // lockstep solve of n systems needs n times as many)
     long long maxb = fftg::RED_BLOCKS * 16;
     for (int a = 1; a < 3; ++a) {
       const long long nl = (long long)H->c * g.Ns / std::max(1, ns[a]);
       maxb = std::max(maxb, 2 * (nl + 1));
-      // the Helmholtz passes of up to FFTG_MAX_FIELDS lockstep systems
-      maxb = std::max(maxb, (long long)FFTG_MAX_FIELDS * (g.Ns / std::max(1, ns[a]) + 1));
+      maxb = std::max(maxb, g.Ns / std::max(1, ns[a]) + 1);
     }
-    H->npartials = (size_t)maxb;
+    H->psys = maxb;
+    // up to FFTG_MAX_FIELDS lockstep systems (the Helmholtz solves of the
+    // non-local fields) without growing
+    H->npartials = (size_t)maxb * FFTG_MAX_FIELDS;
     H->partials = (double*)dalloc(sizeof(double) * H->npartials);
-    H->dsums = (double*)dalloc(sizeof(double) * 64);
-    // one Krylov control block per system of a lockstep solve (Helmholtz:
-    // one per non-local field)
+    H->dsums = (double*)dalloc(sizeof(double) * (2 * FFTG_MAX_FIELDS + 64));
+    // one Krylov control block per system of a lockstep solve
     H->ctl = (KrylovCtl*)dalloc(sizeof(KrylovCtl) * FFTG_MAX_FIELDS);
     HIPCHK(hipHostMalloc((void**)&H->hctl, sizeof(KrylovCtl) * FFTG_MAX_FIELDS,
                          hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * 64, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * (2 * FFTG_MAX_FIELDS + 64),
+                         hipHostMallocDefault));
     for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
     return FFTG_OK;
@@ -2631,21 +3218,44 @@ fftg_status fftg_batch_step(fftg_batch_item* items, int n, int nworkers,
   }
   std::sort(hs.begin(), hs.end());
   if (std::adjacent_find(hs.begin(), hs.end()) != hs.end()) return FFTG_E_INVALID;
-  // largest RVE first (longest-processing-time order balances the workers)
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return items[a].h->g.N > items[b].h->g.N; });
+  // classes of items that run in lockstep (FFTG_BATCH_LOCKSTEP=0: every item
+  // alone on its own handle and stream)
+  const char* ls = std::getenv("FFTG_BATCH_LOCKSTEP");
+  const bool lockstep = !(ls && ls[0] == '0' && ls[1] == '\0');
+  std::vector<std::vector<int>> units;
+  for (int i = 0; i < n; ++i) {
+    bool placed = false;
+    if (lockstep)
+      for (auto& u : units)
+        if (same_class(items[u[0]], items[i])) {
+          u.push_back(i);
+          placed = true;
+          break;
+        }
+    if (!placed) units.push_back({i});
+  }
+  // largest work first (longest-processing-time order balances the workers)
+  auto vox = [&](const std::vector<int>& u) { return (long long)u.size() * items[u[0]].h->g.N; };
+  std::stable_sort(units.begin(), units.end(),
+                   [&](const std::vector<int>& a, const std::vector<int>& b) {
+                     return vox(a) > vox(b);
+                   });
+  const int nu = (int)units.size();
   std::atomic<int> next{0};
   auto work = [&]() {
-    for (int k = next.fetch_add(1); k < n; k = next.fetch_add(1)) {
-      fftg_batch_item& it = items[order[k]];
+    for (int k = next.fetch_add(1); k < nu; k = next.fetch_add(1)) {
+      const std::vector<int>& u = units[k];
+      if (u.size() > 1) {
+        run_class(items, u, cg, pcg, newton_tol, newton_maxit, stagger_tol, max_stagger_iters);
+        continue;
+      }
+      fftg_batch_item& it = items[u[0]];
       it.status = staggered_step(it.h, it.phase, it.tab, it.nphase, it.nfields, it.state,
                                  &it.target, cg, pcg, newton_tol, newton_maxit, stagger_tol,
                                  max_stagger_iters, it.sigma_out, it.homog_out, &it.stats);
     }
   };
-  const int nw = std::min(nworkers, std::max(n, 1));
+  const int nw = std::min(nworkers, std::max(nu, 1));
   std::vector<std::thread> pool;
   for (int w = 1; w < nw; ++w) pool.emplace_back(work);
   work();
