@@ -3205,6 +3205,9 @@ fftg_status helmholtz_solve_noalloc(const fftg_grid* grid, void* hip_stream, con
 
 const char* helmholtz_noalloc_last_error(void) { return g_noalloc_error.c_str(); }
 
+// voxels a lockstep sub-class of large grids aims at
+constexpr long long kClassVoxels = 4LL << 20;
+
 fftg_status fftg_batch_step(fftg_batch_item* items, int n, int nworkers,
                             const fftg_krylov_opts* cg, const fftg_krylov_opts* pcg,
                             double newton_tol, int newton_maxit, double stagger_tol,
@@ -3233,6 +3236,29 @@ fftg_status fftg_batch_step(fftg_batch_item* items, int n, int nworkers,
           break;
         }
     if (!placed) units.push_back({i});
+  }
+  // A class of large grids is split into sub-classes of about kClassVoxels
+  // voxels (FFTG_BATCH_CLASS_VOXELS overrides), run by different workers: a
+  // sub-class already fills the GPU, and several of them in flight keep it
+  // busy while one waits on its host decisions or on its slowest RVE.
+  long long cap = kClassVoxels;
+  if (const char* cv = std::getenv("FFTG_BATCH_CLASS_VOXELS")) {
+    const long long v = std::atoll(cv);
+    if (v > 0) cap = v;
+  }
+  {
+    std::vector<std::vector<int>> split;
+    for (auto& u : units) {
+      const long long per = std::max(1LL, cap / items[u[0]].h->g.N);
+      const int m = (int)u.size();
+      const int nsub = (int)((m + per - 1) / per);
+      for (int k = 0, at = 0; k < nsub; ++k) {
+        const int len = m / nsub + (k < m % nsub ? 1 : 0);
+        split.emplace_back(u.begin() + at, u.begin() + at + len);
+        at += len;
+      }
+    }
+    units.swap(split);
   }
   // largest work first (longest-processing-time order balances the workers)
   auto vox = [&](const std::vector<int>& u) { return (long long)u.size() * items[u[0]].h->g.N; };
