@@ -161,6 +161,10 @@ struct fftg_handle {
   // Krylov loops launch their iterations directly instead of through HIP
   // graphs (the allocation-free entry point: instantiating a graph allocates)
   bool nograph = false;
+  // Galerkin CG scalar steps folded into the passes instead of two scalar
+  // kernels per iteration (FFTG_GAL_FOLD=1 at creation).  Off by default: the
+  // redundant per-workgroup reductions cost about what the two launches do.
+  bool fold = false;
   bool fp32() const { return prec == FFTG_FP32_REFINED; }
   size_t wsz() const { return fp32() ? sizeof(float) : sizeof(double); }
 };
@@ -602,19 +606,29 @@ void validate_macro(const fftg_macro* t, int c) {
 
 // One Galerkin CG iteration of nsys stacked systems (RVEs of one grid, each
 // with its own scalars; spectra [sys][c][Ns], tangent [sys][N][8]): 6 passes
-// + 2 scalar kernels, all on H->st.
+// and 2 scalar kernels on H->st.  With H->fold the scalar steps are folded
+// into the passes instead: the inverse outer pass finishes the previous
+// iteration (r.r, stop test, beta) from the residual pass's partial sums, the
+// residual pass forms alpha from the forward pass's; parity = the
+// iteration's index & 1 (the slot of the control block it writes).
 template <typename T>
-void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1) {
+void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1, int parity = 0) {
   const Geo& g = H->g;
   const int c = H->c;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
   const T scl = T(1.0 / (double)g.N);
   const long long lps = (long long)c * g.n3 * g.n1h;  // y lines per system
+  const int nbd = fftg::gal_dot_count<T>(H->plan[oa], g, c, zo);
+  const int nbr = fftg::gal_resid_count(g);
+  double* dpart = H->partials;                             // p.Ap, [sys][nbd]
+  double* rpart = H->partials + (long long)nsys * nbd;     // r.r, [sys][nbr]
+  const bool fold = H->fold;
   {
     KT t(H, K_GAL_OI);
     fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr), C<T>(H->kp),
-                                C<T>(H->kx), C<T>(H->kw), H->ctl, H->st, H->tsh_o, nsys);
+                                C<T>(H->kx), C<T>(H->kw), H->ctl, H->st, H->tsh_o, nsys, parity,
+                                fold ? rpart : nullptr, nbr);
   }
   inner_inv<T>(H, c * nsys, C<T>(H->kw), H->ctl, K_GAL_YI, lps);
   {
@@ -623,25 +637,24 @@ void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1) {
                                    reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st, nsys);
   }
   inner_fwd<T>(H, c * nsys, C<T>(H->kw), H->ctl, K_GAL_YF, lps);
-  int nb;
   {
     KT t(H, K_GAL_OF);
-    nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
-                                     C<T>(H->kw), H->partials, H->ctl, H->st, nsys);
+    const int nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
+                                               C<T>(H->kw), dpart, H->ctl, H->st, nsys);
+    if (nb != nbd) throw Fail{FFTG_E_HIP, "Galerkin forward pass: partial count mismatch"};
   }
-  {
+  if (!fold) {
     KT t(H, K_SMALL);
-    fftg::launch_fin_alpha(H->partials, nb, H->ctl, H->st, nsys);
+    fftg::launch_fin_alpha(dpart, nbd, H->ctl, H->st, nsys);
   }
-  int nr;
   {
     KT t(H, K_GAL_RES);
-    nr = fftg::launch_gal_resid<T>(g, c, SY<T>(H), mask, C<T>(H->kr), C<T>(H->kw), H->partials,
-                                   H->ctl, H->st, nsys);
+    fftg::launch_gal_resid<T>(g, c, SY<T>(H), mask, C<T>(H->kr), C<T>(H->kw), rpart, H->ctl,
+                              H->st, nsys, parity, fold ? dpart : nullptr, nbd);
   }
-  {
+  if (!fold) {
     KT t(H, K_SMALL);
-    fftg::launch_fin_beta(H->partials, nr, 1, H->ctl, H->st, nsys);
+    fftg::launch_fin_beta(rpart, nbr, 1, H->ctl, H->st, nsys);
   }
 }
 
@@ -658,7 +671,7 @@ hipGraphExec_t capture(fftg_handle* H, F body) {
   hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     try {
-      for (int i = 0; i < kGraphIters; ++i) body();
+      for (int i = 0; i < kGraphIters; ++i) body(i);
     } catch (...) {
       (void)hipStreamEndCapture(H->cap, &graph);
       if (graph) (void)hipGraphDestroy(graph);
@@ -681,12 +694,13 @@ hipGraphExec_t gal_graph(fftg_handle* H, const unsigned char* mask, int nsys) {
   unsigned long long key = 1ull + (H->fp32() ? 2ull : 0ull);
   for (int i = 0; i < 6; ++i) key |= (unsigned long long)(mask[i] & 1) << (8 + i);
   key |= (unsigned long long)nsys << 16;
+  key |= H->fold ? 4ull : 0ull;
   if (H->ggal.exec && H->ggal.key == key) return H->ggal.exec;
   if (H->ggal.exec) (void)hipGraphExecDestroy(H->ggal.exec);
   H->ggal.exec = nullptr;
   unsigned char m[6];
   std::memcpy(m, mask, 6);
-  H->ggal.exec = capture(H, [&]() { gal_iteration<T>(H, m, nsys); });
+  H->ggal.exec = capture(H, [&](int i) { gal_iteration<T>(H, m, nsys, i & 1); });
   H->ggal.key = key;
   return H->ggal.exec;
 }
@@ -712,6 +726,12 @@ void galerkin_cg_n(fftg_handle* H, const unsigned char* mask, int nsys, const do
     k[q].maxit = maxit;
     k[q].window = std::is_same<T, float>::value ? kFp32StagnationWindow : 0;
     k[q].done = (!need[q] || bb[q] == 0.0) ? 1 : (maxit <= 0 ? 2 : 0);
+    // slot 0: the state before the first iteration
+    k[q].rzs[0] = bb[q];
+    k[q].rrmins[0] = bb[q];
+    k[q].its[0] = 0;
+    k[q].itmins[0] = 0;
+    k[q].first = 1;
     all = all && k[q].done;
   }
   write_ctls(H, nsys, k);
@@ -730,9 +750,10 @@ void galerkin_cg_n(fftg_handle* H, const unsigned char* mask, int nsys, const do
     while (!all) {
       int before = 0;
       for (int q = 0; q < nsys; ++q) before = std::max(before, k[q].iters);
+      // chunks of even length: the iteration's parity is it & 1
       for (int it = 0; it < chunk; ++it) {
         H->kt_iter = it;
-        gal_iteration<T>(H, mask, nsys);
+        gal_iteration<T>(H, mask, nsys, it & 1);
       }
       H->kt_iter = -1;
       check_launch();
@@ -811,7 +832,7 @@ hipGraphExec_t helm_graph(fftg_handle* H, const T* ell2, int nsys) {
   H->ghelm_next = (H->ghelm_next + 1) % 4;
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
   sl.exec = nullptr;
-  sl.exec = capture(H, [&]() { helm_iteration<T>(H, ell2, nsys); });
+  sl.exec = capture(H, [&](int) { helm_iteration<T>(H, ell2, nsys); });
   sl.key = key;
   return sl.exec;
 }
@@ -2329,6 +2350,7 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
     HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
     return FFTG_OK;
   });
+  if (const char* f = std::getenv("FFTG_GAL_FOLD")) H->fold = f[0] == '1' && f[1] == '\0';
   if (rc == FFTG_OK) tune_tiles(H);
   if (rc != FFTG_OK) {
     g_create_error = H->err;

@@ -380,4 +380,15 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return red[0];
 }
 
+// Sum of nb partial sums in a fixed order: lane l adds p[l], p[l + NT], ...,
+// then the fixed tree.  Every lane gets the result; `red` (NT doubles of LDS)
+// may be reused only after a barrier.
+template <int NT = FFT_THREADS>
+__device__ __forceinline__ double ordered_sum_t(const double* __restrict__ p, int nb,
+                                                double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) acc += p[i];
+  return block_sum<NT>(acc, red);
+}
+
 }  // namespace fftg

@@ -427,20 +427,81 @@ FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>
 // Stacked systems (several RVEs of one grid solved in lockstep): spectra
 // [sys][comp][Ns]; the tiles of a (system, component) slab never reach into
 // the next one (tpo tiles per slab), and system sys uses ctl[sys].
+//
+// rpart (folded scalars): the r.r partial sums of the previous iteration's
+// residual pass, [sys][nbr].  Every workgroup sums them in the same fixed
+// order and takes the same decisions (stop test, beta = r.r / r.r_old); the
+// first workgroup of each system records them in slot `parity` of its
+// control block.  Without rpart, alpha and beta come from the control block
+// (the scalar kernels ran in between).
 template <typename T, int NF, int SH>
 FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
                                const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
                                cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long inner,
                                long long ostride, long long es, int TL_rt, int tpo, int ncomp,
-                               const KrylovCtl* __restrict__ ctl_all) {
+                               KrylovCtl* __restrict__ ctl_all, int parity,
+                               const double* __restrict__ rpart, int nbr) {
   const long long o = blockIdx.x / tpo;  // (system, component) slab
-  const KrylovCtl* ctl = ctl_all + o / ncomp;
-  if (ctl->done) return;
+  const int sys = (int)(o / ncomp);
+  KrylovCtl* ctl = ctl_all + sys;
+  // The first workgroup of the system may set done while this pass runs:
+  // the whole workgroup acts on one reading of it, so that no wave leaves
+  // while the others sum or update.
+  __shared__ int s_done;
+  if (threadIdx.x == 0) s_done = ctl->done;
+  __syncthreads();
+  if (s_done) return;
   constexpr bool FIX = NF > 0;
   constexpr int TB = tile_budget<SH>();
-  const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
   __shared__ cpx<T> buf[FIX ? fs_tile<T, TB>(NF) * NF : LDS_ELEMS];
   constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
+  static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
+  T alpha, beta;
+  if (!rpart) {
+    alpha = (T)ctl->alpha;
+    beta = (T)ctl->beta;
+  } else if (ctl->first) {
+    alpha = T(0);
+    beta = T(0);
+  } else {
+    const int q = parity ^ 1;  // slot of the previous iteration
+    const double rz = ordered_sum_t<NT>(rpart + (long long)sys * nbr, nbr,
+                                        reinterpret_cast<double*>(buf));
+    __syncthreads();  // the tile below reuses the reduction scratch
+    const int it = ctl->its[q] + 1;
+    double rrmin = ctl->rrmins[q];
+    int itmin = ctl->itmins[q];
+    if (rz < rrmin) {
+      rrmin = rz;
+      itmin = it;
+    }
+    int done = 0;
+    if (!isfinite(rz))
+      done = 4;
+    else if (rz <= ctl->tol2)
+      done = 1;
+    else if (it >= ctl->maxit)
+      done = 2;
+    else if (ctl->window > 0 && it - itmin >= ctl->window)
+      done = 5;
+    const double b = rz / ctl->rzs[q];
+    if (blockIdx.x % (tpo * ncomp) == 0 && threadIdx.x == 0) {
+      ctl->rzs[parity] = rz;
+      ctl->its[parity] = it;
+      ctl->rrmins[parity] = rrmin;
+      ctl->itmins[parity] = itmin;
+      ctl->iters = it;
+      ctl->rz = rz;
+      ctl->rr = rz;
+      ctl->rrmin = rrmin;
+      ctl->itmin = itmin;
+      ctl->beta = b;
+      if (done) ctl->done = done;
+    }
+    if (done) return;
+    alpha = (T)ctl->alpha;  // step of the previous iteration (its residual pass)
+    beta = (T)b;
+  }
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T, TB>(NF) : TL_rt;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
@@ -747,18 +808,52 @@ FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo 
 // r <- r - alpha G*(w) ; partial sums of weighted |r|^2
 // Stacked systems: blockIdx.y is the system (spectra [sys][comp][Ns]), its
 // partials at blockIdx.y * gridDim.x.
+//
+// dpart (folded scalars): the p.Ap partial sums of this iteration's forward
+// pass, [sys][nbd]; every workgroup sums them in the same fixed order and
+// forms alpha = r.r / p.Ap (r.r from slot `parity`), the first workgroup of
+// each system records alpha (the step the next inverse pass, or the final
+// update, applies to x).  Without dpart, alpha comes from the control block.
 template <typename T, int C>
 FFTG_KERNEL void k_gal_resid(Geo g, Sym<T> sym, unsigned char mk0, unsigned char mk1,
                              unsigned char mk2, unsigned char mk3, unsigned char mk4,
                              unsigned char mk5, cpx<T>* __restrict__ r_all,
                              const cpx<T>* __restrict__ w_all, double* __restrict__ partials,
-                             const KrylovCtl* __restrict__ ctl_all) {
-  const KrylovCtl* ctl = ctl_all + blockIdx.y;
-  if (ctl->done) return;
+                             KrylovCtl* __restrict__ ctl_all, int parity,
+                             const double* __restrict__ dpart, int nbd) {
+  KrylovCtl* ctl = ctl_all + blockIdx.y;
+  // one reading of done per workgroup (the first workgroup may set it while
+  // this pass runs)
+  __shared__ int s_done;
+  if (threadIdx.x == 0) s_done = ctl->done;
+  __syncthreads();
+  if (s_done) return;
   cpx<T>* __restrict__ r = r_all + (long long)blockIdx.y * C * g.Ns;
   const cpx<T>* __restrict__ w = w_all + (long long)blockIdx.y * C * g.Ns;
   __shared__ double red[FFT_THREADS];
-  const T alpha = (T)ctl->alpha;
+  T alpha;
+  if (dpart) {
+    const double pAp = ordered_sum_t<FFT_THREADS>(dpart + (long long)blockIdx.y * nbd, nbd, red);
+    const double rz = ctl->rzs[parity];
+    int bad = 0;
+    double a = 0.0;
+    if (!isfinite(pAp) || !isfinite(rz))
+      bad = 4;
+    else if (!(pAp > 0.0))
+      bad = 3;
+    else
+      a = rz / pAp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctl->pAp = pAp;
+      ctl->alpha = a;
+      ctl->first = 0;
+      if (bad) ctl->done = bad;
+    }
+    if (bad) return;
+    alpha = (T)a;
+  } else {
+    alpha = (T)ctl->alpha;
+  }
   const unsigned char mask[6] = {mk0, mk1, mk2, mk3, mk4, mk5};
   double acc = 0.0;
   for (long long gi = (long long)blockIdx.x * FFT_THREADS + threadIdx.x; gi < g.Ns;
@@ -2294,8 +2389,9 @@ static inline void outer_lines(const Geo& g, int ncomp, bool zouter, long long& 
 
 template <typename T>
 int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
-                       cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, const KrylovCtl* ctl,
-                       hipStream_t st, int sh, int nsys) {
+                       cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, KrylovCtl* ctl,
+                       hipStream_t st, int sh, int nsys, int parity, const double* rpart,
+                       int nbr) {
   long long nl, inner, os, es;
   outer_lines(g, c, zouter, nl, inner, os, es);
   long long nb = 0;
@@ -2305,7 +2401,7 @@ int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
     const int tpo = tiles_per_sys(inner, TL);
     nb = (long long)tpo * c * nsys;
     hipLaunchKernelGGL((k_gal_dir_inv<T, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw, r,
-                       pp, x, w, inner, os, es, TL, tpo, c, ctl);
+                       pp, x, w, inner, os, es, TL, tpo, c, ctl, parity, rpart, nbr);
   }))
   return (int)nb;
 }
@@ -2326,6 +2422,19 @@ int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, boo
   })
   return (int)(nb / nsys);  // partials per system
 }
+
+template <typename T>
+int gal_dot_count(const Plan& p, const Geo& g, int c, bool zouter) {
+  long long nl, inner, os, es;
+  outer_lines(g, c, zouter, nl, inner, os, es);
+  int cnt = 0;
+  FFTG_DISPATCH_N(p.n, {
+    const int TL = NF ? fs_tile<T, kDotBytes<T>>(NF) : tile_lines(p.n, 1);
+    cnt = tiles_per_sys(inner, TL) * c;
+  })
+  return cnt;
+}
+int gal_resid_count(const Geo& g) { return grid_for(g.Ns); }
 
 static inline int fused_lines_rt(int n1, int c) {
   int NL = (2 * LDS_ELEMS) / (c * n1);
@@ -2380,15 +2489,15 @@ void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* 
 
 template <typename T>
 int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char* m,
-                     cpx<T>* r, const cpx<T>* w, double* partials, const KrylovCtl* ctl,
-                     hipStream_t st, int nsys) {
+                     cpx<T>* r, const cpx<T>* w, double* partials, KrylovCtl* ctl,
+                     hipStream_t st, int nsys, int parity, const double* dpart, int nbd) {
   const int nb = grid_for(g.Ns);
   if (c == 6)
     hipLaunchKernelGGL((k_gal_resid<T, 6>), dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
-                       m[2], m[3], m[4], m[5], r, w, partials, ctl);
+                       m[2], m[3], m[4], m[5], r, w, partials, ctl, parity, dpart, nbd);
   else
     hipLaunchKernelGGL((k_gal_resid<T, 3>), dim3(nb, nsys), dim3(FFT_THREADS), 0, st, g, sym, m[0], m[1],
-                       m[2], m[3], m[4], m[5], r, w, partials, ctl);
+                       m[2], m[3], m[4], m[5], r, w, partials, ctl, parity, dpart, nbd);
   return nb;
 }
 
@@ -2733,14 +2842,15 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, i
                                   long long, long long, bool, const KrylovCtl*, hipStream_t,     \
                                   int, long long);                                               \
   template int launch_gal_dir_inv<T>(const Plan&, const cpx<T>*, const Geo&, int, bool, cpx<T>*, \
-                                     cpx<T>*, cpx<T>*, cpx<T>*, const KrylovCtl*, hipStream_t,   \
-                                     int, int);                                                  \
+                                     cpx<T>*, cpx<T>*, cpx<T>*, KrylovCtl*, hipStream_t, int,    \
+                                     int, int, const double*, int);                              \
+  template int gal_dot_count<T>(const Plan&, const Geo&, int, bool);                            \
   template int launch_gal_dot_fwd<T>(const Plan&, const cpx<T>*, const Geo&, int, bool,          \
                                      const cpx<T>*, cpx<T>*, double*, const KrylovCtl*,          \
                                      hipStream_t, int);                                          \
   template int launch_gal_resid<T>(const Geo&, int, const Sym<T>&, const unsigned char*,        \
-                                    cpx<T>*, const cpx<T>*, double*, const KrylovCtl*,           \
-                                    hipStream_t, int);                                           \
+                                    cpx<T>*, const cpx<T>*, double*, KrylovCtl*, hipStream_t,   \
+                                    int, int, const double*, int);                               \
   template int launch_gal_rhs<T>(const Geo&, int, const Sym<double>&, const unsigned char*,     \
                                   const double*, const cpx<double>*, cpx<T>*, double*,           \
                                   hipStream_t, int, const double*);                              \

@@ -46,6 +46,13 @@ struct KrylovCtl {
   int done;       // 0 running, 1 converged, 2 max iterations, 3 breakdown,
                   // 4 non-finite, 5 stagnated (no new smallest residual for
                   // `window` iterations: the rounding floor of FP32 vectors)
+  // Galerkin CG with the scalar steps folded into the passes: the state of
+  // iteration k lives in slot k & 1 (the pass that writes slot k & 1 reads
+  // slot (k & 1) ^ 1 in every workgroup, so no workgroup sees a half-updated
+  // value); first = 1 until the first residual pass has run.
+  double rzs[2], rrmins[2];
+  int its[2], itmins[2];
+  int first;
 };
 
 struct Mat {
@@ -84,8 +91,9 @@ void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nli
 // system).
 template <typename T>
 int launch_gal_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
-                       cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, const KrylovCtl* ctl,
-                       hipStream_t st, int sh = 0, int nsys = 1);
+                       cpx<T>* r, cpx<T>* pp, cpx<T>* x, cpx<T>* w, KrylovCtl* ctl,
+                       hipStream_t st, int sh = 0, int nsys = 1, int parity = 0,
+                       const double* rpart = nullptr, int nbr = 0);
 template <typename T>
 int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        const cpx<T>* pp, cpx<T>* w, double* partials, const KrylovCtl* ctl,
@@ -96,8 +104,16 @@ void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cp
                         int nsys = 1);
 template <typename T>
 int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char* mask6,
-                      cpx<T>* r, const cpx<T>* w, double* partials, const KrylovCtl* ctl,
-                      hipStream_t st, int nsys = 1);
+                      cpx<T>* r, const cpx<T>* w, double* partials, KrylovCtl* ctl,
+                      hipStream_t st, int nsys = 1, int parity = 0,
+                      const double* dpart = nullptr, int nbd = 0);
+// Folded scalar steps (rpart / dpart given): the inverse pass reads the r.r
+// partial sums of the previous residual pass ([sys][gal_resid_count]), the
+// residual pass the p.Ap partial sums of the forward pass
+// ([sys][gal_dot_count]); the two sets must live in different buffers.
+template <typename T>
+int gal_dot_count(const Plan& p, const Geo& g, int c, bool zouter);
+int gal_resid_count(const Geo& g);
 // S_sys (optional): per-system mean stress targets [sys][6] in place of Sbar6;
 // partials [sys][2][count].
 template <typename T>

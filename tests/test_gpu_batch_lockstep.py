@@ -164,3 +164,63 @@ def test_lockstep_class_with_an_invalid_member():
     for i in (0, 2):
         _check_member(i, rves[i], FP64, [tg[i]], res, batch)
     batch.close()
+
+
+def test_many_rves_on_concurrent_streams_match_lockstep(monkeypatch):
+    """Sixteen FP32-refined RVEs, each alone on its own stream with eight
+    worker threads (kernels of different RVEs interleave on the GPU), against
+    the same RVEs as lockstep classes: no member fails, and the two runs
+    agree bitwise (status, iteration counts, staggered error, states)."""
+    from paper_2103_04770_amd import FP32_REFINED
+    from paper_2103_04770_amd.batch import RVEBatch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rves = _damage_rves([24, 32, 24, 32] * 4, 700)
+    tg = _targets(len(rves), [3e-3, 5e-3])
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("FFTG_BATCH_LOCKSTEP", mode)
+        batch = RVEBatch(rves, prec=FP32_REFINED)
+        res = [batch.step(tg, nworkers=8, **TOLS) for _ in range(2)]
+        torch.cuda.synchronize()
+        out[mode] = (res, [t.clone() for t in batch.states])
+        batch.close()
+    conv = 0
+    for i in range(len(rves)):
+        for k in range(2):
+            a, b = out["0"][0][k][i], out["1"][0][k][i]
+            assert a["status"] >= 0 and a["status"] == b["status"], (i, k)
+            assert a["cg_iters"] == b["cg_iters"] and a["err"] == b["err"], (i, k)
+            conv += a["converged"]
+        assert torch.equal(out["0"][1][i], out["1"][1][i]), i
+    say("converged increments:", conv, "of", 2 * len(rves))
+    assert conv >= len(rves)
+
+
+def test_folded_scalar_steps_agree_with_scalar_kernels(monkeypatch):
+    """The Galerkin CG with its scalar steps folded into the passes
+    (FFTG_GAL_FOLD=1) against the default with scalar kernels: a lockstep
+    class and a lone RVE through one increment agree to rounding (the partial
+    sums are added in another order)."""
+    from paper_2103_04770_amd import FP64
+    from paper_2103_04770_amd.batch import RVEBatch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rves = _damage_rves([16, 16, 16, 24], 800)
+    tg = _targets(len(rves), [4e-3, 6e-3])
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("FFTG_GAL_FOLD", mode)
+        batch = RVEBatch(rves, prec=FP64)
+        res = batch.step(tg, nworkers=2, **TOLS)
+        torch.cuda.synchronize()
+        out[mode] = (res, [t.clone() for t in batch.states])
+        batch.close()
+    for i in range(len(rves)):
+        a, b = out["1"][0][i], out["0"][0][i]
+        assert a["converged"] and b["converged"], i
+        assert abs(a["cg_iters"] - b["cg_iters"]) <= 0.05 * b["cg_iters"] + 2, i
+        rel = np.abs(a["sigma_mean"] - b["sigma_mean"]).max() / np.abs(b["sigma_mean"]).max()
+        assert rel <= 1e-9, (i, rel)
+        e = (out["1"][1][i][:6] - out["0"][1][i][:6]).abs().max().item()
+        assert e <= 1e-9 * out["0"][1][i][:6].abs().max().item(), (i, e)
