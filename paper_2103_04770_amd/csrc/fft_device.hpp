@@ -23,18 +23,36 @@ struct alignas(2 * sizeof(T)) cpx {
   T x, y;
 };
 
+// The complex arithmetic fixes its own roundings: products are never fused
+// into a following sum by the compiler (fp contract off), and the complex
+// product uses one explicit fma per component.  So a transform rounds the
+// same way in every instantiation (tile size, lines per thread), and results
+// do not depend on the tile the autotuner picks.
 template <typename T>
 __device__ __forceinline__ cpx<T> mk(T a, T b) { return cpx<T>{a, b}; }
 template <typename T>
-__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
-template <typename T>
-__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
-template <typename T>
-__device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) {
+#pragma clang fp contract(off)
+  return {a.x + b.x, a.y + b.y};
 }
 template <typename T>
-__device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) {
+#pragma clang fp contract(off)
+  return {a.x - b.x, a.y - b.y};
+}
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+#pragma clang fp contract(off)
+  const T ry = a.y * b.y, iy = a.y * b.x;
+  return {fma_t(a.x, b.x, -ry), fma_t(a.x, b.y, iy)};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) {
+#pragma clang fp contract(off)
+  return {a.x * s, a.y * s};
+}
 template <typename T>
 __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.x, -a.y}; }
 // a * i
@@ -57,6 +75,7 @@ __device__ __forceinline__ void dft2(cpx<T>* v) {
 
 template <bool FWD, typename T>
 __device__ __forceinline__ void dft3(cpx<T>* v) {
+#pragma clang fp contract(off)
   const T s3 = T(0.86602540378443864676372317075294);  // sqrt(3)/2
   cpx<T> t = v[1] + v[2];
   cpx<T> m = v[0] - scale(t, T(0.5));
@@ -81,6 +100,7 @@ __device__ __forceinline__ void dft4(cpx<T>* v) { dft4<FWD>(v[0], v[1], v[2], v[
 
 template <bool FWD, typename T>
 __device__ __forceinline__ void dft8(cpx<T>* v) {
+#pragma clang fp contract(off)
   const T c = T(0.70710678118654752440084436210485);  // sqrt(1/2)
   cpx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
   cpx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
@@ -294,6 +314,87 @@ template <typename T, bool FWD, bool LINEFAST, int N, int NL, int LD, int NT = F
 __device__ __forceinline__ void lds_fft_c(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
   static_assert(!PAD || (!LINEFAST && LD >= N + N / 8), "padded layout: line pitch");
   lds_fft_stages<T, FWD, LINEFAST, N, NL, LD, NT, PAD, 0, 1>(buf, tw);
+}
+
+// Direct-stage form of lds_fft_c for line-fast tiles: the first stage takes
+// its inputs from ld(t) (element t of the thread's line, tid % NL) straight
+// into registers, the last stage hands its outputs to st(t, v), and only the
+// stages in between go through LDS (element t of line l at t * NL + l).  The
+// butterflies, twiddles and their order are those of lds_fft_c, so the
+// results are the same bit for bit; a 3-stage transform makes 2 LDS round
+// trips and 3 barriers instead of 4 and 7.
+// FIRST / LAST: this stage reads from ld / writes to st (else from / to LDS).
+template <typename T, int R, bool FWD, int N, int NL, int NS, int NT, bool FIRST, bool LAST,
+          typename LDF, typename STF>
+__device__ __forceinline__ void stage_d(cpx<T>* buf, const cpx<T>* __restrict__ tw, LDF& ld,
+                                        STF& st) {
+  static_assert(NT % NL == 0, "each thread keeps one line");
+  constexpr int M = N / R;
+  constexpr int TOTAL = NL * M;
+  constexpr int MAXB = (TOTAL + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  const int line = tid % NL;
+  cpx<T> v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = tid + q * NT;
+    if (TOTAL % NT == 0 || b < TOTAL) {
+      const int j = b / NL;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = FIRST ? ld(j + r * M) : buf[(j + r * M) * NL + line];
+    }
+  }
+  if (!FIRST && !LAST) __syncthreads();  // every read of the stage before its writes
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = tid + q * NT;
+    if (TOTAL % NT == 0 || b < TOTAL) {
+      const int j = b / NL;
+      const int k = j % NS;
+      if (NS > 1) {
+        constexpr int STEP = N / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[k * r * STEP];
+          if (!FWD) w.y = -w.y;
+          v[q][r] = v[q][r] * w;
+        }
+      }
+      if (R == 2) dft2<FWD>(v[q]);
+      if (R == 3) dft3<FWD>(v[q]);
+      if (R == 4) dft4<FWD>(v[q]);
+      if (R == 8) dft8<FWD>(v[q]);
+      const int o = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (LAST)
+          st(o + r * NS, v[q][r]);
+        else
+          buf[(o + r * NS) * NL + line] = v[q][r];
+      }
+    }
+  }
+  if (!LAST) __syncthreads();  // the stage's writes before the next stage reads
+}
+
+template <typename T, bool FWD, int N, int NL, int NT, bool GIN, bool GOUT, int S, int NS,
+          typename LDF, typename STF>
+__device__ __forceinline__ void direct_stages(cpx<T>* buf, const cpx<T>* __restrict__ tw, LDF& ld,
+                                              STF& st) {
+  if constexpr (S < c_nst(N)) {
+    constexpr int R = c_radix(N, S);
+    stage_d<T, R, FWD, N, NL, NS, NT, GIN && S == 0, GOUT && S + 1 == c_nst(N)>(buf, tw, ld, st);
+    direct_stages<T, FWD, N, NL, NT, GIN, GOUT, S + 1, NS * R>(buf, tw, ld, st);
+  }
+}
+
+// GIN = false: the input is already in LDS (line-fast, pitch NL, after a
+// barrier); GOUT = false: the output stays in LDS (a barrier follows).
+template <typename T, bool FWD, int N, int NL, int NT, typename LDF, typename STF,
+          bool GIN = true, bool GOUT = true>
+__device__ __forceinline__ void lds_fft_direct(cpx<T>* buf, const cpx<T>* __restrict__ tw, LDF ld,
+                                               STF st) {
+  direct_stages<T, FWD, N, NL, NT, GIN, GOUT, 0, 1>(buf, tw, ld, st);
 }
 
 // LDS budgets of the fixed-length kernels (bytes).  A smaller tile leaves

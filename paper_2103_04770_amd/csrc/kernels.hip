@@ -411,14 +411,21 @@ FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long L = tile * TL + l;
   const long long lb = L < nlines ? line_base(L, inner, ostride) : -1;
-  for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? data[lb + t * es] : mk(T(0), T(0));
-  __syncthreads();
-  if constexpr (FIX)
-    lds_fft_c<T, FWD, true, NF, fs_tile<T, TB>(NF), fs_tile<T, TB>(NF), NT>(buf, tw);
-  else
+  if constexpr (FIX) {
+    // first stage straight from global memory, last stage straight to it
+    auto ld = [&](int t) { return lb >= 0 ? data[lb + t * es] : mk(T(0), T(0)); };
+    auto st = [&](int t, cpx<T> v) {
+      if (lb >= 0) data[lb + t * es] = v;
+    };
+    lds_fft_direct<T, FWD, NF, fs_tile<T, TB>(NF), NT>(buf, tw, ld, st);
+  } else {
+    for (int t = t0; t < n; t += dt)
+      buf[t * TL + l] = lb >= 0 ? data[lb + t * es] : mk(T(0), T(0));
+    __syncthreads();
     lds_fft<T, FWD, true>(buf, plan, TL, TL, tw);
-  if (lb >= 0)
-    for (int t = t0; t < n; t += dt) data[lb + t * es] = buf[t * TL + l];
+    if (lb >= 0)
+      for (int t = t0; t < n; t += dt) data[lb + t * es] = buf[t * TL + l];
+  }
 }
 
 // Outer-axis inverse pass of the Galerkin CG (per component):
@@ -507,7 +514,8 @@ FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long Lloc = (long long)(blockIdx.x % tpo) * TL + l;
   const long long lb = Lloc < inner ? line_base(o * inner + Lloc, inner, ostride) : -1;
-  for (int t = t0; t < n; t += dt) {
+  // the update of element t of the thread's line (each element once)
+  auto upd = [&](int t) {
     cpx<T> pn = mk(T(0), T(0));
     if (lb >= 0) {
       const long long gi = lb + t * es;
@@ -516,15 +524,31 @@ FFTG_KERNEL_WIDE void k_gal_dir_inv(Plan plan, const cpx<T>* __restrict__ tw,
       pn = r[gi] + scale(po, beta);
       pp[gi] = pn;
     }
-    buf[t * TL + l] = pn;
-  }
-  __syncthreads();
-  if constexpr (FIX)
-    lds_fft_c<T, false, true, NF, fs_tile<T, TB>(NF), fs_tile<T, TB>(NF), NT>(buf, tw);
-  else
+    return pn;
+  };
+  if constexpr (FIX) {
+    // last stage straight to w; FP32: first stage straight from the update
+    // (FP64 keeps the update in its own sweep through LDS, which measures
+    // faster at 96^3 and 128^3: all threads load, not only those of the
+    // first stage's butterflies)
+    auto st = [&](int t, cpx<T> v) {
+      if (lb >= 0) w[lb + t * es] = v;
+    };
+    if constexpr (sizeof(T) == 4) {
+      lds_fft_direct<T, false, NF, fs_tile<T, TB>(NF), NT>(buf, tw, upd, st);
+    } else {
+      for (int t = t0; t < n; t += dt) buf[t * TL + l] = upd(t);
+      __syncthreads();
+      lds_fft_direct<T, false, NF, fs_tile<T, TB>(NF), NT, decltype(upd), decltype(st), false,
+                     true>(buf, tw, upd, st);
+    }
+  } else {
+    for (int t = t0; t < n; t += dt) buf[t * TL + l] = upd(t);
+    __syncthreads();
     lds_fft<T, false, true>(buf, plan, TL, TL, tw);
-  if (lb >= 0)
-    for (int t = t0; t < n; t += dt) w[lb + t * es] = buf[t * TL + l];
+    if (lb >= 0)
+      for (int t = t0; t < n; t += dt) w[lb + t * es] = buf[t * TL + l];
+  }
 }
 
 // Outer-axis forward pass of the Galerkin CG: w <- forward transform of w,
@@ -551,24 +575,26 @@ FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
   const long long Lloc = (long long)(blockIdx.x % tpo) * TL + l;
   const long long lb = Lloc < inner ? line_base(o * inner + Lloc, inner, ostride) : -1;
-  for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? w[lb + t * es] : mk(T(0), T(0));
-  __syncthreads();
-  if constexpr (FIX)
-    lds_fft_c<T, true, true, NF, fs_tile<T, kDotBytes<T>>(NF), fs_tile<T, kDotBytes<T>>(NF),
-              NT>(buf, tw);
-  else
-    lds_fft<T, true, true>(buf, plan, TL, TL, tw);
+  // every element of a line has the same kx (es is a multiple of n1h)
+  const double wt = lb >= 0 ? hweight((int)(lb % n1h), n1h) : 0.0;
   double acc = 0.0;
-  if (lb >= 0) {
-    // every element of a line has the same kx (es is a multiple of n1h)
-    const double wt = hweight((int)(lb % n1h), n1h);
-    for (int t = t0; t < n; t += dt) {
+  auto st = [&](int t, cpx<T> v) {
+    if (lb >= 0) {
       const long long gi = lb + t * es;
-      const cpx<T> v = buf[t * TL + l];
       w[gi] = v;
       const cpx<T> pv = pp[gi];
       acc += wt * ((double)pv.x * (double)v.x + (double)pv.y * (double)v.y);
     }
+  };
+  if constexpr (FIX) {
+    // first stage straight from w, last stage straight back with the dot
+    auto ld = [&](int t) { return lb >= 0 ? w[lb + t * es] : mk(T(0), T(0)); };
+    lds_fft_direct<T, true, NF, fs_tile<T, kDotBytes<T>>(NF), NT>(buf, tw, ld, st);
+  } else {
+    for (int t = t0; t < n; t += dt) buf[t * TL + l] = lb >= 0 ? w[lb + t * es] : mk(T(0), T(0));
+    __syncthreads();
+    lds_fft<T, true, true>(buf, plan, TL, TL, tw);
+    for (int t = t0; t < n; t += dt) st(t, buf[t * TL + l]);
   }
   const double s = block_sum<NT>(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;

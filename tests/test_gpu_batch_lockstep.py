@@ -207,12 +207,12 @@ def test_folded_scalar_steps_agree_with_scalar_kernels(monkeypatch):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     rves = _damage_rves([16, 16, 16, 24], 800)
-    tg = _targets(len(rves), [4e-3, 6e-3])
+    tg = _targets(len(rves), [4e-3, 5e-3])
     out = {}
     for mode in ("1", "0"):
         monkeypatch.setenv("FFTG_GAL_FOLD", mode)
         batch = RVEBatch(rves, prec=FP64)
-        res = batch.step(tg, nworkers=2, **TOLS)
+        res = batch.step(tg, nworkers=2, **dict(TOLS, max_stagger=60))
         torch.cuda.synchronize()
         out[mode] = (res, [t.clone() for t in batch.states])
         batch.close()
