@@ -304,13 +304,13 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
   constexpr bool FIX = NF > 0;
   constexpr int NT = FIX ? kFusedThreads : FFT_THREADS;
   constexpr int LDX = FIX ? padded_pitch(NF) : 1;
-  __shared__ cpx<T> buf[FIX ? ND * fx_fused_lines<T>(NF, ND) / 2 * LDX : LDS_ELEMS];
+  __shared__ cpx<T> buf[FIX ? ND * fx_helm_lines<T>(NF, ND) / 2 * LDX : LDS_ELEMS];
   // A workgroup holds lines of one system only: two real lines share one
   // complex transform, which leaves rounding of the larger line's magnitude
   // in the smaller one, so lines of fields of very different size must never
   // be paired.
   const long long lpsys = (long long)g.n2 * g.n3;
-  const int NL = FIX ? fx_fused_lines<T>(NF, ND) : NL_rt;
+  const int NL = FIX ? fx_helm_lines<T>(NF, ND) : NL_rt;
   const long long bps = (lpsys + NL - 1) / NL;  // workgroups per system
   const long long sys = blockIdx.x / bps;
   const long long line0 = sys * lpsys + (blockIdx.x % bps) * NL;
@@ -329,7 +329,7 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, false, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, LDX, NT, true>(
+    lds_fft_c<T, false, false, NF, ND * fx_helm_lines<T>(NF, ND) / 2, LDX, NT, true>(
         buf, tw);
   else
     lds_fft<T, false, false>(buf, plan, P, n1, tw);
@@ -348,7 +348,7 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
   }
   __syncthreads();
   if constexpr (FIX)
-    lds_fft_c<T, true, false, NF, ND * fx_fused_lines<T>(NF, ND) / 2, LDX, NT, true>(
+    lds_fft_c<T, true, false, NF, ND * fx_helm_lines<T>(NF, ND) / 2, LDX, NT, true>(
         buf, tw);
   else
     lds_fft<T, true, false>(buf, plan, P, n1, tw);
@@ -673,17 +673,32 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
     }
   }
   __syncthreads();
-  if constexpr (FIX)
-    lds_fft_c<T, false, true, NF, NC * fs_tile_wide<T>(NF, NC), NC * fs_tile_wide<T>(NF, NC),
-              NT>(buf, tw);
-  else
-    lds_fft<T, false, true>(buf, plan, ld, ld, tw);
-  if (lb >= 0)
-    for (int t = t0; t < n; t += dt) {
-      const long long gi = lb + t * es;
+  constexpr int TLC = FIX ? fs_tile_wide<T>(NF, NC) : 1;
+  if constexpr (FIX && NT % (NC * TLC) == 0) {
+    // last stage straight to the NC fields (pseudo-line pl = field pl / TL,
+    // line pl % TL of the tile)
+    const int pl = threadIdx.x % (NC * TLC), jf = pl / TLC;
+    const long long Lf = (long long)(blockIdx.x % tpo) * TLC + pl % TLC;
+    const long long lbf = Lf < inner ? line_base((long long)sys * inner + Lf, inner, ostride) : -1;
+    auto nold = [](int) { return mk(T(0), T(0)); };
+    auto stf = [&](int t, cpx<T> v) {
+      if (lbf >= 0) w[jf * wstride + lbf + t * es] = v;
+    };
+    lds_fft_direct<T, false, NF, NC * TLC, NT, decltype(nold), decltype(stf), false, true>(
+        buf, tw, nold, stf);
+  } else {
+    if constexpr (FIX)
+      lds_fft_c<T, false, true, NF, NC * fs_tile_wide<T>(NF, NC), NC * fs_tile_wide<T>(NF, NC),
+                NT>(buf, tw);
+    else
+      lds_fft<T, false, true>(buf, plan, ld, ld, tw);
+    if (lb >= 0)
+      for (int t = t0; t < n; t += dt) {
+        const long long gi = lb + t * es;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) w[j * wstride + gi] = buf[t * ld + j * TL + l];
-    }
+        for (int j = 0; j < NC; ++j) w[j * wstride + gi] = buf[t * ld + j * TL + l];
+      }
+  }
 }
 
 // y pass of the split Helmholtz operator (3D), lines (z, kx) of the
@@ -788,22 +803,35 @@ FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo 
   const long long lb = Lloc < inner ? line_base(L, inner, ostride) : -1;
   const bool zouter = g.ndim == 3;
   const int lkx = (int)(Lloc % g.n1h), lky = (int)(Lloc / g.n1h);
-  for (int t = t0; t < n; t += dt) {
-    if (lb >= 0) {
-      const long long gi = lb + t * es;
+  constexpr int TLC = FIX ? fs_tile_wide<T>(NF, NC) : 1;
+  if constexpr (FIX && NT % (NC * TLC) == 0) {
+    // first stage straight from the NC fields: the thread's pseudo-line of
+    // the tile is field pl / TL, line pl % TL
+    const int pl = threadIdx.x % (NC * TLC), jf = pl / TLC;
+    const long long Lf = (long long)(blockIdx.x % tpo) * TLC + pl % TLC;
+    const long long lbf = Lf < inner ? line_base((long long)sys * inner + Lf, inner, ostride) : -1;
+    auto ldf = [&](int t) { return lbf >= 0 ? w[jf * wstride + lbf + t * es] : mk(T(0), T(0)); };
+    auto nost = [](int, cpx<T>) {};
+    lds_fft_direct<T, true, NF, NC * TLC, NT, decltype(ldf), decltype(nost), true, false>(
+        buf, tw, ldf, nost);
+  } else {
+    for (int t = t0; t < n; t += dt) {
+      if (lb >= 0) {
+        const long long gi = lb + t * es;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = w[j * wstride + gi];
-    } else {
+        for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = w[j * wstride + gi];
+      } else {
 #pragma unroll
-      for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
+        for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
+      }
     }
+    __syncthreads();
+    if constexpr (FIX)
+      lds_fft_c<T, true, true, NF, NC * fs_tile_wide<T>(NF, NC), NC * fs_tile_wide<T>(NF, NC),
+                NT>(buf, tw);
+    else
+      lds_fft<T, true, true>(buf, plan, ld, ld, tw);
   }
-  __syncthreads();
-  if constexpr (FIX)
-    lds_fft_c<T, true, true, NF, NC * fs_tile_wide<T>(NF, NC), NC * fs_tile_wide<T>(NF, NC),
-              NT>(buf, tw);
-  else
-    lds_fft<T, true, true>(buf, plan, ld, ld, tw);
   double acc = 0.0;
   for (int t = t0; t < n; t += dt) {
     if (lb >= 0) {
@@ -2498,13 +2526,13 @@ void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* 
   const long long ws = (long long)nsys * g.Ns;
   FFTG_DISPATCH_N(g.n1, {
     if (g.ndim == 3) {
-      const int NL = NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
+      const int NL = NF ? fx_helm_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
       const long long nb = (lpsys + NL - 1) / NL * nsys;
       hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 3>), dim3((unsigned)nb),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
                          st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl);
     } else {
-      const int NL = NF ? fx_fused_lines<T>(NF, 2) : fused_lines_rt(g.n1, 2);
+      const int NL = NF ? fx_helm_lines<T>(NF, 2) : fused_lines_rt(g.n1, 2);
       const long long nb = (lpsys + NL - 1) / NL * nsys;
       hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 2>), dim3((unsigned)nb),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,

@@ -64,11 +64,16 @@ def short(name):
 
 
 def _trace_durations(path):
-    d = collections.defaultdict(list)
+    """Per kernel, the durations (us) of its launches in launch order."""
+    rows = []
     fh = gzip.open(path, "rt") if path.endswith(".gz") else open(path)
     for r in csv.DictReader(fh):
-        d[short(r["Kernel_Name"])].append(
-            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        rows.append((int(r["Start_Timestamp"]), short(r["Kernel_Name"]),
+                     (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    rows.sort()
+    d = collections.defaultdict(list)
+    for _, k, us in rows:
+        d[k].append(us)
     return d
 
 
@@ -96,11 +101,17 @@ def stats_text(path, cmd, trace=None, top=20):
 
 
 def _counter(dirpath, name):
+    """Per kernel, the counter value of each dispatch, in dispatch order."""
     path = glob.glob(os.path.join(dirpath, "*counter_collection.csv"))[0]
-    agg = collections.defaultdict(list)
-    for r in csv.DictReader(open(path)):
+    rows = []
+    for i, r in enumerate(csv.DictReader(open(path))):
         if r["Counter_Name"] == name:
-            agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+            order = int(r["Dispatch_Id"]) if r.get("Dispatch_Id", "").isdigit() else i
+            rows.append((order, short(r["Kernel_Name"]), float(r["Counter_Value"])))
+    rows.sort()
+    agg = collections.defaultdict(list)
+    for _, k, v in rows:
+        agg[k].append(v)
     return agg
 
 
@@ -156,8 +167,22 @@ def rates(trace, fetch_dir, write_dir, copy_mib, cmd_trace, cmd_counters, peak_g
     cf = copy_mib * 1024.0 / max(F["__amd_rocclr_copyBuffer"])
     cw = copy_mib * 1024.0 / max(W["__amd_rocclr_copyBuffer"])
     rows = []
+    paired = 0
     for k, v in dur.items():
         if k not in F or k not in W or k.startswith("__amd"):
+            continue
+        if len(v) == len(F[k]) == len(W[k]):
+            # the same launches in both runs (deterministic workload): pair
+            # them one by one, so that a launch's bytes go with its own
+            # duration (lockstep Krylov launches cover a varying number of
+            # live systems)
+            b = [(f * cf + w * cw) * 1024.0 for f, w in zip(F[k], W[k])]
+            bmax = max(b)
+            sel = [i for i in range(len(v)) if b[i] >= 0.5 * bmax]
+            tb, tu = sum(b[i] for i in sel), sum(v[i] for i in sel)
+            us, mb = tu / len(sel), tb / len(sel) / 1e6
+            rows.append((tu, k + " *", len(sel), us, mb, tb / tu / 1e3))
+            paired += 1
             continue
         full = [x for x in v if x >= 0.2 * max(v)]
         us = sum(full) / len(full)
@@ -167,7 +192,9 @@ def rates(trace, fetch_dir, write_dir, copy_mib, cmd_trace, cmd_counters, peak_g
     out = ["HBM rate per pass: rocprofv3 counter bytes / rocprofv3 kernel duration",
            "durations: " + cmd_trace, "bytes: " + cmd_counters,
            "full launches only (duration >= 20%% of the kernel's longest; bytes: counters >= 50%%"
-           " of the kernel's largest); peak %.0f GB/s" % peak_gbs, "",
+           " of the kernel's largest); peak %.0f GB/s" % peak_gbs,
+           "* = the runs launched this kernel the same number of times: launches paired one by one"
+           " (bytes >= 50%% of the largest, their own durations); %d kernels paired" % paired, "",
            "%-52s %6s %10s %10s %10s %7s" % ("kernel", "full", "avg_us", "MB", "GB/s", "of_peak")]
     for _, k, n, us, mb, gbs in rows[:top]:
         out.append("%-52s %6d %10.2f %10.1f %10.0f %7.3f" % (k[:52], n, us, mb, gbs,

@@ -134,6 +134,27 @@ def test_profiling_summaries_on_synthetic_csv(tmp_path):
     assert full == 2 and us == pytest.approx(50.0)
     assert mb == pytest.approx(400 * 1024 / 1e6, abs=0.05)
     assert gbs == pytest.approx(400 * 1024 / 50e-6 / 1e9, abs=0.5)   # printed to 1 GB/s
+    # the same launches in both runs: paired one by one (a lockstep launch
+    # with fewer live systems moves fewer bytes in less time)
+    k2 = "void fftg::k_h_div_fwd<double, 128, 3, true>"
+    q2 = '"%s"' % k2
+    trace.write_text("Kernel_Name,Start_Timestamp,End_Timestamp\n"
+                     "%s,300000,360000\n%s,0,50000\n%s,100000,110000\n" % (q2, q2, q2))
+    for name, counter, copy_kib in (("f", "FETCH_SIZE", 512.0), ("w", "WRITE_SIZE", 1024.0)):
+        vals = (100.0, 20.0, 100.0) if counter == "FETCH_SIZE" else (200.0, 40.0, 200.0)
+        (tmp_path / name / "run_counter_collection.csv").write_text(
+            "Kernel_Name,Counter_Name,Counter_Value,Dispatch_Id\n"
+            "__amd_rocclr_copyBuffer,%s,%f,1\n%s,%s,%f,2\n%s,%s,%f,3\n%s,%s,%f,4\n" % (
+                counter, copy_kib, q2, counter, vals[0], q2, counter, vals[1], q2, counter,
+                vals[2]))
+    text = pr.rates(str(trace), str(tmp_path / "f"), str(tmp_path / "w"), 1, "t", "c")
+    row = [l for l in text.splitlines() if l.startswith(k2)][0]
+    assert "true> *" in row
+    f = row.split()
+    # launches in start order: 50, 10, 60 us with 400, 80, 400 KiB: the
+    # first and last are full, 800 KiB in 110 us
+    assert int(f[-5]) == 2 and float(f[-4]) == pytest.approx(55.0)
+    assert float(f[-2]) == pytest.approx(800 * 1024 / 110e-6 / 1e9, abs=0.5)
 
 
 def test_bench_refuses_more_than_one_gpu():
