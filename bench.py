@@ -60,7 +60,8 @@ def kernel_bytes(name, n, c, nd, J, fp32):
         "galerkin_outer_dir_inv": 6 * c * Ns * zc,
         "galerkin_outer_dot_fwd": 3 * c * Ns * zc,
         "galerkin_resid": 3 * c * Ns * zc,
-        "helmholtz_x_fused": 2 * nd * Ns * zc + N * zr,
+        # the staggered step reads ell^2 through the 1-byte phase index
+        "helmholtz_x_fused": 2 * nd * Ns * zc + N,
         # 3D: the outer passes transform two fields; the y passes map two
         # fields to the three gradient components and back
         "helmholtz_y_inv": (2 + nd) * Ns * zc,

@@ -112,6 +112,13 @@ struct fftg_handle {
   void *hx = nullptr, *hr = nullptr, *hp = nullptr, *hAp = nullptr, *hb = nullptr,
        *hw = nullptr;
   int helm_cap = 0;       // systems the Helmholtz workspace holds (one per field)
+  // ell^2 of the Helmholtz x pass from a per-phase table (staggered step of
+  // one RVE: hphase is its phase array while the solve runs, else null):
+  // ptab [field][kMaxPhases] in work precision, ptab64 in FP64, hptab pinned
+  const unsigned char* hphase = nullptr;
+  void* ptab = nullptr;
+  double* ptab64 = nullptr;
+  double* hptab = nullptr;
   void* rtmp = nullptr;   // real scratch [max(c, 2)][N] in work precision
   void* ell2w = nullptr;  // work-precision ell2 [N]
   cpx<double>* ref64 = nullptr;  // FP64 refinement workspace, 6 spectra per system
@@ -152,6 +159,7 @@ struct fftg_handle {
   struct GraphSlot {
     hipGraphExec_t exec = nullptr;
     unsigned long long key = 0;
+    const void* kphase = nullptr;  // Helmholtz graphs: the phase array they read
   };
   GraphSlot ggal;
   GraphSlot ghelm[4];
@@ -778,6 +786,12 @@ void galerkin_cg(fftg_handle* H, const unsigned char* mask, double bb, double to
   status = k.done;
 }
 
+// the per-phase ell^2 table of the work precision, while a phase array is set
+template <typename T>
+const T* phase_tab(fftg_handle* H) {
+  return H->hphase ? static_cast<const T*>(H->ptab) : nullptr;
+}
+
 // One Helmholtz PCG iteration of nsys stacked systems (one per non-local
 // field, each with its own scalars): 5 passes + 2 scalar kernels, all on H->st.
 template <typename T>
@@ -795,7 +809,7 @@ void helm_iteration(fftg_handle* H, const T* ell2, int nsys) {
   {
     KT t(H, K_HLM_X);
     fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl,
-                                    H->ctl, H->st, nsys);
+                                    H->ctl, H->st, nsys, H->hphase, phase_tab<T>(H));
   }
   helm_inner<T>(H, true, C<T>(H->hw), H->ctl, K_HLM_YF, nsys);
   int nb;
@@ -827,13 +841,14 @@ hipGraphExec_t helm_graph(fftg_handle* H, const T* ell2, int nsys) {
   const unsigned long long key = (unsigned long long)(uintptr_t)ell2 |
                                  (H->fp32() ? 1ull : 0ull) | ((unsigned long long)nsys << 1);
   for (auto& sl : H->ghelm)
-    if (sl.exec && sl.key == key) return sl.exec;
+    if (sl.exec && sl.key == key && sl.kphase == H->hphase) return sl.exec;
   auto& sl = H->ghelm[H->ghelm_next];
   H->ghelm_next = (H->ghelm_next + 1) % 4;
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
   sl.exec = nullptr;
   sl.exec = capture(H, [&](int) { helm_iteration<T>(H, ell2, nsys); });
   sl.key = key;
+  sl.kphase = H->hphase;
   return sl.exec;
 }
 
@@ -895,7 +910,7 @@ void helm_krylov(fftg_handle* H, const T* ell2, int nsys, const double* ell2_ref
                               C<T>(H->hx), C<T>(H->hx), C<T>(H->hw), H->ctl, H->st, nsys);
     helm_inner<T>(H, false, C<T>(H->hw), nullptr, K_HLM_YI, nsys);
     fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl, nullptr,
-                                    H->st, nsys);
+                                    H->st, nsys, H->hphase, phase_tab<T>(H));
     helm_inner<T>(H, true, C<T>(H->hw), nullptr, K_HLM_YF, nsys);
     fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hx),
                               C<T>(H->hw), C<T>(H->hAp), nullptr, H->ctl, H->st, nsys);
@@ -1043,7 +1058,8 @@ void helm_apply64(fftg_handle* H, const cpx<double>* x, cpx<double>* w, cpx<doub
                                  xm, xm, w, nullptr, H->st, nsys);
   helm_inner<double>(H, false, w, nullptr, K_HLM_YI, nsys);
   fftg::launch_x_fused_helm<double, double>(H->plan[0], TW<double>(H, 0), g, w, ell2,
-                                            1.0 / (double)g.N, nullptr, H->st, nsys);
+                                            1.0 / (double)g.N, nullptr, H->st, nsys, H->hphase,
+                                            H->hphase ? H->ptab64 : nullptr);
   helm_inner<double>(H, true, w, nullptr, K_HLM_YF, nsys);
   fftg::launch_h_div_fwd<double>(H->plan[oa], TW<double>(H, oa), g, zo, H->S64, x, w, Ap,
                                  nullptr, nullptr, H->st, nsys);
@@ -1375,6 +1391,9 @@ void destroy(fftg_handle* H) {
   dfree((void*&)H->ctl);
   if (H->hctl) (void)hipHostFree(H->hctl);
   if (H->hsums) (void)hipHostFree(H->hsums);
+  dfree(H->ptab);
+  dfree((void*&)H->ptab64);
+  if (H->hptab) (void)hipHostFree(H->hptab);
   dfree(H->hx);
   dfree(H->hr);
   dfree(H->hp);
@@ -1491,6 +1510,32 @@ int mech_adjoint(fftg_handle* H, const unsigned char* phase, const MatTable& tab
   return it;
 }
 
+// ell^2 of the fields of one RVE as per-phase tables for the Helmholtz x
+// pass (the values k_ell2 writes into the ell^2 fields), and its phase array;
+// the guard clears the phase array again when the staggered step ends.
+void set_helm_phase(fftg_handle* H, const unsigned char* phase, const MatTable& t, int J) {
+  const int nt = FFTG_MAX_FIELDS * fftg::kMaxPhases;
+  double* h64 = H->hptab;
+  float* h32 = reinterpret_cast<float*>(H->hptab + nt);
+  for (int j = 0; j < J; ++j)
+    for (int p = 0; p < fftg::kMaxPhases; ++p) {
+      const double v = t.m[p < t.nphase ? p : 0].ell2[j];
+      h64[j * fftg::kMaxPhases + p] = v;
+      h32[j * fftg::kMaxPhases + p] = (float)v;
+    }
+  const size_t n = (size_t)J * fftg::kMaxPhases;
+  HIPCHK(hipMemcpyAsync(H->ptab64, h64, sizeof(double) * n, hipMemcpyHostToDevice, H->st));
+  if (H->fp32())
+    HIPCHK(hipMemcpyAsync(H->ptab, h32, sizeof(float) * n, hipMemcpyHostToDevice, H->st));
+  else
+    HIPCHK(hipMemcpyAsync(H->ptab, h64, sizeof(double) * n, hipMemcpyHostToDevice, H->st));
+  H->hphase = phase;
+}
+struct PhaseGuard {
+  fftg_handle* H;
+  ~PhaseGuard() { H->hphase = nullptr; }
+};
+
 // One increment of Algorithm 1 on a validated call.  abort_on_mech: leave
 // the staggered loop as soon as a mechanics solve fails (adaptive driver);
 // newton_div: Newton divergence guard (0 = off).
@@ -1522,6 +1567,8 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
     HIPCHK(hipMemcpyAsync(H->ab_k, s_abar, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
                           H->st));
   fill_ell2(H, t, J, phase);
+  PhaseGuard pg{H};
+  if (J > 0) set_helm_phase(H, phase, t, J);
   fftg_stats acc{};
   bool converged = false;
   int k = 0;
@@ -2346,6 +2393,11 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
                          hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * (2 * FFTG_MAX_FIELDS + 64),
                          hipHostMallocDefault));
+    // per-phase ell^2 tables of the Helmholtz x pass (FP64 and work precision)
+    const size_t nt = (size_t)FFTG_MAX_FIELDS * fftg::kMaxPhases;
+    H->ptab = dalloc(H->wsz() * nt);
+    H->ptab64 = (double*)dalloc(sizeof(double) * nt);
+    HIPCHK(hipHostMalloc((void**)&H->hptab, sizeof(double) * 2 * nt, hipHostMallocDefault));
     for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
     return FFTG_OK;

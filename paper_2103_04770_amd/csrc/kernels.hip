@@ -296,11 +296,16 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
 // Fused x pass of the Helmholtz operator: C2R of the ND gradient
 // components, multiply by scale * ell^2(x), R2C.
 // Stacked systems: nsys x n2 x n3 lines per gradient component (component
-// stride wstride), ell2 [sys][N].
+// stride wstride), ell2 [sys][N].  With a phase array (shared by the
+// systems: the fields of one RVE), ell^2 comes from the per-phase table
+// ptab [sys][kMaxPhases] instead: 1 byte per voxel read instead of a
+// real, and the same values as the field it would replace.
 template <typename T, typename TL, int NF, int ND>
 FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int NL_rt,
                                 cpx<T>* __restrict__ w, const TL* __restrict__ ell2, T scl,
-                                int nsys, long long wstride, const KrylovCtl* __restrict__ ctl) {
+                                int nsys, long long wstride, const KrylovCtl* __restrict__ ctl,
+                                const unsigned char* __restrict__ phase,
+                                const TL* __restrict__ ptab) {
   constexpr bool FIX = NF > 0;
   constexpr int NT = FIX ? kFusedThreads : FFT_THREADS;
   constexpr int LDX = FIX ? padded_pitch(NF) : 1;
@@ -338,7 +343,9 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
     const int l = e / n1, x = e % n1;
     const long long line = line0 + l;
     if (line >= nlines) continue;
-    const T f = (T)ell2[line * n1 + x] * scl;
+    const TL e2 = phase ? ptab[sys * kMaxPhases + phase[(line - sys * lpsys) * n1 + x]]
+                        : ell2[line * n1 + x];
+    const T f = (T)e2 * scl;
 #pragma unroll
     for (int q = 0; q < ND; ++q) {
       const int s = q * NL + l;
@@ -2521,7 +2528,8 @@ void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cp
 
 template <typename T, typename TL>
 void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
-                         const TL* ell2, T scl, const KrylovCtl* ctl, hipStream_t st, int nsys) {
+                         const TL* ell2, T scl, const KrylovCtl* ctl, hipStream_t st, int nsys,
+                         const unsigned char* phase, const TL* ptab) {
   const long long lpsys = (long long)g.n2 * g.n3;
   const long long ws = (long long)nsys * g.Ns;
   FFTG_DISPATCH_N(g.n1, {
@@ -2530,13 +2538,13 @@ void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* 
       const long long nb = (lpsys + NL - 1) / NL * nsys;
       hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 3>), dim3((unsigned)nb),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
-                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl);
+                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl, phase, ptab);
     } else {
       const int NL = NF ? fx_helm_lines<T>(NF, 2) : fused_lines_rt(g.n1, 2);
       const long long nb = (lpsys + NL - 1) / NL * nsys;
       hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 2>), dim3((unsigned)nb),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
-                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl);
+                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl, phase, ptab);
     }
   })
 }
@@ -2927,7 +2935,8 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, i
   template void launch_x_fused_gal<T, T>(const Plan&, const cpx<T>*, const Geo&, int, cpx<T>*,   \
                                          const T*, T, const KrylovCtl*, hipStream_t, int);       \
   template void launch_x_fused_helm<T, T>(const Plan&, const cpx<T>*, const Geo&, cpx<T>*,       \
-                                          const T*, T, const KrylovCtl*, hipStream_t, int);      \
+                                          const T*, T, const KrylovCtl*, hipStream_t, int,       \
+                                          const unsigned char*, const T*);                       \
   template void launch_constitutive<T>(const MatTable&, const Geo&, int, int,                    \
                                        const unsigned char*, const double*, const double*,       \
                                        const double*, double*, double*, double*, T*,             \

@@ -64,10 +64,11 @@ struct Mat {
   // nucleation, cap of f* and the porosity fV at which the surface vanishes
   double n, q1, q2, q3, fC, fF, fN, eN, sN, fu, fV;
 };
+constexpr int kMaxPhases = 16;  // phases of a material table
 struct MatTable {
   int nphase;
   int gtn;  // 1 when some phase is a Gurson matrix
-  Mat m[16];
+  Mat m[kMaxPhases];
 };
 
 constexpr int RED_BLOCKS = 2048;  // largest grid of the pointwise kernels
@@ -146,10 +147,13 @@ template <typename T>
 int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, const cpx<T>* pp, cpx<T>* w, cpx<T>* Ap,
                      double* partials, const KrylovCtl* ctl, hipStream_t st, int nsys = 1);
+// phase / ptab (optional): ell^2 from a per-phase table ptab [sys][kMaxPhases]
+// indexed by the phase array shared by the systems, instead of ell2.
 template <typename T, typename TL>
 void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
                          const TL* ell2, T scale, const KrylovCtl* ctl, hipStream_t st,
-                         int nsys = 1);
+                         int nsys = 1, const unsigned char* phase = nullptr,
+                         const TL* ptab = nullptr);
 template <typename T>
 int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const cpx<T>* b,
                    const cpx<T>* Ap, double* partials, const KrylovCtl* ctl, hipStream_t st,
