@@ -104,7 +104,7 @@ struct fftg_handle {
   KrylovCtl* ctl = nullptr;
   KrylovCtl* hctl = nullptr;  // pinned
   double* hsums = nullptr;    // pinned
-  // control blocks held (and 2 sys_cap + 64 sums); systems the Galerkin
+  // control blocks held (and 16 sys_cap + 64 sums); systems the Galerkin
   // workspace holds (stacked [sys][c][Ns], tangent [sys][N][8])
   int sys_cap = FFTG_MAX_FIELDS, gal_cap = 1;
   BatchWS* bws = nullptr;  // lockstep batch class workspace (lead handle of a class)
@@ -398,9 +398,9 @@ void ensure_sys(fftg_handle* H, int n) {
     H->hctl = nullptr;
     H->hsums = nullptr;
     H->ctl = (KrylovCtl*)dalloc(sizeof(KrylovCtl) * (size_t)n);
-    H->dsums = (double*)dalloc(sizeof(double) * (2 * (size_t)n + 64));
+    H->dsums = (double*)dalloc(sizeof(double) * (16 * (size_t)n + 64));
     HIPCHK(hipHostMalloc((void**)&H->hctl, sizeof(KrylovCtl) * (size_t)n, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * (2 * (size_t)n + 64),
+    HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * (16 * (size_t)n + 64),
                          hipHostMallocDefault));
     H->sys_cap = n;
   }
@@ -1232,6 +1232,27 @@ void comp_means(fftg_handle* H, int ncomp, const double* f, double* out) {
   for (int k = 0; k < ncomp; ++k) out[k] /= (double)H->g.N;
 }
 
+// Means of ncomp fields of several RVEs with one read-back: f[k] (device,
+// [ncomp][N]) -> out[6 k + i].  Each is summed as comp_means sums it.  Needs
+// ensure_sys(n) for n >= f.size() / 2.
+void batch_means(fftg_handle* H, int ncomp, const std::vector<const double*>& f,
+                 std::vector<double>& out) {
+  const int n = (int)f.size();
+  out.assign(6 * (size_t)n, 0.0);
+  if (n == 0) return;
+  const long long stride = 6LL * fftg::RED_BLOCKS;  // comp_sums partials of one field set
+  for (int k = 0; k < n; ++k) {
+    double* part = H->partials + k * stride;
+    const int nb = fftg::launch_comp_sums(H->g.N, ncomp, f[k], part, H->st);
+    fftg::launch_fin_sums(part, nb, ncomp, H->dsums + 6 * k, H->st);
+  }
+  HIPCHK(hipMemcpyAsync(H->hsums, H->dsums, sizeof(double) * 6 * n, hipMemcpyDeviceToHost,
+                        H->st));
+  sync(H);
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < ncomp; ++i) out[6 * k + i] = H->hsums[6 * k + i] / (double)H->g.N;
+}
+
 double wall_ms(std::chrono::steady_clock::time_point a) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
 }
@@ -1745,15 +1766,22 @@ void mechanics_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* 
   const int c = H->c;
   const int n = (int)S.size();
   const double sqN = std::sqrt((double)g.N);
+  std::vector<const double*> fl;
   for (auto& s : S) {
     s.nl = s.live;
     s.o = MechOut{};
     s.o.relres = HUGE_VAL;
     s.r = 0;
+    if (s.nl) fl.push_back(s.eps);
+  }
+  std::vector<double> mv;
+  batch_means(H, c, fl, mv);
+  int km = 0;
+  for (auto& s : S) {
     if (!s.nl) continue;
     // move the strain-controlled means to their targets
-    double mean[6], delta[6] = {0, 0, 0, 0, 0, 0};
-    comp_means(H, c, s.eps, mean);
+    const double* mean = &mv[6 * km++];
+    double delta[6] = {0, 0, 0, 0, 0, 0};
     bool any = false;
     for (int k = 0; k < c; ++k)
       if (!mask[k]) {
@@ -1846,37 +1874,50 @@ void mechanics_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* 
   for (auto& s : S) s.o.newton = s.r;
 }
 
-// Commit an RVE's increment to its item (the end of stagger_core).
-void commit_bsys(fftg_handle* H, BSys& s, int J, std::chrono::steady_clock::time_point t_all) {
+// Commit the increments of RVEs to their items (the end of stagger_core),
+// their means read back together.
+void commit_many(fftg_handle* H, const std::vector<BSys*>& L, int J,
+                 std::chrono::steady_clock::time_point t_all) {
+  if (L.empty()) return;
   const int c = H->c;
   const long long N = H->g.N;
-  fftg_batch_item& it = *s.it;
-  HIPCHK(hipMemcpyAsync(s.s_eps, s.eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice, H->st));
-  HIPCHK(hipMemcpyAsync(s.s_epsp, s.st1, sizeof(double) * 7 * N, hipMemcpyDeviceToDevice, H->st));
-  if (J > 0) {
-    fftg::launch_commit_hist(s.tab, N, J, it.phase, s.ab, s.s_abar, s.s_hist, H->st);
-    HIPCHK(hipMemcpyAsync(s.s_abar, s.ab, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
+  std::vector<const double*> f;
+  for (BSys* s : L) {
+    fftg_batch_item& it = *s->it;
+    HIPCHK(hipMemcpyAsync(s->s_eps, s->eps, sizeof(double) * c * N, hipMemcpyDeviceToDevice,
                           H->st));
+    HIPCHK(hipMemcpyAsync(s->s_epsp, s->st1, sizeof(double) * 7 * N, hipMemcpyDeviceToDevice,
+                          H->st));
+    if (J > 0) {
+      fftg::launch_commit_hist(s->tab, N, J, it.phase, s->ab, s->s_abar, s->s_hist, H->st);
+      HIPCHK(hipMemcpyAsync(s->s_abar, s->ab, sizeof(double) * J * N, hipMemcpyDeviceToDevice,
+                            H->st));
+    }
+    HIPCHK(hipMemcpyAsync(it.sigma_out, s->sig, sizeof(double) * c * N,
+                          hipMemcpyDeviceToDevice, H->st));
+    f.push_back(s->sig);
   }
-  HIPCHK(hipMemcpyAsync(it.sigma_out, s.sig, sizeof(double) * c * N, hipMemcpyDeviceToDevice,
-                        H->st));
-  double ms[6], me[6];
-  comp_means(H, c, s.sig, ms);
-  comp_means(H, c, s.eps, me);
-  for (int i = 0; i < 12; ++i) it.homog_out[i] = 0.0;
-  for (int i = 0; i < c; ++i) {
-    it.homog_out[i] = ms[i];
-    it.homog_out[6 + i] = me[i];
-  }
+  for (BSys* s : L) f.push_back(s->eps);
+  std::vector<double> mv;
+  batch_means(H, c, f, mv);  // synchronises: the copies above are done
   check_launch();
-  sync(H);
+  const int n = (int)L.size();
   const double tot = wall_ms(t_all);
-  s.acc.t_ms[3] = std::max(0.0, tot - s.acc.t_ms[0] - s.acc.t_ms[1] - s.acc.t_ms[2]);
-  s.acc.inner_converged = s.inner_ok ? 1 : 0;
-  it.stats = s.acc;
-  it.status = s.converged && s.inner_ok ? FFTG_OK : FFTG_NOT_CONVERGED;
-  s.committed = true;
-  s.live = false;
+  for (int k = 0; k < n; ++k) {
+    BSys& s = *L[k];
+    fftg_batch_item& it = *s.it;
+    for (int i = 0; i < 12; ++i) it.homog_out[i] = 0.0;
+    for (int i = 0; i < c; ++i) {
+      it.homog_out[i] = mv[6 * k + i];
+      it.homog_out[6 + i] = mv[6 * (n + k) + i];
+    }
+    s.acc.t_ms[3] = std::max(0.0, tot - s.acc.t_ms[0] - s.acc.t_ms[1] - s.acc.t_ms[2]);
+    s.acc.inner_converged = s.inner_ok ? 1 : 0;
+    it.stats = s.acc;
+    it.status = s.converged && s.inner_ok ? FFTG_OK : FFTG_NOT_CONVERGED;
+    s.committed = true;
+    s.live = false;
+  }
 }
 
 // One increment of Algorithm 1 for every RVE of a class (stagger_core's
@@ -2004,14 +2045,20 @@ void stagger_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* ma
                             sizeof(double) * part[s.q].size(), hipMemcpyDeviceToHost, H->st));
     }
     sync(H);
+    std::vector<const double*> fl;
+    for (auto& s : S)
+      if (s.live) fl.push_back(s.eps);
+    std::vector<double> mv;
+    batch_means(H, c, fl, mv);
+    std::vector<BSys*> done;
+    int km = 0;
     for (auto& s : S) {
       if (!s.live) continue;
       const int nb = nbe[s.q];
       const std::vector<double>& pt = part[s.q];
       double mx = 0.0;
       for (int b = 0; b < nb; ++b) mx = std::max(mx, pt[b]);
-      double mean[6];
-      comp_means(H, c, s.eps, mean);
+      const double* mean = &mv[6 * km++];
       double mn = 0.0;
       for (int i = 0; i < c; ++i) mn += mean[i] * mean[i];
       mn = std::sqrt(mn);
@@ -2029,12 +2076,15 @@ void stagger_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* ma
       s.acc.err = err;
       if (err <= stol) {
         s.converged = true;
-        commit_bsys(H, s, J, t_all);
+        done.push_back(&s);
       }
     }
+    commit_many(H, done, J, t_all);
   }
+  std::vector<BSys*> rest;
   for (auto& s : S)
-    if (s.live) commit_bsys(H, s, J, t_all);
+    if (s.live) rest.push_back(&s);
+  commit_many(H, rest, J, t_all);
   H->tan_valid = false;  // the tangent buffer holds the class's tangents
 }
 
@@ -2386,12 +2436,12 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
     // non-local fields) without growing
     H->npartials = (size_t)maxb * FFTG_MAX_FIELDS;
     H->partials = (double*)dalloc(sizeof(double) * H->npartials);
-    H->dsums = (double*)dalloc(sizeof(double) * (2 * FFTG_MAX_FIELDS + 64));
+    H->dsums = (double*)dalloc(sizeof(double) * (16 * FFTG_MAX_FIELDS + 64));
     // one Krylov control block per system of a lockstep solve
     H->ctl = (KrylovCtl*)dalloc(sizeof(KrylovCtl) * FFTG_MAX_FIELDS);
     HIPCHK(hipHostMalloc((void**)&H->hctl, sizeof(KrylovCtl) * FFTG_MAX_FIELDS,
                          hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * (2 * FFTG_MAX_FIELDS + 64),
+    HIPCHK(hipHostMalloc((void**)&H->hsums, sizeof(double) * (16 * FFTG_MAX_FIELDS + 64),
                          hipHostMallocDefault));
     // per-phase ell^2 tables of the Helmholtz x pass (FP64 and work precision)
     const size_t nt = (size_t)FFTG_MAX_FIELDS * fftg::kMaxPhases;
