@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "fftg.h"
+#include "host_logic.hpp"
 #include "kernels.hpp"
 
 using fftg::cpx;
@@ -61,10 +62,7 @@ struct HipError {
       throw HipError{std::string(#expr) + ": " + hipGetErrorString(e_)};               \
   } while (0)
 
-struct Fail {
-  fftg_status code;
-  std::string msg;
-};
+using fftg_host::Fail;
 
 // Workspace of a lockstep batch class (several RVEs of one grid solved as
 // stacked systems): FP64 fields [sys][comp][N], ell2 [sys][J][N].
@@ -571,31 +569,7 @@ bool has_gtn(const fftg_phase* tab, int nphase) {
 }
 
 void validate_table(const fftg_phase* tab, int nphase, int nfields) {
-  if (!tab || nphase < 1 || nphase > FFTG_MAX_PHASES)
-    throw Fail{FFTG_E_INVALID, "phase table: null or nphase outside [1, 16]"};
-  if (nfields < 0 || nfields > FFTG_MAX_FIELDS)
-    throw Fail{FFTG_E_INVALID, "nfields outside [0, 4]"};
-  for (int p = 0; p < nphase; ++p) {
-    const fftg_phase& q = tab[p];
-    if (q.model < 0 || q.model > 3) throw Fail{FFTG_E_INVALID, "unknown phase model"};
-    if (!(q.E > 0) || !(q.nu > -1.0 && q.nu < 0.5))
-      throw Fail{FFTG_E_INVALID, "phase elastic constants out of range"};
-    if (q.dfield >= nfields) throw Fail{FFTG_E_INVALID, "phase dfield >= nfields"};
-    if (q.model == FFTG_GTN) {
-      if (q.dfield < 0 || q.dfield + 1 >= nfields)
-        throw Fail{FFTG_E_INVALID, "a Gurson phase needs fields dfield and dfield + 1"};
-      if (!(q.sy > 0) || !(q.n_hard > 0 && q.n_hard < 1) || !(q.q1 > 0) || !(q.q2 > 0) ||
-          !(q.q3 > 0) || !(q.fC >= 0 && q.fF > q.fC) || !(q.fN >= 0) || !(q.sN > 0) ||
-          !(q.fu >= 0 && q.fu < q.q1 / q.q3 && 1.0 + q.q3 * q.fu * q.fu - 2.0 * q.q1 * q.fu > 0))
-        throw Fail{FFTG_E_INVALID, "Gurson parameters out of range"};
-      continue;
-    }
-    if (q.model != FFTG_ELASTIC && q.dfield >= 0 && !(q.dR > q.dC))
-      throw Fail{FFTG_E_INVALID, "damage law needs dR > dC"};
-    // the stiffness factor 1 - D must stay positive (the adjoints divide by it)
-    if (q.model != FFTG_ELASTIC && q.dfield >= 0 && !(q.dmax >= 0.0 && q.dmax < 1.0))
-      throw Fail{FFTG_E_INVALID, "damage law needs 0 <= dmax < 1"};
-  }
+  fftg_host::check_table(tab, nphase, nfields);
 }
 
 // Every phase id must index the table: counted on the device, one read-back.
@@ -1805,8 +1779,7 @@ void mechanics_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* 
                                    H->st);
     }
     if (!any) break;
-    check_launch();
-    sync(H);
+    check_launch();  // no wait: the residual read-back below waits for the stream
     const double tc = wall_ms(t0);
     t0 = std::chrono::steady_clock::now();
     for (auto& s : S) {
@@ -1862,8 +1835,7 @@ void mechanics_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* 
       s.o.cg += k[s.q].iters;
       galerkin_solution_at<T>(H, mask, s.kx, s.spec, s.eps, true);
     }
-    check_launch();
-    sync(H);
+    check_launch();  // the next Newton step's read-back waits for these
     const double tcg = wall_ms(t0);
     for (auto& s : S)
       if (need[s.q] && s.nl) {
@@ -2032,7 +2004,6 @@ void stagger_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* ma
         }
       }
     }
-    sync(H);
     const double thm = wall_ms(th);
     // staggered error (Algorithm 1 (iii)), per RVE
     for (auto& s : S) {
@@ -2086,19 +2057,6 @@ void stagger_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* ma
     if (s.live) rest.push_back(&s);
   commit_many(H, rest, J, t_all);
   H->tan_valid = false;  // the tangent buffer holds the class's tangents
-}
-
-// Items that can share a lockstep class: one grid, voxel size, derivative
-// scheme, precision, field count and macro mask.
-bool same_class(const fftg_batch_item& a, const fftg_batch_item& b) {
-  const fftg_handle* x = a.h;
-  const fftg_handle* y = b.h;
-  if (x->g.ndim != y->g.ndim || x->g.n1 != y->g.n1 || x->g.n2 != y->g.n2 || x->g.n3 != y->g.n3 ||
-      x->h != y->h || x->scheme != y->scheme || x->prec != y->prec || a.nfields != b.nfields)
-    return false;
-  for (int k = 0; k < x->c; ++k)
-    if ((a.target.mask[k] != 0) != (b.target.mask[k] != 0)) return false;
-  return true;
 }
 
 // One increment of every item of a class on the first item's handle; the
@@ -3099,18 +3057,10 @@ fftg_status fftg_drive(fftg_handle* H, const unsigned char* phase, const fftg_ph
       H->drive_bak_n = nstate + nsig;
     }
     const MatTable t = make_table(tab, nphase, J);
-    double tl = opts->t, dt = opts->dt;
-    int recs = 0, attempts = 0, cut = 0, reason = 0;
-    while (tl < opts->t_end) {
-      if (recs >= max_records) {
-        reason = 3;
-        break;
-      }
-      if (attempts >= opts->max_attempts) {
-        reason = 2;
-        break;
-      }
-      const double tn = dt >= opts->t_end - tl ? opts->t_end : tl + dt;
+    fftg_host::DriveCtl dc{opts->t,      opts->dt,    opts->t_end,       opts->dt_min,
+                           opts->dt_max, opts->grow,  max_records,       opts->max_attempts};
+    double tn = 0.0;
+    while (dc.next(tn)) {
       fftg_macro tgt = *target_end;
       for (int k = 0; k < 6; ++k) {
         tgt.E[k] = tn * target_end->E[k];
@@ -3120,39 +3070,33 @@ fftg_status fftg_drive(fftg_handle* H, const unsigned char* phase, const fftg_ph
                             hipMemcpyDeviceToDevice, H->st));
       HIPCHK(hipMemcpyAsync(H->drive_bak + nstate, sigma_out, sizeof(double) * nsig,
                             hipMemcpyDeviceToDevice, H->st));
-      ++attempts;
       auto t0 = std::chrono::steady_clock::now();
       double homog[12];
       const StaggerOut o =
           stagger_core(H, phase, t, J, state, &tgt, cg, pcg, newton_tol, newton_maxit,
                        stagger_tol, max_stagger_iters, sigma_out, homog, true, opts->newton_div);
       if (o.converged && o.inner_ok) {
-        tl = tn;
-        fftg_drive_record& r = records[recs++];
+        const int cuts = dc.cut;
+        fftg_drive_record& r = records[dc.accepted(tn)];
         r.t = tn;
         for (int i = 0; i < 12; ++i) r.homog[i] = homog[i];
         r.err = o.stats.err;
-        r.cutbacks = cut;
+        r.cutbacks = cuts;
         r.stagger_iters = o.stats.stagger_iters;
         r.newton_iters = o.stats.newton_iters;
         r.cg_iters = o.stats.cg_iters;
         r.pcg_iters = o.stats.pcg_iters;
         r.ms = wall_ms(t0);
-        cut = 0;
-        dt = std::min(dt * opts->grow, opts->dt_max);
       } else {
         HIPCHK(hipMemcpyAsync(state, H->drive_bak, sizeof(double) * nstate,
                               hipMemcpyDeviceToDevice, H->st));
         HIPCHK(hipMemcpyAsync(sigma_out, H->drive_bak + nstate, sizeof(double) * nsig,
                               hipMemcpyDeviceToDevice, H->st));
-        ++cut;
-        dt = dt / 2.0;
-        if (dt < opts->dt_min) {
-          reason = 1;
-          break;
-        }
+        if (!dc.rejected()) break;
       }
     }
+    const double tl = dc.t, dt = dc.dt;
+    const int reason = dc.reason, attempts = dc.attempts, recs = dc.recs;
     sync(H);
     opts->t = tl;
     opts->dt = dt;
@@ -3346,50 +3290,35 @@ fftg_status fftg_batch_step(fftg_batch_item* items, int n, int nworkers,
   std::sort(hs.begin(), hs.end());
   if (std::adjacent_find(hs.begin(), hs.end()) != hs.end()) return FFTG_E_INVALID;
   // classes of items that run in lockstep (FFTG_BATCH_LOCKSTEP=0: every item
-  // alone on its own handle and stream)
+  // alone on its own handle and stream); a class of large grids is split into
+  // sub-classes of about kClassVoxels voxels (FFTG_BATCH_CLASS_VOXELS
+  // overrides), run by different workers: a sub-class already fills the GPU,
+  // and several of them in flight keep it busy while one waits on its host
+  // decisions or on its slowest RVE.
   const char* ls = std::getenv("FFTG_BATCH_LOCKSTEP");
   const bool lockstep = !(ls && ls[0] == '0' && ls[1] == '\0');
-  std::vector<std::vector<int>> units;
-  for (int i = 0; i < n; ++i) {
-    bool placed = false;
-    if (lockstep)
-      for (auto& u : units)
-        if (same_class(items[u[0]], items[i])) {
-          u.push_back(i);
-          placed = true;
-          break;
-        }
-    if (!placed) units.push_back({i});
-  }
-  // A class of large grids is split into sub-classes of about kClassVoxels
-  // voxels (FFTG_BATCH_CLASS_VOXELS overrides), run by different workers: a
-  // sub-class already fills the GPU, and several of them in flight keep it
-  // busy while one waits on its host decisions or on its slowest RVE.
   long long cap = kClassVoxels;
   if (const char* cv = std::getenv("FFTG_BATCH_CLASS_VOXELS")) {
     const long long v = std::atoll(cv);
     if (v > 0) cap = v;
   }
-  {
-    std::vector<std::vector<int>> split;
-    for (auto& u : units) {
-      const long long per = std::max(1LL, cap / items[u[0]].h->g.N);
-      const int m = (int)u.size();
-      const int nsub = (int)((m + per - 1) / per);
-      for (int k = 0, at = 0; k < nsub; ++k) {
-        const int len = m / nsub + (k < m % nsub ? 1 : 0);
-        split.emplace_back(u.begin() + at, u.begin() + at + len);
-        at += len;
-      }
-    }
-    units.swap(split);
+  std::vector<fftg_host::ItemKey> keys(n);
+  for (int i = 0; i < n; ++i) {
+    const fftg_handle* x = items[i].h;
+    fftg_host::ItemKey& k = keys[i];
+    k.ndim = x->g.ndim;
+    k.n1 = x->g.n1;
+    k.n2 = x->g.n2;
+    k.n3 = x->g.n3;
+    k.c = x->c;
+    k.scheme = x->scheme;
+    k.prec = x->prec;
+    k.nfields = items[i].nfields;
+    k.h = x->h;
+    std::memcpy(k.mask, items[i].target.mask, 6);
+    k.voxels = x->g.N;
   }
-  // largest work first (longest-processing-time order balances the workers)
-  auto vox = [&](const std::vector<int>& u) { return (long long)u.size() * items[u[0]].h->g.N; };
-  std::stable_sort(units.begin(), units.end(),
-                   [&](const std::vector<int>& a, const std::vector<int>& b) {
-                     return vox(a) > vox(b);
-                   });
+  const std::vector<std::vector<int>> units = fftg_host::batch_units(keys, lockstep, cap);
   const int nu = (int)units.size();
   std::atomic<int> next{0};
   auto work = [&]() {
