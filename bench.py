@@ -889,6 +889,10 @@ def main():
                          "E11 = 0.01 (FP64; at most 8 minutes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a device copy of MB megabytes (counter calibration)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 64-RVE batch leg and print its record as the JSON line")
+    ap.add_argument("--batch-workers", type=int, default=8,
+                    help="host worker threads of the batch leg (1: every call from one thread)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single device, and "
@@ -908,6 +912,10 @@ def main():
             bb.copy_(a)
         torch.cuda.synchronize()
         del a, bb
+    if args.batch_only:
+        rec = run_batch(nworkers=max(1, args.batch_workers))
+        print(json.dumps(dict(batch=rec)), flush=True)
+        return
     ws = ms.workload("spheres_two_fields_%d" % args.n)
     N = int(np.prod(ws["shape"]))
     vf = float(ws["phase"].mean())
@@ -1012,7 +1020,7 @@ def main():
         out["adaptive_driver"] = run_driver()
         out["adjoint"] = run_adjoint()
         out["c2_fixed_path"] = run_c2_fixed()
-        out["batch"] = run_batch()
+        out["batch"] = run_batch(nworkers=max(1, args.batch_workers))
         out["gtn"] = run_gtn()
     if args.c5:
         out["c5_path_gradient"] = run_c5()
