@@ -152,12 +152,22 @@ struct fftg_handle {
   };
   int kt_iter = -1;
   std::vector<Pend> pend;
-  // captured Krylov iteration chunks (one graph launch = kGraphIters iterations)
+  // captured Krylov iteration chunks: kGraphIters iterations per launch, or
+  // kTailIters near the stop test
   hipStream_t cap = nullptr;
   struct GraphSlot {
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // kGraphIters, kTailIters iterations
     unsigned long long key = 0;
+    const void* kell = nullptr;    // Helmholtz graphs: the ell2 field they read
     const void* kphase = nullptr;  // Helmholtz graphs: the phase array they read
+    int knsys = 0;
+    void drop() {
+      for (auto& e : exec) {
+        if (e) (void)hipGraphExecDestroy(e);
+        e = nullptr;
+      }
+      key = 0;
+    }
   };
   GraphSlot ggal;
   GraphSlot ghelm[4];
@@ -366,19 +376,23 @@ void read_sums(fftg_handle* H, int nb, int nred, double* out) {
   sync(H);
   for (int i = 0; i < nred; ++i) out[i] = H->hsums[i];
 }
+// finalise nred sums of partials into the device sums from slot `at`, to be
+// read later together with others (read_dsums)
+void stage_sums(fftg_handle* H, int nb, int nred, int at) {
+  fftg::launch_fin_sums(H->partials, nb, nred, H->dsums + at, H->st);
+}
+void read_dsums(fftg_handle* H, int n, double* out) {
+  HIPCHK(hipMemcpyAsync(H->hsums, H->dsums, sizeof(double) * n, hipMemcpyDeviceToHost, H->st));
+  sync(H);
+  for (int i = 0; i < n; ++i) out[i] = H->hsums[i];
+}
 
 // The captured Krylov graphs hold the workspace pointers: drop them before a
 // buffer they use is reallocated.
 void drop_graphs(fftg_handle* H) {
   HIPCHK(hipStreamSynchronize(H->st));
-  if (H->ggal.exec) (void)hipGraphExecDestroy(H->ggal.exec);
-  H->ggal.exec = nullptr;
-  H->ggal.key = 0;
-  for (auto& sl : H->ghelm) {
-    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-    sl.exec = nullptr;
-    sl.key = 0;
-  }
+  H->ggal.drop();
+  for (auto& sl : H->ghelm) sl.drop();
 }
 
 // Control blocks, sums and partials for a lockstep solve of n systems.
@@ -640,20 +654,23 @@ void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1, int 
   }
 }
 
-// Capture `body` kGraphIters times on the private capture stream into an
+// Capture `body` `iters` times on the private capture stream into an
 // executable graph.  Every launch inside reads the device control block, so
-// iterations past convergence return at once.
+// iterations past convergence return at once.  Krylov loops launch graphs of
+// kGraphIters iterations, and graphs of kTailIters (even, so that the
+// parity of an iteration is its index & 1 in either) near the stop test.
 constexpr int kGraphIters = 8;
+constexpr int kTailIters = 2;
 
 template <typename F>
-hipGraphExec_t capture(fftg_handle* H, F body) {
+hipGraphExec_t capture(fftg_handle* H, F body, int iters = kGraphIters) {
   hipStream_t saved = H->st;
   H->st = H->cap;
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     try {
-      for (int i = 0; i < kGraphIters; ++i) body(i);
+      for (int i = 0; i < iters; ++i) body(i);
     } catch (...) {
       (void)hipStreamEndCapture(H->cap, &graph);
       if (graph) (void)hipGraphDestroy(graph);
@@ -671,20 +688,66 @@ hipGraphExec_t capture(fftg_handle* H, F body) {
   return ex;
 }
 
+// Iterations the slowest live system of a lockstep Krylov solve still needs,
+// predicted from how fast its residual fell between two reads of the control
+// blocks (prev, then k); -1 when some live system has no such rate yet.
+// Only the launch pattern follows from it: iterations past a system's stop
+// test return at once whatever was predicted.
+int predict_left(int nsys, const KrylovCtl* k, const KrylovCtl* prev) {
+  int left = 0;
+  for (int q = 0; q < nsys; ++q) {
+    if (k[q].done) continue;
+    const int di = k[q].iters - prev[q].iters;
+    if (di <= 0 || !(k[q].rr > 0.0) || !(k[q].rr < prev[q].rr) || !(k[q].tol2 > 0.0)) return -1;
+    const double rate = std::log(k[q].rr / prev[q].rr) / di;  // < 0
+    const double need = std::log(k[q].tol2 / k[q].rr) / rate;
+    int n = need < 1.0 ? 1 : need > 1e6 ? 1000000 : (int)std::ceil(need);
+    n = std::min(n, std::max(1, k[q].maxit - k[q].iters));
+    left = std::max(left, n);
+  }
+  return left;
+}
+
+// Graph launches of a lockstep Krylov solve until every system is done:
+// `full` (kGraphIters iterations) while the stop test is further away than
+// that, else as many launches of `tail` (kTailIters) as predict_left asks
+// for; the control blocks are read after each round.
+void run_krylov_graphs(fftg_handle* H, int nsys, KrylovCtl* k, hipGraphExec_t full,
+                       hipGraphExec_t tail) {
+  std::vector<KrylovCtl> prev(k, k + nsys);
+  for (;;) {
+    bool all = true;
+    for (int q = 0; q < nsys; ++q) all = all && k[q].done;
+    if (all) return;
+    const int left = predict_left(nsys, k, prev.data());
+    prev.assign(k, k + nsys);
+    if (left < 0 || left > kGraphIters - kTailIters) {
+      HIPCHK(hipGraphLaunch(full, H->st));
+    } else {
+      for (int i = 0; i < (left + kTailIters - 1) / kTailIters; ++i)
+        HIPCHK(hipGraphLaunch(tail, H->st));
+    }
+    read_ctls(H, nsys, k);
+  }
+}
+
+// The Galerkin CG graphs (kGraphIters and kTailIters iterations) of a mask,
+// system count, precision and scalar-step form.
 template <typename T>
-hipGraphExec_t gal_graph(fftg_handle* H, const unsigned char* mask, int nsys) {
+fftg_handle::GraphSlot& gal_graphs(fftg_handle* H, const unsigned char* mask, int nsys) {
   unsigned long long key = 1ull + (H->fp32() ? 2ull : 0ull);
   for (int i = 0; i < 6; ++i) key |= (unsigned long long)(mask[i] & 1) << (8 + i);
   key |= (unsigned long long)nsys << 16;
   key |= H->fold ? 4ull : 0ull;
-  if (H->ggal.exec && H->ggal.key == key) return H->ggal.exec;
-  if (H->ggal.exec) (void)hipGraphExecDestroy(H->ggal.exec);
-  H->ggal.exec = nullptr;
+  auto& sl = H->ggal;
+  if (sl.exec[0] && sl.key == key) return sl;
+  sl.drop();
   unsigned char m[6];
   std::memcpy(m, mask, 6);
-  H->ggal.exec = capture(H, [&](int i) { gal_iteration<T>(H, m, nsys, i & 1); });
-  H->ggal.key = key;
-  return H->ggal.exec;
+  sl.exec[0] = capture(H, [&](int i) { gal_iteration<T>(H, m, nsys, i & 1); }, kGraphIters);
+  sl.exec[1] = capture(H, [&](int i) { gal_iteration<T>(H, m, nsys, i & 1); }, kTailIters);
+  sl.key = key;
+  return sl;
 }
 
 // ------------------------------------------------------------ Galerkin CG
@@ -720,12 +783,9 @@ void galerkin_cg_n(fftg_handle* H, const unsigned char* mask, int nsys, const do
   HIPCHK(hipMemsetAsync(H->kx, 0, sizeof(cpx<T>) * c * g.Ns * nsys, H->st));
   HIPCHK(hipMemsetAsync(H->kp, 0, sizeof(cpx<T>) * c * g.Ns * nsys, H->st));
   if (!H->prof) {
-    hipGraphExec_t ex = gal_graph<T>(H, mask, nsys);
-    while (!all) {
-      HIPCHK(hipGraphLaunch(ex, H->st));
-      read_ctls(H, nsys, k);
-      all = true;
-      for (int q = 0; q < nsys; ++q) all = all && k[q].done;
+    if (!all) {
+      auto& sl = gal_graphs<T>(H, mask, nsys);
+      run_krylov_graphs(H, nsys, k, sl.exec[0], sl.exec[1]);
     }
   } else {
     int chunk = 2;
@@ -808,22 +868,25 @@ void helm_iteration(fftg_handle* H, const T* ell2, int nsys) {
   }
 }
 
+// The Helmholtz PCG graphs (kGraphIters and kTailIters iterations) of an
+// ell2 field, system count, precision and phase array (the four most recent).
 template <typename T>
-hipGraphExec_t helm_graph(fftg_handle* H, const T* ell2, int nsys) {
-  // buffers are at least 256-byte aligned: the low bits carry the precision
-  // and the system count
-  const unsigned long long key = (unsigned long long)(uintptr_t)ell2 |
-                                 (H->fp32() ? 1ull : 0ull) | ((unsigned long long)nsys << 1);
+fftg_handle::GraphSlot& helm_graphs(fftg_handle* H, const T* ell2, int nsys) {
+  const unsigned long long key = H->fp32() ? 1ull : 2ull;
   for (auto& sl : H->ghelm)
-    if (sl.exec && sl.key == key && sl.kphase == H->hphase) return sl.exec;
+    if (sl.exec[0] && sl.key == key && sl.kell == ell2 && sl.knsys == nsys &&
+        sl.kphase == H->hphase)
+      return sl;
   auto& sl = H->ghelm[H->ghelm_next];
   H->ghelm_next = (H->ghelm_next + 1) % 4;
-  if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-  sl.exec = nullptr;
-  sl.exec = capture(H, [&](int) { helm_iteration<T>(H, ell2, nsys); });
+  sl.drop();
+  sl.exec[0] = capture(H, [&](int) { helm_iteration<T>(H, ell2, nsys); }, kGraphIters);
+  sl.exec[1] = capture(H, [&](int) { helm_iteration<T>(H, ell2, nsys); }, kTailIters);
   sl.key = key;
+  sl.kell = ell2;
+  sl.knsys = nsys;
   sl.kphase = H->hphase;
-  return sl.exec;
+  return sl;
 }
 
 // ------------------------------------------------------------ Helmholtz PCG
@@ -835,11 +898,7 @@ void alloc_helm(fftg_handle* H, int nsys = 1) {
   const Geo& g = H->g;
   if (H->hx) {
     HIPCHK(hipStreamSynchronize(H->st));
-    for (auto& sl : H->ghelm) {
-      if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-      sl.exec = nullptr;
-      sl.key = 0;
-    }
+    for (auto& sl : H->ghelm) sl.drop();
     for (void** p : {&H->hx, &H->hr, &H->hp, &H->hAp, &H->hb, &H->hw}) dfree(*p);
   }
   const size_t cs = 2 * H->wsz() * (size_t)g.Ns * (size_t)nsys;
@@ -858,18 +917,21 @@ void alloc_helm(fftg_handle* H, int nsys = 1) {
 // b in H->hb (weighted |b_s|^2 = bb[s]), x0 in H->hx (x0_zero: x0 = 0, H->hx
 // is cleared); systems with bb[s] = 0 or tol[s] < 0 start as done.  On
 // return H->hx holds x and k[s] the final control block of system s.
+// bb_staged: the |b_s|^2 are still on the device (device sums 0 .. nsys-1)
+// and are read into bb together with the initial residual; a system with
+// bb[s] = 0 then gets x = 0 (the solution for a zero source).
 template <typename T>
-void helm_krylov(fftg_handle* H, const T* ell2, int nsys, const double* ell2_ref,
-                 const double* bb, const double* tol, const int* maxit, bool x0_zero,
-                 KrylovCtl* k) {
+void helm_krylov(fftg_handle* H, const T* ell2, int nsys, const double* ell2_ref, double* bb,
+                 const double* tol, const int* maxit, bool x0_zero, KrylovCtl* k,
+                 bool bb_staged = false) {
   const Geo& g = H->g;
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
   const T scl = T(1.0 / (double)g.N);
   for (int q = 0; q < nsys; ++q) {
     k[q] = KrylovCtl{};
-    k[q].bb = bb[q];
-    k[q].tol2 = tol[q] * tol[q] * bb[q];
+    k[q].bb = bb_staged ? 0.0 : bb[q];
+    k[q].tol2 = tol[q] * tol[q] * k[q].bb;
     k[q].maxit = maxit[q];
     k[q].window = std::is_same<T, float>::value ? kFp32StagnationWindow : 0;
     k[q].ell2ref = ell2_ref[q];
@@ -893,7 +955,22 @@ void helm_krylov(fftg_handle* H, const T* ell2, int nsys, const double* ell2_ref
                                           x0_zero ? C<T>(H->hx) : C<T>(H->hAp), H->partials,
                                           H->ctl, H->st, nsys);
   std::vector<double> s2(2 * (size_t)nsys);
-  read_sums(H, nr0, 2 * nsys, s2.data());
+  if (bb_staged) {
+    std::vector<double> all3(3 * (size_t)nsys);
+    stage_sums(H, nr0, 2 * nsys, nsys);
+    read_dsums(H, 3 * nsys, all3.data());
+    for (int q = 0; q < nsys; ++q) {
+      bb[q] = all3[q];
+      s2[2 * q] = all3[nsys + 2 * q];
+      s2[2 * q + 1] = all3[nsys + 2 * q + 1];
+      k[q].bb = bb[q];
+      k[q].tol2 = tol[q] * tol[q] * bb[q];
+      if (bb[q] == 0.0)
+        HIPCHK(hipMemsetAsync(C<T>(H->hx) + q * g.Ns, 0, sizeof(cpx<T>) * g.Ns, H->st));
+    }
+  } else {
+    read_sums(H, nr0, 2 * nsys, s2.data());
+  }
   bool all = true;
   for (int q = 0; q < nsys; ++q) {
     k[q].rz = s2[2 * q];
@@ -908,12 +985,9 @@ void helm_krylov(fftg_handle* H, const T* ell2, int nsys, const double* ell2_ref
   write_ctls(H, nsys, k);
   HIPCHK(hipMemsetAsync(H->hp, 0, sizeof(cpx<T>) * g.Ns * nsys, H->st));
   if (!H->prof && !H->nograph) {
-    hipGraphExec_t ex = helm_graph<T>(H, ell2, nsys);
-    while (!all) {
-      HIPCHK(hipGraphLaunch(ex, H->st));
-      read_ctls(H, nsys, k);
-      all = true;
-      for (int q = 0; q < nsys; ++q) all = all && k[q].done;
+    if (!all) {
+      auto& sl = helm_graphs<T>(H, ell2, nsys);
+      run_krylov_graphs(H, nsys, k, sl.exec[0], sl.exec[1]);
     }
   } else {
     int chunk = 2;
@@ -943,15 +1017,23 @@ void helm_krylov(fftg_handle* H, const T* ell2, int nsys, const double* ell2_ref
 }
 
 // preconditioner length^2 of each system: the given one, else the volume
-// mean of its ell2 [sys][N]
+// mean of its ell2 [sys][N].  cache (optional): the means of an earlier call
+// on the same ell2 fields when it holds nsys of them, else filled here (the
+// staggered loops solve with unchanged lengths pass after pass).
 template <typename T>
-void ell2_reference(fftg_handle* H, const T* ell2, double ell2_ref, int nsys, double* out) {
+void ell2_reference(fftg_handle* H, const T* ell2, double ell2_ref, int nsys, double* out,
+                    std::vector<double>* cache = nullptr) {
   if (ell2_ref > 0.0) {
     for (int q = 0; q < nsys; ++q) out[q] = ell2_ref;
     return;
   }
+  if (cache && (int)cache->size() == nsys) {
+    std::copy(cache->begin(), cache->end(), out);
+    return;
+  }
   read_sums(H, fftg::launch_sum_ell2<T>(H->g.N, ell2, H->partials, H->st, nsys), nsys, out);
   for (int q = 0; q < nsys; ++q) out[q] /= (double)H->g.N;
+  if (cache) cache->assign(out, out + nsys);
 }
 
 // Transforms of nsys stacked scalar fields, one field at a time: the x pass
@@ -984,7 +1066,7 @@ struct HelmOut {
 // with skip[q] set are not solved and their abar is left alone.
 void helmholtz_pcg64(fftg_handle* H, const double* alpha, const double* ell2, double ell2_ref,
                      double* abar, double tol, int maxit, int nsys, HelmOut* out,
-                     const unsigned char* skip = nullptr) {
+                     const unsigned char* skip = nullptr, std::vector<double>* refc = nullptr) {
   const Geo& g = H->g;
   fwd_fields(H, nsys, alpha, C<double>(H->hb), skip);
   std::vector<double> bb(nsys), ref(nsys), tols(nsys);
@@ -993,20 +1075,18 @@ void helmholtz_pcg64(fftg_handle* H, const double* alpha, const double* ell2, do
     if (skip && skip[q])
       HIPCHK(hipMemsetAsync(C<double>(H->hb) + q * g.Ns, 0, sizeof(cpx<double>) * g.Ns, H->st));
   fftg::launch_hermitize<double>(g, nsys, C<double>(H->hb), H->st);
-  read_sums(H, fftg::launch_wnorm2<double>(g, 1, C<double>(H->hb), H->partials, H->st, nsys),
-            nsys, bb.data());
-  ell2_reference<double>(H, ell2, ell2_ref, nsys, ref.data());
+  ell2_reference<double>(H, ell2, ell2_ref, nsys, ref.data(), refc);
+  // |b|^2 stays on the device until the initial residual is read with it
+  stage_sums(H, fftg::launch_wnorm2<double>(g, 1, C<double>(H->hb), H->partials, H->st, nsys),
+             nsys, 0);
   fwd_fields(H, nsys, abar, C<double>(H->hx), skip);
   for (int q = 0; q < nsys; ++q) {
     tols[q] = skip && skip[q] ? -1.0 : tol;
     mits[q] = maxit;
-    // a zero source has the zero solution
-    if (bb[q] == 0.0)
-      HIPCHK(hipMemsetAsync(C<double>(H->hx) + q * g.Ns, 0, sizeof(cpx<double>) * g.Ns, H->st));
   }
   std::vector<KrylovCtl> k(nsys);
   helm_krylov<double>(H, ell2, nsys, ref.data(), bb.data(), tols.data(), mits.data(), false,
-                      k.data());
+                      k.data(), true);
   inv_fields(H, nsys, C<double>(H->hx), abar, skip);
   check_launch();
   for (int q = 0; q < nsys; ++q) {
@@ -1052,7 +1132,8 @@ constexpr int kHelmSweeps = 30;
 // residual (5: the attainable accuracy is reached); the others go on.
 void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32,
                        const double* ell2_64, double ell2_ref, double* abar, double tol,
-                       int maxit, int nsys, HelmOut* out, const unsigned char* skip = nullptr) {
+                       int maxit, int nsys, HelmOut* out, const unsigned char* skip = nullptr,
+                       std::vector<double>* refc = nullptr) {
   const Geo& g = H->g;
   const long long Ns = g.Ns;
   cpx<double>* S = H->spec64;
@@ -1079,7 +1160,7 @@ void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32
   std::vector<double> bb(nsys), ref(nsys), rr(nsys), rr_prev(nsys), tin(nsys);
   std::vector<int> mits(nsys);
   read_sums(H, fftg::launch_wnorm2<double>(g, 1, b, H->partials, H->st, nsys), nsys, bb.data());
-  ell2_reference<float>(H, ell2_32, ell2_ref, nsys, ref.data());
+  ell2_reference<float>(H, ell2_32, ell2_ref, nsys, ref.data(), refc);
   fwd_fields(H, nsys, abar, x, skip);
   fftg::launch_hermitize<double>(g, nsys, x, H->st);
   int active = 0;
@@ -1153,17 +1234,19 @@ void helmholtz_refined(fftg_handle* H, const double* alpha, const float* ell2_32
 // the work-precision ell2 [sys][N] (FP32 on FP32-refined handles), ell2_64
 // the FP64 one (read by the FP64 residuals of the refinement; equal to ell2w
 // on FP64 handles).  skip (optional): fields not to solve (abar untouched).
+// refc (optional): reference lengths of earlier solves on the same fields
+// (ell2_reference).
 void helm_solve(fftg_handle* H, const double* alpha, const void* ell2w, const double* ell2_64,
                 double ell2_ref, double* abar, double tol, int maxit, int nsys, HelmOut* out,
-                const unsigned char* skip = nullptr) {
+                const unsigned char* skip = nullptr, std::vector<double>* refc = nullptr) {
   if (nsys < 1) throw Fail{FFTG_E_INVALID, "no Helmholtz field"};
   ensure_sys(H, nsys);
   alloc_helm(H, nsys);
   if (H->fp32())
     helmholtz_refined(H, alpha, reinterpret_cast<const float*>(ell2w), ell2_64, ell2_ref, abar,
-                      tol, maxit, nsys, out, skip);
+                      tol, maxit, nsys, out, skip, refc);
   else
-    helmholtz_pcg64(H, alpha, ell2_64, ell2_ref, abar, tol, maxit, nsys, out, skip);
+    helmholtz_pcg64(H, alpha, ell2_64, ell2_ref, abar, tol, maxit, nsys, out, skip, refc);
 }
 
 // ------------------------------------------------------------ mechanics
@@ -1421,9 +1504,8 @@ void destroy(fftg_handle* H) {
   }
   for (auto e : H->evpool) (void)hipEventDestroy(e);
   H->evpool.clear();
-  if (H->ggal.exec) (void)hipGraphExecDestroy(H->ggal.exec);
-  for (auto& sl : H->ghelm)
-    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+  H->ggal.drop();
+  for (auto& sl : H->ghelm) sl.drop();
   if (H->cap) (void)hipStreamDestroy(H->cap);
 }
 
@@ -1568,6 +1650,7 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
   bool converged = false;
   int k = 0;
   double err = 0.0;
+  std::vector<double> ell2_means;  // preconditioner lengths, fixed within the step
   for (k = 0; k < max_stagger_iters; ++k) {
     if (J > 0) fftg::launch_damage(t, N, J, phase, H->ab_k, s_hist, s_abar, H->Dj, H->st);
     HIPCHK(hipMemcpyAsync(H->eps_prev, H->eps_k, sizeof(double) * c * N,
@@ -1597,7 +1680,7 @@ StaggerOut stagger_core(fftg_handle* H, const unsigned char* phase, const MatTab
       // every field's Helmholtz solve (Algorithm 1 (ii)) at once, in lockstep
       HelmOut ho[FFTG_MAX_FIELDS];
       helm_solve(H, H->alph, ell2w_of(H, 0), ell2d_of(H, 0), -1.0, H->ab_k, pcg->tol,
-                 pcg->maxit, J, ho);
+                 pcg->maxit, J, ho, nullptr, &ell2_means);
       for (int j = 0; j < J; ++j) {
         if (ho[j].status == 3) throw Fail{FFTG_E_BREAKDOWN, "Helmholtz PCG breakdown"};
         if (ho[j].status == 4) throw Fail{FFTG_E_NONFINITE, "non-finite value in Helmholtz PCG"};
@@ -1955,6 +2038,7 @@ void stagger_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* ma
   const double* ell2_64 = H->fp32() ? B->ell2j64 : static_cast<const double*>(B->ell2j);
   std::vector<unsigned char> skip((size_t)n * Jm, 0);
   std::vector<HelmOut> ho((size_t)n * Jm);
+  std::vector<double> ell2_means;  // preconditioner lengths, fixed within the step
   std::vector<std::vector<double>> part(n);
   std::vector<int> nbe(n, 0);
   for (int k = 0; k < maxk; ++k) {
@@ -1988,7 +2072,7 @@ void stagger_batch(fftg_handle* H, std::vector<BSys>& S, const unsigned char* ma
       }
       // every field of every live RVE (Algorithm 1 (ii)) in one lockstep solve
       helm_solve(H, B->alph, B->ell2j, ell2_64, -1.0, B->ab_k, pcg->tol, pcg->maxit, n * J,
-                 ho.data(), skip.data());
+                 ho.data(), skip.data(), &ell2_means);
       for (auto& s : S) {
         if (!s.live) continue;
         for (int j = 0; j < J && s.live; ++j) {

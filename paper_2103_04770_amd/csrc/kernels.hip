@@ -389,6 +389,21 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Stacked systems that converge at different times: with one contiguous run
+// per XCD, the tiles of a converged system would leave the XCDs that hold
+// them idle while the others still work.  With chunk > 0 the XCDs take runs
+// of `chunk` tiles in turn (XCD x the runs x, x + 8, x + 16, ...), so the
+// tiles of every system spread over all eight XCDs, and neighbouring tiles
+// still share an XCD within a run.  A bijection of [0, nb): the tail past
+// the last whole round of 8 runs keeps its own order.
+__device__ __forceinline__ long long xcd_tile(long long b, long long nb, int chunk) {
+  if (chunk <= 0) return xcd_tile(b, nb);
+  const long long span = 8LL * chunk, whole = nb / span * span;
+  if (b >= whole) return b;
+  const long long x = b & 7, i = b >> 3;
+  return ((i / chunk) * 8 + x) * chunk + i % chunk;
+}
+
 // SH: tile budget code (chosen per handle by timing): FFTG_TILE_BYTES >> SH
 // for SH = 0, 1, 2, twice FFTG_TILE_BYTES for SH = 3 (gfx950 workgroups may
 // hold up to 160 KB of LDS).
@@ -397,17 +412,19 @@ constexpr int tile_budget() { return SH == 3 ? 2 * FFTG_TILE_BYTES : FFTG_TILE_B
 
 // ctl (optional): the control blocks of the systems the lines belong to,
 // lps lines each; a tile whose systems have all converged returns at once.
+// chunk: the XCD run length of xcd_tile (0: one contiguous run per XCD).
 template <typename T, bool FWD, int NF, int SH>
 FFTG_KERNEL_WIDE void k_strided(Plan plan, const cpx<T>* __restrict__ tw, cpx<T>* __restrict__ data,
                            long long nlines, long long inner, long long ostride, long long es,
-                           int TL_rt, const KrylovCtl* __restrict__ ctl, long long lps) {
+                           int TL_rt, const KrylovCtl* __restrict__ ctl, long long lps,
+                           int chunk) {
   constexpr bool FIX = NF > 0;
   constexpr int TB = tile_budget<SH>();
   __shared__ cpx<T> buf[FIX ? fs_tile<T, TB>(NF) * NF : LDS_ELEMS];
   constexpr int NT = FIX ? kStridedThreads : FFT_THREADS;
   const int n = FIX ? NF : plan.n;
   const int TL = FIX ? fs_tile<T, TB>(NF) : TL_rt;
-  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x, chunk);
   if (ctl) {
     const long long last = (tile + 1) * TL - 1 < nlines ? (tile + 1) * TL - 1 : nlines - 1;
     bool live = false;
@@ -715,11 +732,13 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
 // Forward: transforms w_0, w_1, w_2 and folds the x and y components,
 //   u = f_x c_y Y(w_0) + c_x f_y Y(w_1),  v = c_x c_y Y(w_2)  -> w_0, w_1,
 // which the outer forward pass (k_h_div_fwd<SPLIT>) finishes with c_z, f_z.
-// Stacked systems: lines (sys, z, kx) in order, gradient fields wstride apart.
+// Stacked systems: lines (sys, z, kx) in order, gradient fields wstride apart;
+// chunk as in k_strided.
 template <typename T, bool FWD, int NF>
 FFTG_KERNEL_WIDE void k_h_y_split(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
                                   cpx<T>* __restrict__ w, long long nlines, int TL_rt,
-                                  long long wstride, const KrylovCtl* __restrict__ ctl) {
+                                  long long wstride, const KrylovCtl* __restrict__ ctl,
+                                  int chunk) {
   constexpr bool FIX = NF > 0;
   __shared__ cpx<T> buf[FIX ? 3 * fs_tile_wide<T>(NF, 3) * NF : LDS_ELEMS];
   const int n = FIX ? NF : plan.n;
@@ -727,7 +746,7 @@ FFTG_KERNEL_WIDE void k_h_y_split(Plan plan, const cpx<T>* __restrict__ tw, Geo 
   const int TL = FIX ? fs_tile_wide<T>(NF, 3) : TL_rt;
   const int ld = 3 * TL;
   const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
-  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x, chunk);
   if (ctl) {
     // skip a tile whose systems have all converged
     const long long lpsys = (long long)g.n3 * g.n1h;
@@ -2410,6 +2429,16 @@ static inline int tile_lines(int n, int ncomp) {
     }                               \
   }
 
+// XCD run length for lines of several stacked systems, lps lines each, in
+// tiles of TL lines: runs of up to 16 tiles, at least 8 runs per system, so
+// that every system keeps all eight XCDs busy when others have converged; 0
+// (one contiguous run per XCD) for a single system.
+static inline int xcd_chunk(long long nlines, long long lps, int TL) {
+  if (lps >= nlines) return 0;
+  const long long per = lps / TL / 8;
+  return (int)(per < 1 ? 1 : per > 16 ? 16 : per);
+}
+
 template <typename T>
 void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nlines,
                     long long inner, long long ostride, long long es, bool fwd,
@@ -2419,12 +2448,13 @@ void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nli
     const int TL = NF ? fs_tile<T, tile_budget<SH>()>(NF) : tile_lines(p.n, 1);
     const int NT = NF ? kStridedThreads : FFT_THREADS;
     const long long nb = (nlines + TL - 1) / TL;
+    const int chunk = xcd_chunk(nlines, lps, TL);
     if (fwd)
       hipLaunchKernelGGL((k_strided<T, true, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw,
-                         data, nlines, inner, ostride, es, TL, ctl, lps);
+                         data, nlines, inner, ostride, es, TL, ctl, lps, chunk);
     else
       hipLaunchKernelGGL((k_strided<T, false, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p,
-                         tw, data, nlines, inner, ostride, es, TL, ctl, lps);
+                         tw, data, nlines, inner, ostride, es, TL, ctl, lps, chunk);
   }))
 }
 
@@ -2630,14 +2660,15 @@ void launch_h_y_split(const Plan& p, const cpx<T>* tw, const Geo& g, const Sym<T
   FFTG_DISPATCH_N(p.n, {
     const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
     const long long nb = (nl + TL - 1) / TL;
+    const int chunk = xcd_chunk(nl, (long long)g.n3 * g.n1h, TL);
     if (fwd)
       hipLaunchKernelGGL((k_h_y_split<T, true, NF>), dim3((unsigned)nb),
                          dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, w, nl, TL,
-                         ws, ctl);
+                         ws, ctl, chunk);
     else
       hipLaunchKernelGGL((k_h_y_split<T, false, NF>), dim3((unsigned)nb),
                          dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, w, nl, TL,
-                         ws, ctl);
+                         ws, ctl, chunk);
   })
 }
 
