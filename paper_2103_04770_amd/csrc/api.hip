@@ -711,7 +711,10 @@ int predict_left(int nsys, const KrylovCtl* k, const KrylovCtl* prev) {
 // Graph launches of a lockstep Krylov solve until every system is done:
 // `full` (kGraphIters iterations) while the stop test is further away than
 // that, else as many launches of `tail` (kTailIters) as predict_left asks
-// for; the control blocks are read after each round.
+// for; the control blocks are read after each round.  A round far from the
+// stop test queues several full graphs (half the predicted iterations, as
+// convergence may speed up), so that the GPU does not wait on the host's
+// read between them.
 void run_krylov_graphs(fftg_handle* H, int nsys, KrylovCtl* k, hipGraphExec_t full,
                        hipGraphExec_t tail) {
   std::vector<KrylovCtl> prev(k, k + nsys);
@@ -722,7 +725,8 @@ void run_krylov_graphs(fftg_handle* H, int nsys, KrylovCtl* k, hipGraphExec_t fu
     const int left = predict_left(nsys, k, prev.data());
     prev.assign(k, k + nsys);
     if (left < 0 || left > kGraphIters - kTailIters) {
-      HIPCHK(hipGraphLaunch(full, H->st));
+      const int nfull = std::max(1, std::min(8, left / (2 * kGraphIters)));
+      for (int i = 0; i < nfull; ++i) HIPCHK(hipGraphLaunch(full, H->st));
     } else {
       for (int i = 0; i < (left + kTailIters - 1) / kTailIters; ++i)
         HIPCHK(hipGraphLaunch(tail, H->st));
