@@ -58,7 +58,9 @@ def kernel_bytes(name, n, c, nd, J, fp32):
         "galerkin_y_inv": 2 * c * Ns * zc,
         "galerkin_y_fwd": 2 * c * Ns * zc,
         "galerkin_outer_dir_inv": 6 * c * Ns * zc,
-        "galerkin_outer_dot_fwd": 3 * c * Ns * zc,
+        # p.Ap is summed in real space by the x pass: the forward pass reads
+        # only the transform's input
+        "galerkin_outer_dot_fwd": 2 * c * Ns * zc,
         "galerkin_resid": 3 * c * Ns * zc,
         # the staggered step reads ell^2 through the 1-byte phase index
         "helmholtz_x_fused": 2 * nd * Ns * zc + N,

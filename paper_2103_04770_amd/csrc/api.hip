@@ -181,6 +181,10 @@ struct fftg_handle {
   // kernels per iteration (FFTG_GAL_FOLD=1 at creation).  Off by default: the
   // redundant per-workgroup reductions cost about what the two launches do.
   bool fold = false;
+  // Galerkin CG p.Ap summed in real space by the fused x pass (so that the
+  // forward outer pass does not read p) instead of on the half spectrum by
+  // the forward outer pass (FFTG_GAL_XDOT=0 at creation)
+  bool xdot = true;
   bool fp32() const { return prec == FFTG_FP32_REFINED; }
   size_t wsz() const { return fp32() ? sizeof(float) : sizeof(double); }
 };
@@ -615,7 +619,8 @@ void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1, int 
   const int oa = outer_axis(H);
   const T scl = T(1.0 / (double)g.N);
   const long long lps = (long long)c * g.n3 * g.n1h;  // y lines per system
-  const int nbd = fftg::gal_dot_count<T>(H->plan[oa], g, c, zo);
+  const bool xdot = H->xdot;
+  const int nbd = xdot ? fftg::gal_xdot_count<T>(g, c) : fftg::gal_dot_count<T>(H->plan[oa], g, c, zo);
   const int nbr = fftg::gal_resid_count(g);
   double* dpart = H->partials;                             // p.Ap, [sys][nbd]
   double* rpart = H->partials + (long long)nsys * nbd;     // r.r, [sys][nbr]
@@ -629,15 +634,18 @@ void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1, int 
   inner_inv<T>(H, c * nsys, C<T>(H->kw), H->ctl, K_GAL_YI, lps);
   {
     KT t(H, K_GAL_X);
-    fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
-                                   reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st, nsys);
+    const int nb = fftg::launch_x_fused_gal<T, T>(
+        H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw), reinterpret_cast<const T*>(H->tan), scl,
+        H->ctl, H->st, nsys, xdot ? dpart : nullptr);
+    if (xdot && nb != nbd) throw Fail{FFTG_E_HIP, "Galerkin x pass: partial count mismatch"};
   }
   inner_fwd<T>(H, c * nsys, C<T>(H->kw), H->ctl, K_GAL_YF, lps);
   {
     KT t(H, K_GAL_OF);
-    const int nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
-                                               C<T>(H->kw), dpart, H->ctl, H->st, nsys);
-    if (nb != nbd) throw Fail{FFTG_E_HIP, "Galerkin forward pass: partial count mismatch"};
+    const int nb = fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo,
+                                               xdot ? nullptr : C<T>(H->kp), C<T>(H->kw),
+                                               xdot ? nullptr : dpart, H->ctl, H->st, nsys);
+    if (!xdot && nb != nbd) throw Fail{FFTG_E_HIP, "Galerkin forward pass: partial count mismatch"};
   }
   if (!fold) {
     KT t(H, K_SMALL);
@@ -743,6 +751,7 @@ fftg_handle::GraphSlot& gal_graphs(fftg_handle* H, const unsigned char* mask, in
   for (int i = 0; i < 6; ++i) key |= (unsigned long long)(mask[i] & 1) << (8 + i);
   key |= (unsigned long long)nsys << 16;
   key |= H->fold ? 4ull : 0ull;
+  key |= H->xdot ? 8ull : 0ull;
   auto& sl = H->ggal;
   if (sl.exec[0] && sl.key == key) return sl;
   sl.drop();
@@ -2477,6 +2486,11 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
       maxb = std::max(maxb, 2 * (nl + 1));
       maxb = std::max(maxb, g.Ns / std::max(1, ns[a]) + 1);
     }
+    // the Galerkin x pass's p.Ap partials and the residual pass's r.r
+    maxb = std::max(maxb, (long long)fftg::gal_xdot_count<double>(g, H->c) +
+                              fftg::gal_resid_count(g));
+    maxb = std::max(maxb, (long long)fftg::gal_xdot_count<float>(g, H->c) +
+                              fftg::gal_resid_count(g));
     H->psys = maxb;
     // up to FFTG_MAX_FIELDS lockstep systems (the Helmholtz solves of the
     // non-local fields) without growing
@@ -2499,6 +2513,7 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
     return FFTG_OK;
   });
   if (const char* f = std::getenv("FFTG_GAL_FOLD")) H->fold = f[0] == '1' && f[1] == '\0';
+  if (const char* f = std::getenv("FFTG_GAL_XDOT")) H->xdot = !(f[0] == '0' && f[1] == '\0');
   if (rc == FFTG_OK) tune_tiles(H);
   if (rc != FFTG_OK) {
     g_create_error = H->err;
@@ -2596,7 +2611,8 @@ fftg_status fftg_time_kernel(fftg_handle* H, int kid, int reps, double* avg_ms) 
       switch (kid) {
         case K_GAL_X:
           fftg::launch_x_fused_gal<T, T>(H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw),
-                                         reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st);
+                                         reinterpret_cast<const T*>(H->tan), scl, H->ctl, H->st,
+                                         1, H->xdot ? H->partials : nullptr);
           break;
         case K_GAL_YI:
           inner_inv<T>(H, c, C<T>(H->kw), H->ctl, K_GAL_YI);
@@ -2609,8 +2625,9 @@ fftg_status fftg_time_kernel(fftg_handle* H, int kid, int reps, double* avg_ms) 
                                       C<T>(H->kp), C<T>(H->kx), C<T>(H->kw), H->ctl, H->st, H->tsh_o);
           break;
         case K_GAL_OF:
-          fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kp),
-                                      C<T>(H->kw), H->partials, H->ctl, H->st);
+          fftg::launch_gal_dot_fwd<T>(H->plan[oa], TW<T>(H, oa), g, c, zo,
+                                      H->xdot ? nullptr : C<T>(H->kp), C<T>(H->kw),
+                                      H->xdot ? nullptr : H->partials, H->ctl, H->st);
           break;
         case K_GAL_RES:
           fftg::launch_gal_resid<T>(g, c, SY<T>(H), H->mask_last, C<T>(H->kr), C<T>(H->kw),

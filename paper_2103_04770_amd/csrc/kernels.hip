@@ -202,10 +202,19 @@ FFTG_KERNEL void k_x_c2r(Plan plan, const cpx<T>* __restrict__ tw, const cpx<T>*
 //
 // Stacked systems: spectra [sys][comp][Ns], tangent [sys][N][8]; a workgroup
 // holds lines of one system only (system blockIdx.x / bps).
+//
+// partials (optional): the CG's p . A p, summed in real space.  The forward
+// pass of the CG takes p in the range of the projection G* (an orthogonal
+// projection, frequency by frequency), so p . G*(F(K:eps_p)) = p . F(K:eps_p),
+// and by Parseval's identity that is the sum over voxels of eps_p : K : eps_p
+// (the inverse transform here carries no 1/N, `scl` does): each workgroup
+// writes the sum over its voxels to partials[blockIdx.x], [sys][bps].  The
+// forward pass then need not read p.
 template <typename T, typename TT, int NF, int C>
 FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, int NL_rt,
                                cpx<T>* __restrict__ w_all, const TT* __restrict__ tan_all, T scl,
-                               const KrylovCtl* __restrict__ ctl) {
+                               const KrylovCtl* __restrict__ ctl,
+                               double* __restrict__ partials) {
   constexpr bool FIX = NF > 0;
   constexpr int NT = FIX ? kFusedThreads : FFT_THREADS;
   // fixed-length path: padded line pitch (conflict-free Stockham stages)
@@ -237,6 +246,7 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
   else
     lds_fft<T, false, false>(buf, plan, P, n1, tw);
   T* fb = reinterpret_cast<T*>(buf);
+  double dot = 0.0;
   for (int e = threadIdx.x; e < NL * n1; e += NT) {
     const int l = e / n1, x = e % n1;
     const long long line = line0 + l;
@@ -274,7 +284,11 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
       out[2] = b * ev[2] - md * m[5];
     }
 #pragma unroll
-    for (int q = 0; q < C; ++q) fb[slot[q]] = out[q] * scl;
+    for (int q = 0; q < C; ++q) {
+      const T o = out[q] * scl;
+      fb[slot[q]] = o;
+      dot += (double)ev[q] * (double)o;
+    }
   }
   __syncthreads();
   if constexpr (FIX)
@@ -290,6 +304,13 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
     unpack_forward<FIX>(buf, p, k, n1, ld, A, B);
     if (la < nlines) w[(sa / NL) * g.Ns + la * n1h + k] = A;
     if (lb < nlines) w[(sb / NL) * g.Ns + lb * n1h + k] = B;
+  }
+  if (partials) {
+    // the tile is free once every wave is past the loop above (block_sum
+    // starts with a barrier)
+    static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
+    const double s = block_sum<NT>(dot, reinterpret_cast<double*>(buf));
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
   }
 }
 
@@ -606,8 +627,10 @@ FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
     if (lb >= 0) {
       const long long gi = lb + t * es;
       w[gi] = v;
-      const cpx<T> pv = pp[gi];
-      acc += wt * ((double)pv.x * (double)v.x + (double)pv.y * (double)v.y);
+      if (pp) {
+        const cpx<T> pv = pp[gi];
+        acc += wt * ((double)pv.x * (double)v.x + (double)pv.y * (double)v.y);
+      }
     }
   };
   if constexpr (FIX) {
@@ -620,8 +643,10 @@ FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
     lds_fft<T, true, true>(buf, plan, TL, TL, tw);
     for (int t = t0; t < n; t += dt) st(t, buf[t * TL + l]);
   }
-  const double s = block_sum<NT>(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (pp) {
+    const double s = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
 }
 
 // Outer-axis inverse pass of the Helmholtz PCG (single scalar spectrum):
@@ -2535,25 +2560,40 @@ static inline int fused_lines_rt(int n1, int c) {
   return NL;
 }
 
-template <typename T, typename TT>
-void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
-                        const TT* tan, T scl, const KrylovCtl* ctl, hipStream_t st, int nsys) {
+template <typename T>
+int gal_xdot_count(const Geo& g, int c) {
   const long long nlines = (long long)g.n2 * g.n3;
+  int cnt = 0;
+  FFTG_DISPATCH_N(g.n1, {
+    const int NL = c == 6 ? (NF ? fx_fused_lines<T>(NF, 6) : fused_lines_rt(g.n1, 6))
+                          : (NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3));
+    cnt = (int)((nlines + NL - 1) / NL);
+  })
+  return cnt;
+}
+
+template <typename T, typename TT>
+int launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
+                       const TT* tan, T scl, const KrylovCtl* ctl, hipStream_t st, int nsys,
+                       double* partials) {
+  const long long nlines = (long long)g.n2 * g.n3;
+  long long bps = 0;
   FFTG_DISPATCH_N(g.n1, {
     if (c == 6) {
       const int NL = NF ? fx_fused_lines<T>(NF, 6) : fused_lines_rt(g.n1, 6);
-      const long long nb = (nlines + NL - 1) / NL * nsys;
-      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 6>), dim3((unsigned)nb),
+      bps = (nlines + NL - 1) / NL;
+      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 6>), dim3((unsigned)(bps * nsys)),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
-                         st, p, tw, g, NL, w, tan, scl, ctl);
+                         st, p, tw, g, NL, w, tan, scl, ctl, partials);
     } else {
       const int NL = NF ? fx_fused_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
-      const long long nb = (nlines + NL - 1) / NL * nsys;
-      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 3>), dim3((unsigned)nb),
+      bps = (nlines + NL - 1) / NL;
+      hipLaunchKernelGGL((k_x_fused_gal<T, TT, NF, 3>), dim3((unsigned)(bps * nsys)),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
-                         st, p, tw, g, NL, w, tan, scl, ctl);
+                         st, p, tw, g, NL, w, tan, scl, ctl, partials);
     }
   })
+  return (int)bps;  // partials per system
 }
 
 template <typename T, typename TL>
@@ -2963,8 +3003,10 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, i
                                  hipStream_t, int);                                              \
   template void launch_hermitize<T>(const Geo&, int, cpx<T>*, hipStream_t);                     \
   template int launch_wnorm2<T>(const Geo&, int, const cpx<T>*, double*, hipStream_t, int);     \
-  template void launch_x_fused_gal<T, T>(const Plan&, const cpx<T>*, const Geo&, int, cpx<T>*,   \
-                                         const T*, T, const KrylovCtl*, hipStream_t, int);       \
+  template int launch_x_fused_gal<T, T>(const Plan&, const cpx<T>*, const Geo&, int, cpx<T>*,    \
+                                        const T*, T, const KrylovCtl*, hipStream_t, int,         \
+                                        double*);                                                \
+  template int gal_xdot_count<T>(const Geo&, int);                                               \
   template void launch_x_fused_helm<T, T>(const Plan&, const cpx<T>*, const Geo&, cpx<T>*,       \
                                           const T*, T, const KrylovCtl*, hipStream_t, int,       \
                                           const unsigned char*, const T*);                       \

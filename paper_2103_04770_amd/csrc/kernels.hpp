@@ -99,10 +99,15 @@ template <typename T>
 int launch_gal_dot_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
                        const cpx<T>* pp, cpx<T>* w, double* partials, const KrylovCtl* ctl,
                        hipStream_t st, int nsys = 1);
+// partials (optional): the CG's p . A p summed in real space, [sys][count]
+// with count = gal_xdot_count (returned); the forward pass then takes pp =
+// nullptr and writes no partials.
 template <typename T, typename TT>
-void launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
-                        const TT* tan, T scale, const KrylovCtl* ctl, hipStream_t st,
-                        int nsys = 1);
+int launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx<T>* w,
+                       const TT* tan, T scale, const KrylovCtl* ctl, hipStream_t st,
+                       int nsys = 1, double* partials = nullptr);
+template <typename T>
+int gal_xdot_count(const Geo& g, int c);
 template <typename T>
 int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char* mask6,
                       cpx<T>* r, const cpx<T>* w, double* partials, KrylovCtl* ctl,
