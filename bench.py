@@ -42,7 +42,8 @@ def log(*a):
 
 
 KERNEL_CLASSES = ["galerkin_x_fused", "galerkin_y_inv", "galerkin_y_fwd", "galerkin_outer_dir_inv",
-                  "galerkin_outer_dot_fwd", "galerkin_resid", "helmholtz_x_fused",
+                  "galerkin_outer_fwd_resid", "galerkin_outer_dot_fwd", "galerkin_resid",
+                  "helmholtz_x_fused",
                   "helmholtz_outer_dir_inv", "helmholtz_outer_div_fwd", "helmholtz_resid"]
 
 
@@ -62,6 +63,9 @@ def kernel_bytes(name, n, c, nd, J, fp32):
         # only the transform's input
         "galerkin_outer_dot_fwd": 2 * c * Ns * zc,
         "galerkin_resid": 3 * c * Ns * zc,
+        # the forward pass fused with the residual update: reads w and r,
+        # writes r (the transform itself is not stored)
+        "galerkin_outer_fwd_resid": 3 * c * Ns * zc,
         # the staggered step reads ell^2 through the 1-byte phase index
         "helmholtz_x_fused": 2 * nd * Ns * zc + N,
         # 3D: the outer passes transform two fields; the y passes map two

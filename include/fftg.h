@@ -499,7 +499,7 @@ fftg_status fftg_apply_helmholtz(fftg_handle* h, const double* ell2, const doubl
 
 /* ---- kernel timing ---- */
 
-#define FFTG_NKERNELS 16
+#define FFTG_NKERNELS 17
 /* Per-kernel-class GPU time, measured with HIP events recorded on the
  * handle's stream around every launch while profiling is on.  Returns (when
  * non-NULL) the milliseconds and launch counts accumulated since profiling was

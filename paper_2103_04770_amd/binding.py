@@ -11,6 +11,9 @@ import os
 
 import numpy as np
 
+# kernel classes of fftg_profile / fftg_kernel_name (FFTG_NKERNELS)
+NKERNELS = 17
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
@@ -533,7 +536,7 @@ class Solver:
     def profile(self, enable):
         """Per-kernel-class GPU time (HIP events on the handle's stream).
         Returns (ms, launches) accumulated since profiling was last enabled."""
-        n = 16
+        n = NKERNELS
         ms = (ct.c_double * n)()
         cnt = (ct.c_longlong * n)()
         self._check(self.lib.fftg_profile(self.h, int(bool(enable)), ms, cnt))
@@ -547,7 +550,7 @@ class Solver:
         return ms.value
 
     def kernel_names(self):
-        return [self.lib.fftg_kernel_name(i).decode() for i in range(16)]
+        return [self.lib.fftg_kernel_name(i).decode() for i in range(NKERNELS)]
 
     # ---------------------------------------------------------------- helpers
     def state_layout(self, nfields):

@@ -185,6 +185,10 @@ struct fftg_handle {
   // forward outer pass does not read p) instead of on the half spectrum by
   // the forward outer pass (FFTG_GAL_XDOT=0 at creation)
   bool xdot = true;
+  // with xdot (and without fold): the forward outer pass and the residual
+  // update as one pass that does not store the transform (FFTG_GAL_FUSE=0 at
+  // creation: two passes)
+  bool fuse_res = true;
   bool fp32() const { return prec == FFTG_FP32_REFINED; }
   size_t wsz() const { return fp32() ? sizeof(float) : sizeof(double); }
 };
@@ -287,7 +291,7 @@ void dfree(void*& p) {
 enum Kid {
   K_GAL_X = 0, K_GAL_YI, K_GAL_YF, K_GAL_OI, K_GAL_OF, K_GAL_RES,
   K_HLM_X, K_HLM_YI, K_HLM_YF, K_HLM_OI, K_HLM_OF, K_HLM_RES,
-  K_CONST, K_TR_X, K_TR_YZ, K_SMALL
+  K_CONST, K_TR_X, K_TR_YZ, K_SMALL, K_GAL_OFR
 };
 const char* const kKernelNames[FFTG_NKERNELS] = {
     "galerkin_x_fused",       "galerkin_y_inv",       "galerkin_y_fwd",
@@ -295,7 +299,7 @@ const char* const kKernelNames[FFTG_NKERNELS] = {
     "helmholtz_x_fused",      "helmholtz_y_inv",      "helmholtz_y_fwd",
     "helmholtz_outer_dir_inv", "helmholtz_outer_div_fwd", "helmholtz_resid",
     "constitutive",           "transform_x",          "transform_yz",
-    "small"};
+    "small",                  "galerkin_outer_fwd_resid"};
 
 // Waits for the stream, then books the timed launches; launches of Krylov
 // chunk iterations at index >= keep (run past convergence, so they returned
@@ -620,11 +624,13 @@ void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1, int 
   const T scl = T(1.0 / (double)g.N);
   const long long lps = (long long)c * g.n3 * g.n1h;  // y lines per system
   const bool xdot = H->xdot;
+  const bool fold = H->fold;
+  const bool fused = xdot && !fold && H->fuse_res;
   const int nbd = xdot ? fftg::gal_xdot_count<T>(g, c) : fftg::gal_dot_count<T>(H->plan[oa], g, c, zo);
-  const int nbr = fftg::gal_resid_count(g);
+  const int nbr = fused ? fftg::gal_fwd_resid_count<T>(H->plan[oa], g, c, zo)
+                        : fftg::gal_resid_count(g);
   double* dpart = H->partials;                             // p.Ap, [sys][nbd]
   double* rpart = H->partials + (long long)nsys * nbd;     // r.r, [sys][nbr]
-  const bool fold = H->fold;
   {
     KT t(H, K_GAL_OI);
     fftg::launch_gal_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, C<T>(H->kr), C<T>(H->kp),
@@ -638,6 +644,26 @@ void gal_iteration(fftg_handle* H, const unsigned char* mask, int nsys = 1, int 
         H->plan[0], TW<T>(H, 0), g, c, C<T>(H->kw), reinterpret_cast<const T*>(H->tan), scl,
         H->ctl, H->st, nsys, xdot ? dpart : nullptr);
     if (xdot && nb != nbd) throw Fail{FFTG_E_HIP, "Galerkin x pass: partial count mismatch"};
+  }
+  if (fused) {
+    // alpha from the x pass's p.Ap, then one forward pass that updates r
+    {
+      KT t(H, K_SMALL);
+      fftg::launch_fin_alpha(dpart, nbd, H->ctl, H->st, nsys);
+    }
+    inner_fwd<T>(H, c * nsys, C<T>(H->kw), H->ctl, K_GAL_YF, lps);
+    {
+      KT t(H, K_GAL_OFR);
+      const int nb = fftg::launch_gal_fwd_resid<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, SY<T>(H),
+                                                   mask, C<T>(H->kw), C<T>(H->kr), rpart, H->ctl,
+                                                   H->st, nsys);
+      if (nb != nbr) throw Fail{FFTG_E_HIP, "Galerkin forward pass: partial count mismatch"};
+    }
+    {
+      KT t(H, K_SMALL);
+      fftg::launch_fin_beta(rpart, nbr, 1, H->ctl, H->st, nsys);
+    }
+    return;
   }
   inner_fwd<T>(H, c * nsys, C<T>(H->kw), H->ctl, K_GAL_YF, lps);
   {
@@ -752,6 +778,7 @@ fftg_handle::GraphSlot& gal_graphs(fftg_handle* H, const unsigned char* mask, in
   key |= (unsigned long long)nsys << 16;
   key |= H->fold ? 4ull : 0ull;
   key |= H->xdot ? 8ull : 0ull;
+  key |= H->fuse_res ? 16ull : 0ull;
   auto& sl = H->ggal;
   if (sl.exec[0] && sl.key == key) return sl;
   sl.drop();
@@ -2491,6 +2518,13 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
                               fftg::gal_resid_count(g));
     maxb = std::max(maxb, (long long)fftg::gal_xdot_count<float>(g, H->c) +
                               fftg::gal_resid_count(g));
+    for (int a = 1; a < 3; ++a) {
+      if (a >= g.ndim) break;
+      maxb = std::max(maxb, (long long)fftg::gal_xdot_count<double>(g, H->c) +
+                                fftg::gal_fwd_resid_count<double>(H->plan[a], g, H->c, g.ndim == 3));
+      maxb = std::max(maxb, (long long)fftg::gal_xdot_count<float>(g, H->c) +
+                                fftg::gal_fwd_resid_count<float>(H->plan[a], g, H->c, g.ndim == 3));
+    }
     H->psys = maxb;
     // up to FFTG_MAX_FIELDS lockstep systems (the Helmholtz solves of the
     // non-local fields) without growing
@@ -2514,6 +2548,7 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
   });
   if (const char* f = std::getenv("FFTG_GAL_FOLD")) H->fold = f[0] == '1' && f[1] == '\0';
   if (const char* f = std::getenv("FFTG_GAL_XDOT")) H->xdot = !(f[0] == '0' && f[1] == '\0');
+  if (const char* f = std::getenv("FFTG_GAL_FUSE")) H->fuse_res = !(f[0] == '0' && f[1] == '\0');
   if (rc == FFTG_OK) tune_tiles(H);
   if (rc != FFTG_OK) {
     g_create_error = H->err;
@@ -2632,6 +2667,11 @@ fftg_status fftg_time_kernel(fftg_handle* H, int kid, int reps, double* avg_ms) 
         case K_GAL_RES:
           fftg::launch_gal_resid<T>(g, c, SY<T>(H), H->mask_last, C<T>(H->kr), C<T>(H->kw),
                                     H->partials, H->ctl, H->st);
+          break;
+        case K_GAL_OFR:
+          fftg::launch_gal_fwd_resid<T>(H->plan[oa], TW<T>(H, oa), g, c, zo, SY<T>(H),
+                                        H->mask_last, C<T>(H->kw), C<T>(H->kr), H->partials,
+                                        H->ctl, H->st);
           break;
         case K_HLM_X:
           fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw),

@@ -479,6 +479,17 @@ constexpr int fs_tile(int n) {                                          // y / z
 }
 template <typename T>
 constexpr int fs_tile_wide(int n, int nc) { return pow2_floor(kElemsWide<T> / (n * nc)); }
+// Galerkin forward pass fused with the residual update: every component of
+// a tile's lines in LDS at once
+#ifndef FFTG_FWDRES_BYTES
+#define FFTG_FWDRES_BYTES 49152
+#endif
+template <typename T>
+constexpr int fr_tile(int n, int nc) {
+  return pow2_floor(FFTG_FWDRES_BYTES / (int)sizeof(cpx<T>) / (n * nc)) < 1
+             ? 1
+             : pow2_floor(FFTG_FWDRES_BYTES / (int)sizeof(cpx<T>) / (n * nc));
+}
 
 // Deterministic workgroup sum (fixed tree over NT lanes); the result is valid
 // in thread 0.  `red` must hold NT doubles of LDS.

@@ -986,6 +986,80 @@ FFTG_KERNEL void k_gal_resid(Geo g, Sym<T> sym, unsigned char mk0, unsigned char
   if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
+// Outer-axis forward pass of the Galerkin CG fused with the residual update,
+// for the iteration whose p.Ap the x pass summed (alpha is in the control
+// block): the C components of TL lines are transformed together in LDS, so
+// that every frequency has all of them for the projection G* (its zero
+// frequency: the mixed-control mask), and
+//   r <- r - alpha G*(Z(w)),  partial sums of weighted |r|^2,
+// without storing the transform.  Lines are (ky, kx) in 3D (z outer) and kx
+// in 2D (y outer), inner per component.  Stacked systems: spectra
+// [sys][comp][Ns], tpo tiles per system, partials [sys][tpo]; tiles are
+// taken through xcd_tile (chunk).
+template <typename T, int NF, int C>
+FFTG_KERNEL_WIDE void k_gal_fwd_resid(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
+                                      Sym<T> sym, unsigned mbits, const cpx<T>* __restrict__ w_all,
+                                      cpx<T>* __restrict__ r_all, long long inner, long long es,
+                                      int TL_rt, int tpo, int chunk,
+                                      double* __restrict__ partials,
+                                      const KrylovCtl* __restrict__ ctl_all) {
+  constexpr bool FIX = NF > 0;
+  constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
+  constexpr int TLF = FIX ? fr_tile<T>(NF, C) : 1;
+  __shared__ cpx<T> buf[FIX ? C * TLF * NF : LDS_ELEMS];
+  static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x, chunk);
+  const long long sys = tile / tpo;
+  const KrylovCtl* ctl = ctl_all + sys;
+  if (ctl->done) return;
+  const int n = FIX ? NF : plan.n;
+  const int TL = FIX ? TLF : TL_rt;
+  const int ld = C * TL;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
+  const long long L = (tile % tpo) * TL + l;  // line of a component slab
+  const bool live = L < inner;
+  const cpx<T>* __restrict__ w = w_all + sys * C * g.Ns;
+  cpx<T>* __restrict__ r = r_all + sys * C * g.Ns;
+  for (int t = t0; t < n; t += dt)
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      buf[t * ld + j * TL + l] = live ? w[j * g.Ns + L + t * es] : mk(T(0), T(0));
+  __syncthreads();
+  if constexpr (FIX)
+    lds_fft_c<T, true, true, NF, C * TLF, C * TLF, NT>(buf, tw);
+  else
+    lds_fft<T, true, true>(buf, plan, ld, ld, tw);
+  const T alpha = (T)ctl->alpha;
+  const bool zouter = g.ndim == 3;
+  const int kx = live ? (int)(L % g.n1h) : 0, lky = live ? (int)(L / g.n1h) : 0;
+  const double wt = live ? hweight(kx, g.n1h) : 0.0;
+  double acc = 0.0;
+  if (live)
+    for (int t = t0; t < n; t += dt) {
+      const long long gi = L + t * es;
+      cpx<T> v[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) v[j] = buf[t * ld + j * TL + l];
+      if (gi == 0) {
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+          if (!((mbits >> j) & 1u)) v[j] = mk(T(0), T(0));
+      } else {
+        T q[3];
+        qvec(sym, false, kx, zouter ? lky : t, zouter ? t : 0, q);
+        project_point<T, C>(q, v);
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const cpx<T> rn = r[j * g.Ns + gi] - scale(v[j], alpha);
+        r[j * g.Ns + gi] = rn;
+        acc += wt * ((double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y);
+      }
+    }
+  const double s = block_sum<NT>(acc, reinterpret_cast<double*>(buf));
+  if (threadIdx.x == 0) partials[tile] = s;
+}
+
 // Newton right-hand side b = -G*(sigma - Sbar) from the FP64 stress spectrum;
 // partials: [0] weighted |b|^2, [1] weighted |sigma_hat|^2.
 // Stacked systems: blockIdx.y is the system; Sb_sys (when given) holds the
@@ -2634,6 +2708,51 @@ int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char
 }
 
 template <typename T>
+int launch_gal_fwd_resid(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
+                         const Sym<T>& sym, const unsigned char* m, const cpx<T>* w, cpx<T>* r,
+                         double* partials, const KrylovCtl* ctl, hipStream_t st, int nsys) {
+  long long nl, inner, os, es;
+  outer_lines(g, 1, zouter, nl, inner, os, es);
+  unsigned mb = 0;
+  for (int i = 0; i < 6; ++i)
+    if (m[i]) mb |= 1u << i;
+  int tpo = 0;
+  FFTG_DISPATCH_N(p.n, {
+    if (c == 6) {
+      const int TL = NF ? fr_tile<T>(NF, 6) : tile_lines(p.n, 6);
+      tpo = tiles_per_sys(inner, TL);
+      const long long nb = (long long)tpo * nsys;
+      const int chunk = xcd_chunk(nb * TL, (long long)tpo * TL, TL);
+      hipLaunchKernelGGL((k_gal_fwd_resid<T, NF, 6>), dim3((unsigned)nb),
+                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, mb, w, r,
+                         inner, es, TL, tpo, chunk, partials, ctl);
+    } else {
+      const int TL = NF ? fr_tile<T>(NF, 3) : tile_lines(p.n, 3);
+      tpo = tiles_per_sys(inner, TL);
+      const long long nb = (long long)tpo * nsys;
+      const int chunk = xcd_chunk(nb * TL, (long long)tpo * TL, TL);
+      hipLaunchKernelGGL((k_gal_fwd_resid<T, NF, 3>), dim3((unsigned)nb),
+                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, mb, w, r,
+                         inner, es, TL, tpo, chunk, partials, ctl);
+    }
+  })
+  return tpo;  // partials per system
+}
+
+template <typename T>
+int gal_fwd_resid_count(const Plan& p, const Geo& g, int c, bool zouter) {
+  long long nl, inner, os, es;
+  outer_lines(g, 1, zouter, nl, inner, os, es);
+  int cnt = 0;
+  FFTG_DISPATCH_N(p.n, {
+    const int TL = c == 6 ? (NF ? fr_tile<T>(NF, 6) : tile_lines(p.n, 6))
+                          : (NF ? fr_tile<T>(NF, 3) : tile_lines(p.n, 3));
+    cnt = tiles_per_sys(inner, TL);
+  })
+  return cnt;
+}
+
+template <typename T>
 int launch_gal_rhs(const Geo& g, int c, const Sym<double>& sym, const unsigned char* m,
                    const double* S, const cpx<double>* sh, cpx<T>* r, double* partials,
                    hipStream_t st, int nsys, const double* S_sys) {
@@ -3007,6 +3126,10 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, i
                                         const T*, T, const KrylovCtl*, hipStream_t, int,         \
                                         double*);                                                \
   template int gal_xdot_count<T>(const Geo&, int);                                               \
+  template int launch_gal_fwd_resid<T>(const Plan&, const cpx<T>*, const Geo&, int, bool,       \
+                                       const Sym<T>&, const unsigned char*, const cpx<T>*,       \
+                                       cpx<T>*, double*, const KrylovCtl*, hipStream_t, int);    \
+  template int gal_fwd_resid_count<T>(const Plan&, const Geo&, int, bool);                     \
   template void launch_x_fused_helm<T, T>(const Plan&, const cpx<T>*, const Geo&, cpx<T>*,       \
                                           const T*, T, const KrylovCtl*, hipStream_t, int,       \
                                           const unsigned char*, const T*);                       \

@@ -108,6 +108,16 @@ int launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx
                        int nsys = 1, double* partials = nullptr);
 template <typename T>
 int gal_xdot_count(const Geo& g, int c);
+// Forward outer pass fused with the residual update r <- r - alpha G*(Z(w))
+// (alpha in the control blocks), partial sums of weighted |r|^2 [sys][count]
+// with count = gal_fwd_resid_count (returned).
+template <typename T>
+int launch_gal_fwd_resid(const Plan& p, const cpx<T>* tw, const Geo& g, int c, bool zouter,
+                         const Sym<T>& sym, const unsigned char* mask6, const cpx<T>* w,
+                         cpx<T>* r, double* partials, const KrylovCtl* ctl, hipStream_t st,
+                         int nsys = 1);
+template <typename T>
+int gal_fwd_resid_count(const Plan& p, const Geo& g, int c, bool zouter);
 template <typename T>
 int launch_gal_resid(const Geo& g, int c, const Sym<T>& sym, const unsigned char* mask6,
                       cpx<T>* r, const cpx<T>* w, double* partials, KrylovCtl* ctl,

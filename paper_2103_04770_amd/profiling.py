@@ -31,6 +31,7 @@ CLASSES = {
     "k_gal_dir_inv": "galerkin_outer_dir_inv",
     "k_gal_dot_fwd": "galerkin_outer_dot_fwd",
     "k_gal_resid": "galerkin_resid",
+    "k_gal_fwd_resid": "galerkin_outer_fwd_resid",
     "k_x_fused_helm": "helmholtz_x_fused",
     "k_h_dir_inv": "helmholtz_outer_dir_inv",
     "k_h_div_fwd": "helmholtz_outer_div_fwd",
