@@ -722,33 +722,11 @@ hipGraphExec_t capture(fftg_handle* H, F body, int iters = kGraphIters) {
   return ex;
 }
 
-// Iterations the slowest live system of a lockstep Krylov solve still needs,
-// predicted from how fast its residual fell between two reads of the control
-// blocks (prev, then k); -1 when some live system has no such rate yet.
-// Only the launch pattern follows from it: iterations past a system's stop
-// test return at once whatever was predicted.
-int predict_left(int nsys, const KrylovCtl* k, const KrylovCtl* prev) {
-  int left = 0;
-  for (int q = 0; q < nsys; ++q) {
-    if (k[q].done) continue;
-    const int di = k[q].iters - prev[q].iters;
-    if (di <= 0 || !(k[q].rr > 0.0) || !(k[q].rr < prev[q].rr) || !(k[q].tol2 > 0.0)) return -1;
-    const double rate = std::log(k[q].rr / prev[q].rr) / di;  // < 0
-    const double need = std::log(k[q].tol2 / k[q].rr) / rate;
-    int n = need < 1.0 ? 1 : need > 1e6 ? 1000000 : (int)std::ceil(need);
-    n = std::min(n, std::max(1, k[q].maxit - k[q].iters));
-    left = std::max(left, n);
-  }
-  return left;
-}
-
-// Graph launches of a lockstep Krylov solve until every system is done:
-// `full` (kGraphIters iterations) while the stop test is further away than
-// that, else as many launches of `tail` (kTailIters) as predict_left asks
-// for; the control blocks are read after each round.  A round far from the
-// stop test queues several full graphs (half the predicted iterations, as
-// convergence may speed up), so that the GPU does not wait on the host's
-// read between them.
+// Graph launches of a lockstep Krylov solve until every system is done, in
+// rounds planned by fftg_host::plan_round from the predicted iterations
+// left (fftg_host::predict_left); the control blocks are read after each
+// round.  Several full graphs queued in one round keep the GPU from waiting
+// on the host's read between them.
 void run_krylov_graphs(fftg_handle* H, int nsys, KrylovCtl* k, hipGraphExec_t full,
                        hipGraphExec_t tail) {
   std::vector<KrylovCtl> prev(k, k + nsys);
@@ -756,15 +734,11 @@ void run_krylov_graphs(fftg_handle* H, int nsys, KrylovCtl* k, hipGraphExec_t fu
     bool all = true;
     for (int q = 0; q < nsys; ++q) all = all && k[q].done;
     if (all) return;
-    const int left = predict_left(nsys, k, prev.data());
+    const auto round = fftg_host::plan_round(fftg_host::predict_left(nsys, k, prev.data()),
+                                             kGraphIters, kTailIters);
     prev.assign(k, k + nsys);
-    if (left < 0 || left > kGraphIters - kTailIters) {
-      const int nfull = std::max(1, std::min(8, left / (2 * kGraphIters)));
-      for (int i = 0; i < nfull; ++i) HIPCHK(hipGraphLaunch(full, H->st));
-    } else {
-      for (int i = 0; i < (left + kTailIters - 1) / kTailIters; ++i)
-        HIPCHK(hipGraphLaunch(tail, H->st));
-    }
+    for (int i = 0; i < round.full; ++i) HIPCHK(hipGraphLaunch(full, H->st));
+    for (int i = 0; i < round.tail; ++i) HIPCHK(hipGraphLaunch(tail, H->st));
     read_ctls(H, nsys, k);
   }
 }

@@ -1,11 +1,12 @@
 // Host-only logic of the library that touches no GPU: argument validation
-// of the phase table, the adaptive driver's step control, and the grouping
-// of batch items into lockstep units.  Plain C++17 (no HIP), so that it also
+// of the phase table, the adaptive driver's step control, the grouping of
+// batch items into lockstep units, and the pacing of Krylov graph launches.  Plain C++17 (no HIP), so that it also
 // builds into a host test program under the address and undefined-behaviour
 // sanitizers.
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -146,6 +147,45 @@ inline std::vector<std::vector<int>> batch_units(const std::vector<ItemKey>& key
                      return work(a) > work(b);
                    });
   return split;
+}
+
+// Iterations the slowest live system of a lockstep Krylov solve still needs,
+// predicted from how fast its residual fell between two reads of the control
+// blocks (prev, then k); -1 when some live system has no such rate yet.  Ctl
+// has the fields done, iters, maxit, rr and tol2 (the stop test rr <= tol2).
+// Only the launch pattern follows from it: iterations past a system's stop
+// test return at once whatever was predicted.
+template <class Ctl>
+int predict_left(int nsys, const Ctl* k, const Ctl* prev) {
+  int left = 0;
+  for (int q = 0; q < nsys; ++q) {
+    if (k[q].done) continue;
+    const int di = k[q].iters - prev[q].iters;
+    if (di <= 0 || !(k[q].rr > 0.0) || !(k[q].rr < prev[q].rr) || !(k[q].tol2 > 0.0)) return -1;
+    const double rate = std::log(k[q].rr / prev[q].rr) / di;  // < 0
+    const double need = std::log(k[q].tol2 / k[q].rr) / rate;
+    int n = need < 1.0 ? 1 : need > 1e6 ? 1000000 : (int)std::ceil(need);
+    n = std::min(n, std::max(1, k[q].maxit - k[q].iters));
+    left = std::max(left, n);
+  }
+  return left;
+}
+
+// Graph launches of one round of a Krylov solve, from predict_left's `left`:
+// full graphs (full_iters iterations each) while the stop test is further
+// away than full_iters - tail_iters, several of them (half the predicted
+// iterations, at most 8: convergence may speed up) when it is far; else
+// enough tail graphs (tail_iters each) to cover `left`.
+struct Round {
+  int full = 0, tail = 0;
+};
+inline Round plan_round(int left, int full_iters, int tail_iters) {
+  Round r;
+  if (left < 0 || left > full_iters - tail_iters)
+    r.full = std::max(1, std::min(8, left / (2 * full_iters)));
+  else
+    r.tail = (left + tail_iters - 1) / tail_iters;
+  return r;
 }
 
 }  // namespace fftg_host

@@ -1,6 +1,7 @@
 // Host-only checks of the library's host logic (phase-table validation, the
 // adaptive driver's step control, the grouping of batch items into lockstep
 // units), built with the address and undefined-behaviour sanitizers.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -236,10 +237,73 @@ static void batch_checks() {
   }
 }
 
+// A control block with the fields predict_left reads.
+struct Ctl {
+  int done = 0, iters = 0, maxit = 1000;
+  double rr = 0.0, tol2 = 0.0;
+};
+
+void pacing_checks() {
+  Ctl prev[2], k[2];
+  // no rate yet (no iteration between the reads): -1
+  prev[0].rr = k[0].rr = 1.0;
+  prev[0].tol2 = k[0].tol2 = 1e-12;
+  CHECK(fftg_host::predict_left(1, k, prev) == -1);
+  // residual halved per iteration over 8 iterations: log2(rr / tol2) more
+  k[0].iters = 8;
+  k[0].rr = std::pow(0.5, 8);
+  CHECK(fftg_host::predict_left(1, k, prev) == 32);
+  // a residual that grew gives no rate
+  Ctl up = k[0];
+  up.rr = 2.0;
+  CHECK(fftg_host::predict_left(1, &up, prev) == -1);
+  // done systems are ignored; the slowest live one decides
+  prev[1] = prev[0];
+  k[1] = k[0];
+  k[1].rr = std::pow(0.25, 8);  // a quarter per iteration: 12 more from 2^-16
+  CHECK(fftg_host::predict_left(2, k, prev) == 32);
+  k[0].done = 1;
+  CHECK(fftg_host::predict_left(2, k, prev) == 12);
+  // the stop test nearly met: at least one; maxit bounds the prediction
+  k[1].rr = 1.01e-12;
+  CHECK(fftg_host::predict_left(2, k, prev) == 1);
+  k[1].rr = std::pow(0.25, 8);
+  k[1].maxit = 10;
+  CHECK(fftg_host::predict_left(2, k, prev) == 2);
+  // a nearly flat residual stays bounded
+  k[1].maxit = 1 << 30;
+  k[1].rr = prev[1].rr * (1.0 - 1e-15);
+  const int far = fftg_host::predict_left(2, k, prev);
+  CHECK(far >= 1 && far <= 1000000);
+  // launch rounds for graphs of 8 and 2 iterations
+  auto rd = fftg_host::plan_round(-1, 8, 2);
+  CHECK(rd.full == 1 && rd.tail == 0);
+  rd = fftg_host::plan_round(7, 8, 2);
+  CHECK(rd.full == 1 && rd.tail == 0);
+  rd = fftg_host::plan_round(6, 8, 2);
+  CHECK(rd.full == 0 && rd.tail == 3);
+  rd = fftg_host::plan_round(1, 8, 2);
+  CHECK(rd.full == 0 && rd.tail == 1);
+  rd = fftg_host::plan_round(0, 8, 2);  // every live system already at its test
+  CHECK(rd.full == 0 && rd.tail == 0);
+  rd = fftg_host::plan_round(40, 8, 2);
+  CHECK(rd.full == 2 && rd.tail == 0);
+  rd = fftg_host::plan_round(1000000, 8, 2);
+  CHECK(rd.full == 8 && rd.tail == 0);
+  // a round never queues more iterations than predicted beyond one graph
+  for (int left = 0; left < 400; ++left) {
+    const auto r = fftg_host::plan_round(left, 8, 2);
+    const int its = 8 * r.full + 2 * r.tail;
+    CHECK(its <= std::max(left + 1, 8));
+    CHECK(left == 0 || its >= std::min(left, 8));
+  }
+}
+
 int main() {
   table_checks();
   drive_checks();
   batch_checks();
+  pacing_checks();
   if (failures) {
     std::printf("%d checks failed\n", failures);
     return 1;
