@@ -484,6 +484,10 @@ constexpr int fs_tile_wide(int n, int nc) { return pow2_floor(kElemsWide<T> / (n
 #ifndef FFTG_FWDRES_BYTES
 #define FFTG_FWDRES_BYTES 49152
 #endif
+#ifndef FFTG_FWDRES_THREADS
+#define FFTG_FWDRES_THREADS 512
+#endif
+constexpr int kFwdResThreads = FFTG_FWDRES_THREADS;
 template <typename T>
 constexpr int fr_tile(int n, int nc) {
   return pow2_floor(FFTG_FWDRES_BYTES / (int)sizeof(cpx<T>) / (n * nc)) < 1

@@ -997,14 +997,14 @@ FFTG_KERNEL void k_gal_resid(Geo g, Sym<T> sym, unsigned char mk0, unsigned char
 // [sys][comp][Ns], tpo tiles per system, partials [sys][tpo]; tiles are
 // taken through xcd_tile (chunk).
 template <typename T, int NF, int C>
-FFTG_KERNEL_WIDE void k_gal_fwd_resid(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
+__global__ __launch_bounds__(kFwdResThreads) void k_gal_fwd_resid(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
                                       Sym<T> sym, unsigned mbits, const cpx<T>* __restrict__ w_all,
                                       cpx<T>* __restrict__ r_all, long long inner, long long es,
                                       int TL_rt, int tpo, int chunk,
                                       double* __restrict__ partials,
                                       const KrylovCtl* __restrict__ ctl_all) {
   constexpr bool FIX = NF > 0;
-  constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
+  constexpr int NT = FIX ? kFwdResThreads : FFT_THREADS;
   constexpr int TLF = FIX ? fr_tile<T>(NF, C) : 1;
   __shared__ cpx<T> buf[FIX ? C * TLF * NF : LDS_ELEMS];
   static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
@@ -2724,7 +2724,7 @@ int launch_gal_fwd_resid(const Plan& p, const cpx<T>* tw, const Geo& g, int c, b
       const long long nb = (long long)tpo * nsys;
       const int chunk = xcd_chunk(nb * TL, (long long)tpo * TL, TL);
       hipLaunchKernelGGL((k_gal_fwd_resid<T, NF, 6>), dim3((unsigned)nb),
-                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, mb, w, r,
+                         dim3(NF ? kFwdResThreads : FFT_THREADS), 0, st, p, tw, g, sym, mb, w, r,
                          inner, es, TL, tpo, chunk, partials, ctl);
     } else {
       const int TL = NF ? fr_tile<T>(NF, 3) : tile_lines(p.n, 3);
@@ -2732,7 +2732,7 @@ int launch_gal_fwd_resid(const Plan& p, const cpx<T>* tw, const Geo& g, int c, b
       const long long nb = (long long)tpo * nsys;
       const int chunk = xcd_chunk(nb * TL, (long long)tpo * TL, TL);
       hipLaunchKernelGGL((k_gal_fwd_resid<T, NF, 3>), dim3((unsigned)nb),
-                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, mb, w, r,
+                         dim3(NF ? kFwdResThreads : FFT_THREADS), 0, st, p, tw, g, sym, mb, w, r,
                          inner, es, TL, tpo, chunk, partials, ctl);
     }
   })
