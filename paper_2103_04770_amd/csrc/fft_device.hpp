@@ -517,6 +517,8 @@ template <int NT = FFT_THREADS>
 __device__ __forceinline__ double ordered_sum_t(const double* __restrict__ p, int nb,
                                                 double* red) {
   double acc = 0.0;
+  // unrolled so that several loads are in flight; the additions keep their order
+#pragma unroll 8
   for (int i = threadIdx.x; i < nb; i += NT) acc += p[i];
   return block_sum<NT>(acc, red);
 }

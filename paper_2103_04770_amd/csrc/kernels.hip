@@ -1235,6 +1235,8 @@ FFTG_KERNEL void k_wnorm2(Geo g, int ncomp, const cpx<T>* __restrict__ a,
 // ============================================================ scalars
 __device__ double ordered_sum(const double* __restrict__ p, int nb, double* red) {
   double acc = 0.0;
+  // unrolled so that several loads are in flight; the additions keep their order
+#pragma unroll 8
   for (int i = threadIdx.x; i < nb; i += FFT_THREADS) acc += p[i];
   return block_sum(acc, red);
 }
@@ -2547,7 +2549,14 @@ void launch_strided(const Plan& p, const cpx<T>* tw, cpx<T>* data, long long nli
     const int TL = NF ? fs_tile<T, tile_budget<SH>()>(NF) : tile_lines(p.n, 1);
     const int NT = NF ? kStridedThreads : FFT_THREADS;
     const long long nb = (nlines + TL - 1) / TL;
-    const int chunk = xcd_chunk(nlines, lps, TL);
+    // One FP64 system, inverse: runs of 16 tiles handed to the XCDs in turn
+    // rather than one contiguous run each.  Part of the spectrum this pass
+    // reads (just written by the outer inverse pass) is still in the
+    // Infinity Cache, unevenly over the tile range; with contiguous runs the
+    // XCDs holding the uncached runs set the pass's time (measured in the CG
+    // loop at 128^3: 46.9 -> 42.4 us; the forward pass and FP32 are faster
+    // with contiguous runs).
+    const int chunk = lps < nlines ? xcd_chunk(nlines, lps, TL) : (!fwd && sizeof(T) == 8 ? 16 : 0);
     if (fwd)
       hipLaunchKernelGGL((k_strided<T, true, NF, SH>), dim3((unsigned)nb), dim3(NT), 0, st, p, tw,
                          data, nlines, inner, ostride, es, TL, ctl, lps, chunk);
