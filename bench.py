@@ -73,7 +73,9 @@ def kernel_bytes(name, n, c, nd, J, fp32):
         "helmholtz_y_inv": (2 + nd) * Ns * zc,
         "helmholtz_y_fwd": (nd + 2) * Ns * zc,
         "helmholtz_outer_dir_inv": (5 + 2) * Ns * zc,
-        "helmholtz_outer_div_fwd": (2 + 2) * Ns * zc,
+        # the forward pass fused with the residual update: the two
+        # transformed fields, p and r in, r out (without the fusion: 2 + 2)
+        "helmholtz_outer_div_fwd": (2 + 3) * Ns * zc,
         "helmholtz_resid": 3 * Ns * zc,
         "constitutive": N * (1 + 8 * (2 * c + 14 + 2 * J) + 8 * zr),
     }

@@ -189,6 +189,11 @@ struct fftg_handle {
   // update as one pass that does not store the transform (FFTG_GAL_FUSE=0 at
   // creation: two passes)
   bool fuse_res = true;
+  // Helmholtz PCG: p.Lp summed by the inverse pass (|p|^2) and the x pass
+  // (ell^2 |grad p|^2), and the forward pass fused with the residual update
+  // (FFTG_HELM_FUSE=0 at creation: forward pass, scalar kernel and residual
+  // pass apart)
+  bool hfuse = true;
   bool fp32() const { return prec == FFTG_FP32_REFINED; }
   size_t wsz() const { return fp32() ? sizeof(float) : sizeof(double); }
 };
@@ -848,6 +853,46 @@ void helm_iteration(fftg_handle* H, const T* ell2, int nsys) {
   const bool zo = g.ndim == 3;
   const int oa = outer_axis(H);
   const T scl = T(1.0 / (double)g.N);
+  if (H->hfuse) {
+    // p.Lp = weighted |p|^2 (inverse pass, [sys][nbp]) + the sum of
+    // ell^2 |grad p|^2 over the voxels (x pass, [sys][nbx], after them); alpha
+    // from both, then the forward pass updates r ([sys][2][nbr], from the
+    // start again).  The counts stay below the workspace's partials: nbp is
+    // at most the lines of one slab, nbx the x lines, nbr the slab's lines.
+    double* ppart = H->partials;
+    int nbp, nbx;
+    {
+      KT t(H, K_HLM_OI);
+      nbp = fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true,
+                                      C<T>(H->hr), C<T>(H->hp), C<T>(H->hx), C<T>(H->hw), H->ctl,
+                                      H->st, nsys, ppart);
+    }
+    double* xpart = H->partials + (long long)nsys * nbp;
+    helm_inner<T>(H, false, C<T>(H->hw), H->ctl, K_HLM_YI, nsys);
+    {
+      KT t(H, K_HLM_X);
+      nbx = fftg::launch_x_fused_helm<T, T>(H->plan[0], TW<T>(H, 0), g, C<T>(H->hw), ell2, scl,
+                                            H->ctl, H->st, nsys, H->hphase, phase_tab<T>(H),
+                                            xpart);
+    }
+    {
+      KT t(H, K_SMALL);
+      fftg::launch_fin_alpha2(ppart, nbp, xpart, nbx, H->ctl, H->st, nsys);
+    }
+    helm_inner<T>(H, true, C<T>(H->hw), H->ctl, K_HLM_YF, nsys);
+    int nr;
+    {
+      KT t(H, K_HLM_OF);
+      nr = fftg::launch_h_fwd_resid<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hp),
+                                       C<T>(H->hw), C<T>(H->hr), H->partials, H->ctl, H->st,
+                                       nsys);
+    }
+    {
+      KT t(H, K_SMALL);
+      fftg::launch_fin_beta(H->partials, nr, 2, H->ctl, H->st, nsys);
+    }
+    return;
+  }
   {
     KT t(H, K_HLM_OI);
     fftg::launch_h_dir_inv<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), true, C<T>(H->hr),
@@ -886,7 +931,7 @@ void helm_iteration(fftg_handle* H, const T* ell2, int nsys) {
 // ell2 field, system count, precision and phase array (the four most recent).
 template <typename T>
 fftg_handle::GraphSlot& helm_graphs(fftg_handle* H, const T* ell2, int nsys) {
-  const unsigned long long key = H->fp32() ? 1ull : 2ull;
+  const unsigned long long key = (H->fp32() ? 1ull : 2ull) | (H->hfuse ? 4ull : 0ull);
   for (auto& sl : H->ghelm)
     if (sl.exec[0] && sl.key == key && sl.kell == ell2 && sl.knsys == nsys &&
         sl.kphase == H->hphase)
@@ -2523,6 +2568,7 @@ fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** o
   if (const char* f = std::getenv("FFTG_GAL_FOLD")) H->fold = f[0] == '1' && f[1] == '\0';
   if (const char* f = std::getenv("FFTG_GAL_XDOT")) H->xdot = !(f[0] == '0' && f[1] == '\0');
   if (const char* f = std::getenv("FFTG_GAL_FUSE")) H->fuse_res = !(f[0] == '0' && f[1] == '\0');
+  if (const char* f = std::getenv("FFTG_HELM_FUSE")) H->hfuse = !(f[0] == '0' && f[1] == '\0');
   if (rc == FFTG_OK) tune_tiles(H);
   if (rc != FFTG_OK) {
     g_create_error = H->err;
@@ -2658,8 +2704,13 @@ fftg_status fftg_time_kernel(fftg_handle* H, int kid, int reps, double* avg_ms) 
                                     H->st);
           break;
         case K_HLM_OF:
-          fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hp),
-                                    C<T>(H->hw), C<T>(H->hAp), H->partials, H->ctl, H->st);
+          if (H->hfuse)
+            fftg::launch_h_fwd_resid<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H),
+                                        C<T>(H->hp), C<T>(H->hw), C<T>(H->hr), H->partials,
+                                        H->ctl, H->st);
+          else
+            fftg::launch_h_div_fwd<T>(H->plan[oa], TW<T>(H, oa), g, zo, SY<T>(H), C<T>(H->hp),
+                                      C<T>(H->hw), C<T>(H->hAp), H->partials, H->ctl, H->st);
           break;
         case K_HLM_RES:
           fftg::launch_h_resid<T>(g, SY<T>(H), false, C<T>(H->hr), C<T>(H->hb), C<T>(H->hAp),

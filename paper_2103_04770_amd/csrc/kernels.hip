@@ -316,6 +316,9 @@ FFTG_KERNEL void k_x_fused_gal(Plan plan, const cpx<T>* __restrict__ tw, Geo g, 
 
 // Fused x pass of the Helmholtz operator: C2R of the ND gradient
 // components, multiply by scale * ell^2(x), R2C.
+// partials (optional): the PCG's sum over voxels of ell^2 |grad p|^2 (the
+// gradient part of p . L p by Parseval's identity; the inverse transform
+// carries no 1/N, `scale` does), one per workgroup, [sys][bps].
 // Stacked systems: nsys x n2 x n3 lines per gradient component (component
 // stride wstride), ell2 [sys][N].  With a phase array (shared by the
 // systems: the fields of one RVE), ell^2 comes from the per-phase table
@@ -326,7 +329,7 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
                                 cpx<T>* __restrict__ w, const TL* __restrict__ ell2, T scl,
                                 int nsys, long long wstride, const KrylovCtl* __restrict__ ctl,
                                 const unsigned char* __restrict__ phase,
-                                const TL* __restrict__ ptab) {
+                                const TL* __restrict__ ptab, double* __restrict__ partials) {
   constexpr bool FIX = NF > 0;
   constexpr int NT = FIX ? kFusedThreads : FFT_THREADS;
   constexpr int LDX = FIX ? padded_pitch(NF) : 1;
@@ -360,6 +363,7 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
   else
     lds_fft<T, false, false>(buf, plan, P, n1, tw);
   T* fb = reinterpret_cast<T*>(buf);
+  double dot = 0.0;
   for (int e = threadIdx.x; e < NL * n1; e += NT) {
     const int l = e / n1, x = e % n1;
     const long long line = line0 + l;
@@ -371,7 +375,10 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
     for (int q = 0; q < ND; ++q) {
       const int s = q * NL + l;
       const int slot = s < P ? 2 * xaddr<FIX>(s, x, ld) : 2 * xaddr<FIX>(s - P, x, ld) + 1;
-      fb[slot] = fb[slot] * f;
+      const T gq = fb[slot];
+      const T o = gq * f;
+      fb[slot] = o;
+      dot += (double)gq * (double)o;
     }
   }
   __syncthreads();
@@ -388,6 +395,13 @@ FFTG_KERNEL void k_x_fused_helm(Plan plan, const cpx<T>* __restrict__ tw, Geo g,
     unpack_forward<FIX>(buf, p, k, n1, ld, A, B);
     if (la < nlines) w[(sa / NL) * wstride + la * n1h + k] = A;
     if (lb < nlines) w[(sb / NL) * wstride + lb * n1h + k] = B;
+  }
+  if (partials) {
+    // the tile is free once every wave is past the loop above (block_sum
+    // starts with a barrier)
+    static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
+    const double s = block_sum<NT>(dot, reinterpret_cast<double*>(buf));
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
   }
 }
 
@@ -652,6 +666,8 @@ FFTG_KERNEL_WIDE void k_gal_dot_fwd(Plan plan, const cpx<T>* __restrict__ tw,
 // Outer-axis inverse pass of the Helmholtz PCG (single scalar spectrum):
 //   update: p <- M r + beta p ; x <- x + alpha p_old
 //   w_j <- inverse transform of (i q~_j p), j < ND.
+// ppart (optional, with update): weighted |p|^2 of the new p, one partial
+// sum per workgroup [sys][tpo] (the identity part of p . L p).
 // The fixed-length path uses a 48 KB tile so that tile rows stay >= 128 B.
 //
 // SPLIT (3D): the modified frequencies factor per axis, q_x = f_x c_y c_z,
@@ -669,13 +685,15 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
                              int update, const cpx<T>* __restrict__ r, cpx<T>* __restrict__ pp,
                              cpx<T>* __restrict__ x, cpx<T>* __restrict__ w, long long inner,
                              long long ostride, long long es, int TL_rt, int tpo,
-                             long long wstride, const KrylovCtl* __restrict__ ctl_all) {
+                             long long wstride, const KrylovCtl* __restrict__ ctl_all,
+                             double* __restrict__ ppart) {
   const int sys = (int)(blockIdx.x / tpo);
   const KrylovCtl* ctl = ctl_all ? ctl_all + sys : nullptr;
   if (ctl && ctl->done) return;
   constexpr bool FIX = NF > 0;
   constexpr int NC = SPLIT ? 2 : ND;  // fields transformed
   __shared__ cpx<T> buf[FIX ? NC * fs_tile_wide<T>(NF, NC) * NF : LDS_ELEMS];
+  double pp2 = 0.0;  // weighted |p|^2 of the new p (ppart)
   const int n = FIX ? NF : plan.n;
   constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
   const int TL = FIX ? fs_tile_wide<T>(NF, NC) : TL_rt;
@@ -702,6 +720,7 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
         x[gi] = x[gi] + scale(po, alpha);
         pn = scale(r[gi], minv) + scale(po, beta);
         pp[gi] = pn;
+        pp2 += (double)pn.x * (double)pn.x + (double)pn.y * (double)pn.y;
       } else {
         pn = pp[gi];
       }
@@ -747,6 +766,14 @@ FFTG_KERNEL_WIDE void k_h_dir_inv(Plan plan, const cpx<T>* __restrict__ tw, Geo 
 #pragma unroll
         for (int j = 0; j < NC; ++j) w[j * wstride + gi] = buf[t * ld + j * TL + l];
       }
+  }
+  if (ppart) {
+    // every element of the thread's line has the same kx; the tile is free
+    // once every wave is past the transform (block_sum starts with a barrier)
+    static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
+    const double wt = lb >= 0 ? hweight(lkx, g.n1h) : 0.0;
+    const double s = block_sum<NT>(wt * pp2, reinterpret_cast<double*>(buf));
+    if (threadIdx.x == 0) ppart[blockIdx.x] = s;
   }
 }
 
@@ -907,6 +934,103 @@ FFTG_KERNEL_WIDE void k_h_div_fwd(Plan plan, const cpx<T>* __restrict__ tw, Geo 
   }
   const double s = block_sum<NT>(acc, red);
   if (partials && threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Outer-axis forward pass of the Helmholtz PCG fused with the residual
+// update, for the iteration whose p . L p the inverse pass (|p|^2) and the x
+// pass (ell^2 |grad p|^2) summed (alpha is in the control block): the
+// transform of k_h_div_fwd, then per coefficient
+//   r <- r - alpha (p - i sum_j q~_j w_j),  partial sums of weighted r . M r
+// and |r|^2 ([sys][2][tpo]), without storing L p.
+template <typename T, int NF, int ND, bool SPLIT>
+FFTG_KERNEL_WIDE void k_h_fwd_resid(Plan plan, const cpx<T>* __restrict__ tw, Geo g, Sym<T> sym,
+                                    const cpx<T>* __restrict__ pp, cpx<T>* __restrict__ w,
+                                    cpx<T>* __restrict__ r, long long inner, long long ostride,
+                                    long long es, int TL_rt, int tpo, long long wstride,
+                                    double* __restrict__ partials,
+                                    const KrylovCtl* __restrict__ ctl_all) {
+  const int sys = (int)(blockIdx.x / tpo);
+  const KrylovCtl* ctl = ctl_all + sys;
+  if (ctl->done) return;
+  constexpr bool FIX = NF > 0;
+  constexpr int NC = SPLIT ? 2 : ND;  // fields transformed
+  __shared__ cpx<T> buf[FIX ? NC * fs_tile_wide<T>(NF, NC) * NF : LDS_ELEMS];
+  double* red = reinterpret_cast<double*>(buf);  // reused after the transform (block_sum syncs)
+  const int n = FIX ? NF : plan.n;
+  constexpr int NT = FIX ? kWideThreads : FFT_THREADS;
+  static_assert(sizeof(buf) >= NT * sizeof(double), "reduction scratch aliases the tile");
+  const int TL = FIX ? fs_tile_wide<T>(NF, NC) : TL_rt;
+  const int ld = NC * TL;
+  const int l = threadIdx.x % TL, t0 = threadIdx.x / TL, dt = NT / TL;
+  const long long Lloc = (long long)(blockIdx.x % tpo) * TL + l;
+  const long long L = (long long)sys * inner + Lloc;
+  const long long lb = Lloc < inner ? line_base(L, inner, ostride) : -1;
+  const bool zouter = g.ndim == 3;
+  const int lkx = (int)(Lloc % g.n1h), lky = (int)(Lloc / g.n1h);
+  constexpr int TLC = FIX ? fs_tile_wide<T>(NF, NC) : 1;
+  if constexpr (FIX && NT % (NC * TLC) == 0) {
+    // first stage straight from the NC fields: the thread's pseudo-line of
+    // the tile is field pl / TL, line pl % TL
+    const int pl = threadIdx.x % (NC * TLC), jf = pl / TLC;
+    const long long Lf = (long long)(blockIdx.x % tpo) * TLC + pl % TLC;
+    const long long lbf = Lf < inner ? line_base((long long)sys * inner + Lf, inner, ostride) : -1;
+    auto ldf = [&](int t) { return lbf >= 0 ? w[jf * wstride + lbf + t * es] : mk(T(0), T(0)); };
+    auto nost = [](int, cpx<T>) {};
+    lds_fft_direct<T, true, NF, NC * TLC, NT, decltype(ldf), decltype(nost), true, false>(
+        buf, tw, ldf, nost);
+  } else {
+    for (int t = t0; t < n; t += dt) {
+      if (lb >= 0) {
+        const long long gi = lb + t * es;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = w[j * wstride + gi];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) buf[t * ld + j * TL + l] = mk(T(0), T(0));
+      }
+    }
+    __syncthreads();
+    if constexpr (FIX)
+      lds_fft_c<T, true, true, NF, NC * fs_tile_wide<T>(NF, NC), NC * fs_tile_wide<T>(NF, NC),
+                NT>(buf, tw);
+    else
+      lds_fft<T, true, true>(buf, plan, ld, ld, tw);
+  }
+  const T alpha = (T)ctl->alpha;
+  const T l2 = (T)ctl->ell2ref;
+  double arz = 0.0, arr = 0.0;
+  for (int t = t0; t < n; t += dt) {
+    if (lb >= 0) {
+      const long long gi = lb + t * es;
+      const int kx = lkx, ky = zouter ? lky : t, kz = zouter ? t : 0;
+      const cpx<T> pv = pp[gi];
+      T q[3];
+      qvec(sym, true, kx, ky, kz, q);
+      cpx<T> div = mk(T(0), T(0));
+      if constexpr (SPLIT) {
+        const T* b = sym.base;
+        div = scale(buf[t * ld + l], b[sym.cs[2] + kz]) +
+              scale(buf[t * ld + TL + l], b[sym.gq[2] + kz]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < ND; ++j) div = div + scale(buf[t * ld + j * TL + l], q[j]);
+      }
+      const cpx<T> a = pv + mul_mi(div);
+      const T minv = T(1) / (T(1) + l2 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]));
+      const cpx<T> rn = r[gi] - scale(a, alpha);
+      r[gi] = rn;
+      const double wt = hweight(kx, g.n1h);
+      const double rr = (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
+      arr += wt * rr;
+      arz += wt * rr * (double)minv;
+    }
+  }
+  double* pt = partials + (long long)sys * 2 * tpo;
+  const int loc = (int)(blockIdx.x % tpo);
+  double sm = block_sum<NT>(arz, red);
+  if (threadIdx.x == 0) pt[loc] = sm;
+  sm = block_sum<NT>(arr, red);
+  if (threadIdx.x == 0) pt[tpo + loc] = sm;
 }
 
 // ============================================================ pointwise
@@ -1259,6 +1383,30 @@ FFTG_KERNEL void k_fin_alpha(const double* __restrict__ partials, int nb, Krylov
   __shared__ double red[FFT_THREADS];
   const double pAp = ordered_sum(partials + (long long)blockIdx.x * nb, nb, red);
   if (threadIdx.x == 0) {
+    ctl->pAp = pAp;
+    if (!isfinite(pAp) || !isfinite(ctl->rz)) {
+      ctl->alpha = 0.0;
+      ctl->done = 4;
+    } else if (!(pAp > 0.0)) {
+      ctl->alpha = 0.0;
+      ctl->done = 3;
+    } else {
+      ctl->alpha = ctl->rz / pAp;
+    }
+  }
+}
+
+// p.Ap as the sum of two sets of partial sums (system s: pa + s * na and
+// pb + s * nb); otherwise as k_fin_alpha.
+FFTG_KERNEL void k_fin_alpha2(const double* __restrict__ pa, int na,
+                              const double* __restrict__ pb, int nb, KrylovCtl* ctl_all) {
+  KrylovCtl* ctl = ctl_all + blockIdx.x;
+  if (ctl->done) return;
+  __shared__ double red[FFT_THREADS];
+  const double sa = ordered_sum(pa + (long long)blockIdx.x * na, na, red);
+  const double sb = ordered_sum(pb + (long long)blockIdx.x * nb, nb, red);
+  if (threadIdx.x == 0) {
+    const double pAp = sa + sb;
     ctl->pAp = pAp;
     if (!isfinite(pAp) || !isfinite(ctl->rz)) {
       ctl->alpha = 0.0;
@@ -2691,26 +2839,28 @@ int launch_x_fused_gal(const Plan& p, const cpx<T>* tw, const Geo& g, int c, cpx
 }
 
 template <typename T, typename TL>
-void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
-                         const TL* ell2, T scl, const KrylovCtl* ctl, hipStream_t st, int nsys,
-                         const unsigned char* phase, const TL* ptab) {
+int launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
+                        const TL* ell2, T scl, const KrylovCtl* ctl, hipStream_t st, int nsys,
+                        const unsigned char* phase, const TL* ptab, double* partials) {
   const long long lpsys = (long long)g.n2 * g.n3;
   const long long ws = (long long)nsys * g.Ns;
+  long long bps = 0;
   FFTG_DISPATCH_N(g.n1, {
     if (g.ndim == 3) {
       const int NL = NF ? fx_helm_lines<T>(NF, 3) : fused_lines_rt(g.n1, 3);
-      const long long nb = (lpsys + NL - 1) / NL * nsys;
-      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 3>), dim3((unsigned)nb),
+      bps = (lpsys + NL - 1) / NL;
+      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 3>), dim3((unsigned)(bps * nsys)),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
-                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl, phase, ptab);
+                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl, phase, ptab, partials);
     } else {
       const int NL = NF ? fx_helm_lines<T>(NF, 2) : fused_lines_rt(g.n1, 2);
-      const long long nb = (lpsys + NL - 1) / NL * nsys;
-      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 2>), dim3((unsigned)nb),
+      bps = (lpsys + NL - 1) / NL;
+      hipLaunchKernelGGL((k_x_fused_helm<T, TL, NF, 2>), dim3((unsigned)(bps * nsys)),
                          dim3(NF ? kFusedThreads : FFT_THREADS), 0,
-                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl, phase, ptab);
+                         st, p, tw, g, NL, w, ell2, scl, nsys, ws, ctl, phase, ptab, partials);
     }
   })
+  return (int)bps;  // partials per system
 }
 
 template <typename T>
@@ -2804,7 +2954,7 @@ void launch_project(const Geo& g, int c, const Sym<T>& sym, const unsigned char*
 template <typename T>
 int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, bool update, const cpx<T>* r, cpx<T>* pp, cpx<T>* x,
-                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st, int nsys) {
+                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st, int nsys, double* ppart) {
   long long nl, inner, os, es;
   outer_lines(g, 1, zouter, nl, inner, os, es);
   const long long ws = (long long)nsys * g.Ns;
@@ -2814,17 +2964,20 @@ int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
       tpo = tiles_per_sys(inner, TL);
       hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3, true>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl);
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl,
+                         ppart);
     } else if (g.ndim == 3) {
       const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
       tpo = tiles_per_sys(inner, TL);
       hipLaunchKernelGGL((k_h_dir_inv<T, NF, 3, false>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl);
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl,
+                         ppart);
     } else {
       const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
       tpo = tiles_per_sys(inner, TL);
       hipLaunchKernelGGL((k_h_dir_inv<T, NF, 2, false>), dim3((unsigned)(tpo * nsys)), dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p,
-                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl);
+                         tw, g, sym, update ? 1 : 0, r, pp, x, w, inner, os, es, TL, tpo, ws, ctl,
+                         ppart);
     }
   })
   return tpo;
@@ -2878,6 +3031,38 @@ int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
     }
   })
   return tpo;
+}
+
+template <typename T>
+int launch_h_fwd_resid(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
+                       const Sym<T>& sym, const cpx<T>* pp, cpx<T>* w, cpx<T>* r,
+                       double* partials, const KrylovCtl* ctl, hipStream_t st, int nsys) {
+  long long nl, inner, os, es;
+  outer_lines(g, 1, zouter, nl, inner, os, es);
+  const long long ws = (long long)nsys * g.Ns;
+  int tpo = 0;
+  FFTG_DISPATCH_N(p.n, {
+    if (helm_split(g)) {
+      const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_fwd_resid<T, NF, 3, true>), dim3((unsigned)(tpo * nsys)),
+                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, pp, w, r,
+                         inner, os, es, TL, tpo, ws, partials, ctl);
+    } else if (g.ndim == 3) {
+      const int TL = NF ? fs_tile_wide<T>(NF, 3) : tile_lines(p.n, 3);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_fwd_resid<T, NF, 3, false>), dim3((unsigned)(tpo * nsys)),
+                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, pp, w, r,
+                         inner, os, es, TL, tpo, ws, partials, ctl);
+    } else {
+      const int TL = NF ? fs_tile_wide<T>(NF, 2) : tile_lines(p.n, 2);
+      tpo = tiles_per_sys(inner, TL);
+      hipLaunchKernelGGL((k_h_fwd_resid<T, NF, 2, false>), dim3((unsigned)(tpo * nsys)),
+                         dim3(NF ? kWideThreads : FFT_THREADS), 0, st, p, tw, g, sym, pp, w, r,
+                         inner, os, es, TL, tpo, ws, partials, ctl);
+    }
+  })
+  return tpo;  // [sys][2][tpo] partials
 }
 
 template <typename T>
@@ -2939,6 +3124,10 @@ void launch_tangent_apply(long long N, int c, const TT* tan, const double* gsig,
 
 void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st, int nsys) {
   hipLaunchKernelGGL(k_fin_alpha, dim3(nsys), dim3(FFT_THREADS), 0, st, partials, nb, ctl);
+}
+void launch_fin_alpha2(const double* pa, int na, const double* pb, int nb, KrylovCtl* ctl,
+                       hipStream_t st, int nsys) {
+  hipLaunchKernelGGL(k_fin_alpha2, dim3(nsys), dim3(FFT_THREADS), 0, st, pa, na, pb, nb, ctl);
 }
 void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st,
                      int nsys) {
@@ -3130,7 +3319,10 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, i
                                   hipStream_t);                                                  \
   template int launch_h_dir_inv<T>(const Plan&, const cpx<T>*, const Geo&, bool, const Sym<T>&,  \
                                    bool, const cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*,               \
-                                   const KrylovCtl*, hipStream_t, int);                          \
+                                   const KrylovCtl*, hipStream_t, int, double*);                 \
+  template int launch_h_fwd_resid<T>(const Plan&, const cpx<T>*, const Geo&, bool,              \
+                                     const Sym<T>&, const cpx<T>*, cpx<T>*, cpx<T>*, double*,    \
+                                     const KrylovCtl*, hipStream_t, int);                        \
   template int launch_h_div_fwd<T>(const Plan&, const cpx<T>*, const Geo&, bool, const Sym<T>&,  \
                                    const cpx<T>*, cpx<T>*, cpx<T>*, double*, const KrylovCtl*,   \
                                    hipStream_t, int);                                            \
@@ -3150,9 +3342,9 @@ int launch_sum_ell2(long long N, const T* e, double* partials, hipStream_t st, i
                                        const Sym<T>&, const unsigned char*, const cpx<T>*,       \
                                        cpx<T>*, double*, const KrylovCtl*, hipStream_t, int);    \
   template int gal_fwd_resid_count<T>(const Plan&, const Geo&, int, bool);                     \
-  template void launch_x_fused_helm<T, T>(const Plan&, const cpx<T>*, const Geo&, cpx<T>*,       \
-                                          const T*, T, const KrylovCtl*, hipStream_t, int,       \
-                                          const unsigned char*, const T*);                       \
+  template int launch_x_fused_helm<T, T>(const Plan&, const cpx<T>*, const Geo&, cpx<T>*,        \
+                                         const T*, T, const KrylovCtl*, hipStream_t, int,        \
+                                         const unsigned char*, const T*, double*);               \
   template void launch_constitutive<T>(const MatTable&, const Geo&, int, int,                    \
                                        const unsigned char*, const double*, const double*,       \
                                        const double*, double*, double*, double*, T*,             \

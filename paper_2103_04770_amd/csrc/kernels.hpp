@@ -154,21 +154,33 @@ inline bool helm_split(const Geo& g) { return g.ndim == 3 && g.n2 > 1; }
 template <typename T>
 void launch_h_y_split(const Plan& p, const cpx<T>* tw, const Geo& g, const Sym<T>& sym,
                       cpx<T>* w, bool fwd, const KrylovCtl* ctl, hipStream_t st, int nsys = 1);
+// ppart (optional, with update): weighted |p|^2 of the new p, [sys][count]
+// with count the returned tiles per system.
 template <typename T>
 int launch_h_dir_inv(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, bool update, const cpx<T>* r, cpx<T>* pp, cpx<T>* x,
-                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st, int nsys = 1);
+                     cpx<T>* w, const KrylovCtl* ctl, hipStream_t st, int nsys = 1,
+                     double* ppart = nullptr);
+// The forward pass fused with the residual update r <- r - alpha L p (alpha
+// in the control blocks), partials [sys][2][count] (weighted r.Mr, |r|^2),
+// count returned.
+template <typename T>
+int launch_h_fwd_resid(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
+                       const Sym<T>& sym, const cpx<T>* pp, cpx<T>* w, cpx<T>* r,
+                       double* partials, const KrylovCtl* ctl, hipStream_t st, int nsys = 1);
 template <typename T>
 int launch_h_div_fwd(const Plan& p, const cpx<T>* tw, const Geo& g, bool zouter,
                      const Sym<T>& sym, const cpx<T>* pp, cpx<T>* w, cpx<T>* Ap,
                      double* partials, const KrylovCtl* ctl, hipStream_t st, int nsys = 1);
 // phase / ptab (optional): ell^2 from a per-phase table ptab [sys][kMaxPhases]
 // indexed by the phase array shared by the systems, instead of ell2.
+// partials (optional): sum of ell^2 |grad p|^2 per workgroup, [sys][count]
+// with count returned.
 template <typename T, typename TL>
-void launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
-                         const TL* ell2, T scale, const KrylovCtl* ctl, hipStream_t st,
-                         int nsys = 1, const unsigned char* phase = nullptr,
-                         const TL* ptab = nullptr);
+int launch_x_fused_helm(const Plan& p, const cpx<T>* tw, const Geo& g, cpx<T>* w,
+                        const TL* ell2, T scale, const KrylovCtl* ctl, hipStream_t st,
+                        int nsys = 1, const unsigned char* phase = nullptr,
+                        const TL* ptab = nullptr, double* partials = nullptr);
 template <typename T>
 int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const cpx<T>* b,
                    const cpx<T>* Ap, double* partials, const KrylovCtl* ctl, hipStream_t st,
@@ -177,6 +189,8 @@ int launch_h_resid(const Geo& g, const Sym<T>& sym, bool init, cpx<T>* r, const 
 // Krylov scalars: one workgroup per system (partials of system s at s * nb,
 // or s * nred * nb)
 void launch_fin_alpha(double* partials, int nb, KrylovCtl* ctl, hipStream_t st, int nsys = 1);
+void launch_fin_alpha2(const double* pa, int na, const double* pb, int nb, KrylovCtl* ctl,
+                       hipStream_t st, int nsys = 1);
 void launch_fin_beta(double* partials, int nb, int nred, KrylovCtl* ctl, hipStream_t st,
                      int nsys = 1);
 void launch_fin_sums(const double* partials, int nb, int nred, double* out, hipStream_t st);

@@ -35,6 +35,7 @@ CLASSES = {
     "k_x_fused_helm": "helmholtz_x_fused",
     "k_h_dir_inv": "helmholtz_outer_dir_inv",
     "k_h_div_fwd": "helmholtz_outer_div_fwd",
+    "k_h_fwd_resid": "helmholtz_outer_div_fwd",
     "k_h_resid": "helmholtz_resid",
 }
 
