@@ -77,3 +77,31 @@ def test_interface_contrast_limits_leakage():
         r = helmholtz.helmholtz_solve(alpha, ell2, tol=1e-12, maxit=5000)
         leak.append(r["abar"][:, ~host].sum() / r["abar"].sum())
     assert leak[0] > leak[1] > leak[2]
+
+
+@pytest.mark.parametrize("shape", [(8, 6), (6, 8, 10)])
+def test_energy_form_of_the_operator(shape):
+    """p . L p = sum |p|^2 + sum ell^2 |grad p|^2 over the voxels, for the
+    gradient the operator itself uses (i q~_j); the spectral side is the
+    weighted half-spectrum sum.  The GPU's PCG forms p . L p from these two
+    real-space and spectral pieces instead of from L p."""
+    rng = np.random.default_rng(5)
+    N = int(np.prod(shape))
+    p = rng.standard_normal(shape)
+    ell2 = rng.uniform(0.05, 4.0, size=shape)
+    _, qt = spectral.symbols(shape)
+    qt = [np.broadcast_to(v, shape) for v in qt]
+    P = spectral.fftn(p)
+    LP = helmholtz.operator(P, ell2, qt)
+    spectral_sum = float(np.vdot(P, LP).real) / N
+    grads = [np.real(spectral.ifftn(1j * qj * P)) for qj in qt]
+    energy = float((p * p).sum()) + float(sum((ell2 * g * g).sum() for g in grads))
+    assert abs(spectral_sum - energy) <= 1e-12 * energy
+    # the half spectrum with Hermitian weights gives the same first term
+    n1 = shape[-1]
+    Ph = np.fft.rfftn(p, axes=tuple(range(len(shape))))
+    wt = np.full(Ph.shape[-1], 2.0)
+    wt[0] = 1.0
+    if n1 % 2 == 0:
+        wt[-1] = 1.0
+    assert abs(float((wt * np.abs(Ph) ** 2).sum()) / N - float((p * p).sum())) <= 1e-12 * N
