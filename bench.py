@@ -1003,6 +1003,13 @@ def main():
             converged_increments=n32, timed_increments=r32["records"],
             cg_iters=r32["tot"]["cg"], pcg_iters=r32["tot"]["pcg"],
             newton_iters=r32["tot"]["newton"],
+            # the Helmholtz loop time includes its FP64 refinement sweeps
+            loops={
+                "galerkin_cg": dict(iters=r32["tot"]["cg"], voxel_iters_per_s=round(
+                    N * r32["tot"]["cg"] / max(r32["tot"]["t_ms"][1] / 1e3, 1e-9), 1)),
+                "helmholtz_pcg": dict(iters=r32["tot"]["pcg"], voxel_iters_per_s=round(
+                    N * r32["tot"]["pcg"] / max(r32["tot"]["t_ms"][2] / 1e3, 1e-9), 1)),
+                "t_ms": [round(x, 1) for x in r32["tot"]["t_ms"]]},
             homog_stress_rel_err_vs_fp64=err,
             homog_stress_err_increments=len(both),
             field_errors_vs_fp64=(field_errors(ws, r32["final"], r["final"]) if last_both
