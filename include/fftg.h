@@ -151,7 +151,17 @@ typedef struct {
 /* Create a solver for one grid.  `hip_stream` is a hipStream_t (NULL = the
  * default stream).  The handle owns its workspace (spectra, Krylov vectors,
  * tangent, FFT tables, reduction scratch), sized from the grid, until
- * fftg_destroy.  Errors: INVALID (null, ndim), UNSUPPORTED (sizes), HIP. */
+ * fftg_destroy.  Errors: INVALID (null, ndim), UNSUPPORTED (sizes), HIP.
+ * Read from the environment at creation (all default to the form measured
+ * fastest; the others give the same iterates, with sums in another order):
+ *   FFTG_GAL_XDOT=0   Galerkin CG p.Ap on the half spectrum by the forward
+ *                     outer pass instead of in real space by the x pass
+ *   FFTG_GAL_FUSE=0   Galerkin forward outer pass and residual update as two
+ *                     passes instead of one
+ *   FFTG_GAL_FOLD=1   Galerkin scalar steps folded into the passes (with the
+ *                     two-pass form)
+ *   FFTG_HELM_FUSE=0  Helmholtz p.Lp on the half spectrum and the forward
+ *                     pass and residual update as two passes */
 fftg_status fftg_create(const fftg_grid* grid, void* hip_stream, fftg_handle** out);
 fftg_status fftg_destroy(fftg_handle* h);
 /* Text of the last error on this handle (or of the last failed create when h
