@@ -1,10 +1,12 @@
-"""The Galerkin CG's three forms of one iteration give the same increments
-to rounding: the default (p.Ap summed in real space by the x pass, forward
+"""The forms of one Krylov iteration give the same increments to rounding.
+Galerkin CG: the default (p.Ap summed in real space by the x pass, forward
 outer pass fused with the residual update), the two-pass form
 (FFTG_GAL_FUSE=0: forward pass and residual pass apart) and the form with
-p.Ap on the half spectrum (FFTG_GAL_XDOT=0).  The three order their sums
-differently, so the states agree to rounding, not bitwise.  3D (six
-components, the fixed-length and the generic outer-axis kernels) and 2D."""
+p.Ap on the half spectrum (FFTG_GAL_XDOT=0).  Helmholtz PCG: the default
+(p.Lp from the inverse and x passes, forward pass fused with the residual
+update) and the two-pass form (FFTG_HELM_FUSE=0).  The forms order their
+sums differently, so the states agree to rounding, not bitwise.  3D (the
+fixed-length and the generic outer-axis kernels) and 2D."""
 import sys
 
 import numpy as np
@@ -16,7 +18,7 @@ pytestmark = pytest.mark.gpu
 from paper_2103_04770_amd import microstructure as ms  # noqa: E402
 
 TOLS = dict(cg_tol=1e-11, pcg_tol=1e-11, newton_tol=1e-10, stagger_tol=1e-9, max_stagger=60)
-FORMS = [{}, {"FFTG_GAL_FUSE": "0"}, {"FFTG_GAL_XDOT": "0"}]
+FORMS = [{}, {"FFTG_GAL_FUSE": "0"}, {"FFTG_GAL_XDOT": "0"}, {"FFTG_HELM_FUSE": "0"}]
 
 
 def say(*a):
@@ -26,7 +28,7 @@ def say(*a):
 
 def _run(shape, env, monkeypatch):
     from paper_2103_04770_amd import FP64, Solver
-    for k in ("FFTG_GAL_FUSE", "FFTG_GAL_XDOT"):
+    for k in ("FFTG_GAL_FUSE", "FFTG_GAL_XDOT", "FFTG_HELM_FUSE"):
         monkeypatch.delenv(k, raising=False)
     for k, v in env.items():
         monkeypatch.setenv(k, v)
@@ -69,6 +71,7 @@ def test_cg_forms_agree(shape, monkeypatch):
         for a, b in zip(stats, ref_stats):
             assert a["converged"] and b["converged"], env
             assert abs(a["cg_iters"] - b["cg_iters"]) <= 0.02 * b["cg_iters"] + 2, env
+            assert abs(a["pcg_iters"] - b["pcg_iters"]) <= 0.02 * b["pcg_iters"] + 2, env
             rel = np.abs(a["sigma_mean"] - b["sigma_mean"]).max() / np.abs(b["sigma_mean"]).max()
             assert rel <= 1e-10, (env, rel)
         scale = np.abs(ref_state).max()
